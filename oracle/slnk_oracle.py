@@ -1,0 +1,639 @@
+"""FP64 numpy oracle of the semi-Lagrangian (SL) Gauss--Newton--Krylov path.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): the product path never
+imports this module.
+
+Conventions (stated once, used everywhere below)
+------------------------------------------------
+* Periodic grid on [0, 2*pi)^2 with n1 x n2 nodes, x_i = 2*pi*i/n (the paper's
+  (-pi, pi)^2 is the same torus, shifted).  Arrays are indexed [i1, i2] with
+  i2 the fastest axis; a velocity is an array of shape (2, n1, n2).
+* Pseudospectral calculus (section 3.2): unnormalised forward DFT, 1/N on the
+  inverse; odd-order symbols (gradient, divergence) drop the Nyquist mode,
+  even-order symbols (the regulariser) keep it.
+* Interpolation (section 3.3.2, "Interpolation"; section 3.5): the C^2 periodic
+  cubic spline, i.e. the tensor-product cubic B-spline whose coefficients solve
+  the periodic system (c[i-1] + 4 c[i] + c[i+1]) / 6 = f[i] along each axis.
+* Time grid t^j = j*ht, ht = 1/nt (section 3.2).  Time integrals over [0, 1]
+  use the composite trapezoid rule on t^0..t^nt.
+* Parity status: every function here is pinned by a test in
+  ``tests/test_oracle_*.py`` (closed forms, library routines, invariants,
+  finite differences, brute force on tiny grids).
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "Grid", "Params", "Level", "Linearization",
+    "fft_grad", "fft_div", "reg_symbol", "apply_reg", "apply_proj", "leray",
+    "spline_coefficients", "bspline_weights", "interpolate",
+    "trace", "adjoint_factor", "solve_state", "transport_state", "solve_adjoint",
+    "trapezoid_weights", "linearize", "objective", "gradient",
+    "incremental_state", "gn_transport_part", "hessian_matvec",
+    "prec_reg", "split_scale", "lowpass", "restrict", "prolong",
+    "split_matvec", "chebyshev", "lanczos_max", "splitmix64", "splitmix64_uniform",
+    "TwoLevel", "setup_two_level", "apply_two_level",
+    "pcg", "newton_solve", "inner_l2",
+]
+
+
+# ---------------------------------------------------------------------------
+# Grid and parameters
+# ---------------------------------------------------------------------------
+
+class Grid:
+    """Regular periodic grid, cell size h_i = 2*pi/n_i (section 3.2)."""
+
+    def __init__(self, n1: int, n2: int):
+        if n1 % 2 or n2 % 2:
+            raise ValueError("grid sizes must be even")
+        self.n1, self.n2 = int(n1), int(n2)
+        self.shape = (self.n1, self.n2)
+        self.N = self.n1 * self.n2
+        self.h = (2.0 * math.pi / self.n1, 2.0 * math.pi / self.n2)
+        self.cell = self.h[0] * self.h[1]
+        k1 = np.fft.fftfreq(self.n1, 1.0 / self.n1)
+        k2 = np.fft.fftfreq(self.n2, 1.0 / self.n2)
+        self.K1, self.K2 = np.meshgrid(k1, k2, indexing="ij")
+        k1o = k1.copy(); k1o[self.n1 // 2] = 0.0
+        k2o = k2.copy(); k2o[self.n2 // 2] = 0.0
+        self.K1o, self.K2o = np.meshgrid(k1o, k2o, indexing="ij")
+        i1 = np.arange(self.n1, dtype=np.float64)
+        i2 = np.arange(self.n2, dtype=np.float64)
+        I1, I2 = np.meshgrid(i1, i2, indexing="ij")
+        self.X = np.stack([I1 * self.h[0], I2 * self.h[1]])
+
+    def coarse(self) -> "Grid":
+        return Grid(self.n1 // 2, self.n2 // 2)
+
+
+@dataclass
+class Params:
+    """Problem parameters (section 3.5 lists the paper's settings).
+
+    reg: 1, 2, 3 for the H1, H2, H3 seminorm (eq. e:varopt:regv).
+    proj: 0 for the compressible case (K = identity), 1 for the Leray
+          projection (the incompressible case, w = 0).
+    """
+    nt: int
+    beta: float
+    reg: int = 2
+    proj: int = 0
+
+
+# ---------------------------------------------------------------------------
+# Pseudospectral operators (section 3.2; eq. e:diffopregv; Leray operator)
+# ---------------------------------------------------------------------------
+
+def _fft(u):
+    return np.fft.fft2(u)
+
+
+def _ifft_real(U):
+    return np.fft.ifft2(U).real
+
+
+def fft_grad(g: Grid, u):
+    """Spectral gradient of a scalar field: (d1 u, d2 u)."""
+    U = _fft(u)
+    return np.stack([_ifft_real(1j * g.K1o * U), _ifft_real(1j * g.K2o * U)])
+
+
+def fft_div(g: Grid, v):
+    """Spectral divergence of a vector field."""
+    return _ifft_real(1j * g.K1o * _fft(v[0]) + 1j * g.K2o * _fft(v[1]))
+
+
+def reg_symbol(g: Grid, reg: int):
+    """Symbol a(k) of the regularisation operator A (eq. e:diffopregv).
+
+    A = -Laplacian (H1), Laplacian^2 (H2), -Laplacian^3 (H3): a(k) = |k|^(2 reg)
+    (the H3 sign is the one that makes A the positive semidefinite first
+    variation of the seminorm).
+    """
+    return (g.K1 ** 2 + g.K2 ** 2) ** reg
+
+
+def apply_reg(g: Grid, v, reg: int):
+    a = reg_symbol(g, reg)
+    return np.stack([_ifft_real(a * _fft(v[c])) for c in range(2)])
+
+
+def leray(g: Grid, b):
+    """Leray projection K[b] = b - grad Laplacian^{-1} div b (section 3.1)."""
+    B1, B2 = _fft(b[0]), _fft(b[1])
+    k2 = g.K1o ** 2 + g.K2o ** 2
+    safe = np.where(k2 > 0, k2, 1.0)
+    kb = (g.K1o * B1 + g.K2o * B2) / safe
+    kb = np.where(k2 > 0, kb, 0.0)
+    return np.stack([_ifft_real(B1 - g.K1o * kb), _ifft_real(B2 - g.K2o * kb)])
+
+
+def apply_proj(g: Grid, b, proj: int):
+    return b if proj == 0 else leray(g, b)
+
+
+def inner_l2(g: Grid, a, b) -> float:
+    """Discrete L2 inner product: cell area times the Euclidean product."""
+    return g.cell * float(np.sum(a * b))
+
+
+# ---------------------------------------------------------------------------
+# Periodic cubic spline (section 3.3.2, "Interpolation"; section 3.5)
+# ---------------------------------------------------------------------------
+
+def spline_coefficients(g: Grid, f):
+    """B-spline coefficients c of the periodic cubic spline through f.
+
+    Along each axis the coefficients solve the circulant system
+    (c[i-1] + 4 c[i] + c[i+1]) / 6 = f[i]; a circulant system is diagonal in
+    Fourier space, with eigenvalue (2 + cos(2 pi k / n)) / 3 per axis.
+    """
+    b1 = (2.0 + np.cos(2.0 * np.pi * g.K1 / g.n1)) / 3.0
+    b2 = (2.0 + np.cos(2.0 * np.pi * g.K2 / g.n2)) / 3.0
+    return _ifft_real(_fft(f) / (b1 * b2))
+
+
+def bspline_weights(theta):
+    """Uniform cubic B-spline weights for the offsets -1, 0, 1, 2 at fraction theta."""
+    t = theta
+    return (
+        (1.0 - t) ** 3 / 6.0,
+        (3.0 * t ** 3 - 6.0 * t ** 2 + 4.0) / 6.0,
+        (-3.0 * t ** 3 + 3.0 * t ** 2 + 3.0 * t + 1.0) / 6.0,
+        t ** 3 / 6.0,
+    )
+
+
+def _eval_coefficients(g: Grid, c, X):
+    s1 = X[0] / g.h[0]
+    s2 = X[1] / g.h[1]
+    f1 = np.floor(s1); f2 = np.floor(s2)
+    w1 = bspline_weights(s1 - f1)
+    w2 = bspline_weights(s2 - f2)
+    i1 = f1.astype(np.int64); i2 = f2.astype(np.int64)
+    out = np.zeros(np.shape(s1))
+    for a in range(4):
+        r = np.mod(i1 + a - 1, g.n1)
+        for b in range(4):
+            q = np.mod(i2 + b - 1, g.n2)
+            out += w1[a] * w2[b] * c[r, q]
+    return out
+
+
+def interpolate(g: Grid, f, X):
+    """Value at the points X (shape (2, ...), radians) of the spline through f."""
+    return _eval_coefficients(g, spline_coefficients(g, f), X)
+
+
+# ---------------------------------------------------------------------------
+# Characteristics and transport (section 3.3.2; eqs. e:characteristic,
+# e:state-slm, e:adj-slm, e:inc-state-slm, e:inc-adj-slm)
+# ---------------------------------------------------------------------------
+
+def trace(g: Grid, v, ht: float, direction: int):
+    """Departure points of one SL step by Heun's method (section 3.3.2).
+
+    direction = -1: characteristic of the forward equations (dX/dt = v traced
+    back over one step): X* = x - ht v(x), X = x - ht/2 (v(x) + v(X*)).
+    direction = +1: characteristic of the backward (adjoint) equations, which
+    are transported by -v in reversed time: the same formulas with +ht.
+    """
+    s = float(direction)
+    Xs = g.X + s * ht * v
+    vs = np.stack([interpolate(g, v[0], Xs), interpolate(g, v[1], Xs)])
+    return g.X + s * 0.5 * ht * (v + vs)
+
+
+def adjoint_factor(g: Grid, v, Xa, ht: float):
+    """Heun step of d(lambda)/ds = lambda div v along the adjoint characteristic.
+
+    The adjoint equation -d_t lambda - v.grad lambda - lambda div v = 0
+    (eq. e:adj-slm) reads d(lambda)/ds = lambda div v along dX/ds = -v in
+    reversed time s = 1 - t; Heun's method over one step multiplies the
+    departure value by 1 + ht/2 (d_D + d_x) + ht^2/2 d_D d_x, where d_x is
+    div v at the arrival node and d_D at the departure point.
+    """
+    dx = fft_div(g, v)
+    dD = interpolate(g, dx, Xa)
+    return 1.0 + 0.5 * ht * (dD + dx) + 0.5 * ht * ht * dD * dx
+
+
+def solve_state(g: Grid, Xf, m0, nt: int):
+    """State equation (eq. e:state-slm): m^j = m^{j-1} at the departure points."""
+    m = [np.array(m0, dtype=np.float64)]
+    for _ in range(nt):
+        m.append(interpolate(g, m[-1], Xf))
+    return m
+
+
+def transport_state(g: Grid, v, m0, nt: int):
+    """m at t = 1 for the initial value m0 transported by the stationary v."""
+    Xf = trace(g, v, 1.0 / nt, -1)
+    return solve_state(g, Xf, m0, nt)[-1]
+
+
+def solve_adjoint(g: Grid, Xa, gamma, lam_final, nt: int):
+    """Adjoint equation (eq. e:adj-slm), backward from t = 1: list lambda^0..lambda^nt."""
+    lam = [None] * (nt + 1)
+    lam[nt] = np.array(lam_final, dtype=np.float64)
+    for j in range(nt, 0, -1):
+        lam[j - 1] = gamma * interpolate(g, lam[j], Xa)
+    return lam
+
+
+def trapezoid_weights(nt: int):
+    """Weights of the composite trapezoid rule on t^0..t^nt (sum to 1)."""
+    w = np.full(nt + 1, 1.0 / nt)
+    w[0] *= 0.5
+    w[-1] *= 0.5
+    return w
+
+
+@dataclass
+class Level:
+    """One grid level of a registration problem (images and parameters)."""
+    grid: Grid
+    mT: np.ndarray
+    mR: np.ndarray
+    prm: Params
+
+
+@dataclass
+class Linearization:
+    """Quantities fixed for a given v (traced once per Newton iterate)."""
+    level: Level
+    v: np.ndarray
+    Xf: np.ndarray
+    Xa: np.ndarray
+    gamma: np.ndarray
+    m: list
+    gradm: list
+    Av: np.ndarray
+    J: float
+    lam: list = field(default=None)
+    g: np.ndarray = field(default=None)
+
+
+def linearize(L: Level, v) -> Linearization:
+    """Trace both characteristics, solve the state equation, evaluate J."""
+    g, p = L.grid, L.prm
+    ht = 1.0 / p.nt
+    v = np.array(v, dtype=np.float64)
+    Xf = trace(g, v, ht, -1)
+    Xa = trace(g, v, ht, +1)
+    gamma = adjoint_factor(g, v, Xa, ht)
+    m = solve_state(g, Xf, L.mT, p.nt)
+    gradm = [fft_grad(g, mj) for mj in m]
+    Av = apply_reg(g, v, p.reg)
+    J = 0.5 * inner_l2(g, m[-1] - L.mR, m[-1] - L.mR) + 0.5 * p.beta * inner_l2(g, v, Av)
+    return Linearization(L, v, Xf, Xa, gamma, m, gradm, Av, J)
+
+
+def objective(L: Level, v) -> float:
+    """J[v] = 1/2 ||m_1 - m_R||^2 + beta/2 <v, A v> (eq. e:varopt:objective, w-term absent)."""
+    return linearize(L, v).J
+
+
+def gradient(lin: Linearization):
+    """Reduced gradient g = beta A v + K int_0^1 lambda grad m dt (eq. e:control-elim)."""
+    L = lin.level
+    g, p = L.grid, L.prm
+    lam = solve_adjoint(g, lin.Xa, lin.gamma, L.mR - lin.m[-1], p.nt)
+    w = trapezoid_weights(p.nt)
+    b = sum(w[j] * lam[j] * lin.gradm[j] for j in range(p.nt + 1))
+    lin.lam = lam
+    lin.g = p.beta * lin.Av + apply_proj(g, b, p.proj)
+    return lin.g
+
+
+def incremental_state(lin: Linearization, vt):
+    """Incremental state (eq. e:inc-state-slm), list m~^0..m~^nt.
+
+    Along the forward characteristic d(m~)/dt = f with f = -vt . grad m, a
+    source that does not depend on m~, so Heun's step is the trapezoid rule:
+    m~^j = I[m~^{j-1} + ht/2 f^{j-1}](X_f) + ht/2 f^j.
+    """
+    L = lin.level
+    g, p = L.grid, L.prm
+    ht = 1.0 / p.nt
+    f = [-(vt[0] * gm[0] + vt[1] * gm[1]) for gm in lin.gradm]
+    mt = [np.zeros(g.shape)]
+    for j in range(1, p.nt + 1):
+        mt.append(interpolate(g, mt[-1] + 0.5 * ht * f[j - 1], lin.Xf) + 0.5 * ht * f[j])
+    return mt
+
+
+def gn_transport_part(lin: Linearization, vt):
+    """Q[vt] = K int_0^1 lam~ grad m dt of the GN matvec (eqs. e:hessian-matvec, e:inc-adj-slm).
+
+    Gauss--Newton drops every term with lambda (section 3.4.1): the incremental
+    adjoint solves the adjoint equation with final value -m~(1).
+    """
+    L = lin.level
+    g, p = L.grid, L.prm
+    mt = incremental_state(lin, vt)
+    lt = solve_adjoint(g, lin.Xa, lin.gamma, -mt[-1], p.nt)
+    w = trapezoid_weights(p.nt)
+    bt = sum(w[j] * lt[j] * lin.gradm[j] for j in range(p.nt + 1))
+    return apply_proj(g, bt, p.proj)
+
+
+def hessian_matvec(lin: Linearization, vt):
+    """GN reduced Hessian matvec H vt = beta A vt + Q[vt] (eq. e:hessian-matvec)."""
+    L = lin.level
+    return L.prm.beta * apply_reg(L.grid, vt, L.prm.reg) + gn_transport_part(lin, vt)
+
+
+# ---------------------------------------------------------------------------
+# Preconditioners (section 3.4.2)
+# ---------------------------------------------------------------------------
+
+def _reg_symbol_nonzero(g: Grid, reg: int):
+    a = reg_symbol(g, reg)
+    return np.where(a == 0.0, 1.0, a)
+
+
+def prec_reg(g: Grid, r, beta: float, reg: int):
+    """P_REG^{-1} r: spectral inverse of beta A with the zero symbol replaced by 1 (eq. e:reg-precond)."""
+    a = beta * _reg_symbol_nonzero(g, reg)
+    return np.stack([_ifft_real(_fft(r[c]) / a) for c in range(2)])
+
+
+def split_scale(g: Grid, r, beta: float, reg: int):
+    """S r = (beta A')^{-1/2} r, the split spectral preconditioner's half step."""
+    a = beta * _reg_symbol_nonzero(g, reg)
+    return np.stack([_ifft_real(_fft(r[c]) / np.sqrt(a)) for c in range(2)])
+
+
+def _low_mask(g: Grid):
+    """Ideal low-pass: |k_i| < n_i/4, i.e. the modes a grid of half the size keeps (its Nyquist dropped)."""
+    return (np.abs(g.K1) < g.n1 / 4) & (np.abs(g.K2) < g.n2 / 4)
+
+
+def lowpass(g: Grid, r):
+    m = _low_mask(g)
+    return np.stack([_ifft_real(_fft(r[c]) * m) for c in range(2)])
+
+
+def _coarse_index(fine: Grid, coarse: Grid):
+    kc1 = np.fft.fftfreq(coarse.n1, 1.0 / coarse.n1).astype(np.int64)
+    kc2 = np.fft.fftfreq(coarse.n2, 1.0 / coarse.n2).astype(np.int64)
+    keep1 = np.abs(kc1) < coarse.n1 // 2
+    keep2 = np.abs(kc2) < coarse.n2 // 2
+    return kc1, kc2, keep1, keep2
+
+
+def restrict(fine: Grid, coarse: Grid, u):
+    """Spectral restriction: keep the modes |k_i| < n_i/4, rescale for the DFT size."""
+    kc1, kc2, keep1, keep2 = _coarse_index(fine, coarse)
+    U = _fft(u)
+    Uc = U[np.ix_(np.mod(kc1, fine.n1), np.mod(kc2, fine.n2))] * (coarse.N / fine.N)
+    Uc = Uc * np.outer(keep1, keep2)
+    return _ifft_real(Uc)
+
+
+def prolong(fine: Grid, coarse: Grid, uc):
+    """Spectral prolongation: zero padding of the coarse modes (coarse Nyquist dropped)."""
+    kc1, kc2, keep1, keep2 = _coarse_index(fine, coarse)
+    Uc = _fft(uc) * np.outer(keep1, keep2) * (fine.N / coarse.N)
+    U = np.zeros(fine.shape, dtype=np.complex128)
+    U[np.ix_(np.mod(kc1, fine.n1), np.mod(kc2, fine.n2))] = Uc
+    return _ifft_real(U)
+
+
+def split_matvec(lin: Linearization, s):
+    """M s = s + S Q S s: the split spectrally preconditioned GN Hessian (section 3.4.2)."""
+    L = lin.level
+    g, p = L.grid, L.prm
+    w = split_scale(g, s, p.beta, p.reg)
+    return s + split_scale(g, gn_transport_part(lin, w), p.beta, p.reg)
+
+
+def chebyshev(op, b, emin: float, emax: float, k: int):
+    """k steps of the Chebyshev iteration for op x = b from x = 0.
+
+    Textbook Chebyshev acceleration with spectral bounds [emin, emax] (centre
+    theta, half width delta); after k steps the residual is
+    T_k((theta - A)/delta) / T_k(theta/delta) applied to b.  The k-th update
+    needs no new residual, so k steps apply the operator k - 1 times.
+    """
+    theta = 0.5 * (emax + emin)
+    delta = 0.5 * (emax - emin)
+    sigma = theta / delta
+    rho = 1.0 / sigma
+    x = np.zeros_like(b)
+    r = np.array(b, dtype=np.float64)
+    d = r / theta
+    for i in range(k):
+        x = x + d
+        if i == k - 1:
+            break
+        r = r - op(d)
+        rho_next = 1.0 / (2.0 * sigma - rho)
+        d = rho_next * rho * d + (2.0 * rho_next / delta) * r
+        rho = rho_next
+    return x
+
+
+def splitmix64(seed: int, count: int):
+    """'count' outputs of the SplitMix64 generator (Steele, Lea, Flood 2014) started at 'seed'.
+
+    State update: add the Weyl increment 0x9E3779B97F4A7C15 (mod 2^64); output:
+    the state mixed by two xor-shift-multiply rounds and a final xor-shift.
+    """
+    M = (1 << 64) - 1
+    state = seed & M
+    out = []
+    for _ in range(count):
+        state = (state + 0x9E3779B97F4A7C15) & M
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        out.append(z ^ (z >> 31))
+    return out
+
+
+def splitmix64_uniform(seed: int, count: int):
+    """Uniform numbers in [-0.5, 0.5): the top 53 bits of each SplitMix64 output as a fraction, minus 1/2."""
+    return np.array([(z >> 11) * (1.0 / (1 << 53)) - 0.5 for z in splitmix64(seed, count)])
+
+
+def lanczos_max(op, q0, steps: int) -> float:
+    """Largest Ritz value of 'steps' Lanczos steps (no re-orthogonalisation) from q0."""
+    q = q0 / np.sqrt(np.sum(q0 * q0))
+    q_prev = np.zeros_like(q)
+    beta = 0.0
+    alphas, betas = [], []
+    for j in range(steps):
+        w = op(q) - beta * q_prev
+        alpha = float(np.sum(q * w))
+        w = w - alpha * q
+        alphas.append(alpha)
+        beta = float(np.sqrt(np.sum(w * w)))
+        if j == steps - 1 or beta <= 1e-14 * abs(alpha):
+            break
+        betas.append(beta)
+        q_prev, q = q, w / beta
+    T = np.diag(alphas) + np.diag(betas, 1) + np.diag(betas, -1)
+    return float(np.max(np.linalg.eigvalsh(T)))
+
+
+@dataclass
+class TwoLevel:
+    """Data of the nested two-level preconditioner P_2L fixed for one solve."""
+    coarse: Level
+    emin: float
+    emax: float
+    cheb_iters: int
+    lin_c: Linearization = None
+
+
+def setup_two_level(L: Level, cheb_iters=10, lanczos_steps=30, safety=1.05, seed=0x5EED):
+    """Coarse problem and Chebyshev bounds (section 3.4.2, "Nested Preconditioner").
+
+    The coarse problem restricts m_T and m_R spectrally and keeps nt and beta.
+    e_max is the largest Ritz value of Lanczos on the coarse split operator at
+    v = 0 (times a safety factor), computed once per solve; e_min is the
+    analytic estimate min(1 + 1/(beta a'(k))) over the coarse modes.
+    """
+    fg = L.grid
+    cg = fg.coarse()
+    Lc = Level(cg, restrict(fg, cg, L.mT), restrict(fg, cg, L.mR), L.prm)
+    lin0 = linearize(Lc, np.zeros((2,) + cg.shape))
+    q0 = splitmix64_uniform(seed, 2 * cg.N).reshape((2,) + cg.shape)
+    emax = safety * lanczos_max(lambda s: split_matvec(lin0, s), q0, lanczos_steps)
+    emin = float(np.min(1.0 + 1.0 / (L.prm.beta * _reg_symbol_nonzero(cg, L.prm.reg))))
+    return TwoLevel(Lc, emin, emax, cheb_iters)
+
+
+def apply_two_level(L: Level, tl: TwoLevel, r):
+    """P_2L^{-1} r = (I - L) r + Pro C_k(M_c) Res r (section 3.4.2, nested preconditioner)."""
+    fg, cg = L.grid, tl.coarse.grid
+    high = r - lowpass(fg, r)
+    rc = np.stack([restrict(fg, cg, r[c]) for c in range(2)])
+    zc = chebyshev(lambda s: split_matvec(tl.lin_c, s), rc, tl.emin, tl.emax, tl.cheb_iters)
+    return high + np.stack([prolong(fg, cg, zc[c]) for c in range(2)])
+
+
+# ---------------------------------------------------------------------------
+# Newton--Krylov solver (sections 3.4.1 and 3.5)
+# ---------------------------------------------------------------------------
+
+def pcg(op, b, prec, tol: float, maxit: int):
+    """Preconditioned CG from x = 0 (Hestenes--Stiefel), Euclidean products.
+
+    Stops when ||r|| <= tol ||b||, at maxit, or on non-positive curvature
+    p.Ap <= 0 (then the current iterate, or P^{-1} b at the first step, is
+    returned).  Returns (x, iterations, status) with status 'ok', 'maxit' or
+    'negcurv'.
+    """
+    x = np.zeros_like(b)
+    r = np.array(b, dtype=np.float64)
+    bnorm = float(np.sqrt(np.sum(b * b)))
+    if bnorm == 0.0:
+        return x, 0, "ok"
+    z = prec(r)
+    p = z.copy()
+    rz = float(np.sum(r * z))
+    for it in range(1, maxit + 1):
+        q = op(p)
+        pq = float(np.sum(p * q))
+        if pq <= 0.0:
+            return (z if it == 1 else x), it, "negcurv"
+        alpha = rz / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        if float(np.sqrt(np.sum(r * r))) <= tol * bnorm:
+            return x, it, "ok"
+        z = prec(r)
+        rz_next = float(np.sum(r * z))
+        p = z + (rz_next / rz) * p
+        rz = rz_next
+    return x, maxit, "maxit"
+
+
+def newton_solve(L: Level, v0=None, pc: str = "reg", max_newton=10, gtol_rel=1e-2, gtol_abs=1e-5,
+                 max_pcg=500, armijo_c1=1e-4, max_halvings=10, cheb_iters=10, lanczos_steps=30,
+                 emax_safety=1.05, seed=0x5EED, g0_norms=None):
+    """Globalised inexact GN--Krylov solve (sections 3.4.1, 3.5).
+
+    Newton step H vt = -g by PCG with the forcing term
+    eta_k = min(0.5, ||g_k|| / ||g_0||); Armijo backtracking (alpha halved from
+    1, sufficient decrease 1e-4 alpha <g, vt>_L2); stop when
+    ||g_k||_inf / ||g_0||_inf <= gtol_rel or ||g_k||_inf <= gtol_abs.
+    pc = 'reg' runs PCG on H with P_REG; pc = '2l' runs PCG on the split system
+    M s = -S g with P_2L and takes vt = S s.  g_0 is the gradient at v = 0;
+    g0_norms = (||g_0||_inf, ||g_0||_2) may be passed in to skip computing it.
+    """
+    g, p = L.grid, L.prm
+    v = np.zeros((2,) + g.shape) if v0 is None else np.array(v0, dtype=np.float64)
+    rep = {"newton_iters": 0, "pcg_iters": 0, "matvecs": 0, "coarse_matvecs": 0,
+           "grel": [], "J": [], "status": "ok", "alphas": []}
+    tl = setup_two_level(L, cheb_iters, lanczos_steps, emax_safety, seed) if pc == "2l" else None
+    if tl is not None:
+        rep["emin"], rep["emax"] = tl.emin, tl.emax
+    lin = linearize(L, v)
+    grad = gradient(lin)
+    if g0_norms is None:
+        if v0 is None:
+            g0 = grad
+        else:
+            lin0 = linearize(L, np.zeros_like(v))
+            g0 = gradient(lin0)
+        g0_inf = float(np.max(np.abs(g0)))
+        g0_two = float(np.sqrt(np.sum(g0 * g0)))
+    else:
+        g0_inf, g0_two = g0_norms
+    for k in range(max_newton + 1):
+        ginf = float(np.max(np.abs(grad)))
+        gtwo = float(np.sqrt(np.sum(grad * grad)))
+        rep["grel"].append(ginf / g0_inf)
+        rep["J"].append(lin.J)
+        if ginf / g0_inf <= gtol_rel or ginf <= gtol_abs or k == max_newton:
+            break
+        eta = min(0.5, gtwo / g0_two)
+        if tl is None:
+            def op(x):
+                rep["matvecs"] += 1
+                return hessian_matvec(lin, x)
+            vt, its, st = pcg(op, -grad, lambda r: prec_reg(g, r, p.beta, p.reg), eta, max_pcg)
+        else:
+            fg, cg = g, tl.coarse.grid
+            vc = np.stack([restrict(fg, cg, v[c]) for c in range(2)])
+            tl.lin_c = linearize(tl.coarse, vc)
+
+            def op(x):
+                rep["matvecs"] += 1
+                return split_matvec(lin, x)
+
+            def prec(r):
+                rep["coarse_matvecs"] += max(tl.cheb_iters - 1, 0)
+                return apply_two_level(L, tl, r)
+            s, its, st = pcg(op, -split_scale(g, grad, p.beta, p.reg), prec, eta, max_pcg)
+            vt = split_scale(g, s, p.beta, p.reg)
+        rep["pcg_iters"] += its
+        slope = inner_l2(g, grad, vt)
+        alpha, accepted = 1.0, False
+        for _ in range(max_halvings + 1):
+            trial = linearize(L, v + alpha * vt)
+            if trial.J <= lin.J + armijo_c1 * alpha * slope:
+                accepted = True
+                break
+            alpha *= 0.5
+        if not accepted:
+            rep["status"] = "linesearch"
+            break
+        rep["alphas"].append(alpha)
+        v = v + alpha * vt
+        lin = trial
+        grad = gradient(lin)
+        rep["newton_iters"] = k + 1
+    rep["g0_inf"] = g0_inf
+    rep["g0_two"] = g0_two
+    return v, rep

@@ -1,0 +1,148 @@
+"""Seeded synthetic inputs shaped like the paper's 2-D registration problems.
+
+This module holds only input recipes (images, velocity fields, search
+directions); none of the registration method's arithmetic lives here.  Both
+the FP64 oracle (in tests) and the GPU library (in tests and the benchmark)
+consume what it produces.  The reference image m_R of each problem is the
+template transported by the generating velocity; the caller computes it with
+whichever implementation it is exercising.
+
+Value ranges follow the paper's test problems: intensities in [0, 1], velocity
+magnitudes of order 0.5 (section 4, synthetic problems figure), grids from 64^2
+to 512^2.  The paper's own images are not available; these recipes stand in
+for them.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = ["grid_coords", "smooth_a_template", "smooth_a_velocity", "gaussian_sum_isotropic",
+           "gaussian_sum_anisotropic", "random_velocity", "config", "CONFIGS"]
+
+
+def grid_coords(n1, n2):
+    x1 = 2.0 * math.pi * np.arange(n1) / n1
+    x2 = 2.0 * math.pi * np.arange(n2) / n2
+    return np.meshgrid(x1, x2, indexing="ij")
+
+
+def _wrap(d):
+    """Minimum-image difference on the 2*pi-periodic line."""
+    return (d + math.pi) % (2.0 * math.pi) - math.pi
+
+
+def smooth_a_template(n1, n2):
+    """m_T = (sin^2 x1 + sin^2 x2) / 2."""
+    X1, X2 = grid_coords(n1, n2)
+    return 0.5 * (np.sin(X1) ** 2 + np.sin(X2) ** 2)
+
+
+def smooth_a_velocity(n1, n2, amplitude=0.5):
+    """v* = amplitude * (sin x2 cos x1, -sin x1 cos x2): divergence free, -Laplacian v* = 2 v*."""
+    X1, X2 = grid_coords(n1, n2)
+    return amplitude * np.stack([np.sin(X2) * np.cos(X1), -np.sin(X1) * np.cos(X2)])
+
+
+def _normalise(u):
+    lo, hi = float(u.min()), float(u.max())
+    return (u - lo) / (hi - lo)
+
+
+def gaussian_sum_isotropic(n1, n2, rng, count=32, sigma=(0.1, 0.4), amplitude=(0.2, 1.0)):
+    """Sum of isotropic periodic Gaussians (widths in radians), min-max normalised to [0, 1]."""
+    X1, X2 = grid_coords(n1, n2)
+    centres = rng.uniform(0.0, 2.0 * math.pi, size=(count, 2))
+    sig = rng.uniform(sigma[0], sigma[1], size=count)
+    amp = rng.uniform(amplitude[0], amplitude[1], size=count)
+    u = np.zeros((n1, n2))
+    for c, s, a in zip(centres, sig, amp):
+        d1 = _wrap(X1 - c[0]); d2 = _wrap(X2 - c[1])
+        u += a * np.exp(-(d1 * d1 + d2 * d2) / (2.0 * s * s))
+    return _normalise(u)
+
+
+def gaussian_sum_anisotropic(n1, n2, rng, count=64, sigma_px=(2.0, 20.0), amplitude=(0.0, 1.0),
+                             smooth_px=2.0):
+    """Brain-like stand-in: rotated anisotropic Gaussians, Gaussian-smoothed, clipped to [0, 1]."""
+    X1, X2 = grid_coords(n1, n2)
+    h1, h2 = 2.0 * math.pi / n1, 2.0 * math.pi / n2
+    centres = rng.uniform(0.0, 2.0 * math.pi, size=(count, 2))
+    sig = rng.uniform(sigma_px[0], sigma_px[1], size=(count, 2))
+    rot = rng.uniform(0.0, math.pi, size=count)
+    amp = rng.uniform(amplitude[0], amplitude[1], size=count)
+    u = np.zeros((n1, n2))
+    for c, s, r, a in zip(centres, sig, rot, amp):
+        d1 = _wrap(X1 - c[0]) / h1; d2 = _wrap(X2 - c[1]) / h2   # in pixels
+        p = math.cos(r) * d1 + math.sin(r) * d2
+        q = -math.sin(r) * d1 + math.cos(r) * d2
+        u += a * np.exp(-0.5 * ((p / s[0]) ** 2 + (q / s[1]) ** 2))
+    k1 = np.fft.fftfreq(n1, 1.0 / n1); k2 = np.fft.fftfreq(n2, 1.0 / n2)
+    K1, K2 = np.meshgrid(k1, k2, indexing="ij")
+    s1, s2 = smooth_px * h1, smooth_px * h2
+    u = np.fft.ifft2(np.fft.fft2(u) * np.exp(-0.5 * ((K1 * s1) ** 2 + (K2 * s2) ** 2))).real
+    return np.clip(u, 0.0, 1.0)
+
+
+def random_velocity(n1, n2, rng, modes=16, kmax=4, amplitude=0.3):
+    """Smooth periodic velocity from 'modes' random Fourier modes with 1 <= |k| <= kmax.
+
+    Wavevectors are drawn without replacement from the integer lattice
+    points in that annulus; each carries a complex 2-vector with standard
+    normal real and imaginary parts; the field is rescaled so that
+    max_{x,i} |v_i(x)| equals 'amplitude'.
+    """
+    cand = [(a, b) for a in range(-kmax, kmax + 1) for b in range(-kmax, kmax + 1)
+            if 1 <= a * a + b * b <= kmax * kmax]
+    pick = rng.choice(len(cand), size=modes, replace=False)
+    X1, X2 = grid_coords(n1, n2)
+    v = np.zeros((2, n1, n2))
+    for idx in pick:
+        a, b = cand[idx]
+        coef = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+        phase = np.exp(1j * (a * X1 + b * X2))
+        v[0] += (coef[0] * phase).real
+        v[1] += (coef[1] * phase).real
+    return v * (amplitude / float(np.max(np.abs(v))))
+
+
+CONFIGS = {
+    # name: grid, nt, regulariser order, beta, preconditioner, image recipe, velocity recipe, seed
+    "smooth64": dict(n1=64, n2=64, nt=4, reg=1, beta=1e-2, pc="reg", prec="fp64"),
+    "gauss256": dict(n1=256, n2=256, nt=4, reg=2, beta=1e-3, pc="2l", prec="mixed", seed=2),
+    "brain512": dict(n1=512, n2=512, nt=8, reg=1, beta=1e-3, pc="2l", prec="mixed", seed=3),
+}
+
+
+def config(name, n=None, seed=None):
+    """Inputs of one named problem: dict with sizes, parameters, m_T, v_gen and a direction vt.
+
+    'smooth64': the smooth analytic pair (m_T, v*) on 64^2 (or n^2).
+    'gauss256': 32 isotropic Gaussians, 16-mode velocity |k| <= 4, amplitude 0.3.
+    'brain512': 64 anisotropic smoothed Gaussians, 24-mode velocity |k| <= 6,
+                amplitude 0.5.
+    The direction vt (for Hessian matvecs) is a 16-mode |k| <= 4 field of
+    amplitude 0.1 from the seed + 1000 stream.
+    """
+    c = dict(CONFIGS[name])
+    if n is not None:
+        c["n1"] = c["n2"] = int(n)
+    n1, n2 = c["n1"], c["n2"]
+    s = c.get("seed", 1) if seed is None else seed
+    rng = np.random.default_rng(s)
+    if name == "smooth64":
+        c["mT"] = smooth_a_template(n1, n2)
+        c["v_gen"] = smooth_a_velocity(n1, n2)
+    elif name == "gauss256":
+        c["mT"] = gaussian_sum_isotropic(n1, n2, rng)
+        c["v_gen"] = random_velocity(n1, n2, rng, modes=16, kmax=4, amplitude=0.3)
+    elif name == "brain512":
+        c["mT"] = gaussian_sum_anisotropic(n1, n2, rng)
+        c["v_gen"] = random_velocity(n1, n2, rng, modes=24, kmax=6, amplitude=0.5)
+    else:
+        raise KeyError(name)
+    rng_t = np.random.default_rng(s + 1000)
+    c["vt"] = random_velocity(n1, n2, rng_t, modes=16, kmax=4, amplitude=0.1)
+    return c
