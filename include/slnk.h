@@ -1,0 +1,182 @@
+/* slnk.h -- C ABI of the MI355X (gfx950) semi-Lagrangian Newton--Krylov registration path.
+ *
+ * Method: Mang & Biros, "A semi-Lagrangian two-level preconditioned Newton--Krylov solver for
+ * constrained diffeomorphic image registration" (arXiv:1604.02153).  The library evaluates, on
+ * one GPU, the reduced-space quantities of the stationary-velocity registration problem
+ *     min_v  1/2 ||m(1) - m_R||^2 + beta/2 <v, A v>,   d_t m + v . grad m = 0,  m(0) = m_T
+ * (section 2, eq. e:varopt:objective without the mass-source term): the objective, the reduced
+ * gradient (eq. e:control-elim), the Gauss--Newton reduced Hessian matvec (eq. e:hessian-matvec
+ * with the lambda terms dropped, section 3.4.1), the preconditioners P_REG (eq. e:reg-precond) and
+ * P_2L (section 3.4.2, nested two-level preconditioner with a CHEB(k) coarse solve), and the
+ * globalised inexact Newton--PCG solve (sections 3.4.1, 3.5).  Every transport solve is the
+ * semi-Lagrangian scheme of section 3.3.2 (Heun trace, periodic cubic spline interpolation).
+ *
+ * Conventions shared by every entry point
+ *   - Grid: periodic [0, 2 pi)^2 with n1 x n2 nodes, x_i = 2 pi i / n_i.  A scalar field is a
+ *     row-major [n1][n2] array (i2 fastest); a vector field is two consecutive scalar fields
+ *     ([2][n1][n2]).  n1, n2 even, each a product of 2, 3, 5, at least 8 and at most 2048.
+ *   - Element type: double when params.prec == SLNK_PREC_FP64, float when SLNK_PREC_MIXED (fields
+ *     in FP32; every inner product, norm, objective and Chebyshev/Lanczos scalar in FP64).
+ *     Scalar outputs (J, norms, report) are always double.
+ *   - Memory: every field pointer is a DEVICE pointer owned by the caller (e.g. a torch tensor's
+ *     data pointer); the library never frees it.  The library owns its workspace, allocated in
+ *     slnk_create and released in slnk_destroy.
+ *   - Streams: all device work is enqueued on the stream given to slnk_create.  Calls returning
+ *     host scalars (J, the report, status of a solve) synchronise that stream; the others return
+ *     after enqueueing their work, except that any call may synchronise to read a scalar it needs
+ *     (the maximal displacement of a linearisation, the Chebyshev bounds).
+ *   - Errors: no exception crosses the ABI.  Every call returns an slnk_status; the message of
+ *     the last failure is available from slnk_last_error.  A context is used by one host thread
+ *     at a time.
+ */
+#ifndef SLNK_H
+#define SLNK_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct slnk_ctx slnk_ctx;
+
+typedef enum {
+  SLNK_OK = 0,
+  SLNK_EINVAL = 1,          /* invalid argument, size, or call order */
+  SLNK_ENOMEM = 2,          /* device allocation failed */
+  SLNK_EDEVICE = 3,         /* HIP runtime error (message in slnk_last_error) */
+  SLNK_ENAN = 4,            /* non-finite value in an input or an intermediate */
+  SLNK_ELINESEARCH = 5,     /* Armijo backtracking found no acceptable step */
+  SLNK_ENEGCURV = 6,        /* PCG met non-positive curvature (informational in the report) */
+  SLNK_EMAXIT = 7,          /* iteration limit reached (informational in the report) */
+  SLNK_ECHEB_DIVERGED = 8   /* reserved */
+} slnk_status;
+
+typedef enum { SLNK_REG_H1 = 1, SLNK_REG_H2 = 2, SLNK_REG_H3 = 3 } slnk_reg;
+typedef enum { SLNK_PREC_FP64 = 0, SLNK_PREC_MIXED = 1 } slnk_prec;
+typedef enum { SLNK_PC_REG = 1, SLNK_PC_2L = 2 } slnk_pc;
+
+/* Problem and solver parameters (section 3.5 lists the paper's settings).
+ *   nt            number of SL time steps on [0, 1] (ht = 1/nt), >= 1
+ *   reg           regularisation seminorm H1/H2/H3: A = -Lap, Lap^2, -Lap^3 (eq. e:diffopregv)
+ *   beta          regularisation weight beta_v > 0
+ *   prec          element type of every field (see above)
+ *   pc            SLNK_PC_REG: PCG on H with P_REG; SLNK_PC_2L: PCG on the split system
+ *                 (I + S Q S) s = -S g, S = (beta A')^{-1/2}, with P_2L; coarse grid n/2
+ *   cheb_iters    k of CHEB(k) (k steps, k - 1 coarse operator applications); paper: 10
+ *   lanczos_steps Lanczos steps for e_max at v = 0 (paper: about 30)
+ *   emax_safety   e_max = emax_safety * largest Ritz value (>= 1)
+ *   lanczos_seed  seed of the SplitMix64 start vector of the Lanczos iteration
+ * The compressible case (projection K = identity) is the one implemented. */
+typedef struct {
+  int n1, n2, nt;
+  int reg;
+  double beta;
+  int prec;
+  int pc;
+  int cheb_iters;
+  int lanczos_steps;
+  double emax_safety;
+  unsigned long long lanczos_seed;
+} slnk_params;
+
+/* Newton--Krylov options (sections 3.4.1, 3.5).  Stop when ||g||_inf / ||g_0||_inf <= gtol_rel or
+ * ||g||_inf <= gtol_abs (g_0: gradient at v = 0) or after max_newton iterations.  PCG runs from
+ * zero with the forcing term eta_k = min(0.5, ||g_k||_2 / ||g_0||_2) for at most max_pcg steps.
+ * Armijo: alpha = 1 halved at most max_halvings times until
+ * J(v + alpha vt) <= J(v) + armijo_c1 * alpha * <g, vt>_L2. */
+typedef struct {
+  int max_newton;
+  double gtol_rel;
+  double gtol_abs;
+  int max_pcg;
+  double armijo_c1;
+  int max_halvings;
+} slnk_solve_opts;
+
+#define SLNK_REPORT_MAX_ITERS 64
+
+/* Solve report.  grel[k], J[k], pcg[k] for k <= newton_iters (grel[0] = 1 for a cold start). */
+typedef struct {
+  int status;               /* slnk_status of the solve */
+  int newton_iters;
+  int pcg_iters;            /* total over all Newton steps */
+  int matvecs;              /* fine-grid Hessian (or split operator) applications */
+  int coarse_matvecs;       /* coarse-grid split operator applications inside P_2L */
+  int line_search_evals;    /* objective evaluations at trial points */
+  double g0_inf, g0_two;    /* norms of the gradient at v = 0 */
+  double emin, emax;        /* Chebyshev bounds (P_2L) */
+  double grel[SLNK_REPORT_MAX_ITERS + 1];
+  double J[SLNK_REPORT_MAX_ITERS + 1];
+  int pcg[SLNK_REPORT_MAX_ITERS + 1];
+  double time_total_ms;
+  double time_gradient_ms;  /* linearisations + adjoint solves */
+  double time_pcg_ms;       /* Krylov solves including preconditioner */
+  double time_precond_ms;   /* preconditioner applications */
+  double time_linesearch_ms;
+} slnk_solve_report;
+
+/* Default parameters / options (paper settings: CHEB(10), 30 Lanczos steps, gtol 1e-2, 1e-5). */
+void slnk_default_params(slnk_params* p);
+void slnk_default_opts(slnk_solve_opts* o);
+
+/* Create a context on the current HIP device.  'hip_stream' is a hipStream_t (NULL: the null
+ * stream).  Allocates the whole workspace; EINVAL on unsupported sizes, ENOMEM on failure. */
+slnk_status slnk_create(const slnk_params* params, void* hip_stream, slnk_ctx** out);
+void slnk_destroy(slnk_ctx* ctx);
+const char* slnk_last_error(const slnk_ctx* ctx);
+/* Bytes of device workspace the context owns. */
+unsigned long long slnk_workspace_bytes(const slnk_ctx* ctx);
+
+/* Set the reference m_R and template m_T ([n1][n2] each, device).  Copies them; for P_2L also
+ * builds the coarse problem (spectral restriction of both images) and the Chebyshev bounds:
+ * e_max from Lanczos on the coarse split operator at v = 0, e_min = min_k 1 + 1/(beta a'(k))
+ * (section 3.4.2, eigenvalue estimates).  ENAN if an image holds a non-finite value. */
+slnk_status slnk_set_images(slnk_ctx* ctx, const void* m_R, const void* m_T);
+
+/* m1 = m(1) for the initial value m0 transported by the stationary velocity v (state equation,
+ * eq. e:state-slm, nt SL steps).  v [2][n1][n2], m0 and m1 [n1][n2]; may be called before
+ * slnk_set_images.  Does not change the linearisation point. */
+slnk_status slnk_transport_state(slnk_ctx* ctx, const void* v, const void* m0, void* m1);
+
+/* J[v] (eq. e:varopt:objective).  Makes v the linearisation point. */
+slnk_status slnk_objective(slnk_ctx* ctx, const void* v, double* J);
+
+/* Reduced gradient g = beta A v + int_0^1 lambda grad m dt (eq. e:control-elim) into g
+ * [2][n1][n2]; J receives the objective (may be NULL).  Makes v the linearisation point of the
+ * Hessian and, with P_2L, of the coarse problem. */
+slnk_status slnk_gradient(slnk_ctx* ctx, const void* v, void* g, double* J);
+
+/* Hvt = beta A vt + int_0^1 lambda~ grad m dt, the Gauss--Newton matvec (eqs. e:hessian-matvec,
+ * e:inc-state-slm, e:inc-adj-slm) at the last linearisation point.  EINVAL before any
+ * slnk_gradient. */
+slnk_status slnk_hessian_matvec(slnk_ctx* ctx, const void* vt, void* Hvt);
+
+/* out = (I + S Q S) s, the split spectrally preconditioned GN Hessian (section 3.4.2) at the
+ * last linearisation point (the operator P_2L preconditions). */
+slnk_status slnk_split_matvec(slnk_ctx* ctx, const void* s, void* out);
+
+/* z = P^{-1} r.  SLNK_PC_REG: P_REG^{-1} = (beta A')^{-1} (eq. e:reg-precond).  SLNK_PC_2L:
+ * P_2L^{-1} r = (I - L) r + Pro CHEB_k(M_c) Res r at the last linearisation point (section 3.4.2),
+ * acting on the split variable.  EINVAL for P_2L before any slnk_gradient. */
+slnk_status slnk_precond_apply(slnk_ctx* ctx, const void* r, void* z);
+
+/* Chebyshev bounds of P_2L (after slnk_set_images). */
+slnk_status slnk_get_cheb_bounds(const slnk_ctx* ctx, double* emin, double* emax);
+
+/* Copy an internal field of the current linearisation into 'out' (device, element type as
+ * above): which = 0: m(1) [n1][n2]; 1: forward displacements [2][n1][n2] in cells;
+ * 2: adjoint displacements; 3: adjoint step factor gamma [n1][n2]; 4: lambda(0) of the last
+ * gradient [n1][n2]. */
+slnk_status slnk_get_field(slnk_ctx* ctx, int which, void* out);
+
+/* Globalised inexact GN--Krylov solve from the velocity in v_inout (device [2][n1][n2]); the
+ * result overwrites it.  opts NULL: defaults.  report may be NULL.  Returns SLNK_OK when a stop
+ * criterion was met or the Newton limit was reached, SLNK_ELINESEARCH when backtracking failed
+ * (v_inout then holds the last accepted iterate). */
+slnk_status slnk_newton_solve(slnk_ctx* ctx, void* v_inout, const slnk_solve_opts* opts,
+                              slnk_solve_report* report);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLNK_H */

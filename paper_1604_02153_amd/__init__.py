@@ -1,0 +1,214 @@
+"""Python binding of libslnk.so, the MI355X (gfx950) semi-Lagrangian Newton--Krylov path.
+
+Argument marshalling only: every step of the method runs in the HIP library behind the C ABI of
+include/slnk.h.  Fields are torch tensors on the GPU (float32 for the mixed-precision context,
+float64 for the FP64 context); PyTorch provides device memory and the stream, nothing else.
+There is no CPU fallback: without the built library every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["Context", "library_path", "load_library", "SolveOpts", "STATUS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+STATUS = {0: "SLNK_OK", 1: "SLNK_EINVAL", 2: "SLNK_ENOMEM", 3: "SLNK_EDEVICE", 4: "SLNK_ENAN",
+          5: "SLNK_ELINESEARCH", 6: "SLNK_ENEGCURV", 7: "SLNK_EMAXIT", 8: "SLNK_ECHEB_DIVERGED"}
+REG = {"h1": 1, "h2": 2, "h3": 3}
+PREC = {"fp64": 0, "mixed": 1}
+PC = {"reg": 1, "2l": 2}
+REPORT_MAX = 64
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n1", ctypes.c_int), ("n2", ctypes.c_int), ("nt", ctypes.c_int), ("reg", ctypes.c_int),
+                ("beta", ctypes.c_double), ("prec", ctypes.c_int), ("pc", ctypes.c_int),
+                ("cheb_iters", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
+                ("emax_safety", ctypes.c_double), ("lanczos_seed", ctypes.c_ulonglong)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("max_newton", ctypes.c_int), ("gtol_rel", ctypes.c_double), ("gtol_abs", ctypes.c_double),
+                ("max_pcg", ctypes.c_int), ("armijo_c1", ctypes.c_double), ("max_halvings", ctypes.c_int)]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("newton_iters", ctypes.c_int), ("pcg_iters", ctypes.c_int),
+                ("matvecs", ctypes.c_int), ("coarse_matvecs", ctypes.c_int), ("line_search_evals", ctypes.c_int),
+                ("g0_inf", ctypes.c_double), ("g0_two", ctypes.c_double), ("emin", ctypes.c_double),
+                ("emax", ctypes.c_double), ("grel", ctypes.c_double * (REPORT_MAX + 1)),
+                ("J", ctypes.c_double * (REPORT_MAX + 1)), ("pcg", ctypes.c_int * (REPORT_MAX + 1)),
+                ("time_total_ms", ctypes.c_double), ("time_gradient_ms", ctypes.c_double),
+                ("time_pcg_ms", ctypes.c_double), ("time_precond_ms", ctypes.c_double),
+                ("time_linesearch_ms", ctypes.c_double)]
+
+
+EXPORTS = ["slnk_default_params", "slnk_default_opts", "slnk_create", "slnk_destroy", "slnk_last_error",
+           "slnk_workspace_bytes", "slnk_set_images", "slnk_transport_state", "slnk_objective", "slnk_gradient",
+           "slnk_hessian_matvec", "slnk_split_matvec", "slnk_precond_apply", "slnk_get_cheb_bounds",
+           "slnk_get_field", "slnk_newton_solve"]
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libslnk.so")
+
+
+def load_library():
+    """Load libslnk.so (built by paper_1604_02153_amd.build); raises if it is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1604_02153_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, V = ctypes.POINTER, ctypes.c_void_p
+    sig = {
+        "slnk_default_params": (None, [P(Params)]),
+        "slnk_default_opts": (None, [P(SolveOpts)]),
+        "slnk_create": (ctypes.c_int, [P(Params), V, P(V)]),
+        "slnk_destroy": (None, [V]),
+        "slnk_last_error": (ctypes.c_char_p, [V]),
+        "slnk_workspace_bytes": (ctypes.c_ulonglong, [V]),
+        "slnk_set_images": (ctypes.c_int, [V, V, V]),
+        "slnk_transport_state": (ctypes.c_int, [V, V, V, V]),
+        "slnk_objective": (ctypes.c_int, [V, V, P(ctypes.c_double)]),
+        "slnk_gradient": (ctypes.c_int, [V, V, V, P(ctypes.c_double)]),
+        "slnk_hessian_matvec": (ctypes.c_int, [V, V, V]),
+        "slnk_split_matvec": (ctypes.c_int, [V, V, V]),
+        "slnk_precond_apply": (ctypes.c_int, [V, V, V]),
+        "slnk_get_cheb_bounds": (ctypes.c_int, [V, P(ctypes.c_double), P(ctypes.c_double)]),
+        "slnk_get_field": (ctypes.c_int, [V, ctypes.c_int, V]),
+        "slnk_newton_solve": (ctypes.c_int, [V, V, P(SolveOpts), P(SolveReport)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+class SlnkError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    load_library().slnk_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """One registration problem on the current GPU (see include/slnk.h for every call)."""
+
+    def __init__(self, n1, n2, nt, reg="h2", beta=1e-3, prec="mixed", pc="2l", cheb_iters=10,
+                 lanczos_steps=30, emax_safety=1.05, lanczos_seed=0x5EED, stream=None):
+        import torch
+        lib = load_library()
+        p = Params()
+        lib.slnk_default_params(ctypes.byref(p))
+        p.n1, p.n2, p.nt = int(n1), int(n2), int(nt)
+        p.reg = REG[reg] if isinstance(reg, str) else int(reg)
+        p.beta = float(beta)
+        p.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+        p.pc = PC[pc] if isinstance(pc, str) else int(pc)
+        p.cheb_iters, p.lanczos_steps = int(cheb_iters), int(lanczos_steps)
+        p.emax_safety, p.lanczos_seed = float(emax_safety), int(lanczos_seed)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.dtype = torch.float64 if p.prec == 0 else torch.float32
+        self.shape = (p.n1, p.n2)
+        self.params = p
+        self._lib = lib
+        self._ctx = ctypes.c_void_p()
+        self._check(lib.slnk_create(ctypes.byref(p), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(self._ctx)))
+
+    # -- helpers --------------------------------------------------------------------------------
+    def _check(self, st):
+        if st != 0:
+            msg = self._lib.slnk_last_error(self._ctx).decode() if self._ctx else ""
+            raise SlnkError(st, msg)
+
+    def _ptr(self, t, ncomp):
+        shape = self.shape if ncomp == 1 else (ncomp,) + self.shape
+        if not t.is_cuda or t.dtype != self.dtype or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous {self.dtype} CUDA tensor of shape {shape}, got "
+                             f"{t.dtype} {tuple(t.shape)} on {t.device}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def close(self):
+        if self._ctx:
+            self._lib.slnk_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- C ABI ---------------------------------------------------------------------------------
+    def workspace_bytes(self) -> int:
+        return int(self._lib.slnk_workspace_bytes(self._ctx))
+
+    def set_images(self, m_R, m_T):
+        self._check(self._lib.slnk_set_images(self._ctx, self._ptr(m_R, 1), self._ptr(m_T, 1)))
+
+    def transport_state(self, v, m0, m1):
+        self._check(self._lib.slnk_transport_state(self._ctx, self._ptr(v, 2), self._ptr(m0, 1), self._ptr(m1, 1)))
+
+    def objective(self, v) -> float:
+        J = ctypes.c_double()
+        self._check(self._lib.slnk_objective(self._ctx, self._ptr(v, 2), ctypes.byref(J)))
+        return J.value
+
+    def gradient(self, v, g) -> float:
+        J = ctypes.c_double()
+        self._check(self._lib.slnk_gradient(self._ctx, self._ptr(v, 2), self._ptr(g, 2), ctypes.byref(J)))
+        return J.value
+
+    def hessian_matvec(self, vt, out):
+        self._check(self._lib.slnk_hessian_matvec(self._ctx, self._ptr(vt, 2), self._ptr(out, 2)))
+
+    def split_matvec(self, s, out):
+        self._check(self._lib.slnk_split_matvec(self._ctx, self._ptr(s, 2), self._ptr(out, 2)))
+
+    def precond_apply(self, r, z):
+        self._check(self._lib.slnk_precond_apply(self._ctx, self._ptr(r, 2), self._ptr(z, 2)))
+
+    def cheb_bounds(self):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.slnk_get_cheb_bounds(self._ctx, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def get_field(self, which, out):
+        ncomp = 2 if which in (1, 2) else 1
+        self._check(self._lib.slnk_get_field(self._ctx, int(which), self._ptr(out, ncomp)))
+
+    def newton_solve(self, v, opts: SolveOpts | None = None, **kw) -> dict:
+        if opts is None:
+            opts = default_opts(**kw)
+        rep = SolveReport()
+        st = self._lib.slnk_newton_solve(self._ctx, self._ptr(v, 2), ctypes.byref(opts), ctypes.byref(rep))
+        if st not in (0, 5):
+            self._check(st)
+        k = rep.newton_iters
+        return {
+            "status": STATUS.get(st, st), "newton_iters": k, "pcg_iters": rep.pcg_iters, "matvecs": rep.matvecs,
+            "coarse_matvecs": rep.coarse_matvecs, "line_search_evals": rep.line_search_evals,
+            "g0_inf": rep.g0_inf, "g0_two": rep.g0_two, "emin": rep.emin, "emax": rep.emax,
+            "grel": list(rep.grel[: k + 1]), "J": list(rep.J[: k + 1]), "pcg": list(rep.pcg[:k]),
+            "time_total_ms": rep.time_total_ms, "time_gradient_ms": rep.time_gradient_ms,
+            "time_pcg_ms": rep.time_pcg_ms, "time_precond_ms": rep.time_precond_ms,
+            "time_linesearch_ms": rep.time_linesearch_ms,
+        }

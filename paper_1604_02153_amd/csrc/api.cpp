@@ -1,0 +1,949 @@
+// Host orchestration of the semi-Lagrangian Gauss--Newton--Krylov path behind the C ABI of
+// include/slnk.h.  Everything numerical runs in the gfx950 kernels of spectral.hip,
+// transport.hip and blas.hip; this file sequences them, owns the device workspace and keeps the
+// FP64 scalars of the Krylov, Chebyshev, Lanczos and Newton iterations.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/slnk.h"
+#include "kernels.hpp"
+
+namespace slnk {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct Fail {
+  slnk_status st;
+  std::string msg;
+};
+
+#define HIPCHK(expr)                                                                                  \
+  do {                                                                                                \
+    hipError_t _e = (expr);                                                                           \
+    if (_e != hipSuccess) throw ::slnk::Fail{SLNK_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)}; \
+  } while (0)
+
+bool fft_size_ok(int n) {
+  if (n < 8 || n > 2048 || (n & 1)) return false;
+  for (int r : {2, 3, 5})
+    while (n % r == 0) n /= r;
+  return n == 1;
+}
+
+std::vector<int> factorise(int n) {
+  std::vector<int> r;
+  while (n % 4 == 0) r.push_back(4), n /= 4;
+  while (n % 2 == 0) r.push_back(2), n /= 2;
+  while (n % 3 == 0) r.push_back(3), n /= 3;
+  while (n % 5 == 0) r.push_back(5), n /= 5;
+  return r;
+}
+
+double trapezoid_weight(int j, int nt) {  // weight of level j times ht
+  const double ht = 1.0 / nt;
+  return (j == 0 || j == nt) ? 0.5 * ht : ht;
+}
+
+// Largest eigenvalue of the symmetric tridiagonal matrix (diag a, off-diagonal b) by bisection on
+// the Sturm sequence count.
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  const int n = int(a.size());
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {  // eigenvalues < x
+    int c = 0;
+    double d = 1.0;
+    for (int i = 0; i < n; ++i) {
+      const double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+      d = a[i] - x - (i > 0 ? bb / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) == n)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return hi;
+}
+
+std::vector<double> splitmix64_uniform(unsigned long long seed, size_t count) {
+  std::vector<double> out(count);
+  unsigned long long state = seed;
+  for (size_t i = 0; i < count; ++i) {
+    state += 0x9E3779B97F4A7C15ULL;
+    unsigned long long z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z = z ^ (z >> 31);
+    out[i] = double(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+  }
+  return out;
+}
+
+// Bump allocator over one device allocation.
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  template <typename U>
+  U* take(size_t count) {
+    const size_t bytes = (count * sizeof(U) + 255) / 256 * 256;
+    if (used + bytes > size) throw Fail{SLNK_ENOMEM, "workspace arena exhausted"};
+    U* p = reinterpret_cast<U*>(base + used);
+    used += bytes;
+    return p;
+  }
+};
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// --------------------------------------------------------------------------------------------
+template <typename T>
+struct Level {
+  int n1 = 0, n2 = 0, nt = 0;
+  size_t F = 0;
+  double h1 = 0, h2 = 0, cell = 0;
+  SpecGrid<T> sg;
+  T* mT = nullptr;
+  T* mR = nullptr;
+  struct Lin {
+    T* v = nullptr;      // 2F
+    T* df = nullptr;     // 2F  forward displacements (cells)
+    T* da = nullptr;     // 2F  adjoint displacements
+    T* gamma = nullptr;  // F
+    T* m = nullptr;      // (nt+1) F
+    T* gm = nullptr;     // 2 (nt+1) F
+    T* bAv = nullptr;    // 2F
+    double J = 0, Jmis = 0, Jreg = 0;
+    int halo = 0;
+    bool valid = false, has_gm = false;
+  } lin[2];
+  int cur = 0;
+  // work buffers
+  T* cv = nullptr;    // 2F
+  T* divv = nullptr;  // F
+  T* cdiv = nullptr;  // F
+  T* lam = nullptr;   // 2F (ping-pong)
+  T* acc = nullptr;   // 2F
+  T* g = nullptr;     // 2F
+  T* q = nullptr;     // 2F (ping-pong)
+  T* bt = nullptr;    // 2F
+  T* w = nullptr;     // 2F
+  T* coef = nullptr;  // F
+  T* vec[8] = {};     // 8 x 2F Krylov / Chebyshev / Lanczos vectors
+  T* gmT = nullptr;   // 2F gradient of m_T (Lanczos at v = 0)
+  cplx<T>* S1 = nullptr;
+  cplx<T>* S2 = nullptr;
+  cplx<T>* Sk = nullptr;  // kept spectrum (2 spec) for the two-level combine
+  void* tw_row = nullptr;
+  void* tw_col = nullptr;
+  Lin& L() { return lin[cur]; }
+};
+
+template <typename T>
+struct Context {
+  slnk_params prm{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  Arena arena;
+  Level<T> fine, coarse;
+  bool two_level = false;
+  bool images_set = false;
+  bool has_grad = false;
+  double emin = 0, emax = 0;
+  double* partial = nullptr;  // reduction partials
+  double* dres = nullptr;     // device results (32 doubles)
+  double* hres = nullptr;     // pinned host copy
+  int partial_cap = 0;
+  // counters for the current solve
+  int n_matvec = 0, n_coarse = 0;
+  double t_prec = 0;
+
+  // ---- setup ------------------------------------------------------------------------------
+  void plan(FFTPlanDev& pl, int n, void*& tw) {
+    std::vector<int> r = factorise(n);
+    if (int(r.size()) > kFFTMaxStages) throw Fail{SLNK_EINVAL, "FFT length has too many factors"};
+    pl.n = n;
+    pl.nstages = int(r.size());
+    for (size_t i = 0; i < r.size(); ++i) pl.radix[i] = r[i];
+    std::vector<cplx<T>> h(n);
+    for (int q = 0; q < n; ++q) {
+      const double a = 2.0 * kPi * double(q) / double(n);
+      h[q] = {T(std::cos(a)), T(-std::sin(a))};
+    }
+    tw = arena.take<cplx<T>>(n);
+    HIPCHK(hipMemcpy(tw, h.data(), n * sizeof(cplx<T>), hipMemcpyHostToDevice));
+    pl.tw = tw;
+  }
+
+  static size_t level_bytes(int n1, int n2, int nt) {
+    const size_t F = size_t(n1) * n2;
+    const size_t spec = size_t(n1) * (n2 / 2 + 1);
+    const size_t nspec = std::max<size_t>(6, 2 * (nt + 1));
+    size_t fields = 2 /*images*/ + 2 * (2 + 2 + 1 + (nt + 1) + 2 * (nt + 1) + 2) + 2 + 1 + 1 + 2 * 8 + 16 + 2 + 2;
+    return fields * F * sizeof(T) + (2 * nspec + 2) * spec * sizeof(cplx<T>) + (n1 + n2) * sizeof(cplx<T>) +
+           64 * 256;
+  }
+
+  void alloc_level(Level<T>& lv, int n1, int n2, int nt) {
+    lv.n1 = n1;
+    lv.n2 = n2;
+    lv.nt = nt;
+    lv.F = size_t(n1) * n2;
+    lv.h1 = 2.0 * kPi / n1;
+    lv.h2 = 2.0 * kPi / n2;
+    lv.cell = lv.h1 * lv.h2;
+    lv.sg.n1 = n1;
+    lv.sg.n2 = n2;
+    plan(lv.sg.row, n2, lv.tw_row);
+    plan(lv.sg.col, n1, lv.tw_col);
+    const size_t F = lv.F;
+    lv.mT = arena.take<T>(F);
+    lv.mR = arena.take<T>(F);
+    for (auto& L : lv.lin) {
+      L.v = arena.take<T>(2 * F);
+      L.df = arena.take<T>(2 * F);
+      L.da = arena.take<T>(2 * F);
+      L.gamma = arena.take<T>(F);
+      L.m = arena.take<T>((nt + 1) * F);
+      L.gm = arena.take<T>(2 * (nt + 1) * F);
+      L.bAv = arena.take<T>(2 * F);
+    }
+    lv.cv = arena.take<T>(2 * F);
+    lv.divv = arena.take<T>(F);
+    lv.cdiv = arena.take<T>(F);
+    lv.lam = arena.take<T>(2 * F);
+    lv.acc = arena.take<T>(2 * F);
+    lv.g = arena.take<T>(2 * F);
+    lv.q = arena.take<T>(2 * F);
+    lv.bt = arena.take<T>(2 * F);
+    lv.w = arena.take<T>(2 * F);
+    lv.coef = arena.take<T>(F);
+    for (auto& p : lv.vec) p = arena.take<T>(2 * F);
+    lv.gmT = arena.take<T>(2 * F);
+    const size_t nspec = std::max<size_t>(6, 2 * (nt + 1));
+    lv.S1 = arena.take<cplx<T>>(nspec * lv.sg.spec());
+    lv.S2 = arena.take<cplx<T>>(nspec * lv.sg.spec());
+    lv.Sk = arena.take<cplx<T>>(2 * lv.sg.spec());
+  }
+
+  void create(const slnk_params& p, hipStream_t s) {
+    prm = p;
+    stream = s;
+    if (!fft_size_ok(p.n1) || !fft_size_ok(p.n2)) throw Fail{SLNK_EINVAL, "grid sizes must be even products of 2, 3, 5 in [8, 2048]"};
+    if (p.nt < 1 || p.nt > 512) throw Fail{SLNK_EINVAL, "nt must be in [1, 512]"};
+    if (p.reg < 1 || p.reg > 3) throw Fail{SLNK_EINVAL, "reg must be 1, 2 or 3"};
+    if (!(p.beta > 0)) throw Fail{SLNK_EINVAL, "beta must be positive"};
+    if (p.pc != SLNK_PC_REG && p.pc != SLNK_PC_2L) throw Fail{SLNK_EINVAL, "pc must be SLNK_PC_REG or SLNK_PC_2L"};
+    two_level = p.pc == SLNK_PC_2L;
+    if (two_level) {
+      if (!fft_size_ok(p.n1 / 2) || !fft_size_ok(p.n2 / 2)) throw Fail{SLNK_EINVAL, "coarse grid n/2 not supported"};
+      if (p.cheb_iters < 1 || p.lanczos_steps < 2 || !(p.emax_safety >= 1.0)) throw Fail{SLNK_EINVAL, "bad P_2L parameters"};
+    }
+    size_t bytes = level_bytes(p.n1, p.n2, p.nt) + (two_level ? level_bytes(p.n1 / 2, p.n2 / 2, p.nt) : 0);
+    const size_t F = size_t(p.n1) * p.n2;
+    const int tiles = ((p.n1 + 15) / 16) * ((p.n2 + 15) / 16);  // blocks of the 16x16 transport kernels
+    partial_cap = std::max(reduce_blocks(2 * F), tiles) * 4 + 64;
+    bytes += partial_cap * sizeof(double) + 64 * sizeof(double) + 4096;
+    void* base = nullptr;
+    if (hipMalloc(&base, bytes) != hipSuccess) throw Fail{SLNK_ENOMEM, "hipMalloc of the workspace failed"};
+    arena.base = static_cast<char*>(base);
+    arena.size = bytes;
+    partial = arena.take<double>(partial_cap);
+    dres = arena.take<double>(64);
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hres), 64 * sizeof(double), hipHostMallocDefault));
+    alloc_level(fine, p.n1, p.n2, p.nt);
+    if (two_level) alloc_level(coarse, p.n1 / 2, p.n2 / 2, p.nt);
+  }
+
+  void destroy() {
+    if (hres) (void)hipHostFree(hres);
+    if (arena.base) (void)hipFree(arena.base);
+    hres = nullptr;
+    arena.base = nullptr;
+  }
+
+  // read n doubles of dres to the host
+  const double* fetch(int n) {
+    HIPCHK(hipMemcpyAsync(hres, dres, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    return hres;
+  }
+
+  SymbolParams sym(Symbol k) const { return SymbolParams{k, prm.reg, prm.beta}; }
+
+  // ---- linearisation: trace, state, objective ---------------------------------------------
+  // v (device, 2F of T) becomes lin[slot].v; J is computed; grad m is not (see ensure_gm).
+  void linearize(Level<T>& lv, int slot, const T* v, bool need_J = true) {
+    auto& L = lv.lin[slot];
+    const size_t F = lv.F;
+    if (v != L.v) HIPCHK(hipMemcpyAsync(L.v, v, 2 * F * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    HIPCHK(spec_trace_prep<T>(stream, lv.sg, prm.reg, prm.beta, L.v, lv.cv, lv.divv, lv.cdiv, L.bAv, lv.S1, lv.S2));
+    int nb = 0;
+    const double ht = 1.0 / lv.nt;
+    HIPCHK(sl_trace<T>(stream, lv.n1, lv.n2, ht, L.v, lv.cv, lv.divv, lv.cdiv, L.bAv, L.df, L.da, L.gamma, partial, &nb));
+    HIPCHK(finish(stream, nb, 2, 2, 2u, partial, dres));
+    const double* r = fetch(2);
+    const double vAv = r[0], maxd = r[1];
+    if (!std::isfinite(maxd) || !std::isfinite(vAv)) throw Fail{SLNK_ENAN, "non-finite velocity or displacement"};
+    L.halo = int(std::ceil(maxd));
+    L.Jreg = 0.5 * lv.cell * vAv;
+    // state equation
+    HIPCHK(hipMemcpyAsync(L.m, lv.mT, F * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    for (int j = 1; j <= lv.nt; ++j) {
+      StepArgs<T> a;
+      a.n1 = lv.n1;
+      a.n2 = lv.n2;
+      a.halo = L.halo;
+      a.src = L.m + (j - 1) * F;
+      a.dst = L.m + j * F;
+      a.d1 = L.df;
+      a.d2 = L.df + F;
+      a.aux0 = lv.mR;
+      a.ht = ht;
+      a.last = (j == lv.nt) && need_J;
+      a.partial = partial;
+      a.coef = lv.coef;
+      HIPCHK(sl_step<T>(stream, StepKind::State, a, &nb));
+    }
+    if (need_J) {
+      HIPCHK(finish(stream, nb, 2, 1, 0u, partial, dres));
+      const double mis = fetch(1)[0];
+      if (!std::isfinite(mis)) throw Fail{SLNK_ENAN, "non-finite state"};
+      L.Jmis = 0.5 * lv.cell * mis;
+      L.J = L.Jmis + L.Jreg;
+    }
+    L.valid = true;
+    L.has_gm = false;
+  }
+
+  void ensure_gm(Level<T>& lv) {
+    auto& L = lv.L();
+    if (L.has_gm) return;
+    HIPCHK(spec_grad<T>(stream, lv.sg, lv.nt + 1, L.m, L.gm, lv.S1, lv.S2));
+    L.has_gm = true;
+  }
+
+  // adjoint solve + gradient; returns {sum g^2, max |g|} on the host
+  void gradient(Level<T>& lv, double* g2, double* ginf) {
+    auto& L = lv.L();
+    ensure_gm(lv);
+    const size_t F = lv.F;
+    const int nt = lv.nt;
+    const double ht = 1.0 / nt;
+    int nb = 0;
+    for (int j = nt; j >= 1; --j) {
+      StepArgs<T> a;
+      a.n1 = lv.n1;
+      a.n2 = lv.n2;
+      a.halo = L.halo;
+      a.first = j == nt;
+      a.last = j == 1;
+      a.src = a.first ? nullptr : lv.lam + (j % 2) * F;
+      a.aux0 = lv.mR;
+      a.aux1 = L.m + nt * F;
+      a.dst = lv.lam + ((j - 1) % 2) * F;
+      a.d1 = L.da;
+      a.d2 = L.da + F;
+      a.gamma = L.gamma;
+      a.gm_new = L.gm + 2 * (j - 1) * F;
+      a.gm_old = L.gm + 2 * nt * F;
+      a.w_new = trapezoid_weight(j - 1, nt);
+      a.w_old = trapezoid_weight(nt, nt);
+      a.acc = lv.acc;
+      a.addf = L.bAv;
+      a.out2 = lv.g;
+      a.ht = ht;
+      a.partial = partial;
+      a.coef = lv.coef;
+      HIPCHK(sl_step<T>(stream, StepKind::Adjoint, a, &nb));
+    }
+    HIPCHK(finish(stream, nb, 2, 2, 2u, partial, dres));
+    const double* r = fetch(2);
+    *g2 = r[0];
+    *ginf = r[1];
+    if (!std::isfinite(*g2)) throw Fail{SLNK_ENAN, "non-finite gradient"};
+  }
+
+  // bt = Q[vt] (the transport part of the GN matvec) at the current linearisation of lv
+  void gn_transport(Level<T>& lv, const T* vt) {
+    auto& L = lv.L();
+    ensure_gm(lv);
+    const size_t F = lv.F;
+    const int nt = lv.nt;
+    const double ht = 1.0 / nt;
+    int nb = 0;
+    for (int j = 1; j <= nt; ++j) {  // incremental state, forward
+      StepArgs<T> a;
+      a.n1 = lv.n1;
+      a.n2 = lv.n2;
+      a.halo = L.halo;
+      a.first = j == 1;
+      a.last = j == nt;
+      a.src = a.first ? nullptr : lv.q + ((j - 1) % 2) * F;
+      a.dst = lv.q + (j % 2) * F;
+      a.d1 = L.df;
+      a.d2 = L.df + F;
+      a.vt = vt;
+      a.gm_old = L.gm;
+      a.gm_new = L.gm + 2 * j * F;
+      a.w_new = trapezoid_weight(nt, nt);
+      a.acc = lv.bt;
+      a.ht = ht;
+      a.coef = lv.coef;
+      HIPCHK(sl_step<T>(stream, StepKind::IncState, a, &nb));
+    }
+    for (int j = nt; j >= 1; --j) {  // incremental adjoint, backward
+      StepArgs<T> a;
+      a.n1 = lv.n1;
+      a.n2 = lv.n2;
+      a.halo = L.halo;
+      a.src = lv.q + (j % 2) * F;
+      a.dst = j > 1 ? lv.q + ((j - 1) % 2) * F : nullptr;
+      a.d1 = L.da;
+      a.d2 = L.da + F;
+      a.gamma = L.gamma;
+      a.gm_new = L.gm + 2 * (j - 1) * F;
+      a.w_new = trapezoid_weight(j - 1, nt);
+      a.acc = lv.bt;
+      a.ht = ht;
+      a.coef = lv.coef;
+      HIPCHK(sl_step<T>(stream, StepKind::IncAdjoint, a, &nb));
+    }
+  }
+
+  // out = beta A vt + Q vt
+  void hessian(Level<T>& lv, const T* vt, T* out) {
+    gn_transport(lv, vt);
+    HIPCHK(spec_scale<T>(stream, lv.sg, sym(Symbol::Reg), 2, vt, out, lv.bt, lv.S1, lv.S2));
+  }
+
+  // out = s + S Q S s
+  void split_matvec(Level<T>& lv, const T* s, T* out) {
+    HIPCHK(spec_scale<T>(stream, lv.sg, sym(Symbol::RegInvSqrt), 2, s, lv.w, nullptr, lv.S1, lv.S2));
+    gn_transport(lv, lv.w);
+    HIPCHK(spec_scale<T>(stream, lv.sg, sym(Symbol::RegInvSqrt), 2, lv.bt, out, s, lv.S1, lv.S2));
+  }
+
+  // out = s + S Q(0) S s on the coarse level (closed form of the v = 0 operator)
+  void split_matvec_zero(Level<T>& lv, const T* s, T* out) {
+    HIPCHK(spec_scale<T>(stream, lv.sg, sym(Symbol::RegInvSqrt), 2, s, lv.w, nullptr, lv.S1, lv.S2));
+    HIPCHK(q_at_zero<T>(stream, lv.F, lv.w, lv.gmT, 1.0, lv.bt));
+    HIPCHK(spec_scale<T>(stream, lv.sg, sym(Symbol::RegInvSqrt), 2, lv.bt, out, s, lv.S1, lv.S2));
+  }
+
+  double dotv(const Level<T>& lv, const T* a, const T* b) {
+    HIPCHK(dot<T>(stream, 2 * lv.F, a, b, partial, dres));
+    return fetch(1)[0];
+  }
+
+  // ---- two-level preconditioner -----------------------------------------------------------
+  void setup_two_level() {
+    const size_t F = fine.F, Fc = coarse.F;
+    // coarse images
+    HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, 1, fine.mT, coarse.mT, nullptr, fine.S1, coarse.S1, coarse.S2));
+    HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, 1, fine.mR, coarse.mR, nullptr, fine.S1, coarse.S1, coarse.S2));
+    HIPCHK(spec_grad<T>(stream, coarse.sg, 1, coarse.mT, coarse.gmT, coarse.S1, coarse.S2));
+    (void)F;
+    // Lanczos on (I + S Q(0) S) from a SplitMix64 start vector
+    std::vector<double> h = splitmix64_uniform(prm.lanczos_seed, 2 * Fc);
+    std::vector<T> ht(h.begin(), h.end());
+    T* q = coarse.vec[0];
+    T* qp = coarse.vec[1];
+    T* w = coarse.vec[2];
+    HIPCHK(hipMemcpyAsync(q, ht.data(), 2 * Fc * sizeof(T), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    double nq = std::sqrt(dotv(coarse, q, q));
+    HIPCHK(axpby<T>(stream, 2 * Fc, 0.0, q, 1.0 / nq, q));
+    HIPCHK(fill<T>(stream, 2 * Fc, 0.0, qp));
+    std::vector<double> al, be;
+    double beta = 0.0;
+    for (int j = 0; j < prm.lanczos_steps; ++j) {
+      split_matvec_zero(coarse, q, w);
+      HIPCHK(axpby<T>(stream, 2 * Fc, -beta, qp, 1.0, w));
+      const double alpha = dotv(coarse, q, w);
+      HIPCHK(axpby<T>(stream, 2 * Fc, -alpha, q, 1.0, w));
+      al.push_back(alpha);
+      beta = std::sqrt(dotv(coarse, w, w));
+      if (j == prm.lanczos_steps - 1 || beta <= 1e-14 * std::fabs(alpha)) break;
+      be.push_back(beta);
+      std::swap(qp, q);                                            // qp <- q
+      HIPCHK(axpby<T>(stream, 2 * Fc, 1.0 / beta, w, 0.0, q));     // q <- w / beta
+    }
+    be.resize(al.size() > 0 ? al.size() - 1 : 0);
+    emax = prm.emax_safety * tridiag_max_eig(al, be);
+    // e_min = min_k 1 + 1 / (beta a'(k)) over the coarse modes: the largest |k|^2 is at the
+    // corner (nc1/2, nc2/2)
+    const double kk = 0.25 * double(coarse.n1) * coarse.n1 + 0.25 * double(coarse.n2) * coarse.n2;
+    emin = 1.0 + 1.0 / (prm.beta * std::pow(kk, prm.reg));
+    if (!(emax > emin)) throw Fail{SLNK_ENAN, "Lanczos produced an invalid e_max"};
+  }
+
+  void linearize_coarse(const T* v_fine) {
+    HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, 2, v_fine, coarse.vec[7], nullptr, fine.S1, coarse.S1, coarse.S2));
+    coarse.cur = 0;
+    linearize(coarse, 0, coarse.vec[7], false);
+    ensure_gm(coarse);
+  }
+
+  // x = CHEB_k(M_c) b on the coarse level (x, b distinct; uses vec[3..6])
+  void chebyshev(const T* b, T* x) {
+    const size_t n = 2 * coarse.F;
+    const double theta = 0.5 * (emax + emin), delta = 0.5 * (emax - emin);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    T* r = coarse.vec[3];
+    T* d = coarse.vec[4];
+    T* Md = coarse.vec[5];
+    HIPCHK(hipMemcpyAsync(r, b, n * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    HIPCHK(axpby<T>(stream, n, 1.0 / theta, b, 0.0, d));
+    HIPCHK(fill<T>(stream, n, 0.0, x));
+    const int k = prm.cheb_iters;
+    for (int i = 0; i < k; ++i) {
+      HIPCHK(axpby<T>(stream, n, 1.0, d, 1.0, x));
+      if (i == k - 1) break;
+      split_matvec(coarse, d, Md);
+      ++n_coarse;
+      HIPCHK(axpby<T>(stream, n, -1.0, Md, 1.0, r));
+      const double rho_next = 1.0 / (2.0 * sigma - rho);
+      HIPCHK(axpby<T>(stream, n, 2.0 * rho_next / delta, r, rho_next * rho, d));
+      rho = rho_next;
+    }
+  }
+
+  void precond(const T* r, T* z) {
+    const double t0 = now_ms();
+    if (!two_level) {
+      HIPCHK(spec_scale<T>(stream, fine.sg, sym(Symbol::RegInv), 2, r, z, nullptr, fine.S1, fine.S2));
+    } else {
+      T* rc = coarse.vec[6];
+      T* zc = coarse.vec[2];
+      HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, 2, r, rc, fine.Sk, fine.S1, coarse.S1, coarse.S2));
+      chebyshev(rc, zc);
+      HIPCHK(spec_prolong_combine<T>(stream, fine.sg, coarse.sg, 2, fine.Sk, zc, z, fine.S1, coarse.S1, coarse.S2));
+    }
+    HIPCHK(hipStreamSynchronize(stream));
+    t_prec += now_ms() - t0;
+  }
+
+  // fine operator of the Krylov solve: H (P_REG) or the split operator (P_2L)
+  void op(const T* x, T* y) {
+    ++n_matvec;
+    if (two_level)
+      split_matvec(fine, x, y);
+    else
+      hessian(fine, x, y);
+  }
+
+  // PCG from zero on op x = b; returns iterations, status in *st
+  int pcg(const T* b, T* x, double tol, int maxit, int* st) {
+    const size_t n = 2 * fine.F;
+    T* r = fine.vec[0];
+    T* z = fine.vec[1];
+    T* p = fine.vec[2];
+    T* q = fine.vec[3];
+    HIPCHK(fill<T>(stream, n, 0.0, x));
+    HIPCHK(hipMemcpyAsync(r, b, n * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    const double bnorm = std::sqrt(dotv(fine, b, b));
+    *st = SLNK_OK;
+    if (bnorm == 0.0) return 0;
+    precond(r, z);
+    HIPCHK(hipMemcpyAsync(p, z, n * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    double rz = dotv(fine, r, z);
+    for (int it = 1; it <= maxit; ++it) {
+      op(p, q);
+      const double pq = dotv(fine, p, q);
+      if (!std::isfinite(pq)) throw Fail{SLNK_ENAN, "non-finite curvature in PCG"};
+      if (pq <= 0.0) {
+        if (it == 1) HIPCHK(hipMemcpyAsync(x, z, n * sizeof(T), hipMemcpyDeviceToDevice, stream));
+        *st = SLNK_ENEGCURV;
+        return it;
+      }
+      const double alpha = rz / pq;
+      HIPCHK(axpby<T>(stream, n, alpha, p, 1.0, x));
+      HIPCHK(axpby<T>(stream, n, -alpha, q, 1.0, r));
+      const double rr = dotv(fine, r, r);
+      if (std::sqrt(rr) <= tol * bnorm) return it;
+      precond(r, z);
+      const double rz_next = dotv(fine, r, z);
+      HIPCHK(axpby<T>(stream, n, 1.0, z, rz_next / rz, p));
+      rz = rz_next;
+    }
+    *st = SLNK_EMAXIT;
+    return maxit;
+  }
+
+  // ---- Newton -------------------------------------------------------------------------------
+  slnk_status newton(T* v, const slnk_solve_opts& o, slnk_solve_report* rep) {
+    const double t_start = now_ms();
+    slnk_solve_report R;
+    std::memset(&R, 0, sizeof(R));
+    n_matvec = n_coarse = 0;
+    t_prec = 0;
+    const size_t F = fine.F, n = 2 * F;
+    double t_grad = 0, t_pcg = 0, t_ls = 0;
+    if (two_level) {
+      R.emin = emin;
+      R.emax = emax;
+    }
+    // gradient at v = 0 fixes ||g_0|| (section 3.4.1 stopping rule)
+    double g2 = 0, ginf = 0;
+    double t0 = now_ms();
+    T* zero = fine.vec[4];
+    HIPCHK(fill<T>(stream, n, 0.0, zero));
+    fine.cur = 0;
+    linearize(fine, 0, zero);
+    gradient(fine, &g2, &ginf);
+    R.g0_inf = ginf;
+    R.g0_two = std::sqrt(g2);
+    // start point
+    HIPCHK(norms<T>(stream, n, v, partial, dres));
+    const double* nv = fetch(3);
+    if (nv[2] > 0) throw Fail{SLNK_ENAN, "non-finite initial velocity"};
+    if (nv[1] > 0.0) {
+      linearize(fine, 0, v);
+      gradient(fine, &g2, &ginf);
+    }
+    t_grad += now_ms() - t0;
+    slnk_status status = SLNK_OK;
+    int k = 0;
+    T* vt = fine.vec[5];
+    T* rhs = fine.vec[6];
+    T* s = fine.vec[7];
+    for (;; ++k) {
+      const double grel = ginf / R.g0_inf;
+      if (k <= SLNK_REPORT_MAX_ITERS) {
+        R.grel[k] = grel;
+        R.J[k] = fine.L().J;
+      }
+      if (grel <= o.gtol_rel || ginf <= o.gtol_abs || k >= o.max_newton || k >= SLNK_REPORT_MAX_ITERS) break;
+      const double eta = std::min(0.5, std::sqrt(g2) / R.g0_two);
+      t0 = now_ms();
+      int st = 0, its = 0;
+      if (two_level) {
+        linearize_coarse(fine.L().v);
+        HIPCHK(spec_scale<T>(stream, fine.sg, sym(Symbol::RegInvSqrt), 2, fine.g, rhs, nullptr, fine.S1, fine.S2));
+        HIPCHK(axpby<T>(stream, n, 0.0, rhs, -1.0, rhs));
+        its = pcg(rhs, s, eta, o.max_pcg, &st);
+        HIPCHK(spec_scale<T>(stream, fine.sg, sym(Symbol::RegInvSqrt), 2, s, vt, nullptr, fine.S1, fine.S2));
+      } else {
+        HIPCHK(axpby<T>(stream, n, -1.0, fine.g, 0.0, rhs));
+        its = pcg(rhs, vt, eta, o.max_pcg, &st);
+      }
+      t_pcg += now_ms() - t0;
+      R.pcg_iters += its;
+      if (k < SLNK_REPORT_MAX_ITERS) R.pcg[k] = its;
+      // Armijo backtracking
+      t0 = now_ms();
+      const double slope = fine.cell * dotv(fine, fine.g, vt);
+      const double J0 = fine.L().J;
+      const int trial = 1 - fine.cur;
+      double alpha = 1.0;
+      bool ok = false;
+      for (int hv = 0; hv <= o.max_halvings; ++hv) {
+        // trial velocity v + alpha vt in the other slot
+        HIPCHK(xpay<T>(stream, n, fine.L().v, alpha, vt, fine.lin[trial].v));
+        linearize(fine, trial, fine.lin[trial].v);
+        ++R.line_search_evals;
+        if (fine.lin[trial].J <= J0 + o.armijo_c1 * alpha * slope) {
+          ok = true;
+          break;
+        }
+        alpha *= 0.5;
+      }
+      t_ls += now_ms() - t0;
+      if (!ok) {
+        status = SLNK_ELINESEARCH;
+        break;
+      }
+      fine.cur = trial;
+      t0 = now_ms();
+      gradient(fine, &g2, &ginf);
+      t_grad += now_ms() - t0;
+    }
+    R.newton_iters = k;
+    HIPCHK(hipMemcpyAsync(v, fine.L().v, n * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    has_grad = true;
+    R.status = status;
+    R.matvecs = n_matvec;
+    R.coarse_matvecs = n_coarse;
+    R.time_total_ms = now_ms() - t_start;
+    R.time_gradient_ms = t_grad;
+    R.time_pcg_ms = t_pcg;
+    R.time_precond_ms = t_prec;
+    R.time_linesearch_ms = t_ls;
+    if (rep) *rep = R;
+    return status;
+  }
+};
+
+}  // namespace
+}  // namespace slnk
+
+// ============================================================================================
+// C ABI
+// ============================================================================================
+struct slnk_ctx {
+  int prec = 0;
+  std::string err;
+  std::unique_ptr<slnk::Context<float>> f;
+  std::unique_ptr<slnk::Context<double>> d;
+};
+
+namespace {
+
+template <class Fn>
+slnk_status guarded(slnk_ctx* c, Fn&& fn) {
+  if (!c) return SLNK_EINVAL;
+  try {
+    fn();
+    return SLNK_OK;
+  } catch (const slnk::Fail& e) {
+    c->err = e.msg;
+    return e.st;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    return SLNK_EDEVICE;
+  }
+}
+
+template <class Fn>
+slnk_status dispatch(slnk_ctx* c, Fn&& fn) {
+  return guarded(c, [&] {
+    if (c->f)
+      fn(*c->f);
+    else
+      fn(*c->d);
+  });
+}
+
+}  // namespace
+
+extern "C" {
+
+void slnk_default_params(slnk_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->n1 = p->n2 = 256;
+  p->nt = 4;
+  p->reg = SLNK_REG_H2;
+  p->beta = 1e-3;
+  p->prec = SLNK_PREC_MIXED;
+  p->pc = SLNK_PC_2L;
+  p->cheb_iters = 10;
+  p->lanczos_steps = 30;
+  p->emax_safety = 1.05;
+  p->lanczos_seed = 0x5EED;
+}
+
+void slnk_default_opts(slnk_solve_opts* o) {
+  if (!o) return;
+  o->max_newton = 10;
+  o->gtol_rel = 1e-2;
+  o->gtol_abs = 1e-5;
+  o->max_pcg = 500;
+  o->armijo_c1 = 1e-4;
+  o->max_halvings = 10;
+}
+
+slnk_status slnk_create(const slnk_params* params, void* hip_stream, slnk_ctx** out) {
+  if (!params || !out) return SLNK_EINVAL;
+  *out = nullptr;
+  auto c = std::make_unique<slnk_ctx>();
+  c->prec = params->prec;
+  if (params->prec != SLNK_PREC_FP64 && params->prec != SLNK_PREC_MIXED) return SLNK_EINVAL;
+  slnk_status st = guarded(c.get(), [&] {
+    if (params->prec == SLNK_PREC_MIXED) {
+      c->f = std::make_unique<slnk::Context<float>>();
+      c->f->create(*params, static_cast<hipStream_t>(hip_stream));
+    } else {
+      c->d = std::make_unique<slnk::Context<double>>();
+      c->d->create(*params, static_cast<hipStream_t>(hip_stream));
+    }
+  });
+  if (st != SLNK_OK) {
+    if (c->f) c->f->destroy();
+    if (c->d) c->d->destroy();
+    return st;
+  }
+  *out = c.release();
+  return SLNK_OK;
+}
+
+void slnk_destroy(slnk_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->f) ctx->f->destroy();
+  if (ctx->d) ctx->d->destroy();
+  delete ctx;
+}
+
+const char* slnk_last_error(const slnk_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+unsigned long long slnk_workspace_bytes(const slnk_ctx* ctx) {
+  if (!ctx) return 0;
+  return ctx->f ? ctx->f->arena.size : ctx->d->arena.size;
+}
+
+slnk_status slnk_set_images(slnk_ctx* ctx, const void* m_R, const void* m_T) {
+  if (!m_R || !m_T) return SLNK_EINVAL;
+  return dispatch(ctx, [&](auto& C) {
+    using T = std::remove_reference_t<decltype(*C.fine.mT)>;
+    const size_t F = C.fine.F;
+    HIPCHK(hipMemcpyAsync(C.fine.mR, m_R, F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
+    HIPCHK(hipMemcpyAsync(C.fine.mT, m_T, F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
+    for (T* img : {C.fine.mR, C.fine.mT}) {
+      HIPCHK(slnk::norms<T>(C.stream, F, img, C.partial, C.dres));
+      if (C.fetch(3)[2] > 0) throw slnk::Fail{SLNK_ENAN, "non-finite image value"};
+    }
+    C.fine.lin[0].valid = C.fine.lin[1].valid = false;
+    C.has_grad = false;
+    if (C.two_level) C.setup_two_level();
+    C.images_set = true;
+  });
+}
+
+slnk_status slnk_transport_state(slnk_ctx* ctx, const void* v, const void* m0, void* m1) {
+  if (!v || !m0 || !m1) return SLNK_EINVAL;
+  return dispatch(ctx, [&](auto& C) {
+    using T = std::remove_reference_t<decltype(*C.fine.mT)>;
+    auto& lv = C.fine;
+    const size_t F = lv.F;
+    // run in the non-current slot with a temporary template, then restore the images
+    const int slot = 1 - lv.cur;
+    T* saved = lv.vec[0];
+    HIPCHK(hipMemcpyAsync(saved, lv.mT, F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
+    HIPCHK(hipMemcpyAsync(lv.mT, m0, F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
+    C.linearize(lv, slot, static_cast<const T*>(v), false);
+    HIPCHK(hipMemcpyAsync(m1, lv.lin[slot].m + lv.nt * F, F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
+    HIPCHK(hipMemcpyAsync(lv.mT, saved, F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
+    lv.lin[slot].valid = false;
+    HIPCHK(hipStreamSynchronize(C.stream));
+  });
+}
+
+slnk_status slnk_objective(slnk_ctx* ctx, const void* v, double* J) {
+  if (!v || !J) return SLNK_EINVAL;
+  return dispatch(ctx, [&](auto& C) {
+    using T = std::remove_reference_t<decltype(*C.fine.mT)>;
+    if (!C.images_set) throw slnk::Fail{SLNK_EINVAL, "slnk_set_images must come first"};
+    C.fine.cur = 0;
+    C.linearize(C.fine, 0, static_cast<const T*>(v));
+    C.has_grad = false;
+    *J = C.fine.L().J;
+  });
+}
+
+slnk_status slnk_gradient(slnk_ctx* ctx, const void* v, void* g, double* J) {
+  if (!v || !g) return SLNK_EINVAL;
+  return dispatch(ctx, [&](auto& C) {
+    using T = std::remove_reference_t<decltype(*C.fine.mT)>;
+    if (!C.images_set) throw slnk::Fail{SLNK_EINVAL, "slnk_set_images must come first"};
+    C.fine.cur = 0;
+    C.linearize(C.fine, 0, static_cast<const T*>(v));
+    double g2, ginf;
+    C.gradient(C.fine, &g2, &ginf);
+    HIPCHK(hipMemcpyAsync(g, C.fine.g, 2 * C.fine.F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
+    if (C.two_level) C.linearize_coarse(C.fine.L().v);
+    HIPCHK(hipStreamSynchronize(C.stream));
+    if (J) *J = C.fine.L().J;
+    C.has_grad = true;
+  });
+}
+
+slnk_status slnk_hessian_matvec(slnk_ctx* ctx, const void* vt, void* Hvt) {
+  if (!vt || !Hvt) return SLNK_EINVAL;
+  return dispatch(ctx, [&](auto& C) {
+    using T = std::remove_reference_t<decltype(*C.fine.mT)>;
+    if (!C.has_grad) throw slnk::Fail{SLNK_EINVAL, "no linearisation point: call slnk_gradient first"};
+    C.hessian(C.fine, static_cast<const T*>(vt), static_cast<T*>(Hvt));
+  });
+}
+
+slnk_status slnk_split_matvec(slnk_ctx* ctx, const void* s, void* out) {
+  if (!s || !out) return SLNK_EINVAL;
+  return dispatch(ctx, [&](auto& C) {
+    using T = std::remove_reference_t<decltype(*C.fine.mT)>;
+    if (!C.has_grad) throw slnk::Fail{SLNK_EINVAL, "no linearisation point: call slnk_gradient first"};
+    C.split_matvec(C.fine, static_cast<const T*>(s), static_cast<T*>(out));
+  });
+}
+
+slnk_status slnk_precond_apply(slnk_ctx* ctx, const void* r, void* z) {
+  if (!r || !z) return SLNK_EINVAL;
+  return dispatch(ctx, [&](auto& C) {
+    using T = std::remove_reference_t<decltype(*C.fine.mT)>;
+    if (C.two_level && !C.has_grad) throw slnk::Fail{SLNK_EINVAL, "P_2L needs a linearisation point: call slnk_gradient first"};
+    C.precond(static_cast<const T*>(r), static_cast<T*>(z));
+  });
+}
+
+slnk_status slnk_get_cheb_bounds(const slnk_ctx* ctx, double* emin, double* emax) {
+  if (!ctx || !emin || !emax) return SLNK_EINVAL;
+  if (ctx->f) {
+    *emin = ctx->f->emin;
+    *emax = ctx->f->emax;
+  } else {
+    *emin = ctx->d->emin;
+    *emax = ctx->d->emax;
+  }
+  return SLNK_OK;
+}
+
+slnk_status slnk_get_field(slnk_ctx* ctx, int which, void* out) {
+  if (!out) return SLNK_EINVAL;
+  return dispatch(ctx, [&](auto& C) {
+    using T = std::remove_reference_t<decltype(*C.fine.mT)>;
+    auto& lv = C.fine;
+    auto& L = lv.L();
+    if (!L.valid) throw slnk::Fail{SLNK_EINVAL, "no linearisation point"};
+    const size_t F = lv.F;
+    const T* src = nullptr;
+    size_t cnt = F;
+    switch (which) {
+      case 0: src = L.m + lv.nt * F; break;
+      case 1: src = L.df; cnt = 2 * F; break;
+      case 2: src = L.da; cnt = 2 * F; break;
+      case 3: src = L.gamma; break;
+      case 4: src = lv.lam; break;
+      default: throw slnk::Fail{SLNK_EINVAL, "unknown field"};
+    }
+    HIPCHK(hipMemcpyAsync(out, src, cnt * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
+    HIPCHK(hipStreamSynchronize(C.stream));
+  });
+}
+
+slnk_status slnk_newton_solve(slnk_ctx* ctx, void* v_inout, const slnk_solve_opts* opts, slnk_solve_report* report) {
+  if (!v_inout) return SLNK_EINVAL;
+  slnk_solve_opts o;
+  slnk_default_opts(&o);
+  if (opts) o = *opts;
+  slnk_status result = SLNK_OK;
+  slnk_status st = dispatch(ctx, [&](auto& C) {
+    using T = std::remove_reference_t<decltype(*C.fine.mT)>;
+    if (!C.images_set) throw slnk::Fail{SLNK_EINVAL, "slnk_set_images must come first"};
+    if (o.max_newton < 0 || o.max_pcg < 1 || o.max_halvings < 0) throw slnk::Fail{SLNK_EINVAL, "bad options"};
+    result = C.newton(static_cast<T*>(v_inout), o, report);
+  });
+  return st != SLNK_OK ? st : result;
+}
+
+}  // extern "C"

@@ -1,0 +1,214 @@
+// FP64-accumulated reductions and vector updates for the Krylov, Chebyshev and Lanczos layers
+// (section 3.4: PCG inner products, norms of the reduced gradient, Armijo objective values).
+// Every reduction is two-stage with a fixed combination order, so results are deterministic.
+#include "kernels.hpp"
+
+namespace slnk {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxBlocks = 1024;
+
+enum RedOp : int { kDot = 0, kDot3 = 1, kNorms = 2 };
+
+__device__ void block_reduce4(double v[4], unsigned maxmask, int ncomp, double* out) {
+  __shared__ double sh[4][kThreads / 64];
+  const int tid = threadIdx.x;
+  for (int c = 0; c < ncomp; ++c) {
+    double x = v[c];
+    const bool mx = (maxmask >> c) & 1u;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double y = __shfl_down(x, off, 64);
+      x = mx ? fmax(x, y) : x + y;
+    }
+    if ((tid & 63) == 0) sh[c][tid >> 6] = x;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int c = 0; c < ncomp; ++c) {
+      const bool mx = (maxmask >> c) & 1u;
+      double x = sh[c][0];
+      for (int w = 1; w < kThreads / 64; ++w) x = mx ? fmax(x, sh[c][w]) : x + sh[c][w];
+      out[c] = x;
+    }
+  }
+}
+
+template <typename T, int OP>
+__global__ void __launch_bounds__(kThreads) k_reduce(size_t n, const T* __restrict__ a, const T* __restrict__ b,
+                                                      double* __restrict__ partial) {
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const size_t stride = size_t(gridDim.x) * kThreads;
+  for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += stride) {
+    const double x = double(a[i]);
+    if constexpr (OP == kDot) {
+      v[0] += x * double(b[i]);
+    } else if constexpr (OP == kDot3) {
+      const double y = double(b[i]);
+      v[0] += x * x;
+      v[1] += x * y;
+      v[2] += y * y;
+    } else {
+      if (isfinite(x)) {
+        v[0] += x * x;
+        v[1] = fmax(v[1], fabs(x));
+      } else {
+        v[2] += 1.0;
+      }
+    }
+  }
+  constexpr int nc = OP == kDot ? 1 : 3;
+  constexpr unsigned mm = OP == kNorms ? 2u : 0u;
+  block_reduce4(v, mm, nc, partial + 4 * blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kThreads) k_finish(int nparts, int stride, int ncomp, unsigned maxmask,
+                                                      const double* __restrict__ partial, double* __restrict__ result) {
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int p = threadIdx.x; p < nparts; p += kThreads)
+    for (int c = 0; c < ncomp; ++c) {
+      const double x = partial[size_t(p) * stride + c];
+      v[c] = ((maxmask >> c) & 1u) ? fmax(v[c], x) : v[c] + x;
+    }
+  __shared__ double outv[4];
+  block_reduce4(v, maxmask, ncomp, outv);
+  __syncthreads();
+  if (threadIdx.x < ncomp) result[threadIdx.x] = outv[threadIdx.x];
+}
+
+// y = a x + b y; with b == 0 the old y is not read (it may hold anything)
+template <typename T>
+__global__ void k_axpby(size_t n, T a, const T* __restrict__ x, T b, T* __restrict__ y) {
+  const bool ready = b != T(0);
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    y[i] = ready ? a * x[i] + b * y[i] : a * x[i];
+}
+
+template <typename T>
+__global__ void k_xpay(size_t n, const T* __restrict__ x, T a, const T* __restrict__ y, T* __restrict__ z) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    z[i] = x[i] + a * y[i];
+}
+
+template <typename T>
+__global__ void k_fill(size_t n, T v, T* __restrict__ y) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    y[i] = v;
+}
+
+template <typename T>
+__global__ void k_q0(size_t F, const T* __restrict__ w, const T* __restrict__ gm, T scale, T* __restrict__ out) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < F; i += size_t(gridDim.x) * blockDim.x) {
+    const T g1 = gm[i], g2 = gm[i + F];
+    const T d = scale * (w[i] * g1 + w[i + F] * g2);
+    out[i] = d * g1;
+    out[i + F] = d * g2;
+  }
+}
+
+template <typename TI, typename TO>
+__global__ void k_cast(size_t n, const TI* __restrict__ x, TO* __restrict__ y) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    y[i] = TO(x[i]);
+}
+
+inline unsigned grid_for(size_t n) {
+  size_t b = (n + kThreads * 4 - 1) / (kThreads * 4);
+  if (b < 1) b = 1;
+  if (b > 2048) b = 2048;
+  return unsigned(b);
+}
+
+}  // namespace
+
+int reduce_blocks(size_t n) {
+  size_t b = (n + kThreads * 8 - 1) / (kThreads * 8);
+  if (b < 1) b = 1;
+  if (b > kMaxBlocks) b = kMaxBlocks;
+  return int(b);
+}
+
+hipError_t finish(hipStream_t s, int nparts, int stride, int ncomp, unsigned maxmask, const double* partial,
+                  double* result) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kThreads), 0, s, nparts, stride, ncomp, maxmask, partial, result);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dot(hipStream_t s, size_t n, const T* a, const T* b, double* partial, double* result) {
+  const int nb = reduce_blocks(n);
+  hipLaunchKernelGGL((k_reduce<T, kDot>), dim3(nb), dim3(kThreads), 0, s, n, a, b, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return finish(s, nb, 4, 1, 0u, partial, result);
+}
+
+template <typename T>
+hipError_t dot3(hipStream_t s, size_t n, const T* a, const T* b, double* partial, double* result) {
+  const int nb = reduce_blocks(n);
+  hipLaunchKernelGGL((k_reduce<T, kDot3>), dim3(nb), dim3(kThreads), 0, s, n, a, b, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return finish(s, nb, 4, 3, 0u, partial, result);
+}
+
+template <typename T>
+hipError_t norms(hipStream_t s, size_t n, const T* a, double* partial, double* result) {
+  const int nb = reduce_blocks(n);
+  hipLaunchKernelGGL((k_reduce<T, kNorms>), dim3(nb), dim3(kThreads), 0, s, n, a, a, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return finish(s, nb, 4, 3, 2u, partial, result);
+}
+
+template <typename T>
+hipError_t axpby(hipStream_t s, size_t n, double a, const T* x, double b, T* y) {
+  hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, T(a), x, T(b), y);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t xpay(hipStream_t s, size_t n, const T* x, double a, const T* y, T* z) {
+  hipLaunchKernelGGL(k_xpay<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, T(a), y, z);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fill(hipStream_t s, size_t n, double value, T* y) {
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, T(value), y);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t q_at_zero(hipStream_t s, size_t F, const T* w, const T* gm, double scale, T* out) {
+  hipLaunchKernelGGL(k_q0<T>, dim3(grid_for(F)), dim3(kThreads), 0, s, F, w, gm, T(scale), out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t cast_copy(hipStream_t s, size_t n, const double* x, T* y) {
+  hipLaunchKernelGGL((k_cast<double, T>), dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, y);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t cast_back(hipStream_t s, size_t n, const T* x, double* y) {
+  hipLaunchKernelGGL((k_cast<T, double>), dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, y);
+  return hipGetLastError();
+}
+
+#define INST(T)                                                                                    \
+  template hipError_t dot<T>(hipStream_t, size_t, const T*, const T*, double*, double*);          \
+  template hipError_t dot3<T>(hipStream_t, size_t, const T*, const T*, double*, double*);         \
+  template hipError_t norms<T>(hipStream_t, size_t, const T*, double*, double*);                  \
+  template hipError_t axpby<T>(hipStream_t, size_t, double, const T*, double, T*);                \
+  template hipError_t xpay<T>(hipStream_t, size_t, const T*, double, const T*, T*);               \
+  template hipError_t fill<T>(hipStream_t, size_t, double, T*);                                   \
+  template hipError_t q_at_zero<T>(hipStream_t, size_t, const T*, const T*, double, T*);          \
+  template hipError_t cast_copy<T>(hipStream_t, size_t, const double*, T*);                       \
+  template hipError_t cast_back<T>(hipStream_t, size_t, const T*, double*);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace slnk

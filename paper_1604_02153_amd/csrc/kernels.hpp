@@ -1,0 +1,171 @@
+// Host-side launchers of the gfx950 kernels.  Every launcher enqueues on the given stream and
+// returns the launch status; none of them synchronises or allocates.
+#pragma once
+
+#include "common.hpp"
+
+namespace slnk {
+
+constexpr int kFFTMaxStages = 16;
+
+// Factorisation of one transform length into radix-4/2/3/5 stages plus its twiddle table
+// w[q] = exp(-2 pi i q / n), q < n (device memory, computed on the host in FP64).
+struct FFTPlanDev {
+  int n = 0;
+  int nstages = 0;
+  int radix[kFFTMaxStages] = {0};
+  const void* tw = nullptr;
+};
+
+// Grid description passed to every spectral launcher.
+template <typename T>
+struct SpecGrid {
+  int n1 = 0, n2 = 0;      // real-space grid
+  FFTPlanDev row;          // length n2 transforms (along x2, contiguous)
+  FFTPlanDev col;          // length n1 transforms (along x1, strided)
+  int nh() const { return n2 / 2 + 1; }
+  size_t field() const { return size_t(n1) * size_t(n2); }
+  size_t spec() const { return size_t(n1) * size_t(nh()); }
+};
+
+// Scalar symbols applied by spec_scale (all real and even in k).
+enum class Symbol : int {
+  Reg = 0,        // beta a(k), a = |k|^(2 reg)
+  RegInv = 1,     // 1 / (beta a'(k)), a' = a with a(0) replaced by 1   (P_REG^{-1})
+  RegInvSqrt = 2, // (beta a'(k))^{-1/2}                                  (split step S)
+  LowPass = 3,    // 1 for |k1| < n1/4 and |k2| < n2/4, else 0
+  HighPass = 4,   // 1 - LowPass
+  Spline = 5,     // 1 / (B1(k1) B2(k2)), B(k) = (2 + cos(2 pi k / n)) / 3  (B-spline prefilter)
+};
+
+struct SymbolParams {
+  Symbol kind = Symbol::Reg;
+  int reg = 2;
+  double beta = 1.0;
+};
+
+// ---- spectral operators (each: row forward, column forward + symbol + column inverse, row inverse)
+// in/out: real fields; out[i] = symbol(in[i]) + (add ? add[i] : 0), for i < nf (nf = 1 or 2).
+// S1, S2: spectral scratch, each at least 2 * spec() complex.
+template <typename T>
+hipError_t spec_scale(hipStream_t s, const SpecGrid<T>& g, SymbolParams sym, int nf, const T* in, T* out,
+                      const T* add, cplx<T>* S1, cplx<T>* S2);
+
+// Spectral gradient of 'batch' scalar fields m[b] (stride field()): gm[b] = (d1 m, d2 m) with
+// stride 2 field().  Scratch: S1 >= batch spec(), S2 >= 2 batch spec().
+template <typename T>
+hipError_t spec_grad(hipStream_t s, const SpecGrid<T>& g, int batch, const T* m, T* gm, cplx<T>* S1, cplx<T>* S2);
+
+// From v (two fields): spline coefficients cv (two fields), div v, spline coefficients of div v,
+// and beta A v (two fields).  S1 >= 2 spec(), S2 >= 6 spec().
+template <typename T>
+hipError_t spec_trace_prep(hipStream_t s, const SpecGrid<T>& g, int reg, double beta, const T* v, T* cv, T* divv,
+                           T* cdiv, T* bAv, cplx<T>* S1, cplx<T>* S2);
+
+// Spectral restriction of nf fields to the grid gc (n/2): the modes |k_i| < n_i/4 survive.
+// If keep_fine != nullptr the fine spectrum (after both forward passes) is also stored there
+// (nf * spec() complex) for a later prolong_combine.  Scratch: S1 (fine, nf spec()),
+// Sc1/Sc2 (coarse, nf gc.spec() each).
+template <typename T>
+hipError_t spec_restrict(hipStream_t s, const SpecGrid<T>& g, const SpecGrid<T>& gc, int nf, const T* in, T* out_c,
+                         cplx<T>* keep_fine, cplx<T>* S1, cplx<T>* Sc1, cplx<T>* Sc2);
+
+// out = HighPass(fine spectrum kept by spec_restrict) + Prolong(zc): the two-level combine.
+template <typename T>
+hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecGrid<T>& gc, int nf,
+                                const cplx<T>* fine_k, const T* zc, T* out, cplx<T>* S1, cplx<T>* Sc1,
+                                cplx<T>* Sc2);
+
+// ---- semi-Lagrangian transport ---------------------------------------------------------
+// Displacements are stored in cells: departure point of node i is i + d (per axis).
+enum class StepKind : int {
+  State = 0,      // dst = I[src](X_f)
+  Adjoint = 1,    // dst = gamma I[src](X_a); b (+)= ht w lam grad m
+  IncState = 2,   // incremental state (see transport.hip)
+  IncAdjoint = 3, // dst = gamma I[src](X_a); bt += ht w lam~ grad m
+};
+
+template <typename T>
+struct StepArgs {
+  int n1 = 0, n2 = 0;
+  int halo = 0;              // bound D on |displacement| in cells for this linearisation
+  const T* src = nullptr;    // field transported (or nullptr with a 'first' source, see below)
+  T* dst = nullptr;
+  const T* d1 = nullptr;     // displacement fields (cells)
+  const T* d2 = nullptr;
+  const T* gamma = nullptr;  // adjoint step factor
+  // first-step sources (src == nullptr): State: none; Adjoint: mR - mfin; IncState: (ht/2) f(vt, gm0);
+  // IncAdjoint: none
+  const T* aux0 = nullptr;
+  const T* aux1 = nullptr;
+  // accumulation: gm_cur/gm_prev: gradient of m at the arrival (new) time level and, for the
+  // first adjoint step, at the initial (final-time) level
+  const T* gm_new = nullptr; // 2 fields, grad m at the time level being produced
+  const T* gm_old = nullptr; // 2 fields, grad m at the time level of src (first step only)
+  T* acc = nullptr;          // 2 fields accumulator (b or bt)
+  const T* vt = nullptr;     // incremental state: direction (2 fields)
+  const T* addf = nullptr;   // adjoint last step: beta A v added to the accumulator (2 fields)
+  T* out2 = nullptr;         // adjoint last step: gradient output (2 fields)
+  double ht = 0;
+  double w_new = 0;          // trapezoid weight of the produced level (times ht)
+  double w_old = 0;          // trapezoid weight of the src level (first step only)
+  int first = 0, last = 0;
+  double* partial = nullptr; // FP64 per-block partial sums (state last step: misfit; adjoint
+                             // last step: sum g^2 and max |g|)
+  T* coef = nullptr;         // one-field scratch for the coefficient pass when halo exceeds LDS
+};
+
+// Maximum halo (in cells) the fused LDS step supports for a given precision on this device.
+// Larger halos run as a coefficient pass into a.coef followed by a global-memory gather.
+template <typename T>
+int sl_step_max_halo();
+
+// One SL time step.  Partial sums (when a.partial and a.last) go to partial[2 * block + {0,1}];
+// *nblocks_out receives the number of blocks.
+template <typename T>
+hipError_t sl_step(hipStream_t s, StepKind kind, const StepArgs<T>& a, int* nblocks_out);
+
+// Heun trace of both characteristics at once.
+// in: v (2 fields), cv (2 fields, spline coefficients of v), divv, cdiv (coefficients of div v),
+//     bAv (2 fields) for the regularisation energy.
+// out: df (2 fields), da (2 fields), gamma; partial[block] = {sum v . bAv, max |d|}.
+template <typename T>
+hipError_t sl_trace(hipStream_t s, int n1, int n2, double ht, const T* v, const T* cv, const T* divv,
+                    const T* cdiv, const T* bAv, T* df, T* da, T* gamma, double* partial, int* nblocks_out);
+
+// ---- reductions and vector updates -------------------------------------------------------
+// Two-stage deterministic FP64 reductions: per-block partials (reduce_blocks(n) blocks, 4 slots
+// each), then one block that combines them in a fixed order.  'partial' needs
+// 4 * reduce_blocks(n) doubles; results land in device memory.
+int reduce_blocks(size_t n);
+// result[0] = a.b
+template <typename T>
+hipError_t dot(hipStream_t s, size_t n, const T* a, const T* b, double* partial, double* result);
+// result[0] = a.a, result[1] = a.b, result[2] = b.b
+template <typename T>
+hipError_t dot3(hipStream_t s, size_t n, const T* a, const T* b, double* partial, double* result);
+// result[0] = sum a^2, result[1] = max |a|, result[2] = number of non-finite entries
+template <typename T>
+hipError_t norms(hipStream_t s, size_t n, const T* a, double* partial, double* result);
+// combine 'ncomp' components of partial[stride * block + c]: component c is a max if bit c of
+// maxmask is set, else a sum
+hipError_t finish(hipStream_t s, int nparts, int stride, int ncomp, unsigned maxmask, const double* partial,
+                  double* result);
+
+// y = a x + b y (b == 0: y is written without being read)
+template <typename T>
+hipError_t axpby(hipStream_t s, size_t n, double a, const T* x, double b, T* y);
+// z = x + a y
+template <typename T>
+hipError_t xpay(hipStream_t s, size_t n, const T* x, double a, const T* y, T* z);
+template <typename T>
+hipError_t fill(hipStream_t s, size_t n, double value, T* y);
+// Q(0) w = (w . gm) gm pointwise (the transport part of the GN Hessian at v = 0): out = scale * Q w
+template <typename T>
+hipError_t q_at_zero(hipStream_t s, size_t F, const T* w, const T* gm, double scale, T* out);
+template <typename T>
+hipError_t cast_copy(hipStream_t s, size_t n, const double* x, T* y);
+template <typename T>
+hipError_t cast_back(hipStream_t s, size_t n, const T* x, double* y);
+
+}  // namespace slnk

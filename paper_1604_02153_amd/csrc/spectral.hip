@@ -1,0 +1,652 @@
+// Pseudospectral operators on the periodic grid: LDS-resident mixed-radix (4, 2, 3, 5) Stockham
+// FFTs fused with the spectral diagonal operators of the method (section 3.2: Fourier
+// discretisation; eq. e:diffopregv: regulariser symbols; eq. e:reg-precond: P_REG; section
+// 3.4.2: split preconditioning, cut-off filters, spectral restriction and prolongation).
+//
+// Layout.  A real field is [n1][n2].  Two real fields are packed as one complex row (a + i b),
+// transformed along x2 and unpacked into two half spectra [n1][n2/2+1] ("row pass").  The
+// column pass transforms the n2/2+1 columns along x1, applies the symbol (which may read several
+// input spectra and write several outputs) and transforms back.  The inverse row pass packs two
+// Hermitian half spectra into one complex row, inverts it and writes both real fields.
+//
+// Conventions: forward transforms are unnormalised; every symbol carries the 1/(n1 n2) of the
+// inverse.  Odd symbols (derivatives) drop the Nyquist modes, even symbols keep them.
+#include "kernels.hpp"
+
+namespace slnk {
+namespace {
+
+constexpr int kMaxE = 16;          // complex elements per thread held by one FFT stage
+constexpr int kLdsBudget = 64 * 1024;
+
+// ---------------------------------------------------------------------------------------
+// small DFTs; sign = -1 forward, +1 inverse
+// ---------------------------------------------------------------------------------------
+template <typename T, int RAD>
+struct Dft;
+
+template <typename T>
+struct Dft<T, 2> {
+  __device__ static void run(cplx<T>* x, int) {
+    cplx<T> a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  }
+};
+
+template <typename T>
+struct Dft<T, 4> {
+  __device__ static void run(cplx<T>* x, int sign) {
+    cplx<T> a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
+    cplx<T> c = cadd(x[1], x[3]), d = csub(x[1], x[3]);
+    d = sign < 0 ? cmul_mi(d) : cmul_i(d);   // omega = exp(sign 2 pi i / 4) = sign * i
+    x[0] = cadd(a, c);
+    x[1] = cadd(b, d);
+    x[2] = csub(a, c);
+    x[3] = csub(b, d);
+  }
+};
+
+template <typename T>
+struct Dft<T, 3> {
+  __device__ static void run(cplx<T>* x, int sign) {
+    const T h = T(0.866025403784438646763723170752936);  // sin(2 pi / 3)
+    cplx<T> t1 = cadd(x[1], x[2]), t2 = csub(x[1], x[2]);
+    cplx<T> m = {x[0].x - T(0.5) * t1.x, x[0].y - T(0.5) * t1.y};
+    cplx<T> r = cscale(sign < 0 ? cmul_mi(t2) : cmul_i(t2), h);
+    x[0] = cadd(x[0], t1);
+    x[1] = cadd(m, r);
+    x[2] = csub(m, r);
+  }
+};
+
+template <typename T>
+struct Dft<T, 5> {
+  __device__ static void run(cplx<T>* x, int sign) {
+    const T c1 = T(0.309016994374947424102293417182819);   // cos(2 pi / 5)
+    const T c2 = T(-0.809016994374947424102293417182819);  // cos(4 pi / 5)
+    const T s1 = T(0.951056516295153572116439333379382);   // sin(2 pi / 5)
+    const T s2 = T(0.587785252292473129168705954639073);   // sin(4 pi / 5)
+    cplx<T> t1 = cadd(x[1], x[4]), t2 = cadd(x[2], x[3]);
+    cplx<T> t3 = csub(x[1], x[4]), t4 = csub(x[2], x[3]);
+    cplx<T> a1 = {x[0].x + c1 * t1.x + c2 * t2.x, x[0].y + c1 * t1.y + c2 * t2.y};
+    cplx<T> a2 = {x[0].x + c2 * t1.x + c1 * t2.x, x[0].y + c2 * t1.y + c1 * t2.y};
+    cplx<T> b1 = {s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y};
+    cplx<T> b2 = {s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y};
+    b1 = sign < 0 ? cmul_mi(b1) : cmul_i(b1);
+    b2 = sign < 0 ? cmul_mi(b2) : cmul_i(b2);
+    x[0] = cadd(x[0], cadd(t1, t2));
+    x[1] = cadd(a1, b1);
+    x[4] = csub(a1, b1);
+    x[2] = cadd(a2, b2);
+    x[3] = csub(a2, b2);
+  }
+};
+
+// One Stockham stage of radix RAD over 'nbatch' transforms of length n held in LDS; element e of
+// transform b lives at buf[b * bs + e].  p is the product of the radices of earlier stages.
+// The stage reads every input into registers, synchronises, then writes every output, so it
+// works in place.
+template <typename T, int RAD, int MAXB>
+__device__ void fft_stage(cplx<T>* buf, int n, int p, int nbatch, int bs, const cplx<T>* __restrict__ tw,
+                          int sign, int tid, int nthr) {
+  const int nb = n / RAD;
+  const int total = nbatch * nb;
+  const int tws = n / (p * RAD);
+  cplx<T> y[MAXB][RAD];
+  int ob[MAXB];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int t = tid + q * nthr;
+    if (t < total) {
+      const int b = t / nb;
+      const int i = t - b * nb;
+      const int k = i % p;
+      cplx<T> x[RAD];
+#pragma unroll
+      for (int j = 0; j < RAD; ++j) {
+        cplx<T> val = buf[b * bs + i + j * nb];
+        if (j > 0 && k > 0) {
+          cplx<T> w = tw[j * k * tws];
+          if (sign > 0) w.y = -w.y;
+          val = cmul(val, w);
+        }
+        x[j] = val;
+      }
+      Dft<T, RAD>::run(x, sign);
+#pragma unroll
+      for (int j = 0; j < RAD; ++j) y[q][j] = x[j];
+      ob[q] = b * bs + (i - k) * RAD + k;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int t = tid + q * nthr;
+    if (t < total) {
+#pragma unroll
+      for (int j = 0; j < RAD; ++j) buf[ob[q] + j * p] = y[q][j];
+    }
+  }
+  __syncthreads();
+}
+
+// Full transform of nbatch sequences (nbatch * n <= kMaxE * nthr).
+template <typename T>
+__device__ void fft_lds(cplx<T>* buf, const FFTPlanDev& pl, int nbatch, int bs, int sign, int tid, int nthr) {
+  const cplx<T>* tw = static_cast<const cplx<T>*>(pl.tw);
+  int p = 1;
+  for (int s = 0; s < pl.nstages; ++s) {
+    const int r = pl.radix[s];
+    if (r == 4)
+      fft_stage<T, 4, kMaxE / 4>(buf, pl.n, p, nbatch, bs, tw, sign, tid, nthr);
+    else if (r == 2)
+      fft_stage<T, 2, kMaxE / 2>(buf, pl.n, p, nbatch, bs, tw, sign, tid, nthr);
+    else if (r == 3)
+      fft_stage<T, 3, (kMaxE + 2) / 3>(buf, pl.n, p, nbatch, bs, tw, sign, tid, nthr);
+    else
+      fft_stage<T, 5, (kMaxE + 4) / 5>(buf, pl.n, p, nbatch, bs, tw, sign, tid, nthr);
+    p *= r;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// row passes
+// ---------------------------------------------------------------------------------------
+template <typename T>
+struct RealFields {
+  const T* p[8];
+  int count;           // number of real fields
+  long long bstride;   // element offset between batch items
+};
+
+template <typename T>
+struct OutFields {
+  T* p[8];
+  const T* add[8];
+  int count;
+  long long bstride;
+};
+
+// Forward row pass: fields (2q, 2q+1) of 'in' (batch item z) packed as one complex row, FFT along
+// x2, unpacked into half spectra S[z][f][x1][k2] (f = 2q, 2q+1; k2 in [0, n2/2]).
+template <typename T>
+__global__ void __launch_bounds__(256) k_row_fwd(RealFields<T> in, cplx<T>* __restrict__ S, int n1, int n2,
+                                                 int rpb, FFTPlanDev pl) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int nh = n2 / 2 + 1;
+  const int bs = n2 + 1;
+  const int q = blockIdx.y;
+  const int z = blockIdx.z;
+  const int r0 = blockIdx.x * rpb;
+  const int rows = min(rpb, n1 - r0);
+  const int fa = 2 * q, fb = 2 * q + 1;
+  const long long off = (long long)z * in.bstride;
+  const T* A = in.p[fa] + off;
+  const T* B = fb < in.count ? in.p[fb] + off : nullptr;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  for (int idx = tid; idx < rows * n2; idx += nthr) {
+    const int r = idx / n2, c = idx - r * n2;
+    const size_t gi = size_t(r0 + r) * n2 + c;
+    buf[r * bs + c] = {A[gi], B ? B[gi] : T(0)};
+  }
+  __syncthreads();
+  fft_lds<T>(buf, pl, rows, bs, -1, tid, nthr);
+  const size_t sf = size_t(n1) * nh;
+  cplx<T>* SA = S + (size_t(z) * in.count + fa) * sf;
+  cplx<T>* SB = S + (size_t(z) * in.count + fb) * sf;
+  for (int idx = tid; idx < rows * nh; idx += nthr) {
+    const int r = idx / nh, k = idx - r * nh;
+    const cplx<T> zk = buf[r * bs + k];
+    const cplx<T> zm = cconj(buf[r * bs + (k == 0 ? 0 : n2 - k)]);
+    const size_t o = size_t(r0 + r) * nh + k;
+    SA[o] = cscale(cadd(zk, zm), T(0.5));
+    if (B) SB[o] = cscale(cmul_mi(csub(zk, zm)), T(0.5));
+  }
+}
+
+// Inverse row pass: half spectra (2q, 2q+1) of S[z] -> real fields out (plus optional addend).
+template <typename T>
+__global__ void __launch_bounds__(256) k_row_inv(const cplx<T>* __restrict__ S, int nspec, OutFields<T> out,
+                                                 int n1, int n2, int rpb, FFTPlanDev pl) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int nh = n2 / 2 + 1;
+  const int bs = n2 + 1;
+  const int q = blockIdx.y;
+  const int z = blockIdx.z;
+  const int r0 = blockIdx.x * rpb;
+  const int rows = min(rpb, n1 - r0);
+  const int fa = 2 * q, fb = 2 * q + 1;
+  const bool hasb = fb < out.count;
+  const size_t sf = size_t(n1) * nh;
+  const cplx<T>* SA = S + (size_t(z) * nspec + fa) * sf;
+  const cplx<T>* SB = S + (size_t(z) * nspec + fb) * sf;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  for (int idx = tid; idx < rows * n2; idx += nthr) {
+    const int r = idx / n2, k = idx - r * n2;
+    const bool mirror = k > n2 / 2;
+    const int kk = mirror ? n2 - k : k;
+    const size_t o = size_t(r0 + r) * nh + kk;
+    cplx<T> a = SA[o];
+    cplx<T> b = hasb ? SB[o] : cplx<T>{T(0), T(0)};
+    if (kk == 0 || kk == n2 / 2) {  // a real row's DC and Nyquist coefficients are real
+      a.y = T(0);
+      b.y = T(0);
+    }
+    if (mirror) {
+      a = cconj(a);
+      b = cconj(b);
+    }
+    buf[r * bs + k] = cadd(a, cmul_i(b));
+  }
+  __syncthreads();
+  fft_lds<T>(buf, pl, rows, bs, +1, tid, nthr);
+  const long long off = (long long)z * out.bstride;
+  T* OA = out.p[fa] + off;
+  T* OB = hasb ? out.p[fb] + off : nullptr;
+  const T* AA = out.add[fa] ? out.add[fa] + off : nullptr;
+  const T* AB = hasb && out.add[fb] ? out.add[fb] + off : nullptr;
+  for (int idx = tid; idx < rows * n2; idx += nthr) {
+    const int r = idx / n2, c = idx - r * n2;
+    const size_t gi = size_t(r0 + r) * n2 + c;
+    const cplx<T> val = buf[r * bs + c];
+    OA[gi] = AA ? val.x + AA[gi] : val.x;
+    if (OB) OB[gi] = AB ? val.y + AB[gi] : val.y;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// column pass with a symbol
+// ---------------------------------------------------------------------------------------
+enum ColFlags : int { kInK = 1, kOutK = 2 };
+
+// Column pass over B columns (k2 = c0 .. c0 + B - 1) of every input spectrum of batch item z:
+// forward FFT along x1 (unless kInK), op at every (k1, k2), inverse FFT (unless kOutK).
+template <typename T, class Op>
+__global__ void __launch_bounds__(1024) k_col(const cplx<T>* __restrict__ Sin, cplx<T>* __restrict__ Sout, int n1,
+                                              int n2, int B, FFTPlanDev pl, Op op, int flags) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  constexpr int NIN = Op::NIN, NOUT = Op::NOUT;
+  const int nh = n2 / 2 + 1;
+  const int bs = n1 + 1;
+  const int c0 = blockIdx.x * B;
+  const int cols = min(B, nh - c0);
+  const int z = blockIdx.z;
+  const size_t sf = size_t(n1) * nh;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const cplx<T>* in = Sin + size_t(z) * NIN * sf;
+  for (int f = 0; f < NIN; ++f)
+    for (int idx = tid; idx < n1 * cols; idx += nthr) {
+      const int e = idx / cols, b = idx - e * cols;
+      buf[(f * B + b) * bs + e] = in[f * sf + size_t(e) * nh + c0 + b];
+    }
+  __syncthreads();
+  if (!(flags & kInK)) fft_lds<T>(buf, pl, NIN * B, bs, -1, tid, nthr);
+  for (int idx = tid; idx < n1 * cols; idx += nthr) {
+    const int b = idx / n1, e = idx - b * n1;
+    cplx<T> vin[NIN > 0 ? NIN : 1];
+    cplx<T> vout[NOUT > 0 ? NOUT : 1];
+#pragma unroll
+    for (int f = 0; f < NIN; ++f) vin[f] = buf[(f * B + b) * bs + e];
+    op(signed_wavenumber(e, n1), c0 + b, e, z, vin, vout);
+#pragma unroll
+    for (int f = 0; f < NOUT; ++f) buf[(f * B + b) * bs + e] = vout[f];
+  }
+  __syncthreads();
+  if (NOUT == 0) return;
+  if (!(flags & kOutK)) fft_lds<T>(buf, pl, NOUT * B, bs, +1, tid, nthr);
+  cplx<T>* out = Sout + size_t(z) * NOUT * sf;
+  for (int f = 0; f < NOUT; ++f)
+    for (int idx = tid; idx < n1 * cols; idx += nthr) {
+      const int e = idx / cols, b = idx - e * cols;
+      out[f * sf + size_t(e) * nh + c0 + b] = buf[(f * B + b) * bs + e];
+    }
+}
+
+// ---- symbols ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T odd_k(int k, int n) { return (2 * k == -n) ? T(0) : T(k); }  // Nyquist dropped
+
+template <typename T>
+__device__ __forceinline__ T spline_symbol(int k1, int n1, int k2, int n2) {
+  const T b1 = (T(2) + cospi(T(2) * T(k1) / T(n1))) / T(3);
+  const T b2 = (T(2) + cospi(T(2) * T(k2) / T(n2))) / T(3);
+  return b1 * b2;
+}
+
+template <typename T>
+__device__ __forceinline__ T reg_a(int k1, int k2, int reg) {
+  const T q = T(k1) * T(k1) + T(k2) * T(k2);
+  T a = q;
+  for (int r = 1; r < reg; ++r) a *= q;
+  return a;
+}
+
+template <typename T>
+__device__ __forceinline__ T symbol_value(const SymbolParams& sp, int k1, int n1, int k2, int n2) {
+  switch (sp.kind) {
+    case Symbol::Reg:
+      return T(sp.beta) * reg_a<T>(k1, k2, sp.reg);
+    case Symbol::RegInv: {
+      T a = reg_a<T>(k1, k2, sp.reg);
+      if (a == T(0)) a = T(1);
+      return T(1) / (T(sp.beta) * a);
+    }
+    case Symbol::RegInvSqrt: {
+      T a = reg_a<T>(k1, k2, sp.reg);
+      if (a == T(0)) a = T(1);
+      return T(1) / sqrt(T(sp.beta) * a);
+    }
+    case Symbol::LowPass:
+      return (4 * abs(k1) < n1 && 4 * abs(k2) < n2) ? T(1) : T(0);
+    case Symbol::HighPass:
+      return (4 * abs(k1) < n1 && 4 * abs(k2) < n2) ? T(0) : T(1);
+    case Symbol::Spline:
+    default:
+      return T(1) / spline_symbol<T>(k1, n1, k2, n2);
+  }
+}
+
+template <typename T, int NF>
+struct OpScale {
+  static constexpr int NIN = NF, NOUT = NF;
+  SymbolParams sp;
+  int n1, n2;
+  double inv_n;
+  __device__ void operator()(int k1, int k2, int, int, const cplx<T>* in, cplx<T>* out) const {
+    const int k2s = (2 * k2 == n2) ? -k2 : k2;
+    const T s = symbol_value<T>(sp, k1, n1, k2s, n2) * T(inv_n);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) out[f] = cscale(in[f], s);
+  }
+};
+
+template <typename T>
+struct OpGrad {
+  static constexpr int NIN = 1, NOUT = 2;
+  int n1, n2;
+  double inv_n;
+  __device__ void operator()(int k1, int k2, int, int, const cplx<T>* in, cplx<T>* out) const {
+    const T s = T(inv_n);
+    out[0] = cmul_i(cscale(in[0], odd_k<T>(k1, n1) * s));
+    out[1] = cmul_i(cscale(in[0], (2 * k2 == n2 ? T(0) : T(k2)) * s));
+  }
+};
+
+template <typename T>
+struct OpTracePrep {
+  static constexpr int NIN = 2, NOUT = 6;  // cv1, cv2, div v, c_div, beta A v1, beta A v2
+  int n1, n2, reg;
+  double beta, inv_n;
+  __device__ void operator()(int k1, int k2, int, int, const cplx<T>* in, cplx<T>* out) const {
+    const int k2s = (2 * k2 == n2) ? -k2 : k2;
+    const T s = T(inv_n);
+    const T ib = s / spline_symbol<T>(k1, n1, k2s, n2);
+    const T ba = T(beta) * reg_a<T>(k1, k2s, reg) * s;
+    const T o1 = odd_k<T>(k1, n1), o2 = (2 * k2 == n2) ? T(0) : T(k2);
+    const cplx<T> d = cmul_i(cadd(cscale(in[0], o1), cscale(in[1], o2)));
+    out[0] = cscale(in[0], ib);
+    out[1] = cscale(in[1], ib);
+    out[2] = cscale(d, s);
+    out[3] = cscale(d, ib);
+    out[4] = cscale(in[0], ba);
+    out[5] = cscale(in[1], ba);
+  }
+};
+
+// k-space identity (used for coarse forward transforms and coarse inverse transforms)
+template <typename T, int NF>
+struct OpCopy {
+  static constexpr int NIN = NF, NOUT = NF;
+  __device__ void operator()(int, int, int, int, const cplx<T>* in, cplx<T>* out) const {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) out[f] = in[f];
+  }
+};
+
+// Restriction: writes the surviving modes of the fine spectrum (scaled by 1/N_fine so that the
+// coarse inverse needs no further scale) into the coarse k-space buffer, and keeps the fine
+// spectrum (output, k-space) when asked.
+template <typename T, int NF>
+struct OpRestrict {
+  static constexpr int NIN = NF, NOUT = NF;
+  cplx<T>* coarse;   // [z][NF][nc1][nch] k-space
+  int n1, n2, nc1, nc2;
+  double inv_n;
+  __device__ void operator()(int k1, int k2, int, int z, const cplx<T>* in, cplx<T>* out) const {
+    const int nch = nc2 / 2 + 1;
+    if (4 * abs(k1) < n1 && 4 * k2 < n2) {
+      const int e = k1 < 0 ? k1 + nc1 : k1;
+      const size_t sfc = size_t(nc1) * nch;
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+        coarse[(size_t(z) * NF + f) * sfc + size_t(e) * nch + k2] = cscale(in[f], T(inv_n));
+    } else if (abs(k1) <= nc1 / 2 && k2 <= nc2 / 2) {
+      // coarse Nyquist row/column: dropped
+      const int e = k1 < 0 ? k1 + nc1 : k1;
+      if (e < nc1) {
+        const size_t sfc = size_t(nc1) * nch;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) coarse[(size_t(z) * NF + f) * sfc + size_t(e) * nch + k2] = {T(0), T(0)};
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) out[f] = in[f];
+  }
+};
+
+// Two-level combine (input: kept fine spectrum, k-space): high-pass part of it plus the
+// zero-padded coarse spectrum; 1/N_fine for the fine inverse, N_fine/N_coarse for the padding.
+template <typename T, int NF>
+struct OpProlongCombine {
+  static constexpr int NIN = NF, NOUT = NF;
+  const cplx<T>* coarse;   // [NF][nc1][nch] k-space (forward transform, unnormalised)
+  int n1, n2, nc1, nc2;
+  double inv_n, inv_nc;
+  __device__ void operator()(int k1, int k2, int, int, const cplx<T>* in, cplx<T>* out) const {
+    const int nch = nc2 / 2 + 1;
+    const bool low = 4 * abs(k1) < n1 && 4 * k2 < n2;
+    const size_t sfc = size_t(nc1) * nch;
+    const int e = k1 < 0 ? k1 + nc1 : k1;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      if (low)
+        out[f] = cscale(coarse[f * sfc + size_t(e) * nch + k2], T(inv_nc));
+      else
+        out[f] = cscale(in[f], T(inv_n));
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------------------
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+template <typename T>
+void row_config(int n2, int& nthr, int& rpb) {
+  nthr = std::min(256, std::max(64, round_up(n2 / 4, 64)));
+  rpb = std::max(1, (nthr * 4) / n2);
+  while (rpb * n2 > nthr * kMaxE) --rpb;
+}
+
+template <typename T>
+hipError_t launch_row_fwd(hipStream_t s, const SpecGrid<T>& g, RealFields<T> in, int batch, cplx<T>* S) {
+  int nthr, rpb;
+  row_config<T>(g.n2, nthr, rpb);
+  dim3 grid((g.n1 + rpb - 1) / rpb, (in.count + 1) / 2, batch);
+  size_t lds = size_t(rpb) * (g.n2 + 1) * sizeof(cplx<T>);
+  hipLaunchKernelGGL(k_row_fwd<T>, grid, dim3(nthr), lds, s, in, S, g.n1, g.n2, rpb, g.row);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_row_inv(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* S, int nspec, OutFields<T> out,
+                          int batch) {
+  int nthr, rpb;
+  row_config<T>(g.n2, nthr, rpb);
+  dim3 grid((g.n1 + rpb - 1) / rpb, (out.count + 1) / 2, batch);
+  size_t lds = size_t(rpb) * (g.n2 + 1) * sizeof(cplx<T>);
+  hipLaunchKernelGGL(k_row_inv<T>, grid, dim3(nthr), lds, s, S, nspec, out, g.n1, g.n2, rpb, g.row);
+  return hipGetLastError();
+}
+
+template <typename T, class Op>
+hipError_t launch_col(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* Sin, cplx<T>* Sout, Op op, int flags,
+                      int batch) {
+  constexpr int nmax = Op::NIN > Op::NOUT ? Op::NIN : Op::NOUT;
+  const int nh = g.nh();
+  const int col_bytes = (g.n1 + 1) * int(sizeof(cplx<T>)) * nmax;
+  // a few columns per block: enough blocks to spread a small grid over the chip, and every
+  // FFT stage within kMaxE elements per thread at <= 1024 threads
+  int B = std::max(1, std::min(std::min(16, std::max(1, nh / 64)), kLdsBudget / col_bytes));
+  while (B > 1 && nmax * B * g.n1 > 1024 * kMaxE) --B;
+  const int elems = nmax * B * g.n1;
+  int nthr = std::min(1024, std::max(64, round_up((elems + 3) / 4, 64)));
+  while (nthr < 1024 && elems > nthr * kMaxE) nthr += 64;
+  dim3 grid((nh + B - 1) / B, 1, batch);
+  size_t lds = size_t(B) * col_bytes;
+  hipLaunchKernelGGL((k_col<T, Op>), grid, dim3(nthr), lds, s, Sin, Sout, g.n1, g.n2, B, g.col, op, flags);
+  return hipGetLastError();
+}
+
+#define RET_IF(e)                  \
+  do {                             \
+    hipError_t _e = (e);           \
+    if (_e != hipSuccess) return _e; \
+  } while (0)
+
+}  // namespace
+
+template <typename T>
+hipError_t spec_scale(hipStream_t s, const SpecGrid<T>& g, SymbolParams sym, int nf, const T* in, T* out,
+                      const T* add, cplx<T>* S1, cplx<T>* S2) {
+  const size_t F = g.field();
+  RealFields<T> rin{};
+  OutFields<T> rout{};
+  rin.count = nf;
+  rout.count = nf;
+  for (int f = 0; f < nf; ++f) {
+    rin.p[f] = in + f * F;
+    rout.p[f] = out + f * F;
+    rout.add[f] = add ? add + f * F : nullptr;
+  }
+  RET_IF(launch_row_fwd<T>(s, g, rin, 1, S1));
+  const double inv_n = 1.0 / double(F);
+  if (nf == 1) {
+    OpScale<T, 1> op{sym, g.n1, g.n2, inv_n};
+    RET_IF(launch_col<T>(s, g, S1, S2, op, 0, 1));
+  } else {
+    OpScale<T, 2> op{sym, g.n1, g.n2, inv_n};
+    RET_IF(launch_col<T>(s, g, S1, S2, op, 0, 1));
+  }
+  return launch_row_inv<T>(s, g, S2, nf, rout, 1);
+}
+
+template <typename T>
+hipError_t spec_grad(hipStream_t s, const SpecGrid<T>& g, int batch, const T* m, T* gm, cplx<T>* S1, cplx<T>* S2) {
+  const size_t F = g.field();
+  RealFields<T> rin{};
+  rin.count = 1;
+  rin.p[0] = m;
+  rin.bstride = (long long)F;
+  RET_IF(launch_row_fwd<T>(s, g, rin, batch, S1));
+  OpGrad<T> op{g.n1, g.n2, 1.0 / double(F)};
+  RET_IF(launch_col<T>(s, g, S1, S2, op, 0, batch));
+  OutFields<T> rout{};
+  rout.count = 2;
+  rout.p[0] = gm;
+  rout.p[1] = gm + F;
+  rout.bstride = (long long)(2 * F);
+  return launch_row_inv<T>(s, g, S2, 2, rout, batch);
+}
+
+template <typename T>
+hipError_t spec_trace_prep(hipStream_t s, const SpecGrid<T>& g, int reg, double beta, const T* v, T* cv, T* divv,
+                           T* cdiv, T* bAv, cplx<T>* S1, cplx<T>* S2) {
+  const size_t F = g.field();
+  RealFields<T> rin{};
+  rin.count = 2;
+  rin.p[0] = v;
+  rin.p[1] = v + F;
+  RET_IF(launch_row_fwd<T>(s, g, rin, 1, S1));
+  OpTracePrep<T> op{g.n1, g.n2, reg, beta, 1.0 / double(F)};
+  RET_IF(launch_col<T>(s, g, S1, S2, op, 0, 1));
+  OutFields<T> rout{};
+  rout.count = 6;
+  rout.p[0] = cv;
+  rout.p[1] = cv + F;
+  rout.p[2] = divv;
+  rout.p[3] = cdiv;
+  rout.p[4] = bAv;
+  rout.p[5] = bAv + F;
+  return launch_row_inv<T>(s, g, S2, 6, rout, 1);
+}
+
+template <typename T>
+hipError_t spec_restrict(hipStream_t s, const SpecGrid<T>& g, const SpecGrid<T>& gc, int nf, const T* in, T* out_c,
+                         cplx<T>* keep_fine, cplx<T>* S1, cplx<T>* Sc1, cplx<T>* Sc2) {
+  const size_t F = g.field(), Fc = gc.field();
+  RealFields<T> rin{};
+  rin.count = nf;
+  for (int f = 0; f < nf; ++f) rin.p[f] = in + f * F;
+  RET_IF(launch_row_fwd<T>(s, g, rin, 1, S1));
+  const double inv_n = 1.0 / double(F);
+  // the fine column pass only writes the coarse k-space (and keeps the fine spectrum if asked)
+  if (nf == 1) {
+    OpRestrict<T, 1> op{Sc1, g.n1, g.n2, gc.n1, gc.n2, inv_n};
+    RET_IF(launch_col<T>(s, g, S1, keep_fine ? keep_fine : S1, op, kOutK, 1));
+    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 1>{}, kInK, 1));
+  } else {
+    OpRestrict<T, 2> op{Sc1, g.n1, g.n2, gc.n1, gc.n2, inv_n};
+    RET_IF(launch_col<T>(s, g, S1, keep_fine ? keep_fine : S1, op, kOutK, 1));
+    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 2>{}, kInK, 1));
+  }
+  OutFields<T> rout{};
+  rout.count = nf;
+  for (int f = 0; f < nf; ++f) rout.p[f] = out_c + f * Fc;
+  return launch_row_inv<T>(s, gc, Sc2, nf, rout, 1);
+}
+
+template <typename T>
+hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecGrid<T>& gc, int nf,
+                                const cplx<T>* fine_k, const T* zc, T* out, cplx<T>* S1, cplx<T>* Sc1,
+                                cplx<T>* Sc2) {
+  const size_t F = g.field(), Fc = gc.field();
+  RealFields<T> rin{};
+  rin.count = nf;
+  for (int f = 0; f < nf; ++f) rin.p[f] = zc + f * Fc;
+  RET_IF(launch_row_fwd<T>(s, gc, rin, 1, Sc1));
+  if (nf == 1) {
+    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 1>{}, kOutK, 1));
+    OpProlongCombine<T, 1> op{Sc2, g.n1, g.n2, gc.n1, gc.n2, 1.0 / double(F), 1.0 / double(Fc)};
+    RET_IF(launch_col<T>(s, g, fine_k, S1, op, kInK, 1));
+  } else {
+    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 2>{}, kOutK, 1));
+    OpProlongCombine<T, 2> op{Sc2, g.n1, g.n2, gc.n1, gc.n2, 1.0 / double(F), 1.0 / double(Fc)};
+    RET_IF(launch_col<T>(s, g, fine_k, S1, op, kInK, 1));
+  }
+  OutFields<T> rout{};
+  rout.count = nf;
+  for (int f = 0; f < nf; ++f) rout.p[f] = out + f * F;
+  return launch_row_inv<T>(s, g, S1, nf, rout, 1);
+}
+
+#define INST(T)                                                                                                 \
+  template hipError_t spec_scale<T>(hipStream_t, const SpecGrid<T>&, SymbolParams, int, const T*, T*, const T*, \
+                                    cplx<T>*, cplx<T>*);                                                        \
+  template hipError_t spec_grad<T>(hipStream_t, const SpecGrid<T>&, int, const T*, T*, cplx<T>*, cplx<T>*);     \
+  template hipError_t spec_trace_prep<T>(hipStream_t, const SpecGrid<T>&, int, double, const T*, T*, T*, T*, T*, \
+                                         cplx<T>*, cplx<T>*);                                                   \
+  template hipError_t spec_restrict<T>(hipStream_t, const SpecGrid<T>&, const SpecGrid<T>&, int, const T*, T*,  \
+                                       cplx<T>*, cplx<T>*, cplx<T>*, cplx<T>*);                                 \
+  template hipError_t spec_prolong_combine<T>(hipStream_t, const SpecGrid<T>&, const SpecGrid<T>&, int,         \
+                                              const cplx<T>*, const T*, T*, cplx<T>*, cplx<T>*, cplx<T>*);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace slnk

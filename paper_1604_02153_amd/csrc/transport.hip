@@ -1,0 +1,413 @@
+// Semi-Lagrangian transport on gfx950 (section 3.3.2: tracing the characteristic by Heun's
+// method, cubic spline interpolation at the departure points, RK2 along the characteristic;
+// eqs. e:state-slm, e:adj-slm, e:inc-state-slm, e:inc-adj-slm).
+//
+// One time step of any of the four transport equations is one kernel.  A 16x16 tile of output
+// nodes stages the transported field over its departure-point footprint plus the support of the
+// spline prefilter in LDS, computes the periodic cubic B-spline coefficients there with the
+// separable exponential filter c = sqrt(3) sum_t z^|t| f[i+t], z = sqrt(3) - 2 (the inverse of
+// the circulant (1, 4, 1)/6 operator, truncated where |z|^t falls below the working precision),
+// gathers the 4x4 tensor B-spline stencil at every departure point and applies the step's
+// update (Heun weights, adjoint factor, time-integral accumulation) in registers.
+#include "kernels.hpp"
+
+namespace slnk {
+namespace {
+
+constexpr int kTile = 16;
+
+template <typename T>
+struct FilterTaps;
+// |z|^(K+1) * 2 sqrt(3) / (1 - |z|) < 4e-9 (FP32) and < 2e-16 (FP64)
+template <>
+struct FilterTaps<float> {
+  static constexpr int K = 15;
+};
+template <>
+struct FilterTaps<double> {
+  static constexpr int K = 28;
+};
+
+__constant__ double c_taps_d[FilterTaps<double>::K + 1];
+__constant__ float c_taps_f[FilterTaps<float>::K + 1];
+
+template <typename T>
+__device__ __forceinline__ T tap(int t);
+template <>
+__device__ __forceinline__ float tap<float>(int t) { return c_taps_f[t]; }
+template <>
+__device__ __forceinline__ double tap<double>(int t) { return c_taps_d[t]; }
+
+bool g_taps_ready = false;
+
+hipError_t upload_taps() {
+  if (g_taps_ready) return hipSuccess;
+  // exact coefficients in FP64 from the closed form
+  const double z = std::sqrt(3.0) - 2.0;
+  double td[FilterTaps<double>::K + 1];
+  float tf[FilterTaps<float>::K + 1];
+  for (int t = 0; t <= FilterTaps<double>::K; ++t) td[t] = std::sqrt(3.0) * std::pow(z, t);
+  for (int t = 0; t <= FilterTaps<float>::K; ++t) tf[t] = float(td[t]);
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_taps_d), td, sizeof(td));
+  if (e != hipSuccess) return e;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_taps_f), tf, sizeof(tf));
+  if (e == hipSuccess) g_taps_ready = true;
+  return e;
+}
+
+template <typename T>
+__device__ __forceinline__ void bspline_w(T t, T* w) {
+  const T t2 = t * t, t3 = t2 * t;
+  const T s = T(1) - t;
+  w[0] = s * s * s / T(6);
+  w[1] = (T(3) * t3 - T(6) * t2 + T(4)) / T(6);
+  w[2] = (T(-3) * t3 + T(3) * t2 + T(3) * t + T(1)) / T(6);
+  w[3] = t3 / T(6);
+}
+
+// Spline value at (s1, s2) (in cells) from a global coefficient field, periodic.
+template <typename T>
+__device__ T interp_global(const T* __restrict__ c, int n1, int n2, T s1, T s2) {
+  const T f1 = floor(s1), f2 = floor(s2);
+  T w1[4], w2[4];
+  bspline_w(s1 - f1, w1);
+  bspline_w(s2 - f2, w2);
+  const int i1 = int(f1) - 1, i2 = int(f2) - 1;
+  int cols[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) cols[b] = wrap_index(i2 + b, n2);
+  T acc = T(0);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const T* row = c + size_t(wrap_index(i1 + a, n1)) * n2;
+    T r = T(0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) r += w2[b] * row[cols[b]];
+    acc += w1[a] * r;
+  }
+  return acc;
+}
+
+// FP64 block reduction of two values: (sum, max).  Writes partial[2 * block + {0, 1}].
+__device__ void block_sum_max(double s, double m, double* partial) {
+  __shared__ double rs[16], rm[16];
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_down(s, off, 64);
+    m = fmax(m, __shfl_down(m, off, 64));
+  }
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+  if ((tid & 63) == 0) {
+    rs[tid >> 6] = s;
+    rm[tid >> 6] = m;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double ts = 0.0, tm = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      ts += rs[w];
+      tm = fmax(tm, rm[w]);
+    }
+    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+    partial[2 * bid] = ts;
+    partial[2 * bid + 1] = tm;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// fused prefilter + gather step
+// ------------------------------------------------------------------------------------------
+template <typename T, int KIND, bool FIRST>
+__device__ __forceinline__ T load_src(const StepArgs<T>& a, size_t gi) {
+  if constexpr (FIRST && KIND == int(StepKind::Adjoint)) {
+    return a.aux0[gi] - a.aux1[gi];  // lambda(1) = m_R - m(1)
+  } else if constexpr (FIRST && KIND == int(StepKind::IncState)) {
+    const size_t F = size_t(a.n1) * a.n2;
+    // q^0 = (ht/2) f^0, f = -vt . grad m^0
+    return -T(0.5 * a.ht) * (a.vt[gi] * a.gm_old[gi] + a.vt[gi + F] * a.gm_old[gi + F]);
+  } else {
+    return a.src[gi];
+  }
+}
+
+// Stage the transported field over the rows [y0 - lo - K, y0 - lo + G + K) (and likewise the
+// columns) and filter it into the B-spline coefficients of the inner G x G region, which starts
+// at global node (y0 - lo, x0 - lo) and is left at LDS offset 0 of 'A'.  The step kernel uses
+// lo = D + 1, G = 16 + 2D + 3 (the stencil footprint of displacements |d| <= D); the
+// coefficient-only kernel uses lo = 0, G = 16.
+template <typename T, int KIND, bool FIRST>
+__device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, int y0, int x0, int lo, int G) {
+  constexpr int K = FilterTaps<T>::K;
+  const int P = G + 2 * K;
+  T* B1 = A + P * P;  // rows P x cols G
+  T* C = A;           // rows G x cols G (A is dead once B1 is built)
+  const int n1 = a.n1, n2 = a.n2;
+  const int ry = y0 - lo - K, rx = x0 - lo - K;
+  const int tid = threadIdx.y * kTile + threadIdx.x;
+  constexpr int nthr = kTile * kTile;
+  // 1. stage the transported field over the footprint (periodic wrap)
+  for (int idx = tid; idx < P * P; idx += nthr) {
+    const int r = idx / P, c = idx - r * P;
+    const size_t gi = size_t(wrap_index(ry + r, n1)) * n2 + wrap_index(rx + c, n2);
+    A[idx] = load_src<T, KIND, FIRST>(a, gi);
+  }
+  __syncthreads();
+  // 2. prefilter along x2
+  for (int idx = tid; idx < P * G; idx += nthr) {
+    const int r = idx / G, c = idx - r * G;
+    const T* row = A + r * P + c + K;
+    T s = tap<T>(0) * row[0];
+#pragma unroll 4
+    for (int t = 1; t <= K; ++t) s += tap<T>(t) * (row[-t] + row[t]);
+    B1[idx] = s;
+  }
+  __syncthreads();
+  // 3. prefilter along x1
+  for (int idx = tid; idx < G * G; idx += nthr) {
+    const int r = idx / G, c = idx - r * G;
+    const T* col = B1 + (r + K) * G + c;
+    T s = tap<T>(0) * col[0];
+#pragma unroll 4
+    for (int t = 1; t <= K; ++t) s += tap<T>(t) * (col[-t * G] + col[t * G]);
+    C[idx] = s;
+  }
+  __syncthreads();
+}
+
+// Coefficient-only pass (used when the departure footprint exceeds the LDS budget): writes the
+// B-spline coefficients of the step's source field to a.coef.
+template <typename T, int KIND, bool FIRST>
+__global__ void __launch_bounds__(256) k_prefilter(StepArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  T* A = reinterpret_cast<T*>(smem_raw);
+  const int y0 = blockIdx.y * kTile, x0 = blockIdx.x * kTile;
+  stage_coefficients<T, KIND, FIRST>(a, A, y0, x0, 0, kTile);
+  const int i1 = y0 + threadIdx.y, i2 = x0 + threadIdx.x;
+  if (i1 < a.n1 && i2 < a.n2) a.coef[size_t(i1) * a.n2 + i2] = A[threadIdx.y * kTile + threadIdx.x];
+}
+
+template <typename T, int KIND, bool FIRST, bool GLOBAL>
+__global__ void __launch_bounds__(256) k_sl_step(StepArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  T* C = reinterpret_cast<T*>(smem_raw);
+  const int D = a.halo;
+  const int G = kTile + 2 * D + 3;
+  const int n1 = a.n1, n2 = a.n2;
+  const int y0 = blockIdx.y * kTile, x0 = blockIdx.x * kTile;
+  if constexpr (!GLOBAL) stage_coefficients<T, KIND, FIRST>(a, C, y0, x0, D + 1, G);
+
+  // 4. gather at the departure point of this thread's node and update
+  const int i1 = y0 + threadIdx.y, i2 = x0 + threadIdx.x;
+  double red_s = 0.0, red_m = 0.0;
+  if (i1 < n1 && i2 < n2) {
+    const size_t gi = size_t(i1) * n2 + i2;
+    const size_t F = size_t(n1) * n2;
+    const T s1 = T(i1) + a.d1[gi], s2 = T(i2) + a.d2[gi];
+    T u = T(0);
+    if constexpr (GLOBAL) {
+      u = interp_global(a.coef, n1, n2, s1, s2);
+    } else {
+      const T f1 = floor(s1), f2 = floor(s2);
+      T w1[4], w2[4];
+      bspline_w(s1 - f1, w1);
+      bspline_w(s2 - f2, w2);
+      // LDS coordinates of the first stencil row/column (region origin y0 - D - 1); the clamp
+      // is inactive whenever |d| <= D, which the caller guarantees
+      int l1 = int(f1) - y0 + D;
+      int l2 = int(f2) - x0 + D;
+      l1 = min(max(l1, 0), G - 4);
+      l2 = min(max(l2, 0), G - 4);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const T* row = C + (l1 + p) * G + l2;
+        u += w1[p] * (w2[0] * row[0] + w2[1] * row[1] + w2[2] * row[2] + w2[3] * row[3]);
+      }
+    }
+    if constexpr (KIND == int(StepKind::State)) {
+      a.dst[gi] = u;
+      if (a.last) {
+        const double r = double(u) - double(a.aux0[gi]);
+        red_s = r * r;
+      }
+    } else if constexpr (KIND == int(StepKind::Adjoint)) {
+      const T lam = a.gamma[gi] * u;
+      if (a.dst) a.dst[gi] = lam;
+      T b1 = T(a.w_new) * lam * a.gm_new[gi];
+      T b2 = T(a.w_new) * lam * a.gm_new[gi + F];
+      if constexpr (FIRST) {
+        const T l1v = a.aux0[gi] - a.aux1[gi];
+        b1 += T(a.w_old) * l1v * a.gm_old[gi];
+        b2 += T(a.w_old) * l1v * a.gm_old[gi + F];
+      } else {
+        b1 += a.acc[gi];
+        b2 += a.acc[gi + F];
+      }
+      if (a.last) {
+        const T g1 = a.addf[gi] + b1, g2 = a.addf[gi + F] + b2;
+        a.out2[gi] = g1;
+        a.out2[gi + F] = g2;
+        red_s = double(g1) * double(g1) + double(g2) * double(g2);
+        red_m = fmax(fabs(double(g1)), fabs(double(g2)));
+      } else {
+        a.acc[gi] = b1;
+        a.acc[gi + F] = b2;
+      }
+    } else if constexpr (KIND == int(StepKind::IncState)) {
+      const T fnew = -(a.vt[gi] * a.gm_new[gi] + a.vt[gi + F] * a.gm_new[gi + F]);
+      if (!a.last) {
+        a.dst[gi] = u + T(a.ht) * fnew;  // q^j = m~^j + (ht/2) f^j
+      } else {
+        const T lt = -(u + T(0.5 * a.ht) * fnew);  // lambda~(1) = -m~(1)
+        a.dst[gi] = lt;
+        a.acc[gi] = T(a.w_new) * lt * a.gm_new[gi];
+        a.acc[gi + F] = T(a.w_new) * lt * a.gm_new[gi + F];
+      }
+    } else {  // IncAdjoint
+      const T lt = a.gamma[gi] * u;
+      if (a.dst) a.dst[gi] = lt;
+      a.acc[gi] += T(a.w_new) * lt * a.gm_new[gi];
+      a.acc[gi + F] += T(a.w_new) * lt * a.gm_new[gi + F];
+    }
+  }
+  if (a.partial && a.last) block_sum_max(red_s, red_m, a.partial);
+}
+
+template <typename T>
+size_t step_lds_bytes(int G) {
+  const int P = G + 2 * FilterTaps<T>::K;
+  return size_t(P * P + P * G) * sizeof(T);
+}
+
+size_t g_lds_limit = 0;
+
+hipError_t lds_limit(size_t* out) {
+  if (g_lds_limit == 0) {
+    int dev = 0, v = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    g_lds_limit = size_t(v);
+  }
+  *out = g_lds_limit;
+  return hipSuccess;
+}
+
+// ------------------------------------------------------------------------------------------
+// Heun trace of both characteristics + adjoint factor
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_trace(int n1, int n2, T ht, const T* __restrict__ v,
+                                               const T* __restrict__ cv, const T* __restrict__ divv,
+                                               const T* __restrict__ cdiv, const T* __restrict__ bAv,
+                                               T* __restrict__ df, T* __restrict__ da, T* __restrict__ gamma,
+                                               double* partial) {
+  const int i1 = blockIdx.y * kTile + threadIdx.y, i2 = blockIdx.x * kTile + threadIdx.x;
+  double red_s = 0.0, red_m = 0.0;
+  if (i1 < n1 && i2 < n2) {
+    const size_t F = size_t(n1) * n2;
+    const size_t gi = size_t(i1) * n2 + i2;
+    // velocity in cells per unit time
+    const T c1 = T(n1) / T(2.0 * 3.14159265358979323846), c2 = T(n2) / T(2.0 * 3.14159265358979323846);
+    const T u1 = v[gi] * c1, u2 = v[gi + F] * c2;
+    const T* cv1 = cv;
+    const T* cv2 = cv + F;
+    // forward characteristic: X* = x - ht v(x); X_f = x - ht/2 (v(x) + v(X*))
+    T s1 = T(i1) - ht * u1, s2 = T(i2) - ht * u2;
+    T w1 = interp_global(cv1, n1, n2, s1, s2) * c1, w2 = interp_global(cv2, n1, n2, s1, s2) * c2;
+    const T f1 = -T(0.5) * ht * (u1 + w1), f2 = -T(0.5) * ht * (u2 + w2);
+    // adjoint characteristic: the same with +ht
+    s1 = T(i1) + ht * u1;
+    s2 = T(i2) + ht * u2;
+    w1 = interp_global(cv1, n1, n2, s1, s2) * c1;
+    w2 = interp_global(cv2, n1, n2, s1, s2) * c2;
+    const T e1 = T(0.5) * ht * (u1 + w1), e2 = T(0.5) * ht * (u2 + w2);
+    df[gi] = f1;
+    df[gi + F] = f2;
+    da[gi] = e1;
+    da[gi + F] = e2;
+    const T dD = interp_global(cdiv, n1, n2, T(i1) + e1, T(i2) + e2);
+    const T dx = divv[gi];
+    gamma[gi] = T(1) + T(0.5) * ht * (dD + dx) + T(0.5) * ht * ht * dD * dx;
+    red_s = double(v[gi]) * double(bAv[gi]) + double(v[gi + F]) * double(bAv[gi + F]);
+    red_m = fmax(fmax(fabs(double(f1)), fabs(double(f2))), fmax(fabs(double(e1)), fabs(double(e2))));
+  }
+  if (partial) block_sum_max(red_s, red_m, partial);
+}
+
+}  // namespace
+
+template <typename T>
+int sl_step_max_halo() {
+  size_t lim = 0;
+  if (lds_limit(&lim) != hipSuccess) return -1;
+  int D = -1;
+  while (D < 64 && step_lds_bytes<T>(kTile + 2 * (D + 1) + 3) <= lim) ++D;
+  return D;
+}
+
+template <typename T, int KIND, bool FIRST>
+hipError_t launch_step(hipStream_t s, const StepArgs<T>& a, dim3 grid, dim3 block, bool fused) {
+  if (fused) {
+    const size_t lds = step_lds_bytes<T>(kTile + 2 * a.halo + 3);
+    auto kfn = k_sl_step<T, KIND, FIRST, false>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kfn, grid, block, lds, s, a);
+  } else {
+    const size_t lds = step_lds_bytes<T>(kTile);
+    hipLaunchKernelGGL((k_prefilter<T, KIND, FIRST>), grid, block, lds, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sl_step<T, KIND, FIRST, true>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t sl_step(hipStream_t s, StepKind kind, const StepArgs<T>& a, int* nblocks_out) {
+  hipError_t e = upload_taps();
+  if (e != hipSuccess) return e;
+  const int maxh = sl_step_max_halo<T>();
+  if (a.halo < 0) return hipErrorInvalidValue;
+  const bool fused = a.halo <= maxh;
+  if (!fused && a.coef == nullptr) return hipErrorInvalidValue;
+  dim3 grid((a.n2 + kTile - 1) / kTile, (a.n1 + kTile - 1) / kTile);
+  dim3 block(kTile, kTile);
+  if (nblocks_out) *nblocks_out = int(grid.x * grid.y);
+  switch (kind) {
+    case StepKind::State:
+      return launch_step<T, 0, false>(s, a, grid, block, fused);
+    case StepKind::Adjoint:
+      return a.first ? launch_step<T, 1, true>(s, a, grid, block, fused)
+                     : launch_step<T, 1, false>(s, a, grid, block, fused);
+    case StepKind::IncState:
+      return a.first ? launch_step<T, 2, true>(s, a, grid, block, fused)
+                     : launch_step<T, 2, false>(s, a, grid, block, fused);
+    case StepKind::IncAdjoint:
+      return launch_step<T, 3, false>(s, a, grid, block, fused);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t sl_trace(hipStream_t s, int n1, int n2, double ht, const T* v, const T* cv, const T* divv, const T* cdiv,
+                    const T* bAv, T* df, T* da, T* gamma, double* partial, int* nblocks_out) {
+  dim3 grid((n2 + kTile - 1) / kTile, (n1 + kTile - 1) / kTile);
+  dim3 block(kTile, kTile);
+  if (nblocks_out) *nblocks_out = int(grid.x * grid.y);
+  hipLaunchKernelGGL(k_trace<T>, grid, block, 0, s, n1, n2, T(ht), v, cv, divv, cdiv, bAv, df, da, gamma, partial);
+  return hipGetLastError();
+}
+
+template int sl_step_max_halo<float>();
+template int sl_step_max_halo<double>();
+template hipError_t sl_step<float>(hipStream_t, StepKind, const StepArgs<float>&, int*);
+template hipError_t sl_step<double>(hipStream_t, StepKind, const StepArgs<double>&, int*);
+template hipError_t sl_trace<float>(hipStream_t, int, int, double, const float*, const float*, const float*,
+                                    const float*, const float*, float*, float*, float*, double*, int*);
+template hipError_t sl_trace<double>(hipStream_t, int, int, double, const double*, const double*, const double*,
+                                     const double*, const double*, double*, double*, double*, double*, int*);
+
+}  // namespace slnk

@@ -1,0 +1,228 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 context 1e-11 relative L2 per transport solve, gradient and matvec; mixed
+context (FP32 fields, FP64 reductions) 1e-5 per transport solve and 1e-4 on gradients and
+matvecs.  Sizes span several 16x16 tiles with ragged tails and non-power-of-two factors.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from gpu_common import TOL, problem, reg_floor, rel, same_inputs, split_norm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def slnk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1604_02153_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def _t(a, prec):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
+
+
+def _np(t):
+    return t.double().cpu().numpy()
+
+
+def _ctx(slnk, L, prec, pc="reg", **kw):
+    p = L.prm
+    reg = {1: "h1", 2: "h2", 3: "h3"}[p.reg]
+    return slnk.Context(L.grid.n1, L.grid.n2, p.nt, reg=reg, beta=p.beta, prec=prec, pc=pc, **kw)
+
+
+CASES = [
+    # kind, n1, n2, nt, beta, reg, prec
+    ("smooth", 64, 64, 4, 1e-2, 1, "fp64"),
+    ("gauss", 96, 80, 4, 1e-3, 2, "fp64"),
+    ("gauss", 96, 80, 4, 1e-3, 2, "mixed"),
+    ("gauss", 60, 120, 3, 1e-3, 2, "mixed"),
+    ("gauss", 256, 256, 4, 1e-3, 2, "mixed"),
+    ("gauss", 256, 256, 4, 1e-3, 2, "fp64"),
+    ("smooth", 64, 64, 1, 1e-2, 1, "mixed"),
+]
+
+
+def _check_reg_op(L, prec, got, ref, x, tol):
+    """got ~ ref where ref contains beta A x: relative L2 up to the rounding floor of beta A x,
+    and relative error in the split norm (where that floor is divided back out)."""
+    d = got - ref
+    assert np.linalg.norm(d) <= tol * np.linalg.norm(ref) + reg_floor(L, prec, x)
+    assert split_norm(L, d) <= tol * split_norm(L, ref)
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}{c[1]}x{c[2]}_nt{c[3]}_{c[6]}")
+def test_transport_gradient_matvec(slnk, case):
+    kind, n1, n2, nt, beta, reg, prec = case
+    print(f"case {case}", flush=True)
+    L, vgen, vt = problem(kind, n1, n2, nt=nt, beta=beta, reg=reg)
+    L.mT, L.mR, vgen, vt = same_inputs(prec, L.mT, L.mR, vgen, vt)
+    tol = TOL[prec]
+    ctx = _ctx(slnk, L, prec)
+    # state transport of m_T by the generating velocity (eq. e:state-slm)
+    m1 = torch.empty((n1, n2), dtype=ctx.dtype, device="cuda")
+    ctx.transport_state(_t(vgen, prec), _t(L.mT, prec), m1)
+    assert rel(_np(m1), O.transport_state(L.grid, vgen, L.mT, nt)) < tol["transport"]
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    for scale in (0.0, 0.6):
+        v = same_inputs(prec, scale * vgen)
+        lin = O.linearize(L, v)
+        g_ref = O.gradient(lin)
+        g = torch.empty((2, n1, n2), dtype=ctx.dtype, device="cuda")
+        J = ctx.gradient(_t(v, prec), g)
+        assert abs(J - lin.J) / abs(lin.J) < tol["objective"]
+        _check_reg_op(L, prec, _np(g), g_ref, v, tol["gradient"])
+        # internal fields of the linearisation: state at t = 1, adjoint at t = 0
+        f = torch.empty((n1, n2), dtype=ctx.dtype, device="cuda")
+        ctx.get_field(0, f)
+        assert rel(_np(f), lin.m[-1]) < tol["transport"]
+        ctx.get_field(4, f)
+        if scale > 0:
+            assert rel(_np(f), lin.lam[0]) < 10 * tol["transport"]
+        # GN matvec (eq. e:hessian-matvec)
+        h_ref = O.hessian_matvec(lin, vt)
+        h = torch.empty_like(g)
+        ctx.hessian_matvec(_t(vt, prec), h)
+        _check_reg_op(L, prec, _np(h), h_ref, vt, tol["matvec"])
+        # split operator (no beta A: plain relative L2) and P_REG
+        ctx.split_matvec(_t(vt, prec), h)
+        assert rel(_np(h), O.split_matvec(lin, vt)) < tol["matvec"]
+        ctx.precond_apply(_t(vt, prec), h)
+        assert rel(_np(h), O.prec_reg(L.grid, vt, L.prm.beta, L.prm.reg)) < tol["matvec"]
+    ctx.close()
+
+
+def test_departure_points_and_adjoint_factor(slnk):
+    L, vgen, _ = problem("gauss", 128, 128, nt=4)
+    g = L.grid
+    ctx = _ctx(slnk, L, "fp64")
+    ctx.set_images(_t(L.mR, "fp64"), _t(L.mT, "fp64"))
+    v = vgen
+    ctx.objective(_t(v, "fp64"))
+    lin = O.linearize(L, v)
+    d = torch.empty((2, 128, 128), dtype=torch.float64, device="cuda")
+    ctx.get_field(1, d)
+    cells = (lin.Xf - g.X) / np.array(g.h)[:, None, None]
+    assert np.abs(_np(d) - cells).max() < 1e-11
+    ctx.get_field(2, d)
+    cells = (lin.Xa - g.X) / np.array(g.h)[:, None, None]
+    assert np.abs(_np(d) - cells).max() < 1e-11
+    gam = torch.empty((128, 128), dtype=torch.float64, device="cuda")
+    ctx.get_field(3, gam)
+    assert np.abs(_np(gam) - lin.gamma).max() < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_two_level_preconditioner(slnk, prec):
+    n = 128
+    L, vgen, vt = problem("gauss", n, n, nt=4, beta=1e-3, reg=2)
+    L.mT, L.mR, vgen, vt = same_inputs(prec, L.mT, L.mR, vgen, vt)
+    ctx = _ctx(slnk, L, prec, pc="2l")
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    tl = O.setup_two_level(L)
+    emin, emax = ctx.cheb_bounds()
+    assert abs(emin - tl.emin) < 1e-12 * tl.emin
+    assert abs(emax - tl.emax) / tl.emax < (1e-9 if prec == "fp64" else 1e-5)
+    v = same_inputs(prec, 0.5 * vgen)
+    g = torch.empty((2, n, n), dtype=ctx.dtype, device="cuda")
+    ctx.gradient(_t(v, prec), g)
+    cg = tl.coarse.grid
+    tl.lin_c = O.linearize(tl.coarse, np.stack([O.restrict(L.grid, cg, v[c]) for c in range(2)]))
+    z_ref = O.apply_two_level(L, tl, vt)
+    z = torch.empty_like(g)
+    ctx.precond_apply(_t(vt, prec), z)
+    # the bounds agree to 1e-5 in FP32, which the Chebyshev polynomial passes on
+    assert rel(_np(z), z_ref) < (1e-11 if prec == "fp64" else 1e-4)
+    ctx.close()
+
+
+def test_global_gather_fallback_large_displacement(slnk):
+    """Displacements beyond the LDS footprint take the coefficient pass + global gather."""
+    n, nt = 64, 1
+    L, _, vt = problem("smooth", n, n, nt=nt, beta=1e-2, reg=1)
+    v = 7.0 * np.stack([np.ones((n, n)), 0.5 * np.ones((n, n))]) + L.grid.X[0] * 0
+    v[0] += 0.3 * np.sin(L.grid.X[1])
+    ctx = _ctx(slnk, L, "fp64")
+    ctx.set_images(_t(L.mR, "fp64"), _t(L.mT, "fp64"))
+    lin = O.linearize(L, v)
+    g = torch.empty((2, n, n), dtype=torch.float64, device="cuda")
+    ctx.gradient(_t(v, "fp64"), g)
+    assert rel(_np(g), O.gradient(lin)) < 1e-11
+    h = torch.empty_like(g)
+    ctx.hessian_matvec(_t(vt, "fp64"), h)
+    assert rel(_np(h), O.hessian_matvec(lin, vt)) < 1e-11
+    ctx.close()
+
+
+def test_errors_are_reported(slnk):
+    n = 32
+    L, vgen, vt = problem("smooth", n, n, nt=2, beta=1e-2, reg=1)
+    with pytest.raises(slnk.SlnkError) as e:
+        slnk.Context(30, 34, 2, prec="fp64", pc="reg")       # 17 is not a 2-3-5 number
+    assert e.value.status == 1
+    with pytest.raises(slnk.SlnkError):
+        slnk.Context(32, 32, 0, prec="fp64", pc="reg")
+    ctx = _ctx(slnk, L, "fp64")
+    h = torch.empty((2, n, n), dtype=torch.float64, device="cuda")
+    with pytest.raises(slnk.SlnkError) as e:
+        ctx.hessian_matvec(_t(vt, "fp64"), h)       # no linearisation point yet
+    assert e.value.status == 1
+    bad = L.mR.copy()
+    bad[3, 5] = np.nan
+    with pytest.raises(slnk.SlnkError) as e:
+        ctx.set_images(_t(bad, "fp64"), _t(L.mT, "fp64"))
+    assert e.value.status == 4
+    with pytest.raises(ValueError):
+        ctx.gradient(_t(vgen, "mixed"), h)          # wrong dtype for an FP64 context
+    ctx.close()
+
+
+def test_newton_solve_fp64_matches_oracle(slnk):
+    """Smooth 64^2 problem, H1, beta 1e-2, P_REG, FP64: the GPU takes the oracle's Newton path."""
+    n, nt = 64, 4
+    L, vgen, _ = problem("smooth", n, n, nt=nt, beta=1e-2, reg=1)
+    v_ref, rep_ref = O.newton_solve(L, pc="reg", max_newton=10)
+    ctx = _ctx(slnk, L, "fp64")
+    ctx.set_images(_t(L.mR, "fp64"), _t(L.mT, "fp64"))
+    v = torch.zeros((2, n, n), dtype=torch.float64, device="cuda")
+    rep = ctx.newton_solve(v, max_newton=10)
+    assert rep["status"] == "SLNK_OK"
+    assert rep["newton_iters"] == rep_ref["newton_iters"]
+    assert rep["pcg_iters"] == rep_ref["pcg_iters"]
+    # the last entries of the history are gradient norms near the minimiser, where a 1e-15
+    # perturbation of the data already moves the oracle's own values by ~3e-9 (inexact PCG)
+    assert np.allclose(rep["grel"], rep_ref["grel"], rtol=1e-6, atol=0)
+    assert np.allclose(rep["J"], rep_ref["J"], rtol=1e-11, atol=0)
+    assert rel(_np(v), v_ref) < 1e-9
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_newton_solve_two_level(slnk, prec):
+    """Gaussian 96^2 problem, H2, beta 1e-3, P_2L: same final velocity as the oracle (1e-9 in
+    FP64, 1e-3 mixed), and the oracle's gradient at the GPU's result meets the stop rule."""
+    n, nt = 96, 4
+    L, vgen, _ = problem("gauss", n, n, nt=nt, beta=1e-3, reg=2)
+    L.mT, L.mR = same_inputs(prec, L.mT, L.mR)
+    v_ref, rep_ref = O.newton_solve(L, pc="2l", max_newton=10)
+    ctx = _ctx(slnk, L, prec, pc="2l")
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    v = torch.zeros((2, n, n), dtype=ctx.dtype, device="cuda")
+    rep = ctx.newton_solve(v, max_newton=10)
+    print(rep["grel"], rep_ref["grel"], rep["pcg"], flush=True)
+    assert rep["status"] == "SLNK_OK"
+    vv = _np(v)
+    assert rel(vv, v_ref) < (1e-9 if prec == "fp64" else 1e-3)
+    g_at = O.gradient(O.linearize(L, vv))
+    assert np.abs(g_at).max() / rep_ref["g0_inf"] <= 1.02e-2
+    ctx.close()
