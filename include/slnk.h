@@ -168,6 +168,13 @@ slnk_status slnk_get_cheb_bounds(const slnk_ctx* ctx, double* emin, double* emax
  * gradient [n1][n2]. */
 slnk_status slnk_get_field(slnk_ctx* ctx, int which, void* out);
 
+/* Profiling support: launch one kernel of the hot path 'reps' times back to back on the
+ * context's stream between two HIP events and return the average duration per launch in
+ * *avg_ms.  which = 0: state SL step, 1: adjoint SL step, 2: incremental state SL step,
+ * 3: incremental adjoint SL step (all at the current linearisation, fused LDS variant when the
+ * halo allows), 4: Heun trace of both characteristics.  EINVAL before any slnk_gradient. */
+slnk_status slnk_time_kernel(slnk_ctx* ctx, int which, int reps, double* avg_ms);
+
 /* Globalised inexact GN--Krylov solve from the velocity in v_inout (device [2][n1][n2]); the
  * result overwrites it.  opts NULL: defaults.  report may be NULL.  Returns SLNK_OK when a stop
  * criterion was met or the Newton limit was reached, SLNK_ELINESEARCH when backtracking failed

@@ -50,7 +50,7 @@ class SolveReport(ctypes.Structure):
 EXPORTS = ["slnk_default_params", "slnk_default_opts", "slnk_create", "slnk_destroy", "slnk_last_error",
            "slnk_workspace_bytes", "slnk_set_images", "slnk_transport_state", "slnk_objective", "slnk_gradient",
            "slnk_hessian_matvec", "slnk_split_matvec", "slnk_precond_apply", "slnk_get_cheb_bounds",
-           "slnk_get_field", "slnk_newton_solve"]
+           "slnk_get_field", "slnk_time_kernel", "slnk_newton_solve"]
 
 
 def library_path() -> str:
@@ -83,6 +83,7 @@ def load_library():
         "slnk_precond_apply": (ctypes.c_int, [V, V, V]),
         "slnk_get_cheb_bounds": (ctypes.c_int, [V, P(ctypes.c_double), P(ctypes.c_double)]),
         "slnk_get_field": (ctypes.c_int, [V, ctypes.c_int, V]),
+        "slnk_time_kernel": (ctypes.c_int, [V, ctypes.c_int, ctypes.c_int, P(ctypes.c_double)]),
         "slnk_newton_solve": (ctypes.c_int, [V, V, P(SolveOpts), P(SolveReport)]),
     }
     for name, (res, args) in sig.items():
@@ -194,6 +195,12 @@ class Context:
     def get_field(self, which, out):
         ncomp = 2 if which in (1, 2) else 1
         self._check(self._lib.slnk_get_field(self._ctx, int(which), self._ptr(out, ncomp)))
+
+    def time_kernel(self, which, reps) -> float:
+        """Average duration (ms) of one launch of a hot-path kernel, timed with HIP events."""
+        ms = ctypes.c_double()
+        self._check(self._lib.slnk_time_kernel(self._ctx, int(which), int(reps), ctypes.byref(ms)))
+        return ms.value
 
     def newton_solve(self, v, opts: SolveOpts | None = None, **kw) -> dict:
         if opts is None:

@@ -591,6 +591,69 @@ struct Context {
     return maxit;
   }
 
+  // ---- kernel timing ----------------------------------------------------------------------
+  double time_kernel(int which, int reps) {
+    auto& lv = fine;
+    auto& L = lv.L();
+    ensure_gm(lv);
+    const size_t F = lv.F;
+    const double ht = 1.0 / lv.nt;
+    // sources with sane values: the state, a copy of it, and a zeroed accumulator
+    HIPCHK(hipMemcpyAsync(lv.q, L.m, F * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    HIPCHK(hipMemcpyAsync(lv.q + F, L.m, F * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    HIPCHK(fill<T>(stream, 2 * F, 0.0, lv.acc));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto one = [&](int r) {
+      StepArgs<T> a;
+      a.n1 = lv.n1;
+      a.n2 = lv.n2;
+      a.halo = L.halo;
+      a.src = lv.q + (r % 2) * F;
+      a.dst = lv.q + ((r + 1) % 2) * F;
+      a.ht = ht;
+      a.coef = lv.coef;
+      a.gamma = L.gamma;
+      a.gm_new = L.gm;
+      a.w_new = 1e-3;
+      a.acc = lv.acc;
+      a.vt = L.v;
+      int nb = 0;
+      switch (which) {
+        case 0:
+          a.d1 = L.df, a.d2 = L.df + F;
+          HIPCHK(sl_step<T>(stream, StepKind::State, a, &nb));
+          break;
+        case 1:
+          a.d1 = L.da, a.d2 = L.da + F;
+          HIPCHK(sl_step<T>(stream, StepKind::Adjoint, a, &nb));
+          break;
+        case 2:
+          a.d1 = L.df, a.d2 = L.df + F;
+          HIPCHK(sl_step<T>(stream, StepKind::IncState, a, &nb));
+          break;
+        case 3:
+          a.d1 = L.da, a.d2 = L.da + F;
+          HIPCHK(sl_step<T>(stream, StepKind::IncAdjoint, a, &nb));
+          break;
+        default:
+          HIPCHK(sl_trace<T>(stream, lv.n1, lv.n2, ht, L.v, lv.cv, lv.divv, lv.cdiv, L.bAv, lv.w, lv.bt, lv.coef,
+                             nullptr, &nb));
+      }
+    };
+    one(0);  // first launch outside the timed region (LDS attribute, constant upload)
+    HIPCHK(hipEventRecord(e0, stream));
+    for (int r = 0; r < reps; ++r) one(r);
+    HIPCHK(hipEventRecord(e1, stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return double(ms) / reps;
+  }
+
   // ---- Newton -------------------------------------------------------------------------------
   slnk_status newton(T* v, const slnk_solve_opts& o, slnk_solve_report* rep) {
     const double t_start = now_ms();
@@ -928,6 +991,14 @@ slnk_status slnk_get_field(slnk_ctx* ctx, int which, void* out) {
     }
     HIPCHK(hipMemcpyAsync(out, src, cnt * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
     HIPCHK(hipStreamSynchronize(C.stream));
+  });
+}
+
+slnk_status slnk_time_kernel(slnk_ctx* ctx, int which, int reps, double* avg_ms) {
+  if (!avg_ms || reps < 1 || which < 0 || which > 4) return SLNK_EINVAL;
+  return dispatch(ctx, [&](auto& C) {
+    if (!C.has_grad) throw slnk::Fail{SLNK_EINVAL, "no linearisation point: call slnk_gradient first"};
+    *avg_ms = C.time_kernel(which, reps);
   });
 }
 
