@@ -173,24 +173,35 @@ struct Context {
   double* dres = nullptr;     // device results (32 doubles)
   double* hres = nullptr;     // pinned host copy
   int partial_cap = 0;
+  // FP64 Newton iterate of the fine level and its regularisation term: beta A amplifies the
+  // rounding of v by up to beta max|k|^(2 reg), so v and beta A v are kept in FP64 while the
+  // transport reads an FP32 copy (mixed precision; plain copies in the FP64 context)
+  SpecGrid<double> sg64;
+  void* tw64_row = nullptr;
+  void* tw64_col = nullptr;
+  double* v64[2] = {};
+  double* bAv64[2] = {};
+  cplx<double>* S64a = nullptr;
+  cplx<double>* S64b = nullptr;
   // counters for the current solve
   int n_matvec = 0, n_coarse = 0;
   double t_prec = 0;
 
   // ---- setup ------------------------------------------------------------------------------
+  template <typename U>
   void plan(FFTPlanDev& pl, int n, void*& tw) {
     std::vector<int> r = factorise(n);
     if (int(r.size()) > kFFTMaxStages) throw Fail{SLNK_EINVAL, "FFT length has too many factors"};
     pl.n = n;
     pl.nstages = int(r.size());
     for (size_t i = 0; i < r.size(); ++i) pl.radix[i] = r[i];
-    std::vector<cplx<T>> h(n);
+    std::vector<cplx<U>> h(n);
     for (int q = 0; q < n; ++q) {
       const double a = 2.0 * kPi * double(q) / double(n);
-      h[q] = {T(std::cos(a)), T(-std::sin(a))};
+      h[q] = {U(std::cos(a)), U(-std::sin(a))};
     }
-    tw = arena.take<cplx<T>>(n);
-    HIPCHK(hipMemcpy(tw, h.data(), n * sizeof(cplx<T>), hipMemcpyHostToDevice));
+    tw = arena.take<cplx<U>>(n);
+    HIPCHK(hipMemcpy(tw, h.data(), n * sizeof(cplx<U>), hipMemcpyHostToDevice));
     pl.tw = tw;
   }
 
@@ -213,8 +224,8 @@ struct Context {
     lv.cell = lv.h1 * lv.h2;
     lv.sg.n1 = n1;
     lv.sg.n2 = n2;
-    plan(lv.sg.row, n2, lv.tw_row);
-    plan(lv.sg.col, n1, lv.tw_col);
+    plan<T>(lv.sg.row, n2, lv.tw_row);
+    plan<T>(lv.sg.col, n1, lv.tw_col);
     const size_t F = lv.F;
     lv.mT = arena.take<T>(F);
     lv.mR = arena.take<T>(F);
@@ -261,8 +272,10 @@ struct Context {
     size_t bytes = level_bytes(p.n1, p.n2, p.nt) + (two_level ? level_bytes(p.n1 / 2, p.n2 / 2, p.nt) : 0);
     const size_t F = size_t(p.n1) * p.n2;
     const int tiles = ((p.n1 + 15) / 16) * ((p.n2 + 15) / 16);  // blocks of the 16x16 transport kernels
-    partial_cap = std::max(reduce_blocks(2 * F), tiles) * 4 + 64;
+    partial_cap = 2 * (std::max(reduce_blocks(2 * F), tiles) * 4 + 64);  // two independent halves
     bytes += partial_cap * sizeof(double) + 64 * sizeof(double) + 4096;
+    bytes += 4 * 2 * F * sizeof(double) + 2 * 2 * size_t(p.n1) * (p.n2 / 2 + 1) * sizeof(cplx<double>) +
+             (p.n1 + p.n2) * sizeof(cplx<double>) + 8 * 256;
     void* base = nullptr;
     if (hipMalloc(&base, bytes) != hipSuccess) throw Fail{SLNK_ENOMEM, "hipMalloc of the workspace failed"};
     arena.base = static_cast<char*>(base);
@@ -272,6 +285,16 @@ struct Context {
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hres), 64 * sizeof(double), hipHostMallocDefault));
     alloc_level(fine, p.n1, p.n2, p.nt);
     if (two_level) alloc_level(coarse, p.n1 / 2, p.n2 / 2, p.nt);
+    sg64.n1 = p.n1;
+    sg64.n2 = p.n2;
+    plan<double>(sg64.row, p.n2, tw64_row);
+    plan<double>(sg64.col, p.n1, tw64_col);
+    for (int sl = 0; sl < 2; ++sl) {
+      v64[sl] = arena.take<double>(2 * F);
+      bAv64[sl] = arena.take<double>(2 * F);
+    }
+    S64a = arena.take<cplx<double>>(2 * sg64.spec());
+    S64b = arena.take<cplx<double>>(2 * sg64.spec());
   }
 
   void destroy() {
@@ -291,18 +314,34 @@ struct Context {
   SymbolParams sym(Symbol k) const { return SymbolParams{k, prm.reg, prm.beta}; }
 
   // ---- linearisation: trace, state, objective ---------------------------------------------
-  // v (device, 2F of T) becomes lin[slot].v; J is computed; grad m is not (see ensure_gm).
-  void linearize(Level<T>& lv, int slot, const T* v, bool need_J = true) {
+  // The velocity of lin[slot] comes from v (device, 2F of T) or, on the fine level, from the
+  // FP64 iterate v64src.  Traces both characteristics, solves the state equation and, with
+  // need_J, evaluates J (fine level: beta A v in FP64); grad m is left to ensure_gm.
+  void linearize(Level<T>& lv, int slot, const T* v, bool need_J = true, const double* v64src = nullptr) {
     auto& L = lv.lin[slot];
     const size_t F = lv.F;
-    if (v != L.v) HIPCHK(hipMemcpyAsync(L.v, v, 2 * F * sizeof(T), hipMemcpyDeviceToDevice, stream));
-    HIPCHK(spec_trace_prep<T>(stream, lv.sg, prm.reg, prm.beta, L.v, lv.cv, lv.divv, lv.cdiv, L.bAv, lv.S1, lv.S2));
+    const bool on_fine = &lv == &fine;
+    if (on_fine && v64src) {
+      if (v64src != v64[slot])
+        HIPCHK(hipMemcpyAsync(v64[slot], v64src, 2 * F * sizeof(double), hipMemcpyDeviceToDevice, stream));
+      HIPCHK(cast_copy<T>(stream, 2 * F, v64[slot], L.v));
+    } else {
+      if (v != L.v) HIPCHK(hipMemcpyAsync(L.v, v, 2 * F * sizeof(T), hipMemcpyDeviceToDevice, stream));
+      if (on_fine) HIPCHK(cast_back<T>(stream, 2 * F, L.v, v64[slot]));
+    }
+    HIPCHK(spec_trace_prep<T>(stream, lv.sg, L.v, lv.cv, lv.divv, lv.cdiv, lv.S1, lv.S2));
     int nb = 0;
     const double ht = 1.0 / lv.nt;
-    HIPCHK(sl_trace<T>(stream, lv.n1, lv.n2, ht, L.v, lv.cv, lv.divv, lv.cdiv, L.bAv, L.df, L.da, L.gamma, partial, &nb));
+    HIPCHK(sl_trace<T>(stream, lv.n1, lv.n2, ht, L.v, lv.cv, lv.divv, lv.cdiv, L.df, L.da, L.gamma, partial, &nb));
     HIPCHK(finish(stream, nb, 2, 2, 2u, partial, dres));
-    const double* r = fetch(2);
-    const double vAv = r[0], maxd = r[1];
+    const bool reg_term = need_J && on_fine;
+    if (reg_term) {
+      HIPCHK(spec_scale<double>(stream, sg64, sym(Symbol::Reg), 2, v64[slot], bAv64[slot], nullptr, S64a, S64b));
+      HIPCHK(dot<double>(stream, 2 * F, v64[slot], bAv64[slot], partial + partial_cap / 2, dres + 2));
+      HIPCHK(cast_copy<T>(stream, 2 * F, bAv64[slot], L.bAv));
+    }
+    const double* r = fetch(3);
+    const double maxd = r[1], vAv = reg_term ? r[2] : 0.0;
     if (!std::isfinite(maxd) || !std::isfinite(vAv)) throw Fail{SLNK_ENAN, "non-finite velocity or displacement"};
     L.halo = int(std::ceil(maxd));
     L.Jreg = 0.5 * lv.cell * vAv;
@@ -638,8 +677,8 @@ struct Context {
           HIPCHK(sl_step<T>(stream, StepKind::IncAdjoint, a, &nb));
           break;
         default:
-          HIPCHK(sl_trace<T>(stream, lv.n1, lv.n2, ht, L.v, lv.cv, lv.divv, lv.cdiv, L.bAv, lv.w, lv.bt, lv.coef,
-                             nullptr, &nb));
+          HIPCHK(sl_trace<T>(stream, lv.n1, lv.n2, ht, L.v, lv.cv, lv.divv, lv.cdiv, lv.w, lv.bt, lv.coef, nullptr,
+                             &nb));
       }
     };
     one(0);  // first launch outside the timed region (LDS attribute, constant upload)
@@ -722,9 +761,9 @@ struct Context {
       double alpha = 1.0;
       bool ok = false;
       for (int hv = 0; hv <= o.max_halvings; ++hv) {
-        // trial velocity v + alpha vt in the other slot
-        HIPCHK(xpay<T>(stream, n, fine.L().v, alpha, vt, fine.lin[trial].v));
-        linearize(fine, trial, fine.lin[trial].v);
+        // trial velocity v + alpha vt (FP64 iterate) in the other slot
+        HIPCHK(xpay_mixed<T>(stream, n, v64[fine.cur], alpha, vt, v64[trial]));
+        linearize(fine, trial, nullptr, true, v64[trial]);
         ++R.line_search_evals;
         if (fine.lin[trial].J <= J0 + o.armijo_c1 * alpha * slope) {
           ok = true;
@@ -743,7 +782,7 @@ struct Context {
       t_grad += now_ms() - t0;
     }
     R.newton_iters = k;
-    HIPCHK(hipMemcpyAsync(v, fine.L().v, n * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    HIPCHK(cast_copy<T>(stream, n, v64[fine.cur], v));
     HIPCHK(hipStreamSynchronize(stream));
     has_grad = true;
     R.status = status;

@@ -106,6 +106,13 @@ __global__ void k_q0(size_t F, const T* __restrict__ w, const T* __restrict__ gm
   }
 }
 
+template <typename T>
+__global__ void k_xpay_mixed(size_t n, const double* __restrict__ x, double a, const T* __restrict__ y,
+                             double* __restrict__ z) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    z[i] = x[i] + a * double(y[i]);
+}
+
 template <typename TI, typename TO>
 __global__ void k_cast(size_t n, const TI* __restrict__ x, TO* __restrict__ y) {
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
@@ -197,6 +204,12 @@ hipError_t cast_back(hipStream_t s, size_t n, const T* x, double* y) {
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t xpay_mixed(hipStream_t s, size_t n, const double* x, double a, const T* y, double* z) {
+  hipLaunchKernelGGL(k_xpay_mixed<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, a, y, z);
+  return hipGetLastError();
+}
+
 #define INST(T)                                                                                    \
   template hipError_t dot<T>(hipStream_t, size_t, const T*, const T*, double*, double*);          \
   template hipError_t dot3<T>(hipStream_t, size_t, const T*, const T*, double*, double*);         \
@@ -206,7 +219,8 @@ hipError_t cast_back(hipStream_t s, size_t n, const T* x, double* y) {
   template hipError_t fill<T>(hipStream_t, size_t, double, T*);                                   \
   template hipError_t q_at_zero<T>(hipStream_t, size_t, const T*, const T*, double, T*);          \
   template hipError_t cast_copy<T>(hipStream_t, size_t, const double*, T*);                       \
-  template hipError_t cast_back<T>(hipStream_t, size_t, const T*, double*);
+  template hipError_t cast_back<T>(hipStream_t, size_t, const T*, double*);                       \
+  template hipError_t xpay_mixed<T>(hipStream_t, size_t, const double*, double, const T*, double*);
 INST(float)
 INST(double)
 #undef INST

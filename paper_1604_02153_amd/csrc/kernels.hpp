@@ -56,11 +56,11 @@ hipError_t spec_scale(hipStream_t s, const SpecGrid<T>& g, SymbolParams sym, int
 template <typename T>
 hipError_t spec_grad(hipStream_t s, const SpecGrid<T>& g, int batch, const T* m, T* gm, cplx<T>* S1, cplx<T>* S2);
 
-// From v (two fields): spline coefficients cv (two fields), div v, spline coefficients of div v,
-// and beta A v (two fields).  S1 >= 2 spec(), S2 >= 6 spec().
+// From v (two fields): spline coefficients cv (two fields), div v and the spline coefficients of
+// div v.  S1 >= 2 spec(), S2 >= 4 spec().
 template <typename T>
-hipError_t spec_trace_prep(hipStream_t s, const SpecGrid<T>& g, int reg, double beta, const T* v, T* cv, T* divv,
-                           T* cdiv, T* bAv, cplx<T>* S1, cplx<T>* S2);
+hipError_t spec_trace_prep(hipStream_t s, const SpecGrid<T>& g, const T* v, T* cv, T* divv, T* cdiv, cplx<T>* S1,
+                           cplx<T>* S2);
 
 // Spectral restriction of nf fields to the grid gc (n/2): the modes |k_i| < n_i/4 survive.
 // If keep_fine != nullptr the fine spectrum (after both forward passes) is also stored there
@@ -126,12 +126,11 @@ template <typename T>
 hipError_t sl_step(hipStream_t s, StepKind kind, const StepArgs<T>& a, int* nblocks_out);
 
 // Heun trace of both characteristics at once.
-// in: v (2 fields), cv (2 fields, spline coefficients of v), divv, cdiv (coefficients of div v),
-//     bAv (2 fields) for the regularisation energy.
-// out: df (2 fields), da (2 fields), gamma; partial[block] = {sum v . bAv, max |d|}.
+// in: v (2 fields), cv (2 fields, spline coefficients of v), divv, cdiv (coefficients of div v).
+// out: df (2 fields), da (2 fields), gamma; partial[2 block + 1] = max |d| over the block.
 template <typename T>
 hipError_t sl_trace(hipStream_t s, int n1, int n2, double ht, const T* v, const T* cv, const T* divv,
-                    const T* cdiv, const T* bAv, T* df, T* da, T* gamma, double* partial, int* nblocks_out);
+                    const T* cdiv, T* df, T* da, T* gamma, double* partial, int* nblocks_out);
 
 // ---- reductions and vector updates -------------------------------------------------------
 // Two-stage deterministic FP64 reductions: per-block partials (reduce_blocks(n) blocks, 4 slots
@@ -167,5 +166,8 @@ template <typename T>
 hipError_t cast_copy(hipStream_t s, size_t n, const double* x, T* y);
 template <typename T>
 hipError_t cast_back(hipStream_t s, size_t n, const T* x, double* y);
+// z = x + a y with x, z in FP64 and y in T (the FP64 Newton iterate plus a step in T)
+template <typename T>
+hipError_t xpay_mixed(hipStream_t s, size_t n, const double* x, double a, const T* y, double* z);
 
 }  // namespace slnk

@@ -378,22 +378,19 @@ struct OpGrad {
 
 template <typename T>
 struct OpTracePrep {
-  static constexpr int NIN = 2, NOUT = 6;  // cv1, cv2, div v, c_div, beta A v1, beta A v2
-  int n1, n2, reg;
-  double beta, inv_n;
+  static constexpr int NIN = 2, NOUT = 4;  // cv1, cv2, div v, c_div
+  int n1, n2;
+  double inv_n;
   __device__ void operator()(int k1, int k2, int, int, const cplx<T>* in, cplx<T>* out) const {
     const int k2s = (2 * k2 == n2) ? -k2 : k2;
     const T s = T(inv_n);
     const T ib = s / spline_symbol<T>(k1, n1, k2s, n2);
-    const T ba = T(beta) * reg_a<T>(k1, k2s, reg) * s;
     const T o1 = odd_k<T>(k1, n1), o2 = (2 * k2 == n2) ? T(0) : T(k2);
     const cplx<T> d = cmul_i(cadd(cscale(in[0], o1), cscale(in[1], o2)));
     out[0] = cscale(in[0], ib);
     out[1] = cscale(in[1], ib);
     out[2] = cscale(d, s);
     out[3] = cscale(d, ib);
-    out[4] = cscale(in[0], ba);
-    out[5] = cscale(in[1], ba);
   }
 };
 
@@ -565,25 +562,23 @@ hipError_t spec_grad(hipStream_t s, const SpecGrid<T>& g, int batch, const T* m,
 }
 
 template <typename T>
-hipError_t spec_trace_prep(hipStream_t s, const SpecGrid<T>& g, int reg, double beta, const T* v, T* cv, T* divv,
-                           T* cdiv, T* bAv, cplx<T>* S1, cplx<T>* S2) {
+hipError_t spec_trace_prep(hipStream_t s, const SpecGrid<T>& g, const T* v, T* cv, T* divv, T* cdiv, cplx<T>* S1,
+                           cplx<T>* S2) {
   const size_t F = g.field();
   RealFields<T> rin{};
   rin.count = 2;
   rin.p[0] = v;
   rin.p[1] = v + F;
   RET_IF(launch_row_fwd<T>(s, g, rin, 1, S1));
-  OpTracePrep<T> op{g.n1, g.n2, reg, beta, 1.0 / double(F)};
+  OpTracePrep<T> op{g.n1, g.n2, 1.0 / double(F)};
   RET_IF(launch_col<T>(s, g, S1, S2, op, 0, 1));
   OutFields<T> rout{};
-  rout.count = 6;
+  rout.count = 4;
   rout.p[0] = cv;
   rout.p[1] = cv + F;
   rout.p[2] = divv;
   rout.p[3] = cdiv;
-  rout.p[4] = bAv;
-  rout.p[5] = bAv + F;
-  return launch_row_inv<T>(s, g, S2, 6, rout, 1);
+  return launch_row_inv<T>(s, g, S2, 4, rout, 1);
 }
 
 template <typename T>
@@ -639,8 +634,8 @@ hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecG
   template hipError_t spec_scale<T>(hipStream_t, const SpecGrid<T>&, SymbolParams, int, const T*, T*, const T*, \
                                     cplx<T>*, cplx<T>*);                                                        \
   template hipError_t spec_grad<T>(hipStream_t, const SpecGrid<T>&, int, const T*, T*, cplx<T>*, cplx<T>*);     \
-  template hipError_t spec_trace_prep<T>(hipStream_t, const SpecGrid<T>&, int, double, const T*, T*, T*, T*, T*, \
-                                         cplx<T>*, cplx<T>*);                                                   \
+  template hipError_t spec_trace_prep<T>(hipStream_t, const SpecGrid<T>&, const T*, T*, T*, T*, cplx<T>*,      \
+                                         cplx<T>*);                                                             \
   template hipError_t spec_restrict<T>(hipStream_t, const SpecGrid<T>&, const SpecGrid<T>&, int, const T*, T*,  \
                                        cplx<T>*, cplx<T>*, cplx<T>*, cplx<T>*);                                 \
   template hipError_t spec_prolong_combine<T>(hipStream_t, const SpecGrid<T>&, const SpecGrid<T>&, int,         \

@@ -299,9 +299,8 @@ hipError_t lds_limit(size_t* out) {
 template <typename T>
 __global__ void __launch_bounds__(256) k_trace(int n1, int n2, T ht, const T* __restrict__ v,
                                                const T* __restrict__ cv, const T* __restrict__ divv,
-                                               const T* __restrict__ cdiv, const T* __restrict__ bAv,
-                                               T* __restrict__ df, T* __restrict__ da, T* __restrict__ gamma,
-                                               double* partial) {
+                                               const T* __restrict__ cdiv, T* __restrict__ df,
+                                               T* __restrict__ da, T* __restrict__ gamma, double* partial) {
   const int i1 = blockIdx.y * kTile + threadIdx.y, i2 = blockIdx.x * kTile + threadIdx.x;
   double red_s = 0.0, red_m = 0.0;
   if (i1 < n1 && i2 < n2) {
@@ -329,7 +328,6 @@ __global__ void __launch_bounds__(256) k_trace(int n1, int n2, T ht, const T* __
     const T dD = interp_global(cdiv, n1, n2, T(i1) + e1, T(i2) + e2);
     const T dx = divv[gi];
     gamma[gi] = T(1) + T(0.5) * ht * (dD + dx) + T(0.5) * ht * ht * dD * dx;
-    red_s = double(v[gi]) * double(bAv[gi]) + double(v[gi + F]) * double(bAv[gi + F]);
     red_m = fmax(fmax(fabs(double(f1)), fabs(double(f2))), fmax(fabs(double(e1)), fabs(double(e2))));
   }
   if (partial) block_sum_max(red_s, red_m, partial);
@@ -393,11 +391,11 @@ hipError_t sl_step(hipStream_t s, StepKind kind, const StepArgs<T>& a, int* nblo
 
 template <typename T>
 hipError_t sl_trace(hipStream_t s, int n1, int n2, double ht, const T* v, const T* cv, const T* divv, const T* cdiv,
-                    const T* bAv, T* df, T* da, T* gamma, double* partial, int* nblocks_out) {
+                    T* df, T* da, T* gamma, double* partial, int* nblocks_out) {
   dim3 grid((n2 + kTile - 1) / kTile, (n1 + kTile - 1) / kTile);
   dim3 block(kTile, kTile);
   if (nblocks_out) *nblocks_out = int(grid.x * grid.y);
-  hipLaunchKernelGGL(k_trace<T>, grid, block, 0, s, n1, n2, T(ht), v, cv, divv, cdiv, bAv, df, da, gamma, partial);
+  hipLaunchKernelGGL(k_trace<T>, grid, block, 0, s, n1, n2, T(ht), v, cv, divv, cdiv, df, da, gamma, partial);
   return hipGetLastError();
 }
 
@@ -406,8 +404,8 @@ template int sl_step_max_halo<double>();
 template hipError_t sl_step<float>(hipStream_t, StepKind, const StepArgs<float>&, int*);
 template hipError_t sl_step<double>(hipStream_t, StepKind, const StepArgs<double>&, int*);
 template hipError_t sl_trace<float>(hipStream_t, int, int, double, const float*, const float*, const float*,
-                                    const float*, const float*, float*, float*, float*, double*, int*);
+                                    const float*, float*, float*, float*, double*, int*);
 template hipError_t sl_trace<double>(hipStream_t, int, int, double, const double*, const double*, const double*,
-                                     const double*, const double*, double*, double*, double*, double*, int*);
+                                     const double*, double*, double*, double*, double*, int*);
 
 }  // namespace slnk

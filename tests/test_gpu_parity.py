@@ -80,7 +80,9 @@ def test_transport_gradient_matvec(slnk, case):
         g = torch.empty((2, n1, n2), dtype=ctx.dtype, device="cuda")
         J = ctx.gradient(_t(v, prec), g)
         assert abs(J - lin.J) / abs(lin.J) < tol["objective"]
-        _check_reg_op(L, prec, _np(g), g_ref, v, tol["gradient"])
+        # beta A v is evaluated in FP64 from the given velocity in both contexts: only the FP64
+        # rounding floor of the spectral symbol applies
+        _check_reg_op(L, "fp64", _np(g), g_ref, v, tol["gradient"])
         # internal fields of the linearisation: state at t = 1, adjoint at t = 0
         f = torch.empty((n1, n2), dtype=ctx.dtype, device="cuda")
         ctx.get_field(0, f)
