@@ -48,7 +48,35 @@ def parse():
     ap.add_argument("--matvecs", type=int, default=200, help="isolated matvecs timed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=12, help="oracle matvecs in the CPU sample")
+    ap.add_argument("--probe", action="store_true",
+                    help="counter probe: 20 incremental-adjoint SL steps of the 256^2 problem, then a plain "
+                         "64 MiB elementwise kernel (the reference of the traffic counters); no JSON line")
     return ap.parse_args()
+
+
+def probe():
+    """Launch sequence profiled by the FETCH_SIZE / WRITE_SIZE counter runs."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1604_02153_amd import Context
+    cfg = synth.config("gauss256")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=torch.float32)
+    ctx = Context(256, 256, 4, reg="h2", beta=1e-3, prec="mixed", pc="2l")
+    mT, vg = t(cfg["mT"]), t(cfg["v_gen"])
+    mR = torch.empty_like(mT)
+    ctx.transport_state(vg, mT, mR)
+    ctx.set_images(mR, mT)
+    g = torch.empty_like(vg)
+    ctx.gradient(vg, g)
+    print(f"incremental-adjoint step: {1e3 * ctx.time_kernel(3, 20):.2f} us per launch", flush=True)
+    x = torch.ones(16 * 1024 * 1024, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 2.0, out=y)  # reads and writes 64 MiB
+    torch.cuda.synchronize()
+    ctx.close()
 
 
 def measured_traffic():
@@ -87,6 +115,9 @@ def cpu_baseline(cfg, n_matvec):
 
 def main():
     args = parse()
+    if args.probe:
+        probe()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
               "described in DESIGN.md and not measured.", file=sys.stderr)

@@ -18,6 +18,12 @@
  *   - Element type: double when params.prec == SLNK_PREC_FP64, float when SLNK_PREC_MIXED (fields
  *     in FP32; every inner product, norm, objective and Chebyshev/Lanczos scalar in FP64).
  *     Scalar outputs (J, norms, report) are always double.
+ *   - Batch: a context holds B = params.batch independent problems of the same size (items).
+ *     Every field argument then holds the B items one after the other ([B][n1][n2] for a scalar
+ *     field, [B][2][n1][n2] for a vector field), every host scalar output is an array of B values
+ *     (item order), and every call acts on all items.  Items share no data; the result of an
+ *     item does not depend on the others (the iterations run in lock step with per-item scalars
+ *     and stopping tests).  B = 1 is the single-problem case.
  *   - Memory: every field pointer is a DEVICE pointer owned by the caller (e.g. a torch tensor's
  *     data pointer); the library never frees it.  The library owns its workspace, allocated in
  *     slnk_create and released in slnk_destroy.
@@ -65,6 +71,9 @@ typedef enum { SLNK_PC_REG = 1, SLNK_PC_2L = 2 } slnk_pc;
  *   lanczos_steps Lanczos steps for e_max at v = 0 (paper: about 30)
  *   emax_safety   e_max = emax_safety * largest Ritz value (>= 1)
  *   lanczos_seed  seed of the SplitMix64 start vector of the Lanczos iteration
+ *   use_graphs    1: replay the Hessian matvec and the preconditioner from captured HIP graphs
+ *                 (recorded once per context and buffer pair); 0: launch every kernel
+ *   batch         number of same-size problems B held by the context, 1 <= B <= 4096
  * The compressible case (projection K = identity) is the one implemented. */
 typedef struct {
   int n1, n2, nt;
@@ -76,6 +85,8 @@ typedef struct {
   int lanczos_steps;
   double emax_safety;
   unsigned long long lanczos_seed;
+  int use_graphs;
+  int batch;
 } slnk_params;
 
 /* Newton--Krylov options (sections 3.4.1, 3.5).  Stop when ||g||_inf / ||g_0||_inf <= gtol_rel or
@@ -94,7 +105,8 @@ typedef struct {
 
 #define SLNK_REPORT_MAX_ITERS 64
 
-/* Solve report.  grel[k], J[k], pcg[k] for k <= newton_iters (grel[0] = 1 for a cold start). */
+/* Solve report of one item.  grel[k], J[k], pcg[k] for k <= newton_iters (grel[0] = 1 for a cold
+ * start).  The times are those of the whole batched call (shared by its items). */
 typedef struct {
   int status;               /* slnk_status of the solve */
   int newton_iters;
@@ -137,11 +149,11 @@ slnk_status slnk_set_images(slnk_ctx* ctx, const void* m_R, const void* m_T);
  * slnk_set_images.  Does not change the linearisation point. */
 slnk_status slnk_transport_state(slnk_ctx* ctx, const void* v, const void* m0, void* m1);
 
-/* J[v] (eq. e:varopt:objective).  Makes v the linearisation point. */
+/* J[v] of every item (eq. e:varopt:objective) into J[0..B).  Makes v the linearisation point. */
 slnk_status slnk_objective(slnk_ctx* ctx, const void* v, double* J);
 
 /* Reduced gradient g = beta A v + int_0^1 lambda grad m dt (eq. e:control-elim) into g
- * [2][n1][n2]; J receives the objective (may be NULL).  Makes v the linearisation point of the
+ * [2][n1][n2]; J (B values, may be NULL) receives the objective.  Makes v the linearisation point of the
  * Hessian and, with P_2L, of the coarse problem. */
 slnk_status slnk_gradient(slnk_ctx* ctx, const void* v, void* g, double* J);
 
@@ -159,7 +171,7 @@ slnk_status slnk_split_matvec(slnk_ctx* ctx, const void* s, void* out);
  * acting on the split variable.  EINVAL for P_2L before any slnk_gradient. */
 slnk_status slnk_precond_apply(slnk_ctx* ctx, const void* r, void* z);
 
-/* Chebyshev bounds of P_2L (after slnk_set_images). */
+/* Chebyshev bounds of P_2L of every item (arrays of B; after slnk_set_images). */
 slnk_status slnk_get_cheb_bounds(const slnk_ctx* ctx, double* emin, double* emax);
 
 /* Copy an internal field of the current linearisation into 'out' (device, element type as
@@ -169,16 +181,20 @@ slnk_status slnk_get_cheb_bounds(const slnk_ctx* ctx, double* emin, double* emax
 slnk_status slnk_get_field(slnk_ctx* ctx, int which, void* out);
 
 /* Profiling support: launch one kernel of the hot path 'reps' times back to back on the
- * context's stream between two HIP events and return the average duration per launch in
- * *avg_ms.  which = 0: state SL step, 1: adjoint SL step, 2: incremental state SL step,
+ * context's stream between one pair of HIP events and return the elapsed time divided by reps in
+ * *avg_ms (each launch covers all items).  which = 0: state SL step, 1: adjoint SL step, 2: incremental state SL step,
  * 3: incremental adjoint SL step (all at the current linearisation, fused LDS variant when the
- * halo allows), 4: Heun trace of both characteristics.  EINVAL before any slnk_gradient. */
+ * halo allows), 4: Heun trace of both characteristics, 5: one spectral operator on a vector field
+ * (three launches: row, column and inverse row passes), 6: spectral gradients of the state at all
+ * nt + 1 time levels (three launches).  EINVAL before any slnk_gradient. */
 slnk_status slnk_time_kernel(slnk_ctx* ctx, int which, int reps, double* avg_ms);
 
-/* Globalised inexact GN--Krylov solve from the velocity in v_inout (device [2][n1][n2]); the
- * result overwrites it.  opts NULL: defaults.  report may be NULL.  Returns SLNK_OK when a stop
- * criterion was met or the Newton limit was reached, SLNK_ELINESEARCH when backtracking failed
- * (v_inout then holds the last accepted iterate). */
+/* Globalised inexact GN--Krylov solve from the velocity in v_inout (device [B][2][n1][n2]); the
+ * result overwrites it.  opts NULL: defaults.  report (array of B, may be NULL) receives one
+ * report per item.  Each item stops on its own criteria; the call returns when all have stopped.
+ * Returns SLNK_OK when every item met a stop criterion or the Newton limit, else the status of a
+ * failed item (SLNK_ELINESEARCH when backtracking failed: that item's velocity is then its last
+ * accepted iterate). */
 slnk_status slnk_newton_solve(slnk_ctx* ctx, void* v_inout, const slnk_solve_opts* opts,
                               slnk_solve_report* report);
 

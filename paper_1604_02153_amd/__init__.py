@@ -28,7 +28,8 @@ class Params(ctypes.Structure):
     _fields_ = [("n1", ctypes.c_int), ("n2", ctypes.c_int), ("nt", ctypes.c_int), ("reg", ctypes.c_int),
                 ("beta", ctypes.c_double), ("prec", ctypes.c_int), ("pc", ctypes.c_int),
                 ("cheb_iters", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
-                ("emax_safety", ctypes.c_double), ("lanczos_seed", ctypes.c_ulonglong)]
+                ("emax_safety", ctypes.c_double), ("lanczos_seed", ctypes.c_ulonglong), ("use_graphs", ctypes.c_int),
+                ("batch", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -109,10 +110,14 @@ def default_opts(**kw) -> SolveOpts:
 
 
 class Context:
-    """One registration problem on the current GPU (see include/slnk.h for every call)."""
+    """A batch of same-size registration problems on the current GPU (see include/slnk.h for every
+    call).  With batch == 1 fields have their plain shapes ([n1, n2], [2, n1, n2]) and scalar
+    results are numbers; with batch B > 1 every field carries a leading item axis of length B and
+    scalar results are lists of B values."""
 
     def __init__(self, n1, n2, nt, reg="h2", beta=1e-3, prec="mixed", pc="2l", cheb_iters=10,
-                 lanczos_steps=30, emax_safety=1.05, lanczos_seed=0x5EED, stream=None):
+                 lanczos_steps=30, emax_safety=1.05, lanczos_seed=0x5EED, use_graphs=True, stream=None,
+                 batch=1):
         import torch
         lib = load_library()
         p = Params()
@@ -124,6 +129,9 @@ class Context:
         p.pc = PC[pc] if isinstance(pc, str) else int(pc)
         p.cheb_iters, p.lanczos_steps = int(cheb_iters), int(lanczos_steps)
         p.emax_safety, p.lanczos_seed = float(emax_safety), int(lanczos_seed)
+        p.use_graphs = 1 if use_graphs else 0
+        p.batch = int(batch)
+        self.batch = p.batch
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -142,6 +150,8 @@ class Context:
 
     def _ptr(self, t, ncomp):
         shape = self.shape if ncomp == 1 else (ncomp,) + self.shape
+        if self.batch > 1 or (t.dim() == len(shape) + 1):
+            shape = (self.batch,) + shape
         if not t.is_cuda or t.dtype != self.dtype or tuple(t.shape) != shape or not t.is_contiguous():
             raise ValueError(f"expected a contiguous {self.dtype} CUDA tensor of shape {shape}, got "
                              f"{t.dtype} {tuple(t.shape)} on {t.device}")
@@ -168,15 +178,19 @@ class Context:
     def transport_state(self, v, m0, m1):
         self._check(self._lib.slnk_transport_state(self._ctx, self._ptr(v, 2), self._ptr(m0, 1), self._ptr(m1, 1)))
 
-    def objective(self, v) -> float:
-        J = ctypes.c_double()
-        self._check(self._lib.slnk_objective(self._ctx, self._ptr(v, 2), ctypes.byref(J)))
-        return J.value
+    def _scalars(self, arr):
+        vals = list(arr)
+        return vals[0] if self.batch == 1 else vals
 
-    def gradient(self, v, g) -> float:
-        J = ctypes.c_double()
-        self._check(self._lib.slnk_gradient(self._ctx, self._ptr(v, 2), self._ptr(g, 2), ctypes.byref(J)))
-        return J.value
+    def objective(self, v):
+        J = (ctypes.c_double * self.batch)()
+        self._check(self._lib.slnk_objective(self._ctx, self._ptr(v, 2), J))
+        return self._scalars(J)
+
+    def gradient(self, v, g):
+        J = (ctypes.c_double * self.batch)()
+        self._check(self._lib.slnk_gradient(self._ctx, self._ptr(v, 2), self._ptr(g, 2), J))
+        return self._scalars(J)
 
     def hessian_matvec(self, vt, out):
         self._check(self._lib.slnk_hessian_matvec(self._ctx, self._ptr(vt, 2), self._ptr(out, 2)))
@@ -188,30 +202,39 @@ class Context:
         self._check(self._lib.slnk_precond_apply(self._ctx, self._ptr(r, 2), self._ptr(z, 2)))
 
     def cheb_bounds(self):
-        a, b = ctypes.c_double(), ctypes.c_double()
-        self._check(self._lib.slnk_get_cheb_bounds(self._ctx, ctypes.byref(a), ctypes.byref(b)))
-        return a.value, b.value
+        a, b = (ctypes.c_double * self.batch)(), (ctypes.c_double * self.batch)()
+        self._check(self._lib.slnk_get_cheb_bounds(self._ctx, a, b))
+        if self.batch == 1:
+            return a[0], b[0]
+        return list(zip(a, b))
 
     def get_field(self, which, out):
         ncomp = 2 if which in (1, 2) else 1
         self._check(self._lib.slnk_get_field(self._ctx, int(which), self._ptr(out, ncomp)))
 
     def time_kernel(self, which, reps) -> float:
-        """Average duration (ms) of one launch of a hot-path kernel, timed with HIP events."""
+        """Average duration (ms) of one launch of a hot-path kernel: reps launches back to back
+        between two HIP events on the library's stream."""
         ms = ctypes.c_double()
         self._check(self._lib.slnk_time_kernel(self._ctx, int(which), int(reps), ctypes.byref(ms)))
         return ms.value
 
-    def newton_solve(self, v, opts: SolveOpts | None = None, **kw) -> dict:
+    def newton_solve(self, v, opts: SolveOpts | None = None, **kw):
+        """Newton--Krylov solve in place; one report dict (batch 1) or a list of B dicts."""
         if opts is None:
             opts = default_opts(**kw)
-        rep = SolveReport()
-        st = self._lib.slnk_newton_solve(self._ctx, self._ptr(v, 2), ctypes.byref(opts), ctypes.byref(rep))
+        reps = (SolveReport * self.batch)()
+        st = self._lib.slnk_newton_solve(self._ctx, self._ptr(v, 2), ctypes.byref(opts), reps)
         if st not in (0, 5):
             self._check(st)
+        out = [self._report(r) for r in reps]
+        return out[0] if self.batch == 1 else out
+
+    @staticmethod
+    def _report(rep) -> dict:
         k = rep.newton_iters
         return {
-            "status": STATUS.get(st, st), "newton_iters": k, "pcg_iters": rep.pcg_iters, "matvecs": rep.matvecs,
+            "status": STATUS.get(rep.status, rep.status), "newton_iters": k, "pcg_iters": rep.pcg_iters, "matvecs": rep.matvecs,
             "coarse_matvecs": rep.coarse_matvecs, "line_search_evals": rep.line_search_evals,
             "g0_inf": rep.g0_inf, "g0_two": rep.g0_two, "emin": rep.emin, "emax": rep.emax,
             "grel": list(rep.grel[: k + 1]), "J": list(rep.J[: k + 1]), "pcg": list(rep.pcg[:k]),

@@ -2,12 +2,19 @@
 // include/slnk.h.  Everything numerical runs in the gfx950 kernels of spectral.hip,
 // transport.hip and blas.hip; this file sequences them, owns the device workspace and keeps the
 // FP64 scalars of the Krylov, Chebyshev, Lanczos and Newton iterations.
+//
+// A context holds B same-size registration problems ("items").  Every kernel launch covers all
+// items (grid z = item); the iterations run in lock step with per-item scalars, and items that
+// have stopped are skipped through device-side masks.  B = 1 is the single-problem case.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -15,14 +22,15 @@
 #include "kernels.hpp"
 
 namespace slnk {
-namespace {
-
-constexpr double kPi = 3.14159265358979323846;
 
 struct Fail {
   slnk_status st;
   std::string msg;
 };
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
 
 #define HIPCHK(expr)                                                                                  \
   do {                                                                                                \
@@ -39,6 +47,7 @@ bool fft_size_ok(int n) {
 
 std::vector<int> factorise(int n) {
   std::vector<int> r;
+  while (n % 8 == 0) r.push_back(8), n /= 8;
   while (n % 4 == 0) r.push_back(4), n /= 4;
   while (n % 2 == 0) r.push_back(2), n /= 2;
   while (n % 3 == 0) r.push_back(3), n /= 3;
@@ -115,15 +124,22 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+bool any_of(const std::vector<int>& m) {
+  return std::any_of(m.begin(), m.end(), [](int a) { return a != 0; });
+}
+
 // --------------------------------------------------------------------------------------------
+// One grid level of B items.  Per item the buffers are consecutive with the sizes noted
+// (F = n1 n2 elements); item z of a buffer of size S per item starts at z S.
 template <typename T>
 struct Level {
-  int n1 = 0, n2 = 0, nt = 0;
+  int n1 = 0, n2 = 0, nt = 0, B = 1;
   size_t F = 0;
-  double h1 = 0, h2 = 0, cell = 0;
+  double cell = 0;
   SpecGrid<T> sg;
-  T* mT = nullptr;
-  T* mR = nullptr;
+  T* mT = nullptr;  // F
+  T* mR = nullptr;  // F
+  // slot 0: the current linearisation point; slot 1: the trial point of the line search
   struct Lin {
     T* v = nullptr;      // 2F
     T* df = nullptr;     // 2F  forward displacements (cells)
@@ -132,47 +148,58 @@ struct Level {
     T* m = nullptr;      // (nt+1) F
     T* gm = nullptr;     // 2 (nt+1) F
     T* bAv = nullptr;    // 2F
-    double J = 0, Jmis = 0, Jreg = 0;
-    int halo = 0;
+    std::vector<double> J, Jreg;
+    std::vector<int> halo;
     bool valid = false, has_gm = false;
   } lin[2];
-  int cur = 0;
+  int* halo_dev = nullptr;  // [2][B]: halo of each slot and item, read by the transport kernels
   // work buffers
   T* cv = nullptr;    // 2F
   T* divv = nullptr;  // F
   T* cdiv = nullptr;  // F
-  T* lam = nullptr;   // 2F (ping-pong)
+  T* lam = nullptr;   // 2F (two time levels)
   T* acc = nullptr;   // 2F
   T* g = nullptr;     // 2F
-  T* q = nullptr;     // 2F (ping-pong)
+  T* q = nullptr;     // 2F (two time levels)
   T* bt = nullptr;    // 2F
   T* w = nullptr;     // 2F
   T* coef = nullptr;  // F
-  T* vec[8] = {};     // 8 x 2F Krylov / Chebyshev / Lanczos vectors
-  T* gmT = nullptr;   // 2F gradient of m_T (Lanczos at v = 0)
+  T* vec[8] = {};     // 2F each: Krylov / Chebyshev / Lanczos vectors
+  T* gmT = nullptr;   // 2F: gradient of m_T (Lanczos at v = 0)
   cplx<T>* S1 = nullptr;
   cplx<T>* S2 = nullptr;
-  cplx<T>* Sk = nullptr;  // kept spectrum (2 spec) for the two-level combine
+  cplx<T>* Sk = nullptr;  // 2 spectra: kept fine spectrum of the two-level combine
   void* tw_row = nullptr;
   void* tw_col = nullptr;
-  Lin& L() { return lin[cur]; }
+  // largest halo of a slot over the items of 'mask' (empty: all items)
+  int max_halo(int slot, const std::vector<int>& mask) const {
+    int h = 0;
+    for (int z = 0; z < B; ++z)
+      if (mask.empty() || mask[z]) h = std::max(h, lin[slot].halo[z]);
+    return h;
+  }
 };
 
 template <typename T>
 struct Context {
   slnk_params prm{};
+  int B = 1;
   hipStream_t stream = nullptr;
-  std::string err;
   Arena arena;
   Level<T> fine, coarse;
   bool two_level = false;
   bool images_set = false;
   bool has_grad = false;
-  double emin = 0, emax = 0;
-  double* partial = nullptr;  // reduction partials
-  double* dres = nullptr;     // device results (32 doubles)
-  double* hres = nullptr;     // pinned host copy
-  int partial_cap = 0;
+  std::vector<double> emin, emax;
+  double* partial = nullptr;  // reduction partials (two independent halves)
+  size_t partial_half = 0;
+  double* dres = nullptr;     // device results [2][4B]
+  double* hres = nullptr;     // pinned host copy of dres
+  double* dsc = nullptr;      // device per-item scalars [16][B]
+  double* hsc = nullptr;      // pinned staging of dsc
+  double* cheb_tab = nullptr; // device [2][cheb_iters][B]: Chebyshev d-update coefficients
+  double* inv_theta = nullptr;  // device [B]: 1 / theta of each item's Chebyshev interval
+  int* masks = nullptr;       // device [4][B]: all ones, PCG, Newton, line search
   // FP64 Newton iterate of the fine level and its regularisation term: beta A amplifies the
   // rounding of v by up to beta max|k|^(2 reg), so v and beta A v are kept in FP64 while the
   // transport reads an FP32 copy (mixed precision; plain copies in the FP64 context)
@@ -183,9 +210,20 @@ struct Context {
   double* bAv64[2] = {};
   cplx<double>* S64a = nullptr;
   cplx<double>* S64b = nullptr;
-  // counters for the current solve
-  int n_matvec = 0, n_coarse = 0;
+  // captured HIP graphs of the matvec and of the preconditioner, keyed by (operation, input,
+  // output, mask); recorded on a private stream, replayed on the caller's stream
+  bool use_graphs = true;
+  bool capturing = false;
+  int halo_cap = 0;  // LDS footprint of graphed SL steps (device halo <= cap)
+  hipStream_t cap_stream = nullptr;
+  std::map<std::tuple<int, const void*, const void*, const void*>, hipGraphExec_t> graphs;
+  // counters of the current solve
+  std::vector<int> n_matvec, n_coarse;
   double t_prec = 0;
+
+  enum { kMaskAll = 0, kMaskPcg = 1, kMaskNewton = 2, kMaskLs = 3 };
+  int* mask(int k) const { return masks + k * B; }
+  double* sc(int k) const { return dsc + k * B; }
 
   // ---- setup ------------------------------------------------------------------------------
   template <typename U>
@@ -205,60 +243,67 @@ struct Context {
     pl.tw = tw;
   }
 
-  static size_t level_bytes(int n1, int n2, int nt) {
+  static size_t level_bytes(int n1, int n2, int nt, int B) {
     const size_t F = size_t(n1) * n2;
     const size_t spec = size_t(n1) * (n2 / 2 + 1);
     const size_t nspec = std::max<size_t>(6, 2 * (nt + 1));
-    size_t fields = 2 /*images*/ + 2 * (2 + 2 + 1 + (nt + 1) + 2 * (nt + 1) + 2) + 2 + 1 + 1 + 2 * 8 + 16 + 2 + 2;
-    return fields * F * sizeof(T) + (2 * nspec + 2) * spec * sizeof(cplx<T>) + (n1 + n2) * sizeof(cplx<T>) +
-           64 * 256;
+    // images; two slots of (v, df, da, gamma, m, gm, bAv); cv, divv, cdiv; lam, acc, g, q, bt, w;
+    // coef; vec[8]; gmT
+    const size_t fields = 2 + 2 * (2 + 2 + 2 + 1 + (nt + 1) + 2 * (nt + 1) + 2) + 2 + 1 + 1 + 2 * 6 + 1 + 2 * 8 + 2;
+    return B * (fields * F * sizeof(T) + (2 * nspec + 2) * spec * sizeof(cplx<T>)) + (n1 + n2) * sizeof(cplx<T>) +
+           96 * 256 + 2 * B * sizeof(int);
   }
 
   void alloc_level(Level<T>& lv, int n1, int n2, int nt) {
     lv.n1 = n1;
     lv.n2 = n2;
     lv.nt = nt;
+    lv.B = B;
     lv.F = size_t(n1) * n2;
-    lv.h1 = 2.0 * kPi / n1;
-    lv.h2 = 2.0 * kPi / n2;
-    lv.cell = lv.h1 * lv.h2;
+    lv.cell = (2.0 * kPi / n1) * (2.0 * kPi / n2);
     lv.sg.n1 = n1;
     lv.sg.n2 = n2;
     plan<T>(lv.sg.row, n2, lv.tw_row);
     plan<T>(lv.sg.col, n1, lv.tw_col);
     const size_t F = lv.F;
-    lv.mT = arena.take<T>(F);
-    lv.mR = arena.take<T>(F);
+    lv.mT = arena.take<T>(B * F);
+    lv.mR = arena.take<T>(B * F);
     for (auto& L : lv.lin) {
-      L.v = arena.take<T>(2 * F);
-      L.df = arena.take<T>(2 * F);
-      L.da = arena.take<T>(2 * F);
-      L.gamma = arena.take<T>(F);
-      L.m = arena.take<T>((nt + 1) * F);
-      L.gm = arena.take<T>(2 * (nt + 1) * F);
-      L.bAv = arena.take<T>(2 * F);
+      L.v = arena.take<T>(B * 2 * F);
+      L.df = arena.take<T>(B * 2 * F);
+      L.da = arena.take<T>(B * 2 * F);
+      L.gamma = arena.take<T>(B * F);
+      L.m = arena.take<T>(B * (nt + 1) * F);
+      L.gm = arena.take<T>(B * 2 * (nt + 1) * F);
+      L.bAv = arena.take<T>(B * 2 * F);
+      L.J.assign(B, 0.0);
+      L.Jreg.assign(B, 0.0);
+      L.halo.assign(B, 0);
     }
-    lv.cv = arena.take<T>(2 * F);
-    lv.divv = arena.take<T>(F);
-    lv.cdiv = arena.take<T>(F);
-    lv.lam = arena.take<T>(2 * F);
-    lv.acc = arena.take<T>(2 * F);
-    lv.g = arena.take<T>(2 * F);
-    lv.q = arena.take<T>(2 * F);
-    lv.bt = arena.take<T>(2 * F);
-    lv.w = arena.take<T>(2 * F);
-    lv.coef = arena.take<T>(F);
-    for (auto& p : lv.vec) p = arena.take<T>(2 * F);
-    lv.gmT = arena.take<T>(2 * F);
+    lv.halo_dev = arena.take<int>(2 * B);
+    lv.cv = arena.take<T>(B * 2 * F);
+    lv.divv = arena.take<T>(B * F);
+    lv.cdiv = arena.take<T>(B * F);
+    lv.lam = arena.take<T>(B * 2 * F);
+    lv.acc = arena.take<T>(B * 2 * F);
+    lv.g = arena.take<T>(B * 2 * F);
+    lv.q = arena.take<T>(B * 2 * F);
+    lv.bt = arena.take<T>(B * 2 * F);
+    lv.w = arena.take<T>(B * 2 * F);
+    lv.coef = arena.take<T>(B * F);
+    for (auto& p : lv.vec) p = arena.take<T>(B * 2 * F);
+    lv.gmT = arena.take<T>(B * 2 * F);
     const size_t nspec = std::max<size_t>(6, 2 * (nt + 1));
-    lv.S1 = arena.take<cplx<T>>(nspec * lv.sg.spec());
-    lv.S2 = arena.take<cplx<T>>(nspec * lv.sg.spec());
-    lv.Sk = arena.take<cplx<T>>(2 * lv.sg.spec());
+    lv.S1 = arena.take<cplx<T>>(B * nspec * lv.sg.spec());
+    lv.S2 = arena.take<cplx<T>>(B * nspec * lv.sg.spec());
+    lv.Sk = arena.take<cplx<T>>(B * 2 * lv.sg.spec());
   }
 
   void create(const slnk_params& p, hipStream_t s) {
     prm = p;
     stream = s;
+    B = p.batch;
+    if (B < 1 || B > 4096) throw Fail{SLNK_EINVAL, "batch must be in [1, 4096]"};
     if (!fft_size_ok(p.n1) || !fft_size_ok(p.n2)) throw Fail{SLNK_EINVAL, "grid sizes must be even products of 2, 3, 5 in [8, 2048]"};
     if (p.nt < 1 || p.nt > 512) throw Fail{SLNK_EINVAL, "nt must be in [1, 512]"};
     if (p.reg < 1 || p.reg > 3) throw Fail{SLNK_EINVAL, "reg must be 1, 2 or 3"};
@@ -267,22 +312,30 @@ struct Context {
     two_level = p.pc == SLNK_PC_2L;
     if (two_level) {
       if (!fft_size_ok(p.n1 / 2) || !fft_size_ok(p.n2 / 2)) throw Fail{SLNK_EINVAL, "coarse grid n/2 not supported"};
-      if (p.cheb_iters < 1 || p.lanczos_steps < 2 || !(p.emax_safety >= 1.0)) throw Fail{SLNK_EINVAL, "bad P_2L parameters"};
+      if (p.cheb_iters < 1 || p.cheb_iters > 64 || p.lanczos_steps < 2 || !(p.emax_safety >= 1.0))
+        throw Fail{SLNK_EINVAL, "bad P_2L parameters"};
     }
-    size_t bytes = level_bytes(p.n1, p.n2, p.nt) + (two_level ? level_bytes(p.n1 / 2, p.n2 / 2, p.nt) : 0);
     const size_t F = size_t(p.n1) * p.n2;
     const int tiles = ((p.n1 + 15) / 16) * ((p.n2 + 15) / 16);  // blocks of the 16x16 transport kernels
-    partial_cap = 2 * (std::max(reduce_blocks(2 * F), tiles) * 4 + 64);  // two independent halves
-    bytes += partial_cap * sizeof(double) + 64 * sizeof(double) + 4096;
-    bytes += 4 * 2 * F * sizeof(double) + 2 * 2 * size_t(p.n1) * (p.n2 / 2 + 1) * sizeof(cplx<double>) +
-             (p.n1 + p.n2) * sizeof(cplx<double>) + 8 * 256;
+    partial_half = size_t(B) * (std::max(reduce_blocks(2 * F), tiles) * 4 + 64);
+    size_t bytes = level_bytes(p.n1, p.n2, p.nt, B) + (two_level ? level_bytes(p.n1 / 2, p.n2 / 2, p.nt, B) : 0);
+    bytes += (2 * partial_half + 8 * B + 16 * B + 2 * 64 * B + B) * sizeof(double) + 4 * B * sizeof(int) + 8192;
+    bytes += B * (4 * 2 * F * sizeof(double) + 2 * 2 * size_t(p.n1) * (p.n2 / 2 + 1) * sizeof(cplx<double>)) +
+             (p.n1 + p.n2) * sizeof(cplx<double>) + 16 * 256;
     void* base = nullptr;
     if (hipMalloc(&base, bytes) != hipSuccess) throw Fail{SLNK_ENOMEM, "hipMalloc of the workspace failed"};
     arena.base = static_cast<char*>(base);
     arena.size = bytes;
-    partial = arena.take<double>(partial_cap);
-    dres = arena.take<double>(64);
-    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hres), 64 * sizeof(double), hipHostMallocDefault));
+    // every buffer starts finite: items skipped by a mask may still be read by unmasked updates
+    HIPCHK(hipMemset(base, 0, bytes));
+    partial = arena.take<double>(2 * partial_half);
+    dres = arena.take<double>(8 * B);
+    dsc = arena.take<double>(16 * B);
+    cheb_tab = arena.take<double>(2 * 64 * B);
+    inv_theta = arena.take<double>(B);
+    masks = arena.take<int>(4 * B);
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hres), 8 * B * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hsc), 16 * B * sizeof(double), hipHostMallocDefault));
     alloc_level(fine, p.n1, p.n2, p.nt);
     if (two_level) alloc_level(coarse, p.n1 / 2, p.n2 / 2, p.nt);
     sg64.n1 = p.n1;
@@ -290,398 +343,604 @@ struct Context {
     plan<double>(sg64.row, p.n2, tw64_row);
     plan<double>(sg64.col, p.n1, tw64_col);
     for (int sl = 0; sl < 2; ++sl) {
-      v64[sl] = arena.take<double>(2 * F);
-      bAv64[sl] = arena.take<double>(2 * F);
+      v64[sl] = arena.take<double>(B * 2 * F);
+      bAv64[sl] = arena.take<double>(B * 2 * F);
     }
-    S64a = arena.take<cplx<double>>(2 * sg64.spec());
-    S64b = arena.take<cplx<double>>(2 * sg64.spec());
+    S64a = arena.take<cplx<double>>(B * 2 * sg64.spec());
+    S64b = arena.take<cplx<double>>(B * 2 * sg64.spec());
+    use_graphs = p.use_graphs != 0;
+    halo_cap = std::min(8, sl_step_max_halo<T>());
+    if (halo_cap < 0) throw Fail{SLNK_EDEVICE, "cannot query the LDS size of the device"};
+    HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+    std::vector<int> ones(B, 1);
+    for (int k = 0; k < 4; ++k) put_mask(k, ones);
+    emin.assign(B, 0.0);
+    emax.assign(B, 0.0);
+    n_matvec.assign(B, 0);
+    n_coarse.assign(B, 0);
+    HIPCHK(hipStreamSynchronize(stream));
+  }
+
+  void clear_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
   }
 
   void destroy() {
+    clear_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    cap_stream = nullptr;
     if (hres) (void)hipHostFree(hres);
+    if (hsc) (void)hipHostFree(hsc);
     if (arena.base) (void)hipFree(arena.base);
-    hres = nullptr;
+    hres = hsc = nullptr;
     arena.base = nullptr;
   }
 
-  // read n doubles of dres to the host
-  const double* fetch(int n) {
-    HIPCHK(hipMemcpyAsync(hres, dres, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+  // read one half of dres (4B doubles; item z's results at 4z + c) to the host
+  const double* fetch(int half) {
+    HIPCHK(hipMemcpyAsync(hres + half * 4 * B, dres + half * 4 * B, 4 * B * sizeof(double), hipMemcpyDeviceToHost,
+                          stream));
     HIPCHK(hipStreamSynchronize(stream));
-    return hres;
+    return hres + half * 4 * B;
   }
+
+  // publish per-item scalars as row k of dsc.  The pinned row is reused only after a later
+  // synchronisation (every caller reads a reduction before writing the same row again).
+  void put_scalars(int k, const std::vector<double>& v) {
+    std::memcpy(hsc + k * B, v.data(), B * sizeof(double));
+    HIPCHK(hipMemcpyAsync(sc(k), hsc + k * B, B * sizeof(double), hipMemcpyHostToDevice, stream));
+  }
+
+  void put_mask(int k, const std::vector<int>& m) { HIPCHK(set_ints(stream, mask(k), m.data(), B)); }
 
   SymbolParams sym(Symbol k) const { return SymbolParams{k, prm.reg, prm.beta}; }
 
+  // SL step arguments shared by every step of a level: the LDS footprint is sized for the largest
+  // item halo of the slot (halo_cap while capturing a graph), and each item stages its own halo
+  // read from device memory
+  StepArgs<T> step_base(Level<T>& lv, int slot, const int* active, bool graphed_halo) {
+    StepArgs<T> a;
+    a.n1 = lv.n1;
+    a.n2 = lv.n2;
+    a.batch = B;
+    a.active = active;
+    a.halo = graphed_halo ? halo_cap : lv.max_halo(slot, {});
+    a.halo_dev = lv.halo_dev + slot * B;
+    a.coef = lv.coef;
+    a.st_coef = (long long)lv.F;
+    a.ht = 1.0 / lv.nt;
+    return a;
+  }
+
   // ---- linearisation: trace, state, objective ---------------------------------------------
-  // The velocity of lin[slot] comes from v (device, 2F of T) or, on the fine level, from the
+  // The velocity of lin[slot] comes from v (device, B x 2F of T) or, on the fine level, from the
   // FP64 iterate v64src.  Traces both characteristics, solves the state equation and, with
-  // need_J, evaluates J (fine level: beta A v in FP64); grad m is left to ensure_gm.
-  void linearize(Level<T>& lv, int slot, const T* v, bool need_J = true, const double* v64src = nullptr) {
+  // need_J, evaluates J (fine level: beta A v in FP64); grad m is left to ensure_gm.  Only the
+  // items of mk (device mask, host copy hmask; nullptr / empty: all) are touched.
+  void linearize(Level<T>& lv, int slot, const T* v, bool need_J, const double* v64src, const int* mk,
+                 const std::vector<int>& hmask) {
     auto& L = lv.lin[slot];
     const size_t F = lv.F;
     const bool on_fine = &lv == &fine;
     if (on_fine && v64src) {
-      if (v64src != v64[slot])
-        HIPCHK(hipMemcpyAsync(v64[slot], v64src, 2 * F * sizeof(double), hipMemcpyDeviceToDevice, stream));
-      HIPCHK(cast_copy<T>(stream, 2 * F, v64[slot], L.v));
+      if (v64src != v64[slot]) HIPCHK(masked_copy<double>(stream, B, 2 * F, v64src, 2 * F, v64[slot], 2 * F, mk));
+      HIPCHK(cast_copy<T>(stream, B * 2 * F, v64[slot], L.v));
     } else {
-      if (v != L.v) HIPCHK(hipMemcpyAsync(L.v, v, 2 * F * sizeof(T), hipMemcpyDeviceToDevice, stream));
-      if (on_fine) HIPCHK(cast_back<T>(stream, 2 * F, L.v, v64[slot]));
+      if (v != L.v) HIPCHK(masked_copy<T>(stream, B, 2 * F, v, 2 * F, L.v, 2 * F, mk));
+      if (on_fine) HIPCHK(cast_back<T>(stream, B * 2 * F, L.v, v64[slot]));
     }
-    HIPCHK(spec_trace_prep<T>(stream, lv.sg, L.v, lv.cv, lv.divv, lv.cdiv, lv.S1, lv.S2));
+    HIPCHK(spec_trace_prep<T>(stream, lv.sg, B, mk, L.v, lv.cv, lv.divv, lv.cdiv, lv.S1, lv.S2));
     int nb = 0;
     const double ht = 1.0 / lv.nt;
-    HIPCHK(sl_trace<T>(stream, lv.n1, lv.n2, ht, L.v, lv.cv, lv.divv, lv.cdiv, L.df, L.da, L.gamma, partial, &nb));
-    HIPCHK(finish(stream, nb, 2, 2, 2u, partial, dres));
+    HIPCHK(sl_trace<T>(stream, lv.n1, lv.n2, B, mk, ht, L.v, lv.cv, lv.divv, lv.cdiv, L.df, L.da, L.gamma, partial,
+                       &nb));
+    HIPCHK(finish(stream, B, nb, 2, 2LL * nb, 2, 2u, partial, dres));
     const bool reg_term = need_J && on_fine;
     if (reg_term) {
-      HIPCHK(spec_scale<double>(stream, sg64, sym(Symbol::Reg), 2, v64[slot], bAv64[slot], nullptr, S64a, S64b));
-      HIPCHK(dot<double>(stream, 2 * F, v64[slot], bAv64[slot], partial + partial_cap / 2, dres + 2));
-      HIPCHK(cast_copy<T>(stream, 2 * F, bAv64[slot], L.bAv));
+      HIPCHK(spec_scale<double>(stream, sg64, B, mk, sym(Symbol::Reg), 2, v64[slot], bAv64[slot], nullptr, S64a,
+                                S64b));
+      HIPCHK(dot<double>(stream, B, 2 * F, v64[slot], bAv64[slot], partial + partial_half, dres + 4 * B));
+      HIPCHK(cast_copy<T>(stream, B * 2 * F, bAv64[slot], L.bAv));
     }
-    const double* r = fetch(3);
-    const double maxd = r[1], vAv = reg_term ? r[2] : 0.0;
-    if (!std::isfinite(maxd) || !std::isfinite(vAv)) throw Fail{SLNK_ENAN, "non-finite velocity or displacement"};
-    L.halo = int(std::ceil(maxd));
-    L.Jreg = 0.5 * lv.cell * vAv;
+    const double* r = fetch(0);
+    std::vector<double> maxd(B), vAv(B, 0.0);
+    for (int z = 0; z < B; ++z) maxd[z] = r[4 * z + 1];
+    if (reg_term) {
+      const double* r2 = fetch(1);
+      for (int z = 0; z < B; ++z) vAv[z] = r2[4 * z];
+    }
+    for (int z = 0; z < B; ++z) {
+      if (!hmask.empty() && !hmask[z]) continue;
+      if (!std::isfinite(maxd[z]) || !std::isfinite(vAv[z])) throw Fail{SLNK_ENAN, "non-finite velocity or displacement"};
+      L.halo[z] = int(std::ceil(maxd[z]));
+      L.Jreg[z] = 0.5 * lv.cell * vAv[z];
+    }
+    HIPCHK(set_ints(stream, lv.halo_dev + slot * B, L.halo.data(), B));
     // state equation
-    HIPCHK(hipMemcpyAsync(L.m, lv.mT, F * sizeof(T), hipMemcpyDeviceToDevice, stream));
+    HIPCHK(masked_copy<T>(stream, B, F, lv.mT, (long long)F, L.m, (long long)((lv.nt + 1) * F), mk));
     for (int j = 1; j <= lv.nt; ++j) {
-      StepArgs<T> a;
-      a.n1 = lv.n1;
-      a.n2 = lv.n2;
-      a.halo = L.halo;
+      StepArgs<T> a = step_base(lv, slot, mk, false);
+      a.halo = lv.max_halo(slot, hmask);
       a.src = L.m + (j - 1) * F;
       a.dst = L.m + j * F;
+      a.st_src = a.st_dst = (long long)((lv.nt + 1) * F);
       a.d1 = L.df;
-      a.d2 = L.df + F;
+      a.st_d = (long long)(2 * F);
       a.aux0 = lv.mR;
-      a.ht = ht;
+      a.st_aux0 = (long long)F;
       a.last = (j == lv.nt) && need_J;
       a.partial = partial;
-      a.coef = lv.coef;
       HIPCHK(sl_step<T>(stream, StepKind::State, a, &nb));
     }
     if (need_J) {
-      HIPCHK(finish(stream, nb, 2, 1, 0u, partial, dres));
-      const double mis = fetch(1)[0];
-      if (!std::isfinite(mis)) throw Fail{SLNK_ENAN, "non-finite state"};
-      L.Jmis = 0.5 * lv.cell * mis;
-      L.J = L.Jmis + L.Jreg;
+      HIPCHK(finish(stream, B, nb, 2, 2LL * nb, 1, 0u, partial, dres));
+      const double* r3 = fetch(0);
+      for (int z = 0; z < B; ++z) {
+        if (!hmask.empty() && !hmask[z]) continue;
+        const double mis = r3[4 * z];
+        if (!std::isfinite(mis)) throw Fail{SLNK_ENAN, "non-finite state"};
+        L.J[z] = 0.5 * lv.cell * mis + L.Jreg[z];
+      }
     }
     L.valid = true;
     L.has_gm = false;
   }
 
   void ensure_gm(Level<T>& lv) {
-    auto& L = lv.L();
+    auto& L = lv.lin[0];
     if (L.has_gm) return;
-    HIPCHK(spec_grad<T>(stream, lv.sg, lv.nt + 1, L.m, L.gm, lv.S1, lv.S2));
+    HIPCHK(spec_grad<T>(stream, lv.sg, B * (lv.nt + 1), L.m, L.gm, lv.S1, lv.S2));
     L.has_gm = true;
   }
 
-  // adjoint solve + gradient; returns {sum g^2, max |g|} on the host
-  void gradient(Level<T>& lv, double* g2, double* ginf) {
-    auto& L = lv.L();
+  // adjoint solve + gradient at slot 0 for the items of mk / hmask; per item sum g^2 and max |g|
+  void gradient(Level<T>& lv, const int* mk, const std::vector<int>& hmask, std::vector<double>& g2,
+                std::vector<double>& ginf) {
+    auto& L = lv.lin[0];
     ensure_gm(lv);
     const size_t F = lv.F;
     const int nt = lv.nt;
-    const double ht = 1.0 / nt;
     int nb = 0;
     for (int j = nt; j >= 1; --j) {
-      StepArgs<T> a;
-      a.n1 = lv.n1;
-      a.n2 = lv.n2;
-      a.halo = L.halo;
+      StepArgs<T> a = step_base(lv, 0, mk, false);
       a.first = j == nt;
       a.last = j == 1;
       a.src = a.first ? nullptr : lv.lam + (j % 2) * F;
+      a.st_src = (long long)(2 * F);
       a.aux0 = lv.mR;
+      a.st_aux0 = (long long)F;
       a.aux1 = L.m + nt * F;
+      a.st_aux1 = (long long)((nt + 1) * F);
       a.dst = lv.lam + ((j - 1) % 2) * F;
+      a.st_dst = (long long)(2 * F);
       a.d1 = L.da;
-      a.d2 = L.da + F;
+      a.st_d = (long long)(2 * F);
       a.gamma = L.gamma;
+      a.st_gamma = (long long)F;
       a.gm_new = L.gm + 2 * (j - 1) * F;
       a.gm_old = L.gm + 2 * nt * F;
+      a.st_gm = (long long)(2 * (nt + 1) * F);
       a.w_new = trapezoid_weight(j - 1, nt);
       a.w_old = trapezoid_weight(nt, nt);
       a.acc = lv.acc;
+      a.st_acc = (long long)(2 * F);
       a.addf = L.bAv;
+      a.st_addf = (long long)(2 * F);
       a.out2 = lv.g;
-      a.ht = ht;
+      a.st_out2 = (long long)(2 * F);
       a.partial = partial;
-      a.coef = lv.coef;
       HIPCHK(sl_step<T>(stream, StepKind::Adjoint, a, &nb));
     }
-    HIPCHK(finish(stream, nb, 2, 2, 2u, partial, dres));
-    const double* r = fetch(2);
-    *g2 = r[0];
-    *ginf = r[1];
-    if (!std::isfinite(*g2)) throw Fail{SLNK_ENAN, "non-finite gradient"};
+    HIPCHK(finish(stream, B, nb, 2, 2LL * nb, 2, 2u, partial, dres));
+    const double* r = fetch(0);
+    g2.assign(B, 0.0);
+    ginf.assign(B, 0.0);
+    for (int z = 0; z < B; ++z) {
+      if (!hmask.empty() && !hmask[z]) continue;
+      g2[z] = r[4 * z];
+      ginf[z] = r[4 * z + 1];
+      if (!std::isfinite(g2[z])) throw Fail{SLNK_ENAN, "non-finite gradient"};
+    }
   }
 
-  // bt = Q[vt] (the transport part of the GN matvec) at the current linearisation of lv
-  void gn_transport(Level<T>& lv, const T* vt) {
-    auto& L = lv.L();
+  // bt = Q[vt] (the transport part of the GN matvec) at slot 0 of lv, items of mk
+  void gn_transport(Level<T>& lv, const T* vt, const int* mk) {
+    auto& L = lv.lin[0];
     ensure_gm(lv);
     const size_t F = lv.F;
     const int nt = lv.nt;
-    const double ht = 1.0 / nt;
     int nb = 0;
+    // while capturing, the LDS is sized for halo_cap so that the graph stays valid for every
+    // later linearisation whose halos fit under it
     for (int j = 1; j <= nt; ++j) {  // incremental state, forward
-      StepArgs<T> a;
-      a.n1 = lv.n1;
-      a.n2 = lv.n2;
-      a.halo = L.halo;
+      StepArgs<T> a = step_base(lv, 0, mk, capturing);
       a.first = j == 1;
       a.last = j == nt;
       a.src = a.first ? nullptr : lv.q + ((j - 1) % 2) * F;
       a.dst = lv.q + (j % 2) * F;
+      a.st_src = a.st_dst = (long long)(2 * F);
       a.d1 = L.df;
-      a.d2 = L.df + F;
+      a.st_d = (long long)(2 * F);
       a.vt = vt;
+      a.st_vt = (long long)(2 * F);
       a.gm_old = L.gm;
       a.gm_new = L.gm + 2 * j * F;
+      a.st_gm = (long long)(2 * (nt + 1) * F);
       a.w_new = trapezoid_weight(nt, nt);
       a.acc = lv.bt;
-      a.ht = ht;
-      a.coef = lv.coef;
+      a.st_acc = (long long)(2 * F);
       HIPCHK(sl_step<T>(stream, StepKind::IncState, a, &nb));
     }
     for (int j = nt; j >= 1; --j) {  // incremental adjoint, backward
-      StepArgs<T> a;
-      a.n1 = lv.n1;
-      a.n2 = lv.n2;
-      a.halo = L.halo;
+      StepArgs<T> a = step_base(lv, 0, mk, capturing);
       a.src = lv.q + (j % 2) * F;
       a.dst = j > 1 ? lv.q + ((j - 1) % 2) * F : nullptr;
+      a.st_src = a.st_dst = (long long)(2 * F);
       a.d1 = L.da;
-      a.d2 = L.da + F;
+      a.st_d = (long long)(2 * F);
       a.gamma = L.gamma;
+      a.st_gamma = (long long)F;
       a.gm_new = L.gm + 2 * (j - 1) * F;
+      a.st_gm = (long long)(2 * (nt + 1) * F);
       a.w_new = trapezoid_weight(j - 1, nt);
       a.acc = lv.bt;
-      a.ht = ht;
-      a.coef = lv.coef;
+      a.st_acc = (long long)(2 * F);
       HIPCHK(sl_step<T>(stream, StepKind::IncAdjoint, a, &nb));
     }
   }
 
   // out = beta A vt + Q vt
-  void hessian(Level<T>& lv, const T* vt, T* out) {
-    gn_transport(lv, vt);
-    HIPCHK(spec_scale<T>(stream, lv.sg, sym(Symbol::Reg), 2, vt, out, lv.bt, lv.S1, lv.S2));
+  void hessian(Level<T>& lv, const T* vt, T* out, const int* mk) {
+    gn_transport(lv, vt, mk);
+    HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, sym(Symbol::Reg), 2, vt, out, lv.bt, lv.S1, lv.S2));
   }
 
   // out = s + S Q S s
-  void split_matvec(Level<T>& lv, const T* s, T* out) {
-    HIPCHK(spec_scale<T>(stream, lv.sg, sym(Symbol::RegInvSqrt), 2, s, lv.w, nullptr, lv.S1, lv.S2));
-    gn_transport(lv, lv.w);
-    HIPCHK(spec_scale<T>(stream, lv.sg, sym(Symbol::RegInvSqrt), 2, lv.bt, out, s, lv.S1, lv.S2));
+  void split_matvec(Level<T>& lv, const T* s, T* out, const int* mk) {
+    HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, sym(Symbol::RegInvSqrt), 2, s, lv.w, nullptr, lv.S1, lv.S2));
+    gn_transport(lv, lv.w, mk);
+    HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, sym(Symbol::RegInvSqrt), 2, lv.bt, out, s, lv.S1, lv.S2));
   }
 
   // out = s + S Q(0) S s on the coarse level (closed form of the v = 0 operator)
   void split_matvec_zero(Level<T>& lv, const T* s, T* out) {
-    HIPCHK(spec_scale<T>(stream, lv.sg, sym(Symbol::RegInvSqrt), 2, s, lv.w, nullptr, lv.S1, lv.S2));
-    HIPCHK(q_at_zero<T>(stream, lv.F, lv.w, lv.gmT, 1.0, lv.bt));
-    HIPCHK(spec_scale<T>(stream, lv.sg, sym(Symbol::RegInvSqrt), 2, lv.bt, out, s, lv.S1, lv.S2));
+    HIPCHK(spec_scale<T>(stream, lv.sg, B, nullptr, sym(Symbol::RegInvSqrt), 2, s, lv.w, nullptr, lv.S1, lv.S2));
+    HIPCHK(q_at_zero<T>(stream, B, lv.F, lv.w, lv.gmT, 1.0, lv.bt));
+    HIPCHK(spec_scale<T>(stream, lv.sg, B, nullptr, sym(Symbol::RegInvSqrt), 2, lv.bt, out, s, lv.S1, lv.S2));
   }
 
-  double dotv(const Level<T>& lv, const T* a, const T* b) {
-    HIPCHK(dot<T>(stream, 2 * lv.F, a, b, partial, dres));
-    return fetch(1)[0];
+  // per-item dot products of two vector fields (host copies; synchronises)
+  std::vector<double> dots(const Level<T>& lv, const T* a, const T* b) {
+    HIPCHK(dot<T>(stream, B, 2 * lv.F, a, b, partial, dres));
+    const double* r = fetch(0);
+    std::vector<double> out(B);
+    for (int z = 0; z < B; ++z) out[z] = r[4 * z];
+    return out;
   }
 
   // ---- two-level preconditioner -----------------------------------------------------------
   void setup_two_level() {
-    const size_t F = fine.F, Fc = coarse.F;
+    const size_t n = 2 * coarse.F;
     // coarse images
-    HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, 1, fine.mT, coarse.mT, nullptr, fine.S1, coarse.S1, coarse.S2));
-    HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, 1, fine.mR, coarse.mR, nullptr, fine.S1, coarse.S1, coarse.S2));
-    HIPCHK(spec_grad<T>(stream, coarse.sg, 1, coarse.mT, coarse.gmT, coarse.S1, coarse.S2));
-    (void)F;
-    // Lanczos on (I + S Q(0) S) from a SplitMix64 start vector
-    std::vector<double> h = splitmix64_uniform(prm.lanczos_seed, 2 * Fc);
-    std::vector<T> ht(h.begin(), h.end());
+    HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, B, nullptr, 1, fine.mT, coarse.mT, nullptr, fine.S1, coarse.S1,
+                            coarse.S2));
+    HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, B, nullptr, 1, fine.mR, coarse.mR, nullptr, fine.S1, coarse.S1,
+                            coarse.S2));
+    HIPCHK(spec_grad<T>(stream, coarse.sg, B, coarse.mT, coarse.gmT, coarse.S1, coarse.S2));
+    // Lanczos on (I + S Q(0) S) of every item from one SplitMix64 start vector
+    std::vector<double> h = splitmix64_uniform(prm.lanczos_seed, n);
+    std::vector<T> ht(B * n);
+    for (int z = 0; z < B; ++z) std::copy(h.begin(), h.end(), ht.begin() + z * n);
     T* q = coarse.vec[0];
     T* qp = coarse.vec[1];
     T* w = coarse.vec[2];
-    HIPCHK(hipMemcpyAsync(q, ht.data(), 2 * Fc * sizeof(T), hipMemcpyHostToDevice, stream));
-    HIPCHK(hipStreamSynchronize(stream));
-    double nq = std::sqrt(dotv(coarse, q, q));
-    HIPCHK(axpby<T>(stream, 2 * Fc, 0.0, q, 1.0 / nq, q));
-    HIPCHK(fill<T>(stream, 2 * Fc, 0.0, qp));
-    std::vector<double> al, be;
-    double beta = 0.0;
+    HIPCHK(hipMemcpyAsync(q, ht.data(), B * n * sizeof(T), hipMemcpyHostToDevice, stream));
+    std::vector<double> nq = dots(coarse, q, q);  // synchronises before ht goes out of scope
+    for (auto& x : nq) x = 1.0 / std::sqrt(x);
+    put_scalars(0, nq);
+    HIPCHK(axpby<T>(stream, B, n, 1.0, sc(0), q, 0.0, nullptr, q));
+    HIPCHK(fill<T>(stream, B * n, 0.0, qp));
+    std::vector<std::vector<double>> al(B), be(B);
+    std::vector<double> beta(B, 0.0);
+    std::vector<int> live(B, 1);
     for (int j = 0; j < prm.lanczos_steps; ++j) {
       split_matvec_zero(coarse, q, w);
-      HIPCHK(axpby<T>(stream, 2 * Fc, -beta, qp, 1.0, w));
-      const double alpha = dotv(coarse, q, w);
-      HIPCHK(axpby<T>(stream, 2 * Fc, -alpha, q, 1.0, w));
-      al.push_back(alpha);
-      beta = std::sqrt(dotv(coarse, w, w));
-      if (j == prm.lanczos_steps - 1 || beta <= 1e-14 * std::fabs(alpha)) break;
-      be.push_back(beta);
-      std::swap(qp, q);                                            // qp <- q
-      HIPCHK(axpby<T>(stream, 2 * Fc, 1.0 / beta, w, 0.0, q));     // q <- w / beta
+      put_scalars(1, beta);
+      HIPCHK(axpby<T>(stream, B, n, -1.0, sc(1), qp, 1.0, nullptr, w));
+      std::vector<double> alpha = dots(coarse, q, w);
+      put_scalars(2, alpha);
+      HIPCHK(axpby<T>(stream, B, n, -1.0, sc(2), q, 1.0, nullptr, w));
+      std::vector<double> ww = dots(coarse, w, w);
+      bool more = false;
+      std::vector<double> inv(B, 0.0);
+      for (int z = 0; z < B; ++z) {
+        if (!live[z]) continue;
+        al[z].push_back(alpha[z]);
+        beta[z] = std::sqrt(ww[z]);
+        if (j == prm.lanczos_steps - 1 || beta[z] <= 1e-14 * std::fabs(alpha[z])) {
+          live[z] = 0;  // last step or breakdown: this item's tridiagonal matrix is complete
+          beta[z] = 0.0;
+        } else {
+          be[z].push_back(beta[z]);
+          inv[z] = 1.0 / beta[z];
+          more = true;
+        }
+      }
+      if (!more) break;
+      std::swap(qp, q);  // qp <- q
+      put_scalars(3, inv);
+      HIPCHK(axpby<T>(stream, B, n, 1.0, sc(3), w, 0.0, nullptr, q));  // q <- w / beta
     }
-    be.resize(al.size() > 0 ? al.size() - 1 : 0);
-    emax = prm.emax_safety * tridiag_max_eig(al, be);
     // e_min = min_k 1 + 1 / (beta a'(k)) over the coarse modes: the largest |k|^2 is at the
     // corner (nc1/2, nc2/2)
     const double kk = 0.25 * double(coarse.n1) * coarse.n1 + 0.25 * double(coarse.n2) * coarse.n2;
-    emin = 1.0 + 1.0 / (prm.beta * std::pow(kk, prm.reg));
-    if (!(emax > emin)) throw Fail{SLNK_ENAN, "Lanczos produced an invalid e_max"};
+    const int k = prm.cheb_iters;
+    std::vector<double> itheta(B), tab(2 * size_t(k) * B, 0.0);
+    for (int z = 0; z < B; ++z) {
+      emax[z] = prm.emax_safety * tridiag_max_eig(al[z], be[z]);
+      emin[z] = 1.0 + 1.0 / (prm.beta * std::pow(kk, prm.reg));
+      if (!(emax[z] > emin[z]) || !std::isfinite(emax[z])) throw Fail{SLNK_ENAN, "Lanczos produced an invalid e_max"};
+      // Chebyshev recurrence of every step (Saad, Algorithm 12.1): d <- c1[i] d + c2[i] r
+      const double theta = 0.5 * (emax[z] + emin[z]), delta = 0.5 * (emax[z] - emin[z]);
+      const double sigma = theta / delta;
+      double rho = 1.0 / sigma;
+      itheta[z] = 1.0 / theta;
+      for (int i = 0; i < k; ++i) {
+        const double rho_next = 1.0 / (2.0 * sigma - rho);
+        tab[size_t(i) * B + z] = rho_next * rho;
+        tab[(size_t(k) + i) * B + z] = 2.0 * rho_next / delta;
+        rho = rho_next;
+      }
+    }
+    HIPCHK(hipMemcpyAsync(cheb_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(inv_theta, itheta.data(), B * sizeof(double), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipStreamSynchronize(stream));
   }
 
-  void linearize_coarse(const T* v_fine) {
-    HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, 2, v_fine, coarse.vec[7], nullptr, fine.S1, coarse.S1, coarse.S2));
-    coarse.cur = 0;
-    linearize(coarse, 0, coarse.vec[7], false);
+  // coarse linearisation at the restriction of the fine slot-0 velocity, items of mk / hmask
+  void linearize_coarse(const int* mk, const std::vector<int>& hmask) {
+    HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, B, mk, 2, fine.lin[0].v, coarse.vec[7], nullptr, fine.S1,
+                            coarse.S1, coarse.S2));
+    linearize(coarse, 0, coarse.vec[7], false, nullptr, mk, hmask);
     ensure_gm(coarse);
   }
 
-  // x = CHEB_k(M_c) b on the coarse level (x, b distinct; uses vec[3..6])
-  void chebyshev(const T* b, T* x) {
+  // x = CHEB_k(M_c) b on the coarse level (x, b distinct; uses vec[3..5])
+  void chebyshev(const T* b, T* x, const int* mk) {
     const size_t n = 2 * coarse.F;
-    const double theta = 0.5 * (emax + emin), delta = 0.5 * (emax - emin);
-    const double sigma = theta / delta;
-    double rho = 1.0 / sigma;
     T* r = coarse.vec[3];
     T* d = coarse.vec[4];
     T* Md = coarse.vec[5];
-    HIPCHK(hipMemcpyAsync(r, b, n * sizeof(T), hipMemcpyDeviceToDevice, stream));
-    HIPCHK(axpby<T>(stream, n, 1.0 / theta, b, 0.0, d));
-    HIPCHK(fill<T>(stream, n, 0.0, x));
     const int k = prm.cheb_iters;
+    HIPCHK(axpby<T>(stream, B, n, 1.0, nullptr, b, 0.0, nullptr, r));
+    HIPCHK(axpby<T>(stream, B, n, 1.0, inv_theta, b, 0.0, nullptr, d));
     for (int i = 0; i < k; ++i) {
-      HIPCHK(axpby<T>(stream, n, 1.0, d, 1.0, x));
+      HIPCHK(axpby<T>(stream, B, n, 1.0, nullptr, d, i == 0 ? 0.0 : 1.0, nullptr, x));
       if (i == k - 1) break;
-      split_matvec(coarse, d, Md);
-      ++n_coarse;
-      HIPCHK(axpby<T>(stream, n, -1.0, Md, 1.0, r));
-      const double rho_next = 1.0 / (2.0 * sigma - rho);
-      HIPCHK(axpby<T>(stream, n, 2.0 * rho_next / delta, r, rho_next * rho, d));
-      rho = rho_next;
+      split_matvec(coarse, d, Md, mk);
+      HIPCHK(axpby<T>(stream, B, n, -1.0, nullptr, Md, 1.0, nullptr, r));
+      HIPCHK(axpby<T>(stream, B, n, 1.0, cheb_tab + (size_t(k) + i) * B, r, 1.0, cheb_tab + size_t(i) * B, d));
     }
   }
 
-  void precond(const T* r, T* z) {
+  // Run 'body' (device work only, no synchronisation) from a graph captured for 'key', or
+  // directly when graphs are off or a current halo exceeds the graphed footprint.
+  template <class Fn>
+  void graphed(std::tuple<int, const void*, const void*, const void*> key, bool eligible, Fn&& body) {
+    if (!use_graphs || !eligible) {
+      body();
+      return;
+    }
+    auto it = graphs.find(key);
+    if (it == graphs.end()) {
+      if (graphs.size() >= 32) clear_graphs();  // callers cycling through many buffers
+      hipStream_t user = stream;
+      stream = cap_stream;
+      capturing = true;
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        try {
+          body();
+        } catch (...) {
+          (void)hipStreamEndCapture(cap_stream, &g);
+          if (g) (void)hipGraphDestroy(g);
+          stream = user;
+          capturing = false;
+          throw;
+        }
+        e = hipStreamEndCapture(cap_stream, &g);
+      }
+      stream = user;
+      capturing = false;
+      if (e != hipSuccess) throw Fail{SLNK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e)};
+      hipGraphExec_t ex = nullptr;
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) throw Fail{SLNK_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e)};
+      it = graphs.emplace(key, ex).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, stream));
+  }
+
+  bool halo_fits(const Level<T>& lv) const { return lv.max_halo(0, {}) <= halo_cap; }
+
+  void count(std::vector<int>& c, const std::vector<int>& hmask, int by) {
+    for (int z = 0; z < B; ++z)
+      if (hmask.empty() || hmask[z]) c[z] += by;
+  }
+
+  void precond(const T* r, T* z, const int* mk, const std::vector<int>& hmask) {
     const double t0 = now_ms();
     if (!two_level) {
-      HIPCHK(spec_scale<T>(stream, fine.sg, sym(Symbol::RegInv), 2, r, z, nullptr, fine.S1, fine.S2));
+      HIPCHK(spec_scale<T>(stream, fine.sg, B, mk, sym(Symbol::RegInv), 2, r, z, nullptr, fine.S1, fine.S2));
     } else {
-      T* rc = coarse.vec[6];
-      T* zc = coarse.vec[2];
-      HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, 2, r, rc, fine.Sk, fine.S1, coarse.S1, coarse.S2));
-      chebyshev(rc, zc);
-      HIPCHK(spec_prolong_combine<T>(stream, fine.sg, coarse.sg, 2, fine.Sk, zc, z, fine.S1, coarse.S1, coarse.S2));
+      graphed({1, r, z, mk}, halo_fits(coarse), [&] {
+        T* rc = coarse.vec[6];
+        T* zc = coarse.vec[2];
+        HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, B, mk, 2, r, rc, fine.Sk, fine.S1, coarse.S1, coarse.S2));
+        chebyshev(rc, zc, mk);
+        HIPCHK(spec_prolong_combine<T>(stream, fine.sg, coarse.sg, B, mk, 2, fine.Sk, zc, z, fine.S1, coarse.S1,
+                                       coarse.S2));
+      });
+      count(n_coarse, hmask, prm.cheb_iters - 1);
     }
     HIPCHK(hipStreamSynchronize(stream));
     t_prec += now_ms() - t0;
   }
 
   // fine operator of the Krylov solve: H (P_REG) or the split operator (P_2L)
-  void op(const T* x, T* y) {
-    ++n_matvec;
-    if (two_level)
-      split_matvec(fine, x, y);
-    else
-      hessian(fine, x, y);
+  void op(const T* x, T* y, const int* mk, const std::vector<int>& hmask) {
+    count(n_matvec, hmask, 1);
+    ensure_gm(fine);
+    graphed({2, x, y, mk}, halo_fits(fine), [&] {
+      if (two_level)
+        split_matvec(fine, x, y, mk);
+      else
+        hessian(fine, x, y, mk);
+    });
   }
 
-  // PCG from zero on op x = b; returns iterations, status in *st
-  int pcg(const T* b, T* x, double tol, int maxit, int* st) {
+  // Per-item PCG from zero on op x = b (relative tolerances tol[z]), in lock step over the items
+  // of 'active'.  Iterations and status of each item in its / st.  Stopped items see zero step
+  // coefficients, which leave their x and r untouched.
+  void pcg(const T* b, T* x, const std::vector<double>& tol, int maxit, std::vector<int> active, std::vector<int>& its,
+           std::vector<int>& st) {
     const size_t n = 2 * fine.F;
     T* r = fine.vec[0];
     T* z = fine.vec[1];
     T* p = fine.vec[2];
     T* q = fine.vec[3];
-    HIPCHK(fill<T>(stream, n, 0.0, x));
-    HIPCHK(hipMemcpyAsync(r, b, n * sizeof(T), hipMemcpyDeviceToDevice, stream));
-    const double bnorm = std::sqrt(dotv(fine, b, b));
-    *st = SLNK_OK;
-    if (bnorm == 0.0) return 0;
-    precond(r, z);
-    HIPCHK(hipMemcpyAsync(p, z, n * sizeof(T), hipMemcpyDeviceToDevice, stream));
-    double rz = dotv(fine, r, z);
-    for (int it = 1; it <= maxit; ++it) {
-      op(p, q);
-      const double pq = dotv(fine, p, q);
-      if (!std::isfinite(pq)) throw Fail{SLNK_ENAN, "non-finite curvature in PCG"};
-      if (pq <= 0.0) {
-        if (it == 1) HIPCHK(hipMemcpyAsync(x, z, n * sizeof(T), hipMemcpyDeviceToDevice, stream));
-        *st = SLNK_ENEGCURV;
-        return it;
-      }
-      const double alpha = rz / pq;
-      HIPCHK(axpby<T>(stream, n, alpha, p, 1.0, x));
-      HIPCHK(axpby<T>(stream, n, -alpha, q, 1.0, r));
-      const double rr = dotv(fine, r, r);
-      if (std::sqrt(rr) <= tol * bnorm) return it;
-      precond(r, z);
-      const double rz_next = dotv(fine, r, z);
-      HIPCHK(axpby<T>(stream, n, 1.0, z, rz_next / rz, p));
-      rz = rz_next;
+    its.assign(B, 0);
+    st.assign(B, SLNK_OK);
+    HIPCHK(fill<T>(stream, B * n, 0.0, x));
+    HIPCHK(axpby<T>(stream, B, n, 1.0, nullptr, b, 0.0, nullptr, r));
+    std::vector<double> bnorm = dots(fine, b, b);
+    for (int k = 0; k < B; ++k) {
+      bnorm[k] = std::sqrt(bnorm[k]);
+      if (bnorm[k] == 0.0) active[k] = 0;
     }
-    *st = SLNK_EMAXIT;
-    return maxit;
+    if (!any_of(active)) return;
+    const int* mk = mask(kMaskPcg);
+    put_mask(kMaskPcg, active);
+    precond(r, z, mk, active);
+    HIPCHK(axpby<T>(stream, B, n, 1.0, nullptr, z, 0.0, nullptr, p));
+    std::vector<double> rz = dots(fine, r, z);
+    std::vector<double> alpha(B), beta(B);
+    for (int it = 1; it <= maxit; ++it) {
+      op(p, q, mk, active);
+      std::vector<double> pq = dots(fine, p, q);
+      for (int k = 0; k < B; ++k) {
+        alpha[k] = 0.0;
+        if (!active[k]) continue;
+        its[k] = it;
+        if (!std::isfinite(pq[k])) throw Fail{SLNK_ENAN, "non-finite curvature in PCG"};
+        if (pq[k] <= 0.0) {
+          // non-positive curvature: stop with the current iterate (at the first step, the
+          // preconditioned residual)
+          if (it == 1) HIPCHK(masked_copy<T>(stream, 1, n, z + k * n, 0, x + k * n, 0, nullptr));
+          st[k] = SLNK_ENEGCURV;
+          active[k] = 0;
+          continue;
+        }
+        alpha[k] = rz[k] / pq[k];
+      }
+      put_scalars(4, alpha);
+      HIPCHK(axpby<T>(stream, B, n, 1.0, sc(4), p, 1.0, nullptr, x));
+      HIPCHK(axpby<T>(stream, B, n, -1.0, sc(4), q, 1.0, nullptr, r));
+      std::vector<double> rr = dots(fine, r, r);
+      bool more = false;
+      for (int k = 0; k < B; ++k) {
+        if (!active[k]) continue;
+        if (std::sqrt(rr[k]) <= tol[k] * bnorm[k])
+          active[k] = 0;
+        else
+          more = true;
+      }
+      if (!more) return;
+      if (it == maxit) break;
+      put_mask(kMaskPcg, active);
+      precond(r, z, mk, active);
+      std::vector<double> rz_next = dots(fine, r, z);
+      for (int k = 0; k < B; ++k) beta[k] = active[k] ? rz_next[k] / rz[k] : 0.0;
+      put_scalars(5, beta);
+      for (int k = 0; k < B; ++k)
+        if (active[k]) rz[k] = rz_next[k];
+      // p <- z + beta p for the running items; stopped items keep p (coefficients 0, 1)
+      for (int k = 0; k < B; ++k) alpha[k] = active[k] ? 1.0 : 0.0;
+      put_scalars(6, alpha);
+      for (int k = 0; k < B; ++k)
+        if (!active[k]) beta[k] = 1.0;
+      put_scalars(7, beta);
+      HIPCHK(axpby<T>(stream, B, n, 1.0, sc(6), z, 1.0, sc(7), p));
+    }
+    for (int k = 0; k < B; ++k)
+      if (active[k]) st[k] = SLNK_EMAXIT;
   }
 
   // ---- kernel timing ----------------------------------------------------------------------
   double time_kernel(int which, int reps) {
     auto& lv = fine;
-    auto& L = lv.L();
+    auto& L = lv.lin[0];
     ensure_gm(lv);
     const size_t F = lv.F;
     const double ht = 1.0 / lv.nt;
-    // sources with sane values: the state, a copy of it, and a zeroed accumulator
-    HIPCHK(hipMemcpyAsync(lv.q, L.m, F * sizeof(T), hipMemcpyDeviceToDevice, stream));
-    HIPCHK(hipMemcpyAsync(lv.q + F, L.m, F * sizeof(T), hipMemcpyDeviceToDevice, stream));
-    HIPCHK(fill<T>(stream, 2 * F, 0.0, lv.acc));
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    // sources with sane values: the state (twice) and a zeroed accumulator
+    HIPCHK(masked_copy<T>(stream, B, F, L.m, (long long)((lv.nt + 1) * F), lv.q, (long long)(2 * F), nullptr));
+    HIPCHK(masked_copy<T>(stream, B, F, L.m, (long long)((lv.nt + 1) * F), lv.q + F, (long long)(2 * F), nullptr));
+    HIPCHK(fill<T>(stream, B * 2 * F, 0.0, lv.acc));
     auto one = [&](int r) {
-      StepArgs<T> a;
-      a.n1 = lv.n1;
-      a.n2 = lv.n2;
-      a.halo = L.halo;
+      StepArgs<T> a = step_base(lv, 0, nullptr, false);
       a.src = lv.q + (r % 2) * F;
       a.dst = lv.q + ((r + 1) % 2) * F;
-      a.ht = ht;
-      a.coef = lv.coef;
+      a.st_src = a.st_dst = (long long)(2 * F);
       a.gamma = L.gamma;
+      a.st_gamma = (long long)F;
       a.gm_new = L.gm;
+      a.st_gm = (long long)(2 * (lv.nt + 1) * F);
       a.w_new = 1e-3;
       a.acc = lv.acc;
+      a.st_acc = (long long)(2 * F);
       a.vt = L.v;
+      a.st_vt = (long long)(2 * F);
+      a.st_d = (long long)(2 * F);
       int nb = 0;
       switch (which) {
         case 0:
-          a.d1 = L.df, a.d2 = L.df + F;
+          a.d1 = L.df;
           HIPCHK(sl_step<T>(stream, StepKind::State, a, &nb));
           break;
         case 1:
-          a.d1 = L.da, a.d2 = L.da + F;
+          a.d1 = L.da;
           HIPCHK(sl_step<T>(stream, StepKind::Adjoint, a, &nb));
           break;
         case 2:
-          a.d1 = L.df, a.d2 = L.df + F;
+          a.d1 = L.df;
           HIPCHK(sl_step<T>(stream, StepKind::IncState, a, &nb));
           break;
         case 3:
-          a.d1 = L.da, a.d2 = L.da + F;
+          a.d1 = L.da;
           HIPCHK(sl_step<T>(stream, StepKind::IncAdjoint, a, &nb));
           break;
-        default:
-          HIPCHK(sl_trace<T>(stream, lv.n1, lv.n2, ht, L.v, lv.cv, lv.divv, lv.cdiv, lv.w, lv.bt, lv.coef, nullptr,
-                             &nb));
+        case 4:  // outputs into work buffers of matching sizes (2F, 2F, F per item)
+          HIPCHK(sl_trace<T>(stream, lv.n1, lv.n2, B, nullptr, ht, L.v, lv.cv, lv.divv, lv.cdiv, lv.w, lv.bt, lv.coef,
+                             nullptr, &nb));
+          break;
+        case 5:
+          HIPCHK(spec_scale<T>(stream, lv.sg, B, nullptr, sym(Symbol::RegInvSqrt), 2, L.v, lv.w, nullptr, lv.S1,
+                               lv.S2));
+          break;
+        default:  // recomputes grad m in place (same values)
+          HIPCHK(spec_grad<T>(stream, lv.sg, B * (lv.nt + 1), L.m, L.gm, lv.S1, lv.S2));
       }
     };
     one(0);  // first launch outside the timed region (LDS attribute, constant upload)
+    // back-to-back launches between one pair of events: for a kernel that fills the device this
+    // is its average duration (the same figure a kernel trace reports)
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, stream));
     for (int r = 0; r < reps; ++r) one(r);
     HIPCHK(hipEventRecord(e1, stream));
@@ -694,107 +953,183 @@ struct Context {
   }
 
   // ---- Newton -------------------------------------------------------------------------------
+  // slot 1 -> slot 0 for the accepted items (device mask(kMaskLs) == host 'acc')
+  void promote_trial(const std::vector<int>& acc) {
+    if (!any_of(acc)) return;
+    const size_t F = fine.F;
+    const int nt = fine.nt;
+    const int* mk = mask(kMaskLs);
+    auto& L0 = fine.lin[0];
+    auto& L1 = fine.lin[1];
+    auto cp = [&](const T* a, T* b, size_t cnt) {
+      HIPCHK(masked_copy<T>(stream, B, cnt, a, (long long)cnt, b, (long long)cnt, mk));
+    };
+    cp(L1.v, L0.v, 2 * F);
+    cp(L1.df, L0.df, 2 * F);
+    cp(L1.da, L0.da, 2 * F);
+    cp(L1.gamma, L0.gamma, F);
+    cp(L1.m, L0.m, (nt + 1) * F);
+    cp(L1.bAv, L0.bAv, 2 * F);
+    HIPCHK(masked_copy<double>(stream, B, 2 * F, v64[1], 2 * F, v64[0], 2 * F, mk));
+    HIPCHK(masked_copy<double>(stream, B, 2 * F, bAv64[1], 2 * F, bAv64[0], 2 * F, mk));
+    for (int z = 0; z < B; ++z)
+      if (acc[z]) {
+        L0.J[z] = L1.J[z];
+        L0.Jreg[z] = L1.Jreg[z];
+        L0.halo[z] = L1.halo[z];
+      }
+    HIPCHK(set_ints(stream, fine.halo_dev, L0.halo.data(), B));
+    L0.has_gm = false;  // recomputed for every item (unchanged values for the others)
+  }
+
   slnk_status newton(T* v, const slnk_solve_opts& o, slnk_solve_report* rep) {
     const double t_start = now_ms();
-    slnk_solve_report R;
-    std::memset(&R, 0, sizeof(R));
-    n_matvec = n_coarse = 0;
+    std::vector<slnk_solve_report> R(B);
+    for (auto& r : R) std::memset(&r, 0, sizeof(r));
+    std::fill(n_matvec.begin(), n_matvec.end(), 0);
+    std::fill(n_coarse.begin(), n_coarse.end(), 0);
     t_prec = 0;
-    const size_t F = fine.F, n = 2 * F;
+    const size_t n = 2 * fine.F;
     double t_grad = 0, t_pcg = 0, t_ls = 0;
-    if (two_level) {
-      R.emin = emin;
-      R.emax = emax;
+    const std::vector<int> all(B, 1);
+    for (int z = 0; z < B; ++z) {
+      R[z].emin = two_level ? emin[z] : 0.0;
+      R[z].emax = two_level ? emax[z] : 0.0;
     }
-    // gradient at v = 0 fixes ||g_0|| (section 3.4.1 stopping rule)
-    double g2 = 0, ginf = 0;
+    // gradient at v = 0 fixes ||g_0|| (stopping rule of section 3.4.1)
+    std::vector<double> g2, ginf;
     double t0 = now_ms();
     T* zero = fine.vec[4];
-    HIPCHK(fill<T>(stream, n, 0.0, zero));
-    fine.cur = 0;
-    linearize(fine, 0, zero);
-    gradient(fine, &g2, &ginf);
-    R.g0_inf = ginf;
-    R.g0_two = std::sqrt(g2);
+    HIPCHK(fill<T>(stream, B * n, 0.0, zero));
+    linearize(fine, 0, zero, true, nullptr, nullptr, {});
+    gradient(fine, nullptr, {}, g2, ginf);
+    for (int z = 0; z < B; ++z) {
+      R[z].g0_inf = ginf[z];
+      R[z].g0_two = std::sqrt(g2[z]);
+    }
     // start point
-    HIPCHK(norms<T>(stream, n, v, partial, dres));
-    const double* nv = fetch(3);
-    if (nv[2] > 0) throw Fail{SLNK_ENAN, "non-finite initial velocity"};
-    if (nv[1] > 0.0) {
-      linearize(fine, 0, v);
-      gradient(fine, &g2, &ginf);
+    HIPCHK(norms<T>(stream, B, n, v, partial, dres));
+    const double* nv = fetch(0);
+    bool warm = false;
+    for (int z = 0; z < B; ++z) {
+      if (nv[4 * z + 2] > 0) throw Fail{SLNK_ENAN, "non-finite initial velocity"};
+      if (nv[4 * z + 1] > 0.0) warm = true;
+    }
+    if (warm) {
+      linearize(fine, 0, v, true, nullptr, nullptr, {});
+      gradient(fine, nullptr, {}, g2, ginf);
     }
     t_grad += now_ms() - t0;
-    slnk_status status = SLNK_OK;
-    int k = 0;
+    std::vector<int> active(B, 1), kit(B, 0), status(B, SLNK_OK);
     T* vt = fine.vec[5];
     T* rhs = fine.vec[6];
     T* s = fine.vec[7];
-    for (;; ++k) {
-      const double grel = ginf / R.g0_inf;
-      if (k <= SLNK_REPORT_MAX_ITERS) {
-        R.grel[k] = grel;
-        R.J[k] = fine.L().J;
+    const int* mk = mask(kMaskNewton);
+    for (int k = 0;; ++k) {
+      std::vector<double> eta(B, 0.0);
+      for (int z = 0; z < B; ++z) {
+        if (!active[z]) continue;
+        const double grel = ginf[z] / R[z].g0_inf;
+        if (k <= SLNK_REPORT_MAX_ITERS) {
+          R[z].grel[k] = grel;
+          R[z].J[k] = fine.lin[0].J[z];
+        }
+        if (grel <= o.gtol_rel || ginf[z] <= o.gtol_abs || k >= o.max_newton || k >= SLNK_REPORT_MAX_ITERS) {
+          active[z] = 0;
+          kit[z] = k;
+          continue;
+        }
+        eta[z] = std::min(0.5, std::sqrt(g2[z]) / R[z].g0_two);
       }
-      if (grel <= o.gtol_rel || ginf <= o.gtol_abs || k >= o.max_newton || k >= SLNK_REPORT_MAX_ITERS) break;
-      const double eta = std::min(0.5, std::sqrt(g2) / R.g0_two);
+      if (!any_of(active)) break;
+      put_mask(kMaskNewton, active);
       t0 = now_ms();
-      int st = 0, its = 0;
+      std::vector<int> its, st;
       if (two_level) {
-        linearize_coarse(fine.L().v);
-        HIPCHK(spec_scale<T>(stream, fine.sg, sym(Symbol::RegInvSqrt), 2, fine.g, rhs, nullptr, fine.S1, fine.S2));
-        HIPCHK(axpby<T>(stream, n, 0.0, rhs, -1.0, rhs));
-        its = pcg(rhs, s, eta, o.max_pcg, &st);
-        HIPCHK(spec_scale<T>(stream, fine.sg, sym(Symbol::RegInvSqrt), 2, s, vt, nullptr, fine.S1, fine.S2));
+        linearize_coarse(mk, active);
+        HIPCHK(spec_scale<T>(stream, fine.sg, B, mk, sym(Symbol::RegInvSqrt), 2, fine.g, rhs, nullptr, fine.S1,
+                             fine.S2));
+        HIPCHK(axpby<T>(stream, B, n, -1.0, nullptr, rhs, 0.0, nullptr, rhs));
+        pcg(rhs, s, eta, o.max_pcg, active, its, st);
+        HIPCHK(spec_scale<T>(stream, fine.sg, B, mk, sym(Symbol::RegInvSqrt), 2, s, vt, nullptr, fine.S1, fine.S2));
       } else {
-        HIPCHK(axpby<T>(stream, n, -1.0, fine.g, 0.0, rhs));
-        its = pcg(rhs, vt, eta, o.max_pcg, &st);
+        HIPCHK(axpby<T>(stream, B, n, -1.0, nullptr, fine.g, 0.0, nullptr, rhs));
+        pcg(rhs, vt, eta, o.max_pcg, active, its, st);
       }
       t_pcg += now_ms() - t0;
-      R.pcg_iters += its;
-      if (k < SLNK_REPORT_MAX_ITERS) R.pcg[k] = its;
-      // Armijo backtracking
+      for (int z = 0; z < B; ++z) {
+        if (!active[z]) continue;
+        R[z].pcg_iters += its[z];
+        if (k < SLNK_REPORT_MAX_ITERS) R[z].pcg[k] = its[z];
+      }
+      // Armijo backtracking per item: trial v + alpha vt (FP64 iterate) in slot 1
       t0 = now_ms();
-      const double slope = fine.cell * dotv(fine, fine.g, vt);
-      const double J0 = fine.L().J;
-      const int trial = 1 - fine.cur;
-      double alpha = 1.0;
-      bool ok = false;
-      for (int hv = 0; hv <= o.max_halvings; ++hv) {
-        // trial velocity v + alpha vt (FP64 iterate) in the other slot
-        HIPCHK(xpay_mixed<T>(stream, n, v64[fine.cur], alpha, vt, v64[trial]));
-        linearize(fine, trial, nullptr, true, v64[trial]);
-        ++R.line_search_evals;
-        if (fine.lin[trial].J <= J0 + o.armijo_c1 * alpha * slope) {
-          ok = true;
-          break;
+      std::vector<double> slope = dots(fine, fine.g, vt);
+      for (auto& x : slope) x *= fine.cell;
+      std::vector<double> alpha(B, 1.0);
+      std::vector<int> searching(active), accepted(B, 0);
+      for (int hv = 0; hv <= o.max_halvings && any_of(searching); ++hv) {
+        put_mask(kMaskLs, searching);
+        put_scalars(8, alpha);
+        HIPCHK(xpay_mixed<T>(stream, B, n, v64[0], 1.0, sc(8), vt, v64[1], mask(kMaskLs)));
+        linearize(fine, 1, nullptr, true, v64[1], mask(kMaskLs), searching);
+        for (int z = 0; z < B; ++z) {
+          if (!searching[z]) continue;
+          ++R[z].line_search_evals;
+          if (fine.lin[1].J[z] <= fine.lin[0].J[z] + o.armijo_c1 * alpha[z] * slope[z]) {
+            searching[z] = 0;
+            accepted[z] = 1;
+          } else {
+            alpha[z] *= 0.5;
+          }
         }
-        alpha *= 0.5;
       }
       t_ls += now_ms() - t0;
-      if (!ok) {
-        status = SLNK_ELINESEARCH;
-        break;
-      }
-      fine.cur = trial;
+      for (int z = 0; z < B; ++z)
+        if (active[z] && !accepted[z]) {  // no acceptable step: stop at the last iterate
+          status[z] = SLNK_ELINESEARCH;
+          active[z] = 0;
+          kit[z] = k;
+        }
+      // accepted trials become the current linearisation point
+      put_mask(kMaskLs, accepted);
+      promote_trial(accepted);
       t0 = now_ms();
-      gradient(fine, &g2, &ginf);
+      if (any_of(active)) {
+        put_mask(kMaskNewton, active);
+        std::vector<double> g2n, ginfn;
+        gradient(fine, mk, active, g2n, ginfn);
+        for (int z = 0; z < B; ++z)
+          if (active[z]) {
+            g2[z] = g2n[z];
+            ginf[z] = ginfn[z];
+          }
+      }
       t_grad += now_ms() - t0;
     }
-    R.newton_iters = k;
-    HIPCHK(cast_copy<T>(stream, n, v64[fine.cur], v));
+    HIPCHK(cast_copy<T>(stream, B * n, v64[0], v));
+    if (two_level) {  // the coarse problem follows the final iterate
+      put_mask(kMaskNewton, all);
+      linearize_coarse(mk, {});
+    }
     HIPCHK(hipStreamSynchronize(stream));
     has_grad = true;
-    R.status = status;
-    R.matvecs = n_matvec;
-    R.coarse_matvecs = n_coarse;
-    R.time_total_ms = now_ms() - t_start;
-    R.time_gradient_ms = t_grad;
-    R.time_pcg_ms = t_pcg;
-    R.time_precond_ms = t_prec;
-    R.time_linesearch_ms = t_ls;
-    if (rep) *rep = R;
-    return status;
+    const double t_total = now_ms() - t_start;
+    slnk_status overall = SLNK_OK;
+    for (int z = 0; z < B; ++z) {
+      R[z].status = status[z];
+      R[z].newton_iters = kit[z];
+      R[z].matvecs = n_matvec[z];
+      R[z].coarse_matvecs = n_coarse[z];
+      R[z].time_total_ms = t_total;
+      R[z].time_gradient_ms = t_grad;
+      R[z].time_pcg_ms = t_pcg;
+      R[z].time_precond_ms = t_prec;
+      R[z].time_linesearch_ms = t_ls;
+      if (status[z] != SLNK_OK) overall = slnk_status(status[z]);
+      if (rep) rep[z] = R[z];
+    }
+    return overall;
   }
 };
 
@@ -805,7 +1140,6 @@ struct Context {
 // C ABI
 // ============================================================================================
 struct slnk_ctx {
-  int prec = 0;
   std::string err;
   std::unique_ptr<slnk::Context<float>> f;
   std::unique_ptr<slnk::Context<double>> d;
@@ -855,6 +1189,8 @@ void slnk_default_params(slnk_params* p) {
   p->lanczos_steps = 30;
   p->emax_safety = 1.05;
   p->lanczos_seed = 0x5EED;
+  p->use_graphs = 1;
+  p->batch = 1;
 }
 
 void slnk_default_opts(slnk_solve_opts* o) {
@@ -870,9 +1206,8 @@ void slnk_default_opts(slnk_solve_opts* o) {
 slnk_status slnk_create(const slnk_params* params, void* hip_stream, slnk_ctx** out) {
   if (!params || !out) return SLNK_EINVAL;
   *out = nullptr;
-  auto c = std::make_unique<slnk_ctx>();
-  c->prec = params->prec;
   if (params->prec != SLNK_PREC_FP64 && params->prec != SLNK_PREC_MIXED) return SLNK_EINVAL;
+  auto c = std::make_unique<slnk_ctx>();
   slnk_status st = guarded(c.get(), [&] {
     if (params->prec == SLNK_PREC_MIXED) {
       c->f = std::make_unique<slnk::Context<float>>();
@@ -909,15 +1244,18 @@ slnk_status slnk_set_images(slnk_ctx* ctx, const void* m_R, const void* m_T) {
   if (!m_R || !m_T) return SLNK_EINVAL;
   return dispatch(ctx, [&](auto& C) {
     using T = std::remove_reference_t<decltype(*C.fine.mT)>;
-    const size_t F = C.fine.F;
-    HIPCHK(hipMemcpyAsync(C.fine.mR, m_R, F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
-    HIPCHK(hipMemcpyAsync(C.fine.mT, m_T, F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
+    const size_t n = C.B * C.fine.F;
+    HIPCHK(hipMemcpyAsync(C.fine.mR, m_R, n * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
+    HIPCHK(hipMemcpyAsync(C.fine.mT, m_T, n * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
     for (T* img : {C.fine.mR, C.fine.mT}) {
-      HIPCHK(slnk::norms<T>(C.stream, F, img, C.partial, C.dres));
-      if (C.fetch(3)[2] > 0) throw slnk::Fail{SLNK_ENAN, "non-finite image value"};
+      HIPCHK(slnk::norms<T>(C.stream, C.B, C.fine.F, img, C.partial, C.dres));
+      const double* r = C.fetch(0);
+      for (int z = 0; z < C.B; ++z)
+        if (r[4 * z + 2] > 0) throw slnk::Fail{SLNK_ENAN, "non-finite image value"};
     }
     C.fine.lin[0].valid = C.fine.lin[1].valid = false;
     C.has_grad = false;
+    C.clear_graphs();
     if (C.two_level) C.setup_two_level();
     C.images_set = true;
   });
@@ -929,15 +1267,16 @@ slnk_status slnk_transport_state(slnk_ctx* ctx, const void* v, const void* m0, v
     using T = std::remove_reference_t<decltype(*C.fine.mT)>;
     auto& lv = C.fine;
     const size_t F = lv.F;
-    // run in the non-current slot with a temporary template, then restore the images
-    const int slot = 1 - lv.cur;
+    const int B = C.B;
+    // run in the trial slot with a temporary template, then restore the images
     T* saved = lv.vec[0];
-    HIPCHK(hipMemcpyAsync(saved, lv.mT, F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
-    HIPCHK(hipMemcpyAsync(lv.mT, m0, F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
-    C.linearize(lv, slot, static_cast<const T*>(v), false);
-    HIPCHK(hipMemcpyAsync(m1, lv.lin[slot].m + lv.nt * F, F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
-    HIPCHK(hipMemcpyAsync(lv.mT, saved, F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
-    lv.lin[slot].valid = false;
+    HIPCHK(hipMemcpyAsync(saved, lv.mT, B * F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
+    HIPCHK(hipMemcpyAsync(lv.mT, m0, B * F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
+    C.linearize(lv, 1, static_cast<const T*>(v), false, nullptr, nullptr, {});
+    HIPCHK(slnk::masked_copy<T>(C.stream, B, F, lv.lin[1].m + lv.nt * F, (long long)((lv.nt + 1) * F),
+                                static_cast<T*>(m1), (long long)F, nullptr));
+    HIPCHK(hipMemcpyAsync(lv.mT, saved, B * F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
+    lv.lin[1].valid = false;
     HIPCHK(hipStreamSynchronize(C.stream));
   });
 }
@@ -947,10 +1286,9 @@ slnk_status slnk_objective(slnk_ctx* ctx, const void* v, double* J) {
   return dispatch(ctx, [&](auto& C) {
     using T = std::remove_reference_t<decltype(*C.fine.mT)>;
     if (!C.images_set) throw slnk::Fail{SLNK_EINVAL, "slnk_set_images must come first"};
-    C.fine.cur = 0;
-    C.linearize(C.fine, 0, static_cast<const T*>(v));
     C.has_grad = false;
-    *J = C.fine.L().J;
+    C.linearize(C.fine, 0, static_cast<const T*>(v), true, nullptr, nullptr, {});
+    for (int z = 0; z < C.B; ++z) J[z] = C.fine.lin[0].J[z];
   });
 }
 
@@ -959,14 +1297,18 @@ slnk_status slnk_gradient(slnk_ctx* ctx, const void* v, void* g, double* J) {
   return dispatch(ctx, [&](auto& C) {
     using T = std::remove_reference_t<decltype(*C.fine.mT)>;
     if (!C.images_set) throw slnk::Fail{SLNK_EINVAL, "slnk_set_images must come first"};
-    C.fine.cur = 0;
-    C.linearize(C.fine, 0, static_cast<const T*>(v));
-    double g2, ginf;
-    C.gradient(C.fine, &g2, &ginf);
-    HIPCHK(hipMemcpyAsync(g, C.fine.g, 2 * C.fine.F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
-    if (C.two_level) C.linearize_coarse(C.fine.L().v);
+    C.has_grad = false;
+    C.linearize(C.fine, 0, static_cast<const T*>(v), true, nullptr, nullptr, {});
+    std::vector<double> g2, ginf;
+    C.gradient(C.fine, nullptr, {}, g2, ginf);
+    HIPCHK(hipMemcpyAsync(g, C.fine.g, C.B * 2 * C.fine.F * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
+    if (C.two_level) {
+      C.put_mask(C.kMaskNewton, std::vector<int>(C.B, 1));
+      C.linearize_coarse(C.mask(C.kMaskNewton), {});
+    }
     HIPCHK(hipStreamSynchronize(C.stream));
-    if (J) *J = C.fine.L().J;
+    if (J)
+      for (int z = 0; z < C.B; ++z) J[z] = C.fine.lin[0].J[z];
     C.has_grad = true;
   });
 }
@@ -976,7 +1318,7 @@ slnk_status slnk_hessian_matvec(slnk_ctx* ctx, const void* vt, void* Hvt) {
   return dispatch(ctx, [&](auto& C) {
     using T = std::remove_reference_t<decltype(*C.fine.mT)>;
     if (!C.has_grad) throw slnk::Fail{SLNK_EINVAL, "no linearisation point: call slnk_gradient first"};
-    C.hessian(C.fine, static_cast<const T*>(vt), static_cast<T*>(Hvt));
+    C.hessian(C.fine, static_cast<const T*>(vt), static_cast<T*>(Hvt), nullptr);
   });
 }
 
@@ -985,7 +1327,7 @@ slnk_status slnk_split_matvec(slnk_ctx* ctx, const void* s, void* out) {
   return dispatch(ctx, [&](auto& C) {
     using T = std::remove_reference_t<decltype(*C.fine.mT)>;
     if (!C.has_grad) throw slnk::Fail{SLNK_EINVAL, "no linearisation point: call slnk_gradient first"};
-    C.split_matvec(C.fine, static_cast<const T*>(s), static_cast<T*>(out));
+    C.split_matvec(C.fine, static_cast<const T*>(s), static_cast<T*>(out), nullptr);
   });
 }
 
@@ -993,19 +1335,19 @@ slnk_status slnk_precond_apply(slnk_ctx* ctx, const void* r, void* z) {
   if (!r || !z) return SLNK_EINVAL;
   return dispatch(ctx, [&](auto& C) {
     using T = std::remove_reference_t<decltype(*C.fine.mT)>;
-    if (C.two_level && !C.has_grad) throw slnk::Fail{SLNK_EINVAL, "P_2L needs a linearisation point: call slnk_gradient first"};
-    C.precond(static_cast<const T*>(r), static_cast<T*>(z));
+    if (C.two_level && !C.has_grad)
+      throw slnk::Fail{SLNK_EINVAL, "P_2L needs a linearisation point: call slnk_gradient first"};
+    C.precond(static_cast<const T*>(r), static_cast<T*>(z), C.mask(C.kMaskAll), {});
   });
 }
 
 slnk_status slnk_get_cheb_bounds(const slnk_ctx* ctx, double* emin, double* emax) {
   if (!ctx || !emin || !emax) return SLNK_EINVAL;
-  if (ctx->f) {
-    *emin = ctx->f->emin;
-    *emax = ctx->f->emax;
-  } else {
-    *emin = ctx->d->emin;
-    *emax = ctx->d->emax;
+  const auto& lo = ctx->f ? ctx->f->emin : ctx->d->emin;
+  const auto& hi = ctx->f ? ctx->f->emax : ctx->d->emax;
+  for (size_t z = 0; z < lo.size(); ++z) {
+    emin[z] = lo[z];
+    emax[z] = hi[z];
   }
   return SLNK_OK;
 }
@@ -1015,26 +1357,27 @@ slnk_status slnk_get_field(slnk_ctx* ctx, int which, void* out) {
   return dispatch(ctx, [&](auto& C) {
     using T = std::remove_reference_t<decltype(*C.fine.mT)>;
     auto& lv = C.fine;
-    auto& L = lv.L();
+    auto& L = lv.lin[0];
     if (!L.valid) throw slnk::Fail{SLNK_EINVAL, "no linearisation point"};
     const size_t F = lv.F;
     const T* src = nullptr;
     size_t cnt = F;
+    long long stride = (long long)F;
     switch (which) {
-      case 0: src = L.m + lv.nt * F; break;
-      case 1: src = L.df; cnt = 2 * F; break;
-      case 2: src = L.da; cnt = 2 * F; break;
+      case 0: src = L.m + lv.nt * F; stride = (long long)((lv.nt + 1) * F); break;
+      case 1: src = L.df; cnt = 2 * F; stride = (long long)(2 * F); break;
+      case 2: src = L.da; cnt = 2 * F; stride = (long long)(2 * F); break;
       case 3: src = L.gamma; break;
-      case 4: src = lv.lam; break;
+      case 4: src = lv.lam; stride = (long long)(2 * F); break;
       default: throw slnk::Fail{SLNK_EINVAL, "unknown field"};
     }
-    HIPCHK(hipMemcpyAsync(out, src, cnt * sizeof(T), hipMemcpyDeviceToDevice, C.stream));
+    HIPCHK(slnk::masked_copy<T>(C.stream, C.B, cnt, src, stride, static_cast<T*>(out), (long long)cnt, nullptr));
     HIPCHK(hipStreamSynchronize(C.stream));
   });
 }
 
 slnk_status slnk_time_kernel(slnk_ctx* ctx, int which, int reps, double* avg_ms) {
-  if (!avg_ms || reps < 1 || which < 0 || which > 4) return SLNK_EINVAL;
+  if (!avg_ms || reps < 1 || which < 0 || which > 6) return SLNK_EINVAL;
   return dispatch(ctx, [&](auto& C) {
     if (!C.has_grad) throw slnk::Fail{SLNK_EINVAL, "no linearisation point: call slnk_gradient first"};
     *avg_ms = C.time_kernel(which, reps);

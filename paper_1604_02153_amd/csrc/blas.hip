@@ -1,6 +1,9 @@
 // FP64-accumulated reductions and vector updates for the Krylov, Chebyshev and Lanczos layers
 // (section 3.4: PCG inner products, norms of the reduced gradient, Armijo objective values).
-// Every reduction is two-stage with a fixed combination order, so results are deterministic.
+// Every operation runs on 'batch' same-size items at once (grid y = item).  Every reduction is
+// two-stage with a fixed combination order, so results are deterministic.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace slnk {
@@ -35,8 +38,11 @@ __device__ void block_reduce4(double v[4], unsigned maxmask, int ncomp, double* 
 }
 
 template <typename T, int OP>
-__global__ void __launch_bounds__(kThreads) k_reduce(size_t n, const T* __restrict__ a, const T* __restrict__ b,
+__global__ void __launch_bounds__(kThreads) k_reduce(size_t n, const T* __restrict__ ab, const T* __restrict__ bb,
                                                       double* __restrict__ partial) {
+  const size_t off = size_t(blockIdx.y) * n;
+  const T* a = ab + off;
+  const T* b = bb + off;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   const size_t stride = size_t(gridDim.x) * kThreads;
   for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += stride) {
@@ -59,11 +65,15 @@ __global__ void __launch_bounds__(kThreads) k_reduce(size_t n, const T* __restri
   }
   constexpr int nc = OP == kDot ? 1 : 3;
   constexpr unsigned mm = OP == kNorms ? 2u : 0u;
-  block_reduce4(v, mm, nc, partial + 4 * blockIdx.x);
+  block_reduce4(v, mm, nc, partial + 4 * (size_t(blockIdx.y) * gridDim.x + blockIdx.x));
 }
 
-__global__ void __launch_bounds__(kThreads) k_finish(int nparts, int stride, int ncomp, unsigned maxmask,
-                                                      const double* __restrict__ partial, double* __restrict__ result) {
+// one block per item: combine the item's partials in a fixed order into result[4 item + c]
+__global__ void __launch_bounds__(kThreads) k_finish(int nparts, int stride, long long per_item, int ncomp,
+                                                      unsigned maxmask, const double* __restrict__ partialb,
+                                                      double* __restrict__ resultb) {
+  const double* partial = partialb + blockIdx.x * per_item;
+  double* result = resultb + 4 * blockIdx.x;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int p = threadIdx.x; p < nparts; p += kThreads)
     for (int c = 0; c < ncomp; ++c) {
@@ -76,12 +86,19 @@ __global__ void __launch_bounds__(kThreads) k_finish(int nparts, int stride, int
   if (threadIdx.x < ncomp) result[threadIdx.x] = outv[threadIdx.x];
 }
 
-// y = a x + b y; with b == 0 the old y is not read (it may hold anything)
+// y = (a ad[z]) x + (b bd[z]) y per item z; with a zero y coefficient the old y is not read
 template <typename T>
-__global__ void k_axpby(size_t n, T a, const T* __restrict__ x, T b, T* __restrict__ y) {
-  const bool ready = b != T(0);
+__global__ void k_axpby(size_t n, double a, const double* ad, const T* __restrict__ xb, double b, const double* bd,
+                        T* __restrict__ yb) {
+  const int z = blockIdx.y;
+  const T ca = T(ad ? a * ad[z] : a), cb = T(bd ? b * bd[z] : b);
+  const T* x = xb + size_t(z) * n;
+  T* y = yb + size_t(z) * n;
+  // a zero coefficient drops its operand unread: items frozen by (0, 1) keep y bit for bit
+  const bool rx = ca != T(0), ry = cb != T(0);
+  if (!rx && cb == T(1)) return;
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
-    y[i] = ready ? a * x[i] + b * y[i] : a * x[i];
+    y[i] = rx ? (ry ? ca * x[i] + cb * y[i] : ca * x[i]) : cb * y[i];
 }
 
 template <typename T>
@@ -97,7 +114,11 @@ __global__ void k_fill(size_t n, T v, T* __restrict__ y) {
 }
 
 template <typename T>
-__global__ void k_q0(size_t F, const T* __restrict__ w, const T* __restrict__ gm, T scale, T* __restrict__ out) {
+__global__ void k_q0(size_t F, const T* __restrict__ wb, const T* __restrict__ gmb, T scale, T* __restrict__ outb) {
+  const size_t off = size_t(blockIdx.y) * 2 * F;
+  const T* w = wb + off;
+  const T* gm = gmb + off;
+  T* out = outb + off;
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < F; i += size_t(gridDim.x) * blockDim.x) {
     const T g1 = gm[i], g2 = gm[i + F];
     const T d = scale * (w[i] * g1 + w[i + F] * g2);
@@ -107,16 +128,39 @@ __global__ void k_q0(size_t F, const T* __restrict__ w, const T* __restrict__ gm
 }
 
 template <typename T>
-__global__ void k_xpay_mixed(size_t n, const double* __restrict__ x, double a, const T* __restrict__ y,
-                             double* __restrict__ z) {
+__global__ void k_xpay_mixed(size_t n, const double* __restrict__ xb, double a, const double* ad,
+                             const T* __restrict__ yb, double* __restrict__ zb, const int* mask) {
+  const int z = blockIdx.y;
+  if (mask && !mask[z]) return;
+  const double c = ad ? a * ad[z] : a;
+  const size_t off = size_t(z) * n;
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
-    z[i] = x[i] + a * double(y[i]);
+    zb[off + i] = xb[off + i] + c * double(yb[off + i]);
+}
+
+template <typename T>
+__global__ void k_masked_copy(size_t n, const T* __restrict__ src, long long ss, T* __restrict__ dst, long long ds,
+                              const int* mask) {
+  const int z = blockIdx.y;
+  if (mask && !mask[z]) return;
+  const T* a = src + z * ss;
+  T* b = dst + z * ds;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    b[i] = a[i];
 }
 
 template <typename TI, typename TO>
 __global__ void k_cast(size_t n, const TI* __restrict__ x, TO* __restrict__ y) {
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
     y[i] = TO(x[i]);
+}
+
+struct IntPack {
+  int v[64];
+};
+
+__global__ void k_set_ints(int* p, IntPack pack, int count) {
+  if (int(threadIdx.x) < count) p[threadIdx.x] = pack.v[threadIdx.x];
 }
 
 inline unsigned grid_for(size_t n) {
@@ -128,6 +172,18 @@ inline unsigned grid_for(size_t n) {
 
 }  // namespace
 
+hipError_t set_ints(hipStream_t s, int* p, const int* host_values, int count) {
+  for (int base = 0; base < count; base += 64) {
+    IntPack pack{};
+    const int c = std::min(64, count - base);
+    for (int i = 0; i < c; ++i) pack.v[i] = host_values[base + i];
+    hipLaunchKernelGGL(k_set_ints, dim3(1), dim3(64), 0, s, p + base, pack, c);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 int reduce_blocks(size_t n) {
   size_t b = (n + kThreads * 8 - 1) / (kThreads * 8);
   if (b < 1) b = 1;
@@ -135,42 +191,44 @@ int reduce_blocks(size_t n) {
   return int(b);
 }
 
-hipError_t finish(hipStream_t s, int nparts, int stride, int ncomp, unsigned maxmask, const double* partial,
-                  double* result) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kThreads), 0, s, nparts, stride, ncomp, maxmask, partial, result);
+hipError_t finish(hipStream_t s, int batch, int nparts, int stride, long long per_item, int ncomp, unsigned maxmask,
+                  const double* partial, double* result) {
+  hipLaunchKernelGGL(k_finish, dim3(batch), dim3(kThreads), 0, s, nparts, stride, per_item, ncomp, maxmask, partial,
+                     result);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t dot(hipStream_t s, size_t n, const T* a, const T* b, double* partial, double* result) {
+hipError_t dot(hipStream_t s, int batch, size_t n, const T* a, const T* b, double* partial, double* result) {
   const int nb = reduce_blocks(n);
-  hipLaunchKernelGGL((k_reduce<T, kDot>), dim3(nb), dim3(kThreads), 0, s, n, a, b, partial);
+  hipLaunchKernelGGL((k_reduce<T, kDot>), dim3(nb, batch), dim3(kThreads), 0, s, n, a, b, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return finish(s, nb, 4, 1, 0u, partial, result);
+  return finish(s, batch, nb, 4, 4LL * nb, 1, 0u, partial, result);
 }
 
 template <typename T>
-hipError_t dot3(hipStream_t s, size_t n, const T* a, const T* b, double* partial, double* result) {
+hipError_t dot3(hipStream_t s, int batch, size_t n, const T* a, const T* b, double* partial, double* result) {
   const int nb = reduce_blocks(n);
-  hipLaunchKernelGGL((k_reduce<T, kDot3>), dim3(nb), dim3(kThreads), 0, s, n, a, b, partial);
+  hipLaunchKernelGGL((k_reduce<T, kDot3>), dim3(nb, batch), dim3(kThreads), 0, s, n, a, b, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return finish(s, nb, 4, 3, 0u, partial, result);
+  return finish(s, batch, nb, 4, 4LL * nb, 3, 0u, partial, result);
 }
 
 template <typename T>
-hipError_t norms(hipStream_t s, size_t n, const T* a, double* partial, double* result) {
+hipError_t norms(hipStream_t s, int batch, size_t n, const T* a, double* partial, double* result) {
   const int nb = reduce_blocks(n);
-  hipLaunchKernelGGL((k_reduce<T, kNorms>), dim3(nb), dim3(kThreads), 0, s, n, a, a, partial);
+  hipLaunchKernelGGL((k_reduce<T, kNorms>), dim3(nb, batch), dim3(kThreads), 0, s, n, a, a, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return finish(s, nb, 4, 3, 2u, partial, result);
+  return finish(s, batch, nb, 4, 4LL * nb, 3, 2u, partial, result);
 }
 
 template <typename T>
-hipError_t axpby(hipStream_t s, size_t n, double a, const T* x, double b, T* y) {
-  hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, T(a), x, T(b), y);
+hipError_t axpby(hipStream_t s, int batch, size_t n, double a, const double* ad, const T* x, double b,
+                 const double* bd, T* y) {
+  hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(n), batch), dim3(kThreads), 0, s, n, a, ad, x, b, bd, y);
   return hipGetLastError();
 }
 
@@ -187,8 +245,8 @@ hipError_t fill(hipStream_t s, size_t n, double value, T* y) {
 }
 
 template <typename T>
-hipError_t q_at_zero(hipStream_t s, size_t F, const T* w, const T* gm, double scale, T* out) {
-  hipLaunchKernelGGL(k_q0<T>, dim3(grid_for(F)), dim3(kThreads), 0, s, F, w, gm, T(scale), out);
+hipError_t q_at_zero(hipStream_t s, int batch, size_t F, const T* w, const T* gm, double scale, T* out) {
+  hipLaunchKernelGGL(k_q0<T>, dim3(grid_for(F), batch), dim3(kThreads), 0, s, F, w, gm, T(scale), out);
   return hipGetLastError();
 }
 
@@ -205,22 +263,34 @@ hipError_t cast_back(hipStream_t s, size_t n, const T* x, double* y) {
 }
 
 template <typename T>
-hipError_t xpay_mixed(hipStream_t s, size_t n, const double* x, double a, const T* y, double* z) {
-  hipLaunchKernelGGL(k_xpay_mixed<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, a, y, z);
+hipError_t xpay_mixed(hipStream_t s, int batch, size_t n, const double* x, double a, const double* ad, const T* y,
+                      double* z, const int* mask) {
+  hipLaunchKernelGGL(k_xpay_mixed<T>, dim3(grid_for(n), batch), dim3(kThreads), 0, s, n, x, a, ad, y, z, mask);
   return hipGetLastError();
 }
 
-#define INST(T)                                                                                    \
-  template hipError_t dot<T>(hipStream_t, size_t, const T*, const T*, double*, double*);          \
-  template hipError_t dot3<T>(hipStream_t, size_t, const T*, const T*, double*, double*);         \
-  template hipError_t norms<T>(hipStream_t, size_t, const T*, double*, double*);                  \
-  template hipError_t axpby<T>(hipStream_t, size_t, double, const T*, double, T*);                \
-  template hipError_t xpay<T>(hipStream_t, size_t, const T*, double, const T*, T*);               \
-  template hipError_t fill<T>(hipStream_t, size_t, double, T*);                                   \
-  template hipError_t q_at_zero<T>(hipStream_t, size_t, const T*, const T*, double, T*);          \
-  template hipError_t cast_copy<T>(hipStream_t, size_t, const double*, T*);                       \
-  template hipError_t cast_back<T>(hipStream_t, size_t, const T*, double*);                       \
-  template hipError_t xpay_mixed<T>(hipStream_t, size_t, const double*, double, const T*, double*);
+template <typename T>
+hipError_t masked_copy(hipStream_t s, int batch, size_t n, const T* src, long long src_stride, T* dst,
+                       long long dst_stride, const int* mask) {
+  hipLaunchKernelGGL(k_masked_copy<T>, dim3(grid_for(n), batch), dim3(kThreads), 0, s, n, src, src_stride, dst,
+                     dst_stride, mask);
+  return hipGetLastError();
+}
+
+#define INST(T)                                                                                            \
+  template hipError_t dot<T>(hipStream_t, int, size_t, const T*, const T*, double*, double*);             \
+  template hipError_t dot3<T>(hipStream_t, int, size_t, const T*, const T*, double*, double*);            \
+  template hipError_t norms<T>(hipStream_t, int, size_t, const T*, double*, double*);                     \
+  template hipError_t axpby<T>(hipStream_t, int, size_t, double, const double*, const T*, double,         \
+                               const double*, T*);                                                        \
+  template hipError_t xpay<T>(hipStream_t, size_t, const T*, double, const T*, T*);                       \
+  template hipError_t fill<T>(hipStream_t, size_t, double, T*);                                           \
+  template hipError_t q_at_zero<T>(hipStream_t, int, size_t, const T*, const T*, double, T*);             \
+  template hipError_t cast_copy<T>(hipStream_t, size_t, const double*, T*);                               \
+  template hipError_t cast_back<T>(hipStream_t, size_t, const T*, double*);                               \
+  template hipError_t xpay_mixed<T>(hipStream_t, int, size_t, const double*, double, const double*,       \
+                                    const T*, double*, const int*);                                       \
+  template hipError_t masked_copy<T>(hipStream_t, int, size_t, const T*, long long, T*, long long, const int*);
 INST(float)
 INST(double)
 #undef INST

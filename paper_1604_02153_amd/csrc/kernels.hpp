@@ -45,36 +45,39 @@ struct SymbolParams {
 };
 
 // ---- spectral operators (each: row forward, column forward + symbol + column inverse, row inverse)
-// in/out: real fields; out[i] = symbol(in[i]) + (add ? add[i] : 0), for i < nf (nf = 1 or 2).
-// S1, S2: spectral scratch, each at least 2 * spec() complex.
+// All operate on 'batch' same-size items; per item the fields are consecutive (nf fields of
+// field() elements) and items follow each other.  'active' (optional, [batch]) skips items.
+// Scratch spectra: S1, S2 hold batch * (fields per item) * spec() complex.
+//
+// out = symbol(in) + (add ? add : 0), nf = 1 or 2 fields per item.
 template <typename T>
-hipError_t spec_scale(hipStream_t s, const SpecGrid<T>& g, SymbolParams sym, int nf, const T* in, T* out,
-                      const T* add, cplx<T>* S1, cplx<T>* S2);
+hipError_t spec_scale(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, SymbolParams sym, int nf,
+                      const T* in, T* out, const T* add, cplx<T>* S1, cplx<T>* S2);
 
-// Spectral gradient of 'batch' scalar fields m[b] (stride field()): gm[b] = (d1 m, d2 m) with
-// stride 2 field().  Scratch: S1 >= batch spec(), S2 >= 2 batch spec().
+// Spectral gradient of 'count' consecutive scalar fields m[c] (stride field()): gm[c] = (d1 m, d2 m)
+// with stride 2 field().  S1 >= count spec(), S2 >= 2 count spec().
 template <typename T>
-hipError_t spec_grad(hipStream_t s, const SpecGrid<T>& g, int batch, const T* m, T* gm, cplx<T>* S1, cplx<T>* S2);
+hipError_t spec_grad(hipStream_t s, const SpecGrid<T>& g, int count, const T* m, T* gm, cplx<T>* S1, cplx<T>* S2);
 
-// From v (two fields): spline coefficients cv (two fields), div v and the spline coefficients of
-// div v.  S1 >= 2 spec(), S2 >= 4 spec().
+// Per item, from v (two fields): spline coefficients cv (two fields), div v and the spline
+// coefficients of div v.  S1 >= 2 batch spec(), S2 >= 4 batch spec().
 template <typename T>
-hipError_t spec_trace_prep(hipStream_t s, const SpecGrid<T>& g, const T* v, T* cv, T* divv, T* cdiv, cplx<T>* S1,
-                           cplx<T>* S2);
+hipError_t spec_trace_prep(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, const T* v, T* cv,
+                           T* divv, T* cdiv, cplx<T>* S1, cplx<T>* S2);
 
-// Spectral restriction of nf fields to the grid gc (n/2): the modes |k_i| < n_i/4 survive.
-// If keep_fine != nullptr the fine spectrum (after both forward passes) is also stored there
-// (nf * spec() complex) for a later prolong_combine.  Scratch: S1 (fine, nf spec()),
-// Sc1/Sc2 (coarse, nf gc.spec() each).
+// Spectral restriction of nf fields per item to the grid gc (n/2): the modes |k_i| < n_i/4
+// survive.  If keep_fine != nullptr the fine spectrum (after both forward passes) is also
+// stored there (batch * nf * spec() complex) for a later prolong_combine.  Scratch: S1 (fine),
+// Sc1/Sc2 (coarse), batch * nf spectra each.
 template <typename T>
-hipError_t spec_restrict(hipStream_t s, const SpecGrid<T>& g, const SpecGrid<T>& gc, int nf, const T* in, T* out_c,
-                         cplx<T>* keep_fine, cplx<T>* S1, cplx<T>* Sc1, cplx<T>* Sc2);
+hipError_t spec_restrict(hipStream_t s, const SpecGrid<T>& g, const SpecGrid<T>& gc, int batch, const int* active,
+                         int nf, const T* in, T* out_c, cplx<T>* keep_fine, cplx<T>* S1, cplx<T>* Sc1, cplx<T>* Sc2);
 
 // out = HighPass(fine spectrum kept by spec_restrict) + Prolong(zc): the two-level combine.
 template <typename T>
-hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecGrid<T>& gc, int nf,
-                                const cplx<T>* fine_k, const T* zc, T* out, cplx<T>* S1, cplx<T>* Sc1,
-                                cplx<T>* Sc2);
+hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecGrid<T>& gc, int batch,
+                                const int* active, int nf, const cplx<T>* fine_k, const T* zc, T* out, cplx<T>* S1,
+                                cplx<T>* Sc1, cplx<T>* Sc2);
 
 // ---- semi-Lagrangian transport ---------------------------------------------------------
 // Displacements are stored in cells: departure point of node i is i + d (per axis).
@@ -85,34 +88,40 @@ enum class StepKind : int {
   IncAdjoint = 3, // dst = gamma I[src](X_a); bt += ht w lam~ grad m
 };
 
+// Arguments of one SL time step of B same-size items (image pairs).  Every pointer addresses item
+// 0; item z uses pointer + z * (that pointer's stride, in elements).
 template <typename T>
 struct StepArgs {
   int n1 = 0, n2 = 0;
-  int halo = 0;              // bound D on |displacement| in cells for this linearisation
-  const T* src = nullptr;    // field transported (or nullptr with a 'first' source, see below)
+  int batch = 1;             // items B (blockIdx.z)
+  const int* active = nullptr;  // optional [B] mask: items with 0 are skipped
+  int halo = 0;              // bound D on |displacement| in cells: sizes the LDS footprint
+  const int* halo_dev = nullptr;  // optional [B] device copy of each item's actual bound (<= halo),
+                                  // read by the kernel so captured graphs stay valid across
+                                  // linearisations
+  const T* src = nullptr;    // field transported (nullptr with a 'first' source, see below)
   T* dst = nullptr;
-  const T* d1 = nullptr;     // displacement fields (cells)
-  const T* d2 = nullptr;
+  const T* d1 = nullptr;     // displacement fields (cells); d2 = d1 + n1 n2
   const T* gamma = nullptr;  // adjoint step factor
-  // first-step sources (src == nullptr): State: none; Adjoint: mR - mfin; IncState: (ht/2) f(vt, gm0);
-  // IncAdjoint: none
+  // first-step sources (src == nullptr): Adjoint: aux0 - aux1 (m_R - m(1)); IncState:
+  // (ht/2) f(vt, gm_old)
   const T* aux0 = nullptr;
   const T* aux1 = nullptr;
-  // accumulation: gm_cur/gm_prev: gradient of m at the arrival (new) time level and, for the
-  // first adjoint step, at the initial (final-time) level
   const T* gm_new = nullptr; // 2 fields, grad m at the time level being produced
   const T* gm_old = nullptr; // 2 fields, grad m at the time level of src (first step only)
   T* acc = nullptr;          // 2 fields accumulator (b or bt)
   const T* vt = nullptr;     // incremental state: direction (2 fields)
   const T* addf = nullptr;   // adjoint last step: beta A v added to the accumulator (2 fields)
   T* out2 = nullptr;         // adjoint last step: gradient output (2 fields)
+  T* coef = nullptr;         // one-field scratch for the coefficient pass when halo exceeds LDS
+  long long st_src = 0, st_dst = 0, st_d = 0, st_gamma = 0, st_aux0 = 0, st_aux1 = 0, st_gm = 0,
+            st_acc = 0, st_vt = 0, st_addf = 0, st_out2 = 0, st_coef = 0;
   double ht = 0;
   double w_new = 0;          // trapezoid weight of the produced level (times ht)
   double w_old = 0;          // trapezoid weight of the src level (first step only)
   int first = 0, last = 0;
-  double* partial = nullptr; // FP64 per-block partial sums (state last step: misfit; adjoint
-                             // last step: sum g^2 and max |g|)
-  T* coef = nullptr;         // one-field scratch for the coefficient pass when halo exceeds LDS
+  double* partial = nullptr; // FP64 per-block partial sums, item z at partial + z * 2 * tiles
+                             // (state last step: misfit; adjoint last step: sum g^2, max |g|)
 };
 
 // Maximum halo (in cells) the fused LDS step supports for a given precision on this device.
@@ -120,54 +129,71 @@ struct StepArgs {
 template <typename T>
 int sl_step_max_halo();
 
-// One SL time step.  Partial sums (when a.partial and a.last) go to partial[2 * block + {0,1}];
-// *nblocks_out receives the number of blocks.
+// One SL time step of every item.  Partial sums (when a.partial and a.last) of item z go to
+// partial[z * 2 * tiles + 2 * block + {0, 1}]; *nblocks_out receives the tiles per item.
 template <typename T>
 hipError_t sl_step(hipStream_t s, StepKind kind, const StepArgs<T>& a, int* nblocks_out);
 
-// Heun trace of both characteristics at once.
-// in: v (2 fields), cv (2 fields, spline coefficients of v), divv, cdiv (coefficients of div v).
-// out: df (2 fields), da (2 fields), gamma; partial[2 block + 1] = max |d| over the block.
+// Heun trace of both characteristics at once, for B items.  Per item: v, cv (spline
+// coefficients of v), df, da are 2 fields (item stride 2F); divv, cdiv (div v and its
+// coefficients), gamma are one field (stride F).  partial[z * 2 * tiles + 2 block + 1] = max |d|.
 template <typename T>
-hipError_t sl_trace(hipStream_t s, int n1, int n2, double ht, const T* v, const T* cv, const T* divv,
-                    const T* cdiv, T* df, T* da, T* gamma, double* partial, int* nblocks_out);
+hipError_t sl_trace(hipStream_t s, int n1, int n2, int batch, const int* active, double ht, const T* v,
+                    const T* cv, const T* divv, const T* cdiv, T* df, T* da, T* gamma, double* partial,
+                    int* nblocks_out);
 
 // ---- reductions and vector updates -------------------------------------------------------
-// Two-stage deterministic FP64 reductions: per-block partials (reduce_blocks(n) blocks, 4 slots
-// each), then one block that combines them in a fixed order.  'partial' needs
-// 4 * reduce_blocks(n) doubles; results land in device memory.
+// Two-stage deterministic FP64 reductions over 'batch' items of n elements each (item stride n):
+// per-block partials (reduce_blocks(n) blocks per item, 4 slots each), then one block per item
+// that combines them in a fixed order.  'partial' needs 4 * batch * reduce_blocks(n) doubles;
+// item z's results land at result[4 z + c] (device memory).
 int reduce_blocks(size_t n);
-// result[0] = a.b
+// result[4z] = a.b
 template <typename T>
-hipError_t dot(hipStream_t s, size_t n, const T* a, const T* b, double* partial, double* result);
-// result[0] = a.a, result[1] = a.b, result[2] = b.b
+hipError_t dot(hipStream_t s, int batch, size_t n, const T* a, const T* b, double* partial, double* result);
+// result[4z + {0,1,2}] = {a.a, a.b, b.b}
 template <typename T>
-hipError_t dot3(hipStream_t s, size_t n, const T* a, const T* b, double* partial, double* result);
-// result[0] = sum a^2, result[1] = max |a|, result[2] = number of non-finite entries
+hipError_t dot3(hipStream_t s, int batch, size_t n, const T* a, const T* b, double* partial, double* result);
+// result[4z + {0,1,2}] = {sum a^2, max |a|, number of non-finite entries}
 template <typename T>
-hipError_t norms(hipStream_t s, size_t n, const T* a, double* partial, double* result);
-// combine 'ncomp' components of partial[stride * block + c]: component c is a max if bit c of
-// maxmask is set, else a sum
-hipError_t finish(hipStream_t s, int nparts, int stride, int ncomp, unsigned maxmask, const double* partial,
-                  double* result);
+hipError_t norms(hipStream_t s, int batch, size_t n, const T* a, double* partial, double* result);
+// combine 'ncomp' components of partial[z * per_item + stride * block + c] for each item z into
+// result[4 z + c]: component c is a max if bit c of maxmask is set, else a sum
+hipError_t finish(hipStream_t s, int batch, int nparts, int stride, long long per_item, int ncomp, unsigned maxmask,
+                  const double* partial, double* result);
 
-// y = a x + b y (b == 0: y is written without being read)
+// Per item z (n elements each): y = (a * ad[z]) x + (b * bd[z]) y, with ad / bd optional [batch]
+// device arrays (nullptr: 1).  An operand whose coefficient is zero is not read, and an item with
+// coefficients (0, 1) is left untouched.
 template <typename T>
-hipError_t axpby(hipStream_t s, size_t n, double a, const T* x, double b, T* y);
-// z = x + a y
+hipError_t axpby(hipStream_t s, int batch, size_t n, double a, const double* ad, const T* x, double b,
+                 const double* bd, T* y);
+// z = x + a y over n elements (one item or all items)
 template <typename T>
 hipError_t xpay(hipStream_t s, size_t n, const T* x, double a, const T* y, T* z);
 template <typename T>
 hipError_t fill(hipStream_t s, size_t n, double value, T* y);
-// Q(0) w = (w . gm) gm pointwise (the transport part of the GN Hessian at v = 0): out = scale * Q w
+// Q(0) w = (w . gm) gm pointwise per item (F nodes, w and gm 2 fields per item): the transport
+// part of the GN Hessian at v = 0
 template <typename T>
-hipError_t q_at_zero(hipStream_t s, size_t F, const T* w, const T* gm, double scale, T* out);
+hipError_t q_at_zero(hipStream_t s, int batch, size_t F, const T* w, const T* gm, double scale, T* out);
 template <typename T>
 hipError_t cast_copy(hipStream_t s, size_t n, const double* x, T* y);
 template <typename T>
 hipError_t cast_back(hipStream_t s, size_t n, const T* x, double* y);
-// z = x + a y with x, z in FP64 and y in T (the FP64 Newton iterate plus a step in T)
+// per item: z = x + (a * ad[z]) y with x, z in FP64 and y in T (the FP64 Newton iterate plus a
+// step); items with mask[z] == 0 are left untouched (mask optional)
 template <typename T>
-hipError_t xpay_mixed(hipStream_t s, size_t n, const double* x, double a, const T* y, double* z);
+hipError_t xpay_mixed(hipStream_t s, int batch, size_t n, const double* x, double a, const double* ad, const T* y,
+                      double* z, const int* mask);
+// per item z with mask[z] != 0 (mask optional): n elements from src + z src_stride to
+// dst + z dst_stride
+template <typename T>
+hipError_t masked_copy(hipStream_t s, int batch, size_t n, const T* src, long long src_stride, T* dst,
+                       long long dst_stride, const int* mask);
+
+// p[i] = host_values[i], i < count (kernel arguments, no staging buffer): publishes
+// per-linearisation integers (halos, masks) to device memory read by captured graphs
+hipError_t set_ints(hipStream_t s, int* p, const int* host_values, int count);
 
 }  // namespace slnk

@@ -48,6 +48,31 @@ struct Dft<T, 4> {
 };
 
 template <typename T>
+struct Dft<T, 8> {
+  __device__ static void run(cplx<T>* x, int sign) {
+    // two radix-4 transforms of the even and odd samples, combined with omega_8^k
+    cplx<T> e[4] = {x[0], x[2], x[4], x[6]};
+    cplx<T> o[4] = {x[1], x[3], x[5], x[7]};
+    Dft<T, 4>::run(e, sign);
+    Dft<T, 4>::run(o, sign);
+    const T r = T(0.707106781186547524400844362104849);  // sqrt(1/2)
+    const T sg = sign < 0 ? T(-1) : T(1);
+    const cplx<T> w1 = {r, sg * r}, w3 = {-r, sg * r};
+    const cplx<T> o1 = cmul(o[1], w1);
+    const cplx<T> o2 = sign < 0 ? cmul_mi(o[2]) : cmul_i(o[2]);
+    const cplx<T> o3 = cmul(o[3], w3);
+    x[0] = cadd(e[0], o[0]);
+    x[4] = csub(e[0], o[0]);
+    x[1] = cadd(e[1], o1);
+    x[5] = csub(e[1], o1);
+    x[2] = cadd(e[2], o2);
+    x[6] = csub(e[2], o2);
+    x[3] = cadd(e[3], o3);
+    x[7] = csub(e[3], o3);
+  }
+};
+
+template <typename T>
 struct Dft<T, 3> {
   __device__ static void run(cplx<T>* x, int sign) {
     const T h = T(0.866025403784438646763723170752936);  // sin(2 pi / 3)
@@ -88,7 +113,7 @@ struct Dft<T, 5> {
 // The stage reads every input into registers, synchronises, then writes every output, so it
 // works in place.
 template <typename T, int RAD, int MAXB>
-__device__ void fft_stage(cplx<T>* buf, int n, int p, int nbatch, int bs, const cplx<T>* __restrict__ tw,
+__device__ void fft_stage(cplx<T>* buf, int n, int p, int nbatch, int bs, const cplx<T>* tw,
                           int sign, int tid, int nthr) {
   const int nb = n / RAD;
   const int total = nbatch * nb;
@@ -131,14 +156,23 @@ __device__ void fft_stage(cplx<T>* buf, int n, int p, int nbatch, int bs, const 
   __syncthreads();
 }
 
-// Full transform of nbatch sequences (nbatch * n <= kMaxE * nthr).
+// Copy the twiddle table of a plan into LDS (the caller synchronises before use).
 template <typename T>
-__device__ void fft_lds(cplx<T>* buf, const FFTPlanDev& pl, int nbatch, int bs, int sign, int tid, int nthr) {
+__device__ __forceinline__ void load_twiddles(cplx<T>* tw_lds, const FFTPlanDev& pl, int tid, int nthr) {
   const cplx<T>* tw = static_cast<const cplx<T>*>(pl.tw);
+  for (int q = tid; q < pl.n; q += nthr) tw_lds[q] = tw[q];
+}
+
+// Full transform of nbatch sequences (nbatch * n <= kMaxE * nthr) with the twiddles in LDS.
+template <typename T>
+__device__ void fft_lds(cplx<T>* buf, const cplx<T>* tw, const FFTPlanDev& pl, int nbatch, int bs, int sign, int tid,
+                        int nthr) {
   int p = 1;
   for (int s = 0; s < pl.nstages; ++s) {
     const int r = pl.radix[s];
-    if (r == 4)
+    if (r == 8)
+      fft_stage<T, 8, kMaxE / 8>(buf, pl.n, p, nbatch, bs, tw, sign, tid, nthr);
+    else if (r == 4)
       fft_stage<T, 4, kMaxE / 4>(buf, pl.n, p, nbatch, bs, tw, sign, tid, nthr);
     else if (r == 2)
       fft_stage<T, 2, kMaxE / 2>(buf, pl.n, p, nbatch, bs, tw, sign, tid, nthr);
@@ -153,19 +187,25 @@ __device__ void fft_lds(cplx<T>* buf, const FFTPlanDev& pl, int nbatch, int bs, 
 // ---------------------------------------------------------------------------------------
 // row passes
 // ---------------------------------------------------------------------------------------
+// Up to 8 real fields per batch item; field f of item z is p[f] + z * bstride[f].  Items with
+// active[z / item_div] == 0 are skipped (active optional).
 template <typename T>
 struct RealFields {
   const T* p[8];
-  int count;           // number of real fields
-  long long bstride;   // element offset between batch items
+  long long bstride[8];
+  int count;
+  const int* active;
+  int item_div;
 };
 
 template <typename T>
 struct OutFields {
   T* p[8];
   const T* add[8];
+  long long bstride[8];
   int count;
-  long long bstride;
+  const int* active;
+  int item_div;
 };
 
 // Forward row pass: fields (2q, 2q+1) of 'in' (batch item z) packed as one complex row, FFT along
@@ -174,7 +214,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_row_fwd(RealFields<T> in, cplx<T>* __restrict__ S, int n1, int n2,
                                                  int rpb, FFTPlanDev pl) {
   extern __shared__ unsigned char smem_raw[];
-  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* buf = tw + n2;
   const int nh = n2 / 2 + 1;
   const int bs = n2 + 1;
   const int q = blockIdx.y;
@@ -182,9 +223,10 @@ __global__ void __launch_bounds__(256) k_row_fwd(RealFields<T> in, cplx<T>* __re
   const int r0 = blockIdx.x * rpb;
   const int rows = min(rpb, n1 - r0);
   const int fa = 2 * q, fb = 2 * q + 1;
-  const long long off = (long long)z * in.bstride;
-  const T* A = in.p[fa] + off;
-  const T* B = fb < in.count ? in.p[fb] + off : nullptr;
+  if (in.active && !in.active[z / in.item_div]) return;
+  load_twiddles<T>(tw, pl, threadIdx.x, blockDim.x);
+  const T* A = in.p[fa] + z * in.bstride[fa];
+  const T* B = fb < in.count ? in.p[fb] + z * in.bstride[fb] : nullptr;
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int idx = tid; idx < rows * n2; idx += nthr) {
     const int r = idx / n2, c = idx - r * n2;
@@ -192,7 +234,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(RealFields<T> in, cplx<T>* __re
     buf[r * bs + c] = {A[gi], B ? B[gi] : T(0)};
   }
   __syncthreads();
-  fft_lds<T>(buf, pl, rows, bs, -1, tid, nthr);
+  fft_lds<T>(buf, tw, pl, rows, bs, -1, tid, nthr);
   const size_t sf = size_t(n1) * nh;
   cplx<T>* SA = S + (size_t(z) * in.count + fa) * sf;
   cplx<T>* SB = S + (size_t(z) * in.count + fb) * sf;
@@ -211,7 +253,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_row_inv(const cplx<T>* __restrict__ S, int nspec, OutFields<T> out,
                                                  int n1, int n2, int rpb, FFTPlanDev pl) {
   extern __shared__ unsigned char smem_raw[];
-  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* buf = tw + n2;
   const int nh = n2 / 2 + 1;
   const int bs = n2 + 1;
   const int q = blockIdx.y;
@@ -220,6 +263,8 @@ __global__ void __launch_bounds__(256) k_row_inv(const cplx<T>* __restrict__ S, 
   const int rows = min(rpb, n1 - r0);
   const int fa = 2 * q, fb = 2 * q + 1;
   const bool hasb = fb < out.count;
+  if (out.active && !out.active[z / out.item_div]) return;
+  load_twiddles<T>(tw, pl, threadIdx.x, blockDim.x);
   const size_t sf = size_t(n1) * nh;
   const cplx<T>* SA = S + (size_t(z) * nspec + fa) * sf;
   const cplx<T>* SB = S + (size_t(z) * nspec + fb) * sf;
@@ -242,12 +287,11 @@ __global__ void __launch_bounds__(256) k_row_inv(const cplx<T>* __restrict__ S, 
     buf[r * bs + k] = cadd(a, cmul_i(b));
   }
   __syncthreads();
-  fft_lds<T>(buf, pl, rows, bs, +1, tid, nthr);
-  const long long off = (long long)z * out.bstride;
-  T* OA = out.p[fa] + off;
-  T* OB = hasb ? out.p[fb] + off : nullptr;
-  const T* AA = out.add[fa] ? out.add[fa] + off : nullptr;
-  const T* AB = hasb && out.add[fb] ? out.add[fb] + off : nullptr;
+  fft_lds<T>(buf, tw, pl, rows, bs, +1, tid, nthr);
+  T* OA = out.p[fa] + z * out.bstride[fa];
+  T* OB = hasb ? out.p[fb] + z * out.bstride[fb] : nullptr;
+  const T* AA = out.add[fa] ? out.add[fa] + z * out.bstride[fa] : nullptr;
+  const T* AB = hasb && out.add[fb] ? out.add[fb] + z * out.bstride[fb] : nullptr;
   for (int idx = tid; idx < rows * n2; idx += nthr) {
     const int r = idx / n2, c = idx - r * n2;
     const size_t gi = size_t(r0 + r) * n2 + c;
@@ -266,10 +310,14 @@ enum ColFlags : int { kInK = 1, kOutK = 2 };
 // forward FFT along x1 (unless kInK), op at every (k1, k2), inverse FFT (unless kOutK).
 template <typename T, class Op>
 __global__ void __launch_bounds__(1024) k_col(const cplx<T>* __restrict__ Sin, cplx<T>* __restrict__ Sout, int n1,
-                                              int n2, int B, FFTPlanDev pl, Op op, int flags) {
+                                              int n2, int B, FFTPlanDev pl, Op op, int flags, const int* active,
+                                              int item_div) {
+  if (active && !active[blockIdx.z / item_div]) return;
   extern __shared__ unsigned char smem_raw[];
-  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* buf = tw + n1;
   constexpr int NIN = Op::NIN, NOUT = Op::NOUT;
+  load_twiddles<T>(tw, pl, threadIdx.x, blockDim.x);
   const int nh = n2 / 2 + 1;
   const int bs = n1 + 1;
   const int c0 = blockIdx.x * B;
@@ -284,7 +332,7 @@ __global__ void __launch_bounds__(1024) k_col(const cplx<T>* __restrict__ Sin, c
       buf[(f * B + b) * bs + e] = in[f * sf + size_t(e) * nh + c0 + b];
     }
   __syncthreads();
-  if (!(flags & kInK)) fft_lds<T>(buf, pl, NIN * B, bs, -1, tid, nthr);
+  if (!(flags & kInK)) fft_lds<T>(buf, tw, pl, NIN * B, bs, -1, tid, nthr);
   for (int idx = tid; idx < n1 * cols; idx += nthr) {
     const int b = idx / n1, e = idx - b * n1;
     cplx<T> vin[NIN > 0 ? NIN : 1];
@@ -297,7 +345,7 @@ __global__ void __launch_bounds__(1024) k_col(const cplx<T>* __restrict__ Sin, c
   }
   __syncthreads();
   if (NOUT == 0) return;
-  if (!(flags & kOutK)) fft_lds<T>(buf, pl, NOUT * B, bs, +1, tid, nthr);
+  if (!(flags & kOutK)) fft_lds<T>(buf, tw, pl, NOUT * B, bs, +1, tid, nthr);
   cplx<T>* out = Sout + size_t(z) * NOUT * sf;
   for (int f = 0; f < NOUT; ++f)
     for (int idx = tid; idx < n1 * cols; idx += nthr) {
@@ -440,10 +488,10 @@ struct OpRestrict {
 template <typename T, int NF>
 struct OpProlongCombine {
   static constexpr int NIN = NF, NOUT = NF;
-  const cplx<T>* coarse;   // [NF][nc1][nch] k-space (forward transform, unnormalised)
+  const cplx<T>* coarse;   // [z][NF][nc1][nch] k-space (forward transform, unnormalised)
   int n1, n2, nc1, nc2;
   double inv_n, inv_nc;
-  __device__ void operator()(int k1, int k2, int, int, const cplx<T>* in, cplx<T>* out) const {
+  __device__ void operator()(int k1, int k2, int, int z, const cplx<T>* in, cplx<T>* out) const {
     const int nch = nc2 / 2 + 1;
     const bool low = 4 * abs(k1) < n1 && 4 * k2 < n2;
     const size_t sfc = size_t(nc1) * nch;
@@ -451,7 +499,7 @@ struct OpProlongCombine {
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       if (low)
-        out[f] = cscale(coarse[f * sfc + size_t(e) * nch + k2], T(inv_nc));
+        out[f] = cscale(coarse[(size_t(z) * NF + f) * sfc + size_t(e) * nch + k2], T(inv_nc));
       else
         out[f] = cscale(in[f], T(inv_n));
     }
@@ -463,10 +511,11 @@ struct OpProlongCombine {
 // ---------------------------------------------------------------------------------------
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// about 8 elements per thread (one radix-8 butterfly per stage), at least one wavefront
 template <typename T>
 void row_config(int n2, int& nthr, int& rpb) {
-  nthr = std::min(256, std::max(64, round_up(n2 / 4, 64)));
-  rpb = std::max(1, (nthr * 4) / n2);
+  nthr = std::min(256, std::max(64, round_up(n2 / 8, 64)));
+  rpb = std::max(1, (nthr * 8) / n2);
   while (rpb * n2 > nthr * kMaxE) --rpb;
 }
 
@@ -475,7 +524,7 @@ hipError_t launch_row_fwd(hipStream_t s, const SpecGrid<T>& g, RealFields<T> in,
   int nthr, rpb;
   row_config<T>(g.n2, nthr, rpb);
   dim3 grid((g.n1 + rpb - 1) / rpb, (in.count + 1) / 2, batch);
-  size_t lds = size_t(rpb) * (g.n2 + 1) * sizeof(cplx<T>);
+  size_t lds = (size_t(rpb) * (g.n2 + 1) + g.n2) * sizeof(cplx<T>);
   hipLaunchKernelGGL(k_row_fwd<T>, grid, dim3(nthr), lds, s, in, S, g.n1, g.n2, rpb, g.row);
   return hipGetLastError();
 }
@@ -486,14 +535,14 @@ hipError_t launch_row_inv(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* S,
   int nthr, rpb;
   row_config<T>(g.n2, nthr, rpb);
   dim3 grid((g.n1 + rpb - 1) / rpb, (out.count + 1) / 2, batch);
-  size_t lds = size_t(rpb) * (g.n2 + 1) * sizeof(cplx<T>);
+  size_t lds = (size_t(rpb) * (g.n2 + 1) + g.n2) * sizeof(cplx<T>);
   hipLaunchKernelGGL(k_row_inv<T>, grid, dim3(nthr), lds, s, S, nspec, out, g.n1, g.n2, rpb, g.row);
   return hipGetLastError();
 }
 
 template <typename T, class Op>
 hipError_t launch_col(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* Sin, cplx<T>* Sout, Op op, int flags,
-                      int batch) {
+                      int batch, const int* active = nullptr, int item_div = 1) {
   constexpr int nmax = Op::NIN > Op::NOUT ? Op::NIN : Op::NOUT;
   const int nh = g.nh();
   const int col_bytes = (g.n1 + 1) * int(sizeof(cplx<T>)) * nmax;
@@ -502,11 +551,12 @@ hipError_t launch_col(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* Sin, c
   int B = std::max(1, std::min(std::min(16, std::max(1, nh / 64)), kLdsBudget / col_bytes));
   while (B > 1 && nmax * B * g.n1 > 1024 * kMaxE) --B;
   const int elems = nmax * B * g.n1;
-  int nthr = std::min(1024, std::max(64, round_up((elems + 3) / 4, 64)));
+  int nthr = std::min(1024, std::max(64, round_up((elems + 7) / 8, 64)));
   while (nthr < 1024 && elems > nthr * kMaxE) nthr += 64;
   dim3 grid((nh + B - 1) / B, 1, batch);
-  size_t lds = size_t(B) * col_bytes;
-  hipLaunchKernelGGL((k_col<T, Op>), grid, dim3(nthr), lds, s, Sin, Sout, g.n1, g.n2, B, g.col, op, flags);
+  size_t lds = size_t(B) * col_bytes + size_t(g.n1) * sizeof(cplx<T>);
+  hipLaunchKernelGGL((k_col<T, Op>), grid, dim3(nthr), lds, s, Sin, Sout, g.n1, g.n2, B, g.col, op, flags, active,
+                     item_div);
   return hipGetLastError();
 }
 
@@ -516,130 +566,139 @@ hipError_t launch_col(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* Sin, c
     if (_e != hipSuccess) return _e; \
   } while (0)
 
+// fields f < nf of a per-item block of nf consecutive fields
+template <typename T, class FL>
+void set_fields(FL& fl, int nf, T* base, size_t F, const int* active) {
+  fl.count = nf;
+  fl.active = active;
+  fl.item_div = 1;
+  for (int f = 0; f < nf; ++f) {
+    fl.p[f] = base + f * F;
+    fl.bstride[f] = (long long)(nf * F);
+  }
+}
+
 }  // namespace
 
 template <typename T>
-hipError_t spec_scale(hipStream_t s, const SpecGrid<T>& g, SymbolParams sym, int nf, const T* in, T* out,
-                      const T* add, cplx<T>* S1, cplx<T>* S2) {
+hipError_t spec_scale(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, SymbolParams sym, int nf,
+                      const T* in, T* out, const T* add, cplx<T>* S1, cplx<T>* S2) {
   const size_t F = g.field();
   RealFields<T> rin{};
+  set_fields(rin, nf, const_cast<T*>(in), F, active);
   OutFields<T> rout{};
-  rin.count = nf;
-  rout.count = nf;
-  for (int f = 0; f < nf; ++f) {
-    rin.p[f] = in + f * F;
-    rout.p[f] = out + f * F;
-    rout.add[f] = add ? add + f * F : nullptr;
-  }
-  RET_IF(launch_row_fwd<T>(s, g, rin, 1, S1));
+  set_fields(rout, nf, out, F, active);
+  for (int f = 0; f < nf; ++f) rout.add[f] = add ? add + f * F : nullptr;
+  RET_IF(launch_row_fwd<T>(s, g, rin, batch, S1));
   const double inv_n = 1.0 / double(F);
   if (nf == 1) {
     OpScale<T, 1> op{sym, g.n1, g.n2, inv_n};
-    RET_IF(launch_col<T>(s, g, S1, S2, op, 0, 1));
+    RET_IF(launch_col<T>(s, g, S1, S2, op, 0, batch, active));
   } else {
     OpScale<T, 2> op{sym, g.n1, g.n2, inv_n};
-    RET_IF(launch_col<T>(s, g, S1, S2, op, 0, 1));
+    RET_IF(launch_col<T>(s, g, S1, S2, op, 0, batch, active));
   }
-  return launch_row_inv<T>(s, g, S2, nf, rout, 1);
+  return launch_row_inv<T>(s, g, S2, nf, rout, batch);
 }
 
 template <typename T>
-hipError_t spec_grad(hipStream_t s, const SpecGrid<T>& g, int batch, const T* m, T* gm, cplx<T>* S1, cplx<T>* S2) {
+hipError_t spec_grad(hipStream_t s, const SpecGrid<T>& g, int count, const T* m, T* gm, cplx<T>* S1, cplx<T>* S2) {
   const size_t F = g.field();
   RealFields<T> rin{};
   rin.count = 1;
   rin.p[0] = m;
-  rin.bstride = (long long)F;
-  RET_IF(launch_row_fwd<T>(s, g, rin, batch, S1));
+  rin.bstride[0] = (long long)F;
+  rin.item_div = 1;
+  RET_IF(launch_row_fwd<T>(s, g, rin, count, S1));
   OpGrad<T> op{g.n1, g.n2, 1.0 / double(F)};
-  RET_IF(launch_col<T>(s, g, S1, S2, op, 0, batch));
+  RET_IF(launch_col<T>(s, g, S1, S2, op, 0, count));
   OutFields<T> rout{};
   rout.count = 2;
   rout.p[0] = gm;
   rout.p[1] = gm + F;
-  rout.bstride = (long long)(2 * F);
-  return launch_row_inv<T>(s, g, S2, 2, rout, batch);
+  rout.bstride[0] = rout.bstride[1] = (long long)(2 * F);
+  rout.item_div = 1;
+  return launch_row_inv<T>(s, g, S2, 2, rout, count);
 }
 
 template <typename T>
-hipError_t spec_trace_prep(hipStream_t s, const SpecGrid<T>& g, const T* v, T* cv, T* divv, T* cdiv, cplx<T>* S1,
-                           cplx<T>* S2) {
+hipError_t spec_trace_prep(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, const T* v, T* cv,
+                           T* divv, T* cdiv, cplx<T>* S1, cplx<T>* S2) {
   const size_t F = g.field();
   RealFields<T> rin{};
-  rin.count = 2;
-  rin.p[0] = v;
-  rin.p[1] = v + F;
-  RET_IF(launch_row_fwd<T>(s, g, rin, 1, S1));
+  set_fields(rin, 2, const_cast<T*>(v), F, active);
+  RET_IF(launch_row_fwd<T>(s, g, rin, batch, S1));
   OpTracePrep<T> op{g.n1, g.n2, 1.0 / double(F)};
-  RET_IF(launch_col<T>(s, g, S1, S2, op, 0, 1));
+  RET_IF(launch_col<T>(s, g, S1, S2, op, 0, batch, active));
   OutFields<T> rout{};
   rout.count = 4;
+  rout.active = active;
+  rout.item_div = 1;
   rout.p[0] = cv;
   rout.p[1] = cv + F;
   rout.p[2] = divv;
   rout.p[3] = cdiv;
-  return launch_row_inv<T>(s, g, S2, 4, rout, 1);
+  rout.bstride[0] = rout.bstride[1] = (long long)(2 * F);
+  rout.bstride[2] = rout.bstride[3] = (long long)F;
+  return launch_row_inv<T>(s, g, S2, 4, rout, batch);
 }
 
 template <typename T>
-hipError_t spec_restrict(hipStream_t s, const SpecGrid<T>& g, const SpecGrid<T>& gc, int nf, const T* in, T* out_c,
-                         cplx<T>* keep_fine, cplx<T>* S1, cplx<T>* Sc1, cplx<T>* Sc2) {
+hipError_t spec_restrict(hipStream_t s, const SpecGrid<T>& g, const SpecGrid<T>& gc, int batch, const int* active,
+                         int nf, const T* in, T* out_c, cplx<T>* keep_fine, cplx<T>* S1, cplx<T>* Sc1, cplx<T>* Sc2) {
   const size_t F = g.field(), Fc = gc.field();
   RealFields<T> rin{};
-  rin.count = nf;
-  for (int f = 0; f < nf; ++f) rin.p[f] = in + f * F;
-  RET_IF(launch_row_fwd<T>(s, g, rin, 1, S1));
+  set_fields(rin, nf, const_cast<T*>(in), F, active);
+  RET_IF(launch_row_fwd<T>(s, g, rin, batch, S1));
   const double inv_n = 1.0 / double(F);
   // the fine column pass only writes the coarse k-space (and keeps the fine spectrum if asked)
   if (nf == 1) {
     OpRestrict<T, 1> op{Sc1, g.n1, g.n2, gc.n1, gc.n2, inv_n};
-    RET_IF(launch_col<T>(s, g, S1, keep_fine ? keep_fine : S1, op, kOutK, 1));
-    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 1>{}, kInK, 1));
+    RET_IF(launch_col<T>(s, g, S1, keep_fine ? keep_fine : S1, op, kOutK, batch, active));
+    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 1>{}, kInK, batch, active));
   } else {
     OpRestrict<T, 2> op{Sc1, g.n1, g.n2, gc.n1, gc.n2, inv_n};
-    RET_IF(launch_col<T>(s, g, S1, keep_fine ? keep_fine : S1, op, kOutK, 1));
-    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 2>{}, kInK, 1));
+    RET_IF(launch_col<T>(s, g, S1, keep_fine ? keep_fine : S1, op, kOutK, batch, active));
+    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 2>{}, kInK, batch, active));
   }
   OutFields<T> rout{};
-  rout.count = nf;
-  for (int f = 0; f < nf; ++f) rout.p[f] = out_c + f * Fc;
-  return launch_row_inv<T>(s, gc, Sc2, nf, rout, 1);
+  set_fields(rout, nf, out_c, Fc, active);
+  return launch_row_inv<T>(s, gc, Sc2, nf, rout, batch);
 }
 
 template <typename T>
-hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecGrid<T>& gc, int nf,
-                                const cplx<T>* fine_k, const T* zc, T* out, cplx<T>* S1, cplx<T>* Sc1,
-                                cplx<T>* Sc2) {
+hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecGrid<T>& gc, int batch,
+                                const int* active, int nf, const cplx<T>* fine_k, const T* zc, T* out, cplx<T>* S1,
+                                cplx<T>* Sc1, cplx<T>* Sc2) {
   const size_t F = g.field(), Fc = gc.field();
   RealFields<T> rin{};
-  rin.count = nf;
-  for (int f = 0; f < nf; ++f) rin.p[f] = zc + f * Fc;
-  RET_IF(launch_row_fwd<T>(s, gc, rin, 1, Sc1));
+  set_fields(rin, nf, const_cast<T*>(zc), Fc, active);
+  RET_IF(launch_row_fwd<T>(s, gc, rin, batch, Sc1));
   if (nf == 1) {
-    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 1>{}, kOutK, 1));
+    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 1>{}, kOutK, batch, active));
     OpProlongCombine<T, 1> op{Sc2, g.n1, g.n2, gc.n1, gc.n2, 1.0 / double(F), 1.0 / double(Fc)};
-    RET_IF(launch_col<T>(s, g, fine_k, S1, op, kInK, 1));
+    RET_IF(launch_col<T>(s, g, fine_k, S1, op, kInK, batch, active));
   } else {
-    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 2>{}, kOutK, 1));
+    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 2>{}, kOutK, batch, active));
     OpProlongCombine<T, 2> op{Sc2, g.n1, g.n2, gc.n1, gc.n2, 1.0 / double(F), 1.0 / double(Fc)};
-    RET_IF(launch_col<T>(s, g, fine_k, S1, op, kInK, 1));
+    RET_IF(launch_col<T>(s, g, fine_k, S1, op, kInK, batch, active));
   }
   OutFields<T> rout{};
-  rout.count = nf;
-  for (int f = 0; f < nf; ++f) rout.p[f] = out + f * F;
-  return launch_row_inv<T>(s, g, S1, nf, rout, 1);
+  set_fields(rout, nf, out, F, active);
+  return launch_row_inv<T>(s, g, S1, nf, rout, batch);
 }
 
 #define INST(T)                                                                                                 \
-  template hipError_t spec_scale<T>(hipStream_t, const SpecGrid<T>&, SymbolParams, int, const T*, T*, const T*, \
-                                    cplx<T>*, cplx<T>*);                                                        \
+  template hipError_t spec_scale<T>(hipStream_t, const SpecGrid<T>&, int, const int*, SymbolParams, int, const T*, \
+                                    T*, const T*, cplx<T>*, cplx<T>*);                                          \
   template hipError_t spec_grad<T>(hipStream_t, const SpecGrid<T>&, int, const T*, T*, cplx<T>*, cplx<T>*);     \
-  template hipError_t spec_trace_prep<T>(hipStream_t, const SpecGrid<T>&, const T*, T*, T*, T*, cplx<T>*,      \
-                                         cplx<T>*);                                                             \
-  template hipError_t spec_restrict<T>(hipStream_t, const SpecGrid<T>&, const SpecGrid<T>&, int, const T*, T*,  \
-                                       cplx<T>*, cplx<T>*, cplx<T>*, cplx<T>*);                                 \
+  template hipError_t spec_trace_prep<T>(hipStream_t, const SpecGrid<T>&, int, const int*, const T*, T*, T*, T*, \
+                                         cplx<T>*, cplx<T>*);                                                   \
+  template hipError_t spec_restrict<T>(hipStream_t, const SpecGrid<T>&, const SpecGrid<T>&, int, const int*, int, \
+                                       const T*, T*, cplx<T>*, cplx<T>*, cplx<T>*, cplx<T>*);                   \
   template hipError_t spec_prolong_combine<T>(hipStream_t, const SpecGrid<T>&, const SpecGrid<T>&, int,         \
-                                              const cplx<T>*, const T*, T*, cplx<T>*, cplx<T>*, cplx<T>*);
+                                              const int*, int, const cplx<T>*, const T*, T*, cplx<T>*, cplx<T>*, \
+                                              cplx<T>*);
 INST(float)
 INST(double)
 #undef INST

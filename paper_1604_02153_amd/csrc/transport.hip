@@ -18,15 +18,20 @@ constexpr int kTile = 16;
 
 template <typename T>
 struct FilterTaps;
-// |z|^(K+1) * 2 sqrt(3) / (1 - |z|) < 4e-9 (FP32) and < 2e-16 (FP64)
+// Truncation error of the filter: 2 sqrt(3) |z|^(K+1) / (1 - |z|) relative to max |f|:
+// 4.7e-8 for K = 13 (below FP32 rounding) and 1.2e-16 for K = 28 (FP64).  R: outputs per thread
+// of the register-blocked filter passes.
 template <>
 struct FilterTaps<float> {
-  static constexpr int K = 15;
+  static constexpr int K = 13;
+  static constexpr int R = 8;
 };
 template <>
 struct FilterTaps<double> {
   static constexpr int K = 28;
+  static constexpr int R = 4;
 };
+constexpr int kMaxChunks = 12;  // footprint side P <= 16 * kMaxChunks
 
 __constant__ double c_taps_d[FilterTaps<double>::K + 1];
 __constant__ float c_taps_f[FilterTaps<float>::K + 1];
@@ -53,6 +58,20 @@ hipError_t upload_taps() {
   e = hipMemcpyToSymbol(HIP_SYMBOL(c_taps_f), tf, sizeof(tf));
   if (e == hipSuccess) g_taps_ready = true;
   return e;
+}
+
+// Tile of this block.  Workgroups go to the 8 XCDs of the chip round-robin in launch order, so
+// the blocks of one XCD are given a contiguous run of tiles (row-major): tile halos shared by
+// neighbouring tiles are then fetched once into that XCD's L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ void xcd_tile(int& ty, int& tx) {
+  const int nb = gridDim.x * gridDim.y;
+  const int b = blockIdx.y * gridDim.x + blockIdx.x;
+  const int x = b % kXcds, local = b / kXcds;
+  const int base = nb / kXcds, rem = nb % kXcds;
+  const int t = x * base + min(x, rem) + local;
+  ty = t / gridDim.x;
+  tx = t - ty * gridDim.x;
 }
 
 template <typename T>
@@ -88,7 +107,8 @@ __device__ T interp_global(const T* __restrict__ c, int n1, int n2, T s1, T s2) 
   return acc;
 }
 
-// FP64 block reduction of two values: (sum, max).  Writes partial[2 * block + {0, 1}].
+// FP64 block reduction of two values: (sum, max).  Writes partial[2 * block + {0, 1}] (block
+// within the item's x-y grid; the caller offsets 'partial' by item).
 __device__ void block_sum_max(double s, double m, double* partial) {
   __shared__ double rs[16], rm[16];
   for (int off = 32; off > 0; off >>= 1) {
@@ -117,6 +137,28 @@ __device__ void block_sum_max(double s, double m, double* partial) {
 // ------------------------------------------------------------------------------------------
 // fused prefilter + gather step
 // ------------------------------------------------------------------------------------------
+// The arguments as seen by item z: every pointer advanced by z times its stride.
+template <typename T>
+__device__ __forceinline__ StepArgs<T> item_view(const StepArgs<T>& b, int z) {
+  StepArgs<T> a = b;
+  auto adv = [z](auto* p, long long st) { return p ? p + z * st : p; };
+  a.src = adv(b.src, b.st_src);
+  a.dst = adv(b.dst, b.st_dst);
+  a.d1 = adv(b.d1, b.st_d);
+  a.gamma = adv(b.gamma, b.st_gamma);
+  a.aux0 = adv(b.aux0, b.st_aux0);
+  a.aux1 = adv(b.aux1, b.st_aux1);
+  a.gm_new = adv(b.gm_new, b.st_gm);
+  a.gm_old = adv(b.gm_old, b.st_gm);
+  a.acc = adv(b.acc, b.st_acc);
+  a.vt = adv(b.vt, b.st_vt);
+  a.addf = adv(b.addf, b.st_addf);
+  a.out2 = adv(b.out2, b.st_out2);
+  a.coef = adv(b.coef, b.st_coef);
+  a.halo_dev = b.halo_dev ? b.halo_dev + z : nullptr;
+  a.partial = b.partial ? b.partial + size_t(z) * 2 * gridDim.x * gridDim.y : nullptr;
+  return a;
+}
 template <typename T, int KIND, bool FIRST>
 __device__ __forceinline__ T load_src(const StepArgs<T>& a, size_t gi) {
   if constexpr (FIRST && KIND == int(StepKind::Adjoint)) {
@@ -135,41 +177,71 @@ __device__ __forceinline__ T load_src(const StepArgs<T>& a, size_t gi) {
 // at global node (y0 - lo, x0 - lo) and is left at LDS offset 0 of 'A'.  The step kernel uses
 // lo = D + 1, G = 16 + 2D + 3 (the stencil footprint of displacements |d| <= D); the
 // coefficient-only kernel uses lo = 0, G = 16.
+// LDS layout: A = P x P staged values (later the G x G coefficients), R words of slack, then
+// B1 = (P + R) x G row-filtered values.  Each filter pass gives a thread R consecutive outputs
+// from a register window of R + 2K inputs; consecutive threads take consecutive rows (row pass)
+// or columns (column pass), so the window loads do not conflict across LDS banks.
 template <typename T, int KIND, bool FIRST>
 __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, int y0, int x0, int lo, int G) {
   constexpr int K = FilterTaps<T>::K;
+  constexpr int R = FilterTaps<T>::R;
   const int P = G + 2 * K;
-  T* B1 = A + P * P;  // rows P x cols G
-  T* C = A;           // rows G x cols G (A is dead once B1 is built)
+  T* B1 = A + P * P + R;
+  T* C = A;
   const int n1 = a.n1, n2 = a.n2;
   const int ry = y0 - lo - K, rx = x0 - lo - K;
-  const int tid = threadIdx.y * kTile + threadIdx.x;
-  constexpr int nthr = kTile * kTile;
-  // 1. stage the transported field over the footprint (periodic wrap)
-  for (int idx = tid; idx < P * P; idx += nthr) {
-    const int r = idx / P, c = idx - r * P;
-    const size_t gi = size_t(wrap_index(ry + r, n1)) * n2 + wrap_index(rx + c, n2);
-    A[idx] = load_src<T, KIND, FIRST>(a, gi);
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tid = ty * kTile + tx;
+  // 1. stage (periodic wrap), rows ty + 16 i, columns tx + 16 k
+  int colw[kMaxChunks];
+#pragma unroll
+  for (int k = 0; k < kMaxChunks; ++k) {
+    const int c = tx + kTile * k;
+    colw[k] = c < P ? wrap_index(rx + c, n2) : 0;
+  }
+  for (int r = ty; r < P; r += kTile) {
+    const size_t rowoff = size_t(wrap_index(ry + r, n1)) * n2;
+    T* dst = A + r * P;
+#pragma unroll
+    for (int k = 0; k < kMaxChunks; ++k) {
+      const int c = tx + kTile * k;
+      if (c < P) dst[c] = load_src<T, KIND, FIRST>(a, rowoff + colw[k]);
+    }
   }
   __syncthreads();
-  // 2. prefilter along x2
-  for (int idx = tid; idx < P * G; idx += nthr) {
-    const int r = idx / G, c = idx - r * G;
-    const T* row = A + r * P + c + K;
-    T s = tap<T>(0) * row[0];
-#pragma unroll 4
-    for (int t = 1; t <= K; ++t) s += tap<T>(t) * (row[-t] + row[t]);
-    B1[idx] = s;
+  const int segs = (G + R - 1) / R;
+  // 2. prefilter along x2: thread -> (row r, segment q), outputs at columns q R .. q R + R - 1
+  for (int sidx = tid; sidx < P * segs; sidx += kTile * kTile) {
+    const int q = sidx / P, r = sidx - q * P;
+    const T* src = A + r * P + q * R;
+    T x[R + 2 * K];
+#pragma unroll
+    for (int i = 0; i < R + 2 * K; ++i) x[i] = src[i];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      T acc = tap<T>(0) * x[j + K];
+#pragma unroll
+      for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[j + K - t] + x[j + K + t]);
+      const int c = q * R + j;
+      if (c < G) B1[r * G + c] = acc;
+    }
   }
   __syncthreads();
-  // 3. prefilter along x1
-  for (int idx = tid; idx < G * G; idx += nthr) {
-    const int r = idx / G, c = idx - r * G;
-    const T* col = B1 + (r + K) * G + c;
-    T s = tap<T>(0) * col[0];
-#pragma unroll 4
-    for (int t = 1; t <= K; ++t) s += tap<T>(t) * (col[-t * G] + col[t * G]);
-    C[idx] = s;
+  // 3. prefilter along x1: thread -> (column c, segment q), outputs at rows q R .. q R + R - 1
+  for (int sidx = tid; sidx < G * segs; sidx += kTile * kTile) {
+    const int q = sidx / G, c = sidx - q * G;
+    const T* src = B1 + (q * R) * G + c;
+    T x[R + 2 * K];
+#pragma unroll
+    for (int i = 0; i < R + 2 * K; ++i) x[i] = src[i * G];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      T acc = tap<T>(0) * x[j + K];
+#pragma unroll
+      for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[j + K - t] + x[j + K + t]);
+      const int r = q * R + j;
+      if (r < G) C[r * G + c] = acc;
+    }
   }
   __syncthreads();
 }
@@ -177,32 +249,76 @@ __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, i
 // Coefficient-only pass (used when the departure footprint exceeds the LDS budget): writes the
 // B-spline coefficients of the step's source field to a.coef.
 template <typename T, int KIND, bool FIRST>
-__global__ void __launch_bounds__(256) k_prefilter(StepArgs<T> a) {
+__global__ void __launch_bounds__(256) k_prefilter(StepArgs<T> args) {
+  if (args.active && !args.active[blockIdx.z]) return;
+  const StepArgs<T> a = item_view(args, blockIdx.z);
   extern __shared__ unsigned char smem_raw[];
   T* A = reinterpret_cast<T*>(smem_raw);
-  const int y0 = blockIdx.y * kTile, x0 = blockIdx.x * kTile;
+  int by, bx;
+  xcd_tile(by, bx);
+  const int y0 = by * kTile, x0 = bx * kTile;
   stage_coefficients<T, KIND, FIRST>(a, A, y0, x0, 0, kTile);
   const int i1 = y0 + threadIdx.y, i2 = x0 + threadIdx.x;
   if (i1 < a.n1 && i2 < a.n2) a.coef[size_t(i1) * a.n2 + i2] = A[threadIdx.y * kTile + threadIdx.x];
 }
 
 template <typename T, int KIND, bool FIRST, bool GLOBAL>
-__global__ void __launch_bounds__(256) k_sl_step(StepArgs<T> a) {
+__global__ void __launch_bounds__(256) k_sl_step(StepArgs<T> args) {
+  if (args.active && !args.active[blockIdx.z]) return;
+  const StepArgs<T> a = item_view(args, blockIdx.z);
   extern __shared__ unsigned char smem_raw[];
   T* C = reinterpret_cast<T*>(smem_raw);
-  const int D = a.halo;
+  constexpr bool kAdj = KIND == int(StepKind::Adjoint);
+  constexpr bool kIncS = KIND == int(StepKind::IncState);
+  constexpr bool kIncA = KIND == int(StepKind::IncAdjoint);
+  // the footprint actually staged: the device-side bound when given (never above the bound the
+  // LDS was sized for)
+  const int D = a.halo_dev ? min(*a.halo_dev, a.halo) : a.halo;
   const int G = kTile + 2 * D + 3;
   const int n1 = a.n1, n2 = a.n2;
-  const int y0 = blockIdx.y * kTile, x0 = blockIdx.x * kTile;
+  const size_t F = size_t(n1) * n2;
+  int by, bx;
+  xcd_tile(by, bx);
+  const int y0 = by * kTile, x0 = bx * kTile;
+  const int i1 = y0 + threadIdx.y, i2 = x0 + threadIdx.x;
+  const bool inside = i1 < n1 && i2 < n2;
+  const size_t gi = inside ? size_t(i1) * n2 + i2 : 0;
+  // per-node operands, loaded before the staging so that their latency overlaps it
+  const T dd1 = a.d1[gi], dd2 = a.d1[gi + F];
+  T gam = T(0), gn1 = T(0), gn2 = T(0), ac1 = T(0), ac2 = T(0), ex0 = T(0), ex1 = T(0), ex2 = T(0);
+  if constexpr (kAdj || kIncA) gam = a.gamma[gi];
+  if constexpr (kAdj || kIncS || kIncA) {
+    gn1 = a.gm_new[gi];
+    gn2 = a.gm_new[gi + F];
+  }
+  if constexpr ((kAdj && !FIRST) || kIncA) {
+    ac1 = a.acc[gi];
+    ac2 = a.acc[gi + F];
+  }
+  if constexpr (kIncS) {
+    ex1 = a.vt[gi];
+    ex2 = a.vt[gi + F];
+  }
+  if constexpr (kAdj && FIRST) {
+    ex0 = a.aux0[gi] - a.aux1[gi];  // lambda(1) at the node
+    ac1 = a.gm_old[gi];
+    ac2 = a.gm_old[gi + F];
+  }
+  if constexpr (KIND == int(StepKind::State)) {
+    if (a.last) ex0 = a.aux0[gi];
+  }
+  if constexpr (kAdj) {
+    if (a.last) {
+      ex1 = a.addf[gi];
+      ex2 = a.addf[gi + F];
+    }
+  }
   if constexpr (!GLOBAL) stage_coefficients<T, KIND, FIRST>(a, C, y0, x0, D + 1, G);
 
-  // 4. gather at the departure point of this thread's node and update
-  const int i1 = y0 + threadIdx.y, i2 = x0 + threadIdx.x;
+  // gather at the departure point of this thread's node and update
   double red_s = 0.0, red_m = 0.0;
-  if (i1 < n1 && i2 < n2) {
-    const size_t gi = size_t(i1) * n2 + i2;
-    const size_t F = size_t(n1) * n2;
-    const T s1 = T(i1) + a.d1[gi], s2 = T(i2) + a.d2[gi];
+  if (inside) {
+    const T s1 = T(i1) + dd1, s2 = T(i2) + dd2;
     T u = T(0);
     if constexpr (GLOBAL) {
       u = interp_global(a.coef, n1, n2, s1, s2);
@@ -226,24 +342,23 @@ __global__ void __launch_bounds__(256) k_sl_step(StepArgs<T> a) {
     if constexpr (KIND == int(StepKind::State)) {
       a.dst[gi] = u;
       if (a.last) {
-        const double r = double(u) - double(a.aux0[gi]);
+        const double r = double(u) - double(ex0);
         red_s = r * r;
       }
-    } else if constexpr (KIND == int(StepKind::Adjoint)) {
-      const T lam = a.gamma[gi] * u;
+    } else if constexpr (kAdj) {
+      const T lam = gam * u;
       if (a.dst) a.dst[gi] = lam;
-      T b1 = T(a.w_new) * lam * a.gm_new[gi];
-      T b2 = T(a.w_new) * lam * a.gm_new[gi + F];
+      T b1 = T(a.w_new) * lam * gn1;
+      T b2 = T(a.w_new) * lam * gn2;
       if constexpr (FIRST) {
-        const T l1v = a.aux0[gi] - a.aux1[gi];
-        b1 += T(a.w_old) * l1v * a.gm_old[gi];
-        b2 += T(a.w_old) * l1v * a.gm_old[gi + F];
+        b1 += T(a.w_old) * ex0 * ac1;
+        b2 += T(a.w_old) * ex0 * ac2;
       } else {
-        b1 += a.acc[gi];
-        b2 += a.acc[gi + F];
+        b1 += ac1;
+        b2 += ac2;
       }
       if (a.last) {
-        const T g1 = a.addf[gi] + b1, g2 = a.addf[gi + F] + b2;
+        const T g1 = ex1 + b1, g2 = ex2 + b2;
         a.out2[gi] = g1;
         a.out2[gi + F] = g2;
         red_s = double(g1) * double(g1) + double(g2) * double(g2);
@@ -252,21 +367,21 @@ __global__ void __launch_bounds__(256) k_sl_step(StepArgs<T> a) {
         a.acc[gi] = b1;
         a.acc[gi + F] = b2;
       }
-    } else if constexpr (KIND == int(StepKind::IncState)) {
-      const T fnew = -(a.vt[gi] * a.gm_new[gi] + a.vt[gi + F] * a.gm_new[gi + F]);
+    } else if constexpr (kIncS) {
+      const T fnew = -(ex1 * gn1 + ex2 * gn2);
       if (!a.last) {
         a.dst[gi] = u + T(a.ht) * fnew;  // q^j = m~^j + (ht/2) f^j
       } else {
         const T lt = -(u + T(0.5 * a.ht) * fnew);  // lambda~(1) = -m~(1)
         a.dst[gi] = lt;
-        a.acc[gi] = T(a.w_new) * lt * a.gm_new[gi];
-        a.acc[gi + F] = T(a.w_new) * lt * a.gm_new[gi + F];
+        a.acc[gi] = T(a.w_new) * lt * gn1;
+        a.acc[gi + F] = T(a.w_new) * lt * gn2;
       }
     } else {  // IncAdjoint
-      const T lt = a.gamma[gi] * u;
+      const T lt = gam * u;
       if (a.dst) a.dst[gi] = lt;
-      a.acc[gi] += T(a.w_new) * lt * a.gm_new[gi];
-      a.acc[gi + F] += T(a.w_new) * lt * a.gm_new[gi + F];
+      a.acc[gi] = ac1 + T(a.w_new) * lt * gn1;
+      a.acc[gi + F] = ac2 + T(a.w_new) * lt * gn2;
     }
   }
   if (a.partial && a.last) block_sum_max(red_s, red_m, a.partial);
@@ -275,7 +390,8 @@ __global__ void __launch_bounds__(256) k_sl_step(StepArgs<T> a) {
 template <typename T>
 size_t step_lds_bytes(int G) {
   const int P = G + 2 * FilterTaps<T>::K;
-  return size_t(P * P + P * G) * sizeof(T);
+  const int R = FilterTaps<T>::R;
+  return size_t(P * P + R + (P + R) * G) * sizeof(T);
 }
 
 size_t g_lds_limit = 0;
@@ -297,14 +413,26 @@ hipError_t lds_limit(size_t* out) {
 // Heun trace of both characteristics + adjoint factor
 // ------------------------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) k_trace(int n1, int n2, T ht, const T* __restrict__ v,
-                                               const T* __restrict__ cv, const T* __restrict__ divv,
-                                               const T* __restrict__ cdiv, T* __restrict__ df,
-                                               T* __restrict__ da, T* __restrict__ gamma, double* partial) {
-  const int i1 = blockIdx.y * kTile + threadIdx.y, i2 = blockIdx.x * kTile + threadIdx.x;
+__global__ void __launch_bounds__(256) k_trace(int n1, int n2, const int* active, T ht, const T* __restrict__ vb,
+                                               const T* __restrict__ cvb, const T* __restrict__ divvb,
+                                               const T* __restrict__ cdivb, T* __restrict__ dfb,
+                                               T* __restrict__ dab, T* __restrict__ gammab, double* partialb) {
+  const int z = blockIdx.z;
+  if (active && !active[z]) return;
+  const size_t F = size_t(n1) * n2;
+  const T* v = vb + 2 * F * z;
+  const T* cv = cvb + 2 * F * z;
+  const T* divv = divvb + F * z;
+  const T* cdiv = cdivb + F * z;
+  T* df = dfb + 2 * F * z;
+  T* da = dab + 2 * F * z;
+  T* gamma = gammab + F * z;
+  double* partial = partialb ? partialb + size_t(z) * 2 * gridDim.x * gridDim.y : nullptr;
+  int by, bx;
+  xcd_tile(by, bx);
+  const int i1 = by * kTile + threadIdx.y, i2 = bx * kTile + threadIdx.x;
   double red_s = 0.0, red_m = 0.0;
   if (i1 < n1 && i2 < n2) {
-    const size_t F = size_t(n1) * n2;
     const size_t gi = size_t(i1) * n2 + i2;
     // velocity in cells per unit time
     const T c1 = T(n1) / T(2.0 * 3.14159265358979323846), c2 = T(n2) / T(2.0 * 3.14159265358979323846);
@@ -340,7 +468,11 @@ int sl_step_max_halo() {
   size_t lim = 0;
   if (lds_limit(&lim) != hipSuccess) return -1;
   int D = -1;
-  while (D < 64 && step_lds_bytes<T>(kTile + 2 * (D + 1) + 3) <= lim) ++D;
+  auto fits = [&](int d) {
+    const int G = kTile + 2 * d + 3;
+    return step_lds_bytes<T>(G) <= lim && G + 2 * FilterTaps<T>::K <= kTile * kMaxChunks;
+  };
+  while (D < 64 && fits(D + 1)) ++D;
   return D;
 }
 
@@ -349,9 +481,13 @@ hipError_t launch_step(hipStream_t s, const StepArgs<T>& a, dim3 grid, dim3 bloc
   if (fused) {
     const size_t lds = step_lds_bytes<T>(kTile + 2 * a.halo + 3);
     auto kfn = k_sl_step<T, KIND, FIRST, false>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return e;
+    static size_t attr_set = 0;  // largest dynamic LDS size already allowed for this kernel
+    if (lds > attr_set) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      if (e != hipSuccess) return e;
+      attr_set = lds;
+    }
     hipLaunchKernelGGL(kfn, grid, block, lds, s, a);
   } else {
     const size_t lds = step_lds_bytes<T>(kTile);
@@ -371,9 +507,10 @@ hipError_t sl_step(hipStream_t s, StepKind kind, const StepArgs<T>& a, int* nblo
   if (a.halo < 0) return hipErrorInvalidValue;
   const bool fused = a.halo <= maxh;
   if (!fused && a.coef == nullptr) return hipErrorInvalidValue;
-  dim3 grid((a.n2 + kTile - 1) / kTile, (a.n1 + kTile - 1) / kTile);
+  dim3 grid((a.n2 + kTile - 1) / kTile, (a.n1 + kTile - 1) / kTile, a.batch);
   dim3 block(kTile, kTile);
   if (nblocks_out) *nblocks_out = int(grid.x * grid.y);
+  if (a.batch < 1) return hipErrorInvalidValue;
   switch (kind) {
     case StepKind::State:
       return launch_step<T, 0, false>(s, a, grid, block, fused);
@@ -390,12 +527,13 @@ hipError_t sl_step(hipStream_t s, StepKind kind, const StepArgs<T>& a, int* nblo
 }
 
 template <typename T>
-hipError_t sl_trace(hipStream_t s, int n1, int n2, double ht, const T* v, const T* cv, const T* divv, const T* cdiv,
-                    T* df, T* da, T* gamma, double* partial, int* nblocks_out) {
-  dim3 grid((n2 + kTile - 1) / kTile, (n1 + kTile - 1) / kTile);
+hipError_t sl_trace(hipStream_t s, int n1, int n2, int batch, const int* active, double ht, const T* v, const T* cv,
+                    const T* divv, const T* cdiv, T* df, T* da, T* gamma, double* partial, int* nblocks_out) {
+  dim3 grid((n2 + kTile - 1) / kTile, (n1 + kTile - 1) / kTile, batch);
   dim3 block(kTile, kTile);
   if (nblocks_out) *nblocks_out = int(grid.x * grid.y);
-  hipLaunchKernelGGL(k_trace<T>, grid, block, 0, s, n1, n2, T(ht), v, cv, divv, cdiv, df, da, gamma, partial);
+  hipLaunchKernelGGL(k_trace<T>, grid, block, 0, s, n1, n2, active, T(ht), v, cv, divv, cdiv, df, da, gamma,
+                     partial);
   return hipGetLastError();
 }
 
@@ -403,9 +541,9 @@ template int sl_step_max_halo<float>();
 template int sl_step_max_halo<double>();
 template hipError_t sl_step<float>(hipStream_t, StepKind, const StepArgs<float>&, int*);
 template hipError_t sl_step<double>(hipStream_t, StepKind, const StepArgs<double>&, int*);
-template hipError_t sl_trace<float>(hipStream_t, int, int, double, const float*, const float*, const float*,
-                                    const float*, float*, float*, float*, double*, int*);
-template hipError_t sl_trace<double>(hipStream_t, int, int, double, const double*, const double*, const double*,
-                                     const double*, double*, double*, double*, double*, int*);
+template hipError_t sl_trace<float>(hipStream_t, int, int, int, const int*, double, const float*, const float*,
+                                    const float*, const float*, float*, float*, float*, double*, int*);
+template hipError_t sl_trace<double>(hipStream_t, int, int, int, const int*, double, const double*, const double*,
+                                     const double*, const double*, double*, double*, double*, double*, int*);
 
 }  // namespace slnk

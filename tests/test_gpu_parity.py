@@ -228,3 +228,126 @@ def test_newton_solve_two_level(slnk, prec):
     g_at = O.gradient(O.linearize(L, vv))
     assert np.abs(g_at).max() / rep_ref["g0_inf"] <= 1.02e-2
     ctx.close()
+
+
+def test_graph_replays_match_eager_launches(slnk):
+    """The captured matvec / preconditioner graphs give the eager results on every replay, with
+    eager work (new linearisation points) between the replays."""
+    n = 128
+    L, vgen, vt = problem("gauss", n, n, nt=4, beta=1e-3, reg=2)
+    L.mT, L.mR, vgen, vt = same_inputs("mixed", L.mT, L.mR, vgen, vt)
+    ctxs = [_ctx(slnk, L, "mixed", pc="2l", use_graphs=flag) for flag in (True, False)]
+    for c in ctxs:
+        c.set_images(_t(L.mR, "mixed"), _t(L.mT, "mixed"))
+    g = torch.empty((2, n, n), dtype=torch.float32, device="cuda")
+    outs = [torch.empty_like(g) for _ in ctxs]
+    for rep, scale in enumerate((0.5, 0.9, 0.2, 0.5)):
+        for c, out in zip(ctxs, outs):
+            c.gradient(_t(scale * vgen, "mixed"), g)       # new linearisation (eager work)
+            torch.cuda.synchronize()
+            c.precond_apply(_t(vt, "mixed"), out)
+            torch.cuda.synchronize()
+        assert torch.equal(outs[0], outs[1]), rep
+    vs = [torch.zeros((2, n, n), dtype=torch.float32, device="cuda") for _ in ctxs]
+    reps = [c.newton_solve(v, max_newton=6) for c, v in zip(ctxs, vs)]
+    assert reps[0]["grel"] == reps[1]["grel"] and reps[0]["pcg"] == reps[1]["pcg"]
+    assert torch.equal(vs[0], vs[1])
+    for c in ctxs:
+        c.close()
+
+
+def _batch_problems(n1, n2, seeds, amps, nt=4, beta=1e-3, reg=2):
+    return [problem("gauss", n1, n2, nt=nt, beta=beta, reg=reg, seed=s, amp=a) for s, a in zip(seeds, amps)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_items_match_single_contexts(slnk, prec):
+    """A context of B = 3 different problems gives, item by item, the results of three B = 1
+    contexts bit for bit (items share no data), and each item matches the oracle."""
+    n1, n2, B = 96, 80, 3
+    probs = _batch_problems(n1, n2, seeds=(5, 6, 7), amps=(0.3, 0.15, 0.45))
+    for L, vgen, vt in probs:
+        L.mT, L.mR = same_inputs(prec, L.mT, L.mR)
+    vts = [same_inputs(prec, p[2]) for p in probs]
+    vs = [same_inputs(prec, 0.6 * p[1]) for p in probs]
+    stack = lambda arrs: _t(np.stack(arrs), prec)
+    L0 = probs[0][0]
+    cb = _ctx(slnk, L0, prec, pc="2l", batch=B)
+    cb.set_images(stack([p[0].mR for p in probs]), stack([p[0].mT for p in probs]))
+    gb = torch.empty((B, 2, n1, n2), dtype=cb.dtype, device="cuda")
+    Jb = cb.gradient(stack(vs), gb)
+    hb, zb, sb = torch.empty_like(gb), torch.empty_like(gb), torch.empty_like(gb)
+    cb.hessian_matvec(stack(vts), hb)
+    cb.split_matvec(stack(vts), sb)
+    cb.precond_apply(stack(vts), zb)
+    bounds = cb.cheb_bounds()
+    tol = TOL[prec]
+    for z, (L, vgen, vt) in enumerate(probs):
+        c1 = _ctx(slnk, L, prec, pc="2l")
+        c1.set_images(_t(L.mR, prec), _t(L.mT, prec))
+        g1 = torch.empty((2, n1, n2), dtype=c1.dtype, device="cuda")
+        J1 = c1.gradient(_t(vs[z], prec), g1)
+        h1, z1, s1 = torch.empty_like(g1), torch.empty_like(g1), torch.empty_like(g1)
+        c1.hessian_matvec(_t(vts[z], prec), h1)
+        c1.split_matvec(_t(vts[z], prec), s1)
+        c1.precond_apply(_t(vts[z], prec), z1)
+        assert Jb[z] == J1 and bounds[z] == c1.cheb_bounds(), z
+        for a, b in ((gb[z], g1), (hb[z], h1), (sb[z], s1), (zb[z], z1)):
+            assert torch.equal(a, b), z
+        c1.close()
+        lin = O.linearize(L, vs[z])
+        assert abs(Jb[z] - lin.J) / abs(lin.J) < tol["objective"]
+        _check_reg_op(L, "fp64", _np(gb[z]), O.gradient(lin), vs[z], tol["gradient"])
+        _check_reg_op(L, prec, _np(hb[z]), O.hessian_matvec(lin, vts[z]), vts[z], tol["matvec"])
+    cb.close()
+
+
+def test_batch_mixed_halos_use_one_path(slnk):
+    """Items whose displacements exceed the LDS footprint and items that fit share launches (the
+    batch takes the coefficient pass + global gather): every item still matches the oracle."""
+    n, nt = 64, 1
+    L, _, vt = problem("smooth", n, n, nt=nt, beta=1e-2, reg=1)
+    big = 7.0 * np.stack([np.ones((n, n)), 0.5 * np.ones((n, n))])
+    big[0] += 0.3 * np.sin(L.grid.X[1])
+    small = 0.05 * big
+    ctx = _ctx(slnk, L, "fp64", batch=2)
+    mm = lambda a: _t(np.stack([a, a]), "fp64")
+    ctx.set_images(mm(L.mR), mm(L.mT))
+    g = torch.empty((2, 2, n, n), dtype=torch.float64, device="cuda")
+    ctx.gradient(_t(np.stack([small, big]), "fp64"), g)
+    h = torch.empty_like(g)
+    ctx.hessian_matvec(mm(vt), h)
+    for z, v in enumerate((small, big)):
+        lin = O.linearize(L, v)
+        assert rel(_np(g[z]), O.gradient(lin)) < 1e-11, z
+        assert rel(_np(h[z]), O.hessian_matvec(lin, vt)) < 1e-11, z
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec,pc", [("fp64", "reg"), ("mixed", "2l")])
+def test_batch_newton_items_stop_on_their_own(slnk, prec, pc):
+    """Batched Newton--Krylov: items that need different numbers of Newton and PCG steps run in
+    lock step; each item's report and velocity equal those of its own B = 1 solve."""
+    n, B = 64, 3
+    probs = _batch_problems(n, n, seeds=(11, 12, 13), amps=(0.35, 0.1, 0.25), beta=1e-3 if pc == "2l" else 1e-2,
+                            reg=2 if pc == "2l" else 1)
+    for L, _, _ in probs:
+        L.mT, L.mR = same_inputs(prec, L.mT, L.mR)
+    L0 = probs[0][0]
+    cb = _ctx(slnk, L0, prec, pc=pc, batch=B)
+    cb.set_images(_t(np.stack([p[0].mR for p in probs]), prec), _t(np.stack([p[0].mT for p in probs]), prec))
+    vb = torch.zeros((B, 2, n, n), dtype=cb.dtype, device="cuda")
+    reps = cb.newton_solve(vb, max_newton=10)
+    iters = set()
+    for z, (L, _, _) in enumerate(probs):
+        c1 = _ctx(slnk, L, prec, pc=pc)
+        c1.set_images(_t(L.mR, prec), _t(L.mT, prec))
+        v1 = torch.zeros((2, n, n), dtype=c1.dtype, device="cuda")
+        r1 = c1.newton_solve(v1, max_newton=10)
+        for key in ("status", "newton_iters", "pcg_iters", "matvecs", "grel", "J", "pcg", "line_search_evals"):
+            assert reps[z][key] == r1[key], (z, key)
+        assert torch.equal(vb[z], v1), z
+        iters.add((r1["newton_iters"], r1["pcg_iters"]))
+        c1.close()
+    assert len(iters) > 1  # the items really took different paths
+    cb.close()
