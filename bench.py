@@ -40,6 +40,10 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "sl_step_incadj_gauss256_counters
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1604_02153_amd", "csrc", "transport.hip")
 
 
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -48,6 +52,8 @@ def parse():
     ap.add_argument("--matvecs", type=int, default=200, help="isolated matvecs timed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=12, help="oracle matvecs in the CPU sample")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-pair ragged batch workload")
+    ap.add_argument("--batched-matvecs", type=int, default=10, help="timed batched matvec calls (64 pairs each)")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: 20 incremental-adjoint SL steps of the 256^2 problem, then a plain "
                          "64 MiB elementwise kernel (the reference of the traffic counters); no JSON line")
@@ -92,6 +98,89 @@ def measured_traffic():
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def matvec_bytes(n1, n2, nt, elem=4):
+    """Algorithmic HBM bytes of one fused GN Hessian matvec: (23 nt + 32) fields of n1 n2 elements.
+    Per incremental-state step 10 fields (gather 1, displacements 2, direction 2, grad m 2, write 1,
+    prefilter 2), per incremental-adjoint step 13 (gather 1, displacements 2, gamma 1, write 1,
+    prefilter 2, grad m 2, accumulator read + write 4), plus 32 fixed (first sources, two forward
+    and two inverse real-FFT passes, the combine)."""
+    return (23 * nt + 32) * n1 * n2 * elem
+
+
+def batched(args, dev):
+    """64 independent pairs with grid sizes drawn from {128, ..., 1024}^2 (seed 4; pair p from the
+    'gauss256' recipe with seed 4000 + p), one ragged batch: bucket per size, buckets concurrent."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1604_02153_amd import BatchContext, Context
+    sizes = synth.batch_sizes(64, 4)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=torch.float32)
+    pairs = [synth.batch_pair(p, n) for p, n in enumerate(sizes)]
+    mT = [t(c["mT"]) for c in pairs]
+    vgen = [t(c["v_gen"]) for c in pairs]
+    vt = [t(c["vt"]) for c in pairs]
+    del pairs
+    # m_R = m_T transported by each pair's velocity (the library's state transport, per size)
+    mR = [torch.empty_like(m) for m in mT]
+    for n in sorted(set(sizes)):
+        idx = [p for p in range(64) if sizes[p] == n]
+        c = Context(n, n, 4, reg="h2", beta=1e-3, prec="mixed", pc="reg", batch=len(idx))
+        out = torch.empty((len(idx), n, n), dtype=torch.float32, device=dev)
+        c.transport_state(torch.stack([vgen[p] for p in idx]), torch.stack([mT[p] for p in idx]), out)
+        for j, p in enumerate(idx):
+            mR[p].copy_(out[j])
+        c.close()
+        del out
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log("batched inputs ready")
+    bc = BatchContext([(n, n) for n in sizes], 4, reg="h2", beta=1e-3, prec="mixed", pc="2l")
+    bc.set_images(mR, mT)
+    g = [torch.empty_like(v) for v in vgen]
+    out = [torch.empty_like(v) for v in vgen]
+    bc.gradient(vgen, g)
+    tuned = bc.autotune(vt, reps=3)
+    for _ in range(2):
+        bc.hessian_matvec(vt, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batched_matvecs):
+        bc.hessian_matvec(vt, out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    mv_rate = 64 * args.batched_matvecs / dt
+    gbs = sum(matvec_bytes(n, n, 4) for n in sizes) * args.batched_matvecs / dt / 1e9
+    v = [torch.zeros_like(x) for x in vgen]
+    bc.newton_solve(v)  # warm-up solve (graph capture, LDS attributes)
+    for x in v:
+        x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = bc.newton_solve(v)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stop = sorted(r["time_to_stop_ms"] for r in reps)
+    buckets = bc.buckets()
+    bc.close()
+    return {
+        "workload": "64 pairs, n^2 with n drawn (seed 4) from {128,256,384,512,768,1024}, gauss256 recipe per "
+                    "pair (seed 4000+p), nt=4, H2 beta=1e-3, P_2L, mixed precision; one bucket per size, "
+                    "buckets concurrent on their own streams",
+        "sizes": {str(n): sizes.count(n) for n in sorted(set(sizes))},
+        "matvecs_per_s": round(mv_rate, 1),
+        "matvec_GBps_algorithmic": round(gbs, 1), "matvec_roofline_frac": round(gbs / HBM_PEAK_GBS, 4),
+        "solve_wall_ms": round(1e3 * wall, 1),
+        "solve_fine_matvecs_per_s": round(sum(r["matvecs"] for r in reps) / wall, 1),
+        "per_pair_time_to_stop_ms": {"median": round(stop[len(stop) // 2], 1), "max": round(stop[-1], 1)},
+        "all_pairs_grel_le_1e-2": all(r["grel"][-1] <= 1e-2 for r in reps),
+        "newton_iters": [r["newton_iters"] for r in reps],
+        "autotune": [{"n": b[0], "pairs": b[2], "sl_path": b[3], "graphs": b[4], "op_ms": round(ms, 3)}
+                     for b, ms in zip(buckets, tuned)],
+    }
 
 
 def cpu_baseline(cfg, n_matvec):
@@ -154,6 +243,7 @@ def main():
     matvecs = sum(r["matvecs"] for r in reps)
     ms_per_step = 1e3 * wall / args.steps
 
+    log(f"single-pair solves: {ms_per_step:.1f} ms each")
     # isolated GN matvecs at the generating velocity (linearisation point), back to back
     g = torch.empty_like(v)
     ctx.gradient(vgen, g)
@@ -192,11 +282,16 @@ def main():
                   "time_gradient_ms": round(last["time_gradient_ms"], 3),
                   "time_linesearch_ms": round(last["time_linesearch_ms"], 3)},
         "isolated_matvecs_per_s": round(iso, 1),
+        "isolated_matvec_GBps_algorithmic": round(matvec_bytes(n1, n2, nt) * iso / 1e9, 1),
         "roofline": roof,
     }
     ctx.close()
+    if not args.no_batched:
+        line["batched"] = batched(args, dev)
+        log("batched workload done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)
+        log("cpu baseline done")
     print(json.dumps(line), flush=True)
 
 

@@ -74,6 +74,10 @@ typedef enum { SLNK_PC_REG = 1, SLNK_PC_2L = 2 } slnk_pc;
  *   use_graphs    1: replay the Hessian matvec and the preconditioner from captured HIP graphs
  *                 (recorded once per context and buffer pair); 0: launch every kernel
  *   batch         number of same-size problems B held by the context, 1 <= B <= 4096
+ *   sl_path       SL step kernels: 0 = fused (LDS prefilter + gather in one kernel) whenever the
+ *                 displacement halo fits in LDS, else coefficient pass + global gather;
+ *                 1 = always the coefficient pass + global gather (a tuning choice: both give the
+ *                 same interpolant up to rounding)
  * The compressible case (projection K = identity) is the one implemented. */
 typedef struct {
   int n1, n2, nt;
@@ -87,6 +91,7 @@ typedef struct {
   unsigned long long lanczos_seed;
   int use_graphs;
   int batch;
+  int sl_path;
 } slnk_params;
 
 /* Newton--Krylov options (sections 3.4.1, 3.5).  Stop when ||g||_inf / ||g_0||_inf <= gtol_rel or
@@ -124,6 +129,7 @@ typedef struct {
   double time_pcg_ms;       /* Krylov solves including preconditioner */
   double time_precond_ms;   /* preconditioner applications */
   double time_linesearch_ms;
+  double time_to_stop_ms;   /* from the call's start until this item met its stop criterion */
 } slnk_solve_report;
 
 /* Default parameters / options (paper settings: CHEB(10), 30 Lanczos steps, gtol 1e-2, 1e-5). */
@@ -197,6 +203,41 @@ slnk_status slnk_time_kernel(slnk_ctx* ctx, int which, int reps, double* avg_ms)
  * accepted iterate). */
 slnk_status slnk_newton_solve(slnk_ctx* ctx, void* v_inout, const slnk_solve_opts* opts,
                               slnk_solve_report* report);
+
+/* ---- Ragged batches ---------------------------------------------------------------------------
+ * A batch holds npairs independent problems whose grids may differ in size.  Pairs of one size
+ * form a bucket served by one batched context (as slnk_create with batch = pairs of that size) on
+ * a stream of its own; the calls below run every bucket from its own host thread, so buckets
+ * overlap on the GPU, and return when all buckets have finished (they synchronise).  Device work
+ * is ordered after the work already enqueued on the stream given to slnk_batch_create.
+ * Per-pair arguments are arrays of npairs device pointers (pair p: [n1[p]][n2[p]] for an image,
+ * [2][n1[p]][n2[p]] for a vector field, element type per base->prec); host scalar outputs are
+ * arrays of npairs.  Each pair's results equal those of a batch-1 context with the same
+ * parameters (same sl_path).  Errors name the bucket; a batch is used by one host thread at a
+ * time. */
+typedef struct slnk_batch slnk_batch;
+
+/* 'base' gives every parameter except n1, n2, batch (taken per pair).  Allocates every bucket's
+ * workspace plus staging for the stacked per-bucket layout. */
+slnk_status slnk_batch_create(const slnk_params* base, int npairs, const int* n1, const int* n2,
+                              void* hip_stream, slnk_batch** out);
+void slnk_batch_destroy(slnk_batch* b);
+const char* slnk_batch_last_error(const slnk_batch* b);
+/* k < 0: *count = number of buckets.  Else bucket k's size, pair count and tuned settings. */
+slnk_status slnk_batch_bucket_info(const slnk_batch* b, int k, int* n1, int* n2, int* count,
+                                   int* sl_path, int* use_graphs);
+slnk_status slnk_batch_set_images(slnk_batch* b, const void* const* m_R, const void* const* m_T);
+slnk_status slnk_batch_gradient(slnk_batch* b, const void* const* v, void* const* g, double* J);
+slnk_status slnk_batch_hessian_matvec(slnk_batch* b, const void* const* vt, void* const* Hvt);
+/* reports: array of npairs (may be NULL); report p's time_to_stop_ms counts from the start of
+ * its bucket's solve. */
+slnk_status slnk_batch_newton_solve(slnk_batch* b, void* const* v_inout, const slnk_solve_opts* opts,
+                                    slnk_solve_report* reports);
+/* Autotuner: for every bucket (one at a time), time 'reps' applications of the Krylov operator
+ * at the current linearisation (set by slnk_batch_gradient) on the direction vt under each of
+ * sl_path in {0, 1} x use_graphs in {0, 1}, and keep the fastest.  best_ms (array of buckets,
+ * may be NULL) receives the winning time per bucket. */
+slnk_status slnk_batch_autotune(slnk_batch* b, const void* const* vt, int reps, double* best_ms);
 
 #ifdef __cplusplus
 }

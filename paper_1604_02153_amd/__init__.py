@@ -11,7 +11,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["Context", "library_path", "load_library", "SolveOpts", "STATUS"]
+__all__ = ["Context", "BatchContext", "library_path", "load_library", "SolveOpts", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -29,7 +29,7 @@ class Params(ctypes.Structure):
                 ("beta", ctypes.c_double), ("prec", ctypes.c_int), ("pc", ctypes.c_int),
                 ("cheb_iters", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
                 ("emax_safety", ctypes.c_double), ("lanczos_seed", ctypes.c_ulonglong), ("use_graphs", ctypes.c_int),
-                ("batch", ctypes.c_int)]
+                ("batch", ctypes.c_int), ("sl_path", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -45,13 +45,15 @@ class SolveReport(ctypes.Structure):
                 ("J", ctypes.c_double * (REPORT_MAX + 1)), ("pcg", ctypes.c_int * (REPORT_MAX + 1)),
                 ("time_total_ms", ctypes.c_double), ("time_gradient_ms", ctypes.c_double),
                 ("time_pcg_ms", ctypes.c_double), ("time_precond_ms", ctypes.c_double),
-                ("time_linesearch_ms", ctypes.c_double)]
+                ("time_linesearch_ms", ctypes.c_double), ("time_to_stop_ms", ctypes.c_double)]
 
 
 EXPORTS = ["slnk_default_params", "slnk_default_opts", "slnk_create", "slnk_destroy", "slnk_last_error",
            "slnk_workspace_bytes", "slnk_set_images", "slnk_transport_state", "slnk_objective", "slnk_gradient",
            "slnk_hessian_matvec", "slnk_split_matvec", "slnk_precond_apply", "slnk_get_cheb_bounds",
-           "slnk_get_field", "slnk_time_kernel", "slnk_newton_solve"]
+           "slnk_get_field", "slnk_time_kernel", "slnk_newton_solve", "slnk_batch_create", "slnk_batch_destroy",
+           "slnk_batch_last_error", "slnk_batch_bucket_info", "slnk_batch_set_images", "slnk_batch_gradient",
+           "slnk_batch_hessian_matvec", "slnk_batch_newton_solve", "slnk_batch_autotune"]
 
 
 def library_path() -> str:
@@ -86,6 +88,15 @@ def load_library():
         "slnk_get_field": (ctypes.c_int, [V, ctypes.c_int, V]),
         "slnk_time_kernel": (ctypes.c_int, [V, ctypes.c_int, ctypes.c_int, P(ctypes.c_double)]),
         "slnk_newton_solve": (ctypes.c_int, [V, V, P(SolveOpts), P(SolveReport)]),
+        "slnk_batch_create": (ctypes.c_int, [P(Params), ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), V, P(V)]),
+        "slnk_batch_destroy": (None, [V]),
+        "slnk_batch_last_error": (ctypes.c_char_p, [V]),
+        "slnk_batch_bucket_info": (ctypes.c_int, [V, ctypes.c_int] + [P(ctypes.c_int)] * 5),
+        "slnk_batch_set_images": (ctypes.c_int, [V, P(V), P(V)]),
+        "slnk_batch_gradient": (ctypes.c_int, [V, P(V), P(V), P(ctypes.c_double)]),
+        "slnk_batch_hessian_matvec": (ctypes.c_int, [V, P(V), P(V)]),
+        "slnk_batch_newton_solve": (ctypes.c_int, [V, P(V), P(SolveOpts), P(SolveReport)]),
+        "slnk_batch_autotune": (ctypes.c_int, [V, P(V), ctypes.c_int, P(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -117,7 +128,7 @@ class Context:
 
     def __init__(self, n1, n2, nt, reg="h2", beta=1e-3, prec="mixed", pc="2l", cheb_iters=10,
                  lanczos_steps=30, emax_safety=1.05, lanczos_seed=0x5EED, use_graphs=True, stream=None,
-                 batch=1):
+                 batch=1, sl_path=0):
         import torch
         lib = load_library()
         p = Params()
@@ -131,6 +142,7 @@ class Context:
         p.emax_safety, p.lanczos_seed = float(emax_safety), int(lanczos_seed)
         p.use_graphs = 1 if use_graphs else 0
         p.batch = int(batch)
+        p.sl_path = int(sl_path)
         self.batch = p.batch
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -240,5 +252,101 @@ class Context:
             "grel": list(rep.grel[: k + 1]), "J": list(rep.J[: k + 1]), "pcg": list(rep.pcg[:k]),
             "time_total_ms": rep.time_total_ms, "time_gradient_ms": rep.time_gradient_ms,
             "time_pcg_ms": rep.time_pcg_ms, "time_precond_ms": rep.time_precond_ms,
-            "time_linesearch_ms": rep.time_linesearch_ms,
+            "time_linesearch_ms": rep.time_linesearch_ms, "time_to_stop_ms": rep.time_to_stop_ms,
         }
+
+
+class BatchContext:
+    """Independent problems of uneven grid sizes (include/slnk.h, ragged batches).  sizes is a
+    list of (n1, n2) per pair; every per-pair argument is a list of tensors (pair order)."""
+
+    def __init__(self, sizes, nt, reg="h2", beta=1e-3, prec="mixed", pc="2l", cheb_iters=10, lanczos_steps=30,
+                 emax_safety=1.05, lanczos_seed=0x5EED, use_graphs=True, sl_path=0, stream=None):
+        import torch
+        lib = load_library()
+        p = Params()
+        lib.slnk_default_params(ctypes.byref(p))
+        p.nt = int(nt)
+        p.reg = REG[reg] if isinstance(reg, str) else int(reg)
+        p.beta = float(beta)
+        p.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+        p.pc = PC[pc] if isinstance(pc, str) else int(pc)
+        p.cheb_iters, p.lanczos_steps = int(cheb_iters), int(lanczos_steps)
+        p.emax_safety, p.lanczos_seed = float(emax_safety), int(lanczos_seed)
+        p.use_graphs, p.sl_path = (1 if use_graphs else 0), int(sl_path)
+        self.sizes = [(int(a), int(b)) for a, b in sizes]
+        self.npairs = len(self.sizes)
+        n1 = (ctypes.c_int * self.npairs)(*[a for a, _ in self.sizes])
+        n2 = (ctypes.c_int * self.npairs)(*[b for _, b in self.sizes])
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.dtype = torch.float64 if p.prec == 0 else torch.float32
+        self._lib = lib
+        self._b = ctypes.c_void_p()
+        self._check(lib.slnk_batch_create(ctypes.byref(p), self.npairs, n1, n2, ctypes.c_void_p(stream.cuda_stream),
+                                          ctypes.byref(self._b)))
+
+    def _check(self, st):
+        if st != 0:
+            msg = self._lib.slnk_batch_last_error(self._b).decode() if self._b else ""
+            raise SlnkError(st, msg)
+
+    def _ptrs(self, ts, ncomp):
+        if len(ts) != self.npairs:
+            raise ValueError(f"expected {self.npairs} tensors, got {len(ts)}")
+        out = (ctypes.c_void_p * self.npairs)()
+        for p, (t, (a, b)) in enumerate(zip(ts, self.sizes)):
+            shape = (a, b) if ncomp == 1 else (ncomp, a, b)
+            if not t.is_cuda or t.dtype != self.dtype or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"pair {p}: expected a contiguous {self.dtype} CUDA tensor of shape {shape}")
+            out[p] = t.data_ptr()
+        return out
+
+    def close(self):
+        if self._b:
+            self._lib.slnk_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def buckets(self):
+        """[(n1, n2, pairs, sl_path, use_graphs)] per bucket."""
+        c = ctypes.c_int()
+        self._check(self._lib.slnk_batch_bucket_info(self._b, -1, None, None, ctypes.byref(c), None, None))
+        out = []
+        for k in range(c.value):
+            v = [ctypes.c_int() for _ in range(5)]
+            self._check(self._lib.slnk_batch_bucket_info(self._b, k, *[ctypes.byref(x) for x in v]))
+            out.append(tuple(x.value for x in v))
+        return out
+
+    def set_images(self, m_R, m_T):
+        self._check(self._lib.slnk_batch_set_images(self._b, self._ptrs(m_R, 1), self._ptrs(m_T, 1)))
+
+    def gradient(self, v, g):
+        J = (ctypes.c_double * self.npairs)()
+        self._check(self._lib.slnk_batch_gradient(self._b, self._ptrs(v, 2), self._ptrs(g, 2), J))
+        return list(J)
+
+    def hessian_matvec(self, vt, out):
+        self._check(self._lib.slnk_batch_hessian_matvec(self._b, self._ptrs(vt, 2), self._ptrs(out, 2)))
+
+    def autotune(self, vt, reps=5):
+        nb = len(self.buckets())
+        best = (ctypes.c_double * nb)()
+        self._check(self._lib.slnk_batch_autotune(self._b, self._ptrs(vt, 2), int(reps), best))
+        return list(best)
+
+    def newton_solve(self, v, opts: SolveOpts | None = None, **kw):
+        if opts is None:
+            opts = default_opts(**kw)
+        reps = (SolveReport * self.npairs)()
+        st = self._lib.slnk_batch_newton_solve(self._b, self._ptrs(v, 2), ctypes.byref(opts), reps)
+        if st not in (0, 5):
+            self._check(st)
+        return [Context._report(r) for r in reps]

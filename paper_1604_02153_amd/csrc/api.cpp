@@ -14,6 +14,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <type_traits>
 #include <vector>
@@ -309,11 +310,19 @@ struct Context {
     if (p.reg < 1 || p.reg > 3) throw Fail{SLNK_EINVAL, "reg must be 1, 2 or 3"};
     if (!(p.beta > 0)) throw Fail{SLNK_EINVAL, "beta must be positive"};
     if (p.pc != SLNK_PC_REG && p.pc != SLNK_PC_2L) throw Fail{SLNK_EINVAL, "pc must be SLNK_PC_REG or SLNK_PC_2L"};
+    if (p.sl_path != 0 && p.sl_path != 1) throw Fail{SLNK_EINVAL, "sl_path must be 0 or 1"};
     two_level = p.pc == SLNK_PC_2L;
     if (two_level) {
       if (!fft_size_ok(p.n1 / 2) || !fft_size_ok(p.n2 / 2)) throw Fail{SLNK_EINVAL, "coarse grid n/2 not supported"};
       if (p.cheb_iters < 1 || p.cheb_iters > 64 || p.lanczos_steps < 2 || !(p.emax_safety >= 1.0))
         throw Fail{SLNK_EINVAL, "bad P_2L parameters"};
+    }
+    {
+      int dev = 0, lim = 0;
+      HIPCHK(hipGetDevice(&dev));
+      HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+      if (spec_lds_bytes<T>(p.n1, p.n2) > size_t(lim) || spec_lds_bytes<double>(p.n1, p.n2) > size_t(lim))
+        throw Fail{SLNK_EINVAL, "grid too large for the LDS-resident FFTs of this precision"};
     }
     const size_t F = size_t(p.n1) * p.n2;
     const int tiles = ((p.n1 + 15) / 16) * ((p.n2 + 15) / 16);  // blocks of the 16x16 transport kernels
@@ -410,6 +419,7 @@ struct Context {
     a.coef = lv.coef;
     a.st_coef = (long long)lv.F;
     a.ht = 1.0 / lv.nt;
+    a.force_global = prm.sl_path == 1;
     return a;
   }
 
@@ -764,7 +774,7 @@ struct Context {
     HIPCHK(hipGraphLaunch(it->second, stream));
   }
 
-  bool halo_fits(const Level<T>& lv) const { return lv.max_halo(0, {}) <= halo_cap; }
+  bool halo_fits(const Level<T>& lv) const { return prm.sl_path == 1 || lv.max_halo(0, {}) <= halo_cap; }
 
   void count(std::vector<int>& c, const std::vector<int>& hmask, int by) {
     for (int z = 0; z < B; ++z)
@@ -952,6 +962,32 @@ struct Context {
     return double(ms) / reps;
   }
 
+  // ---- tuning ---------------------------------------------------------------------------------
+  // switch the SL kernel path / graph replay (captured graphs are dropped)
+  void retune(int sl_path, int graphs_on) {
+    prm.sl_path = sl_path;
+    use_graphs = graphs_on != 0;
+    clear_graphs();
+  }
+
+  // average time (ms) of one application of the Krylov operator at the current linearisation
+  // (all items), after one untimed application
+  double time_operator(const T* x, T* y, int reps) {
+    op(x, y, mask(kMaskAll), {});
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, stream));
+    for (int r = 0; r < reps; ++r) op(x, y, mask(kMaskAll), {});
+    HIPCHK(hipEventRecord(e1, stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return double(ms) / reps;
+  }
+
   // ---- Newton -------------------------------------------------------------------------------
   // slot 1 -> slot 0 for the accepted items (device mask(kMaskLs) == host 'acc')
   void promote_trial(const std::vector<int>& acc) {
@@ -1021,6 +1057,7 @@ struct Context {
     }
     t_grad += now_ms() - t0;
     std::vector<int> active(B, 1), kit(B, 0), status(B, SLNK_OK);
+    std::vector<double> t_stop(B, 0.0);
     T* vt = fine.vec[5];
     T* rhs = fine.vec[6];
     T* s = fine.vec[7];
@@ -1037,6 +1074,7 @@ struct Context {
         if (grel <= o.gtol_rel || ginf[z] <= o.gtol_abs || k >= o.max_newton || k >= SLNK_REPORT_MAX_ITERS) {
           active[z] = 0;
           kit[z] = k;
+          t_stop[z] = now_ms() - t_start;
           continue;
         }
         eta[z] = std::min(0.5, std::sqrt(g2[z]) / R[z].g0_two);
@@ -1090,6 +1128,7 @@ struct Context {
           status[z] = SLNK_ELINESEARCH;
           active[z] = 0;
           kit[z] = k;
+          t_stop[z] = now_ms() - t_start;
         }
       // accepted trials become the current linearisation point
       put_mask(kMaskLs, accepted);
@@ -1122,6 +1161,7 @@ struct Context {
       R[z].matvecs = n_matvec[z];
       R[z].coarse_matvecs = n_coarse[z];
       R[z].time_total_ms = t_total;
+      R[z].time_to_stop_ms = t_stop[z];
       R[z].time_gradient_ms = t_grad;
       R[z].time_pcg_ms = t_pcg;
       R[z].time_precond_ms = t_prec;
@@ -1397,6 +1437,266 @@ slnk_status slnk_newton_solve(slnk_ctx* ctx, void* v_inout, const slnk_solve_opt
     result = C.newton(static_cast<T*>(v_inout), o, report);
   });
   return st != SLNK_OK ? st : result;
+}
+
+}  // extern "C"
+
+// ============================================================================================
+// Ragged batches: pairs of uneven grid sizes.  Pairs of one size form a bucket, held by one
+// batched context (B = pairs of that size); every bucket is driven by its own host thread on its
+// own HIP stream, so the launches of different buckets overlap on the GPU while each bucket runs
+// its items in lock step.  Per-pair device buffers are staged into the bucket's stacked layout.
+// ============================================================================================
+struct slnk_batch {
+  std::string err;
+  int npairs = 0;
+  size_t elem = 0;
+  hipStream_t user = nullptr;
+  struct Bucket {
+    int n1 = 0, n2 = 0;
+    std::vector<int> pairs;    // pair ids, in item order
+    slnk_ctx* ctx = nullptr;
+    hipStream_t stream = nullptr;
+    char* img = nullptr;       // [2][B][F]: m_R then m_T
+    char* vin = nullptr;       // [B][2][F]
+    char* vout = nullptr;      // [B][2][F]
+    int sl_path = 0, use_graphs = 1;
+    size_t F() const { return size_t(n1) * n2; }
+  };
+  std::vector<Bucket> buckets;
+};
+
+namespace {
+
+void batch_release(slnk_batch* b) {
+  for (auto& k : b->buckets) {
+    if (k.ctx) slnk_destroy(k.ctx);
+    if (k.img) (void)hipFree(k.img);
+    if (k.vin) (void)hipFree(k.vin);
+    if (k.vout) (void)hipFree(k.vout);
+    if (k.stream) (void)hipStreamDestroy(k.stream);
+    k = slnk_batch::Bucket{};
+  }
+}
+
+// Run fn(bucket) for every bucket, one host thread each, after the caller's stream has reached
+// this point; the first failure (in bucket order) is returned with its message.
+template <class Fn>
+slnk_status batch_run(slnk_batch* b, Fn&& fn) {
+  if (!b) return SLNK_EINVAL;
+  hipEvent_t ready = nullptr;
+  if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ready, b->user) != hipSuccess) {
+    b->err = "cannot order the batch after the caller's stream";
+    if (ready) (void)hipEventDestroy(ready);
+    return SLNK_EDEVICE;
+  }
+  const size_t nb = b->buckets.size();
+  std::vector<slnk_status> st(nb, SLNK_OK);
+  std::vector<std::string> msg(nb);
+  std::vector<std::thread> th;
+  th.reserve(nb);
+  for (size_t i = 0; i < nb; ++i) {
+    th.emplace_back([&, i] {
+      auto& k = b->buckets[i];
+      try {
+        HIPCHK(hipStreamWaitEvent(k.stream, ready, 0));
+        st[i] = fn(k);
+        if (st[i] != SLNK_OK && st[i] != SLNK_ELINESEARCH) msg[i] = slnk_last_error(k.ctx);
+        HIPCHK(hipStreamSynchronize(k.stream));
+      } catch (const slnk::Fail& e) {
+        st[i] = e.st;
+        msg[i] = e.msg;
+      } catch (const std::exception& e) {
+        st[i] = SLNK_EDEVICE;
+        msg[i] = e.what();
+      }
+    });
+  }
+  for (auto& t : th) t.join();
+  (void)hipEventDestroy(ready);
+  slnk_status res = SLNK_OK;
+  for (size_t i = 0; i < nb; ++i)
+    if (st[i] != SLNK_OK && st[i] != SLNK_ELINESEARCH) {
+      b->err = "bucket " + std::to_string(b->buckets[i].n1) + "x" + std::to_string(b->buckets[i].n2) + ": " + msg[i];
+      return st[i];
+    } else if (st[i] == SLNK_ELINESEARCH) {
+      res = SLNK_ELINESEARCH;
+    }
+  return res;
+}
+
+// copy per-pair buffers (cnt elements each) into / out of a bucket's stacked buffer
+void stage_in(const slnk_batch* b, const slnk_batch::Bucket& k, const void* const* src, char* dst, size_t cnt) {
+  const size_t bytes = cnt * b->elem;
+  for (size_t z = 0; z < k.pairs.size(); ++z)
+    HIPCHK(hipMemcpyAsync(dst + z * bytes, src[k.pairs[z]], bytes, hipMemcpyDeviceToDevice, k.stream));
+}
+
+void stage_out(const slnk_batch* b, const slnk_batch::Bucket& k, const char* src, void* const* dst, size_t cnt) {
+  const size_t bytes = cnt * b->elem;
+  for (size_t z = 0; z < k.pairs.size(); ++z)
+    HIPCHK(hipMemcpyAsync(dst[k.pairs[z]], src + z * bytes, bytes, hipMemcpyDeviceToDevice, k.stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+slnk_status slnk_batch_create(const slnk_params* base, int npairs, const int* n1, const int* n2, void* hip_stream,
+                              slnk_batch** out) {
+  if (!base || !n1 || !n2 || !out || npairs < 1) return SLNK_EINVAL;
+  *out = nullptr;
+  auto b = std::make_unique<slnk_batch>();
+  b->npairs = npairs;
+  b->elem = base->prec == SLNK_PREC_FP64 ? sizeof(double) : sizeof(float);
+  b->user = static_cast<hipStream_t>(hip_stream);
+  // buckets by size, largest grids first (they start first and take longest)
+  std::map<std::pair<long long, long long>, std::vector<int>> by;
+  for (int p = 0; p < npairs; ++p) by[{-(long long)n1[p] * n2[p], (long long)n1[p]}].push_back(p);
+  for (auto& kv : by) {
+    slnk_batch::Bucket k;
+    k.n1 = n1[kv.second[0]];
+    k.n2 = n2[kv.second[0]];
+    k.pairs = kv.second;
+    b->buckets.push_back(std::move(k));
+  }
+  for (auto& k : b->buckets) {
+    slnk_params p = *base;
+    p.n1 = k.n1;
+    p.n2 = k.n2;
+    p.batch = int(k.pairs.size());
+    k.sl_path = p.sl_path;
+    k.use_graphs = p.use_graphs;
+    const size_t F = k.F(), B = k.pairs.size();
+    if (hipStreamCreateWithFlags(&k.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&k.img), 2 * B * F * b->elem) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&k.vin), 2 * B * F * b->elem) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&k.vout), 2 * B * F * b->elem) != hipSuccess) {
+      batch_release(b.get());
+      return SLNK_ENOMEM;
+    }
+    slnk_status st = slnk_create(&p, k.stream, &k.ctx);
+    if (st != SLNK_OK) {
+      batch_release(b.get());
+      return st;
+    }
+  }
+  *out = b.release();
+  return SLNK_OK;
+}
+
+void slnk_batch_destroy(slnk_batch* b) {
+  if (!b) return;
+  batch_release(b);
+  delete b;
+}
+
+const char* slnk_batch_last_error(const slnk_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+slnk_status slnk_batch_bucket_info(const slnk_batch* b, int k, int* n1, int* n2, int* count, int* sl_path,
+                                   int* use_graphs) {
+  if (!b) return SLNK_EINVAL;
+  if (k < 0) {
+    if (count) *count = int(b->buckets.size());
+    return SLNK_OK;
+  }
+  if (k >= int(b->buckets.size())) return SLNK_EINVAL;
+  const auto& q = b->buckets[k];
+  if (n1) *n1 = q.n1;
+  if (n2) *n2 = q.n2;
+  if (count) *count = int(q.pairs.size());
+  if (sl_path) *sl_path = q.sl_path;
+  if (use_graphs) *use_graphs = q.use_graphs;
+  return SLNK_OK;
+}
+
+slnk_status slnk_batch_set_images(slnk_batch* b, const void* const* m_R, const void* const* m_T) {
+  if (!b || !m_R || !m_T) return SLNK_EINVAL;
+  for (int p = 0; p < b->npairs; ++p)
+    if (!m_R[p] || !m_T[p]) return SLNK_EINVAL;
+  return batch_run(b, [&](slnk_batch::Bucket& k) {
+    const size_t F = k.F(), B = k.pairs.size();
+    stage_in(b, k, m_R, k.img, F);
+    stage_in(b, k, m_T, k.img + B * F * b->elem, F);
+    return slnk_set_images(k.ctx, k.img, k.img + B * F * b->elem);
+  });
+}
+
+slnk_status slnk_batch_gradient(slnk_batch* b, const void* const* v, void* const* g, double* J) {
+  if (!b || !v || !g) return SLNK_EINVAL;
+  return batch_run(b, [&](slnk_batch::Bucket& k) {
+    std::vector<double> Jk(k.pairs.size());
+    stage_in(b, k, v, k.vin, 2 * k.F());
+    slnk_status st = slnk_gradient(k.ctx, k.vin, k.vout, Jk.data());
+    if (st != SLNK_OK) return st;
+    stage_out(b, k, k.vout, g, 2 * k.F());
+    if (J)
+      for (size_t z = 0; z < k.pairs.size(); ++z) J[k.pairs[z]] = Jk[z];
+    return SLNK_OK;
+  });
+}
+
+slnk_status slnk_batch_hessian_matvec(slnk_batch* b, const void* const* vt, void* const* Hvt) {
+  if (!b || !vt || !Hvt) return SLNK_EINVAL;
+  return batch_run(b, [&](slnk_batch::Bucket& k) {
+    stage_in(b, k, vt, k.vin, 2 * k.F());
+    slnk_status st = slnk_hessian_matvec(k.ctx, k.vin, k.vout);
+    if (st != SLNK_OK) return st;
+    stage_out(b, k, k.vout, Hvt, 2 * k.F());
+    return SLNK_OK;
+  });
+}
+
+slnk_status slnk_batch_newton_solve(slnk_batch* b, void* const* v_inout, const slnk_solve_opts* opts,
+                                    slnk_solve_report* reports) {
+  if (!b || !v_inout) return SLNK_EINVAL;
+  return batch_run(b, [&](slnk_batch::Bucket& k) {
+    std::vector<slnk_solve_report> rk(k.pairs.size());
+    stage_in(b, k, v_inout, k.vin, 2 * k.F());
+    slnk_status st = slnk_newton_solve(k.ctx, k.vin, opts, rk.data());
+    if (st != SLNK_OK && st != SLNK_ELINESEARCH) return st;
+    stage_out(b, k, k.vin, v_inout, 2 * k.F());
+    if (reports)
+      for (size_t z = 0; z < k.pairs.size(); ++z) reports[k.pairs[z]] = rk[z];
+    return st;
+  });
+}
+
+slnk_status slnk_batch_autotune(slnk_batch* b, const void* const* vt, int reps, double* best_ms) {
+  if (!b || !vt || reps < 1) return SLNK_EINVAL;
+  // one bucket at a time, so that the candidates are timed without interference
+  for (size_t i = 0; i < b->buckets.size(); ++i) {
+    auto& k = b->buckets[i];
+    slnk_status st = guarded(k.ctx, [&] {
+      stage_in(b, k, vt, k.vin, 2 * k.F());
+      auto tune = [&](auto& C) {
+        using T = std::remove_reference_t<decltype(*C.fine.mT)>;
+        if (!C.has_grad) throw slnk::Fail{SLNK_EINVAL, "no linearisation point: call slnk_batch_gradient first"};
+        double best = 1e300;
+        int bp = 0, bg = 1;
+        for (int path = 0; path < 2; ++path)
+          for (int gr = 0; gr < 2; ++gr) {
+            C.retune(path, gr);
+            const double ms = C.time_operator(reinterpret_cast<const T*>(k.vin), reinterpret_cast<T*>(k.vout), reps);
+            if (ms < best) best = ms, bp = path, bg = gr;
+          }
+        C.retune(bp, bg);
+        k.sl_path = bp;
+        k.use_graphs = bg;
+        if (best_ms) best_ms[i] = best;
+      };
+      if (k.ctx->f)
+        tune(*k.ctx->f);
+      else
+        tune(*k.ctx->d);
+    });
+    if (st != SLNK_OK) {
+      b->err = slnk_last_error(k.ctx);
+      return st;
+    }
+  }
+  return SLNK_OK;
 }
 
 }  // extern "C"

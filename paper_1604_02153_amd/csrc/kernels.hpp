@@ -44,6 +44,10 @@ struct SymbolParams {
   double beta = 1.0;
 };
 
+// Largest dynamic LDS (bytes) a spectral launch on an n1 x n2 grid asks for.
+template <typename T>
+size_t spec_lds_bytes(int n1, int n2);
+
 // ---- spectral operators (each: row forward, column forward + symbol + column inverse, row inverse)
 // All operate on 'batch' same-size items; per item the fields are consecutive (nf fields of
 // field() elements) and items follow each other.  'active' (optional, [batch]) skips items.
@@ -120,6 +124,7 @@ struct StepArgs {
   double w_new = 0;          // trapezoid weight of the produced level (times ht)
   double w_old = 0;          // trapezoid weight of the src level (first step only)
   int first = 0, last = 0;
+  int force_global = 0;      // 1: coefficient pass + global gather even when the halo fits LDS
   double* partial = nullptr; // FP64 per-block partial sums, item z at partial + z * 2 * tiles
                              // (state last step: misfit; adjoint last step: sum g^2, max |g|)
 };

@@ -11,6 +11,9 @@
 //
 // Conventions: forward transforms are unnormalised; every symbol carries the 1/(n1 n2) of the
 // inverse.  Odd symbols (derivatives) drop the Nyquist modes, even symbols keep them.
+#include <atomic>
+#include <mutex>
+
 #include "kernels.hpp"
 
 namespace slnk {
@@ -18,6 +21,21 @@ namespace {
 
 constexpr int kMaxE = 16;          // complex elements per thread held by one FFT stage
 constexpr int kLdsBudget = 64 * 1024;
+constexpr size_t kLdsDefault = 64 * 1024;  // dynamic LDS a kernel gets without an attribute
+
+std::mutex g_attr_mutex;
+
+// Raise a kernel's dynamic-LDS limit before its first launch above 64 KiB (once per size).
+template <typename K>
+hipError_t allow_lds(K kfn, size_t lds, std::atomic<size_t>& allowed) {
+  if (lds <= kLdsDefault || lds <= allowed.load(std::memory_order_acquire)) return hipSuccess;
+  std::lock_guard<std::mutex> lock(g_attr_mutex);
+  if (lds <= allowed.load(std::memory_order_relaxed)) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     int(lds));
+  if (e == hipSuccess) allowed.store(lds, std::memory_order_release);
+  return e;
+}
 
 // ---------------------------------------------------------------------------------------
 // small DFTs; sign = -1 forward, +1 inverse
@@ -509,6 +527,12 @@ struct OpProlongCombine {
 // ---------------------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------------------
+#define RET_IF(e)                  \
+  do {                             \
+    hipError_t _e = (e);           \
+    if (_e != hipSuccess) return _e; \
+  } while (0)
+
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 // about 8 elements per thread (one radix-8 butterfly per stage), at least one wavefront
@@ -525,6 +549,8 @@ hipError_t launch_row_fwd(hipStream_t s, const SpecGrid<T>& g, RealFields<T> in,
   row_config<T>(g.n2, nthr, rpb);
   dim3 grid((g.n1 + rpb - 1) / rpb, (in.count + 1) / 2, batch);
   size_t lds = (size_t(rpb) * (g.n2 + 1) + g.n2) * sizeof(cplx<T>);
+  static std::atomic<size_t> allowed{0};
+  RET_IF(allow_lds(k_row_fwd<T>, lds, allowed));
   hipLaunchKernelGGL(k_row_fwd<T>, grid, dim3(nthr), lds, s, in, S, g.n1, g.n2, rpb, g.row);
   return hipGetLastError();
 }
@@ -536,8 +562,23 @@ hipError_t launch_row_inv(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* S,
   row_config<T>(g.n2, nthr, rpb);
   dim3 grid((g.n1 + rpb - 1) / rpb, (out.count + 1) / 2, batch);
   size_t lds = (size_t(rpb) * (g.n2 + 1) + g.n2) * sizeof(cplx<T>);
+  static std::atomic<size_t> allowed{0};
+  RET_IF(allow_lds(k_row_inv<T>, lds, allowed));
   hipLaunchKernelGGL(k_row_inv<T>, grid, dim3(nthr), lds, s, S, nspec, out, g.n1, g.n2, rpb, g.row);
   return hipGetLastError();
+}
+
+// Column pass shape: B columns per block -- enough blocks to spread a small grid over the chip,
+// every FFT stage within kMaxE elements per thread at <= 1024 threads -- and its LDS bytes.
+template <typename T>
+void col_config(int n1, int nh, int nmax, int& B, int& nthr, size_t& lds) {
+  const int col_bytes = (n1 + 1) * int(sizeof(cplx<T>)) * nmax;
+  B = std::max(1, std::min(std::min(16, std::max(1, nh / 64)), kLdsBudget / col_bytes));
+  while (B > 1 && nmax * B * n1 > 1024 * kMaxE) --B;
+  const int elems = nmax * B * n1;
+  nthr = std::min(1024, std::max(64, round_up((elems + 7) / 8, 64)));
+  while (nthr < 1024 && elems > nthr * kMaxE) nthr += 64;
+  lds = size_t(B) * col_bytes + size_t(n1) * sizeof(cplx<T>);
 }
 
 template <typename T, class Op>
@@ -545,26 +586,17 @@ hipError_t launch_col(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* Sin, c
                       int batch, const int* active = nullptr, int item_div = 1) {
   constexpr int nmax = Op::NIN > Op::NOUT ? Op::NIN : Op::NOUT;
   const int nh = g.nh();
-  const int col_bytes = (g.n1 + 1) * int(sizeof(cplx<T>)) * nmax;
-  // a few columns per block: enough blocks to spread a small grid over the chip, and every
-  // FFT stage within kMaxE elements per thread at <= 1024 threads
-  int B = std::max(1, std::min(std::min(16, std::max(1, nh / 64)), kLdsBudget / col_bytes));
-  while (B > 1 && nmax * B * g.n1 > 1024 * kMaxE) --B;
-  const int elems = nmax * B * g.n1;
-  int nthr = std::min(1024, std::max(64, round_up((elems + 7) / 8, 64)));
-  while (nthr < 1024 && elems > nthr * kMaxE) nthr += 64;
+  int B, nthr;
+  size_t lds;
+  col_config<T>(g.n1, nh, nmax, B, nthr, lds);
   dim3 grid((nh + B - 1) / B, 1, batch);
-  size_t lds = size_t(B) * col_bytes + size_t(g.n1) * sizeof(cplx<T>);
+  static std::atomic<size_t> allowed{0};
+  RET_IF(allow_lds(k_col<T, Op>, lds, allowed));
   hipLaunchKernelGGL((k_col<T, Op>), grid, dim3(nthr), lds, s, Sin, Sout, g.n1, g.n2, B, g.col, op, flags, active,
                      item_div);
   return hipGetLastError();
 }
 
-#define RET_IF(e)                  \
-  do {                             \
-    hipError_t _e = (e);           \
-    if (_e != hipSuccess) return _e; \
-  } while (0)
 
 // fields f < nf of a per-item block of nf consecutive fields
 template <typename T, class FL>
@@ -579,6 +611,16 @@ void set_fields(FL& fl, int nf, T* base, size_t F, const int* active) {
 }
 
 }  // namespace
+
+template <typename T>
+size_t spec_lds_bytes(int n1, int n2) {
+  int nthr, rpb, B;
+  row_config<T>(n2, nthr, rpb);
+  const size_t row = (size_t(rpb) * (n2 + 1) + n2) * sizeof(cplx<T>);
+  size_t col = 0;
+  col_config<T>(n1, n2 / 2 + 1, 4, B, nthr, col);  // widest operator: four spectra per column
+  return std::max(row, col);
+}
 
 template <typename T>
 hipError_t spec_scale(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, SymbolParams sym, int nf,
@@ -689,6 +731,7 @@ hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecG
 }
 
 #define INST(T)                                                                                                 \
+  template size_t spec_lds_bytes<T>(int, int);                                                                  \
   template hipError_t spec_scale<T>(hipStream_t, const SpecGrid<T>&, int, const int*, SymbolParams, int, const T*, \
                                     T*, const T*, cplx<T>*, cplx<T>*);                                          \
   template hipError_t spec_grad<T>(hipStream_t, const SpecGrid<T>&, int, const T*, T*, cplx<T>*, cplx<T>*);     \

@@ -9,10 +9,17 @@
 // the circulant (1, 4, 1)/6 operator, truncated where |z|^t falls below the working precision),
 // gathers the 4x4 tensor B-spline stencil at every departure point and applies the step's
 // update (Heun weights, adjoint factor, time-integral accumulation) in registers.
+#include <atomic>
+#include <mutex>
+
 #include "kernels.hpp"
 
 namespace slnk {
 namespace {
+
+// one-time host set-up (filter taps, LDS limit, kernel LDS attributes) may be reached from
+// several host threads driving contexts on different streams
+std::mutex g_setup_mutex;
 
 constexpr int kTile = 16;
 
@@ -43,10 +50,12 @@ __device__ __forceinline__ float tap<float>(int t) { return c_taps_f[t]; }
 template <>
 __device__ __forceinline__ double tap<double>(int t) { return c_taps_d[t]; }
 
-bool g_taps_ready = false;
+std::atomic<bool> g_taps_ready{false};
 
 hipError_t upload_taps() {
-  if (g_taps_ready) return hipSuccess;
+  if (g_taps_ready.load(std::memory_order_acquire)) return hipSuccess;
+  std::lock_guard<std::mutex> lock(g_setup_mutex);
+  if (g_taps_ready.load(std::memory_order_relaxed)) return hipSuccess;
   // exact coefficients in FP64 from the closed form
   const double z = std::sqrt(3.0) - 2.0;
   double td[FilterTaps<double>::K + 1];
@@ -56,7 +65,7 @@ hipError_t upload_taps() {
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_taps_d), td, sizeof(td));
   if (e != hipSuccess) return e;
   e = hipMemcpyToSymbol(HIP_SYMBOL(c_taps_f), tf, sizeof(tf));
-  if (e == hipSuccess) g_taps_ready = true;
+  if (e == hipSuccess) g_taps_ready.store(true, std::memory_order_release);
   return e;
 }
 
@@ -394,18 +403,18 @@ size_t step_lds_bytes(int G) {
   return size_t(P * P + R + (P + R) * G) * sizeof(T);
 }
 
-size_t g_lds_limit = 0;
+std::atomic<size_t> g_lds_limit{0};
 
 hipError_t lds_limit(size_t* out) {
-  if (g_lds_limit == 0) {
+  if (g_lds_limit.load(std::memory_order_acquire) == 0) {
     int dev = 0, v = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return e;
-    g_lds_limit = size_t(v);
+    g_lds_limit.store(size_t(v), std::memory_order_release);
   }
-  *out = g_lds_limit;
+  *out = g_lds_limit.load(std::memory_order_acquire);
   return hipSuccess;
 }
 
@@ -481,12 +490,15 @@ hipError_t launch_step(hipStream_t s, const StepArgs<T>& a, dim3 grid, dim3 bloc
   if (fused) {
     const size_t lds = step_lds_bytes<T>(kTile + 2 * a.halo + 3);
     auto kfn = k_sl_step<T, KIND, FIRST, false>;
-    static size_t attr_set = 0;  // largest dynamic LDS size already allowed for this kernel
-    if (lds > attr_set) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-      if (e != hipSuccess) return e;
-      attr_set = lds;
+    static std::atomic<size_t> attr_set{0};  // largest dynamic LDS size allowed for this kernel
+    if (lds > attr_set.load(std::memory_order_acquire)) {
+      std::lock_guard<std::mutex> lock(g_setup_mutex);
+      if (lds > attr_set.load(std::memory_order_relaxed)) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        attr_set.store(lds, std::memory_order_release);
+      }
     }
     hipLaunchKernelGGL(kfn, grid, block, lds, s, a);
   } else {
@@ -505,7 +517,7 @@ hipError_t sl_step(hipStream_t s, StepKind kind, const StepArgs<T>& a, int* nblo
   if (e != hipSuccess) return e;
   const int maxh = sl_step_max_halo<T>();
   if (a.halo < 0) return hipErrorInvalidValue;
-  const bool fused = a.halo <= maxh;
+  const bool fused = a.halo <= maxh && !a.force_global;
   if (!fused && a.coef == nullptr) return hipErrorInvalidValue;
   dim3 grid((a.n2 + kTile - 1) / kTile, (a.n1 + kTile - 1) / kTile, a.batch);
   dim3 block(kTile, kTile);

@@ -20,7 +20,8 @@ import math
 import numpy as np
 
 __all__ = ["grid_coords", "smooth_a_template", "smooth_a_velocity", "gaussian_sum_isotropic",
-           "gaussian_sum_anisotropic", "random_velocity", "config", "CONFIGS"]
+           "gaussian_sum_anisotropic", "random_velocity", "config", "CONFIGS", "BATCH_SIZES", "batch_sizes",
+           "batch_pair"]
 
 
 def grid_coords(n1, n2):
@@ -53,14 +54,16 @@ def _normalise(u):
 
 def gaussian_sum_isotropic(n1, n2, rng, count=32, sigma=(0.1, 0.4), amplitude=(0.2, 1.0)):
     """Sum of isotropic periodic Gaussians (widths in radians), min-max normalised to [0, 1]."""
-    X1, X2 = grid_coords(n1, n2)
+    x1 = 2.0 * math.pi * np.arange(n1) / n1
+    x2 = 2.0 * math.pi * np.arange(n2) / n2
     centres = rng.uniform(0.0, 2.0 * math.pi, size=(count, 2))
     sig = rng.uniform(sigma[0], sigma[1], size=count)
     amp = rng.uniform(amplitude[0], amplitude[1], size=count)
     u = np.zeros((n1, n2))
     for c, s, a in zip(centres, sig, amp):
-        d1 = _wrap(X1 - c[0]); d2 = _wrap(X2 - c[1])
-        u += a * np.exp(-(d1 * d1 + d2 * d2) / (2.0 * s * s))
+        # an isotropic Gaussian is the outer product of two 1-D Gaussians
+        d1 = _wrap(x1 - c[0]); d2 = _wrap(x2 - c[1])
+        u += np.outer(a * np.exp(-d1 * d1 / (2.0 * s * s)), np.exp(-d2 * d2 / (2.0 * s * s)))
     return _normalise(u)
 
 
@@ -97,14 +100,15 @@ def random_velocity(n1, n2, rng, modes=16, kmax=4, amplitude=0.3):
     cand = [(a, b) for a in range(-kmax, kmax + 1) for b in range(-kmax, kmax + 1)
             if 1 <= a * a + b * b <= kmax * kmax]
     pick = rng.choice(len(cand), size=modes, replace=False)
-    X1, X2 = grid_coords(n1, n2)
+    x1 = 2.0 * math.pi * np.arange(n1) / n1
+    x2 = 2.0 * math.pi * np.arange(n2) / n2
     v = np.zeros((2, n1, n2))
     for idx in pick:
         a, b = cand[idx]
         coef = rng.standard_normal(2) + 1j * rng.standard_normal(2)
-        phase = np.exp(1j * (a * X1 + b * X2))
-        v[0] += (coef[0] * phase).real
-        v[1] += (coef[1] * phase).real
+        e1, e2 = np.exp(1j * a * x1), np.exp(1j * b * x2)  # the plane wave factorises
+        v[0] += np.outer(coef[0] * e1, e2).real
+        v[1] += np.outer(coef[1] * e1, e2).real
     return v * (amplitude / float(np.max(np.abs(v))))
 
 
@@ -146,3 +150,19 @@ def config(name, n=None, seed=None):
     rng_t = np.random.default_rng(s + 1000)
     c["vt"] = random_velocity(n1, n2, rng_t, modes=16, kmax=4, amplitude=0.1)
     return c
+
+
+# Grid sizes of the batched workload: 64 independent pairs, sizes drawn (seed 4) from these.
+BATCH_SIZES = (128, 256, 384, 512, 768, 1024)
+
+
+def batch_sizes(count=64, seed=4):
+    """Grid size n (n x n) of each pair of the batched workload, drawn uniformly from BATCH_SIZES."""
+    rng = np.random.default_rng(seed)
+    return [int(BATCH_SIZES[i]) for i in rng.integers(0, len(BATCH_SIZES), size=count)]
+
+
+def batch_pair(p, n):
+    """Pair p of the batched workload on an n x n grid: the 'gauss256' recipe (32 isotropic
+    Gaussians, 16-mode velocity |k| <= 4, amplitude 0.3) from the stream seeded 4000 + p."""
+    return config("gauss256", n=n, seed=4000 + p)

@@ -27,6 +27,15 @@ def reg_floor(L, prec, x):
     return 64.0 * EPS[prec] * L.prm.beta * amax * float(np.linalg.norm(x))
 
 
+def split_floor(L, prec, x):
+    """Rounding floor of S (beta A x) in the split norm, S = (beta A')^{-1/2}: the FFT rounding of x
+    (white over the modes, eps relative) is multiplied by beta a(k) and then by (beta a(k))^{-1/2},
+    i.e. by up to sqrt(beta max a); about 0.5 eps sqrt(beta max a) ||x|| is observed in FP32."""
+    g = L.grid
+    amax = float(((g.n1 / 2) ** 2 + (g.n2 / 2) ** 2) ** L.prm.reg)
+    return 8.0 * EPS[prec] * (L.prm.beta * amax) ** 0.5 * float(np.linalg.norm(x))
+
+
 def split_norm(L, x):
     """||S x||, S = (beta A')^{-1/2}: the norm of the split-preconditioned Krylov iteration."""
     return float(np.linalg.norm(O.split_scale(L.grid, x, L.prm.beta, L.prm.reg)))

@@ -54,6 +54,7 @@ int main(void) {
   F(slnk_params, n1); F(slnk_params, n2); F(slnk_params, nt); F(slnk_params, reg); F(slnk_params, beta);
   F(slnk_params, prec); F(slnk_params, pc); F(slnk_params, cheb_iters); F(slnk_params, lanczos_steps);
   F(slnk_params, emax_safety); F(slnk_params, lanczos_seed); F(slnk_params, use_graphs); F(slnk_params, batch);
+  F(slnk_params, sl_path);
   printf("slnk_solve_opts size %zu 0\n", sizeof(slnk_solve_opts));
   F(slnk_solve_opts, max_newton); F(slnk_solve_opts, gtol_rel); F(slnk_solve_opts, gtol_abs);
   F(slnk_solve_opts, max_pcg); F(slnk_solve_opts, armijo_c1); F(slnk_solve_opts, max_halvings);
@@ -64,6 +65,7 @@ int main(void) {
   F(slnk_solve_report, emax); F(slnk_solve_report, grel); F(slnk_solve_report, J); F(slnk_solve_report, pcg);
   F(slnk_solve_report, time_total_ms); F(slnk_solve_report, time_gradient_ms); F(slnk_solve_report, time_pcg_ms);
   F(slnk_solve_report, time_precond_ms); F(slnk_solve_report, time_linesearch_ms);
+  F(slnk_solve_report, time_to_stop_ms);
   return 0;
 }
 """
@@ -101,7 +103,8 @@ def test_defaults_are_the_paper_settings(pkg):
 
 
 @pytest.mark.parametrize("change", [dict(n1=30, n2=34), dict(nt=0), dict(batch=0), dict(reg=4), dict(beta=0.0),
-                                    dict(prec=7), dict(pc=3), dict(n1=2048 * 2), dict(cheb_iters=0)])
+                                    dict(prec=7), dict(pc=3), dict(n1=2048 * 2), dict(cheb_iters=0),
+                                    dict(sl_path=2)])
 def test_create_rejects_bad_parameters_before_device_work(pkg, change):
     lib = pkg.load_library()
     p = pkg.Params()
