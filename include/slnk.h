@@ -130,6 +130,7 @@ typedef struct {
   double time_precond_ms;   /* preconditioner applications */
   double time_linesearch_ms;
   double time_to_stop_ms;   /* from the call's start until this item met its stop criterion */
+  int fallback;             /* 1: the given start had no smaller ||g||_inf than v = 0 and was replaced by v = 0 */
 } slnk_solve_report;
 
 /* Default parameters / options (paper settings: CHEB(10), 30 Lanczos steps, gtol 1e-2, 1e-5). */
@@ -196,13 +197,62 @@ slnk_status slnk_get_field(slnk_ctx* ctx, int which, void* out);
 slnk_status slnk_time_kernel(slnk_ctx* ctx, int which, int reps, double* avg_ms);
 
 /* Globalised inexact GN--Krylov solve from the velocity in v_inout (device [B][2][n1][n2]); the
- * result overwrites it.  opts NULL: defaults.  report (array of B, may be NULL) receives one
+ * result overwrites it.  A nonzero start is kept only if its ||g||_inf is below that at v = 0,
+ * else the item starts from v = 0 (report.fallback = 1).  opts NULL: defaults.  report (array of B, may be NULL) receives one
  * report per item.  Each item stops on its own criteria; the call returns when all have stopped.
  * Returns SLNK_OK when every item met a stop criterion or the Newton limit, else the status of a
  * failed item (SLNK_ELINESEARCH when backtracking failed: that item's velocity is then its last
  * accepted iterate). */
 slnk_status slnk_newton_solve(slnk_ctx* ctx, void* v_inout, const slnk_solve_opts* opts,
                               slnk_solve_report* report);
+
+/* ---- Learned warm start -----------------------------------------------------------------------
+ * A periodic convolutional U-Net (a form added to the paper's method): input (m_R, m_T), output
+ * an initial velocity v_0 [2][H][W] for the Newton--Krylov solve.  'levels' resolutions (H and W
+ * divisible by 2^(levels-1), the coarsest H W a multiple of 64), base_channels C (a multiple of
+ * 32) doubling per level, two 3x3 periodic convolutions + ReLU per level, 2x2 average pooling,
+ * nearest upsampling with concatenated skips, a linear 3x3 output convolution.  Weights and
+ * activations are BF16 on the matrix cores with FP32 sums; Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8) updates FP32 master weights.  Parameters: one FP32 array of slnk_unet_param_count
+ * values; layer k (encoder levels first, then decoder levels from coarse to fine, then the
+ * output layer) holds W[9][cout][cin] (tap 3 (dy + 1) + (dx + 1) reads pixel (y + dy, x + dx))
+ * then bias[cout], each padded to a multiple of 64 values.  All arrays are device FP32 unless
+ * stated; calls enqueue on the network's stream, train_step and the parameter copies synchronise
+ * it.  A network is used by one host thread at a time. */
+typedef struct slnk_unet slnk_unet;
+typedef struct {
+  int height, width;
+  int levels;
+  int base_channels;
+  int max_batch;                 /* largest batch of any call */
+  unsigned long long seed;       /* SplitMix64 seed of the He-uniform initialisation */
+  int start_kmax;                /* learned solve: Fourier modes |k| <= start_kmax of the network's
+                                    velocity are kept as the start (0: all); the regulariser
+                                    beta A weighs the others by up to beta |k|^(2 reg) */
+} slnk_unet_params;
+
+void slnk_unet_default_params(slnk_unet_params* p);  /* 256 x 256, 4 levels, 32 channels, batch 16 */
+slnk_status slnk_unet_create(const slnk_unet_params* p, void* hip_stream, slnk_unet** out);
+void slnk_unet_destroy(slnk_unet* u);
+const char* slnk_unet_last_error(const slnk_unet* u);
+long long slnk_unet_param_count(const slnk_unet* u);
+/* host FP32 arrays of slnk_unet_param_count values; set_params also resets the Adam moments */
+slnk_status slnk_unet_get_params(slnk_unet* u, float* host);
+slnk_status slnk_unet_set_params(slnk_unet* u, const float* host);
+/* gradient of the loss of the last train_step with respect to every parameter (host FP32) */
+slnk_status slnk_unet_get_grads(slnk_unet* u, float* host);
+/* v [batch][2][H][W] = network(m_R, m_T), images [batch][H][W] */
+slnk_status slnk_unet_forward(slnk_unet* u, int batch, const float* m_R, const float* m_T, float* v);
+/* one step on the mean squared error mean((v - v_target)^2) over batch x 2 x H x W: forward,
+ * backward and (lr > 0) one Adam step; *loss (may be NULL) receives the loss before the step */
+slnk_status slnk_unet_train_step(slnk_unet* u, int batch, const float* m_R, const float* m_T,
+                                 const float* v_target, double lr, double* loss);
+/* Learned solve of a mixed-precision context whose grid matches the network: v_out (device,
+ * [B][2][n1][n2]) = the modes |k| <= start_kmax of network(m_R, m_T) for every item, then
+ * slnk_newton_solve from there (with its fallback to v = 0).  The report times include the
+ * network's forward pass. */
+slnk_status slnk_newton_solve_learned(slnk_ctx* ctx, slnk_unet* u, void* v_out, const slnk_solve_opts* opts,
+                                      slnk_solve_report* report);
 
 /* ---- Ragged batches ---------------------------------------------------------------------------
  * A batch holds npairs independent problems whose grids may differ in size.  Pairs of one size

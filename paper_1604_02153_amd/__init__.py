@@ -11,7 +11,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["Context", "BatchContext", "library_path", "load_library", "SolveOpts", "STATUS"]
+__all__ = ["Context", "BatchContext", "UNet", "library_path", "load_library", "SolveOpts", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -45,7 +45,14 @@ class SolveReport(ctypes.Structure):
                 ("J", ctypes.c_double * (REPORT_MAX + 1)), ("pcg", ctypes.c_int * (REPORT_MAX + 1)),
                 ("time_total_ms", ctypes.c_double), ("time_gradient_ms", ctypes.c_double),
                 ("time_pcg_ms", ctypes.c_double), ("time_precond_ms", ctypes.c_double),
-                ("time_linesearch_ms", ctypes.c_double), ("time_to_stop_ms", ctypes.c_double)]
+                ("time_linesearch_ms", ctypes.c_double), ("time_to_stop_ms", ctypes.c_double),
+                ("fallback", ctypes.c_int)]
+
+
+class UNetParams(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int), ("width", ctypes.c_int), ("levels", ctypes.c_int),
+                ("base_channels", ctypes.c_int), ("max_batch", ctypes.c_int), ("seed", ctypes.c_ulonglong),
+                ("start_kmax", ctypes.c_int)]
 
 
 EXPORTS = ["slnk_default_params", "slnk_default_opts", "slnk_create", "slnk_destroy", "slnk_last_error",
@@ -53,7 +60,10 @@ EXPORTS = ["slnk_default_params", "slnk_default_opts", "slnk_create", "slnk_dest
            "slnk_hessian_matvec", "slnk_split_matvec", "slnk_precond_apply", "slnk_get_cheb_bounds",
            "slnk_get_field", "slnk_time_kernel", "slnk_newton_solve", "slnk_batch_create", "slnk_batch_destroy",
            "slnk_batch_last_error", "slnk_batch_bucket_info", "slnk_batch_set_images", "slnk_batch_gradient",
-           "slnk_batch_hessian_matvec", "slnk_batch_newton_solve", "slnk_batch_autotune"]
+           "slnk_batch_hessian_matvec", "slnk_batch_newton_solve", "slnk_batch_autotune", "slnk_unet_default_params",
+           "slnk_unet_create", "slnk_unet_destroy", "slnk_unet_last_error", "slnk_unet_param_count",
+           "slnk_unet_get_params", "slnk_unet_set_params", "slnk_unet_get_grads", "slnk_unet_forward",
+           "slnk_unet_train_step", "slnk_newton_solve_learned"]
 
 
 def library_path() -> str:
@@ -97,6 +107,17 @@ def load_library():
         "slnk_batch_hessian_matvec": (ctypes.c_int, [V, P(V), P(V)]),
         "slnk_batch_newton_solve": (ctypes.c_int, [V, P(V), P(SolveOpts), P(SolveReport)]),
         "slnk_batch_autotune": (ctypes.c_int, [V, P(V), ctypes.c_int, P(ctypes.c_double)]),
+        "slnk_unet_default_params": (None, [P(UNetParams)]),
+        "slnk_unet_create": (ctypes.c_int, [P(UNetParams), V, P(V)]),
+        "slnk_unet_destroy": (None, [V]),
+        "slnk_unet_last_error": (ctypes.c_char_p, [V]),
+        "slnk_unet_param_count": (ctypes.c_longlong, [V]),
+        "slnk_unet_get_params": (ctypes.c_int, [V, V]),
+        "slnk_unet_set_params": (ctypes.c_int, [V, V]),
+        "slnk_unet_get_grads": (ctypes.c_int, [V, V]),
+        "slnk_unet_forward": (ctypes.c_int, [V, ctypes.c_int, V, V, V]),
+        "slnk_unet_train_step": (ctypes.c_int, [V, ctypes.c_int, V, V, V, ctypes.c_double, P(ctypes.c_double)]),
+        "slnk_newton_solve_learned": (ctypes.c_int, [V, V, V, P(SolveOpts), P(SolveReport)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -242,6 +263,17 @@ class Context:
         out = [self._report(r) for r in reps]
         return out[0] if self.batch == 1 else out
 
+    def newton_solve_learned(self, unet, v, opts: SolveOpts | None = None, **kw):
+        """Warm start v = unet(m_R, m_T) (written into v), then the Newton--Krylov solve."""
+        if opts is None:
+            opts = default_opts(**kw)
+        reps = (SolveReport * self.batch)()
+        st = self._lib.slnk_newton_solve_learned(self._ctx, unet._u, self._ptr(v, 2), ctypes.byref(opts), reps)
+        if st not in (0, 5):
+            self._check(st)
+        out = [self._report(r) for r in reps]
+        return out[0] if self.batch == 1 else out
+
     @staticmethod
     def _report(rep) -> dict:
         k = rep.newton_iters
@@ -253,6 +285,7 @@ class Context:
             "time_total_ms": rep.time_total_ms, "time_gradient_ms": rep.time_gradient_ms,
             "time_pcg_ms": rep.time_pcg_ms, "time_precond_ms": rep.time_precond_ms,
             "time_linesearch_ms": rep.time_linesearch_ms, "time_to_stop_ms": rep.time_to_stop_ms,
+            "fallback": bool(rep.fallback),
         }
 
 
@@ -350,3 +383,103 @@ class BatchContext:
         if st not in (0, 5):
             self._check(st)
         return [Context._report(r) for r in reps]
+
+
+class UNet:
+    """The learned warm start (include/slnk.h): a periodic conv U-Net on BF16 matrix cores.
+    Images are float32 CUDA tensors [batch, H, W]; velocities [batch, 2, H, W]."""
+
+    def __init__(self, height=256, width=256, levels=4, base_channels=32, max_batch=16, seed=0xC0FFEE, stream=None,
+                 start_kmax=8):
+        import torch
+        lib = load_library()
+        p = UNetParams()
+        lib.slnk_unet_default_params(ctypes.byref(p))
+        p.height, p.width, p.levels = int(height), int(width), int(levels)
+        p.base_channels, p.max_batch, p.seed = int(base_channels), int(max_batch), int(seed)
+        p.start_kmax = int(start_kmax)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.params = p
+        self._lib = lib
+        self._u = ctypes.c_void_p()
+        st = lib.slnk_unet_create(ctypes.byref(p), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(self._u))
+        if st != 0:
+            raise SlnkError(st, "slnk_unet_create failed (sizes, channels or memory)")
+        self.n_params = int(lib.slnk_unet_param_count(self._u))
+
+    def _check(self, st):
+        if st != 0:
+            raise SlnkError(st, self._lib.slnk_unet_last_error(self._u).decode())
+
+    def _ptr(self, t, shape):
+        import torch
+        if not t.is_cuda or t.dtype != torch.float32 or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous float32 CUDA tensor of shape {tuple(shape)}, got "
+                             f"{t.dtype} {tuple(t.shape)}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def close(self):
+        if self._u:
+            self._lib.slnk_unet_destroy(self._u)
+            self._u = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._check(self._lib.slnk_unet_get_params(self._u, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def set_params(self, w):
+        import numpy as np
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        if w.shape != (self.n_params,):
+            raise ValueError(f"expected {self.n_params} parameters, got {w.shape}")
+        self._check(self._lib.slnk_unet_set_params(self._u, w.ctypes.data_as(ctypes.c_void_p)))
+
+    def get_grads(self):
+        import numpy as np
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._check(self._lib.slnk_unet_get_grads(self._u, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def forward(self, m_R, m_T, v):
+        b, h, w = m_R.shape
+        self._check(self._lib.slnk_unet_forward(self._u, int(b), self._ptr(m_R, (b, h, w)), self._ptr(m_T, (b, h, w)),
+                                                self._ptr(v, (b, 2, h, w))))
+
+    def train_step(self, m_R, m_T, v_target, lr):
+        b, h, w = m_R.shape
+        loss = ctypes.c_double()
+        self._check(self._lib.slnk_unet_train_step(self._u, int(b), self._ptr(m_R, (b, h, w)),
+                                                   self._ptr(m_T, (b, h, w)), self._ptr(v_target, (b, 2, h, w)),
+                                                   float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def save(self, path):
+        """Parameters as a raw little-endian float32 file with a small text header."""
+        import numpy as np
+        w = self.get_params()
+        p = self.params
+        with open(path, "wb") as f:
+            hdr = f"SLNKUNET1 {p.height} {p.width} {p.levels} {p.base_channels} {self.n_params}\n".encode()
+            f.write(hdr)
+            f.write(w.astype("<f4").tobytes())
+
+    def load(self, path):
+        import numpy as np
+        with open(path, "rb") as f:
+            hdr = f.readline().decode().split()
+            p = self.params
+            want = ["SLNKUNET1", str(p.height), str(p.width), str(p.levels), str(p.base_channels), str(self.n_params)]
+            if hdr != want:
+                raise ValueError(f"{path}: header {hdr} does not match this network {want}")
+            w = np.frombuffer(f.read(), dtype="<f4")
+        self.set_params(w)

@@ -21,6 +21,7 @@
 
 #include "../../include/slnk.h"
 #include "kernels.hpp"
+#include "unet_net.hpp"
 
 namespace slnk {
 
@@ -1045,16 +1046,33 @@ struct Context {
     }
     // start point
     HIPCHK(norms<T>(stream, B, n, v, partial, dres));
-    const double* nv = fetch(0);
+    const double* r0 = fetch(0);
+    const std::vector<double> nv(r0, r0 + 4 * B);
     bool warm = false;
     for (int z = 0; z < B; ++z) {
       if (nv[4 * z + 2] > 0) throw Fail{SLNK_ENAN, "non-finite initial velocity"};
       if (nv[4 * z + 1] > 0.0) warm = true;
     }
+    std::vector<int> fallback(B, 0);
     if (warm) {
       linearize(fine, 0, v, true, nullptr, nullptr, {});
-      gradient(fine, nullptr, {}, g2, ginf);
+      std::vector<double> g2w, ginfw;
+      gradient(fine, nullptr, {}, g2w, ginfw);
+      // keep a start only where it lowers ||g||_inf; elsewhere start again from v = 0
+      for (int z = 0; z < B; ++z) {
+        fallback[z] = nv[4 * z + 1] > 0.0 && !(ginfw[z] < ginf[z]);
+        if (!fallback[z]) g2[z] = g2w[z], ginf[z] = ginfw[z];
+      }
+      if (any_of(fallback)) {
+        put_mask(kMaskLs, fallback);
+        linearize(fine, 0, zero, true, nullptr, mask(kMaskLs), fallback);
+        std::vector<double> g2f, ginff;
+        gradient(fine, mask(kMaskLs), fallback, g2f, ginff);
+        for (int z = 0; z < B; ++z)
+          if (fallback[z]) g2[z] = g2f[z], ginf[z] = ginff[z];
+      }
     }
+    for (int z = 0; z < B; ++z) R[z].fallback = fallback[z];
     t_grad += now_ms() - t0;
     std::vector<int> active(B, 1), kit(B, 0), status(B, SLNK_OK);
     std::vector<double> t_stop(B, 0.0);
@@ -1435,6 +1453,43 @@ slnk_status slnk_newton_solve(slnk_ctx* ctx, void* v_inout, const slnk_solve_opt
     if (!C.images_set) throw slnk::Fail{SLNK_EINVAL, "slnk_set_images must come first"};
     if (o.max_newton < 0 || o.max_pcg < 1 || o.max_halvings < 0) throw slnk::Fail{SLNK_EINVAL, "bad options"};
     result = C.newton(static_cast<T*>(v_inout), o, report);
+  });
+  return st != SLNK_OK ? st : result;
+}
+
+slnk_status slnk_newton_solve_learned(slnk_ctx* ctx, slnk_unet* u, void* v_out, const slnk_solve_opts* opts,
+                                      slnk_solve_report* report) {
+  if (!ctx || !u || !v_out) return SLNK_EINVAL;
+  if (!ctx->f) {
+    ctx->err = "the learned solve needs a mixed-precision (FP32 field) context";
+    return SLNK_EINVAL;
+  }
+  slnk_solve_opts o;
+  slnk_default_opts(&o);
+  if (opts) o = *opts;
+  slnk_status result = SLNK_OK;
+  slnk_status st = guarded(ctx, [&] {
+    auto& C = *ctx->f;
+    if (!C.images_set) throw slnk::Fail{SLNK_EINVAL, "slnk_set_images must come first"};
+    if (o.max_newton < 0 || o.max_pcg < 1 || o.max_halvings < 0) throw slnk::Fail{SLNK_EINVAL, "bad options"};
+    const double t0 = slnk::now_ms();
+    const slnk_status fs = slnk_unet_forward_on(u, C.stream, C.B, C.fine.n1, C.fine.n2, C.fine.mR, C.fine.mT,
+                                                   static_cast<float*>(v_out));
+    if (fs != SLNK_OK) throw slnk::Fail{fs, std::string("network: ") + slnk_unet_last_error(u)};
+    const int kmax = slnk_unet_start_kmax(u);
+    if (kmax > 0) {
+      slnk::SymbolParams sp{slnk::Symbol::Cutoff, C.prm.reg, C.prm.beta, kmax};
+      HIPCHK(slnk::spec_scale<float>(C.stream, C.fine.sg, C.B, nullptr, sp, 2, static_cast<const float*>(v_out),
+                                     static_cast<float*>(v_out), nullptr, C.fine.S1, C.fine.S2));
+    }
+    HIPCHK(hipStreamSynchronize(C.stream));
+    const double t_net = slnk::now_ms() - t0;
+    result = C.newton(static_cast<float*>(v_out), o, report);
+    if (report)
+      for (int z = 0; z < C.B; ++z) {
+        report[z].time_total_ms += t_net;
+        report[z].time_to_stop_ms += t_net;
+      }
   });
   return st != SLNK_OK ? st : result;
 }

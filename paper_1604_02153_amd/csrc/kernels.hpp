@@ -36,12 +36,14 @@ enum class Symbol : int {
   LowPass = 3,    // 1 for |k1| < n1/4 and |k2| < n2/4, else 0
   HighPass = 4,   // 1 - LowPass
   Spline = 5,     // 1 / (B1(k1) B2(k2)), B(k) = (2 + cos(2 pi k / n)) / 3  (B-spline prefilter)
+  Cutoff = 6,     // 1 for k1^2 + k2^2 <= kmax^2, else 0 (smooth part of a field)
 };
 
 struct SymbolParams {
   Symbol kind = Symbol::Reg;
   int reg = 2;
   double beta = 1.0;
+  int kmax = 0;
 };
 
 // Largest dynamic LDS (bytes) a spectral launch on an n1 x n2 grid asks for.

@@ -410,6 +410,8 @@ __device__ __forceinline__ T symbol_value(const SymbolParams& sp, int k1, int n1
       return (4 * abs(k1) < n1 && 4 * abs(k2) < n2) ? T(1) : T(0);
     case Symbol::HighPass:
       return (4 * abs(k1) < n1 && 4 * abs(k2) < n2) ? T(0) : T(1);
+    case Symbol::Cutoff:
+      return (k1 * k1 + k2 * k2 <= sp.kmax * sp.kmax) ? T(1) : T(0);
     case Symbol::Spline:
     default:
       return T(1) / spline_symbol<T>(k1, n1, k2, n2);

@@ -1,0 +1,429 @@
+// Convolutional U-Net kernels on the gfx950 BF16 matrix cores (warm start of the Newton--Krylov
+// solve; a form added to the paper's method).  Activations are NHWC BF16 ("views": base pointer,
+// channels per pixel, channel offset, so that a concatenation is two views into one tensor),
+// weights are [tap][out][in] BF16 with FP32 master copies, accumulation is FP32.
+//
+// Convolutions are 3x3 with periodic (circular) padding -- the images live on the torus -- and
+// run as implicit GEMMs on v_mfma_f32_16x16x32_bf16: M = output pixels, N = output channels,
+// K = 9 taps x input channels.  Lane l of a wavefront supplies row l%16 and the eight K values
+// 8(l/16)..8(l/16)+7 of the A tile, column l%16 and the same K values of the B tile, and receives
+// rows 4(l/16)..4(l/16)+3 of column l%16 of the 16x16 result.
+#include "unet_kernels.hpp"
+
+namespace slnk {
+namespace unet {
+namespace {
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(bf16 h) { return __uint_as_float(unsigned(h) << 16); }
+// round to nearest even (finite values)
+__device__ __forceinline__ bf16 f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return bf16(u >> 16);
+}
+
+__device__ __forceinline__ v8bf load8(const bf16* p) { return *reinterpret_cast<const v8bf*>(p); }
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// ---- convolution (forward, and input gradient with transformed weights) ----------------------
+// Block: four wavefronts along pixels, each 16 MW pixels x 32 output channels (MW x 2 MFMA tiles).
+template <int MW>
+__global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int HW = a.H * a.W;
+  const int pbase = (blockIdx.x * 4 + wave) * (16 * MW);
+  const int cobase = blockIdx.y * 32;
+  int pb[MW], py[MW], px[MW];
+#pragma unroll
+  for (int i = 0; i < MW; ++i) {
+    const int p = pbase + 16 * i + r;
+    pb[i] = p / HW;
+    const int rem = p - pb[i] * HW;
+    py[i] = rem / a.W;
+    px[i] = rem - py[i] * a.W;
+  }
+  v4f acc[MW][2];
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < 9; ++t) {
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    const bf16* src[MW];
+#pragma unroll
+    for (int i = 0; i < MW; ++i) {
+      const int yy = wrap(py[i] + dy, a.H), xx = wrap(px[i] + dx, a.W);
+      src[i] = a.x + (size_t(pb[i]) * HW + size_t(yy) * a.W + xx) * a.xcs + a.xco + 8 * g;
+    }
+    const bf16* wr[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) wr[j] = a.w + (size_t(t) * a.cout + cobase + 16 * j + r) * a.cin + 8 * g;
+#pragma unroll 2
+    for (int kc = 0; kc < a.cin; kc += 32) {
+      v8bf av[MW], bv[2];
+#pragma unroll
+      for (int i = 0; i < MW; ++i) av[i] = load8(src[i] + kc);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = load8(wr[j] + kc);
+#pragma unroll
+      for (int i = 0; i < MW; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int co = cobase + 16 * j + r;
+      const float bias = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int p = pbase + 16 * i + 4 * g + q;
+        float v = acc[i][j][q] + bias;
+        if (a.relu) v = fmaxf(v, 0.f);
+        if (a.y) a.y[size_t(p) * a.ycs + a.yco + co] = f2bf(v);
+        if (a.v && co < a.nv) {
+          const int b = p / HW;
+          a.v[(size_t(b) * a.nv + co) * HW + (p - b * HW)] = v;
+        }
+      }
+    }
+}
+
+// ---- weight gradient ----------------------------------------------------------------------------
+// Partial sums over one pixel chunk of dW[t][co][ci] = sum_p dY[p][co] X[p + d_t][ci] for a 32x32
+// (co, ci) tile and one tap; 128-pixel slabs are staged in LDS transposed to [channel][pixel] so
+// that every lane reads eight consecutive pixels of one channel.
+constexpr int kSlab = 128;
+constexpr int kSlabPad = kSlab + 8;  // row stride: keeps 16-byte alignment, spreads LDS banks
+
+__global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
+  __shared__ bf16 sD[32][kSlabPad];
+  __shared__ bf16 sX[32][kSlabPad];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int wy = wave >> 1, wx = wave & 1;
+  const int nci = a.cin / 32;
+  const int co0 = (blockIdx.x / nci) * 32, ci0 = (blockIdx.x % nci) * 32;
+  const int t = blockIdx.y, dy = t / 3 - 1, dx = t % 3 - 1;
+  const int p0 = blockIdx.z * a.chunk;
+  const int p1 = min(a.P, p0 + a.chunk);
+  const int HW = a.H * a.W;
+  v4f acc = {0.f, 0.f, 0.f, 0.f};
+  for (int ps = p0; ps < p1; ps += kSlab) {
+#pragma unroll
+    for (int rep = 0; rep < 2; ++rep) {
+      const int idx = threadIdx.x + 256 * rep;  // 128 pixels x 4 groups of 8 channels
+      const int pl = idx >> 2, c8 = (idx & 3) * 8;
+      const int p = ps + pl;
+      uint4 dv = {0u, 0u, 0u, 0u}, xv = {0u, 0u, 0u, 0u};
+      if (p < p1) {
+        dv = *reinterpret_cast<const uint4*>(a.dy + size_t(p) * a.dcs + a.dco + co0 + c8);
+        const int b = p / HW, rem = p - b * HW;
+        const int y = rem / a.W, x = rem - (rem / a.W) * a.W;
+        const int yy = wrap(y + dy, a.H), xx = wrap(x + dx, a.W);
+        xv = *reinterpret_cast<const uint4*>(a.x + (size_t(b) * HW + size_t(yy) * a.W + xx) * a.xcs + a.xco + ci0 +
+                                              c8);
+      }
+      const bf16* dh = reinterpret_cast<const bf16*>(&dv);
+      const bf16* xh = reinterpret_cast<const bf16*>(&xv);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        sD[c8 + e][pl] = dh[e];
+        sX[c8 + e][pl] = xh[e];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kSlab; kk += 32) {
+      const v8bf av = load8(&sD[16 * wy + r][kk + 8 * g]);
+      const v8bf bv = load8(&sX[16 * wx + r][kk + 8 * g]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int co = co0 + 16 * wy + 4 * g + q, ci = ci0 + 16 * wx + r;
+    a.partial[((size_t(blockIdx.z) * 9 + t) * a.cout + co) * a.cin + ci] = acc[q];
+  }
+}
+
+// bias gradient partials: partial[z][c] = sum over chunk z of dY[p][c]
+__global__ void __launch_bounds__(256) k_bgrad(const bf16* dy, int dcs, int dco, int C, int P, int chunk,
+                                               float* partial) {
+  const int p0 = blockIdx.x * chunk, p1 = min(P, p0 + chunk);
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    float s = 0.f;
+    for (int p = p0; p < p1; ++p) s += bf2f(dy[size_t(p) * dcs + dco + c]);
+    partial[size_t(blockIdx.x) * C + c] = s;
+  }
+}
+
+// out[i] = sum_z partial[z][i] (fixed order), i < n
+__global__ void k_sum_splits(const float* partial, int splits, size_t n, float* out) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += partial[size_t(z) * n + i];
+    out[i] = s;
+  }
+}
+
+// Wd[t][ci][co] = W[8 - t][co][ci]: the input gradient is the convolution of dY with the
+// spatially flipped, channel-transposed kernel
+__global__ void k_wtrans(const bf16* w, int cout, int cin, bf16* wd) {
+  const size_t n = size_t(9) * cout * cin;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const int co = int(i % cout);
+    const int ci = int((i / cout) % cin);
+    const int t = int(i / (size_t(cout) * cin));
+    wd[i] = w[(size_t(8 - t) * cout + co) * cin + ci];
+  }
+}
+
+// dY[p][c] = 0 where Y[p][c] <= 0 (ReLU derivative), C channels of two views
+__global__ void k_relu_mask(bf16* dy, int dcs, int dco, const bf16* y, int ycs, int yco, int C, int P) {
+  const size_t n = size_t(P) * C;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const size_t p = i / C;
+    const int c = int(i % C);
+    if (!(bf2f(y[p * ycs + yco + c]) > 0.f)) dy[p * dcs + dco + c] = 0;
+  }
+}
+
+// 2x2 average pooling: out [B][H/2][W/2] from in [B][H][W] (H, W of the input)
+__global__ void k_pool(const bf16* x, int xcs, int xco, bf16* y, int ycs, int yco, int C, int B, int H, int W) {
+  const int Ho = H / 2, Wo = W / 2;
+  const size_t n = size_t(B) * Ho * Wo * C;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const int c = int(i % C);
+    const size_t po = i / C;
+    const int xo = int(po % Wo), yo = int((po / Wo) % Ho), b = int(po / (size_t(Wo) * Ho));
+    float s = 0.f;
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx)
+        s += bf2f(x[((size_t(b) * H + 2 * yo + dy) * W + 2 * xo + dx) * xcs + xco + c]);
+    y[po * ycs + yco + c] = f2bf(0.25f * s);
+  }
+}
+
+// gradient of the pooling, accumulated: dX[2y+i][2x+j] += dY[y][x] / 4
+__global__ void k_pool_bwd_add(const bf16* dy, int dcs, int dco, bf16* dx, int xcs, int xco, int C, int B, int H,
+                               int W) {
+  const size_t n = size_t(B) * H * W * C;  // input resolution
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const int c = int(i % C);
+    const size_t p = i / C;
+    const int x = int(p % W), y = int((p / W) % H), b = int(p / (size_t(W) * H));
+    const float gsrc = bf2f(dy[((size_t(b) * (H / 2) + y / 2) * (W / 2) + x / 2) * dcs + dco + c]);
+    bf16* d = dx + p * xcs + xco + c;
+    *d = f2bf(bf2f(*d) + 0.25f * gsrc);
+  }
+}
+
+// nearest-neighbour upsampling by 2: out [B][2H][2W] from in [B][H][W]
+__global__ void k_up(const bf16* x, int xcs, int xco, bf16* y, int ycs, int yco, int C, int B, int H, int W) {
+  const size_t n = size_t(B) * 4 * H * W * C;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const int c = int(i % C);
+    const size_t p = i / C;
+    const int xo = int(p % (2 * W)), yo = int((p / (2 * W)) % (2 * H)), b = int(p / (size_t(4) * H * W));
+    y[p * ycs + yco + c] = x[((size_t(b) * H + yo / 2) * W + xo / 2) * xcs + xco + c];
+  }
+}
+
+// gradient of the upsampling: dX[y][x] = sum of the four dY it was copied to
+__global__ void k_up_bwd(const bf16* dy, int dcs, int dco, bf16* dx, int xcs, int xco, int C, int B, int H, int W) {
+  const size_t n = size_t(B) * H * W * C;  // low resolution
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const int c = int(i % C);
+    const size_t p = i / C;
+    const int x = int(p % W), y = int((p / W) % H), b = int(p / (size_t(W) * H));
+    float s = 0.f;
+    for (int dy2 = 0; dy2 < 2; ++dy2)
+      for (int dx2 = 0; dx2 < 2; ++dx2)
+        s += bf2f(dy[((size_t(b) * 2 * H + 2 * y + dy2) * 2 * W + 2 * x + dx2) * dcs + dco + c]);
+    dx[p * xcs + xco + c] = f2bf(s);
+  }
+}
+
+// network input: channels (m_R, m_T, m_R - m_T, 0, ...) of a C-channel tensor
+__global__ void k_prep(const float* mr, const float* mt, bf16* x, int C, size_t P) {
+  for (size_t p = size_t(blockIdx.x) * blockDim.x + threadIdx.x; p < P; p += size_t(gridDim.x) * blockDim.x) {
+    const float a = mr[p], b = mt[p];
+    bf16* o = x + p * C;
+    o[0] = f2bf(a);
+    o[1] = f2bf(b);
+    o[2] = f2bf(a - b);
+    for (int c = 3; c < C; ++c) o[c] = 0;
+  }
+}
+
+// loss = mean (v - target)^2 over B x 2 x H x W; gradient into the C-channel BF16 tensor dv
+// (channels >= 2 zero); per-block FP64 partial sums
+__global__ void __launch_bounds__(256) k_loss(const float* v, const float* tgt, int B, int HW, int C, bf16* dv,
+                                              double* partial) {
+  __shared__ double red[256];
+  const size_t P = size_t(B) * HW;
+  const float scale = 2.f / float(2 * P);
+  double s = 0.0;
+  for (size_t p = size_t(blockIdx.x) * blockDim.x + threadIdx.x; p < P; p += size_t(gridDim.x) * blockDim.x) {
+    const size_t b = p / HW, q = p % HW;
+    bf16* o = dv + p * C;
+    for (int c = 0; c < 2; ++c) {
+      const size_t k = (b * 2 + c) * HW + q;
+      const float d = v[k] - tgt[k];
+      s += double(d) * d;
+      o[c] = f2bf(scale * d);
+    }
+    for (int c = 2; c < C; ++c) o[c] = 0;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_double(const double* partial, int n, double scale, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += partial[i];
+    *out = s * scale;
+  }
+}
+
+// Adam (Kingma & Ba) on the FP32 master parameters, BF16 mirror written alongside
+__global__ void k_adam(float* w, bf16* wb, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    wb[i] = f2bf(wi);
+  }
+}
+
+__global__ void k_to_bf16(const float* w, bf16* wb, size_t n) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    wb[i] = f2bf(w[i]);
+}
+
+inline unsigned blocks_for(size_t n) {
+  size_t b = (n + 255) / 256;
+  return unsigned(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+}  // namespace
+
+hipError_t conv(hipStream_t s, const ConvArgs& a) {
+  const int HW = a.H * a.W;
+  if (a.cin % 32 || a.cout % 32 || a.xcs % 8 || a.xco % 8 || HW % 64 || a.P % HW) return hipErrorInvalidValue;
+  if (HW % 128 == 0) {
+    hipLaunchKernelGGL(k_conv<2>, dim3(a.P / 128, a.cout / 32), dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_conv<1>, dim3(a.P / 64, a.cout / 32), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+int wgrad_splits(int P, int chunk) { return (P + chunk - 1) / chunk; }
+
+hipError_t wgrad(hipStream_t s, const WgradArgs& a) {
+  if (a.cin % 32 || a.cout % 32 || a.xcs % 8 || a.xco % 8 || a.dcs % 8 || a.dco % 8 || a.chunk % kSlab)
+    return hipErrorInvalidValue;
+  const int splits = wgrad_splits(a.P, a.chunk);
+  hipLaunchKernelGGL(k_wgrad, dim3((a.cout / 32) * (a.cin / 32), 9, splits), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t bgrad(hipStream_t s, const bf16* dy, int dcs, int dco, int C, int P, int chunk, float* partial) {
+  hipLaunchKernelGGL(k_bgrad, dim3((P + chunk - 1) / chunk), dim3(256), 0, s, dy, dcs, dco, C, P, chunk, partial);
+  return hipGetLastError();
+}
+
+hipError_t sum_splits(hipStream_t s, const float* partial, int splits, size_t n, float* out) {
+  hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for(n)), dim3(256), 0, s, partial, splits, n, out);
+  return hipGetLastError();
+}
+
+hipError_t wtrans(hipStream_t s, const bf16* w, int cout, int cin, bf16* wd) {
+  hipLaunchKernelGGL(k_wtrans, dim3(blocks_for(size_t(9) * cout * cin)), dim3(256), 0, s, w, cout, cin, wd);
+  return hipGetLastError();
+}
+
+hipError_t relu_mask(hipStream_t s, bf16* dy, int dcs, int dco, const bf16* y, int ycs, int yco, int C, int P) {
+  hipLaunchKernelGGL(k_relu_mask, dim3(blocks_for(size_t(P) * C)), dim3(256), 0, s, dy, dcs, dco, y, ycs, yco, C, P);
+  return hipGetLastError();
+}
+
+hipError_t pool(hipStream_t s, const bf16* x, int xcs, int xco, bf16* y, int ycs, int yco, int C, int B, int H,
+                int W) {
+  hipLaunchKernelGGL(k_pool, dim3(blocks_for(size_t(B) * H * W * C / 4)), dim3(256), 0, s, x, xcs, xco, y, ycs, yco,
+                     C, B, H, W);
+  return hipGetLastError();
+}
+
+hipError_t pool_bwd_add(hipStream_t s, const bf16* dy, int dcs, int dco, bf16* dx, int xcs, int xco, int C, int B,
+                        int H, int W) {
+  hipLaunchKernelGGL(k_pool_bwd_add, dim3(blocks_for(size_t(B) * H * W * C)), dim3(256), 0, s, dy, dcs, dco, dx, xcs,
+                     xco, C, B, H, W);
+  return hipGetLastError();
+}
+
+hipError_t up(hipStream_t s, const bf16* x, int xcs, int xco, bf16* y, int ycs, int yco, int C, int B, int H, int W) {
+  hipLaunchKernelGGL(k_up, dim3(blocks_for(size_t(B) * 4 * H * W * C)), dim3(256), 0, s, x, xcs, xco, y, ycs, yco, C,
+                     B, H, W);
+  return hipGetLastError();
+}
+
+hipError_t up_bwd(hipStream_t s, const bf16* dy, int dcs, int dco, bf16* dx, int xcs, int xco, int C, int B, int H,
+                  int W) {
+  hipLaunchKernelGGL(k_up_bwd, dim3(blocks_for(size_t(B) * H * W * C)), dim3(256), 0, s, dy, dcs, dco, dx, xcs, xco, C,
+                     B, H, W);
+  return hipGetLastError();
+}
+
+hipError_t prep(hipStream_t s, const float* mr, const float* mt, bf16* x, int C, size_t P) {
+  hipLaunchKernelGGL(k_prep, dim3(blocks_for(P)), dim3(256), 0, s, mr, mt, x, C, P);
+  return hipGetLastError();
+}
+
+int loss_blocks(size_t P) { return int(blocks_for(P) > 1024 ? 1024 : blocks_for(P)); }
+
+hipError_t loss(hipStream_t s, const float* v, const float* tgt, int B, int HW, int C, bf16* dv, double* partial,
+                double* out) {
+  const int nb = loss_blocks(size_t(B) * HW);
+  hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, s, v, tgt, B, HW, C, dv, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_double, dim3(1), dim3(64), 0, s, partial, nb, 1.0 / double(size_t(2) * B * HW), out);
+  return hipGetLastError();
+}
+
+hipError_t adam(hipStream_t s, float* w, bf16* wb, const float* g, float* m, float* v, size_t n, double lr, double b1,
+                double b2, double eps, long long step) {
+  const double c1 = 1.0 - std::pow(b1, double(step)), c2 = 1.0 - std::pow(b2, double(step));
+  hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(256), 0, s, w, wb, g, m, v, n, float(lr), float(b1), float(b2),
+                     float(eps), float(c1), float(c2));
+  return hipGetLastError();
+}
+
+hipError_t to_bf16(hipStream_t s, const float* w, bf16* wb, size_t n) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(n)), dim3(256), 0, s, w, wb, n);
+  return hipGetLastError();
+}
+
+}  // namespace unet
+}  // namespace slnk

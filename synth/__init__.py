@@ -59,11 +59,12 @@ def gaussian_sum_isotropic(n1, n2, rng, count=32, sigma=(0.1, 0.4), amplitude=(0
     centres = rng.uniform(0.0, 2.0 * math.pi, size=(count, 2))
     sig = rng.uniform(sigma[0], sigma[1], size=count)
     amp = rng.uniform(amplitude[0], amplitude[1], size=count)
-    u = np.zeros((n1, n2))
-    for c, s, a in zip(centres, sig, amp):
-        # an isotropic Gaussian is the outer product of two 1-D Gaussians
-        d1 = _wrap(x1 - c[0]); d2 = _wrap(x2 - c[1])
-        u += np.outer(a * np.exp(-d1 * d1 / (2.0 * s * s)), np.exp(-d2 * d2 / (2.0 * s * s)))
+    # an isotropic Gaussian is the outer product of two 1-D Gaussians: the sum is one product of
+    # the (count x n1) and (count x n2) factor matrices
+    d1 = _wrap(x1[None, :] - centres[:, :1])
+    d2 = _wrap(x2[None, :] - centres[:, 1:])
+    inv = 1.0 / (2.0 * sig * sig)[:, None]
+    u = (amp[:, None] * np.exp(-d1 * d1 * inv)).T @ np.exp(-d2 * d2 * inv)
     return _normalise(u)
 
 
@@ -102,13 +103,14 @@ def random_velocity(n1, n2, rng, modes=16, kmax=4, amplitude=0.3):
     pick = rng.choice(len(cand), size=modes, replace=False)
     x1 = 2.0 * math.pi * np.arange(n1) / n1
     x2 = 2.0 * math.pi * np.arange(n2) / n2
-    v = np.zeros((2, n1, n2))
-    for idx in pick:
-        a, b = cand[idx]
-        coef = rng.standard_normal(2) + 1j * rng.standard_normal(2)
-        e1, e2 = np.exp(1j * a * x1), np.exp(1j * b * x2)  # the plane wave factorises
-        v[0] += np.outer(coef[0] * e1, e2).real
-        v[1] += np.outer(coef[1] * e1, e2).real
+    coefs = []
+    for _ in pick:
+        coefs.append(rng.standard_normal(2) + 1j * rng.standard_normal(2))
+    coefs = np.array(coefs)                       # [modes, 2]
+    k = np.array([cand[i] for i in pick])         # [modes, 2]
+    e1 = np.exp(1j * k[:, :1] * x1[None, :])      # the plane wave factorises: [modes, n1]
+    e2 = np.exp(1j * k[:, 1:] * x2[None, :])      # [modes, n2]
+    v = np.stack([((coefs[:, c:c + 1] * e1).T @ e2).real for c in range(2)])
     return v * (amplitude / float(np.max(np.abs(v))))
 
 

@@ -65,7 +65,11 @@ int main(void) {
   F(slnk_solve_report, emax); F(slnk_solve_report, grel); F(slnk_solve_report, J); F(slnk_solve_report, pcg);
   F(slnk_solve_report, time_total_ms); F(slnk_solve_report, time_gradient_ms); F(slnk_solve_report, time_pcg_ms);
   F(slnk_solve_report, time_precond_ms); F(slnk_solve_report, time_linesearch_ms);
-  F(slnk_solve_report, time_to_stop_ms);
+  F(slnk_solve_report, time_to_stop_ms); F(slnk_solve_report, fallback);
+  printf("slnk_unet_params size %zu 0\n", sizeof(slnk_unet_params));
+  F(slnk_unet_params, height); F(slnk_unet_params, width); F(slnk_unet_params, levels);
+  F(slnk_unet_params, base_channels); F(slnk_unet_params, max_batch); F(slnk_unet_params, seed);
+  F(slnk_unet_params, start_kmax);
   return 0;
 }
 """
@@ -77,7 +81,8 @@ def test_ctypes_structs_match_the_header(pkg, tmp_path):
     src.write_text(LAYOUT_PROGRAM)
     subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
-    structs = {"slnk_params": pkg.Params, "slnk_solve_opts": pkg.SolveOpts, "slnk_solve_report": pkg.SolveReport}
+    structs = {"slnk_params": pkg.Params, "slnk_solve_opts": pkg.SolveOpts, "slnk_solve_report": pkg.SolveReport,
+               "slnk_unet_params": pkg.UNetParams}
     seen = {k: [] for k in structs}
     for line in filter(None, out):
         name, field, off, size = line.split()
@@ -123,3 +128,17 @@ def test_calls_reject_null_arguments(pkg):
     assert lib.slnk_newton_solve(None, None, None, None) == 1
     assert lib.slnk_workspace_bytes(None) == 0
     assert lib.slnk_last_error(None) == b"null context"
+
+
+@pytest.mark.parametrize("change", [dict(levels=1), dict(base_channels=16), dict(height=100), dict(max_batch=0),
+                                    dict(height=32, width=32, levels=4)])
+def test_unet_create_rejects_bad_shapes(pkg, change):
+    lib = pkg.load_library()
+    p = pkg.UNetParams()
+    lib.slnk_unet_default_params(ctypes.byref(p))
+    assert (p.height, p.levels, p.base_channels) == (256, 4, 32)
+    for k, v in change.items():
+        setattr(p, k, v)
+    u = ctypes.c_void_p()
+    assert lib.slnk_unet_create(ctypes.byref(p), None, ctypes.byref(u)) == 1
+    assert not u.value

@@ -1,0 +1,153 @@
+"""GPU parity of the learned warm start's network (BF16 MFMA kernels, through the C ABI) against
+the FP64 reference with BF16 rounding mirrored (oracle/unet_oracle.py), and of the warm-started
+solve with its fallback."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synth
+from oracle import unet_oracle as U
+from gpu_common import problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def slnk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1604_02153_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _case(seed, B=2, n=64):
+    rng = np.random.default_rng(seed)
+    mR = np.stack([synth.gaussian_sum_isotropic(n, n, rng) for _ in range(B)]).astype(np.float32)
+    mT = np.stack([synth.gaussian_sum_isotropic(n, n, rng) for _ in range(B)]).astype(np.float32)
+    tgt = np.stack([synth.random_velocity(n, n, rng, amplitude=0.3) for _ in range(B)]).astype(np.float32)
+    return mR, mT, tgt
+
+
+def _net(slnk, arch, params, B=2):
+    net = slnk.UNet(arch.H, arch.W, arch.L, arch.base, max_batch=B)
+    assert net.n_params == arch.n
+    net.set_params(params.astype(np.float32))
+    return net
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 3), (64, 128, 4)])
+def test_forward_matches_reference(slnk, shape):
+    H, W, L = shape
+    arch = U.Arch(H, W, levels=L, base=32)
+    params = U.random_params(arch, np.random.default_rng(1)).astype(np.float32).astype(np.float64)
+    net = _net(slnk, arch, params)
+    mR, mT, _ = _case(2, n=H)
+    if W != H:
+        mR, mT = np.concatenate([mR, mR], axis=2), np.concatenate([mT, mT[:, ::-1]], axis=2)
+    v = torch.empty((2, 2, H, W), dtype=torch.float32, device="cuda")
+    net.forward(_t(mR), _t(mT), v)
+    v_ref, _ = U.forward(arch, params, mR, mT, bf16=True)
+    err = rel(v.cpu().numpy(), v_ref)
+    print(f"forward rel err {err:.2e}", flush=True)
+    assert err < 1e-2
+    net.close()
+
+
+def test_gradients_match_reference(slnk):
+    arch = U.Arch(64, 64, levels=3, base=32)
+    params = U.random_params(arch, np.random.default_rng(3)).astype(np.float32).astype(np.float64)
+    net = _net(slnk, arch, params)
+    mR, mT, tgt = _case(4)
+    loss = net.train_step(_t(mR), _t(mT), _t(tgt), 0.0)
+    g = net.get_grads().astype(np.float64)
+    v_ref, cache = U.forward(arch, params, mR, mT, bf16=True)
+    l_ref, dv = U.mse(v_ref, tgt)
+    g_ref = U.backward(arch, cache, dv, bf16=True)
+    assert abs(loss - l_ref) / l_ref < 1e-3
+    errs = []
+    for k, ly in enumerate(arch.layers):
+        nw = 9 * ly["cout"] * ly["cin"]
+        ew = rel(g[ly["woff"]: ly["woff"] + nw], g_ref[ly["woff"]: ly["woff"] + nw])
+        eb = rel(g[ly["boff"]: ly["boff"] + ly["cout"]], g_ref[ly["boff"]: ly["boff"] + ly["cout"]])
+        errs.append((k, ew, eb))
+    print("per-layer grad rel err", [(k, f"{a:.1e}", f"{b:.1e}") for k, a, b in errs], flush=True)
+    assert all(ew < 3e-2 and eb < 3e-2 for _, ew, eb in errs)
+    assert rel(g, g_ref) < 1e-2
+    net.close()
+
+
+def test_adam_step_matches_reference(slnk):
+    arch = U.Arch(64, 64, levels=3, base=32)
+    params = U.random_params(arch, np.random.default_rng(5)).astype(np.float32).astype(np.float64)
+    net = _net(slnk, arch, params)
+    mR, mT, tgt = _case(6)
+    net.train_step(_t(mR), _t(mT), _t(tgt), 1e-3)
+    g = net.get_grads().astype(np.float64)
+    w1, _, _ = U.adam_step(params, g, np.zeros_like(g), np.zeros_like(g), 1, lr=1e-3)
+    got = net.get_params().astype(np.float64)
+    assert np.max(np.abs(got - w1)) < 1e-6
+    net.close()
+
+
+def test_training_fits_a_learnable_target(slnk):
+    """Adam on a fixed batch whose target is a local function of the input (0.3 (m_R - m_T),
+    0.3 m_T) drives the loss down by an order of magnitude."""
+    net = slnk.UNet(64, 64, 3, 32, max_batch=4, seed=7)
+    mR, mT, _ = _case(8, B=4)
+    tgt = 0.3 * np.stack([mR - mT, mT], axis=1)
+    mR, mT, tgt = _t(mR), _t(mT), _t(tgt)
+    losses = [net.train_step(mR, mT, tgt, 2e-3) for _ in range(80)]
+    print("losses", [f"{x:.3e}" for x in losses[::10]], flush=True)
+    assert losses[-1] < 0.1 * losses[0]
+    net.close()
+
+
+def test_bad_start_falls_back_to_zero(slnk):
+    """A start whose gradient is larger than at v = 0 is replaced by v = 0: the solve then takes
+    exactly the cold-start path."""
+    n = 64
+    L, vgen, _ = problem("smooth", n, n, nt=4, beta=1e-2, reg=1)
+    ctx = slnk.Context(n, n, 4, reg="h1", beta=1e-2, prec="fp64", pc="reg")
+    ctx.set_images(torch.from_numpy(L.mR).cuda(), torch.from_numpy(L.mT).cuda())
+    v0 = torch.zeros((2, n, n), dtype=torch.float64, device="cuda")
+    cold = ctx.newton_solve(v0)
+    vb = torch.from_numpy(-6.0 * vgen).cuda()
+    warm = ctx.newton_solve(vb)
+    assert warm["fallback"] and not cold["fallback"]
+    for key in ("newton_iters", "pcg_iters", "grel", "J"):
+        assert warm[key] == cold[key], key
+    assert torch.equal(vb, v0)
+    ctx.close()
+
+
+def test_learned_solve_with_an_untrained_network(slnk):
+    """The learned solve runs the network on the context's images and solves from its output; an
+    untrained network's near-zero output is either kept or replaced, and the solve converges."""
+    n = 64
+    L, vgen, _ = problem("gauss", n, n, nt=4, beta=1e-3, reg=2, seed=21)
+    mR, mT = L.mR.astype(np.float32), L.mT.astype(np.float32)
+    ctx = slnk.Context(n, n, 4, reg="h2", beta=1e-3, prec="mixed", pc="2l", batch=2)
+    ctx.set_images(_t(np.stack([mR, mR])), _t(np.stack([mT, mT])))
+    net = slnk.UNet(n, n, 3, 32, max_batch=2)
+    v = torch.empty((2, 2, n, n), dtype=torch.float32, device="cuda")
+    reps = ctx.newton_solve_learned(net, v)
+    v_net = torch.empty_like(v)
+    net.forward(_t(np.stack([mR, mR])), _t(np.stack([mT, mT])), v_net)
+    for r in reps:
+        assert r["status"] == "SLNK_OK" and r["grel"][-1] <= 1e-2
+    assert reps[0]["grel"] == reps[1]["grel"]
+    net.close()
+    ctx.close()
