@@ -37,6 +37,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # level (2), read and write the time-integral accumulator (2 + 2), write the new field (1).
 INC_ADJ_FIELDS_PER_POINT = 11
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "sl_step_incadj_gauss256_counters.txt")
+WEIGHTS = os.path.join(ROOT, "paper_1604_02153_amd", "weights", "unet_gauss256.bin")
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1604_02153_amd", "csrc", "transport.hip")
 
 
@@ -51,8 +53,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--matvecs", type=int, default=200, help="isolated matvecs timed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=12, help="oracle matvecs in the CPU sample")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="length of the CPU oracle sample (s)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-pair ragged batch workload")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned vs plain comparison")
+    ap.add_argument("--learned-pairs", type=int, default=32, help="held-out pairs of the learned vs plain timing")
     ap.add_argument("--batched-matvecs", type=int, default=10, help="timed batched matvec calls (64 pairs each)")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: 20 incremental-adjoint SL steps of the 256^2 problem, then a plain "
@@ -183,23 +187,116 @@ def batched(args, dev):
     }
 
 
-def cpu_baseline(cfg, n_matvec):
-    """FP64 oracle (numpy) on the host: GN matvecs at the same linearisation point."""
+def unet_flops(h, w, levels=4, base=32):
+    """Multiply-add flops (2 per MAC) of one forward pass of the U-Net on an h x w pair."""
+    C = [base << l for l in range(levels)]
+    convs = []
+    for l in range(levels):
+        convs += [(32 if l == 0 else C[l - 1], C[l], l), (C[l], C[l], l)]
+    for l in range(levels - 1):
+        convs += [(C[l + 1] + C[l], C[l], l), (C[l], C[l], l)]
+    convs.append((C[0], 32, 0))
+    return sum(2 * 9 * ci * co * (h >> l) * (w >> l) for ci, co, l in convs)
+
+
+def learned(args, dev):
+    """Time to ||g||_rel <= 1e-2 of the plain and the learned solve (network forward + solve from
+    its start, fallback to v = 0) on the 256^2 problem (seed 2) and held-out pairs (seeds 200000...,
+    not seen in training), one pair per context, same GPU."""
     import numpy as np
+    import torch
+
+    from paper_1604_02153_amd import Context, UNet
+    from paper_1604_02153_amd.train_unet import make_pair
+    if not os.path.exists(WEIGHTS):
+        return {"status": "no trained weights at " + os.path.relpath(WEIGHTS, ROOT)}
+    ctx = Context(256, 256, 4, reg="h2", beta=1e-3, prec="mixed", pc="2l", cheb_iters=10, lanczos_steps=30)
+    net = UNet(256, 256, 4, 32, max_batch=1)
+    net.load(WEIGHTS)
+    v = torch.zeros((2, 256, 256), dtype=torch.float32, device=dev)
+    rows = []
+    for i, seed in enumerate([2] + list(range(200000, 200000 + args.learned_pairs))):
+        mT, vg = make_pair(seed)
+        mT, vg = torch.from_numpy(mT).to(dev), torch.from_numpy(vg).to(dev)
+        mR = torch.empty_like(mT)
+        ctx.transport_state(vg, mT, mR)
+        if i == 0:  # warm-up of both paths (graph capture, LDS attributes)
+            ctx.set_images(mR, mT)
+            v.zero_()
+            ctx.newton_solve(v)
+            ctx.set_images_learned(net, mR, mT)
+            ctx.newton_solve_learned(net, v)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.set_images(mR, mT)                   # plain set-up: Lanczos for e_max
+        v.zero_()
+        ts = time.perf_counter()
+        rp = ctx.newton_solve(v)
+        t1 = time.perf_counter()
+        ctx.set_images_learned(net, mR, mT)      # learned set-up: network start + e_max from its head
+        tl = time.perf_counter()
+        rl = ctx.newton_solve_learned(net, v)
+        t2 = time.perf_counter()
+        rows.append((1e3 * (t1 - ts), 1e3 * (t2 - tl), rp["newton_iters"], rl["newton_iters"], rp["pcg_iters"],
+                     rl["pcg_iters"], rl["fallback"], rp["grel"][-1] <= 1e-2, rl["grel"][-1] <= 1e-2,
+                     1e3 * (t1 - t0), 1e3 * (t2 - t1)))
+    a = np.array(rows, dtype=np.float64)
+    # network forward alone (BF16 MFMA), one 256^2 pair
+    mR1, mT1 = mR.reshape(1, 256, 256).contiguous(), mT.reshape(1, 256, 256).contiguous()
+    vo = torch.empty((1, 2, 256, 256), dtype=torch.float32, device=dev)
+    for _ in range(3):
+        net.forward(mR1, mT1, vo)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        net.forward(mR1, mT1, vo)
+    torch.cuda.synchronize()
+    fwd_ms = 1e3 * (time.perf_counter() - t0) / 20
+    tf = unet_flops(256, 256) / (fwd_ms * 1e-3) / 1e12
+    net.close()
+    ctx.close()
+    med = lambda c: round(float(np.median(a[:, c])), 2)
+    return {
+        "workload": f"gauss256 pair (seed 2) + {args.learned_pairs} held-out pairs (seeds 200000...), 256^2, "
+                    "P_2L mixed; learned = U-Net (4 levels, 32 channels, BF16) start from its |k|<=8 modes and "
+                    "e_max from its head; times from the solve call to ||g||rel<=1e-2, and set-up + solve",
+        "seed2_ms": {"plain": round(a[0, 0], 2), "learned": round(a[0, 1], 2)},
+        "median_ms": {"plain": med(0), "learned": med(1)},
+        "median_setup_plus_solve_ms": {"plain": med(9), "learned": med(10)},
+        "mean_ms": {"plain": round(float(a[:, 0].mean()), 2), "learned": round(float(a[:, 1].mean()), 2)},
+        "speedup_median": round(float(np.median(a[:, 0]) / np.median(a[:, 1])), 3),
+        "newton_mean": {"plain": round(float(a[:, 2].mean()), 2), "learned": round(float(a[:, 3].mean()), 2)},
+        "pcg_mean": {"plain": round(float(a[:, 4].mean()), 2), "learned": round(float(a[:, 5].mean()), 2)},
+        "fallback_rate": round(float(a[:, 6].mean()), 3),
+        "reached_grel_1e-2": {"plain": int(a[:, 7].sum()), "learned": int(a[:, 8].sum()), "of": len(rows)},
+        "unet_forward_ms": round(fwd_ms, 3),
+        "unet_roofline": {"bound": "mfma", "achieved": round(tf, 1), "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": round(tf / BF16_MFMA_PEAK_TFLOPS, 4)},
+    }
+
+
+def cpu_baseline(cfg, min_seconds):
+    """FP64 oracle (numpy) on one host thread: GN matvecs at the same linearisation point, repeated
+    until at least min_seconds have passed (the bounded sample)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
 
     import oracle as O
-    g = O.Grid(cfg["n1"], cfg["n2"])
-    L = O.Level(g, cfg["mT"], O.transport_state(g, cfg["v_gen"], cfg["mT"], cfg["nt"]),
-                O.Params(nt=cfg["nt"], beta=cfg["beta"], reg=cfg["reg"]))
-    lin = O.linearize(L, np.zeros((2,) + g.shape))
-    O.hessian_matvec(lin, cfg["vt"])          # warm-up (FFT plans, caches)
-    t0 = time.perf_counter()
-    for _ in range(n_matvec):
-        O.hessian_matvec(lin, cfg["vt"])
-    dt = time.perf_counter() - t0
+    with threadpool_limits(limits=1):
+        g = O.Grid(cfg["n1"], cfg["n2"])
+        L = O.Level(g, cfg["mT"], O.transport_state(g, cfg["v_gen"], cfg["mT"], cfg["nt"]),
+                    O.Params(nt=cfg["nt"], beta=cfg["beta"], reg=cfg["reg"]))
+        lin = O.linearize(L, np.zeros((2,) + g.shape))
+        O.hessian_matvec(lin, cfg["vt"])          # warm-up (FFT plans, caches)
+        n_matvec = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < min_seconds and n_matvec < 2000:
+            O.hessian_matvec(lin, cfg["vt"])
+            n_matvec += 1
+        dt = time.perf_counter() - t0
     return {"value": n_matvec / dt, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_matvec} FP64 GN Hessian matvecs of the 256^2 nt=4 H2 problem at v=0 "
-                      f"({dt:.1f} s, numpy single thread)"}
+                      f"({dt:.1f} s, numpy, BLAS/OpenMP pools limited to one thread)"}
 
 
 def main():
@@ -286,11 +383,14 @@ def main():
         "roofline": roof,
     }
     ctx.close()
+    if not args.no_learned:
+        line["learned_vs_plain"] = learned(args, dev)
+        log("learned vs plain done")
     if not args.no_batched:
         line["batched"] = batched(args, dev)
         log("batched workload done")
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)
+        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
         log("cpu baseline done")
     print(json.dumps(line), flush=True)
 

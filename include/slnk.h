@@ -216,7 +216,11 @@ slnk_status slnk_newton_solve(slnk_ctx* ctx, void* v_inout, const slnk_solve_opt
  * eps 1e-8) updates FP32 master weights.  Parameters: one FP32 array of slnk_unet_param_count
  * values; layer k (encoder levels first, then decoder levels from coarse to fine, then the
  * output layer) holds W[9][cout][cin] (tap 3 (dy + 1) + (dx + 1) reads pixel (y + dy, x + dx))
- * then bias[cout], each padded to a multiple of 64 values.  All arrays are device FP32 unless
+ * then bias[cout], each padded to a multiple of 64 values; last come the scalar head's
+ * w[2 C_top] and bias[1] (each padded to 64), C_top = base_channels 2^(levels-1).  The head reads
+ * the per-channel pixel means (w[0..C_top)) and maxima (w[C_top..2 C_top)) of the coarsest
+ * level's output and predicts y = log(beta (e_max - 1)) of the two-level preconditioner's
+ * Chebyshev bound (the coarse-grid part of the learned form).  All arrays are device FP32 unless
  * stated; calls enqueue on the network's stream, train_step and the parameter copies synchronise
  * it.  A network is used by one host thread at a time. */
 typedef struct slnk_unet slnk_unet;
@@ -241,16 +245,27 @@ slnk_status slnk_unet_get_params(slnk_unet* u, float* host);
 slnk_status slnk_unet_set_params(slnk_unet* u, const float* host);
 /* gradient of the loss of the last train_step with respect to every parameter (host FP32) */
 slnk_status slnk_unet_get_grads(slnk_unet* u, float* host);
-/* v [batch][2][H][W] = network(m_R, m_T), images [batch][H][W] */
-slnk_status slnk_unet_forward(slnk_unet* u, int batch, const float* m_R, const float* m_T, float* v);
-/* one step on the mean squared error mean((v - v_target)^2) over batch x 2 x H x W: forward,
- * backward and (lr > 0) one Adam step; *loss (may be NULL) receives the loss before the step */
+/* v [batch][2][H][W] = network(m_R, m_T), images [batch][H][W]; head [batch] (may be NULL)
+ * receives the scalar head's output */
+slnk_status slnk_unet_forward(slnk_unet* u, int batch, const float* m_R, const float* m_T, float* v,
+                              float* head);
+/* One training step.  With v_target: mean squared error mean((v - v_target)^2) over
+ * batch x 2 x H x W, backpropagated through the convolution layers.  With head_target [batch]:
+ * mean (head - head_target)^2, which trains the head alone (its gradient does not reach the
+ * convolution layers).  At least one target; lr > 0 applies one Adam step to the parameters
+ * that received gradients.  *loss, *head_loss (may be NULL) receive the losses before the step. */
 slnk_status slnk_unet_train_step(slnk_unet* u, int batch, const float* m_R, const float* m_T,
-                                 const float* v_target, double lr, double* loss);
+                                 const float* v_target, const float* head_target, double lr, double* loss,
+                                 double* head_loss);
+/* slnk_set_images with the network: copies m_R, m_T, runs the network once, and (P_2L) takes
+ * e_max = 1 + 1.1 exp(head) / beta from the head instead of the Lanczos iteration (e_min as in
+ * slnk_set_images).  The network's start velocity is kept for the next slnk_newton_solve_learned.
+ * Mixed-precision contexts whose grid matches the network. */
+slnk_status slnk_set_images_learned(slnk_ctx* ctx, slnk_unet* u, const void* m_R, const void* m_T);
 /* Learned solve of a mixed-precision context whose grid matches the network: v_out (device,
- * [B][2][n1][n2]) = the modes |k| <= start_kmax of network(m_R, m_T) for every item, then
- * slnk_newton_solve from there (with its fallback to v = 0).  The report times include the
- * network's forward pass. */
+ * [B][2][n1][n2]) = the modes |k| <= start_kmax of network(m_R, m_T) for every item (kept from
+ * slnk_set_images_learned, else computed here), then slnk_newton_solve from there (with its
+ * fallback to v = 0).  The report times include a forward pass computed here. */
 slnk_status slnk_newton_solve_learned(slnk_ctx* ctx, slnk_unet* u, void* v_out, const slnk_solve_opts* opts,
                                       slnk_solve_report* report);
 

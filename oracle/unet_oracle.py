@@ -15,7 +15,10 @@ GPU kernels can be checked element by element:
 
 Parameters are one flat array laid out as the C ABI documents it: per layer (encoder levels
 fine to coarse, then decoder levels coarse to fine, then the output layer) W[9][cout][cin] then
-bias[cout], each padded to a multiple of 64 values.  The input has 32 channels (m_R, m_T,
+bias[cout], each padded to a multiple of 64 values; then the scalar head (w[2 C_top], bias[1],
+each padded to 64), which maps the per-channel pixel means and maxima of the coarsest level's
+output to one number per item (the learned log(beta (e_max - 1)) of the two-level
+preconditioner).  The input has 32 channels (m_R, m_T,
 m_R - m_T, zeros) and the output layer 32 (two used); a network built for small tests may use
 any channel counts.
 
@@ -64,6 +67,12 @@ class Arch:
             self.dec_b[l] = self._add(self.C[l], self.C[l], True, l)
         self.out = self._add(self.C[0], out_c, False, 0)
         self.in_c, self.out_c = in_c, out_c
+        # scalar head after the convolution layers: w[2 C_top] (means, maxima), bias[1], each padded
+        self.trunk_n = self.n
+        self.hw_off = self.n
+        self.n += _pad64(2 * self.C[-1])
+        self.hb_off = self.n
+        self.n += 64
 
     def _add(self, cin, cout, relu, level):
         woff = self.n
@@ -169,9 +178,23 @@ def forward(arch, params, mR, mT, bf16=False):
         dec[l] = (cat, da, db)
         low = db
     out = layer(arch.out, low)  # FP32 output, no rounding
-    cache.update(feats=feats, dec=dec, last=low)
+    top = feats[L - 1][2]
+    f = np.concatenate([top.mean(axis=(1, 2)), top.max(axis=(1, 2))], axis=1)   # [B, 2 C_top]
+    head = f @ params[arch.hw_off: arch.hw_off + 2 * arch.C[-1]] + params[arch.hb_off]
+    cache.update(feats=feats, dec=dec, last=low, pooled=f, head=head)
     v = np.moveaxis(out[..., :2], -1, 1)
     return v, cache
+
+
+def head_grad(arch, cache, y):
+    """Loss mean_b (head_b - y_b)^2 and its gradient with respect to the head's parameters only
+    (flat, arch layout; the convolution layers get none)."""
+    d = cache["head"] - np.asarray(y, dtype=np.float64)
+    g = np.zeros(arch.n)
+    B = d.size
+    g[arch.hw_off: arch.hw_off + 2 * arch.C[-1]] = (2.0 * d / B) @ cache["pooled"]
+    g[arch.hb_off] = np.sum(2.0 * d / B)
+    return float(np.mean(d * d)), g
 
 
 def mse(v, target):

@@ -63,7 +63,7 @@ EXPORTS = ["slnk_default_params", "slnk_default_opts", "slnk_create", "slnk_dest
            "slnk_batch_hessian_matvec", "slnk_batch_newton_solve", "slnk_batch_autotune", "slnk_unet_default_params",
            "slnk_unet_create", "slnk_unet_destroy", "slnk_unet_last_error", "slnk_unet_param_count",
            "slnk_unet_get_params", "slnk_unet_set_params", "slnk_unet_get_grads", "slnk_unet_forward",
-           "slnk_unet_train_step", "slnk_newton_solve_learned"]
+           "slnk_unet_train_step", "slnk_set_images_learned", "slnk_newton_solve_learned"]
 
 
 def library_path() -> str:
@@ -115,8 +115,10 @@ def load_library():
         "slnk_unet_get_params": (ctypes.c_int, [V, V]),
         "slnk_unet_set_params": (ctypes.c_int, [V, V]),
         "slnk_unet_get_grads": (ctypes.c_int, [V, V]),
-        "slnk_unet_forward": (ctypes.c_int, [V, ctypes.c_int, V, V, V]),
-        "slnk_unet_train_step": (ctypes.c_int, [V, ctypes.c_int, V, V, V, ctypes.c_double, P(ctypes.c_double)]),
+        "slnk_unet_forward": (ctypes.c_int, [V, ctypes.c_int, V, V, V, V]),
+        "slnk_unet_train_step": (ctypes.c_int, [V, ctypes.c_int, V, V, V, V, ctypes.c_double, P(ctypes.c_double),
+                                                P(ctypes.c_double)]),
+        "slnk_set_images_learned": (ctypes.c_int, [V, V, V, V]),
         "slnk_newton_solve_learned": (ctypes.c_int, [V, V, V, P(SolveOpts), P(SolveReport)]),
     }
     for name, (res, args) in sig.items():
@@ -262,6 +264,10 @@ class Context:
             self._check(st)
         out = [self._report(r) for r in reps]
         return out[0] if self.batch == 1 else out
+
+    def set_images_learned(self, unet, m_R, m_T):
+        """set_images with the network: its head gives e_max (no Lanczos) and its start is kept."""
+        self._check(self._lib.slnk_set_images_learned(self._ctx, unet._u, self._ptr(m_R, 1), self._ptr(m_T, 1)))
 
     def newton_solve_learned(self, unet, v, opts: SolveOpts | None = None, **kw):
         """Warm start v = unet(m_R, m_T) (written into v), then the Newton--Krylov solve."""
@@ -450,18 +456,22 @@ class UNet:
         self._check(self._lib.slnk_unet_get_grads(self._u, out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
-    def forward(self, m_R, m_T, v):
+    def forward(self, m_R, m_T, v, head=None):
         b, h, w = m_R.shape
+        hp = self._ptr(head, (b,)) if head is not None else None
         self._check(self._lib.slnk_unet_forward(self._u, int(b), self._ptr(m_R, (b, h, w)), self._ptr(m_T, (b, h, w)),
-                                                self._ptr(v, (b, 2, h, w))))
+                                                self._ptr(v, (b, 2, h, w)), hp))
 
-    def train_step(self, m_R, m_T, v_target, lr):
+    def train_step(self, m_R, m_T, v_target, lr, head_target=None):
+        """One step; returns the velocity loss (or (loss, head_loss) with a head target)."""
         b, h, w = m_R.shape
-        loss = ctypes.c_double()
+        loss, hloss = ctypes.c_double(), ctypes.c_double()
+        vp = self._ptr(v_target, (b, 2, h, w)) if v_target is not None else None
+        hp = self._ptr(head_target, (b,)) if head_target is not None else None
         self._check(self._lib.slnk_unet_train_step(self._u, int(b), self._ptr(m_R, (b, h, w)),
-                                                   self._ptr(m_T, (b, h, w)), self._ptr(v_target, (b, 2, h, w)),
-                                                   float(lr), ctypes.byref(loss)))
-        return loss.value
+                                                   self._ptr(m_T, (b, h, w)), vp, hp, float(lr), ctypes.byref(loss),
+                                                   ctypes.byref(hloss)))
+        return loss.value if head_target is None else (loss.value, hloss.value)
 
     def save(self, path):
         """Parameters as a raw little-endian float32 file with a small text header."""
@@ -474,12 +484,18 @@ class UNet:
             f.write(w.astype("<f4").tobytes())
 
     def load(self, path):
+        """Parameters from save(); a file holding only the convolution layers (no head) leaves the
+        head's current values in place."""
         import numpy as np
         with open(path, "rb") as f:
             hdr = f.readline().decode().split()
             p = self.params
-            want = ["SLNKUNET1", str(p.height), str(p.width), str(p.levels), str(p.base_channels), str(self.n_params)]
-            if hdr != want:
-                raise ValueError(f"{path}: header {hdr} does not match this network {want}")
+            want = ["SLNKUNET1", str(p.height), str(p.width), str(p.levels), str(p.base_channels)]
+            if hdr[:5] != want or len(hdr) != 6 or int(hdr[5]) > self.n_params:
+                raise ValueError(f"{path}: header {hdr} does not match this network {want + [str(self.n_params)]}")
             w = np.frombuffer(f.read(), dtype="<f4")
-        self.set_params(w)
+        if w.size != int(hdr[5]):
+            raise ValueError(f"{path}: {w.size} values, header says {hdr[5]}")
+        full = self.get_params()
+        full[: w.size] = w
+        self.set_params(full)

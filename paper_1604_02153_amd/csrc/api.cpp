@@ -219,6 +219,10 @@ struct Context {
   int halo_cap = 0;  // LDS footprint of graphed SL steps (device halo <= cap)
   hipStream_t cap_stream = nullptr;
   std::map<std::tuple<int, const void*, const void*, const void*>, hipGraphExec_t> graphs;
+  // start velocity and head output of the network, kept by slnk_set_images_learned
+  T* learned_v = nullptr;     // [B][2F]
+  float* learned_y = nullptr; // [B]
+  bool learned_ready = false;
   // counters of the current solve
   std::vector<int> n_matvec, n_coarse;
   double t_prec = 0;
@@ -332,6 +336,7 @@ struct Context {
     bytes += (2 * partial_half + 8 * B + 16 * B + 2 * 64 * B + B) * sizeof(double) + 4 * B * sizeof(int) + 8192;
     bytes += B * (4 * 2 * F * sizeof(double) + 2 * 2 * size_t(p.n1) * (p.n2 / 2 + 1) * sizeof(cplx<double>)) +
              (p.n1 + p.n2) * sizeof(cplx<double>) + 16 * 256;
+    bytes += B * (2 * F * sizeof(T) + sizeof(float)) + 2 * 256;
     void* base = nullptr;
     if (hipMalloc(&base, bytes) != hipSuccess) throw Fail{SLNK_ENOMEM, "hipMalloc of the workspace failed"};
     arena.base = static_cast<char*>(base);
@@ -358,6 +363,8 @@ struct Context {
     }
     S64a = arena.take<cplx<double>>(B * 2 * sg64.spec());
     S64b = arena.take<cplx<double>>(B * 2 * sg64.spec());
+    learned_v = arena.take<T>(B * 2 * F);
+    learned_y = arena.take<float>(B);
     use_graphs = p.use_graphs != 0;
     halo_cap = std::min(8, sl_step_max_halo<T>());
     if (halo_cap < 0) throw Fail{SLNK_EDEVICE, "cannot query the LDS size of the device"};
@@ -631,15 +638,10 @@ struct Context {
   }
 
   // ---- two-level preconditioner -----------------------------------------------------------
-  void setup_two_level() {
+  // Lanczos on (I + S Q(0) S) of every item from one SplitMix64 start vector: tridiagonal
+  // coefficients (al, be) per item
+  void lanczos(std::vector<std::vector<double>>& al, std::vector<std::vector<double>>& be) {
     const size_t n = 2 * coarse.F;
-    // coarse images
-    HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, B, nullptr, 1, fine.mT, coarse.mT, nullptr, fine.S1, coarse.S1,
-                            coarse.S2));
-    HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, B, nullptr, 1, fine.mR, coarse.mR, nullptr, fine.S1, coarse.S1,
-                            coarse.S2));
-    HIPCHK(spec_grad<T>(stream, coarse.sg, B, coarse.mT, coarse.gmT, coarse.S1, coarse.S2));
-    // Lanczos on (I + S Q(0) S) of every item from one SplitMix64 start vector
     std::vector<double> h = splitmix64_uniform(prm.lanczos_seed, n);
     std::vector<T> ht(B * n);
     for (int z = 0; z < B; ++z) std::copy(h.begin(), h.end(), ht.begin() + z * n);
@@ -652,7 +654,6 @@ struct Context {
     put_scalars(0, nq);
     HIPCHK(axpby<T>(stream, B, n, 1.0, sc(0), q, 0.0, nullptr, q));
     HIPCHK(fill<T>(stream, B * n, 0.0, qp));
-    std::vector<std::vector<double>> al(B), be(B);
     std::vector<double> beta(B, 0.0);
     std::vector<int> live(B, 1);
     for (int j = 0; j < prm.lanczos_steps; ++j) {
@@ -683,15 +684,27 @@ struct Context {
       put_scalars(3, inv);
       HIPCHK(axpby<T>(stream, B, n, 1.0, sc(3), w, 0.0, nullptr, q));  // q <- w / beta
     }
+  }
+
+  // e_max from the given per-item values, else from the Lanczos iteration
+  void setup_two_level(const std::vector<double>* emax_given = nullptr) {
+    // coarse images
+    HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, B, nullptr, 1, fine.mT, coarse.mT, nullptr, fine.S1, coarse.S1,
+                            coarse.S2));
+    HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, B, nullptr, 1, fine.mR, coarse.mR, nullptr, fine.S1, coarse.S1,
+                            coarse.S2));
+    HIPCHK(spec_grad<T>(stream, coarse.sg, B, coarse.mT, coarse.gmT, coarse.S1, coarse.S2));
+    std::vector<std::vector<double>> al(B), be(B);
+    if (!emax_given) lanczos(al, be);
     // e_min = min_k 1 + 1 / (beta a'(k)) over the coarse modes: the largest |k|^2 is at the
     // corner (nc1/2, nc2/2)
     const double kk = 0.25 * double(coarse.n1) * coarse.n1 + 0.25 * double(coarse.n2) * coarse.n2;
     const int k = prm.cheb_iters;
     std::vector<double> itheta(B), tab(2 * size_t(k) * B, 0.0);
     for (int z = 0; z < B; ++z) {
-      emax[z] = prm.emax_safety * tridiag_max_eig(al[z], be[z]);
+      emax[z] = emax_given ? (*emax_given)[z] : prm.emax_safety * tridiag_max_eig(al[z], be[z]);
       emin[z] = 1.0 + 1.0 / (prm.beta * std::pow(kk, prm.reg));
-      if (!(emax[z] > emin[z]) || !std::isfinite(emax[z])) throw Fail{SLNK_ENAN, "Lanczos produced an invalid e_max"};
+      if (!(emax[z] > emin[z]) || !std::isfinite(emax[z])) throw Fail{SLNK_ENAN, "invalid Chebyshev bound e_max"};
       // Chebyshev recurrence of every step (Saad, Algorithm 12.1): d <- c1[i] d + c2[i] r
       const double theta = 0.5 * (emax[z] + emin[z]), delta = 0.5 * (emax[z] - emin[z]);
       const double sigma = theta / delta;
@@ -1313,6 +1326,7 @@ slnk_status slnk_set_images(slnk_ctx* ctx, const void* m_R, const void* m_T) {
     }
     C.fine.lin[0].valid = C.fine.lin[1].valid = false;
     C.has_grad = false;
+    C.learned_ready = false;
     C.clear_graphs();
     if (C.two_level) C.setup_two_level();
     C.images_set = true;
@@ -1457,6 +1471,62 @@ slnk_status slnk_newton_solve(slnk_ctx* ctx, void* v_inout, const slnk_solve_opt
   return st != SLNK_OK ? st : result;
 }
 
+namespace {
+
+// v = the modes |k| <= start_kmax of the network's velocity for the context's images; head
+// outputs into y (device, may be NULL)
+void learned_start(slnk::Context<float>& C, slnk_unet* u, float* v, float* y = nullptr) {
+  const slnk_status fs = slnk_unet_forward_on(u, C.stream, C.B, C.fine.n1, C.fine.n2, C.fine.mR, C.fine.mT, v, y);
+  if (fs != SLNK_OK) throw slnk::Fail{fs, std::string("network: ") + slnk_unet_last_error(u)};
+  const int kmax = slnk_unet_start_kmax(u);
+  if (kmax > 0) {
+    slnk::SymbolParams sp{slnk::Symbol::Cutoff, C.prm.reg, C.prm.beta, kmax};
+    HIPCHK(slnk::spec_scale<float>(C.stream, C.fine.sg, C.B, nullptr, sp, 2, v, v, nullptr, C.fine.S1, C.fine.S2));
+  }
+}
+
+}  // namespace
+
+slnk_status slnk_set_images_learned(slnk_ctx* ctx, slnk_unet* u, const void* m_R, const void* m_T) {
+  if (!ctx || !u || !m_R || !m_T) return SLNK_EINVAL;
+  if (!ctx->f) {
+    ctx->err = "the learned set-up needs a mixed-precision (FP32 field) context";
+    return SLNK_EINVAL;
+  }
+  return guarded(ctx, [&] {
+    auto& C = *ctx->f;
+    const size_t n = C.B * C.fine.F;
+    HIPCHK(hipMemcpyAsync(C.fine.mR, m_R, n * sizeof(float), hipMemcpyDeviceToDevice, C.stream));
+    HIPCHK(hipMemcpyAsync(C.fine.mT, m_T, n * sizeof(float), hipMemcpyDeviceToDevice, C.stream));
+    for (float* img : {C.fine.mR, C.fine.mT}) {
+      HIPCHK(slnk::norms<float>(C.stream, C.B, C.fine.F, img, C.partial, C.dres));
+      const double* r = C.fetch(0);
+      for (int z = 0; z < C.B; ++z)
+        if (r[4 * z + 2] > 0) throw slnk::Fail{SLNK_ENAN, "non-finite image value"};
+    }
+    C.fine.lin[0].valid = C.fine.lin[1].valid = false;
+    C.has_grad = false;
+    C.learned_ready = false;
+    C.clear_graphs();
+    learned_start(C, u, C.learned_v, C.learned_y);
+    std::vector<float> y(C.B);
+    HIPCHK(hipMemcpyAsync(y.data(), C.learned_y, C.B * sizeof(float), hipMemcpyDeviceToHost, C.stream));
+    HIPCHK(hipStreamSynchronize(C.stream));
+    if (C.two_level) {
+      // e_max = 1 + 1.1 exp(y) / beta: the head predicts log(beta (e_max - 1)); the factor 1.1 on
+      // top of the safety factor of the training targets guards against underestimates
+      std::vector<double> emax(C.B);
+      for (int z = 0; z < C.B; ++z) {
+        if (!std::isfinite(y[z])) throw slnk::Fail{SLNK_ENAN, "non-finite network head"};
+        emax[z] = 1.0 + 1.1 * std::exp(double(y[z])) / C.prm.beta;
+      }
+      C.setup_two_level(&emax);
+    }
+    C.learned_ready = true;
+    C.images_set = true;
+  });
+}
+
 slnk_status slnk_newton_solve_learned(slnk_ctx* ctx, slnk_unet* u, void* v_out, const slnk_solve_opts* opts,
                                       slnk_solve_report* report) {
   if (!ctx || !u || !v_out) return SLNK_EINVAL;
@@ -1473,14 +1543,11 @@ slnk_status slnk_newton_solve_learned(slnk_ctx* ctx, slnk_unet* u, void* v_out, 
     if (!C.images_set) throw slnk::Fail{SLNK_EINVAL, "slnk_set_images must come first"};
     if (o.max_newton < 0 || o.max_pcg < 1 || o.max_halvings < 0) throw slnk::Fail{SLNK_EINVAL, "bad options"};
     const double t0 = slnk::now_ms();
-    const slnk_status fs = slnk_unet_forward_on(u, C.stream, C.B, C.fine.n1, C.fine.n2, C.fine.mR, C.fine.mT,
-                                                   static_cast<float*>(v_out));
-    if (fs != SLNK_OK) throw slnk::Fail{fs, std::string("network: ") + slnk_unet_last_error(u)};
-    const int kmax = slnk_unet_start_kmax(u);
-    if (kmax > 0) {
-      slnk::SymbolParams sp{slnk::Symbol::Cutoff, C.prm.reg, C.prm.beta, kmax};
-      HIPCHK(slnk::spec_scale<float>(C.stream, C.fine.sg, C.B, nullptr, sp, 2, static_cast<const float*>(v_out),
-                                     static_cast<float*>(v_out), nullptr, C.fine.S1, C.fine.S2));
+    if (C.learned_ready) {
+      HIPCHK(hipMemcpyAsync(v_out, C.learned_v, C.B * 2 * C.fine.F * sizeof(float), hipMemcpyDeviceToDevice,
+                            C.stream));
+    } else {
+      learned_start(C, u, static_cast<float*>(v_out));
     }
     HIPCHK(hipStreamSynchronize(C.stream));
     const double t_net = slnk::now_ms() - t0;

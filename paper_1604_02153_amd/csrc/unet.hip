@@ -315,6 +315,55 @@ __global__ void k_adam(float* w, bf16* wb, const float* g, float* m, float* v, s
   }
 }
 
+// scalar head: per item b, f[b][c] = mean and f[b][C + c] = max over the HW pixels of x[b][p][c]
+// (C channels, FP32), s[b] = bias + sum_{c < 2C} f[b][c] w[c]; one block per item
+__global__ void __launch_bounds__(256) k_head(const bf16* x, int C, int HW, const float* w, const float* bias,
+                                              float* f, float* s) {
+  __shared__ float red[256];
+  const int b = blockIdx.x;
+  float part = 0.f;
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    float acc = 0.f, mx = -3.0e38f;
+    for (int p = 0; p < HW; ++p) {
+      const float xv = bf2f(x[(size_t(b) * HW + p) * C + c]);
+      acc += xv;
+      mx = fmaxf(mx, xv);
+    }
+    const float fc = acc / float(HW);
+    f[size_t(b) * 2 * C + c] = fc;
+    f[size_t(b) * 2 * C + C + c] = mx;
+    part += fc * w[c] + mx * w[C + c];
+  }
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (int(threadIdx.x) < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) s[b] = red[0] + bias[0];
+}
+
+// gradient of mean_b (s[b] - y[b])^2 with respect to the head's weights and bias, and the loss
+__global__ void __launch_bounds__(256) k_head_grad(const float* f, const float* s, const float* y, int B, int C,
+                                                   float* gw, float* gb, double* loss) {
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    float acc = 0.f;
+    for (int b = 0; b < B; ++b) acc += 2.f * (s[b] - y[b]) / float(B) * f[size_t(b) * C + c];
+    gw[c] = acc;
+  }
+  if (threadIdx.x == 0) {
+    float g = 0.f;
+    double l = 0.0;
+    for (int b = 0; b < B; ++b) {
+      const float d = s[b] - y[b];
+      g += 2.f * d / float(B);
+      l += double(d) * d;
+    }
+    gb[0] = g;
+    *loss = l / B;
+  }
+}
+
 __global__ void k_to_bf16(const float* w, bf16* wb, size_t n) {
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
     wb[i] = f2bf(w[i]);
@@ -417,6 +466,18 @@ hipError_t adam(hipStream_t s, float* w, bf16* wb, const float* g, float* m, flo
   const double c1 = 1.0 - std::pow(b1, double(step)), c2 = 1.0 - std::pow(b2, double(step));
   hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(256), 0, s, w, wb, g, m, v, n, float(lr), float(b1), float(b2),
                      float(eps), float(c1), float(c2));
+  return hipGetLastError();
+}
+
+hipError_t head(hipStream_t s, const bf16* x, int C, int HW, int B, const float* w, const float* bias, float* f,
+                float* out) {
+  hipLaunchKernelGGL(k_head, dim3(B), dim3(256), 0, s, x, C, HW, w, bias, f, out);
+  return hipGetLastError();
+}
+
+hipError_t head_grad(hipStream_t s, const float* f, const float* out, const float* y, int B, int C, float* gw,
+                     float* gb, double* loss) {
+  hipLaunchKernelGGL(k_head_grad, dim3(1), dim3(256), 0, s, f, out, y, B, C, gw, gb, loss);
   return hipGetLastError();
 }
 

@@ -69,6 +69,13 @@ hipError_t loss(hipStream_t s, const float* v, const float* tgt, int B, int HW, 
 hipError_t adam(hipStream_t s, float* w, bf16* wb, const float* g, float* m, float* v, size_t n, double lr, double b1,
                 double b2, double eps, long long step);
 hipError_t to_bf16(hipStream_t s, const float* w, bf16* wb, size_t n);
+// scalar head on the pixel mean and maximum of a [B][HW][C] BF16 tensor: f [B][2C] = (means,
+// maxima), out[b] = bias + f[b] . w (w: 2C values); head_grad: the gradient of
+// mean_b (out[b] - y[b])^2 with respect to w and bias, given the feature count 2C (+ the loss)
+hipError_t head(hipStream_t s, const bf16* x, int C, int HW, int B, const float* w, const float* bias, float* f,
+                float* out);
+hipError_t head_grad(hipStream_t s, const float* f, const float* out, const float* y, int B, int C, float* gw,
+                     float* gb, double* loss);
 
 }  // namespace unet
 }  // namespace slnk

@@ -78,7 +78,14 @@ struct slnk_unet {
   double* dloss = nullptr;
   double* hloss = nullptr;
   float* vout = nullptr;
-  long long step = 0;
+  long long step = 0, head_step = 0;
+  // scalar head on the pixel mean and maximum of the bottleneck output: predicts
+  // log(beta (e_max - 1)) of the two-level preconditioner's Chebyshev interval (its weights follow
+  // the convolution layers)
+  size_t trunk_n = 0, hw_off = 0, hb_off = 0;
+  float* hf = nullptr;     // [max_batch][2 C_top] pooled features (means, maxima)
+  float* hs = nullptr;     // [max_batch] head outputs
+  double* hlossd = nullptr;
   // activations and their gradients
   Tensor in0, dv;
   std::vector<Tensor> pin, ea, cat, da, db;  // pin[l]: level input for l > 0 (pooled)
@@ -145,6 +152,11 @@ void build(slnk_unet& u) {
     u.dec_b[l] = add_layer(u, u.C[l], u.C[l], 1, u.C[l], u.C[l]);
   }
   u.out_layer = add_layer(u, u.C[0], kOutC, 0, u.C[0], 2);
+  u.trunk_n = u.nparam;
+  u.hw_off = u.nparam;
+  u.nparam += (size_t(2 * u.C[L - 1]) + 63) / 64 * 64;
+  u.hb_off = u.nparam;
+  u.nparam += 64;
 }
 
 int level_of(const slnk_unet& u, int layer);
@@ -198,6 +210,9 @@ void allocate(slnk_unet& u) {
   u.lpart = u.take<double>(slnk::unet::loss_blocks(size_t(P0)) + 8);
   u.dloss = u.lpart + slnk::unet::loss_blocks(size_t(P0));
   u.vout = u.take<float>(size_t(u.prm.max_batch) * 2 * u.Hs[0] * u.Ws[0]);
+  u.hf = u.take<float>(size_t(u.prm.max_batch) * 2 * u.C[L - 1]);
+  u.hs = u.take<float>(size_t(u.prm.max_batch));
+  u.hlossd = u.take<double>(8);
   u.in0 = u.tensor(kInC, 0, true);
   u.dv = u.tensor(kOutC, 0, true);
   u.pin.resize(L);
@@ -333,7 +348,7 @@ void back_conv(slnk_unet& u, hipStream_t s, int layer, int B, View in, View outv
   }
 }
 
-void forward(slnk_unet& u, hipStream_t s, int B, const float* mr, const float* mt, float* v) {
+void forward(slnk_unet& u, hipStream_t s, int B, const float* mr, const float* mt, float* v, float* head_out) {
   const int L = u.L;
   UCHK(slnk::unet::prep(s, mr, mt, u.in0.p, kInC, size_t(B) * u.Hs[0] * u.Ws[0]));
   for (int l = 0; l < L; ++l) {
@@ -355,6 +370,9 @@ void forward(slnk_unet& u, hipStream_t s, int B, const float* mr, const float* m
     run_conv(u, s, u.dec_b[l], B, u.da[l].at(), u.db[l].at(), nullptr, 0);
   }
   run_conv(u, s, u.out_layer, B, u.db[0].at(), View{}, v, 2);
+  const int lt = L - 1;
+  UCHK(slnk::unet::head(s, u.eb.p, u.C[lt], u.Hs[lt] * u.Ws[lt], B, u.w32 + u.hw_off, u.w32 + u.hb_off, u.hf, u.hs));
+  if (head_out) UCHK(hipMemcpyAsync(head_out, u.hs, B * sizeof(float), hipMemcpyDeviceToDevice, s));
 }
 
 void backward(slnk_unet& u, hipStream_t s, int B) {
@@ -402,12 +420,12 @@ void check_batch(const slnk_unet& u, int B) {
 int slnk_unet_start_kmax(const slnk_unet* u) { return u ? u->prm.start_kmax : 0; }
 
 slnk_status slnk_unet_forward_on(slnk_unet* u, void* stream, int batch, int height, int width, const float* m_R,
-                                 const float* m_T, float* v) {
+                                 const float* m_T, float* v, float* head) {
   return guard(u, [&] {
     check_batch(*u, batch);
     if (height != u->prm.height || width != u->prm.width)
       throw Fail{SLNK_EINVAL, "the network was built for another grid size"};
-    forward(*u, static_cast<hipStream_t>(stream), batch, m_R, m_T, v);
+    forward(*u, static_cast<hipStream_t>(stream), batch, m_R, m_T, v, head);
   });
 }
 
@@ -441,7 +459,7 @@ slnk_status slnk_unet_create(const slnk_unet_params* p, void* hip_stream, slnk_u
   slnk_status st = guard(u.get(), [&] {
     UCHK(hipMemset(u->base, 0, u->cap));
     allocate(*u);
-    UCHK(hipHostMalloc(reinterpret_cast<void**>(&u->hloss), sizeof(double), hipHostMallocDefault));
+    UCHK(hipHostMalloc(reinterpret_cast<void**>(&u->hloss), 2 * sizeof(double), hipHostMallocDefault));
     std::vector<float> h;
     init_params(*u, h);
     UCHK(hipMemcpy(u->w32, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -487,7 +505,7 @@ slnk_status slnk_unet_set_params(slnk_unet* u, const float* host) {
     UCHK(hipMemsetAsync(u->m1, 0, u->nparam * sizeof(float), u->stream));
     UCHK(hipMemsetAsync(u->m2, 0, u->nparam * sizeof(float), u->stream));
     UCHK(hipStreamSynchronize(u->stream));
-    u->step = 0;
+    u->step = u->head_step = 0;
   });
 }
 
@@ -499,30 +517,48 @@ slnk_status slnk_unet_get_grads(slnk_unet* u, float* host) {
   });
 }
 
-slnk_status slnk_unet_forward(slnk_unet* u, int batch, const float* m_R, const float* m_T, float* v) {
+slnk_status slnk_unet_forward(slnk_unet* u, int batch, const float* m_R, const float* m_T, float* v, float* head) {
   if (!m_R || !m_T || !v) return SLNK_EINVAL;
   return guard(u, [&] {
     check_batch(*u, batch);
-    forward(*u, u->stream, batch, m_R, m_T, v);
+    forward(*u, u->stream, batch, m_R, m_T, v, head);
   });
 }
 
 slnk_status slnk_unet_train_step(slnk_unet* u, int batch, const float* m_R, const float* m_T, const float* v_target,
-                                 double lr, double* loss) {
-  if (!m_R || !m_T || !v_target || !(lr >= 0.0)) return SLNK_EINVAL;
+                                 const float* head_target, double lr, double* loss, double* head_loss) {
+  if (!m_R || !m_T || (!v_target && !head_target) || !(lr >= 0.0)) return SLNK_EINVAL;
   return guard(u, [&] {
     check_batch(*u, batch);
     hipStream_t s = u->stream;
-    forward(*u, s, batch, m_R, m_T, u->vout);
-    UCHK(slnk::unet::loss(s, u->vout, v_target, batch, u->Hs[0] * u->Ws[0], kOutC, u->dv.p, u->lpart, u->dloss));
-    backward(*u, s, batch);
-    ++u->step;
-    if (lr > 0.0)
-      UCHK(slnk::unet::adam(s, u->w32, u->wbf, u->grad, u->m1, u->m2, u->nparam, lr, 0.9, 0.999, 1e-8, u->step));
-    UCHK(hipMemcpyAsync(u->hloss, u->dloss, sizeof(double), hipMemcpyDeviceToHost, s));
+    forward(*u, s, batch, m_R, m_T, u->vout, nullptr);
+    if (v_target) {
+      UCHK(slnk::unet::loss(s, u->vout, v_target, batch, u->Hs[0] * u->Ws[0], kOutC, u->dv.p, u->lpart, u->dloss));
+      backward(*u, s, batch);
+      ++u->step;
+      if (lr > 0.0)
+        UCHK(slnk::unet::adam(s, u->w32, u->wbf, u->grad, u->m1, u->m2, u->trunk_n, lr, 0.9, 0.999, 1e-8, u->step));
+    }
+    if (head_target) {
+      // the head learns from the trunk's features; its loss does not flow back into the trunk
+      const int lt = u->L - 1;
+      UCHK(slnk::unet::head_grad(s, u->hf, u->hs, head_target, batch, 2 * u->C[lt], u->grad + u->hw_off,
+                                 u->grad + u->hb_off, u->hlossd));
+      ++u->head_step;
+      const size_t o = u->hw_off, n = u->nparam - u->hw_off;
+      if (lr > 0.0)
+        UCHK(slnk::unet::adam(s, u->w32 + o, u->wbf + o, u->grad + o, u->m1 + o, u->m2 + o, n, lr, 0.9, 0.999, 1e-8,
+                              u->head_step));
+    }
+    double h[2] = {0.0, 0.0};
+    if (v_target) UCHK(hipMemcpyAsync(&u->hloss[0], u->dloss, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (head_target) UCHK(hipMemcpyAsync(&u->hloss[1], u->hlossd, sizeof(double), hipMemcpyDeviceToHost, s));
     UCHK(hipStreamSynchronize(s));
-    if (!std::isfinite(*u->hloss)) throw Fail{SLNK_ENAN, "non-finite training loss"};
-    if (loss) *loss = *u->hloss;
+    if (v_target) h[0] = u->hloss[0];
+    if (head_target) h[1] = u->hloss[1];
+    if (!std::isfinite(h[0]) || !std::isfinite(h[1])) throw Fail{SLNK_ENAN, "non-finite training loss"};
+    if (loss) *loss = h[0];
+    if (head_loss) *head_loss = h[1];
   });
 }
 

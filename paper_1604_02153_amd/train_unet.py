@@ -8,10 +8,13 @@
    the plain method (mixed precision, H2, beta = 1e-3, P_2L, Newton-PCG to ||g||_rel <= 1e-2) in
    batches of 64 on the GPU.  The targets are the solver's velocities, not the generating ones.
 2. Training: the U-Net (4 levels, 32 base channels, BF16 on the matrix cores) on mean squared
-   error, Adam with a cosine learning-rate decay, batches drawn by a seeded permutation.
+   error against the solved velocities, and its scalar head on log(beta (e_max - 1)) of the
+   two-level preconditioner's Lanczos bound of each pair; Adam with a cosine learning-rate decay,
+   batches drawn by a seeded permutation.  --head-only trains the head on a loaded network.
 3. Evaluation on held-out pairs (eval_seed0 ...): wall time to ||g||_rel <= 1e-2 of the plain
-   solve (from v = 0) and of the learned solve (network forward pass + solve from its output, with
-   the fallback to v = 0), on one context of one pair, same GPU.
+   path (set-up with Lanczos, solve from v = 0) and of the learned path (set-up with the network:
+   e_max from the head, start from its velocity; solve with the fallback to v = 0), one pair per
+   context, same GPU; solve-only times are reported too.
 
 Every step runs in the library's kernels; this script only moves tensors and calls the C ABI.
 """
@@ -60,6 +63,7 @@ def generate(seeds, torch, dev, log_every=2048):
     mR_all = torch.empty((M, N, N), dtype=torch.float32, device=dev)
     mT_all = torch.empty_like(mR_all)
     v_all = torch.empty((M, 2, N, N), dtype=torch.float32, device=dev)
+    y_all = torch.empty((M,), dtype=torch.float32, device=dev)
     keep = np.zeros(M, dtype=bool)
     iters = []
     pool = cf.ThreadPoolExecutor(max_workers=8)
@@ -81,12 +85,14 @@ def generate(seeds, torch, dev, log_every=2048):
         mR = torch.empty_like(mT)
         ctx.transport_state(vg, mT, mR)
         ctx.set_images(mR, mT)
+        emax = np.array([b[1] for b in ctx.cheb_bounds()])
         v = torch.zeros_like(vg)
         reps = ctx.newton_solve(v)
         sl = slice(k * CHUNK, k * CHUNK + B)
         mR_all[sl] = mR[:B]
         mT_all[sl] = mT[:B]
         v_all[sl] = v[:B]
+        y_all[sl] = torch.from_numpy(np.log(BETA * (emax[:B] - 1.0)).astype(np.float32)).to(dev)
         for j in range(B):
             ok = reps[j]["status"] == "SLNK_OK" and reps[j]["grel"][-1] <= 1e-2
             keep[k * CHUNK + j] = ok
@@ -98,38 +104,43 @@ def generate(seeds, torch, dev, log_every=2048):
     idx = torch.from_numpy(np.nonzero(keep)[0]).to(dev)
     stats = {"pairs": M, "kept": int(keep.sum()), "solve_s": round(time.perf_counter() - t0, 1),
              "newton_mean": float(np.mean([a for a, _ in iters])), "pcg_mean": float(np.mean([b for _, b in iters]))}
-    return mR_all[idx], mT_all[idx], v_all[idx], stats
+    return mR_all[idx], mT_all[idx], v_all[idx], y_all[idx], stats
 
 
-def train(net, data, epochs, batch, lr0, seed, time_limit, torch, dev):
-    mR, mT, vs = data
+def train(net, data, epochs, batch, lr0, seed, time_limit, torch, dev, head_only=False):
+    mR, mT, vs, ys = data
     M = mR.shape[0]
     steps_per_epoch = M // batch
     total = epochs * steps_per_epoch
     g = torch.Generator().manual_seed(seed)
     t0 = time.perf_counter()
-    history = []
+    history, hist_h = [], []
     step = 0
     for ep in range(epochs):
         perm = torch.randperm(M, generator=g).to(dev)
-        run = 0.0
+        run = hrun = 0.0
         for s in range(steps_per_epoch):
             idx = perm[s * batch:(s + 1) * batch]
             warm = min(1.0, (step + 1) / 200.0)
             lr = lr0 * warm * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * step / max(1, total))))
-            loss = net.train_step(mR[idx].contiguous(), mT[idx].contiguous(), vs[idx].contiguous(), lr)
+            loss, hloss = net.train_step(mR[idx].contiguous(), mT[idx].contiguous(),
+                                         None if head_only else vs[idx].contiguous(), lr,
+                                         head_target=ys[idx].contiguous())
             run += loss
+            hrun += hloss
             step += 1
             if step % 250 == 0:
-                log(f"epoch {ep} step {step}/{total} loss {run / (s + 1):.4e} ({time.perf_counter() - t0:.1f} s)")
+                log(f"epoch {ep} step {step}/{total} loss {run / (s + 1):.4e} head {hrun / (s + 1):.4e} "
+                    f"({time.perf_counter() - t0:.1f} s)")
             if time.perf_counter() - t0 > time_limit:
                 break
         history.append(run / max(1, s + 1))
-        log(f"epoch {ep} mean loss {history[-1]:.4e}")
+        hist_h.append(hrun / max(1, s + 1))
+        log(f"epoch {ep} mean loss {history[-1]:.4e} head {hist_h[-1]:.4e}")
         if time.perf_counter() - t0 > time_limit:
             log("time limit reached")
             break
-    return {"steps": step, "epochs_done": len(history), "loss_per_epoch": history,
+    return {"steps": step, "epochs_done": len(history), "loss_per_epoch": history, "head_loss_per_epoch": hist_h,
             "train_s": round(time.perf_counter() - t0, 1), "ms_per_step": round(1e3 * (time.perf_counter() - t0) / max(1, step), 2)}
 
 
@@ -144,19 +155,24 @@ def evaluate(net, seeds, torch, dev):
         mT, vg = torch.from_numpy(mT).to(dev), torch.from_numpy(vg).to(dev)
         mR = torch.empty_like(mT)
         ctx.transport_state(vg, mT, mR)
-        ctx.set_images(mR, mT)
-        v.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        ctx.set_images(mR, mT)
+        v.zero_()
+        ts = time.perf_counter()
         plain = ctx.newton_solve(v)
         t1 = time.perf_counter()
+        ctx.set_images_learned(net, mR, mT)
+        tl = time.perf_counter()
         learned = ctx.newton_solve_learned(net, v)
         t2 = time.perf_counter()
+        ratio = (learned["emax"] - 1.0) / (plain["emax"] - 1.0)
         rows.append(dict(plain_ms=1e3 * (t1 - t0), learned_ms=1e3 * (t2 - t1),
+                         plain_solve_ms=1e3 * (t1 - ts), learned_solve_ms=1e3 * (t2 - tl),
                          plain_newton=plain["newton_iters"], learned_newton=learned["newton_iters"],
                          plain_pcg=plain["pcg_iters"], learned_pcg=learned["pcg_iters"],
                          plain_ok=plain["grel"][-1] <= 1e-2, learned_ok=learned["grel"][-1] <= 1e-2,
-                         fallback=learned["fallback"]))
+                         fallback=learned["fallback"], emax_ratio=ratio))
         if (i + 1) % 200 == 0:
             log(f"evaluated {i + 1}/{len(seeds)}")
     ctx.close()
@@ -164,6 +180,8 @@ def evaluate(net, seeds, torch, dev):
     return {
         "pairs": len(rows),
         "plain_ms_median": round(float(np.median(col("plain_ms"))), 2),
+        "plain_solve_ms_median": round(float(np.median(col("plain_solve_ms"))), 2),
+        "learned_solve_ms_median": round(float(np.median(col("learned_solve_ms"))), 2),
         "learned_ms_median": round(float(np.median(col("learned_ms"))), 2),
         "plain_ms_mean": round(float(np.mean(col("plain_ms"))), 2),
         "learned_ms_mean": round(float(np.mean(col("learned_ms"))), 2),
@@ -174,6 +192,8 @@ def evaluate(net, seeds, torch, dev):
         "plain_reached": int(col("plain_ok").sum()), "learned_reached": int(col("learned_ok").sum()),
         "fallback_rate": round(float(np.mean(col("fallback"))), 4),
         "learned_faster_fraction": round(float(np.mean(col("learned_ms") < col("plain_ms"))), 4),
+        "emax_ratio_learned_over_lanczos": {q: round(float(np.percentile(col("emax_ratio"), p)), 4)
+                                            for q, p in (("p5", 5), ("median", 50), ("p95", 95))},
     }
 
 
@@ -191,6 +211,7 @@ def main():
     ap.add_argument("--time-limit", type=float, default=600.0, help="training wall-time budget (s)")
     ap.add_argument("--init", default=None, help="weights to start from")
     ap.add_argument("--start-kmax", type=int, default=8, help="Fourier cut-off of the learned start")
+    ap.add_argument("--head-only", action="store_true", help="train only the e_max head of a loaded network")
     ap.add_argument("--report", default=None, help="JSON file for the statistics")
     args = ap.parse_args()
     import torch
@@ -199,15 +220,16 @@ def main():
     torch.cuda.set_device(dev)
     seeds = list(range(args.train_seed0, args.train_seed0 + args.train_pairs))
     log(f"generating and solving {len(seeds)} training pairs")
-    mR, mT, vs, gstats = generate(seeds, torch, dev)
+    mR, mT, vs, ys, gstats = generate(seeds, torch, dev)
     log(f"data: {gstats}")
     net = UNet(N, N, 4, 32, max_batch=args.batch, seed=args.seed, start_kmax=args.start_kmax)
     if args.init:
         net.load(args.init)
-    tstats = train(net, (mR, mT, vs), args.epochs, args.batch, args.lr, args.seed, args.time_limit, torch, dev)
+    tstats = train(net, (mR, mT, vs, ys), args.epochs, args.batch, args.lr, args.seed, args.time_limit, torch, dev,
+                   head_only=args.head_only)
     log(f"training: {tstats}")
     net.save(args.out)
-    del mR, mT, vs
+    del mR, mT, vs, ys
     torch.cuda.empty_cache()
     eseeds = list(range(args.eval_seed0, args.eval_seed0 + args.eval_pairs))
     estats = evaluate(net, eseeds, torch, dev)

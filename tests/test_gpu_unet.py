@@ -52,17 +52,23 @@ def _net(slnk, arch, params, B=2):
 def test_forward_matches_reference(slnk, shape):
     H, W, L = shape
     arch = U.Arch(H, W, levels=L, base=32)
-    params = U.random_params(arch, np.random.default_rng(1)).astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(1)
+    params = U.random_params(arch, rng)
+    params[arch.hw_off: arch.hw_off + 2 * arch.C[-1]] = 0.1 * rng.standard_normal(2 * arch.C[-1])
+    params[arch.hb_off] = 0.3
+    params = params.astype(np.float32).astype(np.float64)
     net = _net(slnk, arch, params)
     mR, mT, _ = _case(2, n=H)
     if W != H:
         mR, mT = np.concatenate([mR, mR], axis=2), np.concatenate([mT, mT[:, ::-1]], axis=2)
     v = torch.empty((2, 2, H, W), dtype=torch.float32, device="cuda")
-    net.forward(_t(mR), _t(mT), v)
-    v_ref, _ = U.forward(arch, params, mR, mT, bf16=True)
+    head = torch.empty((2,), dtype=torch.float32, device="cuda")
+    net.forward(_t(mR), _t(mT), v, head)
+    v_ref, cache = U.forward(arch, params, mR, mT, bf16=True)
     err = rel(v.cpu().numpy(), v_ref)
     print(f"forward rel err {err:.2e}", flush=True)
     assert err < 1e-2
+    assert rel(head.cpu().numpy(), cache["head"]) < 1e-3
     net.close()
 
 
@@ -72,10 +78,10 @@ def test_gradients_match_reference(slnk):
     net = _net(slnk, arch, params)
     mR, mT, tgt = _case(4)
     loss = net.train_step(_t(mR), _t(mT), _t(tgt), 0.0)
-    g = net.get_grads().astype(np.float64)
+    g = net.get_grads().astype(np.float64)[: arch.trunk_n]
     v_ref, cache = U.forward(arch, params, mR, mT, bf16=True)
     l_ref, dv = U.mse(v_ref, tgt)
-    g_ref = U.backward(arch, cache, dv, bf16=True)
+    g_ref = U.backward(arch, cache, dv, bf16=True)[: arch.trunk_n]
     assert abs(loss - l_ref) / l_ref < 1e-3
     errs = []
     for k, ly in enumerate(arch.layers):
@@ -89,16 +95,43 @@ def test_gradients_match_reference(slnk):
     net.close()
 
 
+def test_head_gradients_match_reference(slnk):
+    """The scalar head trains alone: its gradient matches the reference and the convolution
+    layers receive none (their parameters stay put under a head-only Adam step)."""
+    arch = U.Arch(64, 64, levels=3, base=32)
+    rng = np.random.default_rng(9)
+    params = U.random_params(arch, rng).astype(np.float32).astype(np.float64)
+    params[arch.hw_off: arch.hw_off + 2 * arch.C[-1]] = 0.1 * rng.standard_normal(2 * arch.C[-1])
+    params = params.astype(np.float32).astype(np.float64)
+    net = _net(slnk, arch, params)
+    mR, mT, _ = _case(10)
+    y = np.array([0.5, -1.0], dtype=np.float32)
+    _, hl = net.train_step(_t(mR), _t(mT), None, 1e-3, head_target=_t(y))
+    g = net.get_grads().astype(np.float64)
+    _, cache = U.forward(arch, params, mR, mT, bf16=True)
+    l_ref, g_ref = U.head_grad(arch, cache, y)
+    assert abs(hl - l_ref) / l_ref < 1e-3
+    sl = slice(arch.hw_off, arch.n)
+    # the features are BF16 activations: an FP32 (GPU) and an FP64 (reference) sum upstream can
+    # round a value to neighbouring BF16 numbers (2^-8 apart), which the maxima pass on unaveraged
+    assert rel(g[sl], g_ref[sl]) < 5e-3
+    after = net.get_params().astype(np.float64)
+    assert np.array_equal(after[: arch.trunk_n], params[: arch.trunk_n])
+    net.close()
+
+
 def test_adam_step_matches_reference(slnk):
     arch = U.Arch(64, 64, levels=3, base=32)
     params = U.random_params(arch, np.random.default_rng(5)).astype(np.float32).astype(np.float64)
     net = _net(slnk, arch, params)
     mR, mT, tgt = _case(6)
     net.train_step(_t(mR), _t(mT), _t(tgt), 1e-3)
-    g = net.get_grads().astype(np.float64)
-    w1, _, _ = U.adam_step(params, g, np.zeros_like(g), np.zeros_like(g), 1, lr=1e-3)
+    n = arch.trunk_n
+    g = net.get_grads().astype(np.float64)[:n]
+    w1, _, _ = U.adam_step(params[:n], g, np.zeros_like(g), np.zeros_like(g), 1, lr=1e-3)
     got = net.get_params().astype(np.float64)
-    assert np.max(np.abs(got - w1)) < 1e-6
+    assert np.max(np.abs(got[:n] - w1)) < 1e-6
+    assert np.array_equal(got[n:], params[n:])  # the head is not touched by the velocity loss
     net.close()
 
 
@@ -149,5 +182,29 @@ def test_learned_solve_with_an_untrained_network(slnk):
     for r in reps:
         assert r["status"] == "SLNK_OK" and r["grel"][-1] <= 1e-2
     assert reps[0]["grel"] == reps[1]["grel"]
+    net.close()
+    ctx.close()
+
+
+def test_learned_setup_takes_emax_from_the_head(slnk):
+    """set_images_learned: e_max = 1 + 1.1 exp(head) / beta (no Lanczos), e_min unchanged; the
+    learned solve then starts from the kept network output and converges."""
+    n = 64
+    L, vgen, _ = problem("gauss", n, n, nt=4, beta=1e-3, reg=2, seed=23)
+    mR, mT = _t(L.mR[None]), _t(L.mT[None])
+    net = slnk.UNet(n, n, 3, 32, max_batch=1)
+    ctx = slnk.Context(n, n, 4, reg="h2", beta=1e-3, prec="mixed", pc="2l")
+    ctx.set_images(mR[0], mT[0])
+    emin, emax_lanczos = ctx.cheb_bounds()
+    w = net.get_params()
+    arch = U.Arch(n, n, levels=3, base=32)
+    w[arch.hb_off] = np.log(1e-3 * (emax_lanczos - 1.0) / 1.1)   # head = that value (zero weights)
+    net.set_params(w)
+    ctx.set_images_learned(net, mR[0], mT[0])
+    emin2, emax2 = ctx.cheb_bounds()
+    assert emin2 == emin and abs(emax2 - emax_lanczos) / emax_lanczos < 1e-5
+    v = torch.empty((2, n, n), dtype=torch.float32, device="cuda")
+    r = ctx.newton_solve_learned(net, v)
+    assert r["status"] == "SLNK_OK" and r["grel"][-1] <= 1e-2
     net.close()
     ctx.close()

@@ -106,4 +106,27 @@ def test_layout_matches_the_documented_parameter_count():
     for ly in arch.layers:
         assert ly["woff"] == n and ly["boff"] == n + U._pad64(9 * ly["cout"] * ly["cin"])
         n = ly["boff"] + U._pad64(ly["cout"])
-    assert n == arch.n
+    assert n == arch.trunk_n == arch.hw_off and arch.hb_off == n + 512 and arch.n == n + 512 + 64
+
+
+def test_head_gradient_against_finite_differences():
+    arch = U.Arch(8, 8, levels=2, base=2, in_c=3, out_c=2)
+    rng = np.random.default_rng(11)
+    params = U.random_params(arch, rng, scale=1.5)
+    params[arch.hw_off: arch.hw_off + 2 * arch.C[-1]] = rng.standard_normal(2 * arch.C[-1])
+    mR, mT = rng.uniform(0, 1, (3, 8, 8)), rng.uniform(0, 1, (3, 8, 8))
+    y = rng.standard_normal(3)
+
+    def loss(p):
+        _, c = U.forward(arch, p, mR, mT)
+        return U.head_grad(arch, c, y)[0]
+
+    _, cache = U.forward(arch, params, mR, mT)
+    l0, g = U.head_grad(arch, cache, y)
+    assert np.all(g[: arch.trunk_n] == 0)
+    h = 1e-6
+    for off in list(range(arch.hw_off, arch.hw_off + 2 * arch.C[-1])) + [arch.hb_off]:
+        e = np.zeros(arch.n)
+        e[off] = 1.0
+        fd = (loss(params + h * e) - loss(params - h * e)) / (2 * h)
+        assert abs(fd - g[off]) <= 1e-7 * max(1.0, abs(fd))
