@@ -730,21 +730,31 @@ struct Context {
     ensure_gm(coarse);
   }
 
-  // x = CHEB_k(M_c) b on the coarse level (x, b distinct; uses vec[3..5])
+  // x = CHEB_k(M_c) b on the coarse level (Saad, Algorithm 12.1, from x = 0; x, b distinct).
+  // The iteration carries y = S d and u = S r next to d and r: M d = d + S Q y, so each step
+  // needs the transport chain Q y and one spectral transform giving S Q y and S^2 Q y, which
+  // also update u; one fused kernel then updates r, u, d, y, x.
   void chebyshev(const T* b, T* x, const int* mk) {
     const size_t n = 2 * coarse.F;
     T* r = coarse.vec[3];
     T* d = coarse.vec[4];
-    T* Md = coarse.vec[5];
+    T* u = coarse.vec[5];
+    T* y = coarse.vec[0];
+    T* sb = coarse.vec[1];
+    T* s2b = coarse.w;
     const int k = prm.cheb_iters;
     HIPCHK(axpby<T>(stream, B, n, 1.0, nullptr, b, 0.0, nullptr, r));
     HIPCHK(axpby<T>(stream, B, n, 1.0, inv_theta, b, 0.0, nullptr, d));
-    for (int i = 0; i < k; ++i) {
-      HIPCHK(axpby<T>(stream, B, n, 1.0, nullptr, d, i == 0 ? 0.0 : 1.0, nullptr, x));
-      if (i == k - 1) break;
-      split_matvec(coarse, d, Md, mk);
-      HIPCHK(axpby<T>(stream, B, n, -1.0, nullptr, Md, 1.0, nullptr, r));
-      HIPCHK(axpby<T>(stream, B, n, 1.0, cheb_tab + (size_t(k) + i) * B, r, 1.0, cheb_tab + size_t(i) * B, d));
+    HIPCHK(axpby<T>(stream, B, n, 1.0, nullptr, d, 0.0, nullptr, x));
+    if (k == 1) return;
+    HIPCHK(spec_scale<T>(stream, coarse.sg, B, mk, sym(Symbol::RegInvSqrt), 2, b, u, nullptr, coarse.S1, coarse.S2));
+    HIPCHK(axpby<T>(stream, B, n, 1.0, inv_theta, u, 0.0, nullptr, y));
+    for (int i = 0; i < k - 1; ++i) {
+      gn_transport(coarse, y, mk);
+      HIPCHK(spec_scale2<T>(stream, coarse.sg, B, mk, sym(Symbol::RegInvSqrt), sym(Symbol::RegInv), coarse.bt, sb, s2b,
+                            coarse.S1, coarse.S2));
+      HIPCHK(cheb_step<T>(stream, B, n, cheb_tab + size_t(i) * B, cheb_tab + (size_t(k) + i) * B, r, u, d, y, x, sb,
+                          s2b));
     }
   }
 

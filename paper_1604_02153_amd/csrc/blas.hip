@@ -102,6 +102,27 @@ __global__ void k_axpby(size_t n, double a, const double* ad, const T* __restric
 }
 
 template <typename T>
+__global__ void k_cheb_step(size_t n, const double* c1d, const double* c2d, T* __restrict__ rb, T* __restrict__ ub,
+                            T* __restrict__ db, T* __restrict__ yb, T* __restrict__ xb, const T* __restrict__ sbb,
+                            const T* __restrict__ s2bb) {
+  const int z = blockIdx.y;
+  const T c1 = T(c1d[z]), c2 = T(c2d[z]);
+  const size_t off = size_t(z) * n;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const size_t k = off + i;
+    const T dk = db[k], yk = yb[k];
+    const T r = rb[k] - (dk + sbb[k]);
+    const T u = ub[k] - (yk + s2bb[k]);
+    const T d = c1 * dk + c2 * r;
+    rb[k] = r;
+    ub[k] = u;
+    db[k] = d;
+    yb[k] = c1 * yk + c2 * u;
+    xb[k] = xb[k] + d;
+  }
+}
+
+template <typename T>
 __global__ void k_xpay(size_t n, const T* __restrict__ x, T a, const T* __restrict__ y, T* __restrict__ z) {
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
     z[i] = x[i] + a * y[i];
@@ -233,6 +254,13 @@ hipError_t axpby(hipStream_t s, int batch, size_t n, double a, const double* ad,
 }
 
 template <typename T>
+hipError_t cheb_step(hipStream_t s, int batch, size_t n, const double* c1, const double* c2, T* r, T* u, T* d, T* y,
+                     T* x, const T* sb, const T* s2b) {
+  hipLaunchKernelGGL(k_cheb_step<T>, dim3(grid_for(n), batch), dim3(kThreads), 0, s, n, c1, c2, r, u, d, y, x, sb, s2b);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t xpay(hipStream_t s, size_t n, const T* x, double a, const T* y, T* z) {
   hipLaunchKernelGGL(k_xpay<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, T(a), y, z);
   return hipGetLastError();
@@ -284,6 +312,8 @@ hipError_t masked_copy(hipStream_t s, int batch, size_t n, const T* src, long lo
   template hipError_t axpby<T>(hipStream_t, int, size_t, double, const double*, const T*, double,         \
                                const double*, T*);                                                        \
   template hipError_t xpay<T>(hipStream_t, size_t, const T*, double, const T*, T*);                       \
+  template hipError_t cheb_step<T>(hipStream_t, int, size_t, const double*, const double*, T*, T*, T*, T*, T*,   \
+                                   const T*, const T*);                                                         \
   template hipError_t fill<T>(hipStream_t, size_t, double, T*);                                           \
   template hipError_t q_at_zero<T>(hipStream_t, int, size_t, const T*, const T*, double, T*);             \
   template hipError_t cast_copy<T>(hipStream_t, size_t, const double*, T*);                               \

@@ -60,6 +60,12 @@ template <typename T>
 hipError_t spec_scale(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, SymbolParams sym, int nf,
                       const T* in, T* out, const T* add, cplx<T>* S1, cplx<T>* S2);
 
+// out1 = sym1(in), out2 = sym2(in) for vector fields (two fields per item): one forward transform.
+// S1 >= 2 batch spec(), S2 >= 4 batch spec().
+template <typename T>
+hipError_t spec_scale2(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, SymbolParams sym1,
+                       SymbolParams sym2, const T* in, T* out1, T* out2, cplx<T>* S1, cplx<T>* S2);
+
 // Spectral gradient of 'count' consecutive scalar fields m[c] (stride field()): gm[c] = (d1 m, d2 m)
 // with stride 2 field().  S1 >= count spec(), S2 >= 2 count spec().
 template <typename T>
@@ -175,6 +181,13 @@ hipError_t finish(hipStream_t s, int batch, int nparts, int stride, long long pe
 template <typename T>
 hipError_t axpby(hipStream_t s, int batch, size_t n, double a, const double* ad, const T* x, double b,
                  const double* bd, T* y);
+// One step of the Chebyshev iteration on M = I + S Q S carrying y = S d and u = S r, per item z
+// (n elements each), given sb = S Q y and s2b = S^2 Q y:
+//   r -= d + sb;  u -= y + s2b;  d = c1[z] d + c2[z] r;  y = c1[z] y + c2[z] u;  x += d
+template <typename T>
+hipError_t cheb_step(hipStream_t s, int batch, size_t n, const double* c1, const double* c2, T* r, T* u, T* d, T* y,
+                     T* x, const T* sb, const T* s2b);
+
 // z = x + a y over n elements (one item or all items)
 template <typename T>
 hipError_t xpay(hipStream_t s, size_t n, const T* x, double a, const T* y, T* z);

@@ -432,6 +432,24 @@ struct OpScale {
   }
 };
 
+// two symbols of the same two input fields: out[0..2) = sym1 in, out[2..4) = sym2 in
+template <typename T>
+struct OpScale2 {
+  static constexpr int NIN = 2, NOUT = 4;
+  SymbolParams sp1, sp2;
+  int n1, n2;
+  double inv_n;
+  __device__ void operator()(int k1, int k2, int, int, const cplx<T>* in, cplx<T>* out) const {
+    const int k2s = (2 * k2 == n2) ? -k2 : k2;
+    const T a = symbol_value<T>(sp1, k1, n1, k2s, n2) * T(inv_n);
+    const T b = symbol_value<T>(sp2, k1, n1, k2s, n2) * T(inv_n);
+    out[0] = cscale(in[0], a);
+    out[1] = cscale(in[1], a);
+    out[2] = cscale(in[0], b);
+    out[3] = cscale(in[1], b);
+  }
+};
+
 template <typename T>
 struct OpGrad {
   static constexpr int NIN = 1, NOUT = 2;
@@ -688,6 +706,27 @@ hipError_t spec_trace_prep(hipStream_t s, const SpecGrid<T>& g, int batch, const
 }
 
 template <typename T>
+hipError_t spec_scale2(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, SymbolParams sym1,
+                       SymbolParams sym2, const T* in, T* out1, T* out2, cplx<T>* S1, cplx<T>* S2) {
+  const size_t F = g.field();
+  RealFields<T> rin{};
+  set_fields(rin, 2, const_cast<T*>(in), F, active);
+  RET_IF(launch_row_fwd<T>(s, g, rin, batch, S1));
+  OpScale2<T> op{sym1, sym2, g.n1, g.n2, 1.0 / double(F)};
+  RET_IF(launch_col<T>(s, g, S1, S2, op, 0, batch, active));
+  OutFields<T> rout{};
+  rout.count = 4;
+  rout.active = active;
+  rout.item_div = 1;
+  rout.p[0] = out1;
+  rout.p[1] = out1 + F;
+  rout.p[2] = out2;
+  rout.p[3] = out2 + F;
+  rout.bstride[0] = rout.bstride[1] = rout.bstride[2] = rout.bstride[3] = (long long)(2 * F);
+  return launch_row_inv<T>(s, g, S2, 4, rout, batch);
+}
+
+template <typename T>
 hipError_t spec_restrict(hipStream_t s, const SpecGrid<T>& g, const SpecGrid<T>& gc, int batch, const int* active,
                          int nf, const T* in, T* out_c, cplx<T>* keep_fine, cplx<T>* S1, cplx<T>* Sc1, cplx<T>* Sc2) {
   const size_t F = g.field(), Fc = gc.field();
@@ -737,6 +776,8 @@ hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecG
   template hipError_t spec_scale<T>(hipStream_t, const SpecGrid<T>&, int, const int*, SymbolParams, int, const T*, \
                                     T*, const T*, cplx<T>*, cplx<T>*);                                          \
   template hipError_t spec_grad<T>(hipStream_t, const SpecGrid<T>&, int, const T*, T*, cplx<T>*, cplx<T>*);     \
+  template hipError_t spec_scale2<T>(hipStream_t, const SpecGrid<T>&, int, const int*, SymbolParams, SymbolParams, \
+                                     const T*, T*, T*, cplx<T>*, cplx<T>*);                                     \
   template hipError_t spec_trace_prep<T>(hipStream_t, const SpecGrid<T>&, int, const int*, const T*, T*, T*, T*, \
                                          cplx<T>*, cplx<T>*);                                                   \
   template hipError_t spec_restrict<T>(hipStream_t, const SpecGrid<T>&, const SpecGrid<T>&, int, const int*, int, \
