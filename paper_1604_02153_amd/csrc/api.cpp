@@ -166,6 +166,7 @@ struct Level {
   T* bt = nullptr;    // 2F
   T* w = nullptr;     // 2F
   T* coef = nullptr;  // F
+  T* coef2 = nullptr; // F
   T* vec[8] = {};     // 2F each: Krylov / Chebyshev / Lanczos vectors
   T* gmT = nullptr;   // 2F: gradient of m_T (Lanczos at v = 0)
   cplx<T>* S1 = nullptr;
@@ -254,8 +255,8 @@ struct Context {
     const size_t spec = size_t(n1) * (n2 / 2 + 1);
     const size_t nspec = std::max<size_t>(6, 2 * (nt + 1));
     // images; two slots of (v, df, da, gamma, m, gm, bAv); cv, divv, cdiv; lam, acc, g, q, bt, w;
-    // coef; vec[8]; gmT
-    const size_t fields = 2 + 2 * (2 + 2 + 2 + 1 + (nt + 1) + 2 * (nt + 1) + 2) + 2 + 1 + 1 + 2 * 6 + 1 + 2 * 8 + 2;
+    // coef, coef2; vec[8]; gmT
+    const size_t fields = 2 + 2 * (2 + 2 + 2 + 1 + (nt + 1) + 2 * (nt + 1) + 2) + 2 + 1 + 1 + 2 * 6 + 2 + 2 * 8 + 2;
     return B * (fields * F * sizeof(T) + (2 * nspec + 2) * spec * sizeof(cplx<T>)) + (n1 + n2) * sizeof(cplx<T>) +
            96 * 256 + 2 * B * sizeof(int);
   }
@@ -297,6 +298,7 @@ struct Context {
     lv.bt = arena.take<T>(B * 2 * F);
     lv.w = arena.take<T>(B * 2 * F);
     lv.coef = arena.take<T>(B * F);
+    lv.coef2 = arena.take<T>(B * F);
     for (auto& p : lv.vec) p = arena.take<T>(B * 2 * F);
     lv.gmT = arena.take<T>(B * 2 * F);
     const size_t nspec = std::max<size_t>(6, 2 * (nt + 1));
@@ -426,6 +428,8 @@ struct Context {
     a.halo_dev = lv.halo_dev + slot * B;
     a.coef = lv.coef;
     a.st_coef = (long long)lv.F;
+    a.coef2 = lv.coef2;
+    a.st_coef2 = (long long)lv.F;
     a.ht = 1.0 / lv.nt;
     a.force_global = prm.sl_path == 1;
     return a;

@@ -125,9 +125,10 @@ struct StepArgs {
   const T* vt = nullptr;     // incremental state: direction (2 fields)
   const T* addf = nullptr;   // adjoint last step: beta A v added to the accumulator (2 fields)
   T* out2 = nullptr;         // adjoint last step: gradient output (2 fields)
-  T* coef = nullptr;         // one-field scratch for the coefficient pass when halo exceeds LDS
+  T* coef = nullptr;         // one-field scratch: coefficients of the two-kernel (global gather) step
+  T* coef2 = nullptr;        // one-field scratch: row-filtered values of that coefficient pass
   long long st_src = 0, st_dst = 0, st_d = 0, st_gamma = 0, st_aux0 = 0, st_aux1 = 0, st_gm = 0,
-            st_acc = 0, st_vt = 0, st_addf = 0, st_out2 = 0, st_coef = 0;
+            st_acc = 0, st_vt = 0, st_addf = 0, st_out2 = 0, st_coef = 0, st_coef2 = 0;
   double ht = 0;
   double w_new = 0;          // trapezoid weight of the produced level (times ht)
   double w_old = 0;          // trapezoid weight of the src level (first step only)

@@ -20,7 +20,7 @@ namespace slnk {
 namespace {
 
 constexpr int kMaxE = 16;          // complex elements per thread held by one FFT stage
-constexpr int kLdsBudget = 64 * 1024;
+constexpr int kLdsBudget = 136 * 1024;  // column-pass panels (gfx950: 160 KiB of LDS per workgroup)
 constexpr size_t kLdsDefault = 64 * 1024;  // dynamic LDS a kernel gets without an attribute
 
 std::mutex g_attr_mutex;
@@ -588,12 +588,17 @@ hipError_t launch_row_inv(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* S,
   return hipGetLastError();
 }
 
-// Column pass shape: B columns per block -- enough blocks to spread a small grid over the chip,
-// every FFT stage within kMaxE elements per thread at <= 1024 threads -- and its LDS bytes.
+// Column pass shape: B adjacent columns per block.  Small grids keep the block count up (B from
+// nh / 64); when the batch already gives enough blocks, B grows to what the LDS budget allows,
+// so that each row of a panel is a longer contiguous segment (8 columns: 64 bytes in FP32).
+// Every FFT stage stays within kMaxE elements per thread at <= 1024 threads.
 template <typename T>
-void col_config(int n1, int nh, int nmax, int& B, int& nthr, size_t& lds) {
+void col_config(int n1, int nh, int nmax, int batch, int& B, int& nthr, size_t& lds) {
   const int col_bytes = (n1 + 1) * int(sizeof(cplx<T>)) * nmax;
-  B = std::max(1, std::min(std::min(16, std::max(1, nh / 64)), kLdsBudget / col_bytes));
+  const int bmax = std::max(1, std::min(16, kLdsBudget / col_bytes));
+  B = std::max(1, std::min(std::min(16, std::max(1, nh / 64)), bmax));
+  while (B < bmax && ((nh + 2 * B - 1) / (2 * B)) * batch >= 512) B *= 2;
+  B = std::min(B, bmax);
   while (B > 1 && nmax * B * n1 > 1024 * kMaxE) --B;
   const int elems = nmax * B * n1;
   nthr = std::min(1024, std::max(64, round_up((elems + 7) / 8, 64)));
@@ -608,7 +613,7 @@ hipError_t launch_col(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* Sin, c
   const int nh = g.nh();
   int B, nthr;
   size_t lds;
-  col_config<T>(g.n1, nh, nmax, B, nthr, lds);
+  col_config<T>(g.n1, nh, nmax, batch, B, nthr, lds);
   dim3 grid((nh + B - 1) / B, 1, batch);
   static std::atomic<size_t> allowed{0};
   RET_IF(allow_lds(k_col<T, Op>, lds, allowed));
@@ -638,7 +643,7 @@ size_t spec_lds_bytes(int n1, int n2) {
   row_config<T>(n2, nthr, rpb);
   const size_t row = (size_t(rpb) * (n2 + 1) + n2) * sizeof(cplx<T>);
   size_t col = 0;
-  col_config<T>(n1, n2 / 2 + 1, 4, B, nthr, col);  // widest operator: four spectra per column
+  col_config<T>(n1, n2 / 2 + 1, 4, 1 << 20, B, nthr, col);  // widest operator, widest panel
   return std::max(row, col);
 }
 

@@ -9,6 +9,7 @@
 // the circulant (1, 4, 1)/6 operator, truncated where |z|^t falls below the working precision),
 // gathers the 4x4 tensor B-spline stencil at every departure point and applies the step's
 // update (Heun weights, adjoint factor, time-integral accumulation) in registers.
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 
@@ -164,6 +165,7 @@ __device__ __forceinline__ StepArgs<T> item_view(const StepArgs<T>& b, int z) {
   a.addf = adv(b.addf, b.st_addf);
   a.out2 = adv(b.out2, b.st_out2);
   a.coef = adv(b.coef, b.st_coef);
+  a.coef2 = adv(b.coef2, b.st_coef2);
   a.halo_dev = b.halo_dev ? b.halo_dev + z : nullptr;
   a.partial = b.partial ? b.partial + size_t(z) * 2 * gridDim.x * gridDim.y : nullptr;
   return a;
@@ -255,20 +257,67 @@ __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, i
   __syncthreads();
 }
 
-// Coefficient-only pass (used when the departure footprint exceeds the LDS budget): writes the
-// B-spline coefficients of the step's source field to a.coef.
+// Coefficient pass of the two-kernel step (whole-field B-spline coefficients into a.coef, read
+// by the global-memory gather): the separable exponential filter runs along complete periodic
+// rows (into a.coef2), then along columns, so that no output is computed twice.
+// Rows: a block filters 'rpb' whole rows staged in LDS with K wrapped values on either side.
 template <typename T, int KIND, bool FIRST>
-__global__ void __launch_bounds__(256) k_prefilter(StepArgs<T> args) {
+__global__ void __launch_bounds__(256) k_prefilter_rows(StepArgs<T> args, int rpb) {
   if (args.active && !args.active[blockIdx.z]) return;
   const StepArgs<T> a = item_view(args, blockIdx.z);
+  constexpr int K = FilterTaps<T>::K;
   extern __shared__ unsigned char smem_raw[];
-  T* A = reinterpret_cast<T*>(smem_raw);
-  int by, bx;
-  xcd_tile(by, bx);
-  const int y0 = by * kTile, x0 = bx * kTile;
-  stage_coefficients<T, KIND, FIRST>(a, A, y0, x0, 0, kTile);
-  const int i1 = y0 + threadIdx.y, i2 = x0 + threadIdx.x;
-  if (i1 < a.n1 && i2 < a.n2) a.coef[size_t(i1) * a.n2 + i2] = A[threadIdx.y * kTile + threadIdx.x];
+  T* L = reinterpret_cast<T*>(smem_raw);
+  const int n1 = a.n1, n2 = a.n2, W = n2 + 2 * K;
+  const int r0 = blockIdx.x * rpb;
+  const int nr = min(rpb, n1 - r0);
+  for (int idx = threadIdx.x; idx < nr * W; idx += blockDim.x) {
+    const int r = idx / W, c = idx - r * W;
+    L[idx] = load_src<T, KIND, FIRST>(a, size_t(r0 + r) * n2 + wrap_index(c - K, n2));
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nr * n2; idx += blockDim.x) {
+    const int r = idx / n2, c = idx - r * n2;
+    const T* x = L + r * W + c + K;
+    T acc = tap<T>(0) * x[0];
+#pragma unroll
+    for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[-t] + x[t]);
+    a.coef2[size_t(r0 + r) * n2 + c] = acc;
+  }
+}
+
+// Columns: a block filters a panel of kColW columns over kColH rows (plus K wrapped rows above and
+// below), each thread R consecutive rows of one column from a register window.
+constexpr int kColW = 32, kColH = 64;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_prefilter_cols(StepArgs<T> args) {
+  if (args.active && !args.active[blockIdx.z]) return;
+  const StepArgs<T> a = item_view(args, blockIdx.z);
+  constexpr int K = FilterTaps<T>::K;
+  constexpr int R = kColH * kColW / 256;
+  __shared__ T L[(kColH + 2 * K) * kColW];
+  const int n1 = a.n1, n2 = a.n2;
+  const int x0 = blockIdx.x * kColW, y0 = blockIdx.y * kColH;
+  for (int idx = threadIdx.x; idx < (kColH + 2 * K) * kColW; idx += blockDim.x) {
+    const int r = idx / kColW, c = idx - r * kColW;
+    const int col = x0 + c;
+    L[idx] = col < n2 ? a.coef2[size_t(wrap_index(y0 - K + r, n1)) * n2 + col] : T(0);
+  }
+  __syncthreads();
+  const int c = threadIdx.x % kColW, q = threadIdx.x / kColW;
+  const int col = x0 + c;
+  T x[R + 2 * K];
+#pragma unroll
+  for (int i = 0; i < R + 2 * K; ++i) x[i] = L[(q * R + i) * kColW + c];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    T acc = tap<T>(0) * x[j + K];
+#pragma unroll
+    for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[j + K - t] + x[j + K + t]);
+    const int row = y0 + q * R + j;
+    if (row < n1 && col < n2) a.coef[size_t(row) * n2 + col] = acc;
+  }
 }
 
 template <typename T, int KIND, bool FIRST, bool GLOBAL>
@@ -502,9 +551,17 @@ hipError_t launch_step(hipStream_t s, const StepArgs<T>& a, dim3 grid, dim3 bloc
     }
     hipLaunchKernelGGL(kfn, grid, block, lds, s, a);
   } else {
-    const size_t lds = step_lds_bytes<T>(kTile);
-    hipLaunchKernelGGL((k_prefilter<T, KIND, FIRST>), grid, block, lds, s, a);
+    constexpr int K = FilterTaps<T>::K;
+    // a few thousand staged values per block, at most 48 KiB of LDS
+    const int rpb = std::max(1, std::min(4096 / a.n2, int((48 * 1024) / ((a.n2 + 2 * K) * sizeof(T)))));
+    const size_t lds = size_t(rpb) * (a.n2 + 2 * K) * sizeof(T);
+    hipLaunchKernelGGL((k_prefilter_rows<T, KIND, FIRST>), dim3((a.n1 + rpb - 1) / rpb, 1, a.batch), dim3(256), lds,
+                       s, a, rpb);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_prefilter_cols<T>, dim3((a.n2 + kColW - 1) / kColW, (a.n1 + kColH - 1) / kColH, a.batch),
+                       dim3(256), 0, s, a);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_sl_step<T, KIND, FIRST, true>), grid, block, 0, s, a);
   }
@@ -518,7 +575,7 @@ hipError_t sl_step(hipStream_t s, StepKind kind, const StepArgs<T>& a, int* nblo
   const int maxh = sl_step_max_halo<T>();
   if (a.halo < 0) return hipErrorInvalidValue;
   const bool fused = a.halo <= maxh && !a.force_global;
-  if (!fused && a.coef == nullptr) return hipErrorInvalidValue;
+  if (!fused && (a.coef == nullptr || a.coef2 == nullptr)) return hipErrorInvalidValue;
   dim3 grid((a.n2 + kTile - 1) / kTile, (a.n1 + kTile - 1) / kTile, a.batch);
   dim3 block(kTile, kTile);
   if (nblocks_out) *nblocks_out = int(grid.x * grid.y);

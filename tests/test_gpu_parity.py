@@ -446,3 +446,33 @@ def test_large_grids_match_oracle(slnk, shape):
     ctx.hessian_matvec(_t(vt, prec), h)
     _check_reg_op(L, prec, _np(h), O.hessian_matvec(lin, vt), vt, TOL[prec]["matvec"])
     ctx.close()
+
+
+def test_wide_batch_matches_single_contexts(slnk):
+    """A 16-item batch at 128^2 gives its column FFT passes wide panels (several adjacent columns
+    per workgroup); every item still equals its own batch-1 context bit for bit, and the oracle."""
+    n, B, prec = 128, 16, "mixed"
+    probs = _batch_problems(n, n, seeds=tuple(range(50, 50 + B)), amps=[0.1 + 0.02 * i for i in range(B)])
+    for L, _, _ in probs:
+        L.mT, L.mR = same_inputs(prec, L.mT, L.mR)
+    vs = [same_inputs(prec, 0.5 * p[1]) for p in probs]
+    vts = [same_inputs(prec, p[2]) for p in probs]
+    stack = lambda arrs: _t(np.stack(arrs), prec)
+    cb = _ctx(slnk, probs[0][0], prec, pc="reg", batch=B)
+    cb.set_images(stack([p[0].mR for p in probs]), stack([p[0].mT for p in probs]))
+    gb = torch.empty((B, 2, n, n), dtype=torch.float32, device="cuda")
+    cb.gradient(stack(vs), gb)
+    hb = torch.empty_like(gb)
+    cb.hessian_matvec(stack(vts), hb)
+    for z in (0, 7, 15):
+        L = probs[z][0]
+        c1 = _ctx(slnk, L, prec, pc="reg")
+        c1.set_images(_t(L.mR, prec), _t(L.mT, prec))
+        g1, h1 = torch.empty_like(gb[0]), torch.empty_like(gb[0])
+        c1.gradient(_t(vs[z], prec), g1)
+        c1.hessian_matvec(_t(vts[z], prec), h1)
+        assert torch.equal(g1, gb[z]) and torch.equal(h1, hb[z]), z
+        c1.close()
+    lin = O.linearize(probs[7][0], vs[7])
+    _check_reg_op(probs[7][0], prec, _np(hb[7]), O.hessian_matvec(lin, vts[7]), vts[7], TOL[prec]["matvec"])
+    cb.close()
