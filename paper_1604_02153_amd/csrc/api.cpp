@@ -239,12 +239,23 @@ struct Context {
     if (int(r.size()) > kFFTMaxStages) throw Fail{SLNK_EINVAL, "FFT length has too many factors"};
     pl.n = n;
     pl.nstages = int(r.size());
-    for (size_t i = 0; i < r.size(); ++i) pl.radix[i] = r[i];
-    std::vector<cplx<U>> h(n);
-    for (int q = 0; q < n; ++q) {
-      const double a = 2.0 * kPi * double(q) / double(n);
-      h[q] = {U(std::cos(a)), U(-std::sin(a))};
+    // per-stage twiddles: stage s (radix R, p = product of the earlier radices) holds
+    // w^(j k n / (p R)) = exp(-2 pi i j k / (p R)) at twoff[s] + (j - 1) p + k, j = 1..R-1,
+    // k = 0..p-1 (n - 1 values in all), so that consecutive butterflies read consecutive entries
+    std::vector<cplx<U>> h(n, cplx<U>{U(1), U(0)});
+    int p = 1, off = 0;
+    for (size_t st = 0; st < r.size(); ++st) {
+      pl.radix[st] = r[st];
+      pl.twoff[st] = off;
+      for (int j = 1; j < r[st]; ++j)
+        for (int k = 0; k < p; ++k) {
+          const double a = 2.0 * kPi * double(j) * double(k) / double(p * r[st]);
+          h[off + (j - 1) * p + k] = {U(std::cos(a)), U(-std::sin(a))};
+        }
+      off += (r[st] - 1) * p;
+      p *= r[st];
     }
+    pl.ntw = off;
     tw = arena.take<cplx<U>>(n);
     HIPCHK(hipMemcpy(tw, h.data(), n * sizeof(cplx<U>), hipMemcpyHostToDevice));
     pl.tw = tw;
@@ -252,7 +263,7 @@ struct Context {
 
   static size_t level_bytes(int n1, int n2, int nt, int B) {
     const size_t F = size_t(n1) * n2;
-    const size_t spec = size_t(n1) * (n2 / 2 + 1);
+    const size_t spec = size_t(n1) * spec_stride(n2);
     const size_t nspec = std::max<size_t>(6, 2 * (nt + 1));
     // images; two slots of (v, df, da, gamma, m, gm, bAv); cv, divv, cdiv; lam, acc, g, q, bt, w;
     // coef, coef2; vec[8]; gmT
@@ -336,7 +347,7 @@ struct Context {
     partial_half = size_t(B) * (std::max(reduce_blocks(2 * F), tiles) * 4 + 64);
     size_t bytes = level_bytes(p.n1, p.n2, p.nt, B) + (two_level ? level_bytes(p.n1 / 2, p.n2 / 2, p.nt, B) : 0);
     bytes += (2 * partial_half + 8 * B + 16 * B + 2 * 64 * B + B) * sizeof(double) + 4 * B * sizeof(int) + 8192;
-    bytes += B * (4 * 2 * F * sizeof(double) + 2 * 2 * size_t(p.n1) * (p.n2 / 2 + 1) * sizeof(cplx<double>)) +
+    bytes += B * (4 * 2 * F * sizeof(double) + 2 * 2 * size_t(p.n1) * spec_stride(p.n2) * sizeof(cplx<double>)) +
              (p.n1 + p.n2) * sizeof(cplx<double>) + 16 * 256;
     bytes += B * (2 * F * sizeof(T) + sizeof(float)) + 2 * 256;
     void* base = nullptr;

@@ -40,6 +40,11 @@ __host__ __device__ __forceinline__ int wrap_index(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// row stride (complex elements) of a half spectrum [n1][n2/2 + 1]: padded to a multiple of 16 so
+// that every row starts on a 128-byte boundary (FP32) and the strided column passes move whole
+// aligned segments
+__host__ __device__ __forceinline__ int spec_stride(int n2) { return (n2 / 2 + 1 + 15) / 16 * 16; }
+
 // signed wavenumber of FFT-ordered index idx in [0, n)
 __host__ __device__ __forceinline__ int signed_wavenumber(int idx, int n) { return idx < n / 2 ? idx : idx - n; }
 

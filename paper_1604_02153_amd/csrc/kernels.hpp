@@ -8,12 +8,16 @@ namespace slnk {
 
 constexpr int kFFTMaxStages = 16;
 
-// Factorisation of one transform length into radix-4/2/3/5 stages plus its twiddle table
-// w[q] = exp(-2 pi i q / n), q < n (device memory, computed on the host in FP64).
+// Factorisation of one transform length into radix-8/4/2/3/5 stages plus its twiddle table
+// (device memory, computed on the host in FP64): stage s, radix R, p = product of the earlier
+// radices, holds exp(-2 pi i j k / (p R)) at twoff[s] + (j - 1) p + k (j = 1..R-1, k < p);
+// ntw = n - 1 values in all.
 struct FFTPlanDev {
   int n = 0;
   int nstages = 0;
   int radix[kFFTMaxStages] = {0};
+  int twoff[kFFTMaxStages] = {0};
+  int ntw = 0;
   const void* tw = nullptr;
 };
 
@@ -23,9 +27,10 @@ struct SpecGrid {
   int n1 = 0, n2 = 0;      // real-space grid
   FFTPlanDev row;          // length n2 transforms (along x2, contiguous)
   FFTPlanDev col;          // length n1 transforms (along x1, strided)
-  int nh() const { return n2 / 2 + 1; }
+  int nh() const { return n2 / 2 + 1; }        // columns of a half spectrum
+  int nhp() const { return spec_stride(n2); }   // their row stride
   size_t field() const { return size_t(n1) * size_t(n2); }
-  size_t spec() const { return size_t(n1) * size_t(nh()); }
+  size_t spec() const { return size_t(n1) * size_t(nhp()); }
 };
 
 // Scalar symbols applied by spec_scale (all real and even in k).

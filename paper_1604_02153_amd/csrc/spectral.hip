@@ -126,8 +126,18 @@ struct Dft<T, 5> {
   }
 };
 
+// LDS position of element e of a transform: an XOR swizzle of the low five index bits by bits
+// 3..7.  It permutes every aligned block of 32 elements, and it spreads both the contiguous reads
+// and the stride-RAD writes of the Stockham stages (and the column transposes, with a sequence
+// stride of 4 mod 32) over the 64 LDS banks.
+__device__ __forceinline__ int swz(int e) { return e ^ ((e >> 3) & 31); }
+
+// sequence stride (complex elements) of LDS-resident transforms of length n: room for the swizzle
+// (a multiple of 32) plus 4
+__host__ __device__ __forceinline__ int lds_stride(int n) { return (n + 31) / 32 * 32 + 4; }
+
 // One Stockham stage of radix RAD over 'nbatch' transforms of length n held in LDS; element e of
-// transform b lives at buf[b * bs + e].  p is the product of the radices of earlier stages.
+// transform b lives at buf[b * bs + swz(e)].  p is the product of the radices of earlier stages.
 // The stage reads every input into registers, synchronises, then writes every output, so it
 // works in place.
 template <typename T, int RAD, int MAXB>
@@ -135,9 +145,8 @@ __device__ void fft_stage(cplx<T>* buf, int n, int p, int nbatch, int bs, const 
                           int sign, int tid, int nthr) {
   const int nb = n / RAD;
   const int total = nbatch * nb;
-  const int tws = n / (p * RAD);
   cplx<T> y[MAXB][RAD];
-  int ob[MAXB];
+  int ob[MAXB], oi[MAXB];
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
     const int t = tid + q * nthr;
@@ -148,9 +157,9 @@ __device__ void fft_stage(cplx<T>* buf, int n, int p, int nbatch, int bs, const 
       cplx<T> x[RAD];
 #pragma unroll
       for (int j = 0; j < RAD; ++j) {
-        cplx<T> val = buf[b * bs + i + j * nb];
+        cplx<T> val = buf[b * bs + swz(i + j * nb)];
         if (j > 0 && k > 0) {
-          cplx<T> w = tw[j * k * tws];
+          cplx<T> w = tw[(j - 1) * p + k];
           if (sign > 0) w.y = -w.y;
           val = cmul(val, w);
         }
@@ -159,7 +168,8 @@ __device__ void fft_stage(cplx<T>* buf, int n, int p, int nbatch, int bs, const 
       Dft<T, RAD>::run(x, sign);
 #pragma unroll
       for (int j = 0; j < RAD; ++j) y[q][j] = x[j];
-      ob[q] = b * bs + (i - k) * RAD + k;
+      ob[q] = b * bs;
+      oi[q] = (i - k) * RAD + k;
     }
   }
   __syncthreads();
@@ -168,7 +178,7 @@ __device__ void fft_stage(cplx<T>* buf, int n, int p, int nbatch, int bs, const 
     const int t = tid + q * nthr;
     if (t < total) {
 #pragma unroll
-      for (int j = 0; j < RAD; ++j) buf[ob[q] + j * p] = y[q][j];
+      for (int j = 0; j < RAD; ++j) buf[ob[q] + swz(oi[q] + j * p)] = y[q][j];
     }
   }
   __syncthreads();
@@ -178,7 +188,7 @@ __device__ void fft_stage(cplx<T>* buf, int n, int p, int nbatch, int bs, const 
 template <typename T>
 __device__ __forceinline__ void load_twiddles(cplx<T>* tw_lds, const FFTPlanDev& pl, int tid, int nthr) {
   const cplx<T>* tw = static_cast<const cplx<T>*>(pl.tw);
-  for (int q = tid; q < pl.n; q += nthr) tw_lds[q] = tw[q];
+  for (int q = tid; q < pl.ntw; q += nthr) tw_lds[q] = tw[q];
 }
 
 // Full transform of nbatch sequences (nbatch * n <= kMaxE * nthr) with the twiddles in LDS.
@@ -188,16 +198,17 @@ __device__ void fft_lds(cplx<T>* buf, const cplx<T>* tw, const FFTPlanDev& pl, i
   int p = 1;
   for (int s = 0; s < pl.nstages; ++s) {
     const int r = pl.radix[s];
+    const cplx<T>* tws = tw + pl.twoff[s];
     if (r == 8)
-      fft_stage<T, 8, kMaxE / 8>(buf, pl.n, p, nbatch, bs, tw, sign, tid, nthr);
+      fft_stage<T, 8, kMaxE / 8>(buf, pl.n, p, nbatch, bs, tws, sign, tid, nthr);
     else if (r == 4)
-      fft_stage<T, 4, kMaxE / 4>(buf, pl.n, p, nbatch, bs, tw, sign, tid, nthr);
+      fft_stage<T, 4, kMaxE / 4>(buf, pl.n, p, nbatch, bs, tws, sign, tid, nthr);
     else if (r == 2)
-      fft_stage<T, 2, kMaxE / 2>(buf, pl.n, p, nbatch, bs, tw, sign, tid, nthr);
+      fft_stage<T, 2, kMaxE / 2>(buf, pl.n, p, nbatch, bs, tws, sign, tid, nthr);
     else if (r == 3)
-      fft_stage<T, 3, (kMaxE + 2) / 3>(buf, pl.n, p, nbatch, bs, tw, sign, tid, nthr);
+      fft_stage<T, 3, (kMaxE + 2) / 3>(buf, pl.n, p, nbatch, bs, tws, sign, tid, nthr);
     else
-      fft_stage<T, 5, (kMaxE + 4) / 5>(buf, pl.n, p, nbatch, bs, tw, sign, tid, nthr);
+      fft_stage<T, 5, (kMaxE + 4) / 5>(buf, pl.n, p, nbatch, bs, tws, sign, tid, nthr);
     p *= r;
   }
 }
@@ -235,7 +246,7 @@ __global__ void __launch_bounds__(256) k_row_fwd(RealFields<T> in, cplx<T>* __re
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* buf = tw + n2;
   const int nh = n2 / 2 + 1;
-  const int bs = n2 + 1;
+  const int bs = lds_stride(n2);
   const int q = blockIdx.y;
   const int z = blockIdx.z;
   const int r0 = blockIdx.x * rpb;
@@ -249,18 +260,19 @@ __global__ void __launch_bounds__(256) k_row_fwd(RealFields<T> in, cplx<T>* __re
   for (int idx = tid; idx < rows * n2; idx += nthr) {
     const int r = idx / n2, c = idx - r * n2;
     const size_t gi = size_t(r0 + r) * n2 + c;
-    buf[r * bs + c] = {A[gi], B ? B[gi] : T(0)};
+    buf[r * bs + swz(c)] = {A[gi], B ? B[gi] : T(0)};
   }
   __syncthreads();
   fft_lds<T>(buf, tw, pl, rows, bs, -1, tid, nthr);
-  const size_t sf = size_t(n1) * nh;
+  const int nhp = spec_stride(n2);
+  const size_t sf = size_t(n1) * nhp;
   cplx<T>* SA = S + (size_t(z) * in.count + fa) * sf;
   cplx<T>* SB = S + (size_t(z) * in.count + fb) * sf;
   for (int idx = tid; idx < rows * nh; idx += nthr) {
     const int r = idx / nh, k = idx - r * nh;
-    const cplx<T> zk = buf[r * bs + k];
-    const cplx<T> zm = cconj(buf[r * bs + (k == 0 ? 0 : n2 - k)]);
-    const size_t o = size_t(r0 + r) * nh + k;
+    const cplx<T> zk = buf[r * bs + swz(k)];
+    const cplx<T> zm = cconj(buf[r * bs + swz(k == 0 ? 0 : n2 - k)]);
+    const size_t o = size_t(r0 + r) * nhp + k;
     SA[o] = cscale(cadd(zk, zm), T(0.5));
     if (B) SB[o] = cscale(cmul_mi(csub(zk, zm)), T(0.5));
   }
@@ -274,7 +286,7 @@ __global__ void __launch_bounds__(256) k_row_inv(const cplx<T>* __restrict__ S, 
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* buf = tw + n2;
   const int nh = n2 / 2 + 1;
-  const int bs = n2 + 1;
+  const int bs = lds_stride(n2);
   const int q = blockIdx.y;
   const int z = blockIdx.z;
   const int r0 = blockIdx.x * rpb;
@@ -283,7 +295,8 @@ __global__ void __launch_bounds__(256) k_row_inv(const cplx<T>* __restrict__ S, 
   const bool hasb = fb < out.count;
   if (out.active && !out.active[z / out.item_div]) return;
   load_twiddles<T>(tw, pl, threadIdx.x, blockDim.x);
-  const size_t sf = size_t(n1) * nh;
+  const int nhp = spec_stride(n2);
+  const size_t sf = size_t(n1) * nhp;
   const cplx<T>* SA = S + (size_t(z) * nspec + fa) * sf;
   const cplx<T>* SB = S + (size_t(z) * nspec + fb) * sf;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -291,7 +304,7 @@ __global__ void __launch_bounds__(256) k_row_inv(const cplx<T>* __restrict__ S, 
     const int r = idx / n2, k = idx - r * n2;
     const bool mirror = k > n2 / 2;
     const int kk = mirror ? n2 - k : k;
-    const size_t o = size_t(r0 + r) * nh + kk;
+    const size_t o = size_t(r0 + r) * nhp + kk;
     cplx<T> a = SA[o];
     cplx<T> b = hasb ? SB[o] : cplx<T>{T(0), T(0)};
     if (kk == 0 || kk == n2 / 2) {  // a real row's DC and Nyquist coefficients are real
@@ -302,7 +315,7 @@ __global__ void __launch_bounds__(256) k_row_inv(const cplx<T>* __restrict__ S, 
       a = cconj(a);
       b = cconj(b);
     }
-    buf[r * bs + k] = cadd(a, cmul_i(b));
+    buf[r * bs + swz(k)] = cadd(a, cmul_i(b));
   }
   __syncthreads();
   fft_lds<T>(buf, tw, pl, rows, bs, +1, tid, nthr);
@@ -313,7 +326,7 @@ __global__ void __launch_bounds__(256) k_row_inv(const cplx<T>* __restrict__ S, 
   for (int idx = tid; idx < rows * n2; idx += nthr) {
     const int r = idx / n2, c = idx - r * n2;
     const size_t gi = size_t(r0 + r) * n2 + c;
-    const cplx<T> val = buf[r * bs + c];
+    const cplx<T> val = buf[r * bs + swz(c)];
     OA[gi] = AA ? val.x + AA[gi] : val.x;
     if (OB) OB[gi] = AB ? val.y + AB[gi] : val.y;
   }
@@ -337,17 +350,18 @@ __global__ void __launch_bounds__(1024) k_col(const cplx<T>* __restrict__ Sin, c
   constexpr int NIN = Op::NIN, NOUT = Op::NOUT;
   load_twiddles<T>(tw, pl, threadIdx.x, blockDim.x);
   const int nh = n2 / 2 + 1;
-  const int bs = n1 + 1;
+  const int bs = lds_stride(n1);
   const int c0 = blockIdx.x * B;
   const int cols = min(B, nh - c0);
   const int z = blockIdx.z;
-  const size_t sf = size_t(n1) * nh;
+  const int nhp = spec_stride(n2);
+  const size_t sf = size_t(n1) * nhp;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const cplx<T>* in = Sin + size_t(z) * NIN * sf;
   for (int f = 0; f < NIN; ++f)
     for (int idx = tid; idx < n1 * cols; idx += nthr) {
       const int e = idx / cols, b = idx - e * cols;
-      buf[(f * B + b) * bs + e] = in[f * sf + size_t(e) * nh + c0 + b];
+      buf[(f * B + b) * bs + swz(e)] = in[f * sf + size_t(e) * nhp + c0 + b];
     }
   __syncthreads();
   if (!(flags & kInK)) fft_lds<T>(buf, tw, pl, NIN * B, bs, -1, tid, nthr);
@@ -356,10 +370,10 @@ __global__ void __launch_bounds__(1024) k_col(const cplx<T>* __restrict__ Sin, c
     cplx<T> vin[NIN > 0 ? NIN : 1];
     cplx<T> vout[NOUT > 0 ? NOUT : 1];
 #pragma unroll
-    for (int f = 0; f < NIN; ++f) vin[f] = buf[(f * B + b) * bs + e];
+    for (int f = 0; f < NIN; ++f) vin[f] = buf[(f * B + b) * bs + swz(e)];
     op(signed_wavenumber(e, n1), c0 + b, e, z, vin, vout);
 #pragma unroll
-    for (int f = 0; f < NOUT; ++f) buf[(f * B + b) * bs + e] = vout[f];
+    for (int f = 0; f < NOUT; ++f) buf[(f * B + b) * bs + swz(e)] = vout[f];
   }
   __syncthreads();
   if (NOUT == 0) return;
@@ -368,7 +382,7 @@ __global__ void __launch_bounds__(1024) k_col(const cplx<T>* __restrict__ Sin, c
   for (int f = 0; f < NOUT; ++f)
     for (int idx = tid; idx < n1 * cols; idx += nthr) {
       const int e = idx / cols, b = idx - e * cols;
-      out[f * sf + size_t(e) * nh + c0 + b] = buf[(f * B + b) * bs + e];
+      out[f * sf + size_t(e) * nhp + c0 + b] = buf[(f * B + b) * bs + swz(e)];
     }
 }
 
@@ -500,7 +514,7 @@ struct OpRestrict {
   int n1, n2, nc1, nc2;
   double inv_n;
   __device__ void operator()(int k1, int k2, int, int z, const cplx<T>* in, cplx<T>* out) const {
-    const int nch = nc2 / 2 + 1;
+    const int nch = spec_stride(nc2);  // row stride of the coarse half spectrum
     if (4 * abs(k1) < n1 && 4 * k2 < n2) {
       const int e = k1 < 0 ? k1 + nc1 : k1;
       const size_t sfc = size_t(nc1) * nch;
@@ -530,7 +544,7 @@ struct OpProlongCombine {
   int n1, n2, nc1, nc2;
   double inv_n, inv_nc;
   __device__ void operator()(int k1, int k2, int, int z, const cplx<T>* in, cplx<T>* out) const {
-    const int nch = nc2 / 2 + 1;
+    const int nch = spec_stride(nc2);  // row stride of the coarse half spectrum
     const bool low = 4 * abs(k1) < n1 && 4 * k2 < n2;
     const size_t sfc = size_t(nc1) * nch;
     const int e = k1 < 0 ? k1 + nc1 : k1;
@@ -568,7 +582,7 @@ hipError_t launch_row_fwd(hipStream_t s, const SpecGrid<T>& g, RealFields<T> in,
   int nthr, rpb;
   row_config<T>(g.n2, nthr, rpb);
   dim3 grid((g.n1 + rpb - 1) / rpb, (in.count + 1) / 2, batch);
-  size_t lds = (size_t(rpb) * (g.n2 + 1) + g.n2) * sizeof(cplx<T>);
+  size_t lds = (size_t(rpb) * lds_stride(g.n2) + g.n2) * sizeof(cplx<T>);
   static std::atomic<size_t> allowed{0};
   RET_IF(allow_lds(k_row_fwd<T>, lds, allowed));
   hipLaunchKernelGGL(k_row_fwd<T>, grid, dim3(nthr), lds, s, in, S, g.n1, g.n2, rpb, g.row);
@@ -581,7 +595,7 @@ hipError_t launch_row_inv(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* S,
   int nthr, rpb;
   row_config<T>(g.n2, nthr, rpb);
   dim3 grid((g.n1 + rpb - 1) / rpb, (out.count + 1) / 2, batch);
-  size_t lds = (size_t(rpb) * (g.n2 + 1) + g.n2) * sizeof(cplx<T>);
+  size_t lds = (size_t(rpb) * lds_stride(g.n2) + g.n2) * sizeof(cplx<T>);
   static std::atomic<size_t> allowed{0};
   RET_IF(allow_lds(k_row_inv<T>, lds, allowed));
   hipLaunchKernelGGL(k_row_inv<T>, grid, dim3(nthr), lds, s, S, nspec, out, g.n1, g.n2, rpb, g.row);
@@ -594,7 +608,7 @@ hipError_t launch_row_inv(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* S,
 // Every FFT stage stays within kMaxE elements per thread at <= 1024 threads.
 template <typename T>
 void col_config(int n1, int nh, int nmax, int batch, int& B, int& nthr, size_t& lds) {
-  const int col_bytes = (n1 + 1) * int(sizeof(cplx<T>)) * nmax;
+  const int col_bytes = lds_stride(n1) * int(sizeof(cplx<T>)) * nmax;
   const int bmax = std::max(1, std::min(16, kLdsBudget / col_bytes));
   B = std::max(1, std::min(std::min(16, std::max(1, nh / 64)), bmax));
   while (B < bmax && ((nh + 2 * B - 1) / (2 * B)) * batch >= 512) B *= 2;
@@ -641,7 +655,7 @@ template <typename T>
 size_t spec_lds_bytes(int n1, int n2) {
   int nthr, rpb, B;
   row_config<T>(n2, nthr, rpb);
-  const size_t row = (size_t(rpb) * (n2 + 1) + n2) * sizeof(cplx<T>);
+  const size_t row = (size_t(rpb) * lds_stride(n2) + n2) * sizeof(cplx<T>);
   size_t col = 0;
   col_config<T>(n1, n2 / 2 + 1, 4, 1 << 20, B, nthr, col);  // widest operator, widest panel
   return std::max(row, col);
