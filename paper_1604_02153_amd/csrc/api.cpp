@@ -1,5 +1,5 @@
 // Host orchestration of the semi-Lagrangian Gauss--Newton--Krylov path behind the C ABI of
-// include/slnk.h.  Everything numerical runs in the gfx950 kernels of spectral.hip,
+// include/slnk.h.  Everything numerical runs in the gfx950 kernels of spectral_impl.hpp,
 // transport.hip and blas.hip; this file sequences them, owns the device workspace and keeps the
 // FP64 scalars of the Krylov, Chebyshev, Lanczos and Newton iterations.
 //
@@ -242,7 +242,7 @@ struct Context {
     // per-stage twiddles: stage s (radix R, p = product of the earlier radices) holds
     // w^(j k n / (p R)) = exp(-2 pi i j k / (p R)) at twoff[s] + (j - 1) p + k, j = 1..R-1,
     // k = 0..p-1 (n - 1 values in all), so that consecutive butterflies read consecutive entries
-    std::vector<cplx<U>> h(n, cplx<U>{U(1), U(0)});
+    std::vector<cplx<U>> h(2 * size_t(n), cplx<U>{U(1), U(0)});
     int p = 1, off = 0;
     for (size_t st = 0; st < r.size(); ++st) {
       pl.radix[st] = r[st];
@@ -256,9 +256,15 @@ struct Context {
       p *= r[st];
     }
     pl.ntw = off;
-    tw = arena.take<cplx<U>>(n);
-    HIPCHK(hipMemcpy(tw, h.data(), n * sizeof(cplx<U>), hipMemcpyHostToDevice));
+    // roots of unity exp(-2 pi i m / n), m < n, for the wave-level transforms
+    for (int m = 0; m < n; ++m) {
+      const double a = 2.0 * kPi * double(m) / double(n);
+      h[n + m] = {U(std::cos(a)), U(-std::sin(a))};
+    }
+    tw = arena.take<cplx<U>>(2 * n);
+    HIPCHK(hipMemcpy(tw, h.data(), 2 * n * sizeof(cplx<U>), hipMemcpyHostToDevice));
     pl.tw = tw;
+    pl.roots = static_cast<cplx<U>*>(tw) + n;
   }
 
   static size_t level_bytes(int n1, int n2, int nt, int B) {
@@ -268,7 +274,7 @@ struct Context {
     // images; two slots of (v, df, da, gamma, m, gm, bAv); cv, divv, cdiv; lam, acc, g, q, bt, w;
     // coef, coef2; vec[8]; gmT
     const size_t fields = 2 + 2 * (2 + 2 + 2 + 1 + (nt + 1) + 2 * (nt + 1) + 2) + 2 + 1 + 1 + 2 * 6 + 2 + 2 * 8 + 2;
-    return B * (fields * F * sizeof(T) + (2 * nspec + 2) * spec * sizeof(cplx<T>)) + (n1 + n2) * sizeof(cplx<T>) +
+    return B * (fields * F * sizeof(T) + (2 * nspec + 2) * spec * sizeof(cplx<T>)) + 2 * (n1 + n2) * sizeof(cplx<T>) +
            96 * 256 + 2 * B * sizeof(int);
   }
 
@@ -348,7 +354,7 @@ struct Context {
     size_t bytes = level_bytes(p.n1, p.n2, p.nt, B) + (two_level ? level_bytes(p.n1 / 2, p.n2 / 2, p.nt, B) : 0);
     bytes += (2 * partial_half + 8 * B + 16 * B + 2 * 64 * B + B) * sizeof(double) + 4 * B * sizeof(int) + 8192;
     bytes += B * (4 * 2 * F * sizeof(double) + 2 * 2 * size_t(p.n1) * spec_stride(p.n2) * sizeof(cplx<double>)) +
-             (p.n1 + p.n2) * sizeof(cplx<double>) + 16 * 256;
+             2 * (p.n1 + p.n2) * sizeof(cplx<double>) + 16 * 256;
     bytes += B * (2 * F * sizeof(T) + sizeof(float)) + 2 * 256;
     void* base = nullptr;
     if (hipMalloc(&base, bytes) != hipSuccess) throw Fail{SLNK_ENOMEM, "hipMalloc of the workspace failed"};

@@ -11,7 +11,8 @@ constexpr int kFFTMaxStages = 16;
 // Factorisation of one transform length into radix-8/4/2/3/5 stages plus its twiddle table
 // (device memory, computed on the host in FP64): stage s, radix R, p = product of the earlier
 // radices, holds exp(-2 pi i j k / (p R)) at twoff[s] + (j - 1) p + k (j = 1..R-1, k < p);
-// ntw = n - 1 values in all.
+// ntw = n - 1 values in all.  'roots' holds exp(-2 pi i m / n), m < n (device memory, same
+// precision), for the wave-level transforms of the common lengths.
 struct FFTPlanDev {
   int n = 0;
   int nstages = 0;
@@ -19,6 +20,7 @@ struct FFTPlanDev {
   int twoff[kFFTMaxStages] = {0};
   int ntw = 0;
   const void* tw = nullptr;
+  const void* roots = nullptr;
 };
 
 // Grid description passed to every spectral launcher.

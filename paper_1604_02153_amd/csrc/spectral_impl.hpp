@@ -1,5 +1,5 @@
-// Pseudospectral operators on the periodic grid: LDS-resident mixed-radix (4, 2, 3, 5) Stockham
-// FFTs fused with the spectral diagonal operators of the method (section 3.2: Fourier
+// Pseudospectral operators on the periodic grid: LDS-resident mixed-radix (8, 4, 2, 3, 5)
+// Stockham FFTs fused with the spectral diagonal operators of the method (section 3.2: Fourier
 // discretisation; eq. e:diffopregv: regulariser symbols; eq. e:reg-precond: P_REG; section
 // 3.4.2: split preconditioning, cut-off filters, spectral restriction and prolongation).
 //
@@ -11,6 +11,11 @@
 //
 // Conventions: forward transforms are unnormalised; every symbol carries the 1/(n1 n2) of the
 // inverse.  Odd symbols (derivatives) drop the Nyquist modes, even symbols keep them.
+//
+// Compiled once per precision: spectral_f32.hip and spectral_f64.hip define SLNK_SPECTRAL_REAL
+// and include this file.
+#pragma once
+
 #include <atomic>
 #include <mutex>
 
@@ -386,6 +391,320 @@ __global__ void __launch_bounds__(1024) k_col(const cplx<T>* __restrict__ Sin, c
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Wave-level transforms of the common lengths: powers of two 64..1024 and 3 * 2^k, 96..768.
+// A transform belongs to LPT = N / E lanes of one wavefront (E = 16 elements per lane for powers
+// of two, 12 otherwise), so a wavefront holds 64 / LPT transforms.  A stage keeps the lane's
+// elements in registers; between stages the wavefront exchanges them through its own LDS region,
+// so the transforms need no workgroup barrier.  Stockham order: butterfly i (k = i mod p) of a
+// radix-r stage reads elements i + j N / r and writes (i - k) r + k + j p.  Lane lp of a
+// transform owns butterflies lp + LPT q, so the first stage reads elements lp + LPT q + j N / r1
+// and the last stage leaves element lp + LPT q + j N / rL in register q rL + j.  A transform run
+// with the radix list reversed starts from exactly that mapping (and ends in the r1 mapping).
+// ---------------------------------------------------------------------------------------
+template <int N>
+struct WPlan {
+  static constexpr bool kPow2 = (N & (N - 1)) == 0;
+  static constexpr int E = kPow2 ? 16 : 12;
+  static constexpr int LPT = N / E;
+  static constexpr int T = 64 / LPT;
+  static constexpr int NS = N == 64 ? 2 : N == 128 || N == 256 || N == 512 ? 3 : N == 384 || N == 768 ? 5 : 4;
+  static constexpr int radix(int s) {
+    switch (N) {
+      case 64: return 8;
+      case 128: return s == 0 ? 8 : 4;
+      case 256: return s < 2 ? 8 : 4;
+      case 512: return 8;
+      case 1024: return s < 2 ? 8 : 4;
+      case 96: return s == 0 ? 3 : (s < 3 ? 4 : 2);
+      case 192: return s == 0 ? 3 : 4;
+      case 384: return s == 0 ? 3 : (s < 4 ? 4 : 2);
+      case 768: return s == 0 ? 3 : 4;
+    }
+    return 0;
+  }
+  static constexpr int product() {
+    int p = 1;
+    for (int s = 0; s < NS; ++s) p *= radix(s);
+    return p;
+  }
+  // LDS strides (complex elements) of a transform's region: exchange only (column passes), and
+  // exchange plus the transposed access of the row passes (chosen with a bank model of gfx950's
+  // 64 banks)
+  static constexpr int col_stride = N + (N == 64 ? 4 : N == 128 || N == 96 ? 8 : N == 256 || N == 192 ? 16 : 0);
+  static constexpr int row_stride = N + (N == 96 ? 8 : N == 64 || N == 128 || N == 1024 || N == 768 ? 4 : 2);
+  // element e of a region: XOR swizzle of the low five bits (powers of two), identity otherwise
+  __device__ static __forceinline__ int pos(int e) {
+    if constexpr (kPow2)
+      return e ^ ((e >> 3) & 31);
+    else
+      return e;
+  }
+};
+
+// Orders the wavefront's LDS accesses around an exchange (LDS operations of one wavefront complete
+// in issue order; the fences keep the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Transform of length N (SIGN -1 forward, +1 inverse, unnormalised) of the elements x held by lane
+// lp of a transform in the first stage's mapping; returns the outputs in the last stage's mapping.
+// reg: the transform's LDS region (N elements at WPlan::pos); roots: exp(-2 pi i m / N), m < N.
+template <typename T, int N, int SIGN, bool REV, int S = 0, int P = 1>
+__device__ __forceinline__ void wave_fft(cplx<T> (&x)[WPlan<N>::E], cplx<T>* reg, const cplx<T>* roots, int lp) {
+  using PL = WPlan<N>;
+  constexpr int NS = PL::NS;
+  static_assert(PL::product() == N, "radix list must multiply to N");
+  static_assert(PL::E % PL::radix(S < NS ? (REV ? NS - 1 - S : S) : 0) == 0, "radix must divide E");
+  if constexpr (S < NS) {
+    constexpr int r = PL::radix(REV ? NS - 1 - S : S);
+    constexpr int step = N / (r * P);  // w_(rP)^(jk) = roots[j k N / (r P)]
+#pragma unroll
+    for (int q = 0; q < PL::E / r; ++q) {
+      if constexpr (P > 1) {
+        const int k = (lp + PL::LPT * q) % P;
+#pragma unroll
+        for (int j = 1; j < r; ++j) {
+          cplx<T> w = roots[j * k * step];
+          if (SIGN > 0) w.y = -w.y;
+          x[q * r + j] = cmul(x[q * r + j], w);
+        }
+      }
+      Dft<T, r>::run(&x[q * r], SIGN);
+    }
+    if constexpr (S + 1 < NS) {
+      constexpr int rn = PL::radix(REV ? NS - 2 - S : S + 1);
+#pragma unroll
+      for (int q = 0; q < PL::E / r; ++q) {
+        const int i = lp + PL::LPT * q;
+        const int k = i % P;
+#pragma unroll
+        for (int j = 0; j < r; ++j) reg[PL::pos((i - k) * r + k + j * P)] = x[q * r + j];
+      }
+      wave_sync();
+#pragma unroll
+      for (int q = 0; q < PL::E / rn; ++q)
+#pragma unroll
+        for (int j = 0; j < rn; ++j) x[q * rn + j] = reg[PL::pos(lp + PL::LPT * q + j * (N / rn))];
+      wave_sync();
+    }
+    wave_fft<T, N, SIGN, REV, S + 1, P * r>(x, reg, roots, lp);
+  }
+}
+
+// element index held in register m by lane lp in the mapping of a radix-r first or last stage
+template <int N, int r>
+__device__ __forceinline__ int wmap(int lp, int m) {
+  return lp + WPlan<N>::LPT * (m / r) + (m % r) * (N / r);
+}
+
+// ---- wave-level passes -------------------------------------------------------------------
+// Intermediate layout: the half spectra are stored transposed, St[k2][x1] (row k2 < n2/2 + 1 of
+// n1 contiguous values), so that the column transforms read and write whole rows.
+
+// rows per workgroup of the row passes (transposed segments of R complex values)
+template <typename T, int N>
+struct FRow {
+  static constexpr int R = sizeof(T) == 4 ? (N >= 768 ? 8 : 16) : (N >= 768 ? 4 : N >= 192 ? 8 : 16);
+  static constexpr int S = WPlan<N>::row_stride;
+  static constexpr int W = R / WPlan<N>::T;
+  static constexpr int kThreads = 64 * W;
+  static constexpr size_t kLds = (size_t(N) + size_t(R) * S) * sizeof(cplx<T>);
+};
+
+// Forward row pass: fields (2q, 2q+1) of item z packed as one complex row, transformed along x2,
+// unpacked into the transposed half spectra of fields 2q and 2q+1.
+template <typename T, int N>
+__global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_fwd(RealFields<T> in, cplx<T>* __restrict__ S, int n1,
+                                                                   const cplx<T>* __restrict__ roots) {
+  using PL = WPlan<N>;
+  using RW = FRow<T, N>;
+  constexpr int R = RW::R, nh = N / 2 + 1;
+  constexpr int r1 = PL::radix(0), rL = PL::radix(PL::NS - 1);
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* rt = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* zb = rt + N;
+  const int z = blockIdx.z;
+  if (in.active && !in.active[z / in.item_div]) return;
+  const int fa = 2 * blockIdx.y, fb = fa + 1;
+  const int r0 = blockIdx.x * R;
+  const T* A = in.p[fa] + z * in.bstride[fa];
+  const T* B = fb < in.count ? in.p[fb] + z * in.bstride[fb] : nullptr;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int lp = lane % PL::LPT;
+  const int row = (tid >> 6) * PL::T + lane / PL::LPT;
+  const size_t gb = size_t(r0 + row) * N;
+  cplx<T> x[PL::E];
+#pragma unroll
+  for (int m = 0; m < PL::E; ++m) {
+    const int e = wmap<N, r1>(lp, m);
+    x[m] = {A[gb + e], B ? B[gb + e] : T(0)};
+  }
+  for (int i = tid; i < N; i += RW::kThreads) rt[i] = roots[i];
+  __syncthreads();
+  cplx<T>* reg = zb + row * RW::S;
+  wave_fft<T, N, -1, false>(x, reg, rt, lp);
+#pragma unroll
+  for (int m = 0; m < PL::E; ++m) reg[PL::pos(wmap<N, rL>(lp, m))] = x[m];
+  __syncthreads();
+  const size_t sf = size_t(nh) * n1;
+  cplx<T>* SA = S + (size_t(z) * in.count + fa) * sf + r0;
+  cplx<T>* SB = S + (size_t(z) * in.count + fb) * sf + r0;
+  for (int idx = tid; idx < nh * R; idx += RW::kThreads) {
+    const int k = idx / R, rr = idx % R;
+    const cplx<T>* zr = zb + rr * RW::S;
+    const cplx<T> zk = zr[PL::pos(k)];
+    const cplx<T> zm = cconj(zr[PL::pos(k == 0 ? 0 : N - k)]);
+    const size_t o = size_t(k) * n1 + rr;
+    SA[o] = cscale(cadd(zk, zm), T(0.5));
+    if (B) SB[o] = cscale(cmul_mi(csub(zk, zm)), T(0.5));
+  }
+}
+
+// Inverse row pass: transposed half spectra (2q, 2q+1) of item z -> real fields (plus addend).
+template <typename T, int N>
+__global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_inv(const cplx<T>* __restrict__ S, int nspec,
+                                                                   OutFields<T> out, int n1,
+                                                                   const cplx<T>* __restrict__ roots) {
+  using PL = WPlan<N>;
+  using RW = FRow<T, N>;
+  constexpr int R = RW::R, nh = N / 2 + 1;
+  constexpr int r1 = PL::radix(0), rL = PL::radix(PL::NS - 1);
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* rt = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* zb = rt + N;
+  const int z = blockIdx.z;
+  if (out.active && !out.active[z / out.item_div]) return;
+  const int fa = 2 * blockIdx.y, fb = fa + 1;
+  const bool hasb = fb < out.count;
+  const int r0 = blockIdx.x * R;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const size_t sf = size_t(nh) * n1;
+  const cplx<T>* SA = S + (size_t(z) * nspec + fa) * sf + r0;
+  const cplx<T>* SB = S + (size_t(z) * nspec + fb) * sf + r0;
+  for (int i = tid; i < N; i += RW::kThreads) rt[i] = roots[i];
+  for (int idx = tid; idx < nh * R; idx += RW::kThreads) {
+    const int k = idx / R, rr = idx % R;
+    const size_t o = size_t(k) * n1 + rr;
+    cplx<T> a = SA[o];
+    cplx<T> b = hasb ? SB[o] : cplx<T>{T(0), T(0)};
+    if (k == 0 || k == N / 2) {  // a real row's DC and Nyquist coefficients are real
+      a.y = T(0);
+      b.y = T(0);
+    }
+    cplx<T>* zr = zb + rr * RW::S;
+    zr[PL::pos(k)] = cadd(a, cmul_i(b));
+    if (k > 0 && k < N / 2) zr[PL::pos(N - k)] = cadd(cconj(a), cmul_i(cconj(b)));
+  }
+  __syncthreads();
+  const int lp = lane % PL::LPT;
+  const int row = (tid >> 6) * PL::T + lane / PL::LPT;
+  cplx<T>* reg = zb + row * RW::S;
+  cplx<T> x[PL::E];
+#pragma unroll
+  for (int m = 0; m < PL::E; ++m) x[m] = reg[PL::pos(wmap<N, r1>(lp, m))];
+  wave_sync();
+  wave_fft<T, N, +1, false>(x, reg, rt, lp);
+  const size_t gb = size_t(r0 + row) * N;
+  T* OA = out.p[fa] + z * out.bstride[fa] + gb;
+  T* OB = hasb ? out.p[fb] + z * out.bstride[fb] + gb : nullptr;
+  const T* AA = out.add[fa] ? out.add[fa] + z * out.bstride[fa] + gb : nullptr;
+  const T* AB = hasb && out.add[fb] ? out.add[fb] + z * out.bstride[fb] + gb : nullptr;
+#pragma unroll
+  for (int m = 0; m < PL::E; ++m) {
+    const int e = wmap<N, rL>(lp, m);
+    OA[e] = AA ? x[m].x + AA[e] : x[m].x;
+    if (OB) OB[e] = AB ? x[m].y + AB[e] : x[m].y;
+  }
+}
+
+template <typename T, int N>
+struct FCol {
+  static constexpr int W = 4;  // wavefronts per workgroup
+  static constexpr int KR = W * WPlan<N>::T;  // rows k2 per workgroup
+  static constexpr int S = WPlan<N>::col_stride;
+  static constexpr int kThreads = 64 * W;
+  static constexpr size_t kLds = (size_t(N) + size_t(KR) * S) * sizeof(cplx<T>);
+};
+
+// Column pass over rows k2 of the transposed spectra of item z: forward transform along x1 (unless
+// kInK: the input is k-space in the last-stage mapping), op at every (k1, k2), inverse transform
+// (unless kOutK: the output stays k-space).  Each output is formed and transformed on its own, from
+// the inputs held in registers.
+template <typename T, int N, class Op, int FL>
+__global__ void __launch_bounds__(256) k_fcol(const cplx<T>* __restrict__ Sin, cplx<T>* __restrict__ Sout, int nh,
+                                              Op op, const cplx<T>* __restrict__ roots, const int* active,
+                                              int item_div) {
+  using PL = WPlan<N>;
+  using CW = FCol<T, N>;
+  constexpr int NIN = Op::NIN, NOUT = Op::NOUT;
+  constexpr int r1 = PL::radix(0), rL = PL::radix(PL::NS - 1);
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* rt = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* xb = rt + N;
+  const int z = blockIdx.z;
+  if (active && !active[z / item_div]) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int lp = lane % PL::LPT;
+  const int slot = (tid >> 6) * PL::T + lane / PL::LPT;
+  const int k2 = blockIdx.x * CW::KR + slot;
+  const bool valid = k2 < nh;
+  const int k2c = valid ? k2 : nh - 1;
+  const size_t sf = size_t(nh) * N;
+  cplx<T>* reg = xb + slot * CW::S;
+  for (int i = tid; i < N; i += CW::kThreads) rt[i] = roots[i];
+  cplx<T> vin[NIN][PL::E];
+#pragma unroll
+  for (int f = 0; f < NIN; ++f) {
+    const cplx<T>* src = Sin + (size_t(z) * NIN + f) * sf + size_t(k2c) * N;
+#pragma unroll
+    for (int m = 0; m < PL::E; ++m) vin[f][m] = src[(FL & kInK) ? wmap<N, rL>(lp, m) : wmap<N, r1>(lp, m)];
+  }
+  __syncthreads();
+  if constexpr (!(FL & kInK)) {
+#pragma unroll
+    for (int f = 0; f < NIN; ++f) wave_fft<T, N, -1, false>(vin[f], reg, rt, lp);
+  }
+  if constexpr (Op::kPre) {
+    if (valid) {
+#pragma unroll
+      for (int m = 0; m < PL::E; ++m) {
+        cplx<T> v[NIN];
+#pragma unroll
+        for (int f = 0; f < NIN; ++f) v[f] = vin[f][m];
+        op.pre(signed_wavenumber(wmap<N, rL>(lp, m), N), k2, z, v);
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < NOUT; ++g) {
+    cplx<T> y[PL::E];
+#pragma unroll
+    for (int m = 0; m < PL::E; ++m) {
+      cplx<T> v[NIN];
+#pragma unroll
+      for (int f = 0; f < NIN; ++f) v[f] = vin[f][m];
+      y[m] = op.out(g, signed_wavenumber(wmap<N, rL>(lp, m), N), k2c, z, v);
+    }
+    cplx<T>* dst = Sout + (size_t(z) * NOUT + g) * sf + size_t(k2c) * N;
+    if constexpr (!(FL & kOutK)) {
+      wave_fft<T, N, +1, true>(y, reg, rt, lp);
+      if (valid) {
+#pragma unroll
+        for (int m = 0; m < PL::E; ++m) dst[wmap<N, r1>(lp, m)] = y[m];
+      }
+    } else {
+      if (valid) {
+#pragma unroll
+        for (int m = 0; m < PL::E; ++m) dst[wmap<N, rL>(lp, m)] = y[m];
+      }
+    }
+  }
+}
+
 // ---- symbols ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T odd_k(int k, int n) { return (2 * k == -n) ? T(0) : T(k); }  // Nyquist dropped
@@ -432,24 +751,33 @@ __device__ __forceinline__ T symbol_value(const SymbolParams& sp, int k1, int n1
   }
 }
 
+// Every operator gives all outputs at one wavenumber (operator(), generic column pass) and output g
+// alone (out(), wave-level column pass); pre() is a side effect at each wavenumber, run once.
 template <typename T, int NF>
 struct OpScale {
   static constexpr int NIN = NF, NOUT = NF;
+  static constexpr bool kPre = false;
   SymbolParams sp;
   int n1, n2;
   double inv_n;
-  __device__ void operator()(int k1, int k2, int, int, const cplx<T>* in, cplx<T>* out) const {
+  __device__ T coef(int k1, int k2) const {
     const int k2s = (2 * k2 == n2) ? -k2 : k2;
-    const T s = symbol_value<T>(sp, k1, n1, k2s, n2) * T(inv_n);
+    return symbol_value<T>(sp, k1, n1, k2s, n2) * T(inv_n);
+  }
+  __device__ void operator()(int k1, int k2, int, int, const cplx<T>* in, cplx<T>* out) const {
+    const T s = coef(k1, k2);
 #pragma unroll
     for (int f = 0; f < NF; ++f) out[f] = cscale(in[f], s);
   }
+  __device__ void pre(int, int, int, const cplx<T>*) const {}
+  __device__ cplx<T> out(int g, int k1, int k2, int, const cplx<T>* in) const { return cscale(in[g], coef(k1, k2)); }
 };
 
 // two symbols of the same two input fields: out[0..2) = sym1 in, out[2..4) = sym2 in
 template <typename T>
 struct OpScale2 {
   static constexpr int NIN = 2, NOUT = 4;
+  static constexpr bool kPre = false;
   SymbolParams sp1, sp2;
   int n1, n2;
   double inv_n;
@@ -462,11 +790,18 @@ struct OpScale2 {
     out[2] = cscale(in[0], b);
     out[3] = cscale(in[1], b);
   }
+  __device__ void pre(int, int, int, const cplx<T>*) const {}
+  __device__ cplx<T> out(int g, int k1, int k2, int, const cplx<T>* in) const {
+    const int k2s = (2 * k2 == n2) ? -k2 : k2;
+    const T s = symbol_value<T>(g < 2 ? sp1 : sp2, k1, n1, k2s, n2) * T(inv_n);
+    return cscale(in[g & 1], s);
+  }
 };
 
 template <typename T>
 struct OpGrad {
   static constexpr int NIN = 1, NOUT = 2;
+  static constexpr bool kPre = false;
   int n1, n2;
   double inv_n;
   __device__ void operator()(int k1, int k2, int, int, const cplx<T>* in, cplx<T>* out) const {
@@ -474,11 +809,17 @@ struct OpGrad {
     out[0] = cmul_i(cscale(in[0], odd_k<T>(k1, n1) * s));
     out[1] = cmul_i(cscale(in[0], (2 * k2 == n2 ? T(0) : T(k2)) * s));
   }
+  __device__ void pre(int, int, int, const cplx<T>*) const {}
+  __device__ cplx<T> out(int g, int k1, int k2, int, const cplx<T>* in) const {
+    const T k = g == 0 ? odd_k<T>(k1, n1) : (2 * k2 == n2 ? T(0) : T(k2));
+    return cmul_i(cscale(in[0], k * T(inv_n)));
+  }
 };
 
 template <typename T>
 struct OpTracePrep {
   static constexpr int NIN = 2, NOUT = 4;  // cv1, cv2, div v, c_div
+  static constexpr bool kPre = false;
   int n1, n2;
   double inv_n;
   __device__ void operator()(int k1, int k2, int, int, const cplx<T>* in, cplx<T>* out) const {
@@ -492,17 +833,37 @@ struct OpTracePrep {
     out[2] = cscale(d, s);
     out[3] = cscale(d, ib);
   }
+  __device__ void pre(int, int, int, const cplx<T>*) const {}
+  __device__ cplx<T> out(int g, int k1, int k2, int, const cplx<T>* in) const {
+    const int k2s = (2 * k2 == n2) ? -k2 : k2;
+    const T s = T(inv_n);
+    const T f = g == 2 ? s : s / spline_symbol<T>(k1, n1, k2s, n2);
+    if (g < 2) return cscale(in[g], f);
+    const T o1 = odd_k<T>(k1, n1), o2 = (2 * k2 == n2) ? T(0) : T(k2);
+    return cscale(cmul_i(cadd(cscale(in[0], o1), cscale(in[1], o2))), f);
+  }
 };
 
 // k-space identity (used for coarse forward transforms and coarse inverse transforms)
 template <typename T, int NF>
 struct OpCopy {
   static constexpr int NIN = NF, NOUT = NF;
+  static constexpr bool kPre = false;
   __device__ void operator()(int, int, int, int, const cplx<T>* in, cplx<T>* out) const {
 #pragma unroll
     for (int f = 0; f < NF; ++f) out[f] = in[f];
   }
+  __device__ void pre(int, int, int, const cplx<T>*) const {}
+  __device__ cplx<T> out(int g, int, int, int, const cplx<T>* in) const { return in[g]; }
 };
+
+// Position of coarse mode (e, k2) of field f of item z in the coarse k-space buffer: rows of the
+// half spectrum [nc1][nch] (generic passes) or its transpose [nc2 / 2 + 1][nc1] (wave passes).
+__device__ __forceinline__ size_t coarse_at(bool tr, int z, int NF, int f, int e, int k2, int nc1, int nc2) {
+  if (tr) return ((size_t(z) * NF + f) * size_t(nc2 / 2 + 1) + k2) * nc1 + e;
+  const int nch = spec_stride(nc2);
+  return ((size_t(z) * NF + f) * nc1 + e) * nch + k2;
+}
 
 // Restriction: writes the surviving modes of the fine spectrum (scaled by 1/N_fine so that the
 // coarse inverse needs no further scale) into the coarse k-space buffer, and keeps the fine
@@ -510,29 +871,31 @@ struct OpCopy {
 template <typename T, int NF>
 struct OpRestrict {
   static constexpr int NIN = NF, NOUT = NF;
-  cplx<T>* coarse;   // [z][NF][nc1][nch] k-space
+  static constexpr bool kPre = true;
+  cplx<T>* coarse;   // [z][NF] coarse k-space spectra (layout: coarse_at)
   int n1, n2, nc1, nc2;
   double inv_n;
-  __device__ void operator()(int k1, int k2, int, int z, const cplx<T>* in, cplx<T>* out) const {
-    const int nch = spec_stride(nc2);  // row stride of the coarse half spectrum
+  int tr;
+  __device__ void pre(int k1, int k2, int z, const cplx<T>* in) const {
     if (4 * abs(k1) < n1 && 4 * k2 < n2) {
       const int e = k1 < 0 ? k1 + nc1 : k1;
-      const size_t sfc = size_t(nc1) * nch;
 #pragma unroll
-      for (int f = 0; f < NF; ++f)
-        coarse[(size_t(z) * NF + f) * sfc + size_t(e) * nch + k2] = cscale(in[f], T(inv_n));
+      for (int f = 0; f < NF; ++f) coarse[coarse_at(tr, z, NF, f, e, k2, nc1, nc2)] = cscale(in[f], T(inv_n));
     } else if (abs(k1) <= nc1 / 2 && k2 <= nc2 / 2) {
       // coarse Nyquist row/column: dropped
       const int e = k1 < 0 ? k1 + nc1 : k1;
       if (e < nc1) {
-        const size_t sfc = size_t(nc1) * nch;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) coarse[(size_t(z) * NF + f) * sfc + size_t(e) * nch + k2] = {T(0), T(0)};
+        for (int f = 0; f < NF; ++f) coarse[coarse_at(tr, z, NF, f, e, k2, nc1, nc2)] = {T(0), T(0)};
       }
     }
+  }
+  __device__ void operator()(int k1, int k2, int, int z, const cplx<T>* in, cplx<T>* out) const {
+    pre(k1, k2, z, in);
 #pragma unroll
     for (int f = 0; f < NF; ++f) out[f] = in[f];
   }
+  __device__ cplx<T> out(int g, int, int, int, const cplx<T>* in) const { return in[g]; }
 };
 
 // Two-level combine (input: kept fine spectrum, k-space): high-pass part of it plus the
@@ -540,22 +903,23 @@ struct OpRestrict {
 template <typename T, int NF>
 struct OpProlongCombine {
   static constexpr int NIN = NF, NOUT = NF;
-  const cplx<T>* coarse;   // [z][NF][nc1][nch] k-space (forward transform, unnormalised)
+  static constexpr bool kPre = false;
+  const cplx<T>* coarse;   // [z][NF] coarse k-space spectra (forward transform, unnormalised)
   int n1, n2, nc1, nc2;
   double inv_n, inv_nc;
-  __device__ void operator()(int k1, int k2, int, int z, const cplx<T>* in, cplx<T>* out) const {
-    const int nch = spec_stride(nc2);  // row stride of the coarse half spectrum
-    const bool low = 4 * abs(k1) < n1 && 4 * k2 < n2;
-    const size_t sfc = size_t(nc1) * nch;
-    const int e = k1 < 0 ? k1 + nc1 : k1;
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      if (low)
-        out[f] = cscale(coarse[(size_t(z) * NF + f) * sfc + size_t(e) * nch + k2], T(inv_nc));
-      else
-        out[f] = cscale(in[f], T(inv_n));
+  int tr;
+  __device__ cplx<T> out(int g, int k1, int k2, int z, const cplx<T>* in) const {
+    if (4 * abs(k1) < n1 && 4 * k2 < n2) {
+      const int e = k1 < 0 ? k1 + nc1 : k1;
+      return cscale(coarse[coarse_at(tr, z, NF, g, e, k2, nc1, nc2)], T(inv_nc));
     }
+    return cscale(in[g], T(inv_n));
   }
+  __device__ void operator()(int k1, int k2, int, int z, const cplx<T>* in, cplx<T>* out_) const {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) out_[f] = out(f, k1, k2, z, in);
+  }
+  __device__ void pre(int, int, int, const cplx<T>*) const {}
 };
 
 // ---------------------------------------------------------------------------------------
@@ -637,6 +1001,102 @@ hipError_t launch_col(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* Sin, c
 }
 
 
+// ---- wave-level launchers ----------------------------------------------------------------
+bool fast_len(int n) {
+  switch (n) {
+    case 64: case 96: case 128: case 192: case 256: case 384: case 512: case 768: case 1024:
+      return true;
+  }
+  return false;
+}
+
+// the wave-level passes serve a grid when both lengths are common ones (the row passes take
+// rows in groups of at most 16, and every such n1 is a multiple of 16)
+template <typename T>
+bool fast_grid(const SpecGrid<T>& g) {
+  return fast_len(g.n1) && fast_len(g.n2) && g.row.roots && g.col.roots;
+}
+
+#define SLNK_FAST_CASES(X) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+
+template <typename T, int N>
+hipError_t launch_frow_fwd_n(hipStream_t s, const SpecGrid<T>& g, RealFields<T> in, int batch, cplx<T>* S) {
+  using RW = FRow<T, N>;
+  static std::atomic<size_t> allowed{0};
+  RET_IF(allow_lds(k_frow_fwd<T, N>, RW::kLds, allowed));
+  dim3 grid(g.n1 / RW::R, (in.count + 1) / 2, batch);
+  hipLaunchKernelGGL((k_frow_fwd<T, N>), grid, dim3(RW::kThreads), RW::kLds, s, in, S, g.n1,
+                     static_cast<const cplx<T>*>(g.row.roots));
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t launch_frow_inv_n(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* S, int nspec, OutFields<T> out,
+                             int batch) {
+  using RW = FRow<T, N>;
+  static std::atomic<size_t> allowed{0};
+  RET_IF(allow_lds(k_frow_inv<T, N>, RW::kLds, allowed));
+  dim3 grid(g.n1 / RW::R, (out.count + 1) / 2, batch);
+  hipLaunchKernelGGL((k_frow_inv<T, N>), grid, dim3(RW::kThreads), RW::kLds, s, S, nspec, out, g.n1,
+                     static_cast<const cplx<T>*>(g.row.roots));
+  return hipGetLastError();
+}
+
+template <typename T, int N, class Op, int FL>
+hipError_t launch_fcol_n(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* Sin, cplx<T>* Sout, Op op, int batch,
+                         const int* active, int item_div) {
+  using CW = FCol<T, N>;
+  static std::atomic<size_t> allowed{0};
+  RET_IF(allow_lds(k_fcol<T, N, Op, FL>, CW::kLds, allowed));
+  const int nh = g.nh();
+  dim3 grid((nh + CW::KR - 1) / CW::KR, 1, batch);
+  hipLaunchKernelGGL((k_fcol<T, N, Op, FL>), grid, dim3(CW::kThreads), CW::kLds, s, Sin, Sout, nh, op,
+                     static_cast<const cplx<T>*>(g.col.roots), active, item_div);
+  return hipGetLastError();
+}
+
+// Pass dispatch: wave-level passes (transposed spectra) when 'fast', else the generic ones.
+template <typename T>
+hipError_t row_fwd(bool fast, hipStream_t s, const SpecGrid<T>& g, RealFields<T> in, int batch, cplx<T>* S) {
+  if (!fast) return launch_row_fwd<T>(s, g, in, batch, S);
+  switch (g.n2) {
+#define X(N) \
+  case N:    \
+    return launch_frow_fwd_n<T, N>(s, g, in, batch, S);
+    SLNK_FAST_CASES(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t row_inv(bool fast, hipStream_t s, const SpecGrid<T>& g, const cplx<T>* S, int nspec, OutFields<T> out,
+                   int batch) {
+  if (!fast) return launch_row_inv<T>(s, g, S, nspec, out, batch);
+  switch (g.n2) {
+#define X(N) \
+  case N:    \
+    return launch_frow_inv_n<T, N>(s, g, S, nspec, out, batch);
+    SLNK_FAST_CASES(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int FL, typename T, class Op>
+hipError_t col(bool fast, hipStream_t s, const SpecGrid<T>& g, const cplx<T>* Sin, cplx<T>* Sout, Op op, int batch,
+               const int* active = nullptr, int item_div = 1) {
+  if (!fast) return launch_col<T>(s, g, Sin, Sout, op, FL, batch, active, item_div);
+  switch (g.n1) {
+#define X(N) \
+  case N:    \
+    return launch_fcol_n<T, N, Op, FL>(s, g, Sin, Sout, op, batch, active, item_div);
+    SLNK_FAST_CASES(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
 // fields f < nf of a per-item block of nf consecutive fields
 template <typename T, class FL>
 void set_fields(FL& fl, int nf, T* base, size_t F, const int* active) {
@@ -665,52 +1125,55 @@ template <typename T>
 hipError_t spec_scale(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, SymbolParams sym, int nf,
                       const T* in, T* out, const T* add, cplx<T>* S1, cplx<T>* S2) {
   const size_t F = g.field();
+  const bool fast = fast_grid(g);
   RealFields<T> rin{};
   set_fields(rin, nf, const_cast<T*>(in), F, active);
   OutFields<T> rout{};
   set_fields(rout, nf, out, F, active);
   for (int f = 0; f < nf; ++f) rout.add[f] = add ? add + f * F : nullptr;
-  RET_IF(launch_row_fwd<T>(s, g, rin, batch, S1));
+  RET_IF(row_fwd<T>(fast, s, g, rin, batch, S1));
   const double inv_n = 1.0 / double(F);
   if (nf == 1) {
     OpScale<T, 1> op{sym, g.n1, g.n2, inv_n};
-    RET_IF(launch_col<T>(s, g, S1, S2, op, 0, batch, active));
+    RET_IF(col<0>(fast, s, g, S1, S2, op, batch, active));
   } else {
     OpScale<T, 2> op{sym, g.n1, g.n2, inv_n};
-    RET_IF(launch_col<T>(s, g, S1, S2, op, 0, batch, active));
+    RET_IF(col<0>(fast, s, g, S1, S2, op, batch, active));
   }
-  return launch_row_inv<T>(s, g, S2, nf, rout, batch);
+  return row_inv<T>(fast, s, g, S2, nf, rout, batch);
 }
 
 template <typename T>
 hipError_t spec_grad(hipStream_t s, const SpecGrid<T>& g, int count, const T* m, T* gm, cplx<T>* S1, cplx<T>* S2) {
   const size_t F = g.field();
+  const bool fast = fast_grid(g);
   RealFields<T> rin{};
   rin.count = 1;
   rin.p[0] = m;
   rin.bstride[0] = (long long)F;
   rin.item_div = 1;
-  RET_IF(launch_row_fwd<T>(s, g, rin, count, S1));
+  RET_IF(row_fwd<T>(fast, s, g, rin, count, S1));
   OpGrad<T> op{g.n1, g.n2, 1.0 / double(F)};
-  RET_IF(launch_col<T>(s, g, S1, S2, op, 0, count));
+  RET_IF(col<0>(fast, s, g, S1, S2, op, count));
   OutFields<T> rout{};
   rout.count = 2;
   rout.p[0] = gm;
   rout.p[1] = gm + F;
   rout.bstride[0] = rout.bstride[1] = (long long)(2 * F);
   rout.item_div = 1;
-  return launch_row_inv<T>(s, g, S2, 2, rout, count);
+  return row_inv<T>(fast, s, g, S2, 2, rout, count);
 }
 
 template <typename T>
 hipError_t spec_trace_prep(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, const T* v, T* cv,
                            T* divv, T* cdiv, cplx<T>* S1, cplx<T>* S2) {
   const size_t F = g.field();
+  const bool fast = fast_grid(g);
   RealFields<T> rin{};
   set_fields(rin, 2, const_cast<T*>(v), F, active);
-  RET_IF(launch_row_fwd<T>(s, g, rin, batch, S1));
+  RET_IF(row_fwd<T>(fast, s, g, rin, batch, S1));
   OpTracePrep<T> op{g.n1, g.n2, 1.0 / double(F)};
-  RET_IF(launch_col<T>(s, g, S1, S2, op, 0, batch, active));
+  RET_IF(col<0>(fast, s, g, S1, S2, op, batch, active));
   OutFields<T> rout{};
   rout.count = 4;
   rout.active = active;
@@ -721,18 +1184,19 @@ hipError_t spec_trace_prep(hipStream_t s, const SpecGrid<T>& g, int batch, const
   rout.p[3] = cdiv;
   rout.bstride[0] = rout.bstride[1] = (long long)(2 * F);
   rout.bstride[2] = rout.bstride[3] = (long long)F;
-  return launch_row_inv<T>(s, g, S2, 4, rout, batch);
+  return row_inv<T>(fast, s, g, S2, 4, rout, batch);
 }
 
 template <typename T>
 hipError_t spec_scale2(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, SymbolParams sym1,
                        SymbolParams sym2, const T* in, T* out1, T* out2, cplx<T>* S1, cplx<T>* S2) {
   const size_t F = g.field();
+  const bool fast = fast_grid(g);
   RealFields<T> rin{};
   set_fields(rin, 2, const_cast<T*>(in), F, active);
-  RET_IF(launch_row_fwd<T>(s, g, rin, batch, S1));
+  RET_IF(row_fwd<T>(fast, s, g, rin, batch, S1));
   OpScale2<T> op{sym1, sym2, g.n1, g.n2, 1.0 / double(F)};
-  RET_IF(launch_col<T>(s, g, S1, S2, op, 0, batch, active));
+  RET_IF(col<0>(fast, s, g, S1, S2, op, batch, active));
   OutFields<T> rout{};
   rout.count = 4;
   rout.active = active;
@@ -742,30 +1206,33 @@ hipError_t spec_scale2(hipStream_t s, const SpecGrid<T>& g, int batch, const int
   rout.p[2] = out2;
   rout.p[3] = out2 + F;
   rout.bstride[0] = rout.bstride[1] = rout.bstride[2] = rout.bstride[3] = (long long)(2 * F);
-  return launch_row_inv<T>(s, g, S2, 4, rout, batch);
+  return row_inv<T>(fast, s, g, S2, 4, rout, batch);
 }
 
+// The fine and the coarse passes of a restriction or prolongation share the coarse k-space buffer
+// (and the kept fine spectrum), so both grids take the same kind of pass.
 template <typename T>
 hipError_t spec_restrict(hipStream_t s, const SpecGrid<T>& g, const SpecGrid<T>& gc, int batch, const int* active,
                          int nf, const T* in, T* out_c, cplx<T>* keep_fine, cplx<T>* S1, cplx<T>* Sc1, cplx<T>* Sc2) {
   const size_t F = g.field(), Fc = gc.field();
+  const bool fast = fast_grid(g) && fast_grid(gc);
   RealFields<T> rin{};
   set_fields(rin, nf, const_cast<T*>(in), F, active);
-  RET_IF(launch_row_fwd<T>(s, g, rin, batch, S1));
+  RET_IF(row_fwd<T>(fast, s, g, rin, batch, S1));
   const double inv_n = 1.0 / double(F);
   // the fine column pass only writes the coarse k-space (and keeps the fine spectrum if asked)
   if (nf == 1) {
-    OpRestrict<T, 1> op{Sc1, g.n1, g.n2, gc.n1, gc.n2, inv_n};
-    RET_IF(launch_col<T>(s, g, S1, keep_fine ? keep_fine : S1, op, kOutK, batch, active));
-    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 1>{}, kInK, batch, active));
+    OpRestrict<T, 1> op{Sc1, g.n1, g.n2, gc.n1, gc.n2, inv_n, fast ? 1 : 0};
+    RET_IF(col<kOutK>(fast, s, g, S1, keep_fine ? keep_fine : S1, op, batch, active));
+    RET_IF(col<kInK>(fast, s, gc, Sc1, Sc2, OpCopy<T, 1>{}, batch, active));
   } else {
-    OpRestrict<T, 2> op{Sc1, g.n1, g.n2, gc.n1, gc.n2, inv_n};
-    RET_IF(launch_col<T>(s, g, S1, keep_fine ? keep_fine : S1, op, kOutK, batch, active));
-    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 2>{}, kInK, batch, active));
+    OpRestrict<T, 2> op{Sc1, g.n1, g.n2, gc.n1, gc.n2, inv_n, fast ? 1 : 0};
+    RET_IF(col<kOutK>(fast, s, g, S1, keep_fine ? keep_fine : S1, op, batch, active));
+    RET_IF(col<kInK>(fast, s, gc, Sc1, Sc2, OpCopy<T, 2>{}, batch, active));
   }
   OutFields<T> rout{};
   set_fields(rout, nf, out_c, Fc, active);
-  return launch_row_inv<T>(s, gc, Sc2, nf, rout, batch);
+  return row_inv<T>(fast, s, gc, Sc2, nf, rout, batch);
 }
 
 template <typename T>
@@ -773,21 +1240,22 @@ hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecG
                                 const int* active, int nf, const cplx<T>* fine_k, const T* zc, T* out, cplx<T>* S1,
                                 cplx<T>* Sc1, cplx<T>* Sc2) {
   const size_t F = g.field(), Fc = gc.field();
+  const bool fast = fast_grid(g) && fast_grid(gc);
   RealFields<T> rin{};
   set_fields(rin, nf, const_cast<T*>(zc), Fc, active);
-  RET_IF(launch_row_fwd<T>(s, gc, rin, batch, Sc1));
+  RET_IF(row_fwd<T>(fast, s, gc, rin, batch, Sc1));
   if (nf == 1) {
-    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 1>{}, kOutK, batch, active));
-    OpProlongCombine<T, 1> op{Sc2, g.n1, g.n2, gc.n1, gc.n2, 1.0 / double(F), 1.0 / double(Fc)};
-    RET_IF(launch_col<T>(s, g, fine_k, S1, op, kInK, batch, active));
+    RET_IF(col<kOutK>(fast, s, gc, Sc1, Sc2, OpCopy<T, 1>{}, batch, active));
+    OpProlongCombine<T, 1> op{Sc2, g.n1, g.n2, gc.n1, gc.n2, 1.0 / double(F), 1.0 / double(Fc), fast ? 1 : 0};
+    RET_IF(col<kInK>(fast, s, g, fine_k, S1, op, batch, active));
   } else {
-    RET_IF(launch_col<T>(s, gc, Sc1, Sc2, OpCopy<T, 2>{}, kOutK, batch, active));
-    OpProlongCombine<T, 2> op{Sc2, g.n1, g.n2, gc.n1, gc.n2, 1.0 / double(F), 1.0 / double(Fc)};
-    RET_IF(launch_col<T>(s, g, fine_k, S1, op, kInK, batch, active));
+    RET_IF(col<kOutK>(fast, s, gc, Sc1, Sc2, OpCopy<T, 2>{}, batch, active));
+    OpProlongCombine<T, 2> op{Sc2, g.n1, g.n2, gc.n1, gc.n2, 1.0 / double(F), 1.0 / double(Fc), fast ? 1 : 0};
+    RET_IF(col<kInK>(fast, s, g, fine_k, S1, op, batch, active));
   }
   OutFields<T> rout{};
   set_fields(rout, nf, out, F, active);
-  return launch_row_inv<T>(s, g, S1, nf, rout, batch);
+  return row_inv<T>(fast, s, g, S1, nf, rout, batch);
 }
 
 #define INST(T)                                                                                                 \
@@ -804,8 +1272,7 @@ hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecG
   template hipError_t spec_prolong_combine<T>(hipStream_t, const SpecGrid<T>&, const SpecGrid<T>&, int,         \
                                               const int*, int, const cplx<T>*, const T*, T*, cplx<T>*, cplx<T>*, \
                                               cplx<T>*);
-INST(float)
-INST(double)
+INST(SLNK_SPECTRAL_REAL)
 #undef INST
 
 }  // namespace slnk

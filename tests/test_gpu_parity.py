@@ -476,3 +476,55 @@ def test_wide_batch_matches_single_contexts(slnk):
     lin = O.linearize(probs[7][0], vs[7])
     _check_reg_op(probs[7][0], prec, _np(hb[7]), O.hessian_matvec(lin, vts[7]), vts[7], TOL[prec]["matvec"])
     cb.close()
+
+
+WAVE_SHAPES = [
+    # n1, n2, prec: every common transform length (64 .. 1024, 96 .. 768) as a row or column
+    # length of the fine or the coarse grid; (96, 192) has a coarse length (48) outside that set
+    (96, 192, "fp64"),
+    (96, 192, "mixed"),
+    (192, 384, "fp64"),
+    (192, 384, "mixed"),
+    (512, 256, "mixed"),
+    (768, 128, "mixed"),
+    (128, 1024, "mixed"),
+]
+
+
+@pytest.mark.parametrize("shape", WAVE_SHAPES, ids=lambda s: f"{s[0]}x{s[1]}_{s[2]}")
+def test_spectral_passes_all_lengths(slnk, shape):
+    """Gradient, GN matvec, split operator, P_REG and the two-level preconditioner on grids whose
+    lengths take the wave-level spectral passes (and, for a pair of grids, restriction and
+    prolongation between them) against the oracle."""
+    n1, n2, prec = shape
+    print(f"shape {shape}", flush=True)
+    L, vgen, vt = problem("gauss", n1, n2, nt=4, beta=1e-3, reg=2, seed=60)
+    L.mT, L.mR, vgen, vt = same_inputs(prec, L.mT, L.mR, vgen, vt)
+    tol = TOL[prec]
+    v = same_inputs(prec, 0.5 * vgen)
+    lin = O.linearize(L, v)
+    ctx = _ctx(slnk, L, prec, pc="reg")
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    g = torch.empty((2, n1, n2), dtype=ctx.dtype, device="cuda")
+    ctx.gradient(_t(v, prec), g)
+    _check_reg_op(L, "fp64", _np(g), O.gradient(lin), v, tol["gradient"])
+    h = torch.empty_like(g)
+    ctx.hessian_matvec(_t(vt, prec), h)
+    _check_reg_op(L, prec, _np(h), O.hessian_matvec(lin, vt), vt, tol["matvec"])
+    ctx.split_matvec(_t(vt, prec), h)
+    assert rel(_np(h), O.split_matvec(lin, vt)) < tol["matvec"]
+    ctx.precond_apply(_t(vt, prec), h)
+    assert rel(_np(h), O.prec_reg(L.grid, vt, L.prm.beta, L.prm.reg)) < tol["matvec"]
+    ctx.close()
+    ctx = _ctx(slnk, L, prec, pc="2l")
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    tl = O.setup_two_level(L)
+    emin, emax = ctx.cheb_bounds()
+    assert abs(emax - tl.emax) / tl.emax < (1e-9 if prec == "fp64" else 1e-5)
+    ctx.gradient(_t(v, prec), g)
+    cg = tl.coarse.grid
+    tl.lin_c = O.linearize(tl.coarse, np.stack([O.restrict(L.grid, cg, v[c]) for c in range(2)]))
+    z = torch.empty_like(g)
+    ctx.precond_apply(_t(vt, prec), z)
+    assert rel(_np(z), O.apply_two_level(L, tl, vt)) < (1e-11 if prec == "fp64" else 1e-4)
+    ctx.close()
