@@ -13,7 +13,7 @@
 namespace slnk {
 
 template <typename R>
-struct cplx {
+struct alignas(2 * sizeof(R)) cplx {
   R x, y;
 };
 

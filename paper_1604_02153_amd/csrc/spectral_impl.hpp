@@ -450,25 +450,67 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Stage s of the radix list in order REV: radix, product p of the earlier radices, and the offset
+// of its twiddles w_(r p)^(j k) at tw[off + (j - 1) p + k] (j = 1..r-1, k < p; N - 1 in all), so
+// that consecutive butterflies read consecutive entries.
+template <int N, bool REV>
+struct WStages {
+  static constexpr int NS = WPlan<N>::NS;
+  static constexpr int radix(int s) { return WPlan<N>::radix(REV ? NS - 1 - s : s); }
+  static constexpr int pprod(int s) {
+    int p = 1;
+    for (int t = 0; t < s; ++t) p *= radix(t);
+    return p;
+  }
+  static constexpr int off(int s) {
+    int o = 0;
+    for (int t = 0; t < s; ++t) o += (radix(t) - 1) * pprod(t);
+    return o;
+  }
+};
+
+// Fill the stage twiddle table of order REV (N - 1 entries) from the roots exp(-2 pi i m / N).
+template <typename T, int N, bool REV>
+__device__ void fill_twiddles(cplx<T>* tw, const cplx<T>* __restrict__ roots, int tid, int nthr) {
+  using WS = WStages<N, REV>;
+  for (int idx = tid; idx < N - 1; idx += nthr) {
+    int p = 1, r = WS::radix(0), base = 0;
+#pragma unroll
+    for (int t = 1; t < WS::NS; ++t)
+      if (idx >= WS::off(t)) {
+        p = WS::pprod(t);
+        r = WS::radix(t);
+        base = WS::off(t);
+      }
+    const int rel = idx - base;
+    const int j = rel / p + 1, k = rel - (j - 1) * p;
+    tw[idx] = roots[j * k * (N / (r * p))];
+  }
+}
+
 // Transform of length N (SIGN -1 forward, +1 inverse, unnormalised) of the elements x held by lane
 // lp of a transform in the first stage's mapping; returns the outputs in the last stage's mapping.
-// reg: the transform's LDS region (N elements at WPlan::pos); roots: exp(-2 pi i m / N), m < N.
-template <typename T, int N, int SIGN, bool REV, int S = 0, int P = 1>
-__device__ __forceinline__ void wave_fft(cplx<T> (&x)[WPlan<N>::E], cplx<T>* reg, const cplx<T>* roots, int lp) {
+// reg: the transform's LDS region (N elements at WPlan::pos); tw: the stage twiddles of order REV.
+// LAUNDER recomputes the LDS and twiddle addresses of every stage (they depend on lp alone)
+// instead of keeping them live across all transforms of a kernel.
+template <typename T, int N, int SIGN, bool REV, bool LAUNDER, int S = 0, int P = 1>
+__device__ __forceinline__ void wave_fft(cplx<T> (&x)[WPlan<N>::E], cplx<T>* reg, const cplx<T>* tw, int lp) {
   using PL = WPlan<N>;
+  using WS = WStages<N, REV>;
   constexpr int NS = PL::NS;
   static_assert(PL::product() == N, "radix list must multiply to N");
   static_assert(PL::E % PL::radix(S < NS ? (REV ? NS - 1 - S : S) : 0) == 0, "radix must divide E");
   if constexpr (S < NS) {
-    constexpr int r = PL::radix(REV ? NS - 1 - S : S);
-    constexpr int step = N / (r * P);  // w_(rP)^(jk) = roots[j k N / (r P)]
+    constexpr int r = WS::radix(S);
+    static_assert(WS::pprod(S) == P, "stage product");
+    if constexpr (LAUNDER) asm volatile("" : "+v"(lp));
 #pragma unroll
     for (int q = 0; q < PL::E / r; ++q) {
       if constexpr (P > 1) {
         const int k = (lp + PL::LPT * q) % P;
 #pragma unroll
         for (int j = 1; j < r; ++j) {
-          cplx<T> w = roots[j * k * step];
+          cplx<T> w = tw[WS::off(S) + (j - 1) * P + k];
           if (SIGN > 0) w.y = -w.y;
           x[q * r + j] = cmul(x[q * r + j], w);
         }
@@ -491,7 +533,7 @@ __device__ __forceinline__ void wave_fft(cplx<T> (&x)[WPlan<N>::E], cplx<T>* reg
         for (int j = 0; j < rn; ++j) x[q * rn + j] = reg[PL::pos(lp + PL::LPT * q + j * (N / rn))];
       wave_sync();
     }
-    wave_fft<T, N, SIGN, REV, S + 1, P * r>(x, reg, roots, lp);
+    wave_fft<T, N, SIGN, REV, LAUNDER, S + 1, P * r>(x, reg, tw, lp);
   }
 }
 
@@ -543,10 +585,10 @@ __global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_fwd(RealFields<
     const int e = wmap<N, r1>(lp, m);
     x[m] = {A[gb + e], B ? B[gb + e] : T(0)};
   }
-  for (int i = tid; i < N; i += RW::kThreads) rt[i] = roots[i];
+  fill_twiddles<T, N, false>(rt, roots, tid, RW::kThreads);
   __syncthreads();
   cplx<T>* reg = zb + row * RW::S;
-  wave_fft<T, N, -1, false>(x, reg, rt, lp);
+  wave_fft<T, N, -1, false, false>(x, reg, rt, lp);
 #pragma unroll
   for (int m = 0; m < PL::E; ++m) reg[PL::pos(wmap<N, rL>(lp, m))] = x[m];
   __syncthreads();
@@ -585,7 +627,7 @@ __global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_inv(const cplx<
   const size_t sf = size_t(nh) * n1;
   const cplx<T>* SA = S + (size_t(z) * nspec + fa) * sf + r0;
   const cplx<T>* SB = S + (size_t(z) * nspec + fb) * sf + r0;
-  for (int i = tid; i < N; i += RW::kThreads) rt[i] = roots[i];
+  fill_twiddles<T, N, false>(rt, roots, tid, RW::kThreads);
   for (int idx = tid; idx < nh * R; idx += RW::kThreads) {
     const int k = idx / R, rr = idx % R;
     const size_t o = size_t(k) * n1 + rr;
@@ -607,7 +649,7 @@ __global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_inv(const cplx<
 #pragma unroll
   for (int m = 0; m < PL::E; ++m) x[m] = reg[PL::pos(wmap<N, r1>(lp, m))];
   wave_sync();
-  wave_fft<T, N, +1, false>(x, reg, rt, lp);
+  wave_fft<T, N, +1, false, false>(x, reg, rt, lp);
   const size_t gb = size_t(r0 + row) * N;
   T* OA = out.p[fa] + z * out.bstride[fa] + gb;
   T* OB = hasb ? out.p[fb] + z * out.bstride[fb] + gb : nullptr;
@@ -627,7 +669,7 @@ struct FCol {
   static constexpr int KR = W * WPlan<N>::T;  // rows k2 per workgroup
   static constexpr int S = WPlan<N>::col_stride;
   static constexpr int kThreads = 64 * W;
-  static constexpr size_t kLds = (size_t(N) + size_t(KR) * S) * sizeof(cplx<T>);
+  static constexpr size_t kLds = (2 * size_t(N) + size_t(KR) * S) * sizeof(cplx<T>);
 };
 
 // Column pass over rows k2 of the transposed spectra of item z: forward transform along x1 (unless
@@ -643,8 +685,9 @@ __global__ void __launch_bounds__(256) k_fcol(const cplx<T>* __restrict__ Sin, c
   constexpr int NIN = Op::NIN, NOUT = Op::NOUT;
   constexpr int r1 = PL::radix(0), rL = PL::radix(PL::NS - 1);
   extern __shared__ unsigned char smem_raw[];
-  cplx<T>* rt = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* xb = rt + N;
+  cplx<T>* rt = reinterpret_cast<cplx<T>*>(smem_raw);   // forward-order twiddles
+  cplx<T>* rtr = rt + N;                                  // reversed-order twiddles
+  cplx<T>* xb = rt + 2 * N;
   const int z = blockIdx.z;
   if (active && !active[z / item_div]) return;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -655,7 +698,8 @@ __global__ void __launch_bounds__(256) k_fcol(const cplx<T>* __restrict__ Sin, c
   const int k2c = valid ? k2 : nh - 1;
   const size_t sf = size_t(nh) * N;
   cplx<T>* reg = xb + slot * CW::S;
-  for (int i = tid; i < N; i += CW::kThreads) rt[i] = roots[i];
+  if constexpr (!(FL & kInK)) fill_twiddles<T, N, false>(rt, roots, tid, CW::kThreads);
+  if constexpr (!(FL & kOutK)) fill_twiddles<T, N, true>(rtr, roots, tid, CW::kThreads);
   cplx<T> vin[NIN][PL::E];
 #pragma unroll
   for (int f = 0; f < NIN; ++f) {
@@ -663,10 +707,22 @@ __global__ void __launch_bounds__(256) k_fcol(const cplx<T>* __restrict__ Sin, c
 #pragma unroll
     for (int m = 0; m < PL::E; ++m) vin[f][m] = src[(FL & kInK) ? wmap<N, rL>(lp, m) : wmap<N, r1>(lp, m)];
   }
+  // per-wavenumber coefficients of the operator (symbols), formed once for all outputs while
+  // the loads are in flight
+  constexpr int NC = Op::NC > 0 ? Op::NC : 1;
+  T cf[PL::E][NC];
+  if constexpr (Op::NC > 0) {
+#pragma unroll
+    for (int m = 0; m < PL::E; ++m) {
+      op.coef(signed_wavenumber(wmap<N, rL>(lp, m), N), k2c, cf[m]);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) asm volatile("" : "+v"(cf[m][c]));
+    }
+  }
   __syncthreads();
   if constexpr (!(FL & kInK)) {
 #pragma unroll
-    for (int f = 0; f < NIN; ++f) wave_fft<T, N, -1, false>(vin[f], reg, rt, lp);
+    for (int f = 0; f < NIN; ++f) wave_fft<T, N, -1, false, true>(vin[f], reg, rt, lp);
   }
   if constexpr (Op::kPre) {
     if (valid) {
@@ -682,16 +738,18 @@ __global__ void __launch_bounds__(256) k_fcol(const cplx<T>* __restrict__ Sin, c
 #pragma unroll
   for (int g = 0; g < NOUT; ++g) {
     cplx<T> y[PL::E];
+    int lpg = lp;
+    asm volatile("" : "+v"(lpg));
 #pragma unroll
     for (int m = 0; m < PL::E; ++m) {
       cplx<T> v[NIN];
 #pragma unroll
       for (int f = 0; f < NIN; ++f) v[f] = vin[f][m];
-      y[m] = op.out(g, signed_wavenumber(wmap<N, rL>(lp, m), N), k2c, z, v);
+      y[m] = op.out(g, signed_wavenumber(wmap<N, rL>(lpg, m), N), k2c, z, v, cf[m]);
     }
     cplx<T>* dst = Sout + (size_t(z) * NOUT + g) * sf + size_t(k2c) * N;
     if constexpr (!(FL & kOutK)) {
-      wave_fft<T, N, +1, true>(y, reg, rt, lp);
+      wave_fft<T, N, +1, true, true>(y, reg, rtr, lp);
       if (valid) {
 #pragma unroll
         for (int m = 0; m < PL::E; ++m) dst[wmap<N, r1>(lp, m)] = y[m];
@@ -752,31 +810,33 @@ __device__ __forceinline__ T symbol_value(const SymbolParams& sp, int k1, int n1
 }
 
 // Every operator gives all outputs at one wavenumber (operator(), generic column pass) and output g
-// alone (out(), wave-level column pass); pre() is a side effect at each wavenumber, run once.
+// alone (out(), wave-level column pass) from NC real coefficients per wavenumber that coef()
+// forms once for all outputs; pre() is a side effect at each wavenumber, run once.
 template <typename T, int NF>
 struct OpScale {
-  static constexpr int NIN = NF, NOUT = NF;
+  static constexpr int NIN = NF, NOUT = NF, NC = 1;
   static constexpr bool kPre = false;
   SymbolParams sp;
   int n1, n2;
   double inv_n;
-  __device__ T coef(int k1, int k2) const {
+  __device__ void coef(int k1, int k2, T* c) const {
     const int k2s = (2 * k2 == n2) ? -k2 : k2;
-    return symbol_value<T>(sp, k1, n1, k2s, n2) * T(inv_n);
+    c[0] = symbol_value<T>(sp, k1, n1, k2s, n2) * T(inv_n);
   }
   __device__ void operator()(int k1, int k2, int, int, const cplx<T>* in, cplx<T>* out) const {
-    const T s = coef(k1, k2);
+    T s;
+    coef(k1, k2, &s);
 #pragma unroll
     for (int f = 0; f < NF; ++f) out[f] = cscale(in[f], s);
   }
   __device__ void pre(int, int, int, const cplx<T>*) const {}
-  __device__ cplx<T> out(int g, int k1, int k2, int, const cplx<T>* in) const { return cscale(in[g], coef(k1, k2)); }
+  __device__ cplx<T> out(int g, int, int, int, const cplx<T>* in, const T* c) const { return cscale(in[g], c[0]); }
 };
 
 // two symbols of the same two input fields: out[0..2) = sym1 in, out[2..4) = sym2 in
 template <typename T>
 struct OpScale2 {
-  static constexpr int NIN = 2, NOUT = 4;
+  static constexpr int NIN = 2, NOUT = 4, NC = 2;
   static constexpr bool kPre = false;
   SymbolParams sp1, sp2;
   int n1, n2;
@@ -790,17 +850,20 @@ struct OpScale2 {
     out[2] = cscale(in[0], b);
     out[3] = cscale(in[1], b);
   }
-  __device__ void pre(int, int, int, const cplx<T>*) const {}
-  __device__ cplx<T> out(int g, int k1, int k2, int, const cplx<T>* in) const {
+  __device__ void coef(int k1, int k2, T* c) const {
     const int k2s = (2 * k2 == n2) ? -k2 : k2;
-    const T s = symbol_value<T>(g < 2 ? sp1 : sp2, k1, n1, k2s, n2) * T(inv_n);
-    return cscale(in[g & 1], s);
+    c[0] = symbol_value<T>(sp1, k1, n1, k2s, n2) * T(inv_n);
+    c[1] = symbol_value<T>(sp2, k1, n1, k2s, n2) * T(inv_n);
+  }
+  __device__ void pre(int, int, int, const cplx<T>*) const {}
+  __device__ cplx<T> out(int g, int, int, int, const cplx<T>* in, const T* c) const {
+    return cscale(in[g & 1], c[g >> 1]);
   }
 };
 
 template <typename T>
 struct OpGrad {
-  static constexpr int NIN = 1, NOUT = 2;
+  static constexpr int NIN = 1, NOUT = 2, NC = 0;
   static constexpr bool kPre = false;
   int n1, n2;
   double inv_n;
@@ -809,8 +872,9 @@ struct OpGrad {
     out[0] = cmul_i(cscale(in[0], odd_k<T>(k1, n1) * s));
     out[1] = cmul_i(cscale(in[0], (2 * k2 == n2 ? T(0) : T(k2)) * s));
   }
+  __device__ void coef(int, int, T*) const {}
   __device__ void pre(int, int, int, const cplx<T>*) const {}
-  __device__ cplx<T> out(int g, int k1, int k2, int, const cplx<T>* in) const {
+  __device__ cplx<T> out(int g, int k1, int k2, int, const cplx<T>* in, const T*) const {
     const T k = g == 0 ? odd_k<T>(k1, n1) : (2 * k2 == n2 ? T(0) : T(k2));
     return cmul_i(cscale(in[0], k * T(inv_n)));
   }
@@ -818,7 +882,7 @@ struct OpGrad {
 
 template <typename T>
 struct OpTracePrep {
-  static constexpr int NIN = 2, NOUT = 4;  // cv1, cv2, div v, c_div
+  static constexpr int NIN = 2, NOUT = 4, NC = 1;  // cv1, cv2, div v, c_div
   static constexpr bool kPre = false;
   int n1, n2;
   double inv_n;
@@ -833,28 +897,30 @@ struct OpTracePrep {
     out[2] = cscale(d, s);
     out[3] = cscale(d, ib);
   }
-  __device__ void pre(int, int, int, const cplx<T>*) const {}
-  __device__ cplx<T> out(int g, int k1, int k2, int, const cplx<T>* in) const {
+  __device__ void coef(int k1, int k2, T* c) const {
     const int k2s = (2 * k2 == n2) ? -k2 : k2;
-    const T s = T(inv_n);
-    const T f = g == 2 ? s : s / spline_symbol<T>(k1, n1, k2s, n2);
-    if (g < 2) return cscale(in[g], f);
+    c[0] = T(inv_n) / spline_symbol<T>(k1, n1, k2s, n2);
+  }
+  __device__ void pre(int, int, int, const cplx<T>*) const {}
+  __device__ cplx<T> out(int g, int k1, int k2, int, const cplx<T>* in, const T* c) const {
+    if (g < 2) return cscale(in[g], c[0]);
     const T o1 = odd_k<T>(k1, n1), o2 = (2 * k2 == n2) ? T(0) : T(k2);
-    return cscale(cmul_i(cadd(cscale(in[0], o1), cscale(in[1], o2))), f);
+    return cscale(cmul_i(cadd(cscale(in[0], o1), cscale(in[1], o2))), g == 2 ? T(inv_n) : c[0]);
   }
 };
 
 // k-space identity (used for coarse forward transforms and coarse inverse transforms)
 template <typename T, int NF>
 struct OpCopy {
-  static constexpr int NIN = NF, NOUT = NF;
+  static constexpr int NIN = NF, NOUT = NF, NC = 0;
   static constexpr bool kPre = false;
   __device__ void operator()(int, int, int, int, const cplx<T>* in, cplx<T>* out) const {
 #pragma unroll
     for (int f = 0; f < NF; ++f) out[f] = in[f];
   }
+  __device__ void coef(int, int, T*) const {}
   __device__ void pre(int, int, int, const cplx<T>*) const {}
-  __device__ cplx<T> out(int g, int, int, int, const cplx<T>* in) const { return in[g]; }
+  __device__ cplx<T> out(int g, int, int, int, const cplx<T>* in, const T*) const { return in[g]; }
 };
 
 // Position of coarse mode (e, k2) of field f of item z in the coarse k-space buffer: rows of the
@@ -870,7 +936,7 @@ __device__ __forceinline__ size_t coarse_at(bool tr, int z, int NF, int f, int e
 // spectrum (output, k-space) when asked.
 template <typename T, int NF>
 struct OpRestrict {
-  static constexpr int NIN = NF, NOUT = NF;
+  static constexpr int NIN = NF, NOUT = NF, NC = 0;
   static constexpr bool kPre = true;
   cplx<T>* coarse;   // [z][NF] coarse k-space spectra (layout: coarse_at)
   int n1, n2, nc1, nc2;
@@ -895,20 +961,22 @@ struct OpRestrict {
 #pragma unroll
     for (int f = 0; f < NF; ++f) out[f] = in[f];
   }
-  __device__ cplx<T> out(int g, int, int, int, const cplx<T>* in) const { return in[g]; }
+  __device__ void coef(int, int, T*) const {}
+  __device__ cplx<T> out(int g, int, int, int, const cplx<T>* in, const T*) const { return in[g]; }
 };
 
 // Two-level combine (input: kept fine spectrum, k-space): high-pass part of it plus the
 // zero-padded coarse spectrum; 1/N_fine for the fine inverse, N_fine/N_coarse for the padding.
 template <typename T, int NF>
 struct OpProlongCombine {
-  static constexpr int NIN = NF, NOUT = NF;
+  static constexpr int NIN = NF, NOUT = NF, NC = 0;
   static constexpr bool kPre = false;
   const cplx<T>* coarse;   // [z][NF] coarse k-space spectra (forward transform, unnormalised)
   int n1, n2, nc1, nc2;
   double inv_n, inv_nc;
   int tr;
-  __device__ cplx<T> out(int g, int k1, int k2, int z, const cplx<T>* in) const {
+  __device__ void coef(int, int, T*) const {}
+  __device__ cplx<T> out(int g, int k1, int k2, int z, const cplx<T>* in, const T* = nullptr) const {
     if (4 * abs(k1) < n1 && 4 * k2 < n2) {
       const int e = k1 < 0 ? k1 + nc1 : k1;
       return cscale(coarse[coarse_at(tr, z, NF, g, e, k2, nc1, nc2)], T(inv_nc));
@@ -1272,7 +1340,9 @@ hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecG
   template hipError_t spec_prolong_combine<T>(hipStream_t, const SpecGrid<T>&, const SpecGrid<T>&, int,         \
                                               const int*, int, const cplx<T>*, const T*, T*, cplx<T>*, cplx<T>*, \
                                               cplx<T>*);
+#ifdef SLNK_SPECTRAL_REAL
 INST(SLNK_SPECTRAL_REAL)
+#endif
 #undef INST
 
 }  // namespace slnk
