@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned vs plain comparison")
     ap.add_argument("--learned-pairs", type=int, default=32, help="held-out pairs of the learned vs plain timing")
     ap.add_argument("--batched-matvecs", type=int, default=10, help="timed batched matvec calls (64 pairs each)")
+    ap.add_argument("--spectral", action="store_true",
+                    help="spectral-pass probe: 20 two-field spectral scalings at 1024^2 x16, 256^2 x64 and 128^2 "
+                         "x64 batches (for a kernel trace); no JSON line")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: 20 incremental-adjoint SL steps of the 256^2 problem, then a plain "
                          "64 MiB elementwise kernel (the reference of the traffic counters); no JSON line")
@@ -87,6 +90,28 @@ def probe():
         torch.mul(x, 2.0, out=y)  # reads and writes 64 MiB
     torch.cuda.synchronize()
     ctx.close()
+
+
+def spectral_probe():
+    """Launch sequence of the spectral-pass kernel trace: spec_scale (row pass, column pass with the
+    symbol, inverse row pass) on two fields per item, batched."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1604_02153_amd import Context
+    for n, B in [(1024, 16), (256, 64), (128, 64)]:
+        cs = [synth.batch_pair(p, n) for p in range(B)]
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(np.stack(a))).to(device="cuda", dtype=torch.float32)
+        mT, vg = t([c["mT"] for c in cs]), t([c["v_gen"] for c in cs])
+        ctx = Context(n, n, 4, reg="h2", beta=1e-3, prec="mixed", pc="reg", batch=B, sl_path=1)
+        mR = torch.empty_like(mT)
+        ctx.transport_state(vg, mT, mR)
+        ctx.set_images(mR, mT)
+        g = torch.empty_like(vg)
+        ctx.gradient(vg, g)
+        print(f"{n}^2 x{B}: spectral scaling {1e3 * ctx.time_kernel(5, 20):.1f} us per call", flush=True)
+        ctx.close()
 
 
 def measured_traffic():
@@ -301,6 +326,9 @@ def cpu_baseline(cfg, min_seconds):
 
 def main():
     args = parse()
+    if args.spectral:
+        spectral_probe()
+        return
     if args.probe:
         probe()
         return

@@ -393,8 +393,8 @@ __global__ void __launch_bounds__(1024) k_col(const cplx<T>* __restrict__ Sin, c
 
 // ---------------------------------------------------------------------------------------
 // Wave-level transforms of the common lengths: powers of two 64..1024 and 3 * 2^k, 96..768.
-// A transform belongs to LPT = N / E lanes of one wavefront (E = 16 elements per lane for powers
-// of two, 12 otherwise), so a wavefront holds 64 / LPT transforms.  A stage keeps the lane's
+// A transform belongs to LPT = N / E lanes of one wavefront (E = 8 elements per lane for powers
+// of two up to 512, 16 for 1024, 12 otherwise), so a wavefront holds 64 / LPT transforms.  A stage keeps the lane's
 // elements in registers; between stages the wavefront exchanges them through its own LDS region,
 // so the transforms need no workgroup barrier.  Stockham order: butterfly i (k = i mod p) of a
 // radix-r stage reads elements i + j N / r and writes (i - k) r + k + j p.  Lane lp of a
@@ -405,7 +405,7 @@ __global__ void __launch_bounds__(1024) k_col(const cplx<T>* __restrict__ Sin, c
 template <int N>
 struct WPlan {
   static constexpr bool kPow2 = (N & (N - 1)) == 0;
-  static constexpr int E = kPow2 ? 16 : 12;
+  static constexpr int E = kPow2 ? (N <= 512 ? 8 : 16) : 12;
   static constexpr int LPT = N / E;
   static constexpr int T = 64 / LPT;
   static constexpr int NS = N == 64 ? 2 : N == 128 || N == 256 || N == 512 ? 3 : N == 384 || N == 768 ? 5 : 4;
@@ -431,8 +431,8 @@ struct WPlan {
   // LDS strides (complex elements) of a transform's region: exchange only (column passes), and
   // exchange plus the transposed access of the row passes (chosen with a bank model of gfx950's
   // 64 banks)
-  static constexpr int col_stride = N + (N == 64 ? 4 : N == 128 || N == 96 ? 8 : N == 256 || N == 192 ? 16 : 0);
-  static constexpr int row_stride = N + (N == 96 ? 8 : N == 64 || N == 128 || N == 1024 || N == 768 ? 4 : 2);
+  static constexpr int col_stride = N + (N == 64 || N == 96 ? 8 : N == 128 || N == 192 ? 16 : 0);
+  static constexpr int row_stride = N + (N == 96 ? 8 : N == 64 || N == 1024 || N == 768 ? 4 : 2);
   // element e of a region: XOR swizzle of the low five bits (powers of two), identity otherwise
   __device__ static __forceinline__ int pos(int e) {
     if constexpr (kPow2)
