@@ -628,6 +628,8 @@ __global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_inv(const cplx<
   const cplx<T>* SA = S + (size_t(z) * nspec + fa) * sf + r0;
   const cplx<T>* SB = S + (size_t(z) * nspec + fb) * sf + r0;
   fill_twiddles<T, N, false>(rt, roots, tid, RW::kThreads);
+  // the loads of several iterations are issued before their LDS stores
+#pragma unroll 4
   for (int idx = tid; idx < nh * R; idx += RW::kThreads) {
     const int k = idx / R, rr = idx % R;
     const size_t o = size_t(k) * n1 + rr;

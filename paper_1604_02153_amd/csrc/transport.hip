@@ -183,6 +183,32 @@ __device__ __forceinline__ T load_src(const StepArgs<T>& a, size_t gi) {
   }
 }
 
+// Staging of a P x P footprint (P <= 16 CH) by a 16 x 16 block: every thread issues all of its
+// CH x CH loads (rows ty + 16 i, columns tx + 16 k, clamped into the footprint so that no load
+// needs a branch) before it stores any of them, so the loads overlap instead of each waiting
+// for the one before.
+template <typename T, int KIND, bool FIRST, int CH>
+__device__ __forceinline__ void stage_batched(const StepArgs<T>& a, T* A, int P, int ry, const int* colw) {
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  T v[CH][CH];
+#pragma unroll
+  for (int i = 0; i < CH; ++i) {
+    const int r = min(ty + kTile * i, P - 1);
+    const size_t rowoff = size_t(wrap_index(ry + r, a.n1)) * a.n2;
+#pragma unroll
+    for (int k = 0; k < CH; ++k) v[i][k] = load_src<T, KIND, FIRST>(a, rowoff + colw[k]);
+  }
+#pragma unroll
+  for (int i = 0; i < CH; ++i) {
+    const int r = ty + kTile * i;
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      const int c = tx + kTile * k;
+      if (r < P && c < P) A[r * P + c] = v[i][k];
+    }
+  }
+}
+
 // Stage the transported field over the rows [y0 - lo - K, y0 - lo + G + K) (and likewise the
 // columns) and filter it into the B-spline coefficients of the inner G x G region, which starts
 // at global node (y0 - lo, x0 - lo) and is left at LDS offset 0 of 'A'.  The step kernel uses
@@ -210,13 +236,19 @@ __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, i
     const int c = tx + kTile * k;
     colw[k] = c < P ? wrap_index(rx + c, n2) : 0;
   }
-  for (int r = ty; r < P; r += kTile) {
-    const size_t rowoff = size_t(wrap_index(ry + r, n1)) * n2;
-    T* dst = A + r * P;
+  if (P <= 4 * kTile) {
+    stage_batched<T, KIND, FIRST, 4>(a, A, P, ry, colw);
+  } else if (P <= 6 * kTile) {
+    stage_batched<T, KIND, FIRST, 6>(a, A, P, ry, colw);
+  } else {
+    for (int r = ty; r < P; r += kTile) {
+      const size_t rowoff = size_t(wrap_index(ry + r, n1)) * n2;
+      T* dst = A + r * P;
 #pragma unroll
-    for (int k = 0; k < kMaxChunks; ++k) {
-      const int c = tx + kTile * k;
-      if (c < P) dst[c] = load_src<T, KIND, FIRST>(a, rowoff + colw[k]);
+      for (int k = 0; k < kMaxChunks; ++k) {
+        const int c = tx + kTile * k;
+        if (c < P) dst[c] = load_src<T, KIND, FIRST>(a, rowoff + colw[k]);
+      }
     }
   }
   __syncthreads();
@@ -271,6 +303,8 @@ __global__ void __launch_bounds__(256) k_prefilter_rows(StepArgs<T> args, int rp
   const int n1 = a.n1, n2 = a.n2, W = n2 + 2 * K;
   const int r0 = blockIdx.x * rpb;
   const int nr = min(rpb, n1 - r0);
+  // loads of several iterations are issued before their stores (no loop-carried wait)
+#pragma unroll 8
   for (int idx = threadIdx.x; idx < nr * W; idx += blockDim.x) {
     const int r = idx / W, c = idx - r * W;
     L[idx] = load_src<T, KIND, FIRST>(a, size_t(r0 + r) * n2 + wrap_index(c - K, n2));
@@ -299,10 +333,12 @@ __global__ void __launch_bounds__(256) k_prefilter_cols(StepArgs<T> args) {
   __shared__ T L[(kColH + 2 * K) * kColW];
   const int n1 = a.n1, n2 = a.n2;
   const int x0 = blockIdx.x * kColW, y0 = blockIdx.y * kColH;
+#pragma unroll
   for (int idx = threadIdx.x; idx < (kColH + 2 * K) * kColW; idx += blockDim.x) {
     const int r = idx / kColW, c = idx - r * kColW;
-    const int col = x0 + c;
-    L[idx] = col < n2 ? a.coef2[size_t(wrap_index(y0 - K + r, n1)) * n2 + col] : T(0);
+    const int col = min(x0 + c, n2 - 1);
+    const T val = a.coef2[size_t(wrap_index(y0 - K + r, n1)) * n2 + col];
+    L[idx] = x0 + c < n2 ? val : T(0);
   }
   __syncthreads();
   const int c = threadIdx.x % kColW, q = threadIdx.x / kColW;
