@@ -30,13 +30,19 @@ __device__ __forceinline__ v8bf load8(const bf16* p) { return *reinterpret_cast<
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // ---- convolution (forward, and input gradient with transformed weights) ----------------------
-// Block: four wavefronts along pixels, each 16 MW pixels x 32 output channels (MW x 2 MFMA tiles).
-template <int MW>
+// Block: four wavefronts.  KS of them (1, 2 or 4) share one output tile of 16 MW pixels x 32
+// output channels (MW x 2 MFMA tiles) and split its K = 9 taps x cin/32 channel chunks between
+// them; their partial sums meet in LDS and are added in a fixed order.  Small grids (the deep
+// levels: few pixels, many channels) take KS > 1 so that enough wavefronts run.  The K loop is
+// flat over (tap, chunk) and unrolled, so the loads of several steps are in flight together.
+template <int MW, int KS>
 __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
+  constexpr int PG = 4 / KS;  // output tiles per block
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kpart = wave % KS, pg = wave / KS;
   const int r = lane & 15, g = lane >> 4;
   const int HW = a.H * a.W;
-  const int pbase = (blockIdx.x * 4 + wave) * (16 * MW);
+  const int pbase = (blockIdx.x * PG + pg) * (16 * MW);
   const int cobase = blockIdx.y * 32;
   int pb[MW], py[MW], px[MW];
 #pragma unroll
@@ -51,29 +57,59 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
 #pragma unroll
   for (int i = 0; i < MW; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int t = 0; t < 9; ++t) {
-    const int dy = t / 3 - 1, dx = t % 3 - 1;
-    const bf16* src[MW];
+  // this wavefront's K steps st = kpart + KS i (i < nmy), st = 9-tap index t times nk plus the
+  // 32-channel chunk kc; the loads run four steps ahead of the MFMAs (a ring of four register
+  // buffers); steps past the end load a valid step and multiply it by zero weights
+  const int nk = a.cin >> 5;
+  const int S = 9 * nk;
+  const int nmy = (S - kpart + KS - 1) / KS;
+  const float inv_nk = 1.0f / float(nk);
+  auto load_step = [&](int i, v8bf* av, v8bf* bv) {
+    const int st = kpart + KS * min(i, nmy - 1);
+    const int t = int((float(st) + 0.5f) * inv_nk);
+    const int kc = st - t * nk;
+    const int dy = t / 3 - 1, dx = t - 3 * (t / 3) - 1;
 #pragma unroll
-    for (int i = 0; i < MW; ++i) {
-      const int yy = wrap(py[i] + dy, a.H), xx = wrap(px[i] + dx, a.W);
-      src[i] = a.x + (size_t(pb[i]) * HW + size_t(yy) * a.W + xx) * a.xcs + a.xco + 8 * g;
+    for (int m = 0; m < MW; ++m) {
+      const int yy = wrap(py[m] + dy, a.H), xx = wrap(px[m] + dx, a.W);
+      av[m] = load8(a.x + (size_t(pb[m]) * HW + size_t(yy) * a.W + xx) * a.xcs + a.xco + 8 * g + 32 * kc);
     }
-    const bf16* wr[2];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) wr[j] = a.w + (size_t(t) * a.cout + cobase + 16 * j + r) * a.cin + 8 * g;
-#pragma unroll 2
-    for (int kc = 0; kc < a.cin; kc += 32) {
-      v8bf av[MW], bv[2];
+    for (int j = 0; j < 2; ++j)
+      bv[j] = load8(a.w + (size_t(t) * a.cout + cobase + 16 * j + r) * a.cin + 8 * g + 32 * kc);
+  };
+  v8bf ra[4][MW], rb[4][2];
 #pragma unroll
-      for (int i = 0; i < MW; ++i) av[i] = load8(src[i] + kc);
+  for (int q = 0; q < 4; ++q) load_step(q, ra[q], rb[q]);
+  const v8bf zero = {};
+  for (int i = 0; i < nmy; i += 4) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bv[j] = load8(wr[j] + kc);
+    for (int q = 0; q < 4; ++q) {
+      const bool live = i + q < nmy;
+#pragma unroll
+      for (int m = 0; m < MW; ++m)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra[q][m], live ? rb[q][j] : zero, acc[m][j], 0, 0, 0);
+      load_step(i + q + 4, ra[q], rb[q]);
+    }
+  }
+  if constexpr (KS > 1) {
+    __shared__ v4f red[4][MW * 2][64];
+    if (kpart > 0) {
 #pragma unroll
       for (int i = 0; i < MW; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) red[wave][2 * i + j][lane] = acc[i][j];
     }
+    __syncthreads();
+    if (kpart > 0) return;
+#pragma unroll
+    for (int q = 1; q < KS; ++q)
+#pragma unroll
+      for (int i = 0; i < MW; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] += red[wave + q][2 * i + j][lane];
   }
 #pragma unroll
   for (int i = 0; i < MW; ++i)
@@ -154,14 +190,35 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
   }
 }
 
-// bias gradient partials: partial[z][c] = sum over chunk z of dY[p][c]
+// bias gradient partials: partial[z][c] = sum over chunk z of dY[p][c].  Thread (pixel group pg,
+// channels 4 c4 .. 4 c4 + 3) sums every G-th pixel of the chunk (8-byte loads, several in
+// flight); the G group sums meet in LDS in a fixed order.  C is a multiple of 4 and at most 1024.
 __global__ void __launch_bounds__(256) k_bgrad(const bf16* dy, int dcs, int dco, int C, int P, int chunk,
                                                float* partial) {
+  __shared__ float red[256 * 4];
+  const int tpp = C / 4, G = 256 / tpp;
+  const int c4 = threadIdx.x % tpp, pg = threadIdx.x / tpp;
   const int p0 = blockIdx.x * chunk, p1 = min(P, p0 + chunk);
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  if (pg < G) {
+#pragma unroll 8
+    for (int p = p0 + pg; p < p1; p += G) {
+      const uint2 u = *reinterpret_cast<const uint2*>(dy + size_t(p) * dcs + dco + 4 * c4);
+      s0 += __uint_as_float(u.x << 16);
+      s1 += __uint_as_float(u.x & 0xFFFF0000u);
+      s2 += __uint_as_float(u.y << 16);
+      s3 += __uint_as_float(u.y & 0xFFFF0000u);
+    }
+    red[pg * C + 4 * c4 + 0] = s0;
+    red[pg * C + 4 * c4 + 1] = s1;
+    red[pg * C + 4 * c4 + 2] = s2;
+    red[pg * C + 4 * c4 + 3] = s3;
+  }
+  __syncthreads();
   for (int c = threadIdx.x; c < C; c += blockDim.x) {
-    float s = 0.f;
-    for (int p = p0; p < p1; ++p) s += bf2f(dy[size_t(p) * dcs + dco + c]);
-    partial[size_t(blockIdx.x) * C + c] = s;
+    float t = 0.f;
+    for (int q = 0; q < G; ++q) t += red[q * C + c];
+    partial[size_t(blockIdx.x) * C + c] = t;
   }
 }
 
@@ -169,6 +226,7 @@ __global__ void __launch_bounds__(256) k_bgrad(const bf16* dy, int dcs, int dco,
 __global__ void k_sum_splits(const float* partial, int splits, size_t n, float* out) {
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
     float s = 0.f;
+#pragma unroll 8
     for (int z = 0; z < splits; ++z) s += partial[size_t(z) * n + i];
     out[i] = s;
   }
@@ -316,18 +374,46 @@ __global__ void k_adam(float* w, bf16* wb, const float* g, float* m, float* v, s
 }
 
 // scalar head: per item b, f[b][c] = mean and f[b][C + c] = max over the HW pixels of x[b][p][c]
-// (C channels, FP32), s[b] = bias + sum_{c < 2C} f[b][c] w[c]; one block per item
-__global__ void __launch_bounds__(256) k_head(const bf16* x, int C, int HW, const float* w, const float* bias,
-                                              float* f, float* s) {
-  __shared__ float red[256];
+// (C channels, FP32), s[b] = bias + sum_{c < 2C} f[b][c] w[c]; one block of 1024 threads per
+// item.  Thread (pixel group pg, channels 4 c4 .. 4 c4 + 3) covers every G-th pixel with 8-byte
+// loads, several in flight; the group results meet in LDS in a fixed order.  C is a multiple of
+// 4 and at most 4096.
+__global__ void __launch_bounds__(1024) k_head(const bf16* x, int C, int HW, const float* w, const float* bias,
+                                               float* f, float* s) {
+  __shared__ float rs[4096], rm[4096];
+  __shared__ float red[1024];
   const int b = blockIdx.x;
+  const int tpp = C / 4, G = 1024 / tpp;
+  const int c4 = threadIdx.x % tpp, pg = threadIdx.x / tpp;
+  if (pg < G) {
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    float m0 = -3.0e38f, m1 = -3.0e38f, m2 = -3.0e38f, m3 = -3.0e38f;
+#pragma unroll 8
+    for (int p = pg; p < HW; p += G) {
+      const uint2 u = *reinterpret_cast<const uint2*>(x + (size_t(b) * HW + p) * C + 4 * c4);
+      const float v0 = __uint_as_float(u.x << 16), v1 = __uint_as_float(u.x & 0xFFFF0000u);
+      const float v2 = __uint_as_float(u.y << 16), v3 = __uint_as_float(u.y & 0xFFFF0000u);
+      a0 += v0;
+      a1 += v1;
+      a2 += v2;
+      a3 += v3;
+      m0 = fmaxf(m0, v0);
+      m1 = fmaxf(m1, v1);
+      m2 = fmaxf(m2, v2);
+      m3 = fmaxf(m3, v3);
+    }
+    float* ps = rs + pg * 4 * tpp + 4 * c4;
+    float* pm = rm + pg * 4 * tpp + 4 * c4;
+    ps[0] = a0, ps[1] = a1, ps[2] = a2, ps[3] = a3;
+    pm[0] = m0, pm[1] = m1, pm[2] = m2, pm[3] = m3;
+  }
+  __syncthreads();
   float part = 0.f;
   for (int c = threadIdx.x; c < C; c += blockDim.x) {
     float acc = 0.f, mx = -3.0e38f;
-    for (int p = 0; p < HW; ++p) {
-      const float xv = bf2f(x[(size_t(b) * HW + p) * C + c]);
-      acc += xv;
-      mx = fmaxf(mx, xv);
+    for (int q = 0; q < G; ++q) {
+      acc += rs[q * C + c];
+      mx = fmaxf(mx, rm[q * C + c]);
     }
     const float fc = acc / float(HW);
     f[size_t(b) * 2 * C + c] = fc;
@@ -336,7 +422,7 @@ __global__ void __launch_bounds__(256) k_head(const bf16* x, int C, int HW, cons
   }
   red[threadIdx.x] = part;
   __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
+  for (int k = 512; k > 0; k >>= 1) {
     if (int(threadIdx.x) < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
@@ -379,10 +465,26 @@ inline unsigned blocks_for(size_t n) {
 hipError_t conv(hipStream_t s, const ConvArgs& a) {
   const int HW = a.H * a.W;
   if (a.cin % 32 || a.cout % 32 || a.xcs % 8 || a.xco % 8 || HW % 64 || a.P % HW) return hipErrorInvalidValue;
-  if (HW % 128 == 0) {
-    hipLaunchKernelGGL(k_conv<2>, dim3(a.P / 128, a.cout / 32), dim3(256), 0, s, a);
+  // output tiles of 16 MW pixels x 32 channels; split K when they would not give about eight
+  // wavefronts per compute unit
+  const int mw = HW % 128 == 0 ? 2 : 1;
+  const long tiles = long(a.P / (16 * mw)) * (a.cout / 32);
+  const int ks = tiles >= 2048 ? 1 : tiles >= 1024 ? 2 : 4;
+  const dim3 grid(a.P / (16 * mw * (4 / ks)), a.cout / 32);
+  if (mw == 2) {
+    if (ks == 1)
+      hipLaunchKernelGGL((k_conv<2, 1>), grid, dim3(256), 0, s, a);
+    else if (ks == 2)
+      hipLaunchKernelGGL((k_conv<2, 2>), grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_conv<2, 4>), grid, dim3(256), 0, s, a);
   } else {
-    hipLaunchKernelGGL(k_conv<1>, dim3(a.P / 64, a.cout / 32), dim3(256), 0, s, a);
+    if (ks == 1)
+      hipLaunchKernelGGL((k_conv<1, 1>), grid, dim3(256), 0, s, a);
+    else if (ks == 2)
+      hipLaunchKernelGGL((k_conv<1, 2>), grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_conv<1, 4>), grid, dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }
@@ -398,6 +500,7 @@ hipError_t wgrad(hipStream_t s, const WgradArgs& a) {
 }
 
 hipError_t bgrad(hipStream_t s, const bf16* dy, int dcs, int dco, int C, int P, int chunk, float* partial) {
+  if (C % 4 || C > 1024 || dcs % 4 || dco % 4) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_bgrad, dim3((P + chunk - 1) / chunk), dim3(256), 0, s, dy, dcs, dco, C, P, chunk, partial);
   return hipGetLastError();
 }
@@ -471,7 +574,8 @@ hipError_t adam(hipStream_t s, float* w, bf16* wb, const float* g, float* m, flo
 
 hipError_t head(hipStream_t s, const bf16* x, int C, int HW, int B, const float* w, const float* bias, float* f,
                 float* out) {
-  hipLaunchKernelGGL(k_head, dim3(B), dim3(256), 0, s, x, C, HW, w, bias, f, out);
+  if (C % 4 || C > 4096) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_head, dim3(B), dim3(1024), 0, s, x, C, HW, w, bias, f, out);
   return hipGetLastError();
 }
 

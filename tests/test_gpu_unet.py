@@ -68,7 +68,10 @@ def test_forward_matches_reference(slnk, shape):
     err = rel(v.cpu().numpy(), v_ref)
     print(f"forward rel err {err:.2e}", flush=True)
     assert err < 1e-2
-    assert rel(head.cpu().numpy(), cache["head"]) < 1e-3
+    # the head reads the coarsest BF16 activations through per-channel maxima: one rounding flip
+    # of an activation (one BF16 unit, 2^-8 relative), which the GPU's FP32 accumulation order can
+    # cause where the reference's FP64 sums round the other way, moves a maximum by that much
+    assert rel(head.cpu().numpy(), cache["head"]) < 2.0 ** -8
     net.close()
 
 
