@@ -677,7 +677,8 @@ struct FCol {
 // Column pass over rows k2 of the transposed spectra of item z: forward transform along x1 (unless
 // kInK: the input is k-space in the last-stage mapping), op at every (k1, k2), inverse transform
 // (unless kOutK: the output stays k-space).  Each output is formed and transformed on its own, from
-// the inputs held in registers.
+// the inputs held in registers.  With gridDim.y = NOUT (small grids) workgroup row y forms output
+// y only, so that more wavefronts share the work (each repeats the forward transforms).
 template <typename T, int N, class Op, int FL>
 __global__ void __launch_bounds__(256) k_fcol(const cplx<T>* __restrict__ Sin, cplx<T>* __restrict__ Sout, int nh,
                                               Op op, const cplx<T>* __restrict__ roots, const int* active,
@@ -726,8 +727,9 @@ __global__ void __launch_bounds__(256) k_fcol(const cplx<T>* __restrict__ Sin, c
 #pragma unroll
     for (int f = 0; f < NIN; ++f) wave_fft<T, N, -1, false, true>(vin[f], reg, rt, lp);
   }
+  const bool all_out = gridDim.y == 1;
   if constexpr (Op::kPre) {
-    if (valid) {
+    if (valid && (all_out || blockIdx.y == 0)) {
 #pragma unroll
       for (int m = 0; m < PL::E; ++m) {
         cplx<T> v[NIN];
@@ -739,6 +741,7 @@ __global__ void __launch_bounds__(256) k_fcol(const cplx<T>* __restrict__ Sin, c
   }
 #pragma unroll
   for (int g = 0; g < NOUT; ++g) {
+    if (!all_out && g != int(blockIdx.y)) continue;
     cplx<T> y[PL::E];
     int lpg = lp;
     asm volatile("" : "+v"(lpg));
@@ -1119,7 +1122,10 @@ hipError_t launch_fcol_n(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* Sin
   static std::atomic<size_t> allowed{0};
   RET_IF(allow_lds(k_fcol<T, N, Op, FL>, CW::kLds, allowed));
   const int nh = g.nh();
-  dim3 grid((nh + CW::KR - 1) / CW::KR, 1, batch);
+  const int blocks = (nh + CW::KR - 1) / CW::KR;
+  // grids of fewer than a workgroup per compute unit split the outputs over grid rows
+  const int ysplit = (Op::NOUT > 1 && long(blocks) * batch < 256) ? Op::NOUT : 1;
+  dim3 grid(blocks, ysplit, batch);
   hipLaunchKernelGGL((k_fcol<T, N, Op, FL>), grid, dim3(CW::kThreads), CW::kLds, s, Sin, Sout, nh, op,
                      static_cast<const cplx<T>*>(g.col.roots), active, item_div);
   return hipGetLastError();

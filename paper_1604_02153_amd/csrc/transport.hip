@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(256) k_prefilter_cols(StepArgs<T> args) {
   const int n1 = a.n1, n2 = a.n2;
   const int x0 = blockIdx.x * kColW, y0 = blockIdx.y * kColH;
 #pragma unroll
-  for (int idx = threadIdx.x; idx < (kColH + 2 * K) * kColW; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < (kColH + 2 * K) * kColW; idx += 256) {  // 256 threads per block
     const int r = idx / kColW, c = idx - r * kColW;
     const int col = min(x0 + c, n2 - 1);
     const T val = a.coef2[size_t(wrap_index(y0 - K + r, n1)) * n2 + col];
