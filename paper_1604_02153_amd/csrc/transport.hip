@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <atomic>
 #include <mutex>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -292,7 +293,18 @@ __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, i
 // Coefficient pass of the two-kernel step (whole-field B-spline coefficients into a.coef, read
 // by the global-memory gather): the separable exponential filter runs along complete periodic
 // rows (into a.coef2), then along columns, so that no output is computed twice.
-// Rows: a block filters 'rpb' whole rows staged in LDS with K wrapped values on either side.
+// Rows: a block filters 'rpb' whole rows staged in LDS with K wrapped values on either side; a
+// thread forms kRowSeg consecutive outputs from a register window of kRowSeg + 2K staged values.
+// The staged rows carry one slack word after every kRowSeg values, so that the windows of
+// consecutive threads (kRowSeg + 1 words apart) fall on different LDS banks.
+constexpr int kRowSeg = 8;
+
+__host__ __device__ inline int row_stage_len(int n2, int K) { return (n2 + kRowSeg - 1) / kRowSeg * kRowSeg + 2 * K; }
+__host__ __device__ inline int row_stage_stride(int n2, int K) {
+  const int W = row_stage_len(n2, K);
+  return W + W / kRowSeg + 1;
+}
+
 template <typename T, int KIND, bool FIRST>
 __global__ void __launch_bounds__(256) k_prefilter_rows(StepArgs<T> args, int rpb) {
   if (args.active && !args.active[blockIdx.z]) return;
@@ -300,23 +312,57 @@ __global__ void __launch_bounds__(256) k_prefilter_rows(StepArgs<T> args, int rp
   constexpr int K = FilterTaps<T>::K;
   extern __shared__ unsigned char smem_raw[];
   T* L = reinterpret_cast<T*>(smem_raw);
-  const int n1 = a.n1, n2 = a.n2, W = n2 + 2 * K;
+  const int n1 = a.n1, n2 = a.n2;
+  const int W = row_stage_len(n2, K), Wp = row_stage_stride(n2, K);
+  const int nseg = (n2 + kRowSeg - 1) / kRowSeg;
   const int r0 = blockIdx.x * rpb;
   const int nr = min(rpb, n1 - r0);
   // loads of several iterations are issued before their stores (no loop-carried wait)
-#pragma unroll 8
-  for (int idx = threadIdx.x; idx < nr * W; idx += blockDim.x) {
-    const int r = idx / W, c = idx - r * W;
-    L[idx] = load_src<T, KIND, FIRST>(a, size_t(r0 + r) * n2 + wrap_index(c - K, n2));
+  for (int r = 0; r < nr; ++r) {
+    const size_t rowoff = size_t(r0 + r) * n2;
+    T* Lr = L + r * Wp;
+#pragma unroll 4
+    for (int c = threadIdx.x; c < W; c += 256) {
+      int col = c - K;
+      if (col < 0) col += n2;
+      if (col >= n2) col -= n2;
+      if (unsigned(col) >= unsigned(n2)) col = wrap_index(c - K, n2);  // rows shorter than K
+      Lr[c + c / kRowSeg] = load_src<T, KIND, FIRST>(a, rowoff + col);
+    }
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < nr * n2; idx += blockDim.x) {
-    const int r = idx / n2, c = idx - r * n2;
-    const T* x = L + r * W + c + K;
-    T acc = tap<T>(0) * x[0];
+  for (int task = threadIdx.x; task < nr * nseg; task += 256) {
+    const int r = task / nseg, q = task - r * nseg;
+    const T* xw = L + r * Wp + q * (kRowSeg + 1);
+    T x[kRowSeg + 2 * K];
 #pragma unroll
-    for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[-t] + x[t]);
-    a.coef2[size_t(r0 + r) * n2 + c] = acc;
+    for (int i = 0; i < kRowSeg + 2 * K; ++i) x[i] = xw[i + i / kRowSeg];
+    T* out = a.coef2 + size_t(r0 + r) * n2 + q * kRowSeg;
+    T y[kRowSeg];
+#pragma unroll
+    for (int j = 0; j < kRowSeg; ++j) {
+      T acc = tap<T>(0) * x[j + K];
+#pragma unroll
+      for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[j + K - t] + x[j + K + t]);
+      y[j] = acc;
+    }
+    // a lane's outputs are contiguous: 16-byte stores where the row length keeps them aligned
+    if (n2 % kRowSeg == 0) {
+      using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+      constexpr int PER = 16 / sizeof(T);
+#pragma unroll
+      for (int j = 0; j < kRowSeg; j += PER) {
+        V v;
+        T* vp = reinterpret_cast<T*>(&v);
+#pragma unroll
+        for (int e = 0; e < PER; ++e) vp[e] = y[j + e];
+        *reinterpret_cast<V*>(out + j) = v;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kRowSeg; ++j)
+        if (q * kRowSeg + j < n2) out[j] = y[j];
+    }
   }
 }
 
@@ -589,8 +635,9 @@ hipError_t launch_step(hipStream_t s, const StepArgs<T>& a, dim3 grid, dim3 bloc
   } else {
     constexpr int K = FilterTaps<T>::K;
     // a few thousand staged values per block, at most 48 KiB of LDS
-    const int rpb = std::max(1, std::min(4096 / a.n2, int((48 * 1024) / ((a.n2 + 2 * K) * sizeof(T)))));
-    const size_t lds = size_t(rpb) * (a.n2 + 2 * K) * sizeof(T);
+    const int Wp = row_stage_stride(a.n2, K);
+    const int rpb = std::max(1, std::min(4096 / a.n2, int((48 * 1024) / (Wp * sizeof(T)))));
+    const size_t lds = size_t(rpb) * Wp * sizeof(T);
     hipLaunchKernelGGL((k_prefilter_rows<T, KIND, FIRST>), dim3((a.n1 + rpb - 1) / rpb, 1, a.batch), dim3(256), lds,
                        s, a, rpb);
     hipError_t e = hipGetLastError();
