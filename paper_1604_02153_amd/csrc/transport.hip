@@ -33,7 +33,7 @@ struct FilterTaps;
 template <>
 struct FilterTaps<float> {
   static constexpr int K = 13;
-  static constexpr int R = 8;
+  static constexpr int R = 4;
 };
 template <>
 struct FilterTaps<double> {

@@ -199,7 +199,7 @@ def evaluate(net, seeds, torch, dev):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", required=True, help="weights file to write")
+    ap.add_argument("--out", default=None, help="weights file to write (required unless --eval-only)")
     ap.add_argument("--train-pairs", type=int, default=20000)
     ap.add_argument("--train-seed0", type=int, default=100000)
     ap.add_argument("--eval-pairs", type=int, default=1000)
@@ -213,11 +213,27 @@ def main():
     ap.add_argument("--start-kmax", type=int, default=8, help="Fourier cut-off of the learned start")
     ap.add_argument("--head-only", action="store_true", help="train only the e_max head of a loaded network")
     ap.add_argument("--report", default=None, help="JSON file for the statistics")
+    ap.add_argument("--eval-only", action="store_true", help="evaluate the --init weights on the held-out pairs only")
     args = ap.parse_args()
+    if args.eval_only and not args.init:
+        ap.error("--eval-only needs --init")
+    if not args.eval_only and not args.out:
+        ap.error("--out is required")
     import torch
     from paper_1604_02153_amd import UNet
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.eval_only:
+        net = UNet(N, N, 4, 32, max_batch=args.batch, seed=args.seed, start_kmax=args.start_kmax)
+        net.load(args.init)
+        estats = evaluate(net, list(range(args.eval_seed0, args.eval_seed0 + args.eval_pairs)), torch, dev)
+        rep = {"weights": args.init, "evaluation": estats}
+        if args.report:
+            with open(args.report, "w") as f:
+                json.dump(rep, f, indent=1)
+        print(json.dumps(rep), flush=True)
+        net.close()
+        return
     seeds = list(range(args.train_seed0, args.train_seed0 + args.train_pairs))
     log(f"generating and solving {len(seeds)} training pairs")
     mR, mT, vs, ys, gstats = generate(seeds, torch, dev)
