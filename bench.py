@@ -56,8 +56,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="length of the CPU oracle sample (s)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-pair ragged batch workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned vs plain comparison")
+    ap.add_argument("--no-brain", action="store_true", help="skip the 512^2 nt=8 single-pair workload")
     ap.add_argument("--learned-pairs", type=int, default=32, help="held-out pairs of the learned vs plain timing")
     ap.add_argument("--batched-matvecs", type=int, default=10, help="timed batched matvec calls (64 pairs each)")
+    ap.add_argument("--brain-matvecs", type=int, default=100, help="timed matvecs of the 512^2 workload")
     ap.add_argument("--spectral", action="store_true",
                     help="spectral-pass probe: 20 two-field spectral scalings at 1024^2 x16, 256^2 x64 and 128^2 "
                          "x64 batches (for a kernel trace); no JSON line")
@@ -210,6 +212,58 @@ def batched(args, dev):
         "autotune": [{"n": b[0], "pairs": b[2], "sl_path": b[3], "graphs": b[4], "op_ms": round(ms, 3)}
                      for b, ms in zip(buckets, tuned)],
     }
+
+
+def brain512(args, dev):
+    """Single 512^2 pair, nt = 8, H1 beta 1e-3, P_2L (the 'brain512' recipe): Newton solve time and
+    isolated GN matvec rate under both SL kernel paths, with the fraction of the HBM roofline.  (H1
+    without divergence control: on this pair the Gauss-Newton steps blow up at 256^2 and 512^2 and
+    the solve ends in a failed line search -- the FP64 oracle takes the same path at 256^2 -- so
+    its solve figures are reported with their status; the matvec figures are the measurement.)"""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1604_02153_amd import Context
+    cfg = synth.config("brain512")
+    n1, n2, nt = cfg["n1"], cfg["n2"], cfg["nt"]
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=torch.float32)
+    mT, vgen, vt = f32(cfg["mT"]), f32(cfg["v_gen"]), f32(cfg["vt"])
+    out = {"workload": "brain512: 512x512, nt=8, H1 beta=1e-3, P_2L (256^2, CHEB(10)); 64 anisotropic smoothed "
+                       "Gaussians, 24-mode velocity |k|<=6 amplitude 0.5 (seed 3)", "grid": [n1, n2], "nt": nt}
+    rates = {}
+    for path in (0, 1):
+        ctx = Context(n1, n2, nt, reg="h1", beta=cfg["beta"], prec="mixed", pc="2l", sl_path=path)
+        mR = torch.empty_like(mT)
+        ctx.transport_state(vgen, mT, mR)
+        ctx.set_images(mR, mT)
+        v = torch.zeros_like(vgen)
+        ctx.newton_solve(v)  # warm-up (graph capture, LDS attributes)
+        v.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = ctx.newton_solve(v)
+        torch.cuda.synchronize()
+        solve_ms = 1e3 * (time.perf_counter() - t0)
+        g = torch.empty_like(v)
+        ctx.gradient(vgen, g)
+        h = torch.empty_like(v)
+        for _ in range(10):
+            ctx.hessian_matvec(vt, h)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.brain_matvecs):
+            ctx.hessian_matvec(vt, h)
+        torch.cuda.synchronize()
+        rate = args.brain_matvecs / (time.perf_counter() - t1)
+        gbs = matvec_bytes(n1, n2, nt) * rate / 1e9
+        rates[path] = rate
+        out["fused_sl_step" if path == 0 else "two_kernel_sl_step"] = {
+            "solve_ms": round(solve_ms, 2), "solve_status": rep["status"], "newton_iters": rep["newton_iters"],
+            "pcg_iters": rep["pcg_iters"], "grel_final": rep["grel"][-1], "matvecs_per_s": round(rate, 1),
+            "matvec_GBps_algorithmic": round(gbs, 1), "matvec_roofline_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        ctx.close()
+    return out
 
 
 def unet_flops(h, w, levels=4, base=32):
@@ -414,6 +468,9 @@ def main():
     if not args.no_learned:
         line["learned_vs_plain"] = learned(args, dev)
         log("learned vs plain done")
+    if not args.no_brain:
+        line["brain512"] = brain512(args, dev)
+        log("512^2 workload done")
     if not args.no_batched:
         line["batched"] = batched(args, dev)
         log("batched workload done")

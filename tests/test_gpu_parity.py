@@ -528,3 +528,35 @@ def test_spectral_passes_all_lengths(slnk, shape):
     ctx.precond_apply(_t(vt, prec), z)
     assert rel(_np(z), O.apply_two_level(L, tl, vt)) < (1e-11 if prec == "fp64" else 1e-4)
     ctx.close()
+
+
+def test_brain512_recipe_matches_oracle(slnk):
+    """The 512^2 nt = 8 H1 workload (64 anisotropic smoothed Gaussians, 24-mode velocity of
+    amplitude 0.5, seed 3), mixed precision, both SL kernel paths: state transport, gradient and
+    GN matvec at 0.7 v_gen against the oracle."""
+    import synth
+    cfg = synth.config("brain512")
+    n1, n2, nt = cfg["n1"], cfg["n2"], cfg["nt"]
+    prec = "mixed"
+    g = O.Grid(n1, n2)
+    mT, vgen, vt = same_inputs(prec, cfg["mT"], cfg["v_gen"], cfg["vt"])
+    mR = same_inputs(prec, O.transport_state(g, vgen, mT, nt))
+    L = O.Level(g, mT, mR, O.Params(nt=nt, beta=cfg["beta"], reg=cfg["reg"]))
+    v = same_inputs(prec, 0.7 * vgen)
+    lin = O.linearize(L, v)
+    g_ref, h_ref = O.gradient(lin), O.hessian_matvec(lin, vt)
+    m_ref = O.transport_state(g, vgen, mT, nt)
+    for path in (0, 1):
+        print(f"brain512 sl_path {path}", flush=True)
+        ctx = _ctx(slnk, L, prec, pc="reg", sl_path=path)
+        m1 = torch.empty((n1, n2), dtype=torch.float32, device="cuda")
+        ctx.transport_state(_t(vgen, prec), _t(mT, prec), m1)
+        assert rel(_np(m1), m_ref) < TOL[prec]["transport"]
+        ctx.set_images(_t(mR, prec), _t(mT, prec))
+        gg = torch.empty((2, n1, n2), dtype=torch.float32, device="cuda")
+        ctx.gradient(_t(v, prec), gg)
+        _check_reg_op(L, "fp64", _np(gg), g_ref, v, TOL[prec]["gradient"])
+        h = torch.empty_like(gg)
+        ctx.hessian_matvec(_t(vt, prec), h)
+        _check_reg_op(L, prec, _np(h), h_ref, vt, TOL[prec]["matvec"])
+        ctx.close()
