@@ -14,7 +14,8 @@
  * Conventions shared by every entry point
  *   - Grid: periodic [0, 2 pi)^2 with n1 x n2 nodes, x_i = 2 pi i / n_i.  A scalar field is a
  *     row-major [n1][n2] array (i2 fastest); a vector field is two consecutive scalar fields
- *     ([2][n1][n2]).  n1, n2 even, each a product of 2, 3, 5, at least 8 and at most 2048.
+ *     ([2][n1][n2]).  n1, n2 even, each a product of 2, 3, 5, at least 8; n2 at most 2048 and n1
+ *     at most 2000 (the FP64 column transforms of larger n1 would not fit a workgroup's LDS).
  *   - Element type: double when params.prec == SLNK_PREC_FP64, float when SLNK_PREC_MIXED (fields
  *     in FP32; every inner product, norm, objective and Chebyshev/Lanczos scalar in FP64).
  *     Scalar outputs (J, norms, report) are always double.

@@ -330,6 +330,9 @@ struct Context {
     B = p.batch;
     if (B < 1 || B > 4096) throw Fail{SLNK_EINVAL, "batch must be in [1, 4096]"};
     if (!fft_size_ok(p.n1) || !fft_size_ok(p.n2)) throw Fail{SLNK_EINVAL, "grid sizes must be even products of 2, 3, 5 in [8, 2048]"};
+    // the FP64 column transforms (every context has an FP64 part) of n1 > 2000 would need more than
+    // the 160 KiB of LDS a gfx950 workgroup has
+    if (p.n1 > 2000) throw Fail{SLNK_EINVAL, "n1 must be at most 2000 (LDS of the FP64 column transforms)"};
     if (p.nt < 1 || p.nt > 512) throw Fail{SLNK_EINVAL, "nt must be in [1, 512]"};
     if (p.reg < 1 || p.reg > 3) throw Fail{SLNK_EINVAL, "reg must be 1, 2 or 3"};
     if (!(p.beta > 0)) throw Fail{SLNK_EINVAL, "beta must be positive"};

@@ -634,9 +634,11 @@ hipError_t launch_step(hipStream_t s, const StepArgs<T>& a, dim3 grid, dim3 bloc
     hipLaunchKernelGGL(kfn, grid, block, lds, s, a);
   } else {
     constexpr int K = FilterTaps<T>::K;
-    // a few thousand staged values per block, at most 48 KiB of LDS
+    // a few thousand staged values per block, at most 48 KiB of LDS, and fewer rows per block when
+    // that keeps about 2048 blocks in flight (small batches: each row's loads are one round trip)
     const int Wp = row_stage_stride(a.n2, K);
-    const int rpb = std::max(1, std::min(4096 / a.n2, int((48 * 1024) / (Wp * sizeof(T)))));
+    const int rows_all = a.n1 * a.batch;
+    const int rpb = std::max(1, std::min(std::min(4096 / a.n2, int((48 * 1024) / (Wp * sizeof(T)))), rows_all / 2048));
     const size_t lds = size_t(rpb) * Wp * sizeof(T);
     hipLaunchKernelGGL((k_prefilter_rows<T, KIND, FIRST>), dim3((a.n1 + rpb - 1) / rpb, 1, a.batch), dim3(256), lds,
                        s, a, rpb);

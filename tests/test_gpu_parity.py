@@ -560,3 +560,39 @@ def test_brain512_recipe_matches_oracle(slnk):
         ctx.hessian_matvec(_t(vt, prec), h)
         _check_reg_op(L, prec, _np(h), h_ref, vt, TOL[prec]["matvec"])
         ctx.close()
+
+
+def test_largest_grid_closed_forms(slnk):
+    """2000 x 2048, the largest grid a context takes (its lengths take the generic transforms),
+    mixed precision: zero-velocity transport is the identity; a constant velocity of one cell per
+    step along x1 and two along x2 shifts cyclically by nt and 2 nt cells; at v = 0 the gradient is
+    (m_R - m_T) grad m_T and the GN matvec beta A vt + (vt . grad m_T) grad m_T (at v = 0 the state
+    and adjoint are constant in time, so Heun and the trapezoid rule are exact)."""
+    import synth
+    n1, n2, nt, prec = 2000, 2048, 4, "mixed"
+    print(f"grid {n1}x{n2}", flush=True)
+    g = O.Grid(n1, n2)
+    rng = np.random.default_rng(70)
+    mT = synth.gaussian_sum_isotropic(n1, n2, rng)
+    mR = np.roll(mT, (3, -5), axis=(0, 1)) * 0.9 + 0.05
+    vt = synth.random_velocity(n1, n2, np.random.default_rng(71), modes=16, kmax=4, amplitude=0.1)
+    mT, mR, vt = same_inputs(prec, mT, mR, vt)
+    L = O.Level(g, mT, mR, O.Params(nt=nt, beta=1e-3, reg=2))
+    ctx = slnk.Context(n1, n2, nt, reg="h2", beta=1e-3, prec=prec, pc="reg")
+    m1 = torch.empty((n1, n2), dtype=torch.float32, device="cuda")
+    zero = torch.zeros((2, n1, n2), dtype=torch.float32, device="cuda")
+    ctx.transport_state(zero, _t(mT, prec), m1)
+    assert rel(_np(m1), mT) < TOL[prec]["transport"]
+    shift = np.stack([np.full((n1, n2), nt * g.h[0]), np.full((n1, n2), 2 * nt * g.h[1])])
+    ctx.transport_state(_t(shift, prec), _t(mT, prec), m1)
+    assert rel(_np(m1), np.roll(mT, (nt, 2 * nt), axis=(0, 1))) < TOL[prec]["transport"]
+    ctx.set_images(_t(mR, prec), _t(mT, prec))
+    gm = O.fft_grad(g, mT)
+    gg = torch.empty((2, n1, n2), dtype=torch.float32, device="cuda")
+    ctx.gradient(zero, gg)
+    assert rel(_np(gg), (mR - mT)[None] * gm) < TOL[prec]["gradient"]
+    h = torch.empty_like(gg)
+    ctx.hessian_matvec(_t(vt, prec), h)
+    h_ref = 1e-3 * O.apply_reg(g, vt, 2) + (vt[0] * gm[0] + vt[1] * gm[1])[None] * gm
+    _check_reg_op(L, prec, _np(h), h_ref, vt, TOL[prec]["matvec"])
+    ctx.close()
