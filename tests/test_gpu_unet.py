@@ -211,3 +211,40 @@ def test_learned_setup_takes_emax_from_the_head(slnk):
     assert r["status"] == "SLNK_OK" and r["grel"][-1] <= 1e-2
     net.close()
     ctx.close()
+
+
+def test_trained_network_saves_newton_work(slnk):
+    """The shipped trained network (weights/unet_gauss256.bin) on 8 held-out gauss256 pairs (seeds
+    200000..200007, outside its training seeds): every learned solve keeps the network's start and
+    reaches ||g||rel <= 1e-2, and together they need fewer Newton iterations and fewer fine GN
+    matvecs than the plain solves of the same pairs (the counts, not the wall times, which the
+    benchmark reports)."""
+    import os
+    from paper_1604_02153_amd.train_unet import make_pair
+    path = os.path.join(os.path.dirname(slnk.__file__), "weights", "unet_gauss256.bin")
+    n = 256
+    net = slnk.UNet(n, n, 4, 32, max_batch=1, start_kmax=8)
+    net.load(path)
+    ctx = slnk.Context(n, n, 4, reg="h2", beta=1e-3, prec="mixed", pc="2l")
+    v = torch.zeros((2, n, n), dtype=torch.float32, device="cuda")
+    plain_newton = learned_newton = plain_mv = learned_mv = 0
+    for s in range(200000, 200008):
+        mT, vg = make_pair(s)
+        mT, vg = _t(mT), _t(vg)
+        mR = torch.empty_like(mT)
+        ctx.transport_state(vg, mT, mR)
+        ctx.set_images(mR, mT)
+        v.zero_()
+        p = ctx.newton_solve(v)
+        ctx.set_images_learned(net, mR, mT)
+        q = ctx.newton_solve_learned(net, v)
+        print(s, p["newton_iters"], p["matvecs"], q["newton_iters"], q["matvecs"], q["fallback"], flush=True)
+        assert p["grel"][-1] <= 1e-2 and q["grel"][-1] <= 1e-2
+        assert q["status"] == "SLNK_OK" and not q["fallback"]
+        plain_newton += p["newton_iters"]
+        learned_newton += q["newton_iters"]
+        plain_mv += p["matvecs"]
+        learned_mv += q["matvecs"]
+    assert learned_newton < plain_newton and learned_mv < plain_mv
+    net.close()
+    ctx.close()
