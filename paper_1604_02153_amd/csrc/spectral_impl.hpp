@@ -4,10 +4,17 @@
 // 3.4.2: split preconditioning, cut-off filters, spectral restriction and prolongation).
 //
 // Layout.  A real field is [n1][n2].  Two real fields are packed as one complex row (a + i b),
-// transformed along x2 and unpacked into two half spectra [n1][n2/2+1] ("row pass").  The
-// column pass transforms the n2/2+1 columns along x1, applies the symbol (which may read several
-// input spectra and write several outputs) and transforms back.  The inverse row pass packs two
+// transformed along x2 and unpacked into two half spectra ("row pass").  The column pass
+// transforms the n2/2+1 columns along x1, applies the symbol (which may read several input
+// spectra and write several outputs) and transforms back.  The inverse row pass packs two
 // Hermitian half spectra into one complex row, inverts it and writes both real fields.
+//
+// Two implementations.  When n1 and n2 are both common lengths (64..1024 powers of two, 96..768
+// three times a power of two) the wave-level passes run, and the half spectra are stored
+// transposed, [n2/2+1][n1], so that the column pass reads and writes whole rows.  Otherwise the
+// generic passes run on half spectra [n1][spec_stride(n2)], with LDS-resident transforms of any
+// 2-3-5 length and workgroup barriers between stages.  The layout never leaves this file; a
+// restriction or prolongation takes the wave-level form only when both of its grids do.
 //
 // Conventions: forward transforms are unnormalised; every symbol carries the 1/(n1 n2) of the
 // inverse.  Odd symbols (derivatives) drop the Nyquist modes, even symbols keep them.
