@@ -134,6 +134,7 @@ struct StepArgs {
   T* out2 = nullptr;         // adjoint last step: gradient output (2 fields)
   T* coef = nullptr;         // one-field scratch: coefficients of the two-kernel (global gather) step
   T* coef2 = nullptr;        // one-field scratch: row-filtered values of that coefficient pass
+  int two_pass_coef = 0;     // coefficient pass as rows + columns through coef2 (else one 2-D pass)
   long long st_src = 0, st_dst = 0, st_d = 0, st_gamma = 0, st_aux0 = 0, st_aux1 = 0, st_gm = 0,
             st_acc = 0, st_vt = 0, st_addf = 0, st_out2 = 0, st_coef = 0, st_coef2 = 0;
   double ht = 0;

@@ -95,25 +95,45 @@ __device__ __forceinline__ void bspline_w(T t, T* w) {
   w[3] = t3 / T(6);
 }
 
-// Spline value at (s1, s2) (in cells) from a global coefficient field, periodic.
+// Spline value at (s1, s2) (in cells) from a global coefficient field, periodic.  The stencil's
+// first row and column are wrapped once (a division only for departure points outside the
+// grid); its other rows and columns then need at most one subtraction.  Away from the last three
+// columns a stencil row is four consecutive values, read as one 16-byte (FP32) or two 16-byte
+// (FP64) copies: the compiler emits wide loads where the target allows unaligned access and
+// element loads otherwise.
 template <typename T>
 __device__ T interp_global(const T* __restrict__ c, int n1, int n2, T s1, T s2) {
   const T f1 = floor(s1), f2 = floor(s2);
   T w1[4], w2[4];
   bspline_w(s1 - f1, w1);
   bspline_w(s2 - f2, w2);
-  const int i1 = int(f1) - 1, i2 = int(f2) - 1;
-  int cols[4];
-#pragma unroll
-  for (int b = 0; b < 4; ++b) cols[b] = wrap_index(i2 + b, n2);
+  int i1 = int(f1) - 1, i2 = int(f2) - 1;
+  if (unsigned(i1) >= unsigned(n1)) i1 = wrap_index(i1, n1);
+  if (unsigned(i2) >= unsigned(n2)) i2 = wrap_index(i2, n2);
   T acc = T(0);
+  if (i2 + 3 < n2) {
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const T* row = c + size_t(wrap_index(i1 + a, n1)) * n2;
-    T r = T(0);
+    for (int a = 0; a < 4; ++a) {
+      int r = i1 + a;
+      r -= r >= n1 ? n1 : 0;
+      T v[4];
+      __builtin_memcpy(v, c + size_t(r) * n2 + i2, sizeof(v));
+      acc += w1[a] * (w2[0] * v[0] + w2[1] * v[1] + w2[2] * v[2] + w2[3] * v[3]);
+    }
+  } else {
+    int cols[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) r += w2[b] * row[cols[b]];
-    acc += w1[a] * r;
+    for (int b = 0; b < 4; ++b) {
+      const int cb = i2 + b;
+      cols[b] = cb >= n2 ? cb - n2 : cb;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      int r = i1 + a;
+      r -= r >= n1 ? n1 : 0;
+      const T* row = c + size_t(r) * n2;
+      acc += w1[a] * (w2[0] * row[cols[0]] + w2[1] * row[cols[1]] + w2[2] * row[cols[2]] + w2[3] * row[cols[3]]);
+    }
   }
   return acc;
 }
@@ -402,6 +422,95 @@ __global__ void __launch_bounds__(256) k_prefilter_cols(StepArgs<T> args) {
   }
 }
 
+// One-kernel coefficient pass (the two-kernel step's default): a block stages a TS x TS tile of
+// the transported field with K wrapped values on every side in LDS, filters its rows (all PS
+// staged rows, TS outputs each) and then its columns, and writes the TS x TS coefficients.  The
+// halo re-reads hit L2 (tiles of one XCD are contiguous, as in the step kernels), so HBM sees the
+// field once and the coefficients once.  R consecutive outputs per thread from register windows;
+// odd LDS row strides keep consecutive threads on different banks.
+template <typename T>
+struct Prefilter2D {
+  static constexpr int K = FilterTaps<T>::K;
+  static constexpr int TS = sizeof(T) == 4 ? 64 : 32;  // output tile side
+  static constexpr int PS = TS + 2 * K;                 // staged side
+  static constexpr int SA = PS + 1, SB = TS + 1;        // LDS row strides (odd)
+  static constexpr int R = 8;                           // outputs per thread and pass
+  static constexpr size_t kLds = (size_t(PS) * SA + size_t(PS) * SB) * sizeof(T);
+};
+
+template <typename T, int KIND, bool FIRST>
+__global__ void __launch_bounds__(256) k_prefilter_2d(StepArgs<T> args) {
+  if (args.active && !args.active[blockIdx.z]) return;
+  const StepArgs<T> a = item_view(args, blockIdx.z);
+  using P2 = Prefilter2D<T>;
+  constexpr int K = P2::K, TS = P2::TS, PS = P2::PS, SA = P2::SA, SB = P2::SB, R = P2::R;
+  extern __shared__ unsigned char smem_raw[];
+  T* A = reinterpret_cast<T*>(smem_raw);  // [PS][SA] staged values
+  T* B = A + PS * SA;                     // [PS][SB] row-filtered values
+  const int n1 = a.n1, n2 = a.n2;
+  int by, bx;
+  xcd_tile(by, bx);
+  const int y0 = by * TS, x0 = bx * TS;
+  const int tid = threadIdx.x;
+  // 1. stage: every load of the thread is issued before any store (no per-load wait); the grid
+  // is at least PS in both directions (caller), so one add or subtract wraps an index
+  constexpr int NL = (PS * PS + 255) / 256;
+  T v[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int idx = min(tid + 256 * k, PS * PS - 1);  // past the end: repeat a valid load
+    const int r = idx / PS, c = idx - r * PS;
+    int gr = y0 - K + r, gc = x0 - K + c;
+    gr += gr < 0 ? n1 : 0;
+    gr -= gr >= n1 ? n1 : 0;
+    gc += gc < 0 ? n2 : 0;
+    gc -= gc >= n2 ? n2 : 0;
+    v[k] = load_src<T, KIND, FIRST>(a, size_t(gr) * n2 + gc);
+  }
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int idx = tid + 256 * k;
+    if (idx < PS * PS) {
+      const int r = idx / PS, c = idx - r * PS;
+      A[r * SA + c] = v[k];
+    }
+  }
+  __syncthreads();
+  // 2. rows: task (row r, segment q), consecutive threads on consecutive rows
+  for (int task = tid; task < PS * (TS / R); task += 256) {
+    const int q = task / PS, r = task - q * PS;
+    const T* src = A + r * SA + q * R;
+    T x[R + 2 * K];
+#pragma unroll
+    for (int i = 0; i < R + 2 * K; ++i) x[i] = src[i];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      T acc = tap<T>(0) * x[j + K];
+#pragma unroll
+      for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[j + K - t] + x[j + K + t]);
+      B[r * SB + q * R + j] = acc;
+    }
+  }
+  __syncthreads();
+  // 3. columns: task (column c, segment q), consecutive threads on consecutive columns
+  for (int task = tid; task < TS * (TS / R); task += 256) {
+    const int q = task / TS, c = task - q * TS;
+    const T* src = B + (q * R) * SB + c;
+    T x[R + 2 * K];
+#pragma unroll
+    for (int i = 0; i < R + 2 * K; ++i) x[i] = src[i * SB];
+    const int col = x0 + c;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      T acc = tap<T>(0) * x[j + K];
+#pragma unroll
+      for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[j + K - t] + x[j + K + t]);
+      const int row = y0 + q * R + j;
+      if (row < n1 && col < n2) a.coef[size_t(row) * n2 + col] = acc;
+    }
+  }
+}
+
 template <typename T, int KIND, bool FIRST, bool GLOBAL>
 __global__ void __launch_bounds__(256) k_sl_step(StepArgs<T> args) {
   if (args.active && !args.active[blockIdx.z]) return;
@@ -632,6 +741,24 @@ hipError_t launch_step(hipStream_t s, const StepArgs<T>& a, dim3 grid, dim3 bloc
       }
     }
     hipLaunchKernelGGL(kfn, grid, block, lds, s, a);
+  } else if (!a.two_pass_coef && a.n1 >= Prefilter2D<T>::PS && a.n2 >= Prefilter2D<T>::PS) {
+    using P2 = Prefilter2D<T>;
+    static std::atomic<size_t> attr2{0};
+    if (P2::kLds > 64 * 1024 && attr2.load(std::memory_order_acquire) < P2::kLds) {
+      std::lock_guard<std::mutex> lock(g_setup_mutex);
+      if (attr2.load(std::memory_order_relaxed) < P2::kLds) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_prefilter_2d<T, KIND, FIRST>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(P2::kLds));
+        if (e != hipSuccess) return e;
+        attr2.store(P2::kLds, std::memory_order_release);
+      }
+    }
+    hipLaunchKernelGGL((k_prefilter_2d<T, KIND, FIRST>),
+                       dim3((a.n2 + P2::TS - 1) / P2::TS, (a.n1 + P2::TS - 1) / P2::TS, a.batch), dim3(256), P2::kLds,
+                       s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sl_step<T, KIND, FIRST, true>), grid, block, 0, s, a);
   } else {
     constexpr int K = FilterTaps<T>::K;
     // a few thousand staged values per block, at most 48 KiB of LDS, and fewer rows per block when
