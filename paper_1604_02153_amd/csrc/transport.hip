@@ -435,15 +435,16 @@ struct Prefilter2D {
   static constexpr int PS = TS + 2 * K;                 // staged side
   static constexpr int SA = PS + 1, SB = TS + 1;        // LDS row strides (odd)
   static constexpr int R = 8;                           // outputs per thread and pass
+  static constexpr int NT = 512;                        // threads per block
   static constexpr size_t kLds = (size_t(PS) * SA + size_t(PS) * SB) * sizeof(T);
 };
 
 template <typename T, int KIND, bool FIRST>
-__global__ void __launch_bounds__(256) k_prefilter_2d(StepArgs<T> args) {
+__global__ void __launch_bounds__(Prefilter2D<T>::NT) k_prefilter_2d(StepArgs<T> args) {
   if (args.active && !args.active[blockIdx.z]) return;
   const StepArgs<T> a = item_view(args, blockIdx.z);
   using P2 = Prefilter2D<T>;
-  constexpr int K = P2::K, TS = P2::TS, PS = P2::PS, SA = P2::SA, SB = P2::SB, R = P2::R;
+  constexpr int K = P2::K, TS = P2::TS, PS = P2::PS, SA = P2::SA, SB = P2::SB, R = P2::R, NT = P2::NT;
   extern __shared__ unsigned char smem_raw[];
   T* A = reinterpret_cast<T*>(smem_raw);  // [PS][SA] staged values
   T* B = A + PS * SA;                     // [PS][SB] row-filtered values
@@ -454,11 +455,11 @@ __global__ void __launch_bounds__(256) k_prefilter_2d(StepArgs<T> args) {
   const int tid = threadIdx.x;
   // 1. stage: every load of the thread is issued before any store (no per-load wait); the grid
   // is at least PS in both directions (caller), so one add or subtract wraps an index
-  constexpr int NL = (PS * PS + 255) / 256;
+  constexpr int NL = (PS * PS + NT - 1) / NT;
   T v[NL];
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
-    const int idx = min(tid + 256 * k, PS * PS - 1);  // past the end: repeat a valid load
+    const int idx = min(tid + NT * k, PS * PS - 1);  // past the end: repeat a valid load
     const int r = idx / PS, c = idx - r * PS;
     int gr = y0 - K + r, gc = x0 - K + c;
     gr += gr < 0 ? n1 : 0;
@@ -469,7 +470,7 @@ __global__ void __launch_bounds__(256) k_prefilter_2d(StepArgs<T> args) {
   }
 #pragma unroll
   for (int k = 0; k < NL; ++k) {
-    const int idx = tid + 256 * k;
+    const int idx = tid + NT * k;
     if (idx < PS * PS) {
       const int r = idx / PS, c = idx - r * PS;
       A[r * SA + c] = v[k];
@@ -477,7 +478,7 @@ __global__ void __launch_bounds__(256) k_prefilter_2d(StepArgs<T> args) {
   }
   __syncthreads();
   // 2. rows: task (row r, segment q), consecutive threads on consecutive rows
-  for (int task = tid; task < PS * (TS / R); task += 256) {
+  for (int task = tid; task < PS * (TS / R); task += NT) {
     const int q = task / PS, r = task - q * PS;
     const T* src = A + r * SA + q * R;
     T x[R + 2 * K];
@@ -493,7 +494,7 @@ __global__ void __launch_bounds__(256) k_prefilter_2d(StepArgs<T> args) {
   }
   __syncthreads();
   // 3. columns: task (column c, segment q), consecutive threads on consecutive columns
-  for (int task = tid; task < TS * (TS / R); task += 256) {
+  for (int task = tid; task < TS * (TS / R); task += NT) {
     const int q = task / TS, c = task - q * TS;
     const T* src = B + (q * R) * SB + c;
     T x[R + 2 * K];
@@ -754,7 +755,7 @@ hipError_t launch_step(hipStream_t s, const StepArgs<T>& a, dim3 grid, dim3 bloc
       }
     }
     hipLaunchKernelGGL((k_prefilter_2d<T, KIND, FIRST>),
-                       dim3((a.n2 + P2::TS - 1) / P2::TS, (a.n1 + P2::TS - 1) / P2::TS, a.batch), dim3(256), P2::kLds,
+                       dim3((a.n2 + P2::TS - 1) / P2::TS, (a.n1 + P2::TS - 1) / P2::TS, a.batch), dim3(P2::NT), P2::kLds,
                        s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
