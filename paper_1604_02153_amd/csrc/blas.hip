@@ -184,10 +184,13 @@ __global__ void k_set_ints(int* p, IntPack pack, int count) {
   if (int(threadIdx.x) < count) p[threadIdx.x] = pack.v[threadIdx.x];
 }
 
+// One element per thread up to 64 Ki blocks per item: an elementwise kernel then has no
+// loop-carried chain (its loads could not move above the previous element's stores, which may
+// alias them), so small fields finish in one memory round trip.
 inline unsigned grid_for(size_t n) {
-  size_t b = (n + kThreads * 4 - 1) / (kThreads * 4);
+  size_t b = (n + kThreads - 1) / kThreads;
   if (b < 1) b = 1;
-  if (b > 2048) b = 2048;
+  if (b > 65535) b = 65535;
   return unsigned(b);
 }
 

@@ -664,11 +664,21 @@ __global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_inv(const cplx<
   T* OB = hasb ? out.p[fb] + z * out.bstride[fb] + gb : nullptr;
   const T* AA = out.add[fa] ? out.add[fa] + z * out.bstride[fa] + gb : nullptr;
   const T* AB = hasb && out.add[fb] ? out.add[fb] + z * out.bstride[fb] + gb : nullptr;
+  // addends loaded in full before the first store (the outputs may alias nothing, but the
+  // compiler cannot know that, and would otherwise wait for each load in turn)
+  if (AA) {
+#pragma unroll
+    for (int m = 0; m < PL::E; ++m) x[m].x += AA[wmap<N, rL>(lp, m)];
+  }
+  if (AB) {
+#pragma unroll
+    for (int m = 0; m < PL::E; ++m) x[m].y += AB[wmap<N, rL>(lp, m)];
+  }
 #pragma unroll
   for (int m = 0; m < PL::E; ++m) {
     const int e = wmap<N, rL>(lp, m);
-    OA[e] = AA ? x[m].x + AA[e] : x[m].x;
-    if (OB) OB[e] = AB ? x[m].y + AB[e] : x[m].y;
+    OA[e] = x[m].x;
+    if (OB) OB[e] = x[m].y;
   }
 }
 
