@@ -436,7 +436,10 @@ struct Prefilter2D {
   static constexpr int SA = PS + 1, SB = TS + 1;        // LDS row strides (odd)
   static constexpr int R = 8;                           // outputs per thread and pass
   static constexpr int NT = 512;                        // threads per block
-  static constexpr size_t kLds = (size_t(PS) * SA + size_t(PS) * SB) * sizeof(T);
+  static constexpr int KT = (PS * (TS / R) + NT - 1) / NT;  // row-pass tasks per thread
+  // the row-filtered values overwrite the staged ones (after a barrier), so one buffer serves
+  static constexpr size_t kLds = size_t(PS) * SA * sizeof(T);
+  static_assert(SB <= SA, "row-filtered rows must fit the staged rows");
 };
 
 template <typename T, int KIND, bool FIRST>
@@ -447,7 +450,7 @@ __global__ void __launch_bounds__(Prefilter2D<T>::NT) k_prefilter_2d(StepArgs<T>
   constexpr int K = P2::K, TS = P2::TS, PS = P2::PS, SA = P2::SA, SB = P2::SB, R = P2::R, NT = P2::NT;
   extern __shared__ unsigned char smem_raw[];
   T* A = reinterpret_cast<T*>(smem_raw);  // [PS][SA] staged values
-  T* B = A + PS * SA;                     // [PS][SB] row-filtered values
+  T* B = A;                               // [PS][SB] row-filtered values, written over A
   const int n1 = a.n1, n2 = a.n2;
   int by, bx;
   xcd_tile(by, bx);
@@ -477,19 +480,35 @@ __global__ void __launch_bounds__(Prefilter2D<T>::NT) k_prefilter_2d(StepArgs<T>
     }
   }
   __syncthreads();
-  // 2. rows: task (row r, segment q), consecutive threads on consecutive rows
-  for (int task = tid; task < PS * (TS / R); task += NT) {
-    const int q = task / PS, r = task - q * PS;
-    const T* src = A + r * SA + q * R;
-    T x[R + 2 * K];
+  // 2. rows: task (row r, segment q), consecutive threads on consecutive rows; every task's
+  // outputs stay in registers until all staged values are read
+  T y[P2::KT][R];
 #pragma unroll
-    for (int i = 0; i < R + 2 * K; ++i) x[i] = src[i];
+  for (int k = 0; k < P2::KT; ++k) {
+    const int task = tid + k * NT;
+    if (task < PS * (TS / R)) {
+      const int q = task / PS, r = task - q * PS;
+      const T* src = A + r * SA + q * R;
+      T x[R + 2 * K];
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      T acc = tap<T>(0) * x[j + K];
+      for (int i = 0; i < R + 2 * K; ++i) x[i] = src[i];
 #pragma unroll
-      for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[j + K - t] + x[j + K + t]);
-      B[r * SB + q * R + j] = acc;
+      for (int j = 0; j < R; ++j) {
+        T acc = tap<T>(0) * x[j + K];
+#pragma unroll
+        for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[j + K - t] + x[j + K + t]);
+        y[k][j] = acc;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < P2::KT; ++k) {
+    const int task = tid + k * NT;
+    if (task < PS * (TS / R)) {
+      const int q = task / PS, r = task - q * PS;
+#pragma unroll
+      for (int j = 0; j < R; ++j) B[r * SB + q * R + j] = y[k][j];
     }
   }
   __syncthreads();
