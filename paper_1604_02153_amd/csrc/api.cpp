@@ -226,7 +226,10 @@ struct Context {
   bool learned_ready = false;
   // counters of the current solve
   std::vector<int> n_matvec, n_coarse;
+  // preconditioner time: event pairs around each application, summed without stalling the stream
   double t_prec = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prec_ev;
+  size_t prec_used = 0;
 
   enum { kMaskAll = 0, kMaskPcg = 1, kMaskNewton = 2, kMaskLs = 3 };
   int* mask(int k) const { return masks + k * B; }
@@ -407,6 +410,12 @@ struct Context {
 
   void destroy() {
     clear_graphs();
+    for (auto& e : prec_ev) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    prec_ev.clear();
+    prec_used = 0;
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     cap_stream = nullptr;
     if (hres) (void)hipHostFree(hres);
@@ -422,6 +431,40 @@ struct Context {
                           stream));
     HIPCHK(hipStreamSynchronize(stream));
     return hres + half * 4 * B;
+  }
+
+  // next free event pair of the preconditioner timer (a full pool is folded into t_prec first)
+  const std::pair<hipEvent_t, hipEvent_t>& prec_event() {
+    if (prec_used == 256) fold_prec_time();
+    if (prec_used == prec_ev.size()) {
+      std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
+      HIPCHK(hipEventCreate(&e.first));
+      if (hipEventCreate(&e.second) != hipSuccess) {
+        (void)hipEventDestroy(e.first);
+        throw Fail{SLNK_EDEVICE, "hipEventCreate failed"};
+      }
+      prec_ev.push_back(e);
+    }
+    return prec_ev[prec_used++];
+  }
+
+  // add the recorded preconditioner intervals to t_prec (waits for the last one)
+  void fold_prec_time() {
+    if (prec_used == 0) return;
+    HIPCHK(hipEventSynchronize(prec_ev[prec_used - 1].second));
+    for (size_t i = 0; i < prec_used; ++i) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, prec_ev[i].first, prec_ev[i].second));
+      t_prec += ms;
+    }
+    prec_used = 0;
+  }
+
+  // read both halves of dres to the host
+  const double* fetch_both() {
+    HIPCHK(hipMemcpyAsync(hres, dres, 8 * B * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    return hres;
   }
 
   // publish per-item scalars as row k of dsc.  The pinned row is reused only after a later
@@ -773,12 +816,20 @@ struct Context {
     if (k == 1) return;
     HIPCHK(spec_scale<T>(stream, coarse.sg, B, mk, sym(Symbol::RegInvSqrt), 2, b, u, nullptr, coarse.S1, coarse.S2));
     HIPCHK(axpby<T>(stream, B, n, 1.0, inv_theta, u, 0.0, nullptr, y));
+    const bool fused = spec_fast<T>(coarse.sg);
     for (int i = 0; i < k - 1; ++i) {
       gn_transport(coarse, y, mk);
-      HIPCHK(spec_scale2<T>(stream, coarse.sg, B, mk, sym(Symbol::RegInvSqrt), sym(Symbol::RegInv), coarse.bt, sb, s2b,
-                            coarse.S1, coarse.S2));
-      HIPCHK(cheb_step<T>(stream, B, n, cheb_tab + size_t(i) * B, cheb_tab + (size_t(k) + i) * B, r, u, d, y, x, sb,
-                          s2b));
+      const double* c1 = cheb_tab + size_t(i) * B;
+      const double* c2 = cheb_tab + (size_t(k) + i) * B;
+      if (fused) {
+        // the inverse row pass of S Q y, S^2 Q y applies the step in place
+        HIPCHK(spec_scale2_cheb<T>(stream, coarse.sg, B, mk, sym(Symbol::RegInvSqrt), sym(Symbol::RegInv), coarse.bt,
+                                   ChebTail<T>{r, d, x, u, y, c1, c2}, coarse.S1, coarse.S2));
+      } else {
+        HIPCHK(spec_scale2<T>(stream, coarse.sg, B, mk, sym(Symbol::RegInvSqrt), sym(Symbol::RegInv), coarse.bt, sb,
+                              s2b, coarse.S1, coarse.S2));
+        HIPCHK(cheb_step<T>(stream, B, n, c1, c2, r, u, d, y, x, sb, s2b));
+      }
     }
   }
 
@@ -830,7 +881,8 @@ struct Context {
   }
 
   void precond(const T* r, T* z, const int* mk, const std::vector<int>& hmask) {
-    const double t0 = now_ms();
+    const auto& pe = prec_event();
+    HIPCHK(hipEventRecord(pe.first, stream));
     if (!two_level) {
       HIPCHK(spec_scale<T>(stream, fine.sg, B, mk, sym(Symbol::RegInv), 2, r, z, nullptr, fine.S1, fine.S2));
     } else {
@@ -844,8 +896,7 @@ struct Context {
       });
       count(n_coarse, hmask, prm.cheb_iters - 1);
     }
-    HIPCHK(hipStreamSynchronize(stream));
-    t_prec += now_ms() - t0;
+    HIPCHK(hipEventRecord(pe.second, stream));
   }
 
   // fine operator of the Krylov solve: H (P_REG) or the split operator (P_2L)
@@ -862,7 +913,9 @@ struct Context {
 
   // Per-item PCG from zero on op x = b (relative tolerances tol[z]), in lock step over the items
   // of 'active'.  Iterations and status of each item in its / st.  Stopped items see zero step
-  // coefficients, which leave their x and r untouched.
+  // coefficients, which leave their x and r untouched.  The step coefficients are formed in device
+  // memory (rz in row 9 of the scalar block); the host synchronises once per iteration, to read the
+  // curvature p.q together with the residual norm.
   void pcg(const T* b, T* x, const std::vector<double>& tol, int maxit, std::vector<int> active, std::vector<int>& its,
            std::vector<int>& st) {
     const size_t n = 2 * fine.F;
@@ -870,6 +923,8 @@ struct Context {
     T* z = fine.vec[1];
     T* p = fine.vec[2];
     T* q = fine.vec[3];
+    double* rz = sc(9);
+    double* pq_dev = dres + 4 * B;
     its.assign(B, 0);
     st.assign(B, SLNK_OK);
     HIPCHK(fill<T>(stream, B * n, 0.0, x));
@@ -884,34 +939,32 @@ struct Context {
     put_mask(kMaskPcg, active);
     precond(r, z, mk, active);
     HIPCHK(axpby<T>(stream, B, n, 1.0, nullptr, z, 0.0, nullptr, p));
-    std::vector<double> rz = dots(fine, r, z);
-    std::vector<double> alpha(B), beta(B);
+    HIPCHK(dot<T>(stream, B, n, r, z, partial, dres));
+    HIPCHK(pcg_coef(stream, PCG_RZ, B, mk, dres, rz, nullptr, nullptr));
     for (int it = 1; it <= maxit; ++it) {
       op(p, q, mk, active);
-      std::vector<double> pq = dots(fine, p, q);
+      HIPCHK(dot<T>(stream, B, n, p, q, partial, pq_dev));
+      HIPCHK(pcg_coef(stream, PCG_ALPHA, B, mk, pq_dev, rz, sc(4), nullptr));
+      HIPCHK(axpby<T>(stream, B, n, 1.0, sc(4), p, 1.0, nullptr, x));
+      HIPCHK(axpby<T>(stream, B, n, -1.0, sc(4), q, 1.0, nullptr, r));
+      HIPCHK(dot<T>(stream, B, n, r, r, partial, dres));
+      fetch_both();
+      const double* rr = hres;
+      const double* pq = hres + 4 * B;
+      bool more = false;
       for (int k = 0; k < B; ++k) {
-        alpha[k] = 0.0;
         if (!active[k]) continue;
         its[k] = it;
-        if (!std::isfinite(pq[k])) throw Fail{SLNK_ENAN, "non-finite curvature in PCG"};
-        if (pq[k] <= 0.0) {
+        if (!std::isfinite(pq[4 * k])) throw Fail{SLNK_ENAN, "non-finite curvature in PCG"};
+        if (pq[4 * k] <= 0.0) {
           // non-positive curvature: stop with the current iterate (at the first step, the
-          // preconditioned residual)
+          // preconditioned residual); the step coefficient was zero
           if (it == 1) HIPCHK(masked_copy<T>(stream, 1, n, z + k * n, 0, x + k * n, 0, nullptr));
           st[k] = SLNK_ENEGCURV;
           active[k] = 0;
           continue;
         }
-        alpha[k] = rz[k] / pq[k];
-      }
-      put_scalars(4, alpha);
-      HIPCHK(axpby<T>(stream, B, n, 1.0, sc(4), p, 1.0, nullptr, x));
-      HIPCHK(axpby<T>(stream, B, n, -1.0, sc(4), q, 1.0, nullptr, r));
-      std::vector<double> rr = dots(fine, r, r);
-      bool more = false;
-      for (int k = 0; k < B; ++k) {
-        if (!active[k]) continue;
-        if (std::sqrt(rr[k]) <= tol[k] * bnorm[k])
+        if (std::sqrt(rr[4 * k]) <= tol[k] * bnorm[k])
           active[k] = 0;
         else
           more = true;
@@ -920,17 +973,9 @@ struct Context {
       if (it == maxit) break;
       put_mask(kMaskPcg, active);
       precond(r, z, mk, active);
-      std::vector<double> rz_next = dots(fine, r, z);
-      for (int k = 0; k < B; ++k) beta[k] = active[k] ? rz_next[k] / rz[k] : 0.0;
-      put_scalars(5, beta);
-      for (int k = 0; k < B; ++k)
-        if (active[k]) rz[k] = rz_next[k];
+      HIPCHK(dot<T>(stream, B, n, r, z, partial, dres));
       // p <- z + beta p for the running items; stopped items keep p (coefficients 0, 1)
-      for (int k = 0; k < B; ++k) alpha[k] = active[k] ? 1.0 : 0.0;
-      put_scalars(6, alpha);
-      for (int k = 0; k < B; ++k)
-        if (!active[k]) beta[k] = 1.0;
-      put_scalars(7, beta);
+      HIPCHK(pcg_coef(stream, PCG_BETA, B, mk, dres, rz, sc(6), sc(7)));
       HIPCHK(axpby<T>(stream, B, n, 1.0, sc(6), z, 1.0, sc(7), p));
     }
     for (int k = 0; k < B; ++k)
@@ -1072,6 +1117,7 @@ struct Context {
     for (auto& r : R) std::memset(&r, 0, sizeof(r));
     std::fill(n_matvec.begin(), n_matvec.end(), 0);
     std::fill(n_coarse.begin(), n_coarse.end(), 0);
+    prec_used = 0;
     t_prec = 0;
     const size_t n = 2 * fine.F;
     double t_grad = 0, t_pcg = 0, t_ls = 0;
@@ -1217,6 +1263,7 @@ struct Context {
       linearize_coarse(mk, {});
     }
     HIPCHK(hipStreamSynchronize(stream));
+    fold_prec_time();
     has_grad = true;
     const double t_total = now_ms() - t_start;
     slnk_status overall = SLNK_OK;

@@ -3,6 +3,7 @@
 // Every operation runs on 'batch' same-size items at once (grid y = item).  Every reduction is
 // two-stage with a fixed combination order, so results are deterministic.
 #include <algorithm>
+#include <cfloat>
 
 #include "kernels.hpp"
 
@@ -176,6 +177,33 @@ __global__ void k_cast(size_t n, const TI* __restrict__ x, TO* __restrict__ y) {
     y[i] = TO(x[i]);
 }
 
+// Step coefficients of the preconditioned CG iteration kept in device memory (item z's reduction
+// at red[4 z]).  PCG_RZ stores rz[z]; PCG_ALPHA writes c0[z] = rz / pq for running items whose
+// curvature pq is positive and finite, else 0 (the host reads pq with the residual norm and acts
+// on the rest); PCG_BETA forms beta = rz_new / rz, stores rz_new and writes the coefficients of
+// p <- c0 z + c1 p: (1, beta) for running items, (0, 1) for stopped ones.
+__global__ void k_pcg_coef(int mode, int batch, const int* mask, const double* red, double* rz, double* c0,
+                           double* c1) {
+  const int z = threadIdx.x + blockIdx.x * blockDim.x;
+  if (z >= batch) return;
+  const bool run = !mask || mask[z] != 0;
+  const double v = red[4 * z];
+  if (mode == PCG_RZ) {
+    if (run) rz[z] = v;
+  } else if (mode == PCG_ALPHA) {
+    c0[z] = (run && v > 0.0 && v <= DBL_MAX) ? rz[z] / v : 0.0;
+  } else {
+    if (run) {
+      c0[z] = 1.0;
+      c1[z] = v / rz[z];
+      rz[z] = v;
+    } else {
+      c0[z] = 0.0;
+      c1[z] = 1.0;
+    }
+  }
+}
+
 struct IntPack {
   int v[64];
 };
@@ -195,6 +223,13 @@ inline unsigned grid_for(size_t n) {
 }
 
 }  // namespace
+
+hipError_t pcg_coef(hipStream_t s, int mode, int batch, const int* mask, const double* red, double* rz, double* c0,
+                    double* c1) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pcg_coef, dim3((batch + 63) / 64), dim3(64), 0, s, mode, batch, mask, red, rz, c0, c1);
+  return hipGetLastError();
+}
 
 hipError_t set_ints(hipStream_t s, int* p, const int* host_values, int count) {
   for (int base = 0; base < count; base += 64) {

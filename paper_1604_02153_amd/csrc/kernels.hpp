@@ -73,6 +73,29 @@ template <typename T>
 hipError_t spec_scale2(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, SymbolParams sym1,
                        SymbolParams sym2, const T* in, T* out1, T* out2, cplx<T>* S1, cplx<T>* S2);
 
+// Vectors of one Chebyshev step on M = I + S Q S (item stride 2 field(), coefficients per item)
+template <typename T>
+struct ChebTail {
+  T* r;
+  T* d;
+  T* x;
+  T* u;
+  T* y;
+  const double* c1;
+  const double* c2;
+};
+
+// true when the grid takes the wave-level transform passes (both lengths in the fast set)
+template <typename T>
+bool spec_fast(const SpecGrid<T>& g);
+
+// spec_scale2 with sym1 = S, sym2 = S^2 of in = Q y, followed by the Chebyshev step of cheb_step on
+// ct in the same pass (sb and s2b are never stored).  Fast grids only (else hipErrorNotSupported);
+// items with active[z] == 0 are left untouched.  S1 >= 2 batch spec(), S2 >= 4 batch spec().
+template <typename T>
+hipError_t spec_scale2_cheb(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, SymbolParams sym1,
+                            SymbolParams sym2, const T* in, ChebTail<T> ct, cplx<T>* S1, cplx<T>* S2);
+
 // Spectral gradient of 'count' consecutive scalar fields m[c] (stride field()): gm[c] = (d1 m, d2 m)
 // with stride 2 field().  S1 >= count spec(), S2 >= 2 count spec().
 template <typename T>
@@ -220,6 +243,14 @@ hipError_t xpay_mixed(hipStream_t s, int batch, size_t n, const double* x, doubl
 template <typename T>
 hipError_t masked_copy(hipStream_t s, int batch, size_t n, const T* src, long long src_stride, T* dst,
                        long long dst_stride, const int* mask);
+
+// Device-side step coefficients of the lock-step PCG (item z's reduction at red[4 z], z < batch;
+// mask optional): PCG_RZ stores rz; PCG_ALPHA writes c0 = rz / pq, 0 for stopped items and for
+// curvature that is not positive and finite; PCG_BETA writes (c0, c1) = (1, rz_new / rz) and stores
+// rz_new for running items, (0, 1) for stopped ones
+enum { PCG_RZ = 0, PCG_ALPHA = 1, PCG_BETA = 2 };
+hipError_t pcg_coef(hipStream_t s, int mode, int batch, const int* mask, const double* red, double* rz, double* c0,
+                    double* c1);
 
 // p[i] = host_values[i], i < count (kernel arguments, no staging buffer): publishes
 // per-linearisation integers (halos, masks) to device memory read by captured graphs

@@ -614,10 +614,13 @@ __global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_fwd(RealFields<
 }
 
 // Inverse row pass: transposed half spectra (2q, 2q+1) of item z -> real fields (plus addend).
-template <typename T, int N>
+// With CHEB the four fields (S Q y, S^2 Q y) are not stored: they complete the Chebyshev step in
+// place (pair 0 updates r, d, x; pair 1 updates u, y; the arithmetic of cheb_step).
+template <typename T, int N, bool CHEB>
 __global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_inv(const cplx<T>* __restrict__ S, int nspec,
                                                                    OutFields<T> out, int n1,
-                                                                   const cplx<T>* __restrict__ roots) {
+                                                                   const cplx<T>* __restrict__ roots,
+                                                                   ChebTail<T> ct) {
   using PL = WPlan<N>;
   using RW = FRow<T, N>;
   constexpr int R = RW::R, nh = N / 2 + 1;
@@ -660,6 +663,50 @@ __global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_inv(const cplx<
   wave_sync();
   wave_fft<T, N, +1, false, false>(x, reg, rt, lp);
   const size_t gb = size_t(r0 + row) * N;
+  if constexpr (CHEB) {
+    const T c1 = T(ct.c1[z]), c2 = T(ct.c2[z]);
+    const size_t F = size_t(n1) * N;
+    const size_t ib = size_t(z) * 2 * F + gb;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const size_t o = ib + c * F;
+      if (blockIdx.y == 0) {
+        T rv[PL::E], dv[PL::E], xv[PL::E];
+#pragma unroll
+        for (int m = 0; m < PL::E; ++m) {
+          const int e = wmap<N, rL>(lp, m);
+          rv[m] = ct.r[o + e];
+          dv[m] = ct.d[o + e];
+          xv[m] = ct.x[o + e];
+        }
+#pragma unroll
+        for (int m = 0; m < PL::E; ++m) {
+          const int e = wmap<N, rL>(lp, m);
+          const T r = rv[m] - (dv[m] + (c ? x[m].y : x[m].x));
+          const T d = c1 * dv[m] + c2 * r;
+          ct.r[o + e] = r;
+          ct.d[o + e] = d;
+          ct.x[o + e] = xv[m] + d;
+        }
+      } else {
+        T uv[PL::E], yv[PL::E];
+#pragma unroll
+        for (int m = 0; m < PL::E; ++m) {
+          const int e = wmap<N, rL>(lp, m);
+          uv[m] = ct.u[o + e];
+          yv[m] = ct.y[o + e];
+        }
+#pragma unroll
+        for (int m = 0; m < PL::E; ++m) {
+          const int e = wmap<N, rL>(lp, m);
+          const T u = uv[m] - (yv[m] + (c ? x[m].y : x[m].x));
+          ct.u[o + e] = u;
+          ct.y[o + e] = c1 * yv[m] + c2 * u;
+        }
+      }
+    }
+    return;
+  }
   T* OA = out.p[fa] + z * out.bstride[fa] + gb;
   T* OB = hasb ? out.p[fb] + z * out.bstride[fb] + gb : nullptr;
   const T* AA = out.add[fa] ? out.add[fa] + z * out.bstride[fa] + gb : nullptr;
@@ -1120,15 +1167,15 @@ hipError_t launch_frow_fwd_n(hipStream_t s, const SpecGrid<T>& g, RealFields<T> 
   return hipGetLastError();
 }
 
-template <typename T, int N>
+template <typename T, int N, bool CHEB = false>
 hipError_t launch_frow_inv_n(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* S, int nspec, OutFields<T> out,
-                             int batch) {
+                             int batch, ChebTail<T> ct = {}) {
   using RW = FRow<T, N>;
   static std::atomic<size_t> allowed{0};
-  RET_IF(allow_lds(k_frow_inv<T, N>, RW::kLds, allowed));
+  RET_IF(allow_lds(k_frow_inv<T, N, CHEB>, RW::kLds, allowed));
   dim3 grid(g.n1 / RW::R, (out.count + 1) / 2, batch);
-  hipLaunchKernelGGL((k_frow_inv<T, N>), grid, dim3(RW::kThreads), RW::kLds, s, S, nspec, out, g.n1,
-                     static_cast<const cplx<T>*>(g.row.roots));
+  hipLaunchKernelGGL((k_frow_inv<T, N, CHEB>), grid, dim3(RW::kThreads), RW::kLds, s, S, nspec, out, g.n1,
+                     static_cast<const cplx<T>*>(g.row.roots), ct);
   return hipGetLastError();
 }
 
@@ -1302,6 +1349,34 @@ hipError_t spec_scale2(hipStream_t s, const SpecGrid<T>& g, int batch, const int
   return row_inv<T>(fast, s, g, S2, 4, rout, batch);
 }
 
+template <typename T>
+bool spec_fast(const SpecGrid<T>& g) {
+  return fast_grid(g);
+}
+
+template <typename T>
+hipError_t spec_scale2_cheb(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, SymbolParams sym1,
+                            SymbolParams sym2, const T* in, ChebTail<T> ct, cplx<T>* S1, cplx<T>* S2) {
+  if (!fast_grid(g)) return hipErrorNotSupported;
+  RealFields<T> rin{};
+  set_fields(rin, 2, const_cast<T*>(in), g.field(), active);
+  RET_IF(row_fwd<T>(true, s, g, rin, batch, S1));
+  OpScale2<T> op{sym1, sym2, g.n1, g.n2, 1.0 / double(g.field())};
+  RET_IF(col<0>(true, s, g, S1, S2, op, batch, active));
+  OutFields<T> rout{};
+  rout.count = 4;
+  rout.active = active;
+  rout.item_div = 1;
+  switch (g.n2) {
+#define X(N) \
+  case N:    \
+    return launch_frow_inv_n<T, N, true>(s, g, S2, 4, rout, batch, ct);
+    SLNK_FAST_CASES(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
 // The fine and the coarse passes of a restriction or prolongation share the coarse k-space buffer
 // (and the kept fine spectrum), so both grids take the same kind of pass.
 template <typename T>
@@ -1358,6 +1433,9 @@ hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecG
   template hipError_t spec_grad<T>(hipStream_t, const SpecGrid<T>&, int, const T*, T*, cplx<T>*, cplx<T>*);     \
   template hipError_t spec_scale2<T>(hipStream_t, const SpecGrid<T>&, int, const int*, SymbolParams, SymbolParams, \
                                      const T*, T*, T*, cplx<T>*, cplx<T>*);                                     \
+  template bool spec_fast<T>(const SpecGrid<T>&);                                                                \
+  template hipError_t spec_scale2_cheb<T>(hipStream_t, const SpecGrid<T>&, int, const int*, SymbolParams,       \
+                                          SymbolParams, const T*, ChebTail<T>, cplx<T>*, cplx<T>*);             \
   template hipError_t spec_trace_prep<T>(hipStream_t, const SpecGrid<T>&, int, const int*, const T*, T*, T*, T*, \
                                          cplx<T>*, cplx<T>*);                                                   \
   template hipError_t spec_restrict<T>(hipStream_t, const SpecGrid<T>&, const SpecGrid<T>&, int, const int*, int, \
