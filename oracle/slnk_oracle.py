@@ -24,7 +24,7 @@ Conventions (stated once, used everywhere below)
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -34,7 +34,7 @@ __all__ = [
     "spline_coefficients", "bspline_weights", "interpolate",
     "trace", "adjoint_factor", "solve_state", "transport_state", "solve_adjoint",
     "trapezoid_weights", "linearize", "objective", "gradient",
-    "incremental_state", "gn_transport_part", "hessian_matvec",
+    "incremental_state", "gn_transport_part", "fn_transport_part", "transport_part", "hessian_matvec",
     "prec_reg", "split_scale", "lowpass", "restrict", "prolong",
     "split_matvec", "chebyshev", "lanczos_max", "splitmix64", "splitmix64_uniform",
     "TwoLevel", "setup_two_level", "apply_two_level",
@@ -79,11 +79,14 @@ class Params:
     reg: 1, 2, 3 for the H1, H2, H3 seminorm (eq. e:varopt:regv).
     proj: 0 for the compressible case (K = identity), 1 for the Leray
           projection (the incompressible case, w = 0).
+    hessian: "gn" for the Gauss--Newton matvec, "fn" for the full-Newton one
+          (eq. e:hessian-matvec with every lambda term kept).
     """
     nt: int
     beta: float
     reg: int = 2
     proj: int = 0
+    hessian: str = "gn"
 
 
 # ---------------------------------------------------------------------------
@@ -344,10 +347,49 @@ def gn_transport_part(lin: Linearization, vt):
     return apply_proj(g, bt, p.proj)
 
 
-def hessian_matvec(lin: Linearization, vt):
-    """GN reduced Hessian matvec H vt = beta A vt + Q[vt] (eq. e:hessian-matvec)."""
+def fn_transport_part(lin: Linearization, vt):
+    """Q[vt] = K int_0^1 (lam~ grad m + lam grad m~) dt of the full-Newton matvec
+    (eqs. e:hessian-matvec, e:inc-adj-slm; table t:computational-complexity-theoretical, FN rows).
+
+    The incremental adjoint keeps its source: -d_t lam~ - v.grad lam~ - lam~ div v
+    = div(lam vt), i.e. along the adjoint characteristic (dX/ds = -v, s = 1 - t)
+    d(lam~)/ds = lam~ div v + sigma with sigma = div(lam vt) known on every time
+    level.  Heun's step from the departure point (value y_D, source sigma_D) to
+    the node (div v = d_x, source sigma_x) gives
+    gamma y_D + ht/2 (1 + ht d_x) sigma_D + ht/2 sigma_x, so
+    lam~^{j-1} = gamma I[lam~^j](X_a) + ht/2 (1 + ht div v) I[sigma^j](X_a) + ht/2 sigma^{j-1}
+    from lam~^nt = -m~^nt.  lam^j is the adjoint of the linearisation point
+    (computed here when the gradient has not been evaluated yet).
+    """
     L = lin.level
-    return L.prm.beta * apply_reg(L.grid, vt, L.prm.reg) + gn_transport_part(lin, vt)
+    g, p = L.grid, L.prm
+    ht = 1.0 / p.nt
+    if lin.lam is None:
+        gradient(lin)
+    mt = incremental_state(lin, vt)
+    sigma = [fft_div(g, lam_j * vt) for lam_j in lin.lam]
+    dx = fft_div(g, lin.v)
+    lt = [None] * (p.nt + 1)
+    lt[p.nt] = -mt[-1]
+    for j in range(p.nt, 0, -1):
+        lt[j - 1] = (lin.gamma * interpolate(g, lt[j], lin.Xa)
+                     + 0.5 * ht * (1.0 + ht * dx) * interpolate(g, sigma[j], lin.Xa)
+                     + 0.5 * ht * sigma[j - 1])
+    w = trapezoid_weights(p.nt)
+    bt = sum(w[j] * (lt[j] * lin.gradm[j] + lin.lam[j] * fft_grad(g, mt[j])) for j in range(p.nt + 1))
+    return apply_proj(g, bt, p.proj)
+
+
+def transport_part(lin: Linearization, vt):
+    """Q[vt] of the matvec the parameters select (Gauss--Newton or full Newton)."""
+    return fn_transport_part(lin, vt) if lin.level.prm.hessian == "fn" else gn_transport_part(lin, vt)
+
+
+def hessian_matvec(lin: Linearization, vt):
+    """Reduced Hessian matvec H vt = beta A vt + Q[vt] (eq. e:hessian-matvec), GN unless
+    the level's parameters ask for the full-Newton form."""
+    L = lin.level
+    return L.prm.beta * apply_reg(L.grid, vt, L.prm.reg) + transport_part(lin, vt)
 
 
 # ---------------------------------------------------------------------------
@@ -408,11 +450,11 @@ def prolong(fine: Grid, coarse: Grid, uc):
 
 
 def split_matvec(lin: Linearization, s):
-    """M s = s + S Q S s: the split spectrally preconditioned GN Hessian (section 3.4.2)."""
+    """M s = s + S Q S s: the split spectrally preconditioned Hessian (section 3.4.2)."""
     L = lin.level
     g, p = L.grid, L.prm
     w = split_scale(g, s, p.beta, p.reg)
-    return s + split_scale(g, gn_transport_part(lin, w), p.beta, p.reg)
+    return s + split_scale(g, transport_part(lin, w), p.beta, p.reg)
 
 
 def chebyshev(op, b, emin: float, emax: float, k: int):
@@ -497,14 +539,17 @@ class TwoLevel:
 def setup_two_level(L: Level, cheb_iters=10, lanczos_steps=30, safety=1.05, seed=0x5EED):
     """Coarse problem and Chebyshev bounds (section 3.4.2, "Nested Preconditioner").
 
-    The coarse problem restricts m_T and m_R spectrally and keeps nt and beta.
+    The coarse problem restricts m_T and m_R spectrally and keeps nt and beta;
+    its operator is the Gauss--Newton one also when the fine solve uses the
+    full-Newton matvec (the Chebyshev iteration needs a positive definite
+    operator, which the full-Newton Hessian need not be away from the minimiser).
     e_max is the largest Ritz value of Lanczos on the coarse split operator at
     v = 0 (times a safety factor), computed once per solve; e_min is the
     analytic estimate min(1 + 1/(beta a'(k))) over the coarse modes.
     """
     fg = L.grid
     cg = fg.coarse()
-    Lc = Level(cg, restrict(fg, cg, L.mT), restrict(fg, cg, L.mR), L.prm)
+    Lc = Level(cg, restrict(fg, cg, L.mT), restrict(fg, cg, L.mR), replace(L.prm, hessian="gn"))
     lin0 = linearize(Lc, np.zeros((2,) + cg.shape))
     q0 = splitmix64_uniform(seed, 2 * cg.N).reshape((2,) + cg.shape)
     emax = safety * lanczos_max(lambda s: split_matvec(lin0, s), q0, lanczos_steps)

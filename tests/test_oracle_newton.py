@@ -107,3 +107,17 @@ def test_two_level_needs_fewer_pcg_iterations_at_small_beta():
                           lambda r: O.apply_two_level(L, tl, r), 1e-6, 500)
     assert st1 == "ok" and st2 == "ok"
     assert it_2l < it_reg
+
+
+@pytest.mark.parametrize("pc", ["reg", "2l"])
+def test_full_newton_converges_superlinearly(pc):
+    """With the full-Newton matvec the last Newton step contracts the gradient by more than
+    two orders of magnitude (quadratic convergence near the minimiser), reaching
+    ||g||rel <= 1e-5 within five iterations, where Gauss--Newton contracts linearly."""
+    from dataclasses import replace
+    L, _ = _smooth_level(n=64, nt=4, beta=1e-2, reg=1)
+    Lfn = O.Level(L.grid, L.mT, L.mR, replace(L.prm, hessian="fn"))
+    _, rep = O.newton_solve(Lfn, pc=pc, gtol_rel=1e-5, max_newton=8)
+    assert rep["status"] == "ok" and rep["grel"][-1] <= 1e-5 and rep["newton_iters"] <= 5, rep["grel"]
+    assert rep["grel"][-1] < 1e-2 * rep["grel"][-2]
+    assert all(np.diff(rep["J"]) < 0)
