@@ -60,6 +60,7 @@ typedef enum {
 typedef enum { SLNK_REG_H1 = 1, SLNK_REG_H2 = 2, SLNK_REG_H3 = 3 } slnk_reg;
 typedef enum { SLNK_PREC_FP64 = 0, SLNK_PREC_MIXED = 1 } slnk_prec;
 typedef enum { SLNK_PC_REG = 1, SLNK_PC_2L = 2 } slnk_pc;
+typedef enum { SLNK_HESS_GN = 0, SLNK_HESS_FN = 1 } slnk_hessian;
 
 /* Problem and solver parameters (section 3.5 lists the paper's settings).
  *   nt            number of SL time steps on [0, 1] (ht = 1/nt), >= 1
@@ -79,6 +80,12 @@ typedef enum { SLNK_PC_REG = 1, SLNK_PC_2L = 2 } slnk_pc;
  *                 displacement halo fits in LDS, else coefficient pass + global gather;
  *                 1 = always the coefficient pass + global gather (a tuning choice: both give the
  *                 same interpolant up to rounding)
+ *   hessian       SLNK_HESS_GN (default): the Gauss--Newton matvec, which drops every lambda term of
+ *                 eq. e:hessian-matvec; SLNK_HESS_FN: the full-Newton matvec, whose incremental
+ *                 adjoint carries the source div(lambda vt) (eq. e:inc-adj-slm) and whose b~ adds
+ *                 lambda grad m~ (table t:computational-complexity-theoretical, FN rows).  FN keeps
+ *                 lambda^0..lambda^nt of the last gradient, (6 nt + 5) more fields per item; the
+ *                 coarse operator of P_2L stays Gauss--Newton (Chebyshev needs it positive definite)
  * The compressible case (projection K = identity) is the one implemented. */
 typedef struct {
   int n1, n2, nt;
@@ -93,6 +100,7 @@ typedef struct {
   int use_graphs;
   int batch;
   int sl_path;
+  int hessian;
 } slnk_params;
 
 /* Newton--Krylov options (sections 3.4.1, 3.5).  Stop when ||g||_inf / ||g_0||_inf <= gtol_rel or
@@ -166,8 +174,9 @@ slnk_status slnk_objective(slnk_ctx* ctx, const void* v, double* J);
 slnk_status slnk_gradient(slnk_ctx* ctx, const void* v, void* g, double* J);
 
 /* Hvt = beta A vt + int_0^1 lambda~ grad m dt, the Gauss--Newton matvec (eqs. e:hessian-matvec,
- * e:inc-state-slm, e:inc-adj-slm) at the last linearisation point.  EINVAL before any
- * slnk_gradient. */
+ * e:inc-state-slm, e:inc-adj-slm) at the last linearisation point; with hessian = SLNK_HESS_FN
+ * the full-Newton matvec beta A vt + int_0^1 (lambda~ grad m + lambda grad m~) dt.  EINVAL before
+ * any slnk_gradient. */
 slnk_status slnk_hessian_matvec(slnk_ctx* ctx, const void* vt, void* Hvt);
 
 /* out = (I + S Q S) s, the split spectrally preconditioned GN Hessian (section 3.4.2) at the

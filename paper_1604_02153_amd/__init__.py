@@ -21,6 +21,7 @@ STATUS = {0: "SLNK_OK", 1: "SLNK_EINVAL", 2: "SLNK_ENOMEM", 3: "SLNK_EDEVICE", 4
 REG = {"h1": 1, "h2": 2, "h3": 3}
 PREC = {"fp64": 0, "mixed": 1}
 PC = {"reg": 1, "2l": 2}
+HESSIAN = {"gn": 0, "fn": 1}
 REPORT_MAX = 64
 
 
@@ -29,7 +30,7 @@ class Params(ctypes.Structure):
                 ("beta", ctypes.c_double), ("prec", ctypes.c_int), ("pc", ctypes.c_int),
                 ("cheb_iters", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
                 ("emax_safety", ctypes.c_double), ("lanczos_seed", ctypes.c_ulonglong), ("use_graphs", ctypes.c_int),
-                ("batch", ctypes.c_int), ("sl_path", ctypes.c_int)]
+                ("batch", ctypes.c_int), ("sl_path", ctypes.c_int), ("hessian", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -151,7 +152,7 @@ class Context:
 
     def __init__(self, n1, n2, nt, reg="h2", beta=1e-3, prec="mixed", pc="2l", cheb_iters=10,
                  lanczos_steps=30, emax_safety=1.05, lanczos_seed=0x5EED, use_graphs=True, stream=None,
-                 batch=1, sl_path=0):
+                 batch=1, sl_path=0, hessian="gn"):
         import torch
         lib = load_library()
         p = Params()
@@ -166,6 +167,7 @@ class Context:
         p.use_graphs = 1 if use_graphs else 0
         p.batch = int(batch)
         p.sl_path = int(sl_path)
+        p.hessian = HESSIAN[hessian] if isinstance(hessian, str) else int(hessian)
         self.batch = p.batch
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -300,7 +302,7 @@ class BatchContext:
     list of (n1, n2) per pair; every per-pair argument is a list of tensors (pair order)."""
 
     def __init__(self, sizes, nt, reg="h2", beta=1e-3, prec="mixed", pc="2l", cheb_iters=10, lanczos_steps=30,
-                 emax_safety=1.05, lanczos_seed=0x5EED, use_graphs=True, sl_path=0, stream=None):
+                 emax_safety=1.05, lanczos_seed=0x5EED, use_graphs=True, sl_path=0, stream=None, hessian="gn"):
         import torch
         lib = load_library()
         p = Params()
@@ -313,6 +315,7 @@ class BatchContext:
         p.cheb_iters, p.lanczos_steps = int(cheb_iters), int(lanczos_steps)
         p.emax_safety, p.lanczos_seed = float(emax_safety), int(lanczos_seed)
         p.use_graphs, p.sl_path = (1 if use_graphs else 0), int(sl_path)
+        p.hessian = HESSIAN[hessian] if isinstance(hessian, str) else int(hessian)
         self.sizes = [(int(a), int(b)) for a, b in sizes]
         self.npairs = len(self.sizes)
         n1 = (ctypes.c_int * self.npairs)(*[a for a, _ in self.sizes])

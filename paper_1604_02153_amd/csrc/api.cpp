@@ -193,6 +193,16 @@ struct Context {
   bool two_level = false;
   bool images_set = false;
   bool has_grad = false;
+  // full-Newton matvec (fine level only; the coarse operator of P_2L stays Gauss--Newton)
+  bool full_newton = false;
+  struct {
+    T* lam = nullptr;    // (nt+1) F per item: lambda^0..lambda^nt of the slot-0 linearisation
+    T* mt = nullptr;     // nt F: m~^1..m~^nt
+    T* x2 = nullptr;     // 2 (nt+1) F: lambda^j vt, later grad m~^j
+    T* sigma = nullptr;  // (nt+1) F: div(lambda^j vt)
+    T* e = nullptr;      // nt F: I[sigma^j](X_a), then the source of incremental adjoint step j
+    T* divv = nullptr;   // F: div v of the slot-0 linearisation
+  } fn;
   std::vector<double> emin, emax;
   double* partial = nullptr;  // reduction partials (two independent halves)
   size_t partial_half = 0;
@@ -341,6 +351,9 @@ struct Context {
     if (!(p.beta > 0)) throw Fail{SLNK_EINVAL, "beta must be positive"};
     if (p.pc != SLNK_PC_REG && p.pc != SLNK_PC_2L) throw Fail{SLNK_EINVAL, "pc must be SLNK_PC_REG or SLNK_PC_2L"};
     if (p.sl_path != 0 && p.sl_path != 1) throw Fail{SLNK_EINVAL, "sl_path must be 0 or 1"};
+    if (p.hessian != SLNK_HESS_GN && p.hessian != SLNK_HESS_FN)
+      throw Fail{SLNK_EINVAL, "hessian must be SLNK_HESS_GN or SLNK_HESS_FN"};
+    full_newton = p.hessian == SLNK_HESS_FN;
     two_level = p.pc == SLNK_PC_2L;
     if (two_level) {
       if (!fft_size_ok(p.n1 / 2) || !fft_size_ok(p.n2 / 2)) throw Fail{SLNK_EINVAL, "coarse grid n/2 not supported"};
@@ -362,6 +375,7 @@ struct Context {
     bytes += B * (4 * 2 * F * sizeof(double) + 2 * 2 * size_t(p.n1) * spec_stride(p.n2) * sizeof(cplx<double>)) +
              2 * (p.n1 + p.n2) * sizeof(cplx<double>) + 16 * 256;
     bytes += B * (2 * F * sizeof(T) + sizeof(float)) + 2 * 256;
+    if (full_newton) bytes += B * size_t(6 * p.nt + 5) * F * sizeof(T) + 6 * 256;
     void* base = nullptr;
     if (hipMalloc(&base, bytes) != hipSuccess) throw Fail{SLNK_ENOMEM, "hipMalloc of the workspace failed"};
     arena.base = static_cast<char*>(base);
@@ -378,6 +392,14 @@ struct Context {
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hsc), 16 * B * sizeof(double), hipHostMallocDefault));
     alloc_level(fine, p.n1, p.n2, p.nt);
     if (two_level) alloc_level(coarse, p.n1 / 2, p.n2 / 2, p.nt);
+    if (full_newton) {
+      fn.lam = arena.take<T>(B * (p.nt + 1) * F);
+      fn.mt = arena.take<T>(B * p.nt * F);
+      fn.x2 = arena.take<T>(B * 2 * (p.nt + 1) * F);
+      fn.sigma = arena.take<T>(B * (p.nt + 1) * F);
+      fn.e = arena.take<T>(B * p.nt * F);
+      fn.divv = arena.take<T>(B * F);
+    }
     sg64.n1 = p.n1;
     sg64.n2 = p.n2;
     plan<double>(sg64.row, p.n2, tw64_row);
@@ -587,6 +609,13 @@ struct Context {
     const size_t F = lv.F;
     const int nt = lv.nt;
     int nb = 0;
+    // the full-Newton matvec needs every adjoint time level (and div v) of this linearisation
+    const bool keep = full_newton && &lv == &fine;
+    if (keep) {
+      HIPCHK(sub_strided<T>(stream, B, F, lv.mR, (long long)F, L.m + nt * F, (long long)((nt + 1) * F),
+                            fn.lam + nt * F, (long long)((nt + 1) * F)));
+      HIPCHK(spec_div<T>(stream, lv.sg, B, L.v, fn.divv, lv.S1, lv.S2));
+    }
     for (int j = nt; j >= 1; --j) {
       StepArgs<T> a = step_base(lv, 0, mk, false);
       a.first = j == nt;
@@ -599,6 +628,11 @@ struct Context {
       a.st_aux1 = (long long)((nt + 1) * F);
       a.dst = lv.lam + ((j - 1) % 2) * F;
       a.st_dst = (long long)(2 * F);
+      if (keep) {
+        a.src = a.first ? nullptr : fn.lam + j * F;
+        a.dst = fn.lam + (j - 1) * F;
+        a.st_src = a.st_dst = (long long)((nt + 1) * F);
+      }
       a.d1 = L.da;
       a.st_d = (long long)(2 * F);
       a.gamma = L.gamma;
@@ -675,16 +709,92 @@ struct Context {
     }
   }
 
+  // bt = Q[vt] of the full-Newton matvec at slot 0 of the fine level, items of mk:
+  // K int_0^1 (lam~ grad m + lam grad m~) dt, the incremental adjoint carrying the source
+  // sigma = div(lam vt) by Heun's step along the adjoint characteristic:
+  //   lam~^{j-1} = gamma I[lam~^j](X_a) + ht/2 (1 + ht div v) I[sigma^j](X_a) + ht/2 sigma^{j-1}
+  // (eqs. e:hessian-matvec, e:inc-adj-slm).  Needs the adjoint levels kept by gradient().
+  void fn_transport(Level<T>& lv, const T* vt, const int* mk) {
+    auto& L = lv.lin[0];
+    ensure_gm(lv);
+    const size_t F = lv.F;
+    const int nt = lv.nt;
+    const double ht = 1.0 / nt;
+    int nb = 0;
+    HIPCHK(fn_products<T>(stream, B, F, nt, fn.lam, vt, fn.x2));
+    HIPCHK(spec_div<T>(stream, lv.sg, B * (nt + 1), fn.x2, fn.sigma, lv.S1, lv.S2));
+    for (int j = 1; j <= nt; ++j) {  // I[sigma^j](X_a)
+      StepArgs<T> a = step_base(lv, 0, mk, capturing);
+      a.src = fn.sigma + j * F;
+      a.st_src = (long long)((nt + 1) * F);
+      a.dst = fn.e + (j - 1) * F;
+      a.st_dst = (long long)(nt * F);
+      a.d1 = L.da;
+      a.st_d = (long long)(2 * F);
+      HIPCHK(sl_step<T>(stream, StepKind::State, a, &nb));
+    }
+    HIPCHK(fn_source<T>(stream, B, F, nt, ht, fn.divv, fn.sigma, fn.e));
+    for (int j = 1; j <= nt; ++j) {  // incremental state, forward, keeping m~^j
+      StepArgs<T> a = step_base(lv, 0, mk, capturing);
+      a.first = j == 1;
+      a.last = j == nt;
+      a.src = a.first ? nullptr : lv.q + ((j - 1) % 2) * F;
+      a.dst = lv.q + (j % 2) * F;
+      a.st_src = a.st_dst = (long long)(2 * F);
+      a.d1 = L.df;
+      a.st_d = (long long)(2 * F);
+      a.vt = vt;
+      a.st_vt = (long long)(2 * F);
+      a.gm_old = L.gm;
+      a.gm_new = L.gm + 2 * j * F;
+      a.st_gm = (long long)(2 * (nt + 1) * F);
+      a.w_new = trapezoid_weight(nt, nt);
+      a.acc = lv.bt;
+      a.st_acc = (long long)(2 * F);
+      a.out2 = fn.mt + (j - 1) * F;
+      a.st_out2 = (long long)(nt * F);
+      HIPCHK(sl_step<T>(stream, StepKind::IncState, a, &nb));
+    }
+    HIPCHK(spec_grad<T>(stream, lv.sg, B * nt, fn.mt, fn.x2, lv.S1, lv.S2));
+    for (int j = nt; j >= 1; --j) {  // incremental adjoint, backward, with its source
+      StepArgs<T> a = step_base(lv, 0, mk, capturing);
+      a.src = lv.q + (j % 2) * F;
+      a.dst = j > 1 ? lv.q + ((j - 1) % 2) * F : nullptr;
+      a.st_src = a.st_dst = (long long)(2 * F);
+      a.d1 = L.da;
+      a.st_d = (long long)(2 * F);
+      a.gamma = L.gamma;
+      a.st_gamma = (long long)F;
+      a.gm_new = L.gm + 2 * (j - 1) * F;
+      a.st_gm = (long long)(2 * (nt + 1) * F);
+      a.w_new = trapezoid_weight(j - 1, nt);
+      a.acc = lv.bt;
+      a.st_acc = (long long)(2 * F);
+      a.addf = fn.e + (j - 1) * F;
+      a.st_addf = (long long)(nt * F);
+      HIPCHK(sl_step<T>(stream, StepKind::IncAdjoint, a, &nb));
+    }
+    HIPCHK(fn_accumulate<T>(stream, B, F, nt, ht, fn.lam, fn.x2, lv.bt, mk));
+  }
+
+  // the transport part of the fine matvec the parameters select; the coarse level is always GN
+  void transport(Level<T>& lv, const T* vt, const int* mk) {
+    if (full_newton && &lv == &fine)
+      fn_transport(lv, vt, mk);
+    else
+      gn_transport(lv, vt, mk);
+  }
+
   // out = beta A vt + Q vt
   void hessian(Level<T>& lv, const T* vt, T* out, const int* mk) {
-    gn_transport(lv, vt, mk);
+    transport(lv, vt, mk);
     HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, sym(Symbol::Reg), 2, vt, out, lv.bt, lv.S1, lv.S2));
   }
 
   // out = s + S Q S s
   void split_matvec(Level<T>& lv, const T* s, T* out, const int* mk) {
     HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, sym(Symbol::RegInvSqrt), 2, s, lv.w, nullptr, lv.S1, lv.S2));
-    gn_transport(lv, lv.w, mk);
+    transport(lv, lv.w, mk);
     HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, sym(Symbol::RegInvSqrt), 2, lv.bt, out, s, lv.S1, lv.S2));
   }
 

@@ -177,6 +177,65 @@ __global__ void k_cast(size_t n, const TI* __restrict__ x, TO* __restrict__ y) {
     y[i] = TO(x[i]);
 }
 
+// ---- full-Newton matvec helpers (one element per thread; grid y = item, grid z = time level)
+// prod[z][j][c] = lam[z][j] * vt[z][c]   (j = 0..nt, c = 0, 1)
+template <typename T>
+__global__ void k_fn_products(size_t F, int nt1, const T* __restrict__ lam, const T* __restrict__ vt,
+                              T* __restrict__ prod) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= F) return;
+  const int z = blockIdx.y, j = blockIdx.z;
+  const T l = lam[(size_t(z) * nt1 + j) * F + i];
+  const T v1 = vt[size_t(z) * 2 * F + i], v2 = vt[size_t(z) * 2 * F + F + i];
+  T* o = prod + (size_t(z) * nt1 + j) * 2 * F;
+  o[i] = l * v1;
+  o[F + i] = l * v2;
+}
+
+// e[z][j-1] = ht/2 (1 + ht divv[z]) e[z][j-1] + ht/2 sigma[z][j-1]   (j = 1..nt; e holds
+// I[sigma^j](X_a) on entry)
+template <typename T>
+__global__ void k_fn_source(size_t F, int nt, double ht, const T* __restrict__ divv, const T* __restrict__ sigma,
+                            T* __restrict__ e) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= F) return;
+  const int z = blockIdx.y, j = blockIdx.z;  // level j - 1
+  const T h = T(0.5 * ht);
+  const T d = divv[size_t(z) * F + i];
+  const size_t o = (size_t(z) * nt + j) * F + i;
+  e[o] = h * (T(1) + T(ht) * d) * e[o] + h * sigma[(size_t(z) * (nt + 1) + j) * F + i];
+}
+
+// bt[z][c] += sum_{j=1..nt} w_j lam[z][j] gmt[z][j-1][c]  (trapezoid weights of t^1..t^nt)
+template <typename T>
+__global__ void k_fn_accumulate(size_t F, int nt, double ht, const T* __restrict__ lam, const T* __restrict__ gmt,
+                                T* __restrict__ bt, const int* mask) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int z = blockIdx.y;
+  if (i >= F || (mask && !mask[z])) return;
+  T a1 = T(0), a2 = T(0);
+  for (int j = 1; j <= nt; ++j) {
+    const T w = T(j == nt ? 0.5 * ht : ht);
+    const T l = w * lam[(size_t(z) * (nt + 1) + j) * F + i];
+    const T* g = gmt + (size_t(z) * nt + (j - 1)) * 2 * F;
+    a1 += l * g[i];
+    a2 += l * g[F + i];
+  }
+  T* b = bt + size_t(z) * 2 * F;
+  b[i] += a1;
+  b[F + i] += a2;
+}
+
+// out[z] = x[z] - y[z] over n elements, items at strides sx, sy, so
+template <typename T>
+__global__ void k_sub_strided(size_t n, const T* __restrict__ x, long long sx, const T* __restrict__ y, long long sy,
+                              T* __restrict__ out, long long so) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int z = blockIdx.y;
+  out[z * so + i] = x[z * sx + i] - y[z * sy + i];
+}
+
 // Step coefficients of the preconditioned CG iteration kept in device memory (item z's reduction
 // at red[4 z]).  PCG_RZ stores rz[z]; PCG_ALPHA writes c0[z] = rz / pq for running items whose
 // curvature pq is positive and finite, else 0 (the host reads pq with the residual norm and acts
@@ -343,6 +402,36 @@ hipError_t masked_copy(hipStream_t s, int batch, size_t n, const T* src, long lo
   return hipGetLastError();
 }
 
+inline unsigned fn_blocks(size_t F) { return unsigned((F + kThreads - 1) / kThreads); }
+
+template <typename T>
+hipError_t fn_products(hipStream_t s, int batch, size_t F, int nt, const T* lam, const T* vt, T* prod) {
+  hipLaunchKernelGGL(k_fn_products<T>, dim3(fn_blocks(F), batch, nt + 1), dim3(kThreads), 0, s, F, nt + 1, lam, vt,
+                     prod);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fn_source(hipStream_t s, int batch, size_t F, int nt, double ht, const T* divv, const T* sigma, T* e) {
+  hipLaunchKernelGGL(k_fn_source<T>, dim3(fn_blocks(F), batch, nt), dim3(kThreads), 0, s, F, nt, ht, divv, sigma, e);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fn_accumulate(hipStream_t s, int batch, size_t F, int nt, double ht, const T* lam, const T* gmt, T* bt,
+                         const int* mask) {
+  hipLaunchKernelGGL(k_fn_accumulate<T>, dim3(fn_blocks(F), batch), dim3(kThreads), 0, s, F, nt, ht, lam, gmt, bt,
+                     mask);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t sub_strided(hipStream_t s, int batch, size_t n, const T* x, long long sx, const T* y, long long sy, T* out,
+                       long long so) {
+  hipLaunchKernelGGL(k_sub_strided<T>, dim3(fn_blocks(n), batch), dim3(kThreads), 0, s, n, x, sx, y, sy, out, so);
+  return hipGetLastError();
+}
+
 #define INST(T)                                                                                            \
   template hipError_t dot<T>(hipStream_t, int, size_t, const T*, const T*, double*, double*);             \
   template hipError_t dot3<T>(hipStream_t, int, size_t, const T*, const T*, double*, double*);            \
@@ -358,7 +447,13 @@ hipError_t masked_copy(hipStream_t s, int batch, size_t n, const T* src, long lo
   template hipError_t cast_back<T>(hipStream_t, size_t, const T*, double*);                               \
   template hipError_t xpay_mixed<T>(hipStream_t, int, size_t, const double*, double, const double*,       \
                                     const T*, double*, const int*);                                       \
-  template hipError_t masked_copy<T>(hipStream_t, int, size_t, const T*, long long, T*, long long, const int*);
+  template hipError_t masked_copy<T>(hipStream_t, int, size_t, const T*, long long, T*, long long, const int*); \
+  template hipError_t fn_products<T>(hipStream_t, int, size_t, int, const T*, const T*, T*);               \
+  template hipError_t fn_source<T>(hipStream_t, int, size_t, int, double, const T*, const T*, T*);         \
+  template hipError_t fn_accumulate<T>(hipStream_t, int, size_t, int, double, const T*, const T*, T*,      \
+                                       const int*);                                                       \
+  template hipError_t sub_strided<T>(hipStream_t, int, size_t, const T*, long long, const T*, long long, T*, \
+                                     long long);
 INST(float)
 INST(double)
 #undef INST

@@ -73,6 +73,11 @@ template <typename T>
 hipError_t spec_scale2(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, SymbolParams sym1,
                        SymbolParams sym2, const T* in, T* out1, T* out2, cplx<T>* S1, cplx<T>* S2);
 
+// Spectral divergence of 'count' consecutive vector fields w[c] (two fields, stride 2 field()):
+// out[c] = d1 w1 + d2 w2 with stride field().  S1 >= 2 count spec(), S2 >= count spec().
+template <typename T>
+hipError_t spec_div(hipStream_t s, const SpecGrid<T>& g, int count, const T* w, T* out, cplx<T>* S1, cplx<T>* S2);
+
 // Vectors of one Chebyshev step on M = I + S Q S (item stride 2 field(), coefficients per item)
 template <typename T>
 struct ChebTail {
@@ -127,7 +132,7 @@ enum class StepKind : int {
   State = 0,      // dst = I[src](X_f)
   Adjoint = 1,    // dst = gamma I[src](X_a); b (+)= ht w lam grad m
   IncState = 2,   // incremental state (see transport.hip)
-  IncAdjoint = 3, // dst = gamma I[src](X_a); bt += ht w lam~ grad m
+  IncAdjoint = 3, // dst = gamma I[src](X_a) (+ addf: full-Newton source); bt += ht w lam~ grad m
 };
 
 // Arguments of one SL time step of B same-size items (image pairs).  Every pointer addresses item
@@ -153,8 +158,10 @@ struct StepArgs {
   const T* gm_old = nullptr; // 2 fields, grad m at the time level of src (first step only)
   T* acc = nullptr;          // 2 fields accumulator (b or bt)
   const T* vt = nullptr;     // incremental state: direction (2 fields)
-  const T* addf = nullptr;   // adjoint last step: beta A v added to the accumulator (2 fields)
-  T* out2 = nullptr;         // adjoint last step: gradient output (2 fields)
+  const T* addf = nullptr;   // adjoint last step: beta A v added to the accumulator (2 fields);
+                             // incremental adjoint: source term added to gamma I[src] (1 field)
+  T* out2 = nullptr;         // adjoint last step: gradient output (2 fields); incremental
+                             // state: m~^j (1 field, optional)
   T* coef = nullptr;         // one-field scratch: coefficients of the two-kernel (global gather) step
   T* coef2 = nullptr;        // one-field scratch: row-filtered values of that coefficient pass
   int two_pass_coef = 0;     // coefficient pass as rows + columns through coef2 (else one 2-D pass)
@@ -251,6 +258,25 @@ hipError_t masked_copy(hipStream_t s, int batch, size_t n, const T* src, long lo
 enum { PCG_RZ = 0, PCG_ALPHA = 1, PCG_BETA = 2 };
 hipError_t pcg_coef(hipStream_t s, int mode, int batch, const int* mask, const double* red, double* rz, double* c0,
                     double* c1);
+
+// ---- full-Newton matvec (eqs. e:hessian-matvec, e:inc-adj-slm with the lambda terms kept).
+// Per item z: lam [nt+1] fields (adjoint lambda^0..lambda^nt), vt 2 fields.
+// prod[z][j] = lam[z][j] vt[z] (2 fields per level j = 0..nt)
+template <typename T>
+hipError_t fn_products(hipStream_t s, int batch, size_t F, int nt, const T* lam, const T* vt, T* prod);
+// e[z][j-1] <- ht/2 (1 + ht divv[z]) e[z][j-1] + ht/2 sigma[z][j-1], j = 1..nt (e: nt fields per
+// item holding I[sigma^j](X_a) on entry; sigma: nt+1 fields per item)
+template <typename T>
+hipError_t fn_source(hipStream_t s, int batch, size_t F, int nt, double ht, const T* divv, const T* sigma, T* e);
+// bt[z] += sum_{j=1..nt} w_j lam[z][j] gmt[z][j-1] with the trapezoid weights of t^1..t^nt (gmt:
+// nt vector fields per item, the gradients of m~^1..m~^nt); items with mask[z] == 0 untouched
+template <typename T>
+hipError_t fn_accumulate(hipStream_t s, int batch, size_t F, int nt, double ht, const T* lam, const T* gmt, T* bt,
+                         const int* mask);
+// out + z so = (x + z sx) - (y + z sy) over n elements per item
+template <typename T>
+hipError_t sub_strided(hipStream_t s, int batch, size_t n, const T* x, long long sx, const T* y, long long sy, T* out,
+                       long long so);
 
 // p[i] = host_values[i], i < count (kernel arguments, no staging buffer): publishes
 // per-linearisation integers (halos, masks) to device memory read by captured graphs

@@ -950,6 +950,24 @@ struct OpGrad {
 };
 
 template <typename T>
+struct OpDiv {
+  static constexpr int NIN = 2, NOUT = 1, NC = 0;
+  static constexpr bool kPre = false;
+  int n1, n2;
+  double inv_n;
+  __device__ cplx<T> div(int k1, int k2, const cplx<T>* in) const {
+    const T o1 = odd_k<T>(k1, n1), o2 = (2 * k2 == n2) ? T(0) : T(k2);
+    return cscale(cmul_i(cadd(cscale(in[0], o1), cscale(in[1], o2))), T(inv_n));
+  }
+  __device__ void operator()(int k1, int k2, int, int, const cplx<T>* in, cplx<T>* out) const {
+    out[0] = div(k1, k2, in);
+  }
+  __device__ void coef(int, int, T*) const {}
+  __device__ void pre(int, int, int, const cplx<T>*) const {}
+  __device__ cplx<T> out(int, int k1, int k2, int, const cplx<T>* in, const T*) const { return div(k1, k2, in); }
+};
+
+template <typename T>
 struct OpTracePrep {
   static constexpr int NIN = 2, NOUT = 4, NC = 1;  // cv1, cv2, div v, c_div
   static constexpr bool kPre = false;
@@ -1305,6 +1323,23 @@ hipError_t spec_grad(hipStream_t s, const SpecGrid<T>& g, int count, const T* m,
 }
 
 template <typename T>
+hipError_t spec_div(hipStream_t s, const SpecGrid<T>& g, int count, const T* w, T* out, cplx<T>* S1, cplx<T>* S2) {
+  const size_t F = g.field();
+  const bool fast = fast_grid(g);
+  RealFields<T> rin{};
+  set_fields(rin, 2, const_cast<T*>(w), F, nullptr);
+  RET_IF(row_fwd<T>(fast, s, g, rin, count, S1));
+  OpDiv<T> op{g.n1, g.n2, 1.0 / double(F)};
+  RET_IF(col<0>(fast, s, g, S1, S2, op, count));
+  OutFields<T> rout{};
+  rout.count = 1;
+  rout.p[0] = out;
+  rout.bstride[0] = (long long)F;
+  rout.item_div = 1;
+  return row_inv<T>(fast, s, g, S2, 1, rout, count);
+}
+
+template <typename T>
 hipError_t spec_trace_prep(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, const T* v, T* cv,
                            T* divv, T* cdiv, cplx<T>* S1, cplx<T>* S2) {
   const size_t F = g.field();
@@ -1434,6 +1469,7 @@ hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecG
   template hipError_t spec_scale2<T>(hipStream_t, const SpecGrid<T>&, int, const int*, SymbolParams, SymbolParams, \
                                      const T*, T*, T*, cplx<T>*, cplx<T>*);                                     \
   template bool spec_fast<T>(const SpecGrid<T>&);                                                                \
+  template hipError_t spec_div<T>(hipStream_t, const SpecGrid<T>&, int, const T*, T*, cplx<T>*, cplx<T>*);      \
   template hipError_t spec_scale2_cheb<T>(hipStream_t, const SpecGrid<T>&, int, const int*, SymbolParams,       \
                                           SymbolParams, const T*, ChebTail<T>, cplx<T>*, cplx<T>*);             \
   template hipError_t spec_trace_prep<T>(hipStream_t, const SpecGrid<T>&, int, const int*, const T*, T*, T*, T*, \

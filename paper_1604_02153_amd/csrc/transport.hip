@@ -568,6 +568,9 @@ __global__ void __launch_bounds__(256) k_sl_step(StepArgs<T> args) {
     ex1 = a.vt[gi];
     ex2 = a.vt[gi + F];
   }
+  if constexpr (kIncA) {
+    if (a.addf) ex0 = a.addf[gi];  // full-Newton source term of this step
+  }
   if constexpr (kAdj && FIRST) {
     ex0 = a.aux0[gi] - a.aux1[gi];  // lambda(1) at the node
     ac1 = a.gm_old[gi];
@@ -638,16 +641,18 @@ __global__ void __launch_bounds__(256) k_sl_step(StepArgs<T> args) {
       }
     } else if constexpr (kIncS) {
       const T fnew = -(ex1 * gn1 + ex2 * gn2);
+      const T mt = u + T(0.5 * a.ht) * fnew;  // m~^j
+      if (a.out2) a.out2[gi] = mt;             // kept for the full-Newton matvec
       if (!a.last) {
         a.dst[gi] = u + T(a.ht) * fnew;  // q^j = m~^j + (ht/2) f^j
       } else {
-        const T lt = -(u + T(0.5 * a.ht) * fnew);  // lambda~(1) = -m~(1)
+        const T lt = -mt;  // lambda~(1) = -m~(1)
         a.dst[gi] = lt;
         a.acc[gi] = T(a.w_new) * lt * gn1;
         a.acc[gi + F] = T(a.w_new) * lt * gn2;
       }
-    } else {  // IncAdjoint
-      const T lt = gam * u;
+    } else {  // IncAdjoint (ex0: the full-Newton source term, else 0)
+      const T lt = gam * u + ex0;
       if (a.dst) a.dst[gi] = lt;
       a.acc[gi] = ac1 + T(a.w_new) * lt * gn1;
       a.acc[gi + F] = ac2 + T(a.w_new) * lt * gn2;
