@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-pair ragged batch workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned vs plain comparison")
     ap.add_argument("--no-brain", action="store_true", help="skip the 512^2 nt=8 single-pair workload")
+    ap.add_argument("--no-full-newton", action="store_true", help="skip the full-Newton matvec workload")
     ap.add_argument("--learned-pairs", type=int, default=32, help="held-out pairs of the learned vs plain timing")
     ap.add_argument("--batched-matvecs", type=int, default=10, help="timed batched matvec calls (64 pairs each)")
     ap.add_argument("--brain-matvecs", type=int, default=100, help="timed matvecs of the 512^2 workload")
@@ -138,6 +139,67 @@ def matvec_bytes(n1, n2, nt, elem=4):
     prefilter 2, grad m 2, accumulator read + write 4), plus 32 fixed (first sources, two forward
     and two inverse real-FFT passes, the combine)."""
     return (23 * nt + 32) * n1 * n2 * elem
+
+
+def fn_matvec_bytes(n1, n2, nt, elem=4):
+    """Algorithmic HBM bytes of one full-Newton matvec: the GN matvec's (23 nt + 32) fields plus
+    (38 nt + 18): lambda^j vt products 5 (nt + 1), their spectral divergences 9 (nt + 1), the
+    interpolations of sigma^j 6 nt, the Heun sources 4 nt, the kept m~^j nt, their spectral
+    gradients 9 nt, the source reads of the incremental adjoint nt, and lambda grad m~ into b~
+    3 nt + 4."""
+    return (61 * nt + 50) * n1 * n2 * elem
+
+
+def full_newton(args, dev):
+    """gauss256 with the full-Newton matvec: isolated matvec rate and Newton solves to
+    ||g||rel <= 1e-2 and 1e-4 next to the Gauss-Newton solver on the same GPU."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1604_02153_amd import Context
+    cfg = synth.config("gauss256")
+    n1, n2, nt = cfg["n1"], cfg["n2"], cfg["nt"]
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=torch.float32)
+    mT, vgen, vt = f32(cfg["mT"]), f32(cfg["v_gen"]), f32(cfg["vt"])
+    out = {"workload": "gauss256 (256x256, nt=4, H2 beta=1e-3, P_2L mixed) with hessian = full Newton; "
+                       "the coarse operator of P_2L stays Gauss-Newton"}
+    for hess in ("gn", "fn"):
+        ctx = Context(n1, n2, nt, reg="h2", beta=cfg["beta"], prec="mixed", pc="2l", hessian=hess)
+        mR = torch.empty_like(mT)
+        ctx.transport_state(vgen, mT, mR)
+        ctx.set_images(mR, mT)
+        v = torch.zeros_like(vgen)
+        res = {}
+        for gtol in (1e-2, 1e-4):
+            v.zero_()
+            ctx.newton_solve(v, gtol_rel=gtol, max_newton=20)  # warm-up (graph capture)
+            v.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = ctx.newton_solve(v, gtol_rel=gtol, max_newton=20)
+            torch.cuda.synchronize()
+            res[f"solve_to_{gtol:g}"] = {"ms": round(1e3 * (time.perf_counter() - t0), 2), "status": rep["status"],
+                                          "newton_iters": rep["newton_iters"], "pcg_iters": rep["pcg_iters"],
+                                          "grel": [float(f"{x:.3g}") for x in rep["grel"]]}
+        if hess == "fn":
+            g = torch.empty_like(v)
+            ctx.gradient(0.6 * vgen, g)
+            h = torch.empty_like(v)
+            for _ in range(10):
+                ctx.hessian_matvec(vt, h)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.matvecs // 2):
+                ctx.hessian_matvec(vt, h)
+            torch.cuda.synchronize()
+            rate = (args.matvecs // 2) / (time.perf_counter() - t1)
+            gbs = fn_matvec_bytes(n1, n2, nt) * rate / 1e9
+            res.update({"isolated_matvecs_per_s": round(rate, 1), "matvec_GBps_algorithmic": round(gbs, 1),
+                        "matvec_roofline_frac": round(gbs / HBM_PEAK_GBS, 4)})
+        out["gauss_newton" if hess == "gn" else "full_newton"] = res
+        ctx.close()
+    return out
 
 
 def batched(args, dev):
@@ -471,6 +533,9 @@ def main():
     if not args.no_brain:
         line["brain512"] = brain512(args, dev)
         log("512^2 workload done")
+    if not args.no_full_newton:
+        line["full_newton"] = full_newton(args, dev)
+        log("full-Newton workload done")
     if not args.no_batched:
         line["batched"] = batched(args, dev)
         log("batched workload done")
