@@ -247,3 +247,40 @@ def test_full_newton_hessian_symmetric_up_to_discretisation():
         b = O.inner_l2(g, O.hessian_matvec(lin, w1), w2)
         sym.append(abs(a - b) / abs(a))
     assert sym[0] / sym[1] > 3.0 and sym[1] / sym[2] > 3.0 and sym[2] < 2e-3, sym
+
+
+def test_leray_products_equal_compressible_ones_on_divergence_free_directions():
+    """K is self-adjoint and fixes divergence-free fields, so for divergence-free w the directional
+    derivatives of the incompressible problem are those of the compressible one:
+    <g_K, w> = <g_I, w> and <H_K w1, w2> = <H_I w1, w2> (GN and FN), at a compressible v too."""
+    L, vstar = _smooth_problem()
+    g = L.grid
+    v = 0.3 * vstar + synth.random_velocity(64, 64, np.random.default_rng(5), modes=8, kmax=3, amplitude=0.2)
+    w1, w2 = O.leray(g, _direction(64, 1)), O.leray(g, _direction(64, 2))
+    for hess in ("gn", "fn"):
+        lins = [O.linearize(O.Level(g, L.mT, L.mR, O.Params(nt=4, beta=1e-2, reg=1, proj=p, hessian=hess)), v)
+                for p in (0, 1)]
+        gI, gK = O.gradient(lins[0]), O.gradient(lins[1])
+        assert abs(O.inner_l2(g, gK, w1) - O.inner_l2(g, gI, w1)) < 1e-12 * abs(O.inner_l2(g, gI, w1))
+        hI = O.inner_l2(g, O.hessian_matvec(lins[0], w1), w2)
+        hK = O.inner_l2(g, O.hessian_matvec(lins[1], w1), w2)
+        assert abs(hK - hI) < 1e-12 * abs(hI)
+        # K b is divergence-free while b is not (g = beta A v + K b; v itself is compressible here)
+        bAv = 1e-2 * O.apply_reg(g, v, 1)
+        assert np.abs(O.fft_div(g, gI - bAv)).max() > 1e-3 and np.abs(O.fft_div(g, gK - bAv)).max() < 1e-12
+
+
+@pytest.mark.parametrize("pc", ["reg", "2l"])
+def test_leray_newton_keeps_velocity_divergence_free(pc):
+    """The incompressible solve (K = Leray, H1) converges and every iterate stays divergence-free
+    (the gradient, the preconditioners and the Hessian map divergence-free fields to themselves)."""
+    n = 64
+    g = O.Grid(n, n)
+    rng = np.random.default_rng(2)
+    mT = synth.smooth_a_template(n, n)
+    vs = O.leray(g, synth.random_velocity(n, n, rng, modes=16, kmax=3, amplitude=0.3))
+    L = O.Level(g, mT, O.transport_state(g, vs, mT, 4), O.Params(nt=4, beta=1e-2, reg=1, proj=1))
+    v, rep = O.newton_solve(L, pc=pc, max_newton=10)
+    assert rep["status"] == "ok" and rep["grel"][-1] <= 1e-2, rep["grel"]
+    assert np.abs(O.fft_div(g, v)).max() < 1e-12 * np.abs(v).max()
+    assert all(np.diff(rep["J"]) < 0)
