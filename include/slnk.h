@@ -61,6 +61,7 @@ typedef enum { SLNK_REG_H1 = 1, SLNK_REG_H2 = 2, SLNK_REG_H3 = 3 } slnk_reg;
 typedef enum { SLNK_PREC_FP64 = 0, SLNK_PREC_MIXED = 1 } slnk_prec;
 typedef enum { SLNK_PC_REG = 1, SLNK_PC_2L = 2 } slnk_pc;
 typedef enum { SLNK_HESS_GN = 0, SLNK_HESS_FN = 1 } slnk_hessian;
+typedef enum { SLNK_PROJ_NONE = 0, SLNK_PROJ_LERAY = 1 } slnk_proj;
 
 /* Problem and solver parameters (section 3.5 lists the paper's settings).
  *   nt            number of SL time steps on [0, 1] (ht = 1/nt), >= 1
@@ -86,7 +87,10 @@ typedef enum { SLNK_HESS_GN = 0, SLNK_HESS_FN = 1 } slnk_hessian;
  *                 lambda grad m~ (table t:computational-complexity-theoretical, FN rows).  FN keeps
  *                 lambda^0..lambda^nt of the last gradient, (6 nt + 5) more fields per item; the
  *                 coarse operator of P_2L stays Gauss--Newton (Chebyshev needs it positive definite)
- * The compressible case (projection K = identity) is the one implemented. */
+ *   proj          SLNK_PROJ_NONE (default): the compressible case, K = identity; SLNK_PROJ_LERAY:
+ *                 the incompressible case (w = 0), K = the Leray projection b - grad Lap^{-1} div b
+ *                 applied to b in the gradient and to b~ in every matvec (section 3.1), on both
+ *                 levels of P_2L */
 typedef struct {
   int n1, n2, nt;
   int reg;
@@ -101,6 +105,7 @@ typedef struct {
   int batch;
   int sl_path;
   int hessian;
+  int proj;
 } slnk_params;
 
 /* Newton--Krylov options (sections 3.4.1, 3.5).  Stop when ||g||_inf / ||g_0||_inf <= gtol_rel or
@@ -168,7 +173,7 @@ slnk_status slnk_transport_state(slnk_ctx* ctx, const void* v, const void* m0, v
 /* J[v] of every item (eq. e:varopt:objective) into J[0..B).  Makes v the linearisation point. */
 slnk_status slnk_objective(slnk_ctx* ctx, const void* v, double* J);
 
-/* Reduced gradient g = beta A v + int_0^1 lambda grad m dt (eq. e:control-elim) into g
+/* Reduced gradient g = beta A v + K int_0^1 lambda grad m dt (eq. e:control-elim) into g
  * [2][n1][n2]; J (B values, may be NULL) receives the objective.  Makes v the linearisation point of the
  * Hessian and, with P_2L, of the coarse problem. */
 slnk_status slnk_gradient(slnk_ctx* ctx, const void* v, void* g, double* J);

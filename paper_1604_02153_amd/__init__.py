@@ -22,6 +22,7 @@ REG = {"h1": 1, "h2": 2, "h3": 3}
 PREC = {"fp64": 0, "mixed": 1}
 PC = {"reg": 1, "2l": 2}
 HESSIAN = {"gn": 0, "fn": 1}
+PROJ = {"none": 0, "leray": 1}
 REPORT_MAX = 64
 
 
@@ -30,7 +31,8 @@ class Params(ctypes.Structure):
                 ("beta", ctypes.c_double), ("prec", ctypes.c_int), ("pc", ctypes.c_int),
                 ("cheb_iters", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
                 ("emax_safety", ctypes.c_double), ("lanczos_seed", ctypes.c_ulonglong), ("use_graphs", ctypes.c_int),
-                ("batch", ctypes.c_int), ("sl_path", ctypes.c_int), ("hessian", ctypes.c_int)]
+                ("batch", ctypes.c_int), ("sl_path", ctypes.c_int), ("hessian", ctypes.c_int),
+                ("proj", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -152,7 +154,7 @@ class Context:
 
     def __init__(self, n1, n2, nt, reg="h2", beta=1e-3, prec="mixed", pc="2l", cheb_iters=10,
                  lanczos_steps=30, emax_safety=1.05, lanczos_seed=0x5EED, use_graphs=True, stream=None,
-                 batch=1, sl_path=0, hessian="gn"):
+                 batch=1, sl_path=0, hessian="gn", proj="none"):
         import torch
         lib = load_library()
         p = Params()
@@ -168,6 +170,7 @@ class Context:
         p.batch = int(batch)
         p.sl_path = int(sl_path)
         p.hessian = HESSIAN[hessian] if isinstance(hessian, str) else int(hessian)
+        p.proj = PROJ[proj] if isinstance(proj, str) else int(proj)
         self.batch = p.batch
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -302,7 +305,8 @@ class BatchContext:
     list of (n1, n2) per pair; every per-pair argument is a list of tensors (pair order)."""
 
     def __init__(self, sizes, nt, reg="h2", beta=1e-3, prec="mixed", pc="2l", cheb_iters=10, lanczos_steps=30,
-                 emax_safety=1.05, lanczos_seed=0x5EED, use_graphs=True, sl_path=0, stream=None, hessian="gn"):
+                 emax_safety=1.05, lanczos_seed=0x5EED, use_graphs=True, sl_path=0, stream=None, hessian="gn",
+                 proj="none"):
         import torch
         lib = load_library()
         p = Params()
@@ -316,6 +320,7 @@ class BatchContext:
         p.emax_safety, p.lanczos_seed = float(emax_safety), int(lanczos_seed)
         p.use_graphs, p.sl_path = (1 if use_graphs else 0), int(sl_path)
         p.hessian = HESSIAN[hessian] if isinstance(hessian, str) else int(hessian)
+        p.proj = PROJ[proj] if isinstance(proj, str) else int(proj)
         self.sizes = [(int(a), int(b)) for a, b in sizes]
         self.npairs = len(self.sizes)
         n1 = (ctypes.c_int * self.npairs)(*[a for a, _ in self.sizes])

@@ -195,6 +195,8 @@ struct Context {
   bool has_grad = false;
   // full-Newton matvec (fine level only; the coarse operator of P_2L stays Gauss--Newton)
   bool full_newton = false;
+  // incompressible case: K = Leray projection on b, b~ (section 3.1)
+  bool leray = false;
   struct {
     T* lam = nullptr;    // (nt+1) F per item: lambda^0..lambda^nt of the slot-0 linearisation
     T* mt = nullptr;     // nt F: m~^1..m~^nt
@@ -354,6 +356,9 @@ struct Context {
     if (p.hessian != SLNK_HESS_GN && p.hessian != SLNK_HESS_FN)
       throw Fail{SLNK_EINVAL, "hessian must be SLNK_HESS_GN or SLNK_HESS_FN"};
     full_newton = p.hessian == SLNK_HESS_FN;
+    if (p.proj != SLNK_PROJ_NONE && p.proj != SLNK_PROJ_LERAY)
+      throw Fail{SLNK_EINVAL, "proj must be SLNK_PROJ_NONE or SLNK_PROJ_LERAY"};
+    leray = p.proj == SLNK_PROJ_LERAY;
     two_level = p.pc == SLNK_PC_2L;
     if (two_level) {
       if (!fft_size_ok(p.n1 / 2) || !fft_size_ok(p.n2 / 2)) throw Fail{SLNK_EINVAL, "coarse grid n/2 not supported"};
@@ -499,6 +504,12 @@ struct Context {
   void put_mask(int k, const std::vector<int>& m) { HIPCHK(set_ints(stream, mask(k), m.data(), B)); }
 
   SymbolParams sym(Symbol k) const { return SymbolParams{k, prm.reg, prm.beta}; }
+  // a symbol applied to a transport result b or b~: K (Leray) first in the incompressible case
+  SymbolParams symK(Symbol k) const {
+    SymbolParams sp = sym(k);
+    sp.proj = leray ? 1 : 0;
+    return sp;
+  }
 
   // SL step arguments shared by every step of a level: the LDS footprint is sized for the largest
   // item halo of the slot (halo_cap while capturing a graph), and each item stages its own halo
@@ -644,14 +655,19 @@ struct Context {
       a.w_old = trapezoid_weight(nt, nt);
       a.acc = lv.acc;
       a.st_acc = (long long)(2 * F);
-      a.addf = L.bAv;
+      a.addf = leray ? nullptr : L.bAv;  // with K, beta A v is added after the projection
       a.st_addf = (long long)(2 * F);
       a.out2 = lv.g;
       a.st_out2 = (long long)(2 * F);
       a.partial = partial;
       HIPCHK(sl_step<T>(stream, StepKind::Adjoint, a, &nb));
     }
-    HIPCHK(finish(stream, B, nb, 2, 2LL * nb, 2, 2u, partial, dres));
+    if (leray) {  // g = beta A v + K b, then its norms
+      HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, symK(Symbol::One), 2, lv.g, lv.g, L.bAv, lv.S1, lv.S2));
+      HIPCHK(norms<T>(stream, B, 2 * F, lv.g, partial, dres));
+    } else {
+      HIPCHK(finish(stream, B, nb, 2, 2LL * nb, 2, 2u, partial, dres));
+    }
     const double* r = fetch(0);
     g2.assign(B, 0.0);
     ginf.assign(B, 0.0);
@@ -659,7 +675,7 @@ struct Context {
       if (!hmask.empty() && !hmask[z]) continue;
       g2[z] = r[4 * z];
       ginf[z] = r[4 * z + 1];
-      if (!std::isfinite(g2[z])) throw Fail{SLNK_ENAN, "non-finite gradient"};
+      if (!std::isfinite(g2[z]) || (leray && r[4 * z + 2] > 0)) throw Fail{SLNK_ENAN, "non-finite gradient"};
     }
   }
 
@@ -788,6 +804,7 @@ struct Context {
   // out = beta A vt + Q vt
   void hessian(Level<T>& lv, const T* vt, T* out, const int* mk) {
     transport(lv, vt, mk);
+    if (leray) HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, symK(Symbol::One), 2, lv.bt, lv.bt, nullptr, lv.S1, lv.S2));
     HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, sym(Symbol::Reg), 2, vt, out, lv.bt, lv.S1, lv.S2));
   }
 
@@ -795,14 +812,14 @@ struct Context {
   void split_matvec(Level<T>& lv, const T* s, T* out, const int* mk) {
     HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, sym(Symbol::RegInvSqrt), 2, s, lv.w, nullptr, lv.S1, lv.S2));
     transport(lv, lv.w, mk);
-    HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, sym(Symbol::RegInvSqrt), 2, lv.bt, out, s, lv.S1, lv.S2));
+    HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, symK(Symbol::RegInvSqrt), 2, lv.bt, out, s, lv.S1, lv.S2));
   }
 
   // out = s + S Q(0) S s on the coarse level (closed form of the v = 0 operator)
   void split_matvec_zero(Level<T>& lv, const T* s, T* out) {
     HIPCHK(spec_scale<T>(stream, lv.sg, B, nullptr, sym(Symbol::RegInvSqrt), 2, s, lv.w, nullptr, lv.S1, lv.S2));
     HIPCHK(q_at_zero<T>(stream, B, lv.F, lv.w, lv.gmT, 1.0, lv.bt));
-    HIPCHK(spec_scale<T>(stream, lv.sg, B, nullptr, sym(Symbol::RegInvSqrt), 2, lv.bt, out, s, lv.S1, lv.S2));
+    HIPCHK(spec_scale<T>(stream, lv.sg, B, nullptr, symK(Symbol::RegInvSqrt), 2, lv.bt, out, s, lv.S1, lv.S2));
   }
 
   // per-item dot products of two vector fields (host copies; synchronises)
@@ -933,10 +950,10 @@ struct Context {
       const double* c2 = cheb_tab + (size_t(k) + i) * B;
       if (fused) {
         // the inverse row pass of S Q y, S^2 Q y applies the step in place
-        HIPCHK(spec_scale2_cheb<T>(stream, coarse.sg, B, mk, sym(Symbol::RegInvSqrt), sym(Symbol::RegInv), coarse.bt,
+        HIPCHK(spec_scale2_cheb<T>(stream, coarse.sg, B, mk, symK(Symbol::RegInvSqrt), sym(Symbol::RegInv), coarse.bt,
                                    ChebTail<T>{r, d, x, u, y, c1, c2}, coarse.S1, coarse.S2));
       } else {
-        HIPCHK(spec_scale2<T>(stream, coarse.sg, B, mk, sym(Symbol::RegInvSqrt), sym(Symbol::RegInv), coarse.bt, sb,
+        HIPCHK(spec_scale2<T>(stream, coarse.sg, B, mk, symK(Symbol::RegInvSqrt), sym(Symbol::RegInv), coarse.bt, sb,
                               s2b, coarse.S1, coarse.S2));
         HIPCHK(cheb_step<T>(stream, B, n, c1, c2, r, u, d, y, x, sb, s2b));
       }

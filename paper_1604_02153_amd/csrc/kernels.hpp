@@ -44,13 +44,18 @@ enum class Symbol : int {
   HighPass = 4,   // 1 - LowPass
   Spline = 5,     // 1 / (B1(k1) B2(k2)), B(k) = (2 + cos(2 pi k / n)) / 3  (B-spline prefilter)
   Cutoff = 6,     // 1 for k1^2 + k2^2 <= kmax^2, else 0 (smooth part of a field)
+  One = 7,        // 1
 };
 
+// proj = 1: a symbol applied to a vector field (two fields) first projects it onto divergence-free
+// fields, b - k (k . b) / |k|^2 per wavenumber (the Leray operator K of the incompressible case,
+// section 3.1; odd-order wavenumbers, Nyquist components zero, the mean kept)
 struct SymbolParams {
   Symbol kind = Symbol::Reg;
   int reg = 2;
   double beta = 1.0;
   int kmax = 0;
+  int proj = 0;
 };
 
 // Largest dynamic LDS (bytes) a spectral launch on an n1 x n2 grid asks for.
@@ -158,7 +163,8 @@ struct StepArgs {
   const T* gm_old = nullptr; // 2 fields, grad m at the time level of src (first step only)
   T* acc = nullptr;          // 2 fields accumulator (b or bt)
   const T* vt = nullptr;     // incremental state: direction (2 fields)
-  const T* addf = nullptr;   // adjoint last step: beta A v added to the accumulator (2 fields);
+  const T* addf = nullptr;   // adjoint last step: beta A v added to the accumulator (2 fields,
+                             // optional);
                              // incremental adjoint: source term added to gamma I[src] (1 field)
   T* out2 = nullptr;         // adjoint last step: gradient output (2 fields); incremental
                              // state: m~^j (1 field, optional)

@@ -872,6 +872,8 @@ __device__ __forceinline__ T symbol_value(const SymbolParams& sp, int k1, int n1
       return (4 * abs(k1) < n1 && 4 * abs(k2) < n2) ? T(0) : T(1);
     case Symbol::Cutoff:
       return (k1 * k1 + k2 * k2 <= sp.kmax * sp.kmax) ? T(1) : T(0);
+    case Symbol::One:
+      return T(1);
     case Symbol::Spline:
     default:
       return T(1) / spline_symbol<T>(k1, n1, k2, n2);
@@ -881,6 +883,19 @@ __device__ __forceinline__ T symbol_value(const SymbolParams& sp, int k1, int n1
 // Every operator gives all outputs at one wavenumber (operator(), generic column pass) and output g
 // alone (out(), wave-level column pass) from NC real coefficients per wavenumber that coef()
 // forms once for all outputs; pre() is a side effect at each wavenumber, run once.
+// Leray projection of the vector pair (a, b) at column index k1, half-spectrum index k2:
+// (a, b) - k (k . (a, b)) / |k|^2 with the odd-order wavenumbers (Nyquist components zero)
+template <typename T>
+__device__ __forceinline__ void leray_pair(int k1, int n1, int k2, int n2, cplx<T>& a, cplx<T>& b) {
+  const T o1 = odd_k<T>(k1, n1), o2 = (2 * k2 == n2) ? T(0) : T(k2);
+  const T kk = o1 * o1 + o2 * o2;
+  if (kk > T(0)) {
+    const cplx<T> t = cscale(cadd(cscale(a, o1), cscale(b, o2)), T(1) / kk);
+    a = csub(a, cscale(t, o1));
+    b = csub(b, cscale(t, o2));
+  }
+}
+
 template <typename T, int NF>
 struct OpScale {
   static constexpr int NIN = NF, NOUT = NF, NC = 1;
@@ -895,11 +910,29 @@ struct OpScale {
   __device__ void operator()(int k1, int k2, int, int, const cplx<T>* in, cplx<T>* out) const {
     T s;
     coef(k1, k2, &s);
+    if constexpr (NF == 2) {
+      if (sp.proj) {
+        cplx<T> a = in[0], b = in[1];
+        leray_pair<T>(k1, n1, k2, n2, a, b);
+        out[0] = cscale(a, s);
+        out[1] = cscale(b, s);
+        return;
+      }
+    }
 #pragma unroll
     for (int f = 0; f < NF; ++f) out[f] = cscale(in[f], s);
   }
   __device__ void pre(int, int, int, const cplx<T>*) const {}
-  __device__ cplx<T> out(int g, int, int, int, const cplx<T>* in, const T* c) const { return cscale(in[g], c[0]); }
+  __device__ cplx<T> out(int g, int k1, int k2, int, const cplx<T>* in, const T* c) const {
+    if constexpr (NF == 2) {
+      if (sp.proj) {
+        cplx<T> a = in[0], b = in[1];
+        leray_pair<T>(k1, n1, k2, n2, a, b);
+        return cscale(g == 0 ? a : b, c[0]);
+      }
+    }
+    return cscale(in[g], c[0]);
+  }
 };
 
 // two symbols of the same two input fields: out[0..2) = sym1 in, out[2..4) = sym2 in
@@ -914,10 +947,12 @@ struct OpScale2 {
     const int k2s = (2 * k2 == n2) ? -k2 : k2;
     const T a = symbol_value<T>(sp1, k1, n1, k2s, n2) * T(inv_n);
     const T b = symbol_value<T>(sp2, k1, n1, k2s, n2) * T(inv_n);
-    out[0] = cscale(in[0], a);
-    out[1] = cscale(in[1], a);
-    out[2] = cscale(in[0], b);
-    out[3] = cscale(in[1], b);
+    cplx<T> x = in[0], y = in[1];
+    if (sp1.proj) leray_pair<T>(k1, n1, k2, n2, x, y);
+    out[0] = cscale(x, a);
+    out[1] = cscale(y, a);
+    out[2] = cscale(x, b);
+    out[3] = cscale(y, b);
   }
   __device__ void coef(int k1, int k2, T* c) const {
     const int k2s = (2 * k2 == n2) ? -k2 : k2;
@@ -925,7 +960,12 @@ struct OpScale2 {
     c[1] = symbol_value<T>(sp2, k1, n1, k2s, n2) * T(inv_n);
   }
   __device__ void pre(int, int, int, const cplx<T>*) const {}
-  __device__ cplx<T> out(int g, int, int, int, const cplx<T>* in, const T* c) const {
+  __device__ cplx<T> out(int g, int k1, int k2, int, const cplx<T>* in, const T* c) const {
+    if (sp1.proj) {
+      cplx<T> x = in[0], y = in[1];
+      leray_pair<T>(k1, n1, k2, n2, x, y);
+      return cscale((g & 1) ? y : x, c[g >> 1]);
+    }
     return cscale(in[g & 1], c[g >> 1]);
   }
 };

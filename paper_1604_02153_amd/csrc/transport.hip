@@ -580,7 +580,7 @@ __global__ void __launch_bounds__(256) k_sl_step(StepArgs<T> args) {
     if (a.last) ex0 = a.aux0[gi];
   }
   if constexpr (kAdj) {
-    if (a.last) {
+    if (a.last && a.addf) {  // no addend: the caller adds beta A v after projecting b
       ex1 = a.addf[gi];
       ex2 = a.addf[gi + F];
     }
