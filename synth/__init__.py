@@ -114,11 +114,32 @@ def random_velocity(n1, n2, rng, modes=16, kmax=4, amplitude=0.3):
     return v * (amplitude / float(np.max(np.abs(v))))
 
 
+def random_solenoidal_velocity(n1, n2, rng, modes=16, kmax=4, amplitude=0.3):
+    """Smooth periodic divergence-free velocity v = (d2 psi, -d1 psi) of a stream function psi
+    with 'modes' random Fourier modes, 1 <= |k| <= kmax (drawn as in random_velocity, one
+    complex coefficient per mode), rescaled so that max_{x,i} |v_i(x)| equals 'amplitude'."""
+    cand = [(a, b) for a in range(-kmax, kmax + 1) for b in range(-kmax, kmax + 1)
+            if 1 <= a * a + b * b <= kmax * kmax]
+    pick = rng.choice(len(cand), size=modes, replace=False)
+    x1 = 2.0 * math.pi * np.arange(n1) / n1
+    x2 = 2.0 * math.pi * np.arange(n2) / n2
+    coefs = np.array([rng.standard_normal() + 1j * rng.standard_normal() for _ in pick])
+    k = np.array([cand[i] for i in pick])
+    e1 = np.exp(1j * k[:, :1] * x1[None, :])
+    e2 = np.exp(1j * k[:, 1:] * x2[None, :])
+    # d2 of c e^{i k.x} is i k2 c e^{i k.x}; d1 likewise
+    w1 = (1j * k[:, 1] * coefs)[:, None]
+    w2 = (-1j * k[:, 0] * coefs)[:, None]
+    v = np.stack([((w1 * e1).T @ e2).real, ((w2 * e1).T @ e2).real])
+    return v * (amplitude / float(np.max(np.abs(v))))
+
+
 CONFIGS = {
     # name: grid, nt, regulariser order, beta, preconditioner, image recipe, velocity recipe, seed
     "smooth64": dict(n1=64, n2=64, nt=4, reg=1, beta=1e-2, pc="reg", prec="fp64"),
     "gauss256": dict(n1=256, n2=256, nt=4, reg=2, beta=1e-3, pc="2l", prec="mixed", seed=2),
     "brain512": dict(n1=512, n2=512, nt=8, reg=1, beta=1e-3, pc="2l", prec="mixed", seed=3),
+    "brain512ic": dict(n1=512, n2=512, nt=8, reg=1, beta=1e-3, pc="2l", prec="mixed", seed=3, proj="leray"),
 }
 
 
@@ -129,6 +150,8 @@ def config(name, n=None, seed=None):
     'gauss256': 32 isotropic Gaussians, 16-mode velocity |k| <= 4, amplitude 0.3.
     'brain512': 64 anisotropic smoothed Gaussians, 24-mode velocity |k| <= 6,
                 amplitude 0.5.
+    'brain512ic': the same image with a divergence-free 24-mode velocity (stream
+                function modes |k| <= 6), amplitude 0.5, for the incompressible case.
     The direction vt (for Hessian matvecs) is a 16-mode |k| <= 4 field of
     amplitude 0.1 from the seed + 1000 stream.
     """
@@ -147,6 +170,9 @@ def config(name, n=None, seed=None):
     elif name == "brain512":
         c["mT"] = gaussian_sum_anisotropic(n1, n2, rng)
         c["v_gen"] = random_velocity(n1, n2, rng, modes=24, kmax=6, amplitude=0.5)
+    elif name == "brain512ic":
+        c["mT"] = gaussian_sum_anisotropic(n1, n2, rng)
+        c["v_gen"] = random_solenoidal_velocity(n1, n2, rng, modes=24, kmax=6, amplitude=0.5)
     else:
         raise KeyError(name)
     rng_t = np.random.default_rng(s + 1000)

@@ -121,3 +121,27 @@ def test_leray_newton_solve_fp64_matches_oracle(slnk, pc):
     assert rel(vv, v_ref) < 1e-9
     assert np.abs(O.fft_div(g, vv)).max() < 1e-10 * np.abs(vv).max()
     ctx.close()
+
+
+def test_brain512ic_recipe_matches_oracle(slnk):
+    """The incompressible 512^2 nt = 8 H1 workload (brain512 image, divergence-free 24-mode
+    velocity of amplitude 0.5, K = Leray), mixed precision: gradient, GN matvec and P_2L bounds at
+    0.7 v_gen against the oracle."""
+    cfg = synth.config("brain512ic")
+    n1, n2, nt = cfg["n1"], cfg["n2"], cfg["nt"]
+    prec = "mixed"
+    g = O.Grid(n1, n2)
+    mT, vgen, vt = same_inputs(prec, cfg["mT"], cfg["v_gen"], cfg["vt"])
+    mR = same_inputs(prec, O.transport_state(g, vgen, mT, nt))
+    L = O.Level(g, mT, mR, O.Params(nt=nt, beta=cfg["beta"], reg=cfg["reg"], proj=1))
+    v = same_inputs(prec, 0.7 * vgen)
+    lin = O.linearize(L, v)
+    ctx = _ctx(slnk, L, prec, "2l")
+    ctx.set_images(_t(mR, prec), _t(mT, prec))
+    gg = torch.empty((2, n1, n2), dtype=torch.float32, device="cuda")
+    ctx.gradient(_t(v, prec), gg)
+    _check_reg_op(L, "fp64", _np(gg), O.gradient(lin), v, TOL[prec]["gradient"])
+    h = torch.empty_like(gg)
+    ctx.hessian_matvec(_t(vt, prec), h)
+    _check_reg_op(L, prec, _np(h), O.hessian_matvec(lin, vt), vt, TOL[prec]["matvec"])
+    ctx.close()
