@@ -528,15 +528,24 @@ def lanczos_max(op, q0, steps: int) -> float:
 
 @dataclass
 class TwoLevel:
-    """Data of the nested two-level preconditioner P_2L fixed for one solve."""
+    """Data of the nested two-level preconditioner P_2L fixed for one solve.
+
+    solver: "cheb" for CHEB(k) on the coarse split operator, "pcg" for the nested
+    PCG(eps) solve (section 3.4.2): CG on the coarse split operator, itself already
+    spectrally preconditioned, to the relative residual eps times the tolerance of
+    the outer solve."""
     coarse: Level
     emin: float
     emax: float
     cheb_iters: int
     lin_c: Linearization = None
+    solver: str = "cheb"
+    eps: float = 0.1
+    max_inner: int = 200
 
 
-def setup_two_level(L: Level, cheb_iters=10, lanczos_steps=30, safety=1.05, seed=0x5EED):
+def setup_two_level(L: Level, cheb_iters=10, lanczos_steps=30, safety=1.05, seed=0x5EED, solver="cheb",
+                    eps=0.1):
     """Coarse problem and Chebyshev bounds (section 3.4.2, "Nested Preconditioner").
 
     The coarse problem restricts m_T and m_R spectrally and keeps nt and beta;
@@ -554,15 +563,21 @@ def setup_two_level(L: Level, cheb_iters=10, lanczos_steps=30, safety=1.05, seed
     q0 = splitmix64_uniform(seed, 2 * cg.N).reshape((2,) + cg.shape)
     emax = safety * lanczos_max(lambda s: split_matvec(lin0, s), q0, lanczos_steps)
     emin = float(np.min(1.0 + 1.0 / (L.prm.beta * _reg_symbol_nonzero(cg, L.prm.reg))))
-    return TwoLevel(Lc, emin, emax, cheb_iters)
+    return TwoLevel(Lc, emin, emax, cheb_iters, solver=solver, eps=eps)
 
 
-def apply_two_level(L: Level, tl: TwoLevel, r):
-    """P_2L^{-1} r = (I - L) r + Pro C_k(M_c) Res r (section 3.4.2, nested preconditioner)."""
+def apply_two_level(L: Level, tl: TwoLevel, r, outer_tol: float = 1.0):
+    """P_2L^{-1} r = (I - L) r + Pro C(M_c) Res r (section 3.4.2, nested preconditioner), C the
+    coarse solver: CHEB(k), or CG on M_c to the relative residual eps * outer_tol (PCG(eps)).
+    Returns z, or (z, inner iterations) for PCG(eps)."""
     fg, cg = L.grid, tl.coarse.grid
     high = r - lowpass(fg, r)
     rc = np.stack([restrict(fg, cg, r[c]) for c in range(2)])
-    zc = chebyshev(lambda s: split_matvec(tl.lin_c, s), rc, tl.emin, tl.emax, tl.cheb_iters)
+    op = lambda s: split_matvec(tl.lin_c, s)
+    if tl.solver == "pcg":
+        zc, its, _ = pcg(op, rc, lambda x: x, tl.eps * outer_tol, tl.max_inner)
+        return high + np.stack([prolong(fg, cg, zc[c]) for c in range(2)]), its
+    zc = chebyshev(op, rc, tl.emin, tl.emax, tl.cheb_iters)
     return high + np.stack([prolong(fg, cg, zc[c]) for c in range(2)])
 
 
@@ -605,7 +620,7 @@ def pcg(op, b, prec, tol: float, maxit: int):
 
 def newton_solve(L: Level, v0=None, pc: str = "reg", max_newton=10, gtol_rel=1e-2, gtol_abs=1e-5,
                  max_pcg=500, armijo_c1=1e-4, max_halvings=10, cheb_iters=10, lanczos_steps=30,
-                 emax_safety=1.05, seed=0x5EED, g0_norms=None):
+                 emax_safety=1.05, seed=0x5EED, g0_norms=None, coarse_solver="cheb", coarse_eps=0.1):
     """Globalised inexact GN--Krylov solve (sections 3.4.1, 3.5).
 
     Newton step H vt = -g by PCG with the forcing term
@@ -613,14 +628,16 @@ def newton_solve(L: Level, v0=None, pc: str = "reg", max_newton=10, gtol_rel=1e-
     1, sufficient decrease 1e-4 alpha <g, vt>_L2); stop when
     ||g_k||_inf / ||g_0||_inf <= gtol_rel or ||g_k||_inf <= gtol_abs.
     pc = 'reg' runs PCG on H with P_REG; pc = '2l' runs PCG on the split system
-    M s = -S g with P_2L and takes vt = S s.  g_0 is the gradient at v = 0;
+    M s = -S g with P_2L and takes vt = S s; coarse_solver 'cheb' inverts the coarse
+    operator by CHEB(cheb_iters), 'pcg' by PCG(coarse_eps) to coarse_eps * eta_k.  g_0 is the gradient at v = 0;
     g0_norms = (||g_0||_inf, ||g_0||_2) may be passed in to skip computing it.
     """
     g, p = L.grid, L.prm
     v = np.zeros((2,) + g.shape) if v0 is None else np.array(v0, dtype=np.float64)
     rep = {"newton_iters": 0, "pcg_iters": 0, "matvecs": 0, "coarse_matvecs": 0,
            "grel": [], "J": [], "status": "ok", "alphas": []}
-    tl = setup_two_level(L, cheb_iters, lanczos_steps, emax_safety, seed) if pc == "2l" else None
+    tl = setup_two_level(L, cheb_iters, lanczos_steps, emax_safety, seed, coarse_solver, coarse_eps) \
+        if pc == "2l" else None
     if tl is not None:
         rep["emin"], rep["emax"] = tl.emin, tl.emax
     lin = linearize(L, v)
@@ -658,6 +675,10 @@ def newton_solve(L: Level, v0=None, pc: str = "reg", max_newton=10, gtol_rel=1e-
                 return split_matvec(lin, x)
 
             def prec(r):
+                if tl.solver == "pcg":
+                    z, its_c = apply_two_level(L, tl, r, eta)
+                    rep["coarse_matvecs"] += its_c
+                    return z
                 rep["coarse_matvecs"] += max(tl.cheb_iters - 1, 0)
                 return apply_two_level(L, tl, r)
             s, its, st = pcg(op, -split_scale(g, grad, p.beta, p.reg), prec, eta, max_pcg)

@@ -121,3 +121,63 @@ def test_full_newton_converges_superlinearly(pc):
     assert rep["status"] == "ok" and rep["grel"][-1] <= 1e-5 and rep["newton_iters"] <= 5, rep["grel"]
     assert rep["grel"][-1] < 1e-2 * rep["grel"][-2]
     assert all(np.diff(rep["J"]) < 0)
+
+
+def test_nested_pcg_coarse_solve_equals_dense_inverse():
+    """PCG(eps) with a tiny tolerance applies (I - L) r + Pro M_c^{-1} Res r, M_c assembled densely
+    from the coarse split operator on a 32^2 / 16^2 problem and inverted by numpy."""
+    n = 32
+    g = O.Grid(n, n)
+    rng = np.random.default_rng(3)
+    mT = synth.gaussian_sum_isotropic(n, n, rng, count=8, sigma=(0.3, 0.6))
+    vgen = synth.random_velocity(n, n, rng, modes=8, kmax=3, amplitude=0.2)
+    L = O.Level(g, mT, O.transport_state(g, vgen, mT, 4), O.Params(nt=4, beta=1e-2, reg=2))
+    tl = O.setup_two_level(L, solver="pcg", eps=1e-13)
+    cg = tl.coarse.grid
+    tl.lin_c = O.linearize(tl.coarse, np.stack([O.restrict(g, cg, 0.5 * vgen[c]) for c in range(2)]))
+    m = 2 * cg.N
+    M = np.empty((m, m))
+    for k in range(m):
+        e = np.zeros(m); e[k] = 1.0
+        M[:, k] = O.split_matvec(tl.lin_c, e.reshape((2,) + cg.shape)).ravel()
+    r = synth.random_velocity(n, n, np.random.default_rng(9), modes=16, kmax=8, amplitude=1.0)
+    z, its = O.apply_two_level(L, tl, r)
+    rc = np.stack([O.restrict(g, cg, r[c]) for c in range(2)])
+    zc = np.linalg.solve(M, rc.ravel()).reshape((2,) + cg.shape)
+    ref = r - O.lowpass(g, r) + np.stack([O.prolong(g, cg, zc[c]) for c in range(2)])
+    assert its > 1 and np.abs(z - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_nested_pcg_preconditioner_is_nearly_ideal_at_small_beta():
+    """Section 4.2.2: with PCG(1e-1) inverting the coarse operator, the outer PCG at beta = 1e-3
+    needs no more iterations than with CHEB(10), and far fewer than P_REG."""
+    n = 64
+    g = O.Grid(n, n)
+    rng = np.random.default_rng(2)
+    mT = synth.gaussian_sum_isotropic(n, n, rng)
+    vgen = synth.random_velocity(n, n, rng, modes=16, kmax=4, amplitude=0.3)
+    L = O.Level(g, mT, O.transport_state(g, vgen, mT, 4), O.Params(nt=4, beta=1e-3, reg=2))
+    lin = O.linearize(L, np.zeros((2,) + g.shape))
+    grad = O.gradient(lin)
+    p = L.prm
+    rhs = -O.split_scale(g, grad, p.beta, p.reg)
+    its = {}
+    for solver in ("cheb", "pcg"):
+        tl = O.setup_two_level(L, solver=solver, eps=0.1)
+        tl.lin_c = O.linearize(tl.coarse, np.zeros((2,) + tl.coarse.grid.shape))
+        prec = (lambda r: O.apply_two_level(L, tl, r, 1e-6)[0]) if solver == "pcg" else \
+            (lambda r: O.apply_two_level(L, tl, r))
+        _, its[solver], st = O.pcg(lambda s: O.split_matvec(lin, s), rhs, prec, 1e-6, 500)
+        assert st == "ok"
+    _, it_reg, _ = O.pcg(lambda s: O.hessian_matvec(lin, s), -grad, lambda r: O.prec_reg(g, r, p.beta, p.reg),
+                         1e-6, 500)
+    assert its["pcg"] <= its["cheb"] < it_reg, (its, it_reg)
+
+
+def test_newton_with_nested_pcg_coarse_solve_converges():
+    L, _ = _smooth_level(n=64, nt=4, beta=1e-2, reg=1)
+    v, rep = O.newton_solve(L, pc="2l", max_newton=10, coarse_solver="pcg", coarse_eps=0.1)
+    assert rep["status"] == "ok" and rep["grel"][-1] <= 1e-2
+    v2, rep2 = O.newton_solve(L, pc="2l", max_newton=10)
+    assert rep["pcg_iters"] <= rep2["pcg_iters"]
+    assert np.linalg.norm(v - v2) < 2e-2 * np.linalg.norm(v2)
