@@ -62,6 +62,7 @@ typedef enum { SLNK_PREC_FP64 = 0, SLNK_PREC_MIXED = 1 } slnk_prec;
 typedef enum { SLNK_PC_REG = 1, SLNK_PC_2L = 2 } slnk_pc;
 typedef enum { SLNK_HESS_GN = 0, SLNK_HESS_FN = 1 } slnk_hessian;
 typedef enum { SLNK_PROJ_NONE = 0, SLNK_PROJ_LERAY = 1 } slnk_proj;
+typedef enum { SLNK_COARSE_CHEB = 0, SLNK_COARSE_PCG = 1 } slnk_coarse_solver;
 
 /* Problem and solver parameters (section 3.5 lists the paper's settings).
  *   nt            number of SL time steps on [0, 1] (ht = 1/nt), >= 1
@@ -90,7 +91,12 @@ typedef enum { SLNK_PROJ_NONE = 0, SLNK_PROJ_LERAY = 1 } slnk_proj;
  *   proj          SLNK_PROJ_NONE (default): the compressible case, K = identity; SLNK_PROJ_LERAY:
  *                 the incompressible case (w = 0), K = the Leray projection b - grad Lap^{-1} div b
  *                 applied to b in the gradient and to b~ in every matvec (section 3.1), on both
- *                 levels of P_2L */
+ *                 levels of P_2L
+ *   coarse_solver SLNK_COARSE_CHEB (default): P_2L inverts the coarse split operator by CHEB(k);
+ *                 SLNK_COARSE_PCG: by the nested PCG(eps) solve of section 3.4.2, CG on the coarse
+ *                 split operator from zero to the relative residual coarse_eps times the outer
+ *                 PCG tolerance (the forcing term; 1 in slnk_precond_apply), at most 200 steps
+ *   coarse_eps    eps of PCG(eps), in (0, 1); the paper uses 1e-1 */
 typedef struct {
   int n1, n2, nt;
   int reg;
@@ -106,6 +112,8 @@ typedef struct {
   int sl_path;
   int hessian;
   int proj;
+  int coarse_solver;
+  double coarse_eps;
 } slnk_params;
 
 /* Newton--Krylov options (sections 3.4.1, 3.5).  Stop when ||g||_inf / ||g_0||_inf <= gtol_rel or

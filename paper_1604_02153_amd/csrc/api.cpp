@@ -197,6 +197,10 @@ struct Context {
   bool full_newton = false;
   // incompressible case: K = Leray projection on b, b~ (section 3.1)
   bool leray = false;
+  // P_2L coarse solver: CHEB(k), or PCG(eps) to eps times the outer tolerance of each item
+  bool coarse_pcg = false;
+  std::vector<double> outer_tol;
+  static constexpr int kMaxInner = 200;
   struct {
     T* lam = nullptr;    // (nt+1) F per item: lambda^0..lambda^nt of the slot-0 linearisation
     T* mt = nullptr;     // nt F: m~^1..m~^nt
@@ -243,7 +247,7 @@ struct Context {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prec_ev;
   size_t prec_used = 0;
 
-  enum { kMaskAll = 0, kMaskPcg = 1, kMaskNewton = 2, kMaskLs = 3 };
+  enum { kMaskAll = 0, kMaskPcg = 1, kMaskNewton = 2, kMaskLs = 3, kMaskCoarse = 4 };
   int* mask(int k) const { return masks + k * B; }
   double* sc(int k) const { return dsc + k * B; }
 
@@ -359,6 +363,12 @@ struct Context {
     if (p.proj != SLNK_PROJ_NONE && p.proj != SLNK_PROJ_LERAY)
       throw Fail{SLNK_EINVAL, "proj must be SLNK_PROJ_NONE or SLNK_PROJ_LERAY"};
     leray = p.proj == SLNK_PROJ_LERAY;
+    if (p.coarse_solver != SLNK_COARSE_CHEB && p.coarse_solver != SLNK_COARSE_PCG)
+      throw Fail{SLNK_EINVAL, "coarse_solver must be SLNK_COARSE_CHEB or SLNK_COARSE_PCG"};
+    coarse_pcg = p.coarse_solver == SLNK_COARSE_PCG;
+    if (coarse_pcg && !(p.coarse_eps > 0.0 && p.coarse_eps < 1.0))
+      throw Fail{SLNK_EINVAL, "coarse_eps must lie in (0, 1)"};
+    outer_tol.assign(B, 1.0);
     two_level = p.pc == SLNK_PC_2L;
     if (two_level) {
       if (!fft_size_ok(p.n1 / 2) || !fft_size_ok(p.n2 / 2)) throw Fail{SLNK_EINVAL, "coarse grid n/2 not supported"};
@@ -376,7 +386,7 @@ struct Context {
     const int tiles = ((p.n1 + 15) / 16) * ((p.n2 + 15) / 16);  // blocks of the 16x16 transport kernels
     partial_half = size_t(B) * (std::max(reduce_blocks(2 * F), tiles) * 4 + 64);
     size_t bytes = level_bytes(p.n1, p.n2, p.nt, B) + (two_level ? level_bytes(p.n1 / 2, p.n2 / 2, p.nt, B) : 0);
-    bytes += (2 * partial_half + 8 * B + 16 * B + 2 * 64 * B + B) * sizeof(double) + 4 * B * sizeof(int) + 8192;
+    bytes += (2 * partial_half + 8 * B + 16 * B + 2 * 64 * B + B) * sizeof(double) + 5 * B * sizeof(int) + 8192;
     bytes += B * (4 * 2 * F * sizeof(double) + 2 * 2 * size_t(p.n1) * spec_stride(p.n2) * sizeof(cplx<double>)) +
              2 * (p.n1 + p.n2) * sizeof(cplx<double>) + 16 * 256;
     bytes += B * (2 * F * sizeof(T) + sizeof(float)) + 2 * 256;
@@ -392,7 +402,7 @@ struct Context {
     dsc = arena.take<double>(16 * B);
     cheb_tab = arena.take<double>(2 * 64 * B);
     inv_theta = arena.take<double>(B);
-    masks = arena.take<int>(4 * B);
+    masks = arena.take<int>(5 * B);
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hres), 8 * B * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hsc), 16 * B * sizeof(double), hipHostMallocDefault));
     alloc_level(fine, p.n1, p.n2, p.nt);
@@ -422,7 +432,7 @@ struct Context {
     if (halo_cap < 0) throw Fail{SLNK_EDEVICE, "cannot query the LDS size of the device"};
     HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
     std::vector<int> ones(B, 1);
-    for (int k = 0; k < 4; ++k) put_mask(k, ones);
+    for (int k = 0; k < 5; ++k) put_mask(k, ones);
     emin.assign(B, 0.0);
     emax.assign(B, 0.0);
     n_matvec.assign(B, 0);
@@ -1007,11 +1017,70 @@ struct Context {
       if (hmask.empty() || hmask[z]) c[z] += by;
   }
 
+  // PCG(eps) coarse solve (section 3.4.2): CG on the coarse split operator M_c x = b (itself
+  // spectrally preconditioned, so the inner preconditioner is the identity) from zero, per item to
+  // ||b - M_c x|| <= coarse_eps * outer_tol[z] * ||b|| or kMaxInner steps, in lock step over the
+  // items of hmask (empty: all); the step coefficients stay in device memory (rows 10-13 of the
+  // scalar block) and the host synchronises once per step.
+  void coarse_cg(const T* b, T* x, const std::vector<int>& hmask) {
+    const size_t n = 2 * coarse.F;
+    T* r = coarse.vec[0];
+    T* p = coarse.vec[1];
+    T* q = coarse.vec[3];
+    double* rz = sc(13);
+    const int* cm = mask(kMaskCoarse);
+    std::vector<int> active = hmask.empty() ? std::vector<int>(B, 1) : hmask;
+    HIPCHK(fill<T>(stream, B * n, 0.0, x));
+    HIPCHK(axpby<T>(stream, B, n, 1.0, nullptr, b, 0.0, nullptr, r));
+    HIPCHK(axpby<T>(stream, B, n, 1.0, nullptr, b, 0.0, nullptr, p));
+    std::vector<double> bn = dots(coarse, b, b);
+    for (int k = 0; k < B; ++k)
+      if (bn[k] == 0.0) active[k] = 0;
+    if (!any_of(active)) return;
+    put_mask(kMaskCoarse, active);
+    HIPCHK(dot<T>(stream, B, n, r, r, partial, dres));
+    HIPCHK(pcg_coef(stream, PCG_RZ, B, cm, dres, rz, nullptr, nullptr));
+    for (int it = 1; it <= kMaxInner; ++it) {
+      graphed({3, p, q, cm}, halo_fits(coarse), [&] { split_matvec(coarse, p, q, cm); });
+      count(n_coarse, active, 1);
+      HIPCHK(dot<T>(stream, B, n, p, q, partial, dres + 4 * B));
+      HIPCHK(pcg_coef(stream, PCG_ALPHA, B, cm, dres + 4 * B, rz, sc(10), nullptr));
+      HIPCHK(axpby<T>(stream, B, n, 1.0, sc(10), p, 1.0, nullptr, x));
+      HIPCHK(axpby<T>(stream, B, n, -1.0, sc(10), q, 1.0, nullptr, r));
+      HIPCHK(dot<T>(stream, B, n, r, r, partial, dres));
+      fetch_both();
+      bool more = false;
+      for (int k = 0; k < B; ++k) {
+        if (!active[k]) continue;
+        const double pq = hres[4 * B + 4 * k], rr = hres[4 * k];
+        if (!std::isfinite(pq) || !std::isfinite(rr)) throw Fail{SLNK_ENAN, "non-finite coarse PCG"};
+        // non-positive curvature cannot occur for the positive definite coarse operator but in
+        // rounding: stop the item with its current iterate
+        if (pq <= 0.0 || std::sqrt(rr) <= prm.coarse_eps * outer_tol[k] * std::sqrt(bn[k]))
+          active[k] = 0;
+        else
+          more = true;
+      }
+      if (!more) break;
+      put_mask(kMaskCoarse, active);
+      // p <- r + beta p, beta = (r.r)_new / (r.r)_old
+      HIPCHK(pcg_coef(stream, PCG_BETA, B, cm, dres, rz, sc(11), sc(12)));
+      HIPCHK(axpby<T>(stream, B, n, 1.0, sc(11), r, 1.0, sc(12), p));
+    }
+  }
+
   void precond(const T* r, T* z, const int* mk, const std::vector<int>& hmask) {
     const auto& pe = prec_event();
     HIPCHK(hipEventRecord(pe.first, stream));
     if (!two_level) {
       HIPCHK(spec_scale<T>(stream, fine.sg, B, mk, sym(Symbol::RegInv), 2, r, z, nullptr, fine.S1, fine.S2));
+    } else if (coarse_pcg) {
+      T* rc = coarse.vec[6];
+      T* zc = coarse.vec[2];
+      HIPCHK(spec_restrict<T>(stream, fine.sg, coarse.sg, B, mk, 2, r, rc, fine.Sk, fine.S1, coarse.S1, coarse.S2));
+      coarse_cg(rc, zc, hmask);
+      HIPCHK(spec_prolong_combine<T>(stream, fine.sg, coarse.sg, B, mk, 2, fine.Sk, zc, z, fine.S1, coarse.S1,
+                                     coarse.S2));
     } else {
       graphed({1, r, z, mk}, halo_fits(coarse), [&] {
         T* rc = coarse.vec[6];
@@ -1064,6 +1133,7 @@ struct Context {
     if (!any_of(active)) return;
     const int* mk = mask(kMaskPcg);
     put_mask(kMaskPcg, active);
+    for (int k = 0; k < B; ++k) outer_tol[k] = tol[k];  // scales the PCG(eps) coarse tolerance
     precond(r, z, mk, active);
     HIPCHK(axpby<T>(stream, B, n, 1.0, nullptr, z, 0.0, nullptr, p));
     HIPCHK(dot<T>(stream, B, n, r, z, partial, dres));
@@ -1470,6 +1540,8 @@ void slnk_default_params(slnk_params* p) {
   p->lanczos_seed = 0x5EED;
   p->use_graphs = 1;
   p->batch = 1;
+  p->coarse_solver = SLNK_COARSE_CHEB;
+  p->coarse_eps = 0.1;
 }
 
 void slnk_default_opts(slnk_solve_opts* o) {
@@ -1617,6 +1689,7 @@ slnk_status slnk_precond_apply(slnk_ctx* ctx, const void* r, void* z) {
     using T = std::remove_reference_t<decltype(*C.fine.mT)>;
     if (C.two_level && !C.has_grad)
       throw slnk::Fail{SLNK_EINVAL, "P_2L needs a linearisation point: call slnk_gradient first"};
+    std::fill(C.outer_tol.begin(), C.outer_tol.end(), 1.0);  // PCG(eps): coarse tolerance eps
     C.precond(static_cast<const T*>(r), static_cast<T*>(z), C.mask(C.kMaskAll), {});
   });
 }

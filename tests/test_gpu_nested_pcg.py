@@ -1,0 +1,109 @@
+"""GPU parity of the nested PCG(eps) coarse solve of P_2L (section 3.4.2; section 4.2.2 uses
+eps = 1e-1) against the FP64 oracle, through the C ABI."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from gpu_common import problem, rel, same_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def slnk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1604_02153_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def _t(a, prec):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
+
+
+def _np(t):
+    return t.double().cpu().numpy()
+
+
+def _ctx(slnk, L, prec, eps, **kw):
+    p = L.prm
+    reg = {1: "h1", 2: "h2", 3: "h3"}[p.reg]
+    return slnk.Context(L.grid.n1, L.grid.n2, p.nt, reg=reg, beta=p.beta, prec=prec, pc="2l",
+                        coarse_solver="pcg", coarse_eps=eps, **kw)
+
+
+@pytest.mark.parametrize("prec,eps,n1,n2", [("fp64", 1e-1, 96, 80), ("fp64", 1e-6, 96, 80), ("fp64", 1e-3, 128, 128),
+                                            ("mixed", 1e-3, 96, 80), ("mixed", 1e-3, 256, 256)])
+def test_nested_pcg_preconditioner_matches_oracle(slnk, prec, eps, n1, n2):
+    """slnk_precond_apply runs CG on the coarse split operator to the relative residual eps: the
+    FP64 context takes the oracle's inner iterations (1e-10), the mixed one stays within the
+    matvec tolerance (1e-4; measured 1.6e-6)."""
+    L, vgen, vt = problem("gauss", n1, n2, nt=4, beta=1e-3, reg=2)
+    L.mT, L.mR, vgen, vt = same_inputs(prec, L.mT, L.mR, vgen, vt)
+    ctx = _ctx(slnk, L, prec, eps)
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    v = same_inputs(prec, 0.5 * vgen)
+    g = torch.empty((2, n1, n2), dtype=ctx.dtype, device="cuda")
+    ctx.gradient(_t(v, prec), g)
+    tl = O.setup_two_level(L, solver="pcg", eps=eps)
+    cg = tl.coarse.grid
+    tl.lin_c = O.linearize(tl.coarse, np.stack([O.restrict(L.grid, cg, v[c]) for c in range(2)]))
+    z_ref, its = O.apply_two_level(L, tl, vt)
+    z = torch.empty_like(g)
+    ctx.precond_apply(_t(vt, prec), z)
+    print(prec, eps, its, rel(_np(z), z_ref), flush=True)
+    assert rel(_np(z), z_ref) < (1e-10 if prec == "fp64" else 1e-4)
+    ctx.close()
+
+
+def test_nested_pcg_newton_solve_fp64_matches_oracle(slnk):
+    """Gaussian 96^2 problem, H2, beta 1e-3, P_2L with PCG(1e-1), FP64: the oracle's Newton path,
+    outer and inner iteration counts included."""
+    n, nt = 96, 4
+    L, vgen, _ = problem("gauss", n, n, nt=nt, beta=1e-3, reg=2)
+    v_ref, rep_ref = O.newton_solve(L, pc="2l", max_newton=10, coarse_solver="pcg", coarse_eps=0.1)
+    ctx = _ctx(slnk, L, "fp64", 0.1)
+    ctx.set_images(_t(L.mR, "fp64"), _t(L.mT, "fp64"))
+    v = torch.zeros((2, n, n), dtype=torch.float64, device="cuda")
+    rep = ctx.newton_solve(v, max_newton=10)
+    print(rep["grel"], rep_ref["grel"], rep["coarse_matvecs"], rep_ref["coarse_matvecs"], flush=True)
+    assert rep["status"] == "SLNK_OK"
+    assert rep["newton_iters"] == rep_ref["newton_iters"]
+    assert rep["pcg_iters"] == rep_ref["pcg_iters"]
+    assert rep["coarse_matvecs"] == rep_ref["coarse_matvecs"]
+    assert np.allclose(rep["grel"], rep_ref["grel"], rtol=1e-6, atol=0)
+    assert rel(_np(v), v_ref) < 1e-9
+    ctx.close()
+
+
+def test_nested_pcg_batch_items_match_single_contexts(slnk):
+    """B = 3 problems in lock step (each item's inner CG stops on its own): item by item the
+    preconditioner of three B = 1 contexts, bit for bit."""
+    n1, n2, B, prec = 96, 80, 3, "mixed"
+    probs = []
+    for seed, amp in ((5, 0.3), (6, 0.15), (7, 0.45)):
+        L, vgen, vt = problem("gauss", n1, n2, nt=4, beta=1e-3, reg=2, seed=seed, amp=amp)
+        L.mT, L.mR = same_inputs(prec, L.mT, L.mR)
+        probs.append((L, same_inputs(prec, 0.6 * vgen), same_inputs(prec, vt)))
+    stack = lambda arrs: _t(np.stack(arrs), prec)
+    cb = _ctx(slnk, probs[0][0], prec, 1e-3, batch=B)
+    cb.set_images(stack([p[0].mR for p in probs]), stack([p[0].mT for p in probs]))
+    gb = torch.empty((B, 2, n1, n2), dtype=cb.dtype, device="cuda")
+    cb.gradient(stack([p[1] for p in probs]), gb)
+    zb = torch.empty_like(gb)
+    cb.precond_apply(stack([p[2] for p in probs]), zb)
+    for z, (L, v, vt) in enumerate(probs):
+        c1 = _ctx(slnk, L, prec, 1e-3)
+        c1.set_images(_t(L.mR, prec), _t(L.mT, prec))
+        g1 = torch.empty((2, n1, n2), dtype=c1.dtype, device="cuda")
+        c1.gradient(_t(v, prec), g1)
+        z1 = torch.empty_like(g1)
+        c1.precond_apply(_t(vt, prec), z1)
+        assert torch.equal(zb[z], z1), z
+        c1.close()
+    cb.close()
