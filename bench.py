@@ -202,6 +202,40 @@ def full_newton(args, dev):
     return out
 
 
+def preconditioners(args, dev):
+    """gauss256 Newton solves to ||g||rel <= 1e-2 under P_REG, P_2L with CHEB(10) and P_2L with the
+    nested PCG(1e-1) coarse solve (the three schemes of section 4.2.2)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1604_02153_amd import Context
+    cfg = synth.config("gauss256")
+    n1, n2, nt = cfg["n1"], cfg["n2"], cfg["nt"]
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=torch.float32)
+    mT, vgen = f32(cfg["mT"]), f32(cfg["v_gen"])
+    out = {"workload": "gauss256 (256x256, nt=4, H2 beta=1e-3, mixed), Newton to ||g||rel<=1e-2"}
+    for name, kw in (("P_REG", dict(pc="reg")), ("P_2L_CHEB10", dict(pc="2l")),
+                     ("P_2L_PCG0.1", dict(pc="2l", coarse_solver="pcg", coarse_eps=0.1))):
+        ctx = Context(n1, n2, nt, reg="h2", beta=cfg["beta"], prec="mixed", **kw)
+        mR = torch.empty_like(mT)
+        ctx.transport_state(vgen, mT, mR)
+        ctx.set_images(mR, mT)
+        v = torch.zeros_like(vgen)
+        ctx.newton_solve(v, max_newton=20)
+        v.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = ctx.newton_solve(v, max_newton=20)
+        torch.cuda.synchronize()
+        out[name] = {"ms": round(1e3 * (time.perf_counter() - t0), 2), "status": rep["status"],
+                     "newton_iters": rep["newton_iters"], "pcg_iters": rep["pcg_iters"],
+                     "coarse_matvecs": rep["coarse_matvecs"], "time_precond_ms": round(rep["time_precond_ms"], 2),
+                     "grel_final": float(f"{rep['grel'][-1]:.3g}")}
+        ctx.close()
+    return out
+
+
 def batched(args, dev):
     """64 independent pairs with grid sizes drawn from {128, ..., 1024}^2 (seed 4; pair p from the
     'gauss256' recipe with seed 4000 + p), one ragged batch: bucket per size, buckets concurrent."""
@@ -569,6 +603,8 @@ def main():
     if not args.no_full_newton:
         line["full_newton"] = full_newton(args, dev)
         log("full-Newton workload done")
+        line["preconditioners"] = preconditioners(args, dev)
+        log("preconditioner comparison done")
     if not args.no_batched:
         line["batched"] = batched(args, dev)
         log("batched workload done")
