@@ -204,26 +204,26 @@ __device__ __forceinline__ T load_src(const StepArgs<T>& a, size_t gi) {
   }
 }
 
-// Staging of a P x P footprint (P <= 16 CH) by a 16 x 16 block: every thread issues all of its
-// CH x CH loads (rows ty + 16 i, columns tx + 16 k, clamped into the footprint so that no load
-// needs a branch) before it stores any of them, so the loads overlap instead of each waiting
-// for the one before.
-template <typename T, int KIND, bool FIRST, int CH>
+// Staging of a P x P footprint by a 16 x TY block (P <= TY CHR rows, P <= 16 CHC columns): every
+// thread issues all of its CHR x CHC loads (rows ty + TY i, columns tx + 16 k, clamped into the
+// footprint so that no load needs a branch) before it stores any of them, so the loads overlap
+// instead of each waiting for the one before.
+template <typename T, int KIND, bool FIRST, int CHR, int CHC, int TY>
 __device__ __forceinline__ void stage_batched(const StepArgs<T>& a, T* A, int P, int ry, const int* colw) {
   const int tx = threadIdx.x, ty = threadIdx.y;
-  T v[CH][CH];
+  T v[CHR][CHC];
 #pragma unroll
-  for (int i = 0; i < CH; ++i) {
-    const int r = min(ty + kTile * i, P - 1);
+  for (int i = 0; i < CHR; ++i) {
+    const int r = min(ty + TY * i, P - 1);
     const size_t rowoff = size_t(wrap_index(ry + r, a.n1)) * a.n2;
 #pragma unroll
-    for (int k = 0; k < CH; ++k) v[i][k] = load_src<T, KIND, FIRST>(a, rowoff + colw[k]);
+    for (int k = 0; k < CHC; ++k) v[i][k] = load_src<T, KIND, FIRST>(a, rowoff + colw[k]);
   }
 #pragma unroll
-  for (int i = 0; i < CH; ++i) {
-    const int r = ty + kTile * i;
+  for (int i = 0; i < CHR; ++i) {
+    const int r = ty + TY * i;
 #pragma unroll
-    for (int k = 0; k < CH; ++k) {
+    for (int k = 0; k < CHC; ++k) {
       const int c = tx + kTile * k;
       if (r < P && c < P) A[r * P + c] = v[i][k];
     }
@@ -239,7 +239,7 @@ __device__ __forceinline__ void stage_batched(const StepArgs<T>& a, T* A, int P,
 // B1 = (P + R) x G row-filtered values.  Each filter pass gives a thread R consecutive outputs
 // from a register window of R + 2K inputs; consecutive threads take consecutive rows (row pass)
 // or columns (column pass), so the window loads do not conflict across LDS banks.
-template <typename T, int KIND, bool FIRST>
+template <typename T, int KIND, bool FIRST, int TY>
 __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, int y0, int x0, int lo, int G) {
   constexpr int K = FilterTaps<T>::K;
   constexpr int R = FilterTaps<T>::R;
@@ -250,7 +250,8 @@ __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, i
   const int ry = y0 - lo - K, rx = x0 - lo - K;
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * kTile + tx;
-  // 1. stage (periodic wrap), rows ty + 16 i, columns tx + 16 k
+  constexpr int NTH = kTile * TY;
+  // 1. stage (periodic wrap), rows ty + TY i, columns tx + 16 k
   int colw[kMaxChunks];
 #pragma unroll
   for (int k = 0; k < kMaxChunks; ++k) {
@@ -258,11 +259,11 @@ __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, i
     colw[k] = c < P ? wrap_index(rx + c, n2) : 0;
   }
   if (P <= 4 * kTile) {
-    stage_batched<T, KIND, FIRST, 4>(a, A, P, ry, colw);
+    stage_batched<T, KIND, FIRST, (4 * kTile + TY - 1) / TY, 4, TY>(a, A, P, ry, colw);
   } else if (P <= 6 * kTile) {
-    stage_batched<T, KIND, FIRST, 6>(a, A, P, ry, colw);
+    stage_batched<T, KIND, FIRST, (6 * kTile + TY - 1) / TY, 6, TY>(a, A, P, ry, colw);
   } else {
-    for (int r = ty; r < P; r += kTile) {
+    for (int r = ty; r < P; r += TY) {
       const size_t rowoff = size_t(wrap_index(ry + r, n1)) * n2;
       T* dst = A + r * P;
 #pragma unroll
@@ -275,7 +276,7 @@ __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, i
   __syncthreads();
   const int segs = (G + R - 1) / R;
   // 2. prefilter along x2: thread -> (row r, segment q), outputs at columns q R .. q R + R - 1
-  for (int sidx = tid; sidx < P * segs; sidx += kTile * kTile) {
+  for (int sidx = tid; sidx < P * segs; sidx += NTH) {
     const int q = sidx / P, r = sidx - q * P;
     const T* src = A + r * P + q * R;
     T x[R + 2 * K];
@@ -292,7 +293,7 @@ __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, i
   }
   __syncthreads();
   // 3. prefilter along x1: thread -> (column c, segment q), outputs at rows q R .. q R + R - 1
-  for (int sidx = tid; sidx < G * segs; sidx += kTile * kTile) {
+  for (int sidx = tid; sidx < G * segs; sidx += NTH) {
     const int q = sidx / G, c = sidx - q * G;
     const T* src = B1 + (q * R) * G + c;
     T x[R + 2 * K];
@@ -531,8 +532,16 @@ __global__ void __launch_bounds__(Prefilter2D<T>::NT) k_prefilter_2d(StepArgs<T>
   }
 }
 
-template <typename T, int KIND, bool FIRST, bool GLOBAL>
-__global__ void __launch_bounds__(256) k_sl_step(StepArgs<T> args) {
+// Thread rows TY of the fused step's 16 x 16 tile.  On launches of at most kWideBlocks blocks
+// (grids up to 256^2 per item: about one tile per CU, latency-bound) two threads per node share
+// the staging and the prefilter -- the step's longest phase runs one round of filter tasks
+// instead of two, with two waves per SIMD to cover each other's LDS latency -- and the gather and
+// update take the first 16 rows; larger launches keep 16 x 16 blocks, which fill the CUs better.
+constexpr int kFusedRows = 2 * kTile;
+constexpr long long kWideBlocks = 512;
+
+template <typename T, int KIND, bool FIRST, bool GLOBAL, int TY = kTile>
+__global__ void __launch_bounds__(kTile * TY) k_sl_step(StepArgs<T> args) {
   if (args.active && !args.active[blockIdx.z]) return;
   const StepArgs<T> a = item_view(args, blockIdx.z);
   extern __shared__ unsigned char smem_raw[];
@@ -550,7 +559,7 @@ __global__ void __launch_bounds__(256) k_sl_step(StepArgs<T> args) {
   xcd_tile(by, bx);
   const int y0 = by * kTile, x0 = bx * kTile;
   const int i1 = y0 + threadIdx.y, i2 = x0 + threadIdx.x;
-  const bool inside = i1 < n1 && i2 < n2;
+  const bool inside = threadIdx.y < kTile && i1 < n1 && i2 < n2;
   const size_t gi = inside ? size_t(i1) * n2 + i2 : 0;
   // per-node operands, loaded before the staging so that their latency overlaps it
   const T dd1 = a.d1[gi], dd2 = a.d1[gi + F];
@@ -585,7 +594,7 @@ __global__ void __launch_bounds__(256) k_sl_step(StepArgs<T> args) {
       ex2 = a.addf[gi + F];
     }
   }
-  if constexpr (!GLOBAL) stage_coefficients<T, KIND, FIRST>(a, C, y0, x0, D + 1, G);
+  if constexpr (!GLOBAL) stage_coefficients<T, KIND, FIRST, TY>(a, C, y0, x0, D + 1, G);
 
   // gather at the departure point of this thread's node and update
   double red_s = 0.0, red_m = 0.0;
@@ -750,22 +759,29 @@ int sl_step_max_halo() {
   return D;
 }
 
+template <typename T, int KIND, bool FIRST, int TY>
+hipError_t launch_fused(hipStream_t s, const StepArgs<T>& a, dim3 grid) {
+  const size_t lds = step_lds_bytes<T>(kTile + 2 * a.halo + 3);
+  auto kfn = k_sl_step<T, KIND, FIRST, false, TY>;
+  static std::atomic<size_t> attr_set{0};  // largest dynamic LDS size allowed for this kernel
+  if (lds > attr_set.load(std::memory_order_acquire)) {
+    std::lock_guard<std::mutex> lock(g_setup_mutex);
+    if (lds > attr_set.load(std::memory_order_relaxed)) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      if (e != hipSuccess) return e;
+      attr_set.store(lds, std::memory_order_release);
+    }
+  }
+  hipLaunchKernelGGL(kfn, grid, dim3(kTile, TY), lds, s, a);
+  return hipGetLastError();
+}
+
 template <typename T, int KIND, bool FIRST>
 hipError_t launch_step(hipStream_t s, const StepArgs<T>& a, dim3 grid, dim3 block, bool fused) {
   if (fused) {
-    const size_t lds = step_lds_bytes<T>(kTile + 2 * a.halo + 3);
-    auto kfn = k_sl_step<T, KIND, FIRST, false>;
-    static std::atomic<size_t> attr_set{0};  // largest dynamic LDS size allowed for this kernel
-    if (lds > attr_set.load(std::memory_order_acquire)) {
-      std::lock_guard<std::mutex> lock(g_setup_mutex);
-      if (lds > attr_set.load(std::memory_order_relaxed)) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-        attr_set.store(lds, std::memory_order_release);
-      }
-    }
-    hipLaunchKernelGGL(kfn, grid, block, lds, s, a);
+    if ((long long)grid.x * grid.y * grid.z <= kWideBlocks) return launch_fused<T, KIND, FIRST, kFusedRows>(s, a, grid);
+    return launch_fused<T, KIND, FIRST, kTile>(s, a, grid);
   } else if (!a.two_pass_coef && a.n1 >= Prefilter2D<T>::PS && a.n2 >= Prefilter2D<T>::PS) {
     using P2 = Prefilter2D<T>;
     static std::atomic<size_t> attr2{0};
