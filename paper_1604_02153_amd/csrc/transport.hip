@@ -33,7 +33,7 @@ struct FilterTaps;
 template <>
 struct FilterTaps<float> {
   static constexpr int K = 13;
-  static constexpr int R = 4;
+  static constexpr int R = 8;
 };
 template <>
 struct FilterTaps<double> {
@@ -204,6 +204,35 @@ __device__ __forceinline__ T load_src(const StepArgs<T>& a, size_t gi) {
   }
 }
 
+// R consecutive outputs o[j] = sum_{|t| <= K} tap_t x[K + j + t] of the truncated exponential filter
+// (tap_t = tap_0 z^t, z = sqrt(3) - 2) from a window x of R + 2K values.  The causal half
+// P_j = sum_{t=0..K} tap_t x[K + j - t] of the first output and the anticausal half
+// Q_j = sum_{t=1..K} tap_t x[K + j + t] of the last are summed directly; the others follow from the
+// first-order recursions of the exponential taps, which keep the truncation exactly:
+//   P_{j+1} = tap_0 x[K+j+1] + z P_j - z tap_K x[j],  Q_j = z (tap_0 x[K+j+1] + Q_{j+1}) - z tap_K x[2K+j+1]
+// (|z| < 0.27, so rounding errors decay along the recursion).
+template <typename T, int R, int K>
+__device__ __forceinline__ void filter_window(const T* x, T* o) {
+  const T z = T(-0.26794919243112270647);
+  const T t0 = tap<T>(0), zK = z * tap<T>(K);
+  T q[R];
+  T acc = T(0);
+#pragma unroll
+  for (int t = 1; t <= K; ++t) acc += tap<T>(t) * x[K + R - 1 + t];
+  q[R - 1] = acc;
+#pragma unroll
+  for (int j = R - 2; j >= 0; --j) q[j] = z * (t0 * x[K + j + 1] + q[j + 1]) - zK * x[2 * K + j + 1];
+  T pc = T(0);
+#pragma unroll
+  for (int t = 0; t <= K; ++t) pc += tap<T>(t) * x[K - t];
+  o[0] = pc + q[0];
+#pragma unroll
+  for (int j = 0; j < R - 1; ++j) {
+    pc = t0 * x[K + j + 1] + z * pc - zK * x[j];
+    o[j + 1] = pc + q[j + 1];
+  }
+}
+
 // Staging of a P x P footprint by a 16 x TY block (P <= TY CHR rows, P <= 16 CHC columns): every
 // thread issues all of its CHR x CHC loads (rows ty + TY i, columns tx + 16 k, clamped into the
 // footprint so that no load needs a branch) before it stores any of them, so the loads overlap
@@ -235,8 +264,8 @@ __device__ __forceinline__ void stage_batched(const StepArgs<T>& a, T* A, int P,
 // at global node (y0 - lo, x0 - lo) and is left at LDS offset 0 of 'A'.  The step kernel uses
 // lo = D + 1, G = 16 + 2D + 3 (the stencil footprint of displacements |d| <= D); the
 // coefficient-only kernel uses lo = 0, G = 16.
-// LDS layout: A = P x P staged values (later the G x G coefficients), R words of slack, then
-// B1 = (P + R) x G row-filtered values.  Each filter pass gives a thread R consecutive outputs
+// LDS layout: A = P x P staged values (later the G x G coefficients), R words of slack (zero), then
+// B1 = (P + R) x G row-filtered values (the last R rows zero).  Each filter pass gives a thread R consecutive outputs
 // from a register window of R + 2K inputs; consecutive threads take consecutive rows (row pass)
 // or columns (column pass), so the window loads do not conflict across LDS banks.
 template <typename T, int KIND, bool FIRST, int TY>
@@ -251,6 +280,12 @@ __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, i
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * kTile + tx;
   constexpr int NTH = kTile * TY;
+  // The last window of a row (column) reaches up to R - 1 values past the footprint: into the next
+  // staged row, or into the R slack words after A and the R extra rows of B1, which are zeroed
+  // here.  The recursive filter carries those values into the valid outputs (multiplied by taps
+  // that cancel exactly), so they must be finite.
+  for (int i = tid; i < R; i += NTH) A[P * P + i] = T(0);
+  for (int i = tid; i < R * G; i += NTH) B1[P * G + i] = T(0);
   // 1. stage (periodic wrap), rows ty + TY i, columns tx + 16 k
   int colw[kMaxChunks];
 #pragma unroll
@@ -279,16 +314,14 @@ __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, i
   for (int sidx = tid; sidx < P * segs; sidx += NTH) {
     const int q = sidx / P, r = sidx - q * P;
     const T* src = A + r * P + q * R;
-    T x[R + 2 * K];
+    T x[R + 2 * K], o[R];
 #pragma unroll
     for (int i = 0; i < R + 2 * K; ++i) x[i] = src[i];
+    filter_window<T, R, K>(x, o);
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-      T acc = tap<T>(0) * x[j + K];
-#pragma unroll
-      for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[j + K - t] + x[j + K + t]);
       const int c = q * R + j;
-      if (c < G) B1[r * G + c] = acc;
+      if (c < G) B1[r * G + c] = o[j];
     }
   }
   __syncthreads();
@@ -296,16 +329,14 @@ __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, i
   for (int sidx = tid; sidx < G * segs; sidx += NTH) {
     const int q = sidx / G, c = sidx - q * G;
     const T* src = B1 + (q * R) * G + c;
-    T x[R + 2 * K];
+    T x[R + 2 * K], o[R];
 #pragma unroll
     for (int i = 0; i < R + 2 * K; ++i) x[i] = src[i * G];
+    filter_window<T, R, K>(x, o);
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-      T acc = tap<T>(0) * x[j + K];
-#pragma unroll
-      for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[j + K - t] + x[j + K + t]);
       const int r = q * R + j;
-      if (r < G) C[r * G + c] = acc;
+      if (r < G) C[r * G + c] = o[j];
     }
   }
   __syncthreads();
