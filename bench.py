@@ -305,6 +305,7 @@ def batched(args, dev):
         "per_pair_time_to_stop_ms": {"median": round(stop[len(stop) // 2], 1), "max": round(stop[-1], 1)},
         "all_pairs_grel_le_1e-2": all(r["grel"][-1] <= 1e-2 for r in reps),
         "newton_iters": [r["newton_iters"] for r in reps],
+        "pcg_iters": [r["pcg_iters"] for r in reps],
         "autotune": [{"n": b[0], "pairs": b[2], "sl_path": b[3], "graphs": b[4], "op_ms": round(ms, 3)}
                      for b, ms in zip(buckets, tuned)],
     }
