@@ -107,3 +107,13 @@ def test_nested_pcg_batch_items_match_single_contexts(slnk):
         assert torch.equal(zb[z], z1), z
         c1.close()
     cb.close()
+
+
+def test_variant_parameters_are_validated(slnk):
+    """slnk_create rejects unknown Hessian, projection and coarse-solver choices and eps outside
+    (0, 1) with SLNK_EINVAL."""
+    for kw in (dict(hessian=2), dict(proj=2), dict(coarse_solver=2), dict(coarse_solver="pcg", coarse_eps=1.0),
+               dict(coarse_solver="pcg", coarse_eps=0.0)):
+        with pytest.raises(slnk.SlnkError) as e:
+            slnk.Context(32, 32, 2, prec="fp64", pc="2l", **kw)
+        assert e.value.status == 1, kw
