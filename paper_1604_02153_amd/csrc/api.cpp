@@ -571,13 +571,11 @@ struct Context {
       HIPCHK(dot<double>(stream, B, 2 * F, v64[slot], bAv64[slot], partial + partial_half, dres + 4 * B));
       HIPCHK(cast_copy<T>(stream, B * 2 * F, bAv64[slot], L.bAv));
     }
-    const double* r = fetch(0);
+    const double* r = reg_term ? fetch_both() : fetch(0);  // one synchronisation for both halves
     std::vector<double> maxd(B), vAv(B, 0.0);
     for (int z = 0; z < B; ++z) maxd[z] = r[4 * z + 1];
-    if (reg_term) {
-      const double* r2 = fetch(1);
-      for (int z = 0; z < B; ++z) vAv[z] = r2[4 * z];
-    }
+    if (reg_term)
+      for (int z = 0; z < B; ++z) vAv[z] = r[4 * B + 4 * z];
     for (int z = 0; z < B; ++z) {
       if (!hmask.empty() && !hmask[z]) continue;
       if (!std::isfinite(maxd[z]) || !std::isfinite(vAv[z])) throw Fail{SLNK_ENAN, "non-finite velocity or displacement"};
