@@ -517,8 +517,8 @@ def main():
         probe()
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
-              "described in DESIGN.md and not measured.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); runs on several GPUs are not "
+              "part of this benchmark.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
