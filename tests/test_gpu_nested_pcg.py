@@ -117,3 +117,23 @@ def test_variant_parameters_are_validated(slnk):
         with pytest.raises(slnk.SlnkError) as e:
             slnk.Context(32, 32, 2, prec="fp64", pc="2l", **kw)
         assert e.value.status == 1, kw
+
+
+def test_degenerate_inputs_give_zero(slnk):
+    """Zero inputs: the PCG(eps) preconditioner (its coarse CG stops before the first step), and
+    the full-Newton matvec with K = Leray, both return exact zeros."""
+    n = 64
+    L, vgen, vt = problem("gauss", n, n, nt=2, beta=1e-3, reg=2)
+    for kw in (dict(coarse_solver="pcg", coarse_eps=0.1), dict(hessian="fn", proj="leray")):
+        ctx = slnk.Context(n, n, 2, reg="h2", beta=1e-3, prec="fp64", pc="2l", **kw)
+        ctx.set_images(_t(L.mR, "fp64"), _t(L.mT, "fp64"))
+        g = torch.empty((2, n, n), dtype=torch.float64, device="cuda")
+        ctx.gradient(_t(0.5 * vgen, "fp64"), g)
+        zero = torch.zeros_like(g)
+        out = torch.full_like(g, 7.0)
+        ctx.precond_apply(zero, out)
+        assert torch.count_nonzero(out).item() == 0, kw
+        out.fill_(7.0)
+        ctx.hessian_matvec(zero, out)
+        assert torch.count_nonzero(out).item() == 0, kw
+        ctx.close()
