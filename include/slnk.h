@@ -192,13 +192,15 @@ slnk_status slnk_gradient(slnk_ctx* ctx, const void* v, void* g, double* J);
  * any slnk_gradient. */
 slnk_status slnk_hessian_matvec(slnk_ctx* ctx, const void* vt, void* Hvt);
 
-/* out = (I + S Q S) s, the split spectrally preconditioned GN Hessian (section 3.4.2) at the
- * last linearisation point (the operator P_2L preconditions). */
+/* out = (I + S Q S) s, the split spectrally preconditioned Hessian (section 3.4.2; Q of the
+ * Gauss--Newton or full-Newton matvec the parameters select, K applied) at the last
+ * linearisation point (the operator P_2L preconditions). */
 slnk_status slnk_split_matvec(slnk_ctx* ctx, const void* s, void* out);
 
 /* z = P^{-1} r.  SLNK_PC_REG: P_REG^{-1} = (beta A')^{-1} (eq. e:reg-precond).  SLNK_PC_2L:
- * P_2L^{-1} r = (I - L) r + Pro CHEB_k(M_c) Res r at the last linearisation point (section 3.4.2),
- * acting on the split variable.  EINVAL for P_2L before any slnk_gradient. */
+ * P_2L^{-1} r = (I - L) r + Pro C(M_c) Res r at the last linearisation point (section 3.4.2),
+ * acting on the split variable, with C = CHEB_k or (coarse_solver = SLNK_COARSE_PCG) CG on M_c to
+ * the relative residual coarse_eps.  EINVAL for P_2L before any slnk_gradient. */
 slnk_status slnk_precond_apply(slnk_ctx* ctx, const void* r, void* z);
 
 /* Chebyshev bounds of P_2L of every item (arrays of B; after slnk_set_images). */
