@@ -54,7 +54,7 @@ typedef enum {
   SLNK_ELINESEARCH = 5,     /* Armijo backtracking found no acceptable step */
   SLNK_ENEGCURV = 6,        /* PCG met non-positive curvature (informational in the report) */
   SLNK_EMAXIT = 7,          /* iteration limit reached (informational in the report) */
-  SLNK_ECHEB_DIVERGED = 8   /* reserved */
+  SLNK_ECHEB_DIVERGED = 8   /* P_2L stayed indefinite after e_max was re-estimated (per item, informational) */
 } slnk_status;
 
 typedef enum { SLNK_REG_H1 = 1, SLNK_REG_H2 = 2, SLNK_REG_H3 = 3 } slnk_reg;
@@ -153,6 +153,8 @@ typedef struct {
   double time_linesearch_ms;
   double time_to_stop_ms;   /* from the call's start until this item met its stop criterion */
   int fallback;             /* 1: the given start had no smaller ||g||_inf than v = 0 and was replaced by v = 0 */
+  int cheb_reestimates;     /* times a PCG solve found CHEB(k) indefinite (a step's r.z <= 0) and e_max was
+                               re-estimated by Lanczos at the current coarse linearisation (section 4.2.1) */
 } slnk_solve_report;
 
 /* Default parameters / options (paper settings: CHEB(10), 30 Lanczos steps, gtol 1e-2, 1e-5). */
@@ -212,6 +214,12 @@ slnk_status slnk_get_cheb_bounds(const slnk_ctx* ctx, double* emin, double* emax
  * gradient [n1][n2]. */
 slnk_status slnk_get_field(slnk_ctx* ctx, int which, void* out);
 
+/* Chebyshev upper bounds e_max [B] (host) of a P_2L context with images set, in place of the
+ * Lanczos estimate: e.g. an estimate rescaled from a solve with another beta ((e_max - 1) beta does
+ * not depend on beta, section 4.2.1).  EINVAL unless every e_max > e_min is finite.  A solve that
+ * finds the bound too low re-estimates it (slnk_newton_solve). */
+slnk_status slnk_set_cheb_emax(slnk_ctx* ctx, const double* emax);
+
 /* Profiling support: launch one kernel of the hot path 'reps' times back to back on the
  * context's stream between one pair of HIP events and return the elapsed time divided by reps in
  * *avg_ms (each launch covers all items).  which = 0: state SL step, 1: adjoint SL step, 2: incremental state SL step,
@@ -225,9 +233,15 @@ slnk_status slnk_time_kernel(slnk_ctx* ctx, int which, int reps, double* avg_ms)
  * result overwrites it.  A nonzero start is kept only if its ||g||_inf is below that at v = 0,
  * else the item starts from v = 0 (report.fallback = 1).  opts NULL: defaults.  report (array of B, may be NULL) receives one
  * report per item.  Each item stops on its own criteria; the call returns when all have stopped.
- * Returns SLNK_OK when every item met a stop criterion or the Newton limit, else the status of a
- * failed item (SLNK_ELINESEARCH when backtracking failed: that item's velocity is then its last
- * accepted iterate). */
+ * A PCG solve whose step had r.z <= 0 (P_2L with CHEB(k) not positive definite: e_max below the
+ * coarse operator's spectrum) re-estimates that item's e_max by Lanczos on the coarse split
+ * operator at the current iterate and runs again from zero (report.cheb_reestimates).
+ * An item's report.status is SLNK_OK when it met a stop criterion, SLNK_EMAXIT when max_newton
+ * iterations ended it first, SLNK_ELINESEARCH when backtracking failed, SLNK_ECHEB_DIVERGED when
+ * the preconditioner stayed indefinite after the re-estimate (in the last two cases its velocity
+ * is its last accepted iterate).  Returns SLNK_OK when every item met a stop criterion, else the
+ * status of a failed item, or SLNK_EMAXIT (informational) when the only shortfall is the Newton
+ * limit. */
 slnk_status slnk_newton_solve(slnk_ctx* ctx, void* v_inout, const slnk_solve_opts* opts,
                               slnk_solve_report* report);
 
@@ -270,6 +284,12 @@ slnk_status slnk_unet_get_params(slnk_unet* u, float* host);
 slnk_status slnk_unet_set_params(slnk_unet* u, const float* host);
 /* gradient of the loss of the last train_step with respect to every parameter (host FP32) */
 slnk_status slnk_unet_get_grads(slnk_unet* u, float* host);
+/* Diagnostic: launches of the convolution kernel's variants in this process since the last reset
+ * (reset != 0 clears them after reading).  counts[3 (mw - 1) + j]: mw = 1 for output tiles of 16
+ * pixels (H W an odd multiple of 64), 2 for 32 pixels; j = 0, 1, 2 for the reduction over input
+ * channels split 1, 2 or 4 ways across the block's wavefronts (chosen from the number of output
+ * tiles, so that a launch keeps about eight wavefronts per compute unit). */
+void slnk_unet_conv_variants(long long counts[6], int reset);
 /* v [batch][2][H][W] = network(m_R, m_T), images [batch][H][W]; head [batch] (may be NULL)
  * receives the scalar head's output */
 slnk_status slnk_unet_forward(slnk_unet* u, int batch, const float* m_R, const float* m_T, float* v,

@@ -38,7 +38,7 @@ __all__ = [
     "prec_reg", "split_scale", "lowpass", "restrict", "prolong",
     "split_matvec", "chebyshev", "lanczos_max", "splitmix64", "splitmix64_uniform",
     "TwoLevel", "setup_two_level", "apply_two_level",
-    "pcg", "newton_solve", "inner_l2",
+    "pcg", "pcg_reestimating", "reestimate_emax", "newton_solve", "inner_l2",
 ]
 
 
@@ -588,10 +588,13 @@ def apply_two_level(L: Level, tl: TwoLevel, r, outer_tol: float = 1.0):
 def pcg(op, b, prec, tol: float, maxit: int):
     """Preconditioned CG from x = 0 (Hestenes--Stiefel), Euclidean products.
 
-    Stops when ||r|| <= tol ||b||, at maxit, or on non-positive curvature
-    p.Ap <= 0 (then the current iterate, or P^{-1} b at the first step, is
-    returned).  Returns (x, iterations, status) with status 'ok', 'maxit' or
-    'negcurv'.
+    Stops when ||r|| <= tol ||b||, at maxit, on non-positive curvature p.Ap <= 0
+    (then the current iterate, or P^{-1} b at the first step, is returned), or
+    when the preconditioned residual product r.z that gave the step was not
+    positive: the preconditioner is then not positive definite (an e_max below
+    the spectrum makes CHEB(k) indefinite), the iterate is of no use and the
+    status says so.  Returns (x, iterations, status) with status 'ok', 'maxit',
+    'negcurv' or 'indefprec'.
     """
     x = np.zeros_like(b)
     r = np.array(b, dtype=np.float64)
@@ -611,6 +614,8 @@ def pcg(op, b, prec, tol: float, maxit: int):
         r = r - alpha * q
         if float(np.sqrt(np.sum(r * r))) <= tol * bnorm:
             return x, it, "ok"
+        if not rz > 0.0:
+            return x, it, "indefprec"
         z = prec(r)
         rz_next = float(np.sum(r * z))
         p = z + (rz_next / rz) * p
@@ -618,19 +623,47 @@ def pcg(op, b, prec, tol: float, maxit: int):
     return x, maxit, "maxit"
 
 
+def pcg_reestimating(op, b, prec, tol: float, maxit: int, reestimate=None):
+    """pcg; when it finds the preconditioner indefinite and reestimate is given, call it (new
+    Chebyshev bounds) and run PCG once more from zero.  Returns (x, iterations of both runs,
+    status of the last)."""
+    x, its, st = pcg(op, b, prec, tol, maxit)
+    if st == "indefprec" and reestimate is not None:
+        reestimate()
+        x, its2, st = pcg(op, b, prec, tol, maxit)
+        its += its2
+    return x, its, st
+
+
+def reestimate_emax(tl: TwoLevel, lanczos_steps=30, safety=1.05, seed=0x5EED) -> float:
+    """New e_max of CHEB(k) when the preconditioner has turned out indefinite (section 4.2.1:
+    re-estimate the eigenvalues once the preconditioner deteriorates): the Lanczos estimate of
+    setup_two_level, now on the coarse split operator at the coarse problem's current
+    linearisation point."""
+    cg = tl.coarse.grid
+    q0 = splitmix64_uniform(seed, 2 * cg.N).reshape((2,) + cg.shape)
+    return safety * lanczos_max(lambda s: split_matvec(tl.lin_c, s), q0, lanczos_steps)
+
+
 def newton_solve(L: Level, v0=None, pc: str = "reg", max_newton=10, gtol_rel=1e-2, gtol_abs=1e-5,
                  max_pcg=500, armijo_c1=1e-4, max_halvings=10, cheb_iters=10, lanczos_steps=30,
-                 emax_safety=1.05, seed=0x5EED, g0_norms=None, coarse_solver="cheb", coarse_eps=0.1):
+                 emax_safety=1.05, seed=0x5EED, g0_norms=None, coarse_solver="cheb", coarse_eps=0.1,
+                 emax=None):
     """Globalised inexact GN--Krylov solve (sections 3.4.1, 3.5).
 
     Newton step H vt = -g by PCG with the forcing term
     eta_k = min(0.5, ||g_k|| / ||g_0||); Armijo backtracking (alpha halved from
     1, sufficient decrease 1e-4 alpha <g, vt>_L2); stop when
-    ||g_k||_inf / ||g_0||_inf <= gtol_rel or ||g_k||_inf <= gtol_abs.
+    ||g_k||_inf / ||g_0||_inf <= gtol_rel or ||g_k||_inf <= gtol_abs; a solve that reaches
+    max_newton iterations first reports status 'maxit' ('linesearch' when backtracking fails).
     pc = 'reg' runs PCG on H with P_REG; pc = '2l' runs PCG on the split system
     M s = -S g with P_2L and takes vt = S s; coarse_solver 'cheb' inverts the coarse
     operator by CHEB(cheb_iters), 'pcg' by PCG(coarse_eps) to coarse_eps * eta_k.  g_0 is the gradient at v = 0;
-    g0_norms = (||g_0||_inf, ||g_0||_2) may be passed in to skip computing it.
+    g0_norms = (||g_0||_inf, ||g_0||_2) may be passed in to skip computing it.  emax, if given, replaces
+    the Lanczos estimate of the Chebyshev bound (a bound known from elsewhere, e.g. rescaled from a
+    solve with another beta).  A PCG solve that finds CHEB(k) indefinite ('indefprec') re-estimates
+    e_max by Lanczos at the current coarse linearisation and runs again from zero; if that fails too,
+    the solve stops with status 'cheb_diverged'.
     """
     g, p = L.grid, L.prm
     v = np.zeros((2,) + g.shape) if v0 is None else np.array(v0, dtype=np.float64)
@@ -639,7 +672,10 @@ def newton_solve(L: Level, v0=None, pc: str = "reg", max_newton=10, gtol_rel=1e-
     tl = setup_two_level(L, cheb_iters, lanczos_steps, emax_safety, seed, coarse_solver, coarse_eps) \
         if pc == "2l" else None
     if tl is not None:
+        if emax is not None:
+            tl.emax = float(emax)
         rep["emin"], rep["emax"] = tl.emin, tl.emax
+    rep["cheb_reestimates"] = 0
     lin = linearize(L, v)
     grad = gradient(lin)
     if g0_norms is None:
@@ -657,7 +693,10 @@ def newton_solve(L: Level, v0=None, pc: str = "reg", max_newton=10, gtol_rel=1e-
         gtwo = float(np.sqrt(np.sum(grad * grad)))
         rep["grel"].append(ginf / g0_inf)
         rep["J"].append(lin.J)
-        if ginf / g0_inf <= gtol_rel or ginf <= gtol_abs or k == max_newton:
+        if ginf / g0_inf <= gtol_rel or ginf <= gtol_abs:
+            break
+        if k == max_newton:
+            rep["status"] = "maxit"      # the Newton limit ended the solve before convergence
             break
         eta = min(0.5, gtwo / g0_two)
         if tl is None:
@@ -681,7 +720,15 @@ def newton_solve(L: Level, v0=None, pc: str = "reg", max_newton=10, gtol_rel=1e-
                     return z
                 rep["coarse_matvecs"] += max(tl.cheb_iters - 1, 0)
                 return apply_two_level(L, tl, r)
-            s, its, st = pcg(op, -split_scale(g, grad, p.beta, p.reg), prec, eta, max_pcg)
+            def reestimate():
+                tl.emax = reestimate_emax(tl, lanczos_steps, emax_safety, seed)
+                rep["cheb_reestimates"] += 1
+            s, its, st = pcg_reestimating(op, -split_scale(g, grad, p.beta, p.reg), prec, eta, max_pcg,
+                                          reestimate if tl.solver == "cheb" else None)
+            if st == "indefprec":
+                rep["pcg_iters"] += its
+                rep["status"] = "cheb_diverged"
+                break
             vt = split_scale(g, s, p.beta, p.reg)
         rep["pcg_iters"] += its
         slope = inner_l2(g, grad, vt)

@@ -50,7 +50,7 @@ class SolveReport(ctypes.Structure):
                 ("time_total_ms", ctypes.c_double), ("time_gradient_ms", ctypes.c_double),
                 ("time_pcg_ms", ctypes.c_double), ("time_precond_ms", ctypes.c_double),
                 ("time_linesearch_ms", ctypes.c_double), ("time_to_stop_ms", ctypes.c_double),
-                ("fallback", ctypes.c_int)]
+                ("fallback", ctypes.c_int), ("cheb_reestimates", ctypes.c_int)]
 
 
 class UNetParams(ctypes.Structure):
@@ -62,12 +62,12 @@ class UNetParams(ctypes.Structure):
 EXPORTS = ["slnk_default_params", "slnk_default_opts", "slnk_create", "slnk_destroy", "slnk_last_error",
            "slnk_workspace_bytes", "slnk_set_images", "slnk_transport_state", "slnk_objective", "slnk_gradient",
            "slnk_hessian_matvec", "slnk_split_matvec", "slnk_precond_apply", "slnk_get_cheb_bounds",
-           "slnk_get_field", "slnk_time_kernel", "slnk_newton_solve", "slnk_batch_create", "slnk_batch_destroy",
+           "slnk_get_field", "slnk_set_cheb_emax", "slnk_time_kernel", "slnk_newton_solve", "slnk_batch_create", "slnk_batch_destroy",
            "slnk_batch_last_error", "slnk_batch_bucket_info", "slnk_batch_set_images", "slnk_batch_gradient",
            "slnk_batch_hessian_matvec", "slnk_batch_newton_solve", "slnk_batch_autotune", "slnk_unet_default_params",
            "slnk_unet_create", "slnk_unet_destroy", "slnk_unet_last_error", "slnk_unet_param_count",
            "slnk_unet_get_params", "slnk_unet_set_params", "slnk_unet_get_grads", "slnk_unet_forward",
-           "slnk_unet_train_step", "slnk_set_images_learned", "slnk_newton_solve_learned"]
+           "slnk_unet_train_step", "slnk_unet_conv_variants", "slnk_set_images_learned", "slnk_newton_solve_learned"]
 
 
 def library_path() -> str:
@@ -100,6 +100,7 @@ def load_library():
         "slnk_precond_apply": (ctypes.c_int, [V, V, V]),
         "slnk_get_cheb_bounds": (ctypes.c_int, [V, P(ctypes.c_double), P(ctypes.c_double)]),
         "slnk_get_field": (ctypes.c_int, [V, ctypes.c_int, V]),
+        "slnk_set_cheb_emax": (ctypes.c_int, [V, P(ctypes.c_double)]),
         "slnk_time_kernel": (ctypes.c_int, [V, ctypes.c_int, ctypes.c_int, P(ctypes.c_double)]),
         "slnk_newton_solve": (ctypes.c_int, [V, V, P(SolveOpts), P(SolveReport)]),
         "slnk_batch_create": (ctypes.c_int, [P(Params), ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), V, P(V)]),
@@ -122,6 +123,7 @@ def load_library():
         "slnk_unet_forward": (ctypes.c_int, [V, ctypes.c_int, V, V, V, V]),
         "slnk_unet_train_step": (ctypes.c_int, [V, ctypes.c_int, V, V, V, V, ctypes.c_double, P(ctypes.c_double),
                                                 P(ctypes.c_double)]),
+        "slnk_unet_conv_variants": (None, [P(ctypes.c_longlong), ctypes.c_int]),
         "slnk_set_images_learned": (ctypes.c_int, [V, V, V, V]),
         "slnk_newton_solve_learned": (ctypes.c_int, [V, V, V, P(SolveOpts), P(SolveReport)]),
     }
@@ -251,6 +253,13 @@ class Context:
             return a[0], b[0]
         return list(zip(a, b))
 
+    def set_cheb_emax(self, emax):
+        """Chebyshev upper bound(s) of P_2L in place of the Lanczos estimate (one float per item)."""
+        vals = [float(emax)] if self.batch == 1 and not hasattr(emax, "__len__") else [float(x) for x in emax]
+        if len(vals) != self.batch:
+            raise ValueError(f"expected {self.batch} values")
+        self._check(self._lib.slnk_set_cheb_emax(self._ctx, (ctypes.c_double * self.batch)(*vals)))
+
     def get_field(self, which, out):
         ncomp = 2 if which in (1, 2) else 1
         self._check(self._lib.slnk_get_field(self._ctx, int(which), self._ptr(out, ncomp)))
@@ -268,7 +277,7 @@ class Context:
             opts = default_opts(**kw)
         reps = (SolveReport * self.batch)()
         st = self._lib.slnk_newton_solve(self._ctx, self._ptr(v, 2), ctypes.byref(opts), reps)
-        if st not in (0, 5):
+        if st not in (0, 5, 7, 8):  # reported per item: failed line search, Newton limit, indefinite P_2L
             self._check(st)
         out = [self._report(r) for r in reps]
         return out[0] if self.batch == 1 else out
@@ -283,7 +292,7 @@ class Context:
             opts = default_opts(**kw)
         reps = (SolveReport * self.batch)()
         st = self._lib.slnk_newton_solve_learned(self._ctx, unet._u, self._ptr(v, 2), ctypes.byref(opts), reps)
-        if st not in (0, 5):
+        if st not in (0, 5, 7, 8):  # reported per item: failed line search, Newton limit, indefinite P_2L
             self._check(st)
         out = [self._report(r) for r in reps]
         return out[0] if self.batch == 1 else out
@@ -299,7 +308,7 @@ class Context:
             "time_total_ms": rep.time_total_ms, "time_gradient_ms": rep.time_gradient_ms,
             "time_pcg_ms": rep.time_pcg_ms, "time_precond_ms": rep.time_precond_ms,
             "time_linesearch_ms": rep.time_linesearch_ms, "time_to_stop_ms": rep.time_to_stop_ms,
-            "fallback": bool(rep.fallback),
+            "fallback": bool(rep.fallback), "cheb_reestimates": rep.cheb_reestimates,
         }
 
 
@@ -399,7 +408,7 @@ class BatchContext:
             opts = default_opts(**kw)
         reps = (SolveReport * self.npairs)()
         st = self._lib.slnk_batch_newton_solve(self._b, self._ptrs(v, 2), ctypes.byref(opts), reps)
-        if st not in (0, 5):
+        if st not in (0, 5, 7, 8):  # reported per item: failed line search, Newton limit, indefinite P_2L
             self._check(st)
         return [Context._report(r) for r in reps]
 
@@ -468,6 +477,14 @@ class UNet:
         out = np.empty(self.n_params, dtype=np.float32)
         self._check(self._lib.slnk_unet_get_grads(self._u, out.ctypes.data_as(ctypes.c_void_p)))
         return out
+
+    @staticmethod
+    def conv_variant_counts(reset=True) -> dict:
+        """Launches of each convolution kernel variant in this process since the last reset, keyed
+        by (pixels per output tile, ways the channel reduction is split)."""
+        c = (ctypes.c_longlong * 6)()
+        load_library().slnk_unet_conv_variants(c, 1 if reset else 0)
+        return {(16 * mw, ks): int(c[3 * (mw - 1) + j]) for mw in (1, 2) for j, ks in enumerate((1, 2, 4))}
 
     def forward(self, m_R, m_T, v, head=None):
         b, h, w = m_R.shape

@@ -17,6 +17,7 @@
 #include <thread>
 #include <tuple>
 #include <type_traits>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/slnk.h"
@@ -227,6 +228,7 @@ struct Context {
   void* tw64_col = nullptr;
   double* v64[2] = {};
   double* bAv64[2] = {};
+  double* vt64 = nullptr;  // mixed context: FP64 copy of a matvec's input, then beta A of it
   cplx<double>* S64a = nullptr;
   cplx<double>* S64b = nullptr;
   // captured HIP graphs of the matvec and of the preconditioner, keyed by (operation, input,
@@ -387,7 +389,7 @@ struct Context {
     partial_half = size_t(B) * (std::max(reduce_blocks(2 * F), tiles) * 4 + 64);
     size_t bytes = level_bytes(p.n1, p.n2, p.nt, B) + (two_level ? level_bytes(p.n1 / 2, p.n2 / 2, p.nt, B) : 0);
     bytes += (2 * partial_half + 8 * B + 16 * B + 2 * 64 * B + B) * sizeof(double) + 5 * B * sizeof(int) + 8192;
-    bytes += B * (4 * 2 * F * sizeof(double) + 2 * 2 * size_t(p.n1) * spec_stride(p.n2) * sizeof(cplx<double>)) +
+    bytes += B * (5 * 2 * F * sizeof(double) + 2 * 2 * size_t(p.n1) * spec_stride(p.n2) * sizeof(cplx<double>)) +
              2 * (p.n1 + p.n2) * sizeof(cplx<double>) + 16 * 256;
     bytes += B * (2 * F * sizeof(T) + sizeof(float)) + 2 * 256;
     if (full_newton) bytes += B * size_t(6 * p.nt + 5) * F * sizeof(T) + 6 * 256;
@@ -423,6 +425,7 @@ struct Context {
       v64[sl] = arena.take<double>(B * 2 * F);
       bAv64[sl] = arena.take<double>(B * 2 * F);
     }
+    if (std::is_same_v<T, float>) vt64 = arena.take<double>(B * 2 * F);
     S64a = arena.take<cplx<double>>(B * 2 * sg64.spec());
     S64b = arena.take<cplx<double>>(B * 2 * sg64.spec());
     learned_v = arena.take<T>(B * 2 * F);
@@ -809,11 +812,20 @@ struct Context {
       gn_transport(lv, vt, mk);
   }
 
-  // out = beta A vt + Q vt
+  // out = beta A vt + Q vt.  In the mixed context beta A vt is formed in FP64 from the FP32 input
+  // and added to the FP32 transport part in FP64 before the one rounding of the output: an FP32
+  // transform would leave rounding noise of about eps ||vt|| on every mode, which beta a(k)
+  // multiplies by up to beta max|k|^(2 reg) (1e6 for H2 at 256^2, beta = 1e-3).
   void hessian(Level<T>& lv, const T* vt, T* out, const int* mk) {
     transport(lv, vt, mk);
     if (leray) HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, symK(Symbol::One), 2, lv.bt, lv.bt, nullptr, lv.S1, lv.S2));
-    HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, sym(Symbol::Reg), 2, vt, out, lv.bt, lv.S1, lv.S2));
+    if (std::is_same_v<T, float> && &lv == &fine) {  // sg64 and vt64 belong to the fine grid
+      HIPCHK(cast_back<T>(stream, B * 2 * lv.F, vt, vt64));
+      HIPCHK(spec_scale<double>(stream, sg64, B, mk, sym(Symbol::Reg), 2, vt64, vt64, nullptr, S64a, S64b));
+      HIPCHK(add_mixed<T>(stream, B, 2 * lv.F, vt64, lv.bt, out, mk));
+    } else {
+      HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, sym(Symbol::Reg), 2, vt, out, lv.bt, lv.S1, lv.S2));
+    }
   }
 
   // out = s + S Q S s
@@ -840,9 +852,12 @@ struct Context {
   }
 
   // ---- two-level preconditioner -----------------------------------------------------------
-  // Lanczos on (I + S Q(0) S) of every item from one SplitMix64 start vector: tridiagonal
-  // coefficients (al, be) per item
-  void lanczos(std::vector<std::vector<double>>& al, std::vector<std::vector<double>>& be) {
+  // Lanczos on (I + S Q S) from one SplitMix64 start vector: tridiagonal coefficients (al, be) per
+  // item.  Default: Q = Q(0) in closed form, every item.  With mk / hmask: Q at the coarse level's
+  // current linearisation (general transport), only the items of hmask (a re-estimate).
+  void lanczos(std::vector<std::vector<double>>& al, std::vector<std::vector<double>>& be, const int* mk = nullptr,
+               const std::vector<int>& hmask = {}) {
+    const bool current = !hmask.empty();
     const size_t n = 2 * coarse.F;
     std::vector<double> h = splitmix64_uniform(prm.lanczos_seed, n);
     std::vector<T> ht(B * n);
@@ -857,9 +872,12 @@ struct Context {
     HIPCHK(axpby<T>(stream, B, n, 1.0, sc(0), q, 0.0, nullptr, q));
     HIPCHK(fill<T>(stream, B * n, 0.0, qp));
     std::vector<double> beta(B, 0.0);
-    std::vector<int> live(B, 1);
+    std::vector<int> live = current ? hmask : std::vector<int>(B, 1);
     for (int j = 0; j < prm.lanczos_steps; ++j) {
-      split_matvec_zero(coarse, q, w);
+      if (current)
+        split_matvec(coarse, q, w, mk);
+      else
+        split_matvec_zero(coarse, q, w);
       put_scalars(1, beta);
       HIPCHK(axpby<T>(stream, B, n, -1.0, sc(1), qp, 1.0, nullptr, w));
       std::vector<double> alpha = dots(coarse, q, w);
@@ -901,11 +919,30 @@ struct Context {
     // e_min = min_k 1 + 1 / (beta a'(k)) over the coarse modes: the largest |k|^2 is at the
     // corner (nc1/2, nc2/2)
     const double kk = 0.25 * double(coarse.n1) * coarse.n1 + 0.25 * double(coarse.n2) * coarse.n2;
-    const int k = prm.cheb_iters;
-    std::vector<double> itheta(B), tab(2 * size_t(k) * B, 0.0);
     for (int z = 0; z < B; ++z) {
       emax[z] = emax_given ? (*emax_given)[z] : prm.emax_safety * tridiag_max_eig(al[z], be[z]);
       emin[z] = 1.0 + 1.0 / (prm.beta * std::pow(kk, prm.reg));
+    }
+    cheb_tables();
+  }
+
+  // New e_max for the items of hmask whose CHEB(k) turned out indefinite (section 4.2.1:
+  // re-estimate once the preconditioner deteriorates): Lanczos on the coarse split operator at
+  // the current coarse linearisation, same start vector and safety factor as the set-up.
+  void reestimate_emax(const int* mk, const std::vector<int>& hmask) {
+    std::vector<std::vector<double>> al(B), be(B);
+    lanczos(al, be, mk, hmask);
+    for (int z = 0; z < B; ++z)
+      if (hmask[z]) emax[z] = prm.emax_safety * tridiag_max_eig(al[z], be[z]);
+    cheb_tables();
+  }
+
+  // Chebyshev step coefficients of every item from its bounds (device tables read by the
+  // preconditioner, also from captured graphs)
+  void cheb_tables() {
+    const int k = prm.cheb_iters;
+    std::vector<double> itheta(B), tab(2 * size_t(k) * B, 0.0);
+    for (int z = 0; z < B; ++z) {
       if (!(emax[z] > emin[z]) || !std::isfinite(emax[z])) throw Fail{SLNK_ENAN, "invalid Chebyshev bound e_max"};
       // Chebyshev recurrence of every step (Saad, Algorithm 12.1): d <- c1[i] d + c2[i] r
       const double theta = 0.5 * (emax[z] + emin[z]), delta = 0.5 * (emax[z] - emin[z]);
@@ -1106,7 +1143,8 @@ struct Context {
   }
 
   // Per-item PCG from zero on op x = b (relative tolerances tol[z]), in lock step over the items
-  // of 'active'.  Iterations and status of each item in its / st.  Stopped items see zero step
+  // of 'active'.  Iterations and status of each item in its / st (SLNK_OK, SLNK_EMAXIT,
+  // SLNK_ENEGCURV, or SLNK_ECHEB_DIVERGED when the r.z of a step was not positive).  Stopped items see zero step
   // coefficients, which leave their x and r untouched.  The step coefficients are formed in device
   // memory (rz in row 9 of the scalar block); the host synchronises once per iteration, to read the
   // curvature p.q together with the residual norm.
@@ -1132,10 +1170,13 @@ struct Context {
     const int* mk = mask(kMaskPcg);
     put_mask(kMaskPcg, active);
     for (int k = 0; k < B; ++k) outer_tol[k] = tol[k];  // scales the PCG(eps) coarse tolerance
+    // r.z goes to slot 1 of the second result half, which the per-iteration fetch returns with
+    // p.q: a preconditioner that is not positive definite shows as r.z <= 0
+    double* rz_dev = dres + 4 * B + 1;
     precond(r, z, mk, active);
     HIPCHK(axpby<T>(stream, B, n, 1.0, nullptr, z, 0.0, nullptr, p));
-    HIPCHK(dot<T>(stream, B, n, r, z, partial, dres));
-    HIPCHK(pcg_coef(stream, PCG_RZ, B, mk, dres, rz, nullptr, nullptr));
+    HIPCHK(dot<T>(stream, B, n, r, z, partial, rz_dev));
+    HIPCHK(pcg_coef(stream, PCG_RZ, B, mk, rz_dev, rz, nullptr, nullptr));
     for (int it = 1; it <= maxit; ++it) {
       op(p, q, mk, active);
       HIPCHK(dot<T>(stream, B, n, p, q, partial, pq_dev));
@@ -1159,18 +1200,24 @@ struct Context {
           active[k] = 0;
           continue;
         }
-        if (std::sqrt(rr[4 * k]) <= tol[k] * bnorm[k])
+        if (std::sqrt(rr[4 * k]) <= tol[k] * bnorm[k]) {
           active[k] = 0;
-        else
+        } else if (!(pq[4 * k + 1] > 0.0)) {
+          // the r.z that gave this step was not positive: the preconditioner is indefinite and
+          // the iterate of no use (the caller re-estimates the Chebyshev bounds)
+          st[k] = SLNK_ECHEB_DIVERGED;
+          active[k] = 0;
+        } else {
           more = true;
+        }
       }
       if (!more) return;
       if (it == maxit) break;
       put_mask(kMaskPcg, active);
       precond(r, z, mk, active);
-      HIPCHK(dot<T>(stream, B, n, r, z, partial, dres));
+      HIPCHK(dot<T>(stream, B, n, r, z, partial, rz_dev));
       // p <- z + beta p for the running items; stopped items keep p (coefficients 0, 1)
-      HIPCHK(pcg_coef(stream, PCG_BETA, B, mk, dres, rz, sc(6), sc(7)));
+      HIPCHK(pcg_coef(stream, PCG_BETA, B, mk, rz_dev, rz, sc(6), sc(7)));
       HIPCHK(axpby<T>(stream, B, n, 1.0, sc(6), z, 1.0, sc(7), p));
     }
     for (int k = 0; k < B; ++k)
@@ -1377,7 +1424,9 @@ struct Context {
           R[z].grel[k] = grel;
           R[z].J[k] = fine.lin[0].J[z];
         }
-        if (grel <= o.gtol_rel || ginf[z] <= o.gtol_abs || k >= o.max_newton || k >= SLNK_REPORT_MAX_ITERS) {
+        const bool converged = grel <= o.gtol_rel || ginf[z] <= o.gtol_abs;
+        if (converged || k >= o.max_newton || k >= SLNK_REPORT_MAX_ITERS) {
+          if (!converged) status[z] = SLNK_EMAXIT;  // the Newton limit, not the stop test, ended it
           active[z] = 0;
           kit[z] = k;
           t_stop[z] = now_ms() - t_start;
@@ -1395,6 +1444,26 @@ struct Context {
                              fine.S2));
         HIPCHK(axpby<T>(stream, B, n, -1.0, nullptr, rhs, 0.0, nullptr, rhs));
         pcg(rhs, s, eta, o.max_pcg, active, its, st);
+        // an indefinite CHEB(k): new e_max for those items, then their PCG once more from zero
+        std::vector<int> redo(B, 0);
+        for (int z = 0; z < B; ++z) redo[z] = active[z] && st[z] == SLNK_ECHEB_DIVERGED && !coarse_pcg;
+        if (any_of(redo)) {
+          put_mask(kMaskNewton, redo);
+          reestimate_emax(mk, redo);
+          // pcg() starts every item from zero: the retry writes into a spare vector, whose redone
+          // items are copied over their steps
+          T* s2 = fine.vec[4];
+          std::vector<int> its2, st2;
+          pcg(rhs, s2, eta, o.max_pcg, redo, its2, st2);
+          HIPCHK(masked_copy<T>(stream, B, n, s2, (long long)n, s, (long long)n, mk));
+          for (int z = 0; z < B; ++z)
+            if (redo[z]) {
+              its[z] += its2[z];
+              st[z] = st2[z];
+              ++R[z].cheb_reestimates;
+            }
+          put_mask(kMaskNewton, active);
+        }
         HIPCHK(spec_scale<T>(stream, fine.sg, B, mk, sym(Symbol::RegInvSqrt), 2, s, vt, nullptr, fine.S1, fine.S2));
       } else {
         HIPCHK(axpby<T>(stream, B, n, -1.0, nullptr, fine.g, 0.0, nullptr, rhs));
@@ -1405,7 +1474,15 @@ struct Context {
         if (!active[z]) continue;
         R[z].pcg_iters += its[z];
         if (k < SLNK_REPORT_MAX_ITERS) R[z].pcg[k] = its[z];
+        if (st[z] == SLNK_ECHEB_DIVERGED) {  // still indefinite after a new e_max: stop the item
+          status[z] = SLNK_ECHEB_DIVERGED;
+          active[z] = 0;
+          kit[z] = k;
+          t_stop[z] = now_ms() - t_start;
+        }
       }
+      if (!any_of(active)) break;
+      put_mask(kMaskNewton, active);
       // Armijo backtracking per item: trial v + alpha vt (FP64 iterate) in slot 1
       t0 = now_ms();
       std::vector<double> slope = dots(fine, fine.g, vt);
@@ -1473,7 +1550,8 @@ struct Context {
       R[z].time_pcg_ms = t_pcg;
       R[z].time_precond_ms = t_prec;
       R[z].time_linesearch_ms = t_ls;
-      if (status[z] != SLNK_OK) overall = slnk_status(status[z]);
+      // a failed item's status outranks the informational SLNK_EMAXIT
+      if (status[z] != SLNK_OK && (overall == SLNK_OK || overall == SLNK_EMAXIT)) overall = slnk_status(status[z]);
       if (rep) rep[z] = R[z];
     }
     return overall;
@@ -1703,6 +1781,17 @@ slnk_status slnk_get_cheb_bounds(const slnk_ctx* ctx, double* emin, double* emax
   return SLNK_OK;
 }
 
+slnk_status slnk_set_cheb_emax(slnk_ctx* ctx, const double* emax) {
+  if (!emax) return SLNK_EINVAL;
+  return dispatch(ctx, [&](auto& C) {
+    if (!C.two_level || !C.images_set) throw slnk::Fail{SLNK_EINVAL, "needs a P_2L context with images set"};
+    for (int z = 0; z < C.B; ++z)
+      if (!(emax[z] > C.emin[z]) || !std::isfinite(emax[z])) throw slnk::Fail{SLNK_EINVAL, "e_max must exceed e_min"};
+    for (int z = 0; z < C.B; ++z) C.emax[z] = emax[z];
+    C.cheb_tables();
+  });
+}
+
 slnk_status slnk_get_field(slnk_ctx* ctx, int which, void* out) {
   if (!out) return SLNK_EINVAL;
   return dispatch(ctx, [&](auto& C) {
@@ -1880,6 +1969,13 @@ void batch_release(slnk_batch* b) {
   }
 }
 
+// Statuses a solve reports per item without having failed as a call: success, a failed line
+// search or a preconditioner that stayed indefinite (the item keeps its last accepted iterate) and
+// the Newton limit.
+bool solve_outcome(slnk_status st) {
+  return st == SLNK_OK || st == SLNK_ELINESEARCH || st == SLNK_EMAXIT || st == SLNK_ECHEB_DIVERGED;
+}
+
 // Run fn(bucket) for every bucket, one host thread each, after the caller's stream has reached
 // this point; the first failure (in bucket order) is returned with its message.
 template <class Fn>
@@ -1903,7 +1999,7 @@ slnk_status batch_run(slnk_batch* b, Fn&& fn) {
       try {
         HIPCHK(hipStreamWaitEvent(k.stream, ready, 0));
         st[i] = fn(k);
-        if (st[i] != SLNK_OK && st[i] != SLNK_ELINESEARCH) msg[i] = slnk_last_error(k.ctx);
+        if (!solve_outcome(st[i])) msg[i] = slnk_last_error(k.ctx);
         HIPCHK(hipStreamSynchronize(k.stream));
       } catch (const slnk::Fail& e) {
         st[i] = e.st;
@@ -1918,11 +2014,11 @@ slnk_status batch_run(slnk_batch* b, Fn&& fn) {
   (void)hipEventDestroy(ready);
   slnk_status res = SLNK_OK;
   for (size_t i = 0; i < nb; ++i)
-    if (st[i] != SLNK_OK && st[i] != SLNK_ELINESEARCH) {
+    if (!solve_outcome(st[i])) {
       b->err = "bucket " + std::to_string(b->buckets[i].n1) + "x" + std::to_string(b->buckets[i].n2) + ": " + msg[i];
       return st[i];
-    } else if (st[i] == SLNK_ELINESEARCH) {
-      res = SLNK_ELINESEARCH;
+    } else if (st[i] == SLNK_ELINESEARCH || (st[i] == SLNK_EMAXIT && res == SLNK_OK)) {
+      res = st[i];
     }
   return res;
 }
@@ -2056,7 +2152,7 @@ slnk_status slnk_batch_newton_solve(slnk_batch* b, void* const* v_inout, const s
     std::vector<slnk_solve_report> rk(k.pairs.size());
     stage_in(b, k, v_inout, k.vin, 2 * k.F());
     slnk_status st = slnk_newton_solve(k.ctx, k.vin, opts, rk.data());
-    if (st != SLNK_OK && st != SLNK_ELINESEARCH) return st;
+    if (!solve_outcome(st)) return st;
     stage_out(b, k, k.vin, v_inout, 2 * k.F());
     if (reports)
       for (size_t z = 0; z < k.pairs.size(); ++z) reports[k.pairs[z]] = rk[z];

@@ -251,6 +251,9 @@ hipError_t cast_back(hipStream_t s, size_t n, const T* x, double* y);
 template <typename T>
 hipError_t xpay_mixed(hipStream_t s, int batch, size_t n, const double* x, double a, const double* ad, const T* y,
                       double* z, const int* mask);
+// per item z with mask[z] != 0 (mask optional): out = T(x + y) over n elements, the sum in FP64
+template <typename T>
+hipError_t add_mixed(hipStream_t s, int batch, size_t n, const double* x, const T* y, T* out, const int* mask);
 // per item z with mask[z] != 0 (mask optional): n elements from src + z src_stride to
 // dst + z dst_stride
 template <typename T>

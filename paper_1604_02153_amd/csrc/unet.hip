@@ -10,6 +10,8 @@
 // rows 4(l/16)..4(l/16)+3 of column l%16 of the 16x16 result.
 #include "unet_kernels.hpp"
 
+#include <atomic>
+
 namespace slnk {
 namespace unet {
 namespace {
@@ -462,6 +464,14 @@ inline unsigned blocks_for(size_t n) {
 
 }  // namespace
 
+namespace {
+std::atomic<long long> g_conv_launches[6];
+}
+
+void conv_variant_counts(long long out[6], bool reset) {
+  for (int i = 0; i < 6; ++i) out[i] = reset ? g_conv_launches[i].exchange(0) : g_conv_launches[i].load();
+}
+
 hipError_t conv(hipStream_t s, const ConvArgs& a) {
   const int HW = a.H * a.W;
   if (a.cin % 32 || a.cout % 32 || a.xcs % 8 || a.xco % 8 || HW % 64 || a.P % HW) return hipErrorInvalidValue;
@@ -471,6 +481,7 @@ hipError_t conv(hipStream_t s, const ConvArgs& a) {
   const long tiles = long(a.P / (16 * mw)) * (a.cout / 32);
   const int ks = tiles >= 2048 ? 1 : tiles >= 1024 ? 2 : 4;
   const dim3 grid(a.P / (16 * mw * (4 / ks)), a.cout / 32);
+  g_conv_launches[3 * (mw - 1) + (ks == 1 ? 0 : ks == 2 ? 1 : 2)].fetch_add(1);
   if (mw == 2) {
     if (ks == 1)
       hipLaunchKernelGGL((k_conv<2, 1>), grid, dim3(256), 0, s, a);

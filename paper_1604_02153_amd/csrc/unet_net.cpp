@@ -517,6 +517,10 @@ slnk_status slnk_unet_get_grads(slnk_unet* u, float* host) {
   });
 }
 
+void slnk_unet_conv_variants(long long counts[6], int reset) {
+  if (counts) slnk::unet::conv_variant_counts(counts, reset != 0);
+}
+
 slnk_status slnk_unet_forward(slnk_unet* u, int batch, const float* m_R, const float* m_T, float* v, float* head) {
   if (!m_R || !m_T || !v) return SLNK_EINVAL;
   return guard(u, [&] {

@@ -19,21 +19,34 @@ def same_inputs(prec, *arrays):
     return out if len(out) > 1 else out[0]
 
 
-def reg_floor(L, prec, x):
-    """Rounding floor of beta A x: the spectral symbol beta |k|^(2 reg) amplifies the rounding of
-    x and of the FFT (about eps log2 N relative to ||x||) by up to beta max a(k)."""
+# measured errors of the GPU path against the oracle, written out at the end of the session when
+# the environment names a file (PARITY_REPORT)
+ERRORS = []
+
+
+def record(what, err, tol):
+    """Keep and print one measured relative error next to the tolerance it is held to."""
+    ERRORS.append({"what": what, "rel_err": float(err), "tol": float(tol)})
+    print(f"parity {what}: rel err {err:.3e} (tol {tol:.0e})", flush=True)
+
+
+def reg_floor(L, x):
+    """Rounding floor of an FP64 beta A x: the spectral symbol beta |k|^(2 reg) amplifies the
+    rounding of the FFT of x (about eps log2 N relative to ||x||, on every mode) by up to
+    beta max a(k).  Both contexts form beta A in FP64 (the mixed one from its FP32 input), and so
+    does the oracle."""
     g = L.grid
     amax = float(((g.n1 / 2) ** 2 + (g.n2 / 2) ** 2) ** L.prm.reg)
-    return 64.0 * EPS[prec] * L.prm.beta * amax * float(np.linalg.norm(x))
+    return 64.0 * EPS["fp64"] * L.prm.beta * amax * float(np.linalg.norm(x))
 
 
-def split_floor(L, prec, x):
+def split_floor(L, x):
     """Rounding floor of S (beta A x) in the split norm, S = (beta A')^{-1/2}: the FFT rounding of x
     (white over the modes, eps relative) is multiplied by beta a(k) and then by (beta a(k))^{-1/2},
-    i.e. by up to sqrt(beta max a); about 0.5 eps sqrt(beta max a) ||x|| is observed in FP32."""
+    i.e. by up to sqrt(beta max a)."""
     g = L.grid
     amax = float(((g.n1 / 2) ** 2 + (g.n2 / 2) ** 2) ** L.prm.reg)
-    return 8.0 * EPS[prec] * (L.prm.beta * amax) ** 0.5 * float(np.linalg.norm(x))
+    return 8.0 * EPS["fp64"] * (L.prm.beta * amax) ** 0.5 * float(np.linalg.norm(x))
 
 
 def split_norm(L, x):
@@ -45,6 +58,26 @@ def rel(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def check_rel(what, got, ref, tol):
+    """Relative L2 error of a GPU result against the oracle's, recorded and held to tol."""
+    e = rel(got, ref)
+    record(what, e, tol)
+    assert e < tol, (what, e, tol)
+
+
+def check_reg_op(L, got, ref, x, tol, what="operator"):
+    """got ~ ref where ref contains beta A x: relative L2 error at most tol (plus the FP64 rounding
+    floor of beta A x, far below the mixed tolerance; at large grids it sets the FP64 bound), and
+    the same in the split norm that the split-preconditioned PCG works in."""
+    d = got - ref
+    nref = float(np.linalg.norm(ref))
+    e = float(np.linalg.norm(d)) / nref
+    floor = reg_floor(L, x) / nref
+    record(f"{what} {L.grid.n1}x{L.grid.n2} reg{L.prm.reg}", e, tol + floor)
+    assert e <= tol + floor
+    assert split_norm(L, d) <= tol * split_norm(L, ref) + split_floor(L, x)
 
 
 def problem(kind, n1, n2=None, nt=4, beta=1e-3, reg=2, seed=2, amp=0.3):

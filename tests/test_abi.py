@@ -66,7 +66,7 @@ int main(void) {
   F(slnk_solve_report, emax); F(slnk_solve_report, grel); F(slnk_solve_report, J); F(slnk_solve_report, pcg);
   F(slnk_solve_report, time_total_ms); F(slnk_solve_report, time_gradient_ms); F(slnk_solve_report, time_pcg_ms);
   F(slnk_solve_report, time_precond_ms); F(slnk_solve_report, time_linesearch_ms);
-  F(slnk_solve_report, time_to_stop_ms); F(slnk_solve_report, fallback);
+  F(slnk_solve_report, time_to_stop_ms); F(slnk_solve_report, fallback); F(slnk_solve_report, cheb_reestimates);
   printf("slnk_unet_params size %zu 0\n", sizeof(slnk_unet_params));
   F(slnk_unet_params, height); F(slnk_unet_params, width); F(slnk_unet_params, levels);
   F(slnk_unet_params, base_channels); F(slnk_unet_params, max_batch); F(slnk_unet_params, seed);

@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 
 import oracle as O
 import synth
-from gpu_common import TOL, problem, reg_floor, rel, same_inputs, split_floor, split_norm
+from gpu_common import TOL, check_reg_op, problem, record, rel, same_inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -45,10 +45,9 @@ def _ctx(slnk, L, prec, pc="reg", **kw):
     return slnk.Context(L.grid.n1, L.grid.n2, p.nt, reg=reg, beta=p.beta, prec=prec, pc=pc, hessian="fn", **kw)
 
 
-def _check_reg_op(L, prec, got, ref, x, tol):
-    d = got - ref
-    assert np.linalg.norm(d) <= tol * np.linalg.norm(ref) + reg_floor(L, prec, x)
-    assert split_norm(L, d) <= tol * split_norm(L, ref) + split_floor(L, prec, x)
+def _check_reg_op(L, prec, got, ref, x, tol, what="operator"):
+    """got ~ ref where ref contains beta A x (relative L2 and split-norm error, see check_reg_op)."""
+    check_reg_op(L, got, ref, x, tol, f"FN {what} {prec}")
 
 
 def _point(L, vgen, n1, n2):
@@ -90,14 +89,14 @@ def test_full_newton_matvec_matches_oracle(slnk, case):
     assert rel(O.hessian_matvec(lin_gn, vt), h_ref) > 20 * tol["matvec"]
     h = torch.empty_like(g)
     ctx.hessian_matvec(_t(vt, prec), h)
-    _check_reg_op(L, prec, _np(h), h_ref, vt, tol["matvec"])
+    _check_reg_op(L, prec, _np(h), h_ref, vt, tol["matvec"], "matvec")
     ctx.split_matvec(_t(vt, prec), h)
     assert rel(_np(h), O.split_matvec(lin, vt)) < tol["matvec"]
     # a second gradient at another point replaces every kept adjoint level
     v2 = same_inputs(prec, 0.3 * vgen)
     ctx.gradient(_t(v2, prec), g)
     ctx.hessian_matvec(_t(vt, prec), h)
-    _check_reg_op(L, prec, _np(h), O.hessian_matvec(O.linearize(L, v2), vt), vt, tol["matvec"])
+    _check_reg_op(L, prec, _np(h), O.hessian_matvec(O.linearize(L, v2), vt), vt, tol["matvec"], "matvec")
     ctx.close()
 
 
@@ -151,7 +150,7 @@ def test_full_newton_batch_items_match_single_contexts(slnk):
         assert torch.equal(hb[z], h1) and torch.equal(sb[z], s1), z
         c1.close()
         lin = O.linearize(L, v)
-        _check_reg_op(L, prec, _np(hb[z]), O.hessian_matvec(lin, vt), vt, TOL[prec]["matvec"])
+        _check_reg_op(L, prec, _np(hb[z]), O.hessian_matvec(lin, vt), vt, TOL[prec]["matvec"], "matvec")
     cb.close()
 
 

@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 
 import oracle as O
 import synth
-from gpu_common import TOL, problem, reg_floor, rel, same_inputs, split_floor, split_norm
+from gpu_common import TOL, check_reg_op, problem, record, rel, same_inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -42,10 +42,9 @@ def _ctx(slnk, L, prec, pc, **kw):
                         hessian=p.hessian, **kw)
 
 
-def _check_reg_op(L, prec, got, ref, x, tol):
-    d = got - ref
-    assert np.linalg.norm(d) <= tol * np.linalg.norm(ref) + reg_floor(L, prec, x)
-    assert split_norm(L, d) <= tol * split_norm(L, ref) + split_floor(L, prec, x)
+def _check_reg_op(L, prec, got, ref, x, tol, what="operator"):
+    """got ~ ref where ref contains beta A x (relative L2 and split-norm error, see check_reg_op)."""
+    check_reg_op(L, got, ref, x, tol, f"Leray {what} {prec}")
 
 
 CASES = [
@@ -79,10 +78,10 @@ def test_leray_operators_match_oracle(slnk, case):
     J = ctx.gradient(_t(v, prec), g)
     assert abs(J - lin.J) / abs(lin.J) < tol["objective"]
     g_ref = O.gradient(lin)
-    _check_reg_op(L, "fp64", _np(g), g_ref, v, tol["gradient"])
+    _check_reg_op(L, prec, _np(g), g_ref, v, tol["gradient"], "gradient")
     h = torch.empty_like(g)
     ctx.hessian_matvec(_t(vt, prec), h)
-    _check_reg_op(L, prec, _np(h), O.hessian_matvec(lin, vt), vt, tol["matvec"])
+    _check_reg_op(L, prec, _np(h), O.hessian_matvec(lin, vt), vt, tol["matvec"], "matvec")
     ctx.split_matvec(_t(vt, prec), h)
     assert rel(_np(h), O.split_matvec(lin, vt)) < tol["matvec"]
     cg = tl.coarse.grid
@@ -140,8 +139,8 @@ def test_brain512ic_recipe_matches_oracle(slnk):
     ctx.set_images(_t(mR, prec), _t(mT, prec))
     gg = torch.empty((2, n1, n2), dtype=torch.float32, device="cuda")
     ctx.gradient(_t(v, prec), gg)
-    _check_reg_op(L, "fp64", _np(gg), O.gradient(lin), v, TOL[prec]["gradient"])
+    _check_reg_op(L, prec, _np(gg), O.gradient(lin), v, TOL[prec]["gradient"], "gradient")
     h = torch.empty_like(gg)
     ctx.hessian_matvec(_t(vt, prec), h)
-    _check_reg_op(L, prec, _np(h), O.hessian_matvec(lin, vt), vt, TOL[prec]["matvec"])
+    _check_reg_op(L, prec, _np(h), O.hessian_matvec(lin, vt), vt, TOL[prec]["matvec"], "matvec")
     ctx.close()

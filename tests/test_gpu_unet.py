@@ -9,7 +9,7 @@ torch = pytest.importorskip("torch")
 
 import synth
 from oracle import unet_oracle as U
-from gpu_common import problem
+from gpu_common import problem, record
 
 pytestmark = pytest.mark.gpu
 
@@ -48,7 +48,7 @@ def _net(slnk, arch, params, B=2):
     return net
 
 
-@pytest.mark.parametrize("shape", [(64, 64, 3), (64, 128, 4)])
+@pytest.mark.parametrize("shape", [(64, 64, 3), (64, 128, 4), (32, 32, 3)])
 def test_forward_matches_reference(slnk, shape):
     H, W, L = shape
     arch = U.Arch(H, W, levels=L, base=32)
@@ -63,7 +63,11 @@ def test_forward_matches_reference(slnk, shape):
         mR, mT = np.concatenate([mR, mR], axis=2), np.concatenate([mT, mT[:, ::-1]], axis=2)
     v = torch.empty((2, 2, H, W), dtype=torch.float32, device="cuda")
     head = torch.empty((2,), dtype=torch.float32, device="cuda")
+    slnk.UNet.conv_variant_counts(reset=True)
     net.forward(_t(mR), _t(mT), v, head)
+    counts = slnk.UNet.conv_variant_counts()
+    if H == 32:  # coarsest level 8 x 8 = 64 pixels: output tiles of 16 pixels
+        assert counts[(16, 4)] > 0, counts
     v_ref, cache = U.forward(arch, params, mR, mT, bf16=True)
     err = rel(v.cpu().numpy(), v_ref)
     print(f"forward rel err {err:.2e}", flush=True)
@@ -75,11 +79,12 @@ def test_forward_matches_reference(slnk, shape):
     net.close()
 
 
-def test_gradients_match_reference(slnk):
-    arch = U.Arch(64, 64, levels=3, base=32)
+@pytest.mark.parametrize("n", [64, 32])
+def test_gradients_match_reference(slnk, n):
+    arch = U.Arch(n, n, levels=3, base=32)
     params = U.random_params(arch, np.random.default_rng(3)).astype(np.float32).astype(np.float64)
     net = _net(slnk, arch, params)
-    mR, mT, tgt = _case(4)
+    mR, mT, tgt = _case(4, n=n)
     loss = net.train_step(_t(mR), _t(mT), _t(tgt), 0.0)
     g = net.get_grads().astype(np.float64)[: arch.trunk_n]
     v_ref, cache = U.forward(arch, params, mR, mT, bf16=True)
@@ -95,6 +100,83 @@ def test_gradients_match_reference(slnk):
     print("per-layer grad rel err", [(k, f"{a:.1e}", f"{b:.1e}") for k, a, b in errs], flush=True)
     assert all(ew < 3e-2 and eb < 3e-2 for _, ew, eb in errs)
     assert rel(g, g_ref) < 1e-2
+    net.close()
+
+
+def _shipped(slnk, max_batch):
+    import os
+    path = os.path.join(os.path.dirname(slnk.__file__), "weights", "unet_gauss256.bin")
+    net = slnk.UNet(256, 256, 4, 32, max_batch=max_batch, start_kmax=8)
+    net.load(path)
+    return net, U.Arch(256, 256, levels=4, base=32), net.get_params().astype(np.float64)
+
+
+def test_shipped_network_forward_matches_reference(slnk):
+    """The shipped 256^2, 4-level, 32-channel network at batch 1 (the learned solve's forward):
+    output velocity and head against the reference.  Its launches take the kernel variants with
+    32-pixel output tiles and the channel reduction split 1 (65536-pixel level), 2 (128^2 level)
+    and 4 ways (the two coarsest levels)."""
+    from paper_1604_02153_amd.train_unet import make_pair
+    net, arch, params = _shipped(slnk, 1)
+    assert arch.n == net.n_params
+    mT, vg = make_pair(200100)
+    import oracle as O
+    mR = O.transport_state(O.Grid(256, 256), vg.astype(np.float64), mT.astype(np.float64), 4)
+    mR, mT = mR[None].astype(np.float32), mT[None].astype(np.float32)
+    v = torch.empty((1, 2, 256, 256), dtype=torch.float32, device="cuda")
+    head = torch.empty((1,), dtype=torch.float32, device="cuda")
+    slnk.UNet.conv_variant_counts(reset=True)
+    net.forward(_t(mR), _t(mT), v, head)
+    counts = slnk.UNet.conv_variant_counts()
+    print("variants", counts, flush=True)
+    assert counts[(32, 1)] > 0 and counts[(32, 2)] > 0 and counts[(32, 4)] > 0, counts
+    v_ref, cache = U.forward(arch, params, mR, mT, bf16=True)
+    err = rel(v.cpu().numpy(), v_ref)
+    record("U-Net 256^2 forward (shipped weights)", err, 1e-2)
+    assert err < 1e-2
+    eh = rel(head.cpu().numpy(), cache["head"])
+    record("U-Net 256^2 head (shipped weights)", eh, 2.0 ** -8)
+    assert eh < 2.0 ** -8
+    net.close()
+
+
+def test_shipped_network_gradients_match_reference(slnk):
+    """A training step of the shipped 256^2 network at batch 2 (lr 0): the loss and every layer's
+    weight and bias gradients against the reference.  The weight gradients of the 256^2 level sum
+    64 pixel chunks; the forward and input-gradient launches take the unsplit reduction on the two
+    finest levels."""
+    from paper_1604_02153_amd.train_unet import make_pair
+    import oracle as O
+    net, arch, params = _shipped(slnk, 2)
+    mRs, mTs, tgts = [], [], []
+    for s in (200200, 200201):
+        mT, vg = make_pair(s)
+        mRs.append(O.transport_state(O.Grid(256, 256), vg.astype(np.float64), mT.astype(np.float64), 4))
+        mTs.append(mT)
+        tgts.append(vg)
+    mR, mT, tgt = (np.stack(a).astype(np.float32) for a in (mRs, mTs, tgts))
+    slnk.UNet.conv_variant_counts(reset=True)
+    loss = net.train_step(_t(mR), _t(mT), _t(tgt), 0.0)
+    counts = slnk.UNet.conv_variant_counts()
+    print("variants", counts, flush=True)
+    assert counts[(32, 1)] > 0 and counts[(32, 2)] > 0, counts
+    g = net.get_grads().astype(np.float64)[: arch.trunk_n]
+    v_ref, cache = U.forward(arch, params, mR, mT, bf16=True)
+    l_ref, dv = U.mse(v_ref, tgt)
+    g_ref = U.backward(arch, cache, dv, bf16=True)[: arch.trunk_n]
+    assert abs(loss - l_ref) / l_ref < 1e-3
+    worst = 0.0
+    for k, ly in enumerate(arch.layers):
+        nw = 9 * ly["cout"] * ly["cin"]
+        ew = rel(g[ly["woff"]: ly["woff"] + nw], g_ref[ly["woff"]: ly["woff"] + nw])
+        eb = rel(g[ly["boff"]: ly["boff"] + ly["cout"]], g_ref[ly["boff"]: ly["boff"] + ly["cout"]])
+        print(f"layer {k}: weight grad {ew:.2e}, bias grad {eb:.2e}", flush=True)
+        worst = max(worst, ew, eb)
+    record("U-Net 256^2 per-layer gradients, worst (shipped weights)", worst, 3e-2)
+    assert worst < 3e-2
+    eg = rel(g, g_ref)
+    record("U-Net 256^2 all gradients (shipped weights)", eg, 1e-2)
+    assert eg < 1e-2
     net.close()
 
 
@@ -208,6 +290,31 @@ def test_learned_setup_takes_emax_from_the_head(slnk):
     assert emin2 == emin and abs(emax2 - emax_lanczos) / emax_lanczos < 1e-5
     v = torch.empty((2, n, n), dtype=torch.float32, device="cuda")
     r = ctx.newton_solve_learned(net, v)
+    assert r["status"] == "SLNK_OK" and r["grel"][-1] <= 1e-2
+    net.close()
+    ctx.close()
+
+
+def test_learned_emax_below_the_spectrum_is_reestimated(slnk):
+    """A head that predicts e_max far below the Lanczos value (CHEB(10) indefinite): the learned
+    solve detects it in PCG (r.z <= 0), re-estimates e_max by Lanczos and still converges."""
+    n = 64
+    L, vgen, _ = problem("gauss", n, n, nt=4, beta=1e-3, reg=2, seed=21)
+    mR, mT = _t(L.mR[None]), _t(L.mT[None])
+    net = slnk.UNet(n, n, 3, 32, max_batch=1)
+    ctx = slnk.Context(n, n, 4, reg="h2", beta=1e-3, prec="mixed", pc="2l")
+    ctx.set_images(mR[0], mT[0])
+    emin, emax_lanczos = ctx.cheb_bounds()
+    w = net.get_params()
+    arch = U.Arch(n, n, levels=3, base=32)
+    w[arch.hb_off] = np.log(1e-3 * 0.05 * (emax_lanczos - 1.0) / 1.1)   # e_max - 1 at 5% of Lanczos
+    net.set_params(w)
+    ctx.set_images_learned(net, mR[0], mT[0])
+    assert ctx.cheb_bounds()[1] < 1.0 + 0.06 * (emax_lanczos - 1.0)
+    v = torch.empty((2, n, n), dtype=torch.float32, device="cuda")
+    r = ctx.newton_solve_learned(net, v)
+    print(r["grel"], r["pcg"], r["cheb_reestimates"], flush=True)
+    assert r["cheb_reestimates"] >= 1
     assert r["status"] == "SLNK_OK" and r["grel"][-1] <= 1e-2
     net.close()
     ctx.close()

@@ -60,8 +60,10 @@ def test_kkt_true_solution_recovery(pc):
         tl.lin_c = O.linearize(tl.coarse, np.stack([O.restrict(g, cg, vstar[c]) for c in range(2)]))
         # split system: M s = S H vt*, vt = S s
         b = O.split_scale(g, O.hessian_matvec(lin, vt_true), p.beta, p.reg)
-        s, its, st = O.pcg(lambda s: O.split_matvec(lin, s), b,
-                           lambda r: O.apply_two_level(L, tl, r), 1e-12, 500)
+        # at v* the CHEB(10) bounds estimated at v = 0 leave P_2L slightly indefinite on the last
+        # residuals (r.z < 0 near 1e-8): the solve re-estimates e_max there and runs again
+        s, its, st = O.pcg_reestimating(lambda s: O.split_matvec(lin, s), b, lambda r: O.apply_two_level(L, tl, r),
+                                        1e-12, 500, lambda: setattr(tl, "emax", O.reestimate_emax(tl)))
         x = O.split_scale(g, s, p.beta, p.reg)
     assert st == "ok"
     assert np.linalg.norm(x - vt_true) / np.linalg.norm(vt_true) < 1e-10
@@ -181,3 +183,47 @@ def test_newton_with_nested_pcg_coarse_solve_converges():
     v2, rep2 = O.newton_solve(L, pc="2l", max_newton=10)
     assert rep["pcg_iters"] <= rep2["pcg_iters"]
     assert np.linalg.norm(v - v2) < 2e-2 * np.linalg.norm(v2)
+
+
+def test_newton_limit_is_reported():
+    """A solve that the Newton limit ends before the stop test holds reports 'maxit' (section
+    3.4.1 stops on the gradient; the limit is a safeguard, not convergence)."""
+    L, _ = _smooth_level(n=32, nt=4, beta=1e-2, reg=1)
+    _, full = O.newton_solve(L, pc="reg", max_newton=10, gtol_rel=1e-3)
+    assert full["status"] == "ok" and full["newton_iters"] >= 2 and full["grel"][-1] <= 1e-3
+    _, cut = O.newton_solve(L, pc="reg", max_newton=1, gtol_rel=1e-3)
+    assert cut["status"] == "maxit" and cut["newton_iters"] == 1 and cut["grel"][-1] > 1e-3
+    assert cut["grel"] == full["grel"][:2]
+
+
+def test_pcg_reports_an_indefinite_preconditioner():
+    """PCG on an SPD operator with a preconditioner that has a negative eigenvalue: the first step
+    with r.z <= 0 ends the solve with status 'indefprec'; a positive definite one converges."""
+    d = np.linspace(1.0, 4.0, 2 * 3 * 3).reshape(2, 3, 3)
+    b = np.ones_like(d)
+    pinv = 1.0 / d
+    bad = pinv.copy()
+    bad[0, 0, 0] = -50.0        # r.z = sum r^2 / d with one large negative weight: negative at once
+    _, its, st = O.pcg(lambda s: d * s, b, lambda r: bad * r, 1e-12, 50)
+    assert st == "indefprec" and its == 1
+    x, _, st = O.pcg(lambda s: d * s, b, lambda r: pinv * r, 1e-12, 50)
+    assert st == "ok" and np.abs(d * x - b).max() < 1e-10
+
+
+def test_underestimated_emax_is_reestimated():
+    """An e_max far below the coarse operator's spectrum makes CHEB(10) an indefinite preconditioner
+    (its residual polynomial exceeds one above e_max); the solve detects it, re-estimates e_max by
+    Lanczos at the current coarse linearisation (section 4.2.1) and still converges."""
+    n = 64
+    g = O.Grid(n, n)
+    rng = np.random.default_rng(21)
+    mT = synth.gaussian_sum_isotropic(n, n, rng)
+    vgen = synth.random_velocity(n, n, rng, modes=16, kmax=4, amplitude=0.3)
+    L = O.Level(g, mT, O.transport_state(g, vgen, mT, 4), O.Params(nt=4, beta=1e-3, reg=2))
+    _, ref = O.newton_solve(L, pc="2l", max_newton=10)
+    assert ref["cheb_reestimates"] == 0 and ref["status"] == "ok"
+    low = 1.0 + 0.05 * (ref["emax"] - 1.0)
+    _, rep = O.newton_solve(L, pc="2l", max_newton=10, emax=low)
+    assert rep["emax"] == low
+    assert rep["cheb_reestimates"] >= 1
+    assert rep["status"] == "ok" and rep["grel"][-1] <= 1e-2

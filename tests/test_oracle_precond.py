@@ -156,3 +156,41 @@ def test_two_level_preconditioner_is_symmetric_positive():
     # high modes pass unchanged
     hi = r1 - O.lowpass(g, r1)
     assert np.abs(O.apply_two_level(L, tl, hi) - hi).max() < 1e-12
+
+
+def _fourier_second_derivative(n):
+    """Dense periodic Fourier second-derivative matrix on n (even) equispaced nodes, from its
+    closed-form entries (differentiate the periodic sinc interpolant twice): -pi^2/(3h^2) - 1/6 on
+    the diagonal, -(-1)^(i-j) / (2 sin^2((i-j)h/2)) off it.  Its eigenvalues are -k^2 for
+    |k| <= n/2, the Nyquist mode included."""
+    h = 2 * np.pi / n
+    i = np.arange(n)
+    d = (i[:, None] - i[None, :]) % n
+    with np.errstate(divide="ignore"):
+        D = -((-1.0) ** d) / (2.0 * np.sin(d * h / 2) ** 2)
+    D[d == 0] = -np.pi ** 2 / (3 * h ** 2) - 1.0 / 6.0
+    return D
+
+
+@pytest.mark.parametrize("reg", [1, 2, 3])
+def test_emin_is_smallest_eigenvalue_of_identity_plus_inverse_regulariser(reg):
+    """e_min of P_2L is the smallest eigenvalue of I + (beta A')^{-1} on the coarse grid (section
+    3.4.2, eigenvalue estimates: Q taken as a low-rank perturbation of the identity), A' = A with its
+    zero eigenvalue (the constant) replaced by one.  The operator is assembled densely in real
+    space from the sinc-interpolant differentiation matrices, not from FFT symbols; taking the fine
+    grid's modes, or another regulariser power, changes the value."""
+    fg = O.Grid(16, 24)
+    cg = fg.coarse()
+    beta = 2e-3
+    lap = np.kron(_fourier_second_derivative(cg.n1), np.eye(cg.n2)) + \
+        np.kron(np.eye(cg.n1), _fourier_second_derivative(cg.n2))
+    A = np.linalg.matrix_power(-lap, reg)
+    A = 0.5 * (A + A.T)
+    A_prime = A + np.full(A.shape, 1.0 / cg.N)      # constant eigenvector: eigenvalue 0 -> 1
+    M = np.eye(cg.N) + np.linalg.inv(beta * A_prime)
+    e_dense = float(np.linalg.eigvalsh(0.5 * (M + M.T)).min())
+    rng = np.random.default_rng(9)
+    mT = synth.gaussian_sum_isotropic(fg.n1, fg.n2, rng, count=4)
+    mR = synth.gaussian_sum_isotropic(fg.n1, fg.n2, rng, count=4)
+    tl = O.setup_two_level(O.Level(fg, mT, mR, O.Params(nt=2, beta=beta, reg=reg)), lanczos_steps=5)
+    assert abs(tl.emin - e_dense) < 1e-10 * e_dense
