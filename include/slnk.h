@@ -180,6 +180,20 @@ slnk_status slnk_set_images(slnk_ctx* ctx, const void* m_R, const void* m_T);
  * slnk_set_images.  Does not change the linearisation point. */
 slnk_status slnk_transport_state(slnk_ctx* ctx, const void* v, const void* m0, void* m1);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): slnk_transport_state without a context.  params gives
+ * n1, n2, nt, prec (FP64: double fields, MIXED: float fields), batch (items in v [B][2][n1][n2],
+ * m0 and m1 [B][n1][n2], device pointers the caller owns; m1 may alias m0) and sl_path; its other
+ * fields are ignored.  Work goes on hip_stream (a hipStream_t, NULL: the null stream); the call
+ * synchronises it once, to read the displacement bound.  It allocates nothing: its working memory
+ * is one 16 MiB device array of the library (per GPU, held until the process ends: one item of
+ * up to 448^2 points in FP32 or 320^2 in FP64), and sizes whose working set exceeds it return
+ * SLNK_EINVAL.  Calls that overlap on one GPU (other threads or streams) share that array
+ * and race; each call rewrites every part it reads.  msg (may be NULL) receives a message of at
+ * most msg_len bytes when the call fails.  Results equal slnk_transport_state's up to rounding. */
+slnk_status slnk_transport_state_noalloc(const slnk_params* params, void* hip_stream, const void* v, const void* m0,
+                                         void* m1, char* msg, size_t msg_len);
+
 /* J[v] of every item (eq. e:varopt:objective) into J[0..B).  Makes v the linearisation point. */
 slnk_status slnk_objective(slnk_ctx* ctx, const void* v, double* J);
 

@@ -60,7 +60,7 @@ class UNetParams(ctypes.Structure):
 
 
 EXPORTS = ["slnk_default_params", "slnk_default_opts", "slnk_create", "slnk_destroy", "slnk_last_error",
-           "slnk_workspace_bytes", "slnk_set_images", "slnk_transport_state", "slnk_objective", "slnk_gradient",
+           "slnk_workspace_bytes", "slnk_set_images", "slnk_transport_state", "slnk_transport_state_noalloc", "slnk_objective", "slnk_gradient",
            "slnk_hessian_matvec", "slnk_split_matvec", "slnk_precond_apply", "slnk_get_cheb_bounds",
            "slnk_get_field", "slnk_set_cheb_emax", "slnk_time_kernel", "slnk_newton_solve", "slnk_batch_create", "slnk_batch_destroy",
            "slnk_batch_last_error", "slnk_batch_bucket_info", "slnk_batch_set_images", "slnk_batch_gradient",
@@ -93,6 +93,7 @@ def load_library():
         "slnk_workspace_bytes": (ctypes.c_ulonglong, [V]),
         "slnk_set_images": (ctypes.c_int, [V, V, V]),
         "slnk_transport_state": (ctypes.c_int, [V, V, V, V]),
+        "slnk_transport_state_noalloc": (ctypes.c_int, [P(Params), V, V, V, V, ctypes.c_char_p, ctypes.c_size_t]),
         "slnk_objective": (ctypes.c_int, [V, V, P(ctypes.c_double)]),
         "slnk_gradient": (ctypes.c_int, [V, V, V, P(ctypes.c_double)]),
         "slnk_hessian_matvec": (ctypes.c_int, [V, V, V]),
@@ -310,6 +311,38 @@ class Context:
             "time_linesearch_ms": rep.time_linesearch_ms, "time_to_stop_ms": rep.time_to_stop_ms,
             "fallback": bool(rep.fallback), "cheb_reestimates": rep.cheb_reestimates,
         }
+
+
+def transport_state_noalloc(v, m0, m1, nt, sl_path=0, stream=None):
+    """State transport of m0 by v over nt SL steps into m1 (include/slnk.h,
+    slnk_transport_state_noalloc): no context and no device allocation.  Tensors on one CUDA device,
+    float32 (mixed precision) or float64, v [B][2][n1][n2] or [2][n1][n2], m0 and m1 the matching
+    scalar fields."""
+    import torch
+    lib = load_library()
+    batched = v.dim() == 4
+    B = v.shape[0] if batched else 1
+    n1, n2 = v.shape[-2], v.shape[-1]
+    dt = v.dtype
+    if dt not in (torch.float32, torch.float64):
+        raise ValueError("v must be float32 or float64")
+    want = {id(v): (B, 2, n1, n2) if batched else (2, n1, n2), id(m0): (B, n1, n2) if batched else (n1, n2),
+            id(m1): (B, n1, n2) if batched else (n1, n2)}
+    for t in (v, m0, m1):
+        if not t.is_cuda or t.dtype != dt or tuple(t.shape) != want[id(t)] or not t.is_contiguous():
+            raise ValueError(f"expected contiguous {dt} CUDA tensors of shapes {list(want.values())}")
+    p = Params()
+    lib.slnk_default_params(ctypes.byref(p))
+    p.n1, p.n2, p.nt, p.batch, p.sl_path = int(n1), int(n2), int(nt), int(B), int(sl_path)
+    p.prec = 0 if dt == torch.float64 else 1
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    msg = ctypes.create_string_buffer(256)
+    st = lib.slnk_transport_state_noalloc(ctypes.byref(p), ctypes.c_void_p(stream.cuda_stream),
+                                          ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(m0.data_ptr()),
+                                          ctypes.c_void_p(m1.data_ptr()), msg, 256)
+    if st != 0:
+        raise SlnkError(st, msg.value.decode())
 
 
 class BatchContext:

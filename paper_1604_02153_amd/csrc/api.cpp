@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "../../include/slnk.h"
+#include "fft_plan.hpp"
 #include "kernels.hpp"
 #include "unet_net.hpp"
 
@@ -41,22 +42,6 @@ constexpr double kPi = 3.14159265358979323846;
     if (_e != hipSuccess) throw ::slnk::Fail{SLNK_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)}; \
   } while (0)
 
-bool fft_size_ok(int n) {
-  if (n < 8 || n > 2048 || (n & 1)) return false;
-  for (int r : {2, 3, 5})
-    while (n % r == 0) n /= r;
-  return n == 1;
-}
-
-std::vector<int> factorise(int n) {
-  std::vector<int> r;
-  while (n % 8 == 0) r.push_back(8), n /= 8;
-  while (n % 4 == 0) r.push_back(4), n /= 4;
-  while (n % 2 == 0) r.push_back(2), n /= 2;
-  while (n % 3 == 0) r.push_back(3), n /= 3;
-  while (n % 5 == 0) r.push_back(5), n /= 5;
-  return r;
-}
 
 double trapezoid_weight(int j, int nt) {  // weight of level j times ht
   const double ht = 1.0 / nt;
@@ -254,34 +239,13 @@ struct Context {
   double* sc(int k) const { return dsc + k * B; }
 
   // ---- setup ------------------------------------------------------------------------------
+  // plan of length n: radix list and the 2n-entry table of stage twiddles (consecutive butterflies
+  // read consecutive entries) and roots of unity (wave-level transforms), in arena memory
   template <typename U>
   void plan(FFTPlanDev& pl, int n, void*& tw) {
-    std::vector<int> r = factorise(n);
-    if (int(r.size()) > kFFTMaxStages) throw Fail{SLNK_EINVAL, "FFT length has too many factors"};
-    pl.n = n;
-    pl.nstages = int(r.size());
-    // per-stage twiddles: stage s (radix R, p = product of the earlier radices) holds
-    // w^(j k n / (p R)) = exp(-2 pi i j k / (p R)) at twoff[s] + (j - 1) p + k, j = 1..R-1,
-    // k = 0..p-1 (n - 1 values in all), so that consecutive butterflies read consecutive entries
-    std::vector<cplx<U>> h(2 * size_t(n), cplx<U>{U(1), U(0)});
-    int p = 1, off = 0;
-    for (size_t st = 0; st < r.size(); ++st) {
-      pl.radix[st] = r[st];
-      pl.twoff[st] = off;
-      for (int j = 1; j < r[st]; ++j)
-        for (int k = 0; k < p; ++k) {
-          const double a = 2.0 * kPi * double(j) * double(k) / double(p * r[st]);
-          h[off + (j - 1) * p + k] = {U(std::cos(a)), U(-std::sin(a))};
-        }
-      off += (r[st] - 1) * p;
-      p *= r[st];
-    }
-    pl.ntw = off;
-    // roots of unity exp(-2 pi i m / n), m < n, for the wave-level transforms
-    for (int m = 0; m < n; ++m) {
-      const double a = 2.0 * kPi * double(m) / double(n);
-      h[n + m] = {U(std::cos(a)), U(-std::sin(a))};
-    }
+    std::vector<cplx<U>> h(2 * size_t(n));
+    if (!fft_plan_host(n, pl, [&](int i, double re, double im) { h[i] = {U(re), U(im)}; }))
+      throw Fail{SLNK_EINVAL, "FFT length has too many factors"};
     tw = arena.take<cplx<U>>(2 * n);
     HIPCHK(hipMemcpy(tw, h.data(), 2 * n * sizeof(cplx<U>), hipMemcpyHostToDevice));
     pl.tw = tw;
