@@ -286,7 +286,7 @@ def batched(args, dev):
     mv_rate = 64 * args.batched_matvecs / dt
     gbs = sum(matvec_bytes(n, n, 4) for n in sizes) * args.batched_matvecs / dt / 1e9
     v = [torch.zeros_like(x) for x in vgen]
-    bc.newton_solve(v)  # warm-up solve (graph capture, LDS attributes)
+    warm = bc.newton_solve(v)  # warm-up solve (graph capture, LDS attributes)
     for x in v:
         x.zero_()
     torch.cuda.synchronize()
@@ -294,6 +294,11 @@ def batched(args, dev):
     reps = bc.newton_solve(v)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    counts = lambda rs: [(r["newton_iters"], r["pcg_iters"], r["cheb_reestimates"]) for r in rs]
+    same = counts(warm) == counts(reps)
+    if not same:
+        log("batched: warm-up and timed solves differ: " +
+            str([(p, a, b) for p, (a, b) in enumerate(zip(counts(warm), counts(reps))) if a != b]))
     stop = sorted(r["time_to_stop_ms"] for r in reps)
     buckets = bc.buckets()
     bc.close()
@@ -310,6 +315,8 @@ def batched(args, dev):
         "all_pairs_grel_le_1e-2": all(r["grel"][-1] <= 1e-2 for r in reps),
         "newton_iters": [r["newton_iters"] for r in reps],
         "pcg_iters": [r["pcg_iters"] for r in reps],
+        "cheb_reestimates": [r["cheb_reestimates"] for r in reps],
+        "warmup_and_timed_counts_identical": same,
         "autotune": [{"n": b[0], "pairs": b[2], "sl_path": b[3], "graphs": b[4], "op_ms": round(ms, 3)}
                      for b, ms in zip(buckets, tuned)],
     }

@@ -196,6 +196,9 @@ struct Context {
     T* divv = nullptr;   // F: div v of the slot-0 linearisation
   } fn;
   std::vector<double> emin, emax;
+  // e_max of the set-up (Lanczos at v = 0, the network's head or a caller's value): every solve
+  // starts from it, so that a re-estimate inside one solve does not carry over into the next
+  std::vector<double> emax_setup;
   double* partial = nullptr;  // reduction partials (two independent halves)
   size_t partial_half = 0;
   double* dres = nullptr;     // device results [2][4B]
@@ -247,7 +250,8 @@ struct Context {
     if (!fft_plan_host(n, pl, [&](int i, double re, double im) { h[i] = {U(re), U(im)}; }))
       throw Fail{SLNK_EINVAL, "FFT length has too many factors"};
     tw = arena.take<cplx<U>>(2 * n);
-    HIPCHK(hipMemcpy(tw, h.data(), 2 * n * sizeof(cplx<U>), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(tw, h.data(), 2 * n * sizeof(cplx<U>), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipStreamSynchronize(stream));  // h is released on return
     pl.tw = tw;
     pl.roots = static_cast<cplx<U>*>(tw) + n;
   }
@@ -361,8 +365,9 @@ struct Context {
     if (hipMalloc(&base, bytes) != hipSuccess) throw Fail{SLNK_ENOMEM, "hipMalloc of the workspace failed"};
     arena.base = static_cast<char*>(base);
     arena.size = bytes;
-    // every buffer starts finite: items skipped by a mask may still be read by unmasked updates
-    HIPCHK(hipMemset(base, 0, bytes));
+    // every buffer starts finite: items skipped by a mask may still be read by unmasked updates.
+    // Cleared on the context's stream, which may be non-blocking: ordered before all of its work
+    HIPCHK(hipMemsetAsync(base, 0, bytes, stream));
     partial = arena.take<double>(2 * partial_half);
     dres = arena.take<double>(8 * B);
     dsc = arena.take<double>(16 * B);
@@ -402,6 +407,7 @@ struct Context {
     for (int k = 0; k < 5; ++k) put_mask(k, ones);
     emin.assign(B, 0.0);
     emax.assign(B, 0.0);
+    emax_setup.assign(B, 0.0);
     n_matvec.assign(B, 0);
     n_coarse.assign(B, 0);
     HIPCHK(hipStreamSynchronize(stream));
@@ -888,6 +894,7 @@ struct Context {
       emin[z] = 1.0 + 1.0 / (prm.beta * std::pow(kk, prm.reg));
     }
     cheb_tables();
+    emax_setup = emax;
   }
 
   // New e_max for the items of hmask whose CHEB(k) turned out indefinite (section 4.2.1:
@@ -1328,6 +1335,10 @@ struct Context {
     const size_t n = 2 * fine.F;
     double t_grad = 0, t_pcg = 0, t_ls = 0;
     const std::vector<int> all(B, 1);
+    if (two_level && !coarse_pcg && emax != emax_setup) {  // undo an earlier solve's re-estimates
+      emax = emax_setup;
+      cheb_tables();
+    }
     for (int z = 0; z < B; ++z) {
       R[z].emin = two_level ? emin[z] : 0.0;
       R[z].emax = two_level ? emax[z] : 0.0;
@@ -1753,6 +1764,7 @@ slnk_status slnk_set_cheb_emax(slnk_ctx* ctx, const double* emax) {
       if (!(emax[z] > C.emin[z]) || !std::isfinite(emax[z])) throw slnk::Fail{SLNK_EINVAL, "e_max must exceed e_min"};
     for (int z = 0; z < C.B; ++z) C.emax[z] = emax[z];
     C.cheb_tables();
+    C.emax_setup = C.emax;
   });
 }
 

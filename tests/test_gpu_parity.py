@@ -259,6 +259,11 @@ def test_underestimated_emax_is_reestimated(slnk, prec):
     if prec == "fp64":
         assert rep["newton_iters"] == rep_ref["newton_iters"] and rep["pcg_iters"] == rep_ref["pcg_iters"]
     check_rel(f"Newton v, e_max re-estimated, {prec}", _np(v), v_ref, 1e-9 if prec == "fp64" else 1e-3)
+    # a second solve starts again from the set-up bound, not from the first solve's re-estimate
+    v2 = torch.zeros_like(v)
+    rep2 = ctx.newton_solve(v2, max_newton=10)
+    assert rep2["emax"] == low and rep2["cheb_reestimates"] == rep["cheb_reestimates"]
+    assert rep2["pcg"] == rep["pcg"] and torch.equal(v2, v)
     with pytest.raises(slnk.SlnkError) as e:
         ctx.set_cheb_emax(0.5 * emin)
     assert e.value.status == 1
