@@ -39,6 +39,8 @@ __all__ = [
     "split_matvec", "chebyshev", "lanczos_max", "splitmix64", "splitmix64_uniform",
     "TwoLevel", "setup_two_level", "apply_two_level",
     "pcg", "pcg_reestimating", "reestimate_emax", "newton_solve", "inner_l2",
+    "rk2a_forward_op", "rk2a_adjoint_op", "rk2a_state_source", "rk2a_adjoint_source", "rk2a_integrand",
+    "rk2a_heun", "rk2a_solve_state", "rk2a_solve_adjoint", "rk2a_incremental_state", "rk2a_transport_part",
 ]
 
 
@@ -81,12 +83,17 @@ class Params:
           projection (the incompressible case, w = 0).
     hessian: "gn" for the Gauss--Newton matvec, "fn" for the full-Newton one
           (eq. e:hessian-matvec with every lambda term kept).
+    transport: "sl" for the semi-Lagrangian scheme (section 3.3.2), "rk2a" for
+          the stabilised RK2 scheme (section 3.3.1 and the appendix "Stabilized
+          RK2 Scheme"): the transport equations in antisymmetric form,
+          pseudospectral in space, Heun's method in time.
     """
     nt: int
     beta: float
     reg: int = 2
     proj: int = 0
     hessian: str = "gn"
+    transport: str = "sl"
 
 
 # ---------------------------------------------------------------------------
@@ -283,11 +290,106 @@ class Linearization:
     g: np.ndarray = field(default=None)
 
 
+# ---------------------------------------------------------------------------
+# Stabilised RK2 transport (section 3.3.1; appendix "Stabilized RK2 Scheme")
+# ---------------------------------------------------------------------------
+# The state equation in antisymmetric form, d_t m + L m = 0 with
+#   L u = 1/2 (grad u . v + div(u v) - u div v),
+# its first and second variations (adjoint, incremental state, incremental
+# adjoint) and the b / b~ integrands of the gradient and the Hessian matvec, as
+# the appendix derives them.  Derivatives are spectral (odd orders with the
+# Nyquist mode zeroed), products pointwise; every equation is integrated with
+# Heun's method on the nt uniform steps (the adjoint ones backward in time).
+
+def rk2a_forward_op(g: Grid, v, divv, u):
+    """L u = 1/2 (grad u . v + div(u v) - u div v)."""
+    gu = fft_grad(g, u)
+    return 0.5 * (gu[0] * v[0] + gu[1] * v[1] + fft_div(g, u * v) - u * divv)
+
+
+def rk2a_adjoint_op(g: Grid, v, divv, lam):
+    """A lam = 1/2 (div(lam v) + grad lam . v + lam div v); the adjoint equation is
+    -d_t lam - A lam = 0 (A = -L^T for the discrete operators)."""
+    gl = fft_grad(g, lam)
+    return 0.5 * (fft_div(g, lam * v) + gl[0] * v[0] + gl[1] * v[1] + lam * divv)
+
+
+def rk2a_state_source(g: Grid, m, vt):
+    """S(m) vt = 1/2 (div(m vt) + grad m . vt - m div vt): the terms of the incremental state
+    equation that carry vt (d_t m~ + L m~ + S(m) vt = 0)."""
+    gm = fft_grad(g, m)
+    return 0.5 * (fft_div(g, m * vt) + gm[0] * vt[0] + gm[1] * vt[1] - m * fft_div(g, vt))
+
+
+def rk2a_adjoint_source(g: Grid, lam, vt):
+    """1/2 (div(lam vt) + grad lam . vt + lam div vt): the lambda terms of the full-Newton
+    incremental adjoint equation (-d_t lam~ - A lam~ - this = 0)."""
+    gl = fft_grad(g, lam)
+    return 0.5 * (fft_div(g, lam * vt) + gl[0] * vt[0] + gl[1] * vt[1] + lam * fft_div(g, vt))
+
+
+def rk2a_integrand(g: Grid, lam, m):
+    """1/2 (lam grad m - m grad lam + grad(lam m)): the antisymmetric form of lam grad m in b
+    (and, with lam~ or m~ in place of lam or m, in b~)."""
+    gm, gl, glm = fft_grad(g, m), fft_grad(g, lam), fft_grad(g, lam * m)
+    return 0.5 * (lam * gm - m * gl + glm)
+
+
+def rk2a_heun(op, y, ht, src0=None, src1=None):
+    """One step of Heun's method for dy/dt = op(y) + src(t): predictor with the source at the
+    start of the step, corrector with the source at its end (src None: no source)."""
+    k1 = op(y) + (0.0 if src0 is None else src0)
+    k2 = op(y + ht * k1) + (0.0 if src1 is None else src1)
+    return y + 0.5 * ht * (k1 + k2)
+
+
+def rk2a_solve_state(g: Grid, v, m0, nt: int):
+    """m^0 = m0, m^j from m^{j-1} by Heun on d_t m = -L m (forward in time)."""
+    ht = 1.0 / nt
+    divv = fft_div(g, v)
+    m = [np.array(m0, dtype=np.float64)]
+    for _ in range(nt):
+        m.append(rk2a_heun(lambda u: -rk2a_forward_op(g, v, divv, u), m[-1], ht))
+    return m
+
+
+def rk2a_solve_adjoint(g: Grid, v, lam1, nt: int, sources=None):
+    """lam^nt = lam1, lam^{j-1} from lam^j by Heun on d_s lam = A lam (+ sources[j]), s = 1 - t
+    the backward time; sources (optional, nt + 1 levels) is the known right-hand side."""
+    ht = 1.0 / nt
+    divv = fft_div(g, v)
+    lam = [None] * (nt + 1)
+    lam[nt] = np.array(lam1, dtype=np.float64)
+    for j in range(nt, 0, -1):
+        s0 = None if sources is None else sources[j]
+        s1 = None if sources is None else sources[j - 1]
+        lam[j - 1] = rk2a_heun(lambda u: rk2a_adjoint_op(g, v, divv, u), lam[j], ht, s0, s1)
+    return lam
+
+
+def rk2a_incremental_state(g: Grid, v, m, vt, nt: int):
+    """m~^0 = 0, Heun on d_t m~ = -L m~ - S(m) vt with the source at both ends of each step."""
+    ht = 1.0 / nt
+    divv = fft_div(g, v)
+    src = [-rk2a_state_source(g, mj, vt) for mj in m]
+    mt = [np.zeros(g.shape)]
+    for j in range(1, nt + 1):
+        mt.append(rk2a_heun(lambda u: -rk2a_forward_op(g, v, divv, u), mt[-1], ht, src[j - 1], src[j]))
+    return mt
+
+
 def linearize(L: Level, v) -> Linearization:
-    """Trace both characteristics, solve the state equation, evaluate J."""
+    """Trace both characteristics, solve the state equation, evaluate J (RK2A: no
+    characteristics, the state by Heun's method)."""
     g, p = L.grid, L.prm
     ht = 1.0 / p.nt
     v = np.array(v, dtype=np.float64)
+    if p.transport == "rk2a":
+        m = rk2a_solve_state(g, v, L.mT, p.nt)
+        gradm = [fft_grad(g, mj) for mj in m]
+        Av = apply_reg(g, v, p.reg)
+        J = 0.5 * inner_l2(g, m[-1] - L.mR, m[-1] - L.mR) + 0.5 * p.beta * inner_l2(g, v, Av)
+        return Linearization(L, v, None, None, None, m, gradm, Av, J)
     Xf = trace(g, v, ht, -1)
     Xa = trace(g, v, ht, +1)
     gamma = adjoint_factor(g, v, Xa, ht)
@@ -307,9 +409,13 @@ def gradient(lin: Linearization):
     """Reduced gradient g = beta A v + K int_0^1 lambda grad m dt (eq. e:control-elim)."""
     L = lin.level
     g, p = L.grid, L.prm
-    lam = solve_adjoint(g, lin.Xa, lin.gamma, L.mR - lin.m[-1], p.nt)
     w = trapezoid_weights(p.nt)
-    b = sum(w[j] * lam[j] * lin.gradm[j] for j in range(p.nt + 1))
+    if p.transport == "rk2a":
+        lam = rk2a_solve_adjoint(g, lin.v, L.mR - lin.m[-1], p.nt)
+        b = sum(w[j] * rk2a_integrand(g, lam[j], lin.m[j]) for j in range(p.nt + 1))
+    else:
+        lam = solve_adjoint(g, lin.Xa, lin.gamma, L.mR - lin.m[-1], p.nt)
+        b = sum(w[j] * lam[j] * lin.gradm[j] for j in range(p.nt + 1))
     lin.lam = lam
     lin.g = p.beta * lin.Av + apply_proj(g, b, p.proj)
     return lin.g
@@ -380,8 +486,30 @@ def fn_transport_part(lin: Linearization, vt):
     return apply_proj(g, bt, p.proj)
 
 
+def rk2a_transport_part(lin: Linearization, vt):
+    """Q[vt] = K b~ with RK2A transport (appendix "Stabilized RK2 Scheme"): the incremental
+    state, the incremental adjoint from -m~(1) (full Newton: with its lambda source terms) and
+    b~ = int 1/2 (lam~ grad m - m grad lam~ + grad(lam~ m)) dt (full Newton: plus the same
+    form in lam and m~)."""
+    L = lin.level
+    g, p = L.grid, L.prm
+    mt = rk2a_incremental_state(g, lin.v, lin.m, vt, p.nt)
+    fn = p.hessian == "fn"
+    if fn and lin.lam is None:
+        gradient(lin)
+    src = [rk2a_adjoint_source(g, lam_j, vt) for lam_j in lin.lam] if fn else None
+    lt = rk2a_solve_adjoint(g, lin.v, -mt[-1], p.nt, src)
+    w = trapezoid_weights(p.nt)
+    bt = sum(w[j] * rk2a_integrand(g, lt[j], lin.m[j]) for j in range(p.nt + 1))
+    if fn:
+        bt = bt + sum(w[j] * rk2a_integrand(g, lin.lam[j], mt[j]) for j in range(p.nt + 1))
+    return apply_proj(g, bt, p.proj)
+
+
 def transport_part(lin: Linearization, vt):
-    """Q[vt] of the matvec the parameters select (Gauss--Newton or full Newton)."""
+    """Q[vt] of the matvec the parameters select (Gauss--Newton or full Newton; SL or RK2A)."""
+    if lin.level.prm.transport == "rk2a":
+        return rk2a_transport_part(lin, vt)
     return fn_transport_part(lin, vt) if lin.level.prm.hessian == "fn" else gn_transport_part(lin, vt)
 
 
