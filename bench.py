@@ -208,7 +208,9 @@ def full_newton(args, dev):
 
 def preconditioners(args, dev):
     """gauss256 Newton solves to ||g||rel <= 1e-2 under P_REG, P_2L with CHEB(10) and P_2L with the
-    nested PCG(1e-1) coarse solve (the three schemes of section 4.2.2)."""
+    nested PCG(1e-1) coarse solve (the three schemes of section 4.2.2), all with SL transport at
+    nt = 4, and the paper's earlier solver, P_REG with RK2A transport at CFL 0.2 (on this problem's
+    m_R, made by SL transport)."""
     import numpy as np
     import torch
 
@@ -219,11 +221,17 @@ def preconditioners(args, dev):
     f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=torch.float32)
     mT, vgen = f32(cfg["mT"]), f32(cfg["v_gen"])
     out = {"workload": "gauss256 (256x256, nt=4, H2 beta=1e-3, mixed), Newton to ||g||rel<=1e-2"}
+    # the paper's earlier solver: P_REG with the stabilised RK2 transport at CFL 0.2
+    mR = None
+    nt_rk = max(2, int(np.ceil(float(np.abs(cfg["v_gen"]).max()) * max(n1, n2) / (2 * np.pi * 0.2))))
     for name, kw in (("P_REG", dict(pc="reg")), ("P_2L_CHEB10", dict(pc="2l")),
-                     ("P_2L_PCG0.1", dict(pc="2l", coarse_solver="pcg", coarse_eps=0.1))):
-        ctx = Context(n1, n2, nt, reg="h2", beta=cfg["beta"], prec="mixed", **kw)
-        mR = torch.empty_like(mT)
-        ctx.transport_state(vgen, mT, mR)
+                     ("P_2L_PCG0.1", dict(pc="2l", coarse_solver="pcg", coarse_eps=0.1)),
+                     (f"P_REG_RK2A(0.2)_nt{nt_rk}", dict(pc="reg", transport="rk2a", nt=nt_rk))):
+        kw = dict(kw)
+        ctx = Context(n1, n2, kw.pop("nt", nt), reg="h2", beta=cfg["beta"], prec="mixed", **kw)
+        if mR is None:  # one m_R for every solver: SL transport over nt = 4 steps
+            mR = torch.empty_like(mT)
+            ctx.transport_state(vgen, mT, mR)
         ctx.set_images(mR, mT)
         v = torch.zeros_like(vgen)
         ctx.newton_solve(v, max_newton=20)

@@ -63,6 +63,7 @@ typedef enum { SLNK_PC_REG = 1, SLNK_PC_2L = 2 } slnk_pc;
 typedef enum { SLNK_HESS_GN = 0, SLNK_HESS_FN = 1 } slnk_hessian;
 typedef enum { SLNK_PROJ_NONE = 0, SLNK_PROJ_LERAY = 1 } slnk_proj;
 typedef enum { SLNK_COARSE_CHEB = 0, SLNK_COARSE_PCG = 1 } slnk_coarse_solver;
+typedef enum { SLNK_TRANSPORT_SL = 0, SLNK_TRANSPORT_RK2A = 1 } slnk_transport;
 
 /* Problem and solver parameters (section 3.5 lists the paper's settings).
  *   nt            number of SL time steps on [0, 1] (ht = 1/nt), >= 1
@@ -96,7 +97,14 @@ typedef enum { SLNK_COARSE_CHEB = 0, SLNK_COARSE_PCG = 1 } slnk_coarse_solver;
  *                 SLNK_COARSE_PCG: by the nested PCG(eps) solve of section 3.4.2, CG on the coarse
  *                 split operator from zero to the relative residual coarse_eps times the outer
  *                 PCG tolerance (the forcing term; 1 in slnk_precond_apply), at most 200 steps
- *   coarse_eps    eps of PCG(eps), in (0, 1); the paper uses 1e-1 */
+ *   coarse_eps    eps of PCG(eps), in (0, 1); the paper uses 1e-1
+ *   transport     SLNK_TRANSPORT_SL (default): the semi-Lagrangian scheme of section 3.3.2;
+ *                 SLNK_TRANSPORT_RK2A: the stabilised RK2 scheme of section 3.3.1 and the appendix
+ *                 "Stabilized RK2 Scheme" -- the state, adjoint, incremental state and incremental
+ *                 adjoint equations in antisymmetric form with pseudospectral derivatives, Heun's
+ *                 method on the nt steps, and b, b~ in their antisymmetric forms.  Conditionally
+ *                 stable: nt must follow the CFL condition (the paper uses CFL 0.2).  With P_REG and
+ *                 the Gauss--Newton matvec (the paper's earlier solver); sl_path is ignored */
 typedef struct {
   int n1, n2, nt;
   int reg;
@@ -114,6 +122,7 @@ typedef struct {
   int proj;
   int coarse_solver;
   double coarse_eps;
+  int transport;
 } slnk_params;
 
 /* Newton--Krylov options (sections 3.4.1, 3.5).  Stop when ||g||_inf / ||g_0||_inf <= gtol_rel or

@@ -23,6 +23,7 @@ PREC = {"fp64": 0, "mixed": 1}
 PC = {"reg": 1, "2l": 2}
 HESSIAN = {"gn": 0, "fn": 1}
 PROJ = {"none": 0, "leray": 1}
+TRANSPORT = {"sl": 0, "rk2a": 1}
 COARSE = {"cheb": 0, "pcg": 1}
 REPORT_MAX = 64
 
@@ -33,7 +34,8 @@ class Params(ctypes.Structure):
                 ("cheb_iters", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
                 ("emax_safety", ctypes.c_double), ("lanczos_seed", ctypes.c_ulonglong), ("use_graphs", ctypes.c_int),
                 ("batch", ctypes.c_int), ("sl_path", ctypes.c_int), ("hessian", ctypes.c_int),
-                ("proj", ctypes.c_int), ("coarse_solver", ctypes.c_int), ("coarse_eps", ctypes.c_double)]
+                ("proj", ctypes.c_int), ("coarse_solver", ctypes.c_int), ("coarse_eps", ctypes.c_double),
+                ("transport", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -158,7 +160,8 @@ class Context:
 
     def __init__(self, n1, n2, nt, reg="h2", beta=1e-3, prec="mixed", pc="2l", cheb_iters=10,
                  lanczos_steps=30, emax_safety=1.05, lanczos_seed=0x5EED, use_graphs=True, stream=None,
-                 batch=1, sl_path=0, hessian="gn", proj="none", coarse_solver="cheb", coarse_eps=0.1):
+                 batch=1, sl_path=0, hessian="gn", proj="none", coarse_solver="cheb", coarse_eps=0.1,
+                 transport="sl"):
         import torch
         lib = load_library()
         p = Params()
@@ -177,6 +180,7 @@ class Context:
         p.proj = PROJ[proj] if isinstance(proj, str) else int(proj)
         p.coarse_solver = COARSE[coarse_solver] if isinstance(coarse_solver, str) else int(coarse_solver)
         p.coarse_eps = float(coarse_eps)
+        p.transport = TRANSPORT[transport] if isinstance(transport, str) else int(transport)
         self.batch = p.batch
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -351,7 +355,7 @@ class BatchContext:
 
     def __init__(self, sizes, nt, reg="h2", beta=1e-3, prec="mixed", pc="2l", cheb_iters=10, lanczos_steps=30,
                  emax_safety=1.05, lanczos_seed=0x5EED, use_graphs=True, sl_path=0, stream=None, hessian="gn",
-                 proj="none", coarse_solver="cheb", coarse_eps=0.1):
+                 proj="none", coarse_solver="cheb", coarse_eps=0.1, transport="sl"):
         import torch
         lib = load_library()
         p = Params()
@@ -368,6 +372,7 @@ class BatchContext:
         p.proj = PROJ[proj] if isinstance(proj, str) else int(proj)
         p.coarse_solver = COARSE[coarse_solver] if isinstance(coarse_solver, str) else int(coarse_solver)
         p.coarse_eps = float(coarse_eps)
+        p.transport = TRANSPORT[transport] if isinstance(transport, str) else int(transport)
         self.sizes = [(int(a), int(b)) for a, b in sizes]
         self.npairs = len(self.sizes)
         n1 = (ctypes.c_int * self.npairs)(*[a for a, _ in self.sizes])

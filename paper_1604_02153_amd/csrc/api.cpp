@@ -185,6 +185,20 @@ struct Context {
   bool leray = false;
   // P_2L coarse solver: CHEB(k), or PCG(eps) to eps times the outer tolerance of each item
   bool coarse_pcg = false;
+  // stabilised RK2 transport instead of the SL scheme (fine level; P_REG, Gauss--Newton)
+  bool rk2a = false;
+  struct {
+    T* w3 = nullptr;      // 3F: (y, y v1, y v2) of the Heun stage's input
+    T* d3 = nullptr;      // 3F: its spectral derivatives
+    T* w3s = nullptr;     // 3F, 3F: the same for the incremental state's source terms
+    T* d3s = nullptr;
+    T* k = nullptr;       // F: first-stage slope
+    T* y[2] = {};         // F each: current and next time level
+    T* src[2] = {};       // F each: incremental-state sources at two time levels
+    T* pair = nullptr;    // 2F: (lam, lam m)
+    T* g4 = nullptr;      // 4F: (grad lam, grad(lam m))
+    T* divt = nullptr;    // F: div of the matvec direction
+  } rk;
   std::vector<double> outer_tol;
   static constexpr int kMaxInner = 200;
   struct {
@@ -339,6 +353,11 @@ struct Context {
     if (coarse_pcg && !(p.coarse_eps > 0.0 && p.coarse_eps < 1.0))
       throw Fail{SLNK_EINVAL, "coarse_eps must lie in (0, 1)"};
     outer_tol.assign(B, 1.0);
+    if (p.transport != SLNK_TRANSPORT_SL && p.transport != SLNK_TRANSPORT_RK2A)
+      throw Fail{SLNK_EINVAL, "transport must be SLNK_TRANSPORT_SL or SLNK_TRANSPORT_RK2A"};
+    rk2a = p.transport == SLNK_TRANSPORT_RK2A;
+    if (rk2a && (p.pc != SLNK_PC_REG || full_newton))
+      throw Fail{SLNK_EINVAL, "RK2A transport runs with P_REG and the Gauss--Newton matvec"};
     two_level = p.pc == SLNK_PC_2L;
     if (two_level) {
       if (!fft_size_ok(p.n1 / 2) || !fft_size_ok(p.n2 / 2)) throw Fail{SLNK_EINVAL, "coarse grid n/2 not supported"};
@@ -361,6 +380,7 @@ struct Context {
              2 * (p.n1 + p.n2) * sizeof(cplx<double>) + 16 * 256;
     bytes += B * (2 * F * sizeof(T) + sizeof(float)) + 2 * 256;
     if (full_newton) bytes += B * size_t(6 * p.nt + 5) * F * sizeof(T) + 6 * 256;
+    if (rk2a) bytes += B * size_t(24) * F * sizeof(T) + 14 * 256;  // w3, d3, w3s, d3s 12; k, y, src 5; pair 2; g4 4; divt 1
     void* base = nullptr;
     if (hipMalloc(&base, bytes) != hipSuccess) throw Fail{SLNK_ENOMEM, "hipMalloc of the workspace failed"};
     arena.base = static_cast<char*>(base);
@@ -385,6 +405,18 @@ struct Context {
       fn.sigma = arena.take<T>(B * (p.nt + 1) * F);
       fn.e = arena.take<T>(B * p.nt * F);
       fn.divv = arena.take<T>(B * F);
+    }
+    if (rk2a) {
+      rk.w3 = arena.take<T>(B * 3 * F);
+      rk.d3 = arena.take<T>(B * 3 * F);
+      rk.w3s = arena.take<T>(B * 3 * F);
+      rk.d3s = arena.take<T>(B * 3 * F);
+      rk.k = arena.take<T>(B * F);
+      for (auto& y : rk.y) y = arena.take<T>(B * F);
+      for (auto& y : rk.src) y = arena.take<T>(B * F);
+      rk.pair = arena.take<T>(B * 2 * F);
+      rk.g4 = arena.take<T>(B * 4 * F);
+      rk.divt = arena.take<T>(B * F);
     }
     sg64.n1 = p.n1;
     sg64.n2 = p.n2;
@@ -531,12 +563,18 @@ struct Context {
       if (v != L.v) HIPCHK(masked_copy<T>(stream, B, 2 * F, v, 2 * F, L.v, 2 * F, mk));
       if (on_fine) HIPCHK(cast_back<T>(stream, B * 2 * F, L.v, v64[slot]));
     }
-    HIPCHK(spec_trace_prep<T>(stream, lv.sg, B, mk, L.v, lv.cv, lv.divv, lv.cdiv, lv.S1, lv.S2));
+    // RK2A: no characteristics; div v for the antisymmetric operators
+    const bool use_rk = rk2a && on_fine;
     int nb = 0;
     const double ht = 1.0 / lv.nt;
-    HIPCHK(sl_trace<T>(stream, lv.n1, lv.n2, B, mk, ht, L.v, lv.cv, lv.divv, lv.cdiv, L.df, L.da, L.gamma, partial,
-                       &nb));
-    HIPCHK(finish(stream, B, nb, 2, 2LL * nb, 2, 2u, partial, dres));
+    if (use_rk) {
+      HIPCHK(spec_div<T>(stream, lv.sg, B, L.v, lv.divv, lv.S1, lv.S2));
+    } else {
+      HIPCHK(spec_trace_prep<T>(stream, lv.sg, B, mk, L.v, lv.cv, lv.divv, lv.cdiv, lv.S1, lv.S2));
+      HIPCHK(sl_trace<T>(stream, lv.n1, lv.n2, B, mk, ht, L.v, lv.cv, lv.divv, lv.cdiv, L.df, L.da, L.gamma,
+                         partial, &nb));
+      HIPCHK(finish(stream, B, nb, 2, 2LL * nb, 2, 2u, partial, dres));
+    }
     const bool reg_term = need_J && on_fine;
     if (reg_term) {
       HIPCHK(spec_scale<double>(stream, sg64, B, mk, sym(Symbol::Reg), 2, v64[slot], bAv64[slot], nullptr, S64a,
@@ -546,7 +584,7 @@ struct Context {
     }
     const double* r = reg_term ? fetch_both() : fetch(0);  // one synchronisation for both halves
     std::vector<double> maxd(B), vAv(B, 0.0);
-    for (int z = 0; z < B; ++z) maxd[z] = r[4 * z + 1];
+    for (int z = 0; z < B; ++z) maxd[z] = use_rk ? 0.0 : r[4 * z + 1];
     if (reg_term)
       for (int z = 0; z < B; ++z) vAv[z] = r[4 * B + 4 * z];
     for (int z = 0; z < B; ++z) {
@@ -558,7 +596,16 @@ struct Context {
     HIPCHK(set_ints(stream, lv.halo_dev + slot * B, L.halo.data(), B));
     // state equation
     HIPCHK(masked_copy<T>(stream, B, F, lv.mT, (long long)F, L.m, (long long)((lv.nt + 1) * F), mk));
-    for (int j = 1; j <= lv.nt; ++j) {
+    if (use_rk) {
+      const long long sm = (long long)((lv.nt + 1) * F);
+      HIPCHK(rk2a_prod<T>(stream, B, F, L.m, sm, L.v, (long long)(2 * F), rk.w3));
+      for (int j = 1; j <= lv.nt; ++j) rk2a_step(lv, slot, -1, -1, L.m + (j - 1) * F, sm, L.m + j * F, sm, nullptr, nullptr);
+      if (need_J) {
+        HIPCHK(sub_strided<T>(stream, B, F, lv.mR, (long long)F, L.m + lv.nt * F, sm, rk.k, (long long)F));
+        HIPCHK(dot<T>(stream, B, F, rk.k, rk.k, partial, dres));
+      }
+    }
+    for (int j = 1; j <= lv.nt && !use_rk; ++j) {
       StepArgs<T> a = step_base(lv, slot, mk, false);
       a.halo = lv.max_halo(slot, hmask);
       a.src = L.m + (j - 1) * F;
@@ -573,7 +620,7 @@ struct Context {
       HIPCHK(sl_step<T>(stream, StepKind::State, a, &nb));
     }
     if (need_J) {
-      HIPCHK(finish(stream, B, nb, 2, 2LL * nb, 1, 0u, partial, dres));
+      if (!use_rk) HIPCHK(finish(stream, B, nb, 2, 2LL * nb, 1, 0u, partial, dres));
       const double* r3 = fetch(0);
       for (int z = 0; z < B; ++z) {
         if (!hmask.empty() && !hmask[z]) continue;
@@ -584,6 +631,106 @@ struct Context {
     }
     L.valid = true;
     L.has_gm = false;
+  }
+
+  // ---- stabilised RK2 (RK2A) transport ------------------------------------------------------
+  // One Heun step of dy/ds = sgn L_dsgn y + src from y0 (rk.w3 holding its products with v) into
+  // dst: two evaluations of the antisymmetric operator, each one spectral derivative pass.
+  // src0, src1: sources at the start and the end of the step (one field per item, or nullptr).
+  void rk2a_step(Level<T>& lv, int slot, int sgn, int dsgn, const T* y0, long long sy0, T* dst, long long sdst,
+                 const T* src0, const T* src1) {
+    const size_t F = lv.F;
+    RK2AStage<T> a;
+    a.F = F;
+    a.ht = 1.0 / lv.nt;
+    a.sgn = sgn;
+    a.dsgn = dsgn;
+    a.d = rk.d3;
+    a.w3 = rk.w3;
+    a.v = lv.lin[slot].v;
+    a.sv = (long long)(2 * F);
+    a.divv = lv.divv;
+    a.sdiv = (long long)F;
+    a.ssrc = (long long)F;
+    a.k = rk.k;
+    HIPCHK(spec_rk2a<T>(stream, lv.sg, B, rk.w3, rk.d3, lv.S1, lv.S2));
+    a.stage = 1;
+    a.src = src0;
+    HIPCHK(rk2a_stage<T>(stream, B, a));
+    HIPCHK(spec_rk2a<T>(stream, lv.sg, B, rk.w3, rk.d3, lv.S1, lv.S2));
+    a.stage = 2;
+    a.src = src1;
+    a.y0 = y0;
+    a.sy0 = sy0;
+    a.dst = dst;
+    a.sdst = sdst;
+    HIPCHK(rk2a_stage<T>(stream, B, a));
+  }
+
+  // acc (init: =, else +=) ht w_j 1/2 (lam grad m^j - m^j grad lam + grad(lam m^j)) at time level j
+  void rk2a_accumulate(Level<T>& lv, int j, const T* lam, T* acc, bool init) {
+    const size_t F = lv.F;
+    const int nt = lv.nt;
+    auto& L = lv.lin[0];
+    const long long sm = (long long)((nt + 1) * F);
+    HIPCHK(rk2a_pair<T>(stream, B, F, lam, (long long)F, L.m + j * F, sm, rk.pair));
+    HIPCHK(spec_grad<T>(stream, lv.sg, 2 * B, rk.pair, rk.g4, lv.S1, lv.S2));
+    HIPCHK(rk2a_accum<T>(stream, B, F, trapezoid_weight(j, nt), init ? 1 : 0, lam, (long long)F, L.m + j * F, sm,
+                         L.gm + 2 * j * F, (long long)(2 * (nt + 1) * F), rk.g4, acc, (long long)(2 * F)));
+  }
+
+  // adjoint equation from lam^nt (in rk.y[cur]) backward to t = 0, accumulating b (or b~) into acc;
+  // lam stays in rk.y
+  void rk2a_adjoint_sweep(Level<T>& lv, int cur, T* acc) {
+    const size_t F = lv.F;
+    rk2a_accumulate(lv, lv.nt, rk.y[cur], acc, true);
+    HIPCHK(rk2a_prod<T>(stream, B, F, rk.y[cur], (long long)F, lv.lin[0].v, (long long)(2 * F), rk.w3));
+    for (int j = lv.nt; j >= 1; --j) {
+      rk2a_step(lv, 0, +1, +1, rk.y[cur], (long long)F, rk.y[1 - cur], (long long)F, nullptr, nullptr);
+      cur = 1 - cur;
+      rk2a_accumulate(lv, j - 1, rk.y[cur], acc, false);
+    }
+  }
+
+  // b = int 1/2 (lam grad m - m grad lam + grad(lam m)) dt at slot 0 into lv.acc
+  void rk2a_gradient(Level<T>& lv) {
+    const size_t F = lv.F;
+    const int nt = lv.nt;
+    auto& L = lv.lin[0];
+    HIPCHK(spec_div<T>(stream, lv.sg, B, L.v, lv.divv, lv.S1, lv.S2));
+    HIPCHK(sub_strided<T>(stream, B, F, lv.mR, (long long)F, L.m + nt * F, (long long)((nt + 1) * F), rk.y[0],
+                          (long long)F));
+    rk2a_adjoint_sweep(lv, 0, lv.acc);
+  }
+
+  // b~ of the Gauss--Newton matvec with RK2A transport at slot 0 into lv.bt: the incremental state
+  // d_t m~ = -L m~ - S(m) vt, S(m) vt = 1/2 (div(m vt) + vt . grad m - m div vt), from m~ = 0; then the
+  // adjoint equation from -m~(1) with b~ in its antisymmetric form
+  void rk2a_transport(Level<T>& lv, const T* vt) {
+    const size_t F = lv.F;
+    const int nt = lv.nt;
+    auto& L = lv.lin[0];
+    const long long sm = (long long)((nt + 1) * F);
+    HIPCHK(spec_div<T>(stream, lv.sg, B, L.v, lv.divv, lv.S1, lv.S2));
+    HIPCHK(spec_div<T>(stream, lv.sg, B, vt, rk.divt, lv.S1, lv.S2));
+    auto source = [&](int j, T* out) {
+      HIPCHK(rk2a_prod<T>(stream, B, F, L.m + j * F, sm, vt, (long long)(2 * F), rk.w3s));
+      HIPCHK(spec_rk2a<T>(stream, lv.sg, B, rk.w3s, rk.d3s, lv.S1, lv.S2));
+      HIPCHK(rk2a_eval<T>(stream, B, F, -1, -1, rk.d3s, L.m + j * F, sm, vt, (long long)(2 * F), rk.divt,
+                          (long long)F, out, (long long)F));
+    };
+    source(0, rk.src[0]);
+    HIPCHK(fill<T>(stream, B * F, 0.0, rk.y[0]));
+    HIPCHK(fill<T>(stream, B * 3 * F, 0.0, rk.w3));
+    int cur = 0;
+    for (int j = 1; j <= nt; ++j) {
+      source(j, rk.src[j % 2]);
+      rk2a_step(lv, 0, -1, -1, rk.y[cur], (long long)F, rk.y[1 - cur], (long long)F, rk.src[(j - 1) % 2],
+                rk.src[j % 2]);
+      cur = 1 - cur;
+    }
+    HIPCHK(axpby<T>(stream, B, F, -1.0, nullptr, rk.y[cur], 0.0, nullptr, rk.y[cur]));  // lam~(1) = -m~(1)
+    rk2a_adjoint_sweep(lv, cur, lv.bt);
   }
 
   void ensure_gm(Level<T>& lv) {
@@ -601,6 +748,25 @@ struct Context {
     const size_t F = lv.F;
     const int nt = lv.nt;
     int nb = 0;
+    if (rk2a && &lv == &fine) {  // g = beta A v + K b with b from the RK2A adjoint
+      rk2a_gradient(lv);
+      if (leray) {
+        HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, symK(Symbol::One), 2, lv.acc, lv.g, L.bAv, lv.S1, lv.S2));
+      } else {
+        HIPCHK(xpay<T>(stream, B * 2 * F, lv.acc, 1.0, L.bAv, lv.g));
+      }
+      HIPCHK(norms<T>(stream, B, 2 * F, lv.g, partial, dres));
+      const double* r = fetch(0);
+      g2.assign(B, 0.0);
+      ginf.assign(B, 0.0);
+      for (int z = 0; z < B; ++z) {
+        if (!hmask.empty() && !hmask[z]) continue;
+        g2[z] = r[4 * z];
+        ginf[z] = r[4 * z + 1];
+        if (!std::isfinite(g2[z]) || r[4 * z + 2] > 0) throw Fail{SLNK_ENAN, "non-finite gradient"};
+      }
+      return;
+    }
     // the full-Newton matvec needs every adjoint time level (and div v) of this linearisation
     const bool keep = full_newton && &lv == &fine;
     if (keep) {
@@ -776,7 +942,9 @@ struct Context {
 
   // the transport part of the fine matvec the parameters select; the coarse level is always GN
   void transport(Level<T>& lv, const T* vt, const int* mk) {
-    if (full_newton && &lv == &fine)
+    if (rk2a && &lv == &fine)
+      rk2a_transport(lv, vt);
+    else if (full_newton && &lv == &fine)
       fn_transport(lv, vt, mk);
     else
       gn_transport(lv, vt, mk);

@@ -83,6 +83,11 @@ hipError_t spec_scale2(hipStream_t s, const SpecGrid<T>& g, int batch, const int
 template <typename T>
 hipError_t spec_div(hipStream_t s, const SpecGrid<T>& g, int count, const T* w, T* out, cplx<T>* S1, cplx<T>* S2);
 
+// Spatial derivatives of a stabilised RK2 stage for 'count' consecutive blocks of three fields
+// (u, w1, w2), stride 3 field(): out block = (d1 u, d2 u, d1 w1 + d2 w2).  S1, S2 >= 3 count spec().
+template <typename T>
+hipError_t spec_rk2a(hipStream_t s, const SpecGrid<T>& g, int count, const T* in, T* out, cplx<T>* S1, cplx<T>* S2);
+
 // Vectors of one Chebyshev step on M = I + S Q S (item stride 2 field(), coefficients per item)
 template <typename T>
 struct ChebTail {
@@ -286,6 +291,51 @@ hipError_t fn_accumulate(hipStream_t s, int batch, size_t F, int nt, double ht, 
 template <typename T>
 hipError_t sub_strided(hipStream_t s, int batch, size_t n, const T* x, long long sx, const T* y, long long sy, T* out,
                        long long so);
+
+// ---- stabilised RK2 transport (section 3.3.1; appendix "Stabilized RK2 Scheme") --------------
+// Antisymmetric-form operators, L_s y = 1/2 (v . grad y + div(y v) + s y div v): s = -1 gives the
+// state operator L (d_t m = -L m), s = +1 the adjoint operator A (d_s lam = A lam backward).  Per
+// item: three-field blocks (stride 3F) hold (y, y v1, y v2) and their spectral derivatives
+// (d1 y, d2 y, div(y v)) from spec_rk2a.
+// out[z] = (a, a w1, a w2)
+template <typename T>
+hipError_t rk2a_prod(hipStream_t s, int batch, size_t F, const T* a, long long sa, const T* w, long long sw, T* out);
+// One Heun stage of dy/ds = sgn L_dsgn y + src.  stage 1: k = sgn L y + src into k, w3 <- the
+// products of y + ht k.  stage 2: y_new = y0 + ht/2 (k + sgn L y* + src) into dst, w3 <- its products
+// (w3[0] holds the stage's input y or y*; d its derivatives).
+template <typename T>
+struct RK2AStage {
+  int stage = 1;
+  size_t F = 0;
+  double ht = 0;
+  int sgn = -1, dsgn = -1;
+  const T* d = nullptr;
+  T* w3 = nullptr;
+  const T* v = nullptr;
+  long long sv = 0;
+  const T* divv = nullptr;
+  long long sdiv = 0;
+  const T* src = nullptr;  // optional source (one field per item)
+  long long ssrc = 0;
+  const T* y0 = nullptr;   // stage 2: the step's starting value
+  long long sy0 = 0;
+  T* k = nullptr;          // one field per item: the first stage's slope
+  T* dst = nullptr;        // stage 2 output
+  long long sdst = 0;
+};
+template <typename T>
+hipError_t rk2a_stage(hipStream_t s, int batch, const RK2AStage<T>& a);
+// out = sgn 1/2 (w1 d1a + w2 d2a + div(a w) + dsgn a div w) from the derivatives d of (a, a w1, a w2)
+template <typename T>
+hipError_t rk2a_eval(hipStream_t s, int batch, size_t F, int sgn, int dsgn, const T* d, const T* a, long long sa,
+                     const T* w, long long sw, const T* divw, long long sdw, T* out, long long so);
+// out[z] = (lam, lam m)
+template <typename T>
+hipError_t rk2a_pair(hipStream_t s, int batch, size_t F, const T* lam, long long sl, const T* m, long long sm, T* out);
+// acc (init: =, else +=) w/2 (lam grad m - m grad lam + grad(lam m)), g4[z] = (grad lam, grad(lam m))
+template <typename T>
+hipError_t rk2a_accum(hipStream_t s, int batch, size_t F, double w, int init, const T* lam, long long sl, const T* m,
+                      long long sm, const T* gm, long long sgm, const T* g4, T* acc, long long sacc);
 
 // p[i] = host_values[i], i < count (kernel arguments, no staging buffer): publishes
 // per-linearisation integers (halos, masks) to device memory read by captured graphs

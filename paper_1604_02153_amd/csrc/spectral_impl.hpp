@@ -1007,6 +1007,29 @@ struct OpDiv {
   __device__ cplx<T> out(int, int k1, int k2, int, const cplx<T>* in, const T*) const { return div(k1, k2, in); }
 };
 
+// Spatial derivatives of one stabilised RK2 stage: from the spectra of (u, w1, w2) the spectra of
+// (d1 u, d2 u, d1 w1 + d2 w2), odd-order wavenumbers (Nyquist dropped).
+template <typename T>
+struct OpRK2A {
+  static constexpr int NIN = 3, NOUT = 3, NC = 0;
+  static constexpr bool kPre = false;
+  int n1, n2;
+  double inv_n;
+  __device__ cplx<T> der(int g, int k1, int k2, const cplx<T>* in) const {
+    const T o1 = odd_k<T>(k1, n1), o2 = (2 * k2 == n2) ? T(0) : T(k2);
+    const cplx<T> d = g == 0 ? cscale(in[0], o1) : g == 1 ? cscale(in[0], o2)
+                                                         : cadd(cscale(in[1], o1), cscale(in[2], o2));
+    return cscale(cmul_i(d), T(inv_n));
+  }
+  __device__ void operator()(int k1, int k2, int, int, const cplx<T>* in, cplx<T>* out) const {
+#pragma unroll
+    for (int g = 0; g < 3; ++g) out[g] = der(g, k1, k2, in);
+  }
+  __device__ void coef(int, int, T*) const {}
+  __device__ void pre(int, int, int, const cplx<T>*) const {}
+  __device__ cplx<T> out(int g, int k1, int k2, int, const cplx<T>* in, const T*) const { return der(g, k1, k2, in); }
+};
+
 template <typename T>
 struct OpTracePrep {
   static constexpr int NIN = 2, NOUT = 4, NC = 1;  // cv1, cv2, div v, c_div
@@ -1380,6 +1403,20 @@ hipError_t spec_div(hipStream_t s, const SpecGrid<T>& g, int count, const T* w, 
 }
 
 template <typename T>
+hipError_t spec_rk2a(hipStream_t s, const SpecGrid<T>& g, int count, const T* in, T* out, cplx<T>* S1, cplx<T>* S2) {
+  const size_t F = g.field();
+  const bool fast = fast_grid(g);
+  RealFields<T> rin{};
+  set_fields(rin, 3, const_cast<T*>(in), F, nullptr);
+  RET_IF(row_fwd<T>(fast, s, g, rin, count, S1));
+  OpRK2A<T> op{g.n1, g.n2, 1.0 / double(F)};
+  RET_IF(col<0>(fast, s, g, S1, S2, op, count));
+  OutFields<T> rout{};
+  set_fields(rout, 3, out, F, nullptr);
+  return row_inv<T>(fast, s, g, S2, 3, rout, count);
+}
+
+template <typename T>
 hipError_t spec_trace_prep(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, const T* v, T* cv,
                            T* divv, T* cdiv, cplx<T>* S1, cplx<T>* S2) {
   const size_t F = g.field();
@@ -1510,6 +1547,7 @@ hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecG
                                      const T*, T*, T*, cplx<T>*, cplx<T>*);                                     \
   template bool spec_fast<T>(const SpecGrid<T>&);                                                                \
   template hipError_t spec_div<T>(hipStream_t, const SpecGrid<T>&, int, const T*, T*, cplx<T>*, cplx<T>*);      \
+  template hipError_t spec_rk2a<T>(hipStream_t, const SpecGrid<T>&, int, const T*, T*, cplx<T>*, cplx<T>*);     \
   template hipError_t spec_scale2_cheb<T>(hipStream_t, const SpecGrid<T>&, int, const int*, SymbolParams,       \
                                           SymbolParams, const T*, ChebTail<T>, cplx<T>*, cplx<T>*);             \
   template hipError_t spec_trace_prep<T>(hipStream_t, const SpecGrid<T>&, int, const int*, const T*, T*, T*, T*, \

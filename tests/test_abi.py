@@ -55,7 +55,7 @@ int main(void) {
   F(slnk_params, prec); F(slnk_params, pc); F(slnk_params, cheb_iters); F(slnk_params, lanczos_steps);
   F(slnk_params, emax_safety); F(slnk_params, lanczos_seed); F(slnk_params, use_graphs); F(slnk_params, batch);
   F(slnk_params, sl_path); F(slnk_params, hessian); F(slnk_params, proj);
-  F(slnk_params, coarse_solver); F(slnk_params, coarse_eps);
+  F(slnk_params, coarse_solver); F(slnk_params, coarse_eps); F(slnk_params, transport);
   printf("slnk_solve_opts size %zu 0\n", sizeof(slnk_solve_opts));
   F(slnk_solve_opts, max_newton); F(slnk_solve_opts, gtol_rel); F(slnk_solve_opts, gtol_abs);
   F(slnk_solve_opts, max_pcg); F(slnk_solve_opts, armijo_c1); F(slnk_solve_opts, max_halvings);

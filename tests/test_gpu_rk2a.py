@@ -1,0 +1,165 @@
+"""GPU parity of the stabilised RK2 transport (transport = SLNK_TRANSPORT_RK2A; section 3.3.1 and
+the appendix "Stabilized RK2 Scheme"), through the C ABI, against the FP64 oracle: state solve,
+objective, gradient and Gauss--Newton matvec (FP64 1e-11 plus the FP64 rounding floor of beta A,
+mixed 1e-5 / 1e-4), the Newton--Krylov path with P_REG, batched items against single contexts,
+and the parameter checks."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+import synth
+from gpu_common import TOL, check_reg_op, check_rel, problem, same_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def slnk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1604_02153_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def _t(a, prec):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
+
+
+def _np(t):
+    return t.double().cpu().numpy()
+
+
+def _rk_level(kind, n1, n2, nt, beta, reg, prec, seed=2, amp=0.3, proj=0):
+    L, vgen, vt = problem(kind, n1, n2, nt=nt, beta=beta, reg=reg, seed=seed, amp=amp)
+    mT, vgen, vt = same_inputs(prec, L.mT, vgen, vt)
+    g = L.grid
+    mR = same_inputs(prec, O.rk2a_solve_state(g, vgen, mT, nt)[-1])
+    L = O.Level(g, mT, mR, O.Params(nt=nt, beta=beta, reg=reg, transport="rk2a", proj=proj))
+    return L, vgen, vt
+
+
+def _ctx(slnk, L, prec, **kw):
+    p = L.prm
+    reg = {1: "h1", 2: "h2", 3: "h3"}[p.reg]
+    return slnk.Context(L.grid.n1, L.grid.n2, p.nt, reg=reg, beta=p.beta, prec=prec, pc="reg", transport="rk2a",
+                        proj="leray" if p.proj else "none", **kw)
+
+
+def cfl_nt(n1, n2, vmax, c=0.2):
+    """Time steps of RK2A(c): the CFL number c = ht max|v| / h (the paper runs RK2A at 0.2; Heun is
+    unstable for the skew-symmetric operator at larger ht, and rounding of the highest modes then
+    grows)."""
+    return max(2, int(np.ceil(vmax * max(n1, n2) / (2 * np.pi * c))))
+
+
+CASES = [
+    # kind, n1, n2, nt (CFL 0.2 for the generating velocity), beta, reg, prec
+    ("smooth", 64, 64, cfl_nt(64, 64, 0.5), 1e-2, 1, "fp64"),
+    ("gauss", 96, 80, cfl_nt(96, 80, 0.3), 1e-3, 2, "fp64"),
+    ("gauss", 96, 80, cfl_nt(96, 80, 0.3), 1e-3, 2, "mixed"),
+    ("gauss", 128, 128, cfl_nt(128, 128, 0.3), 1e-3, 2, "mixed"),
+    ("smooth", 60, 120, cfl_nt(60, 120, 0.5), 1e-2, 1, "mixed"),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}{c[1]}x{c[2]}_nt{c[3]}_{c[6]}")
+def test_rk2a_transport_gradient_matvec(slnk, case):
+    kind, n1, n2, nt, beta, reg, prec = case
+    print(f"rk2a case {case}", flush=True)
+    L, vgen, vt = _rk_level(kind, n1, n2, nt, beta, reg, prec)
+    tol = TOL[prec]
+    ctx = _ctx(slnk, L, prec)
+    m1 = torch.empty((n1, n2), dtype=ctx.dtype, device="cuda")
+    ctx.transport_state(_t(vgen, prec), _t(L.mT, prec), m1)
+    check_rel(f"RK2A transport {n1}x{n2} nt{nt} {prec}", _np(m1), O.rk2a_solve_state(L.grid, vgen, L.mT, nt)[-1],
+              tol["transport"])
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    v = same_inputs(prec, 0.6 * vgen)
+    lin = O.linearize(L, v)
+    g = torch.empty((2, n1, n2), dtype=ctx.dtype, device="cuda")
+    J = ctx.gradient(_t(v, prec), g)
+    assert abs(J - lin.J) / abs(lin.J) < tol["objective"]
+    check_reg_op(L, _np(g), O.gradient(lin), v, tol["gradient"], f"RK2A gradient {prec}")
+    h = torch.empty_like(g)
+    ctx.hessian_matvec(_t(vt, prec), h)
+    check_reg_op(L, _np(h), O.hessian_matvec(lin, vt), vt, tol["matvec"], f"RK2A matvec {prec}")
+    ctx.close()
+
+
+def test_rk2a_incompressible_matvec(slnk):
+    """K = Leray with RK2A transport (the paper's incompressible runs pair RK2A with P_REG)."""
+    prec = "fp64"
+    L, vgen, vt = _rk_level("gauss", 64, 64, cfl_nt(64, 64, 0.3), 1e-3, 1, prec, proj=1)
+    ctx = _ctx(slnk, L, prec)
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    v = 0.5 * vgen
+    lin = O.linearize(L, v)
+    g = torch.empty((2, 64, 64), dtype=torch.float64, device="cuda")
+    ctx.gradient(_t(v, prec), g)
+    check_reg_op(L, _np(g), O.gradient(lin), v, TOL[prec]["gradient"], "RK2A Leray gradient fp64")
+    h = torch.empty_like(g)
+    ctx.hessian_matvec(_t(vt, prec), h)
+    check_reg_op(L, _np(h), O.hessian_matvec(lin, vt), vt, TOL[prec]["matvec"], "RK2A Leray matvec fp64")
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rk2a_newton_solve_matches_oracle(slnk, prec):
+    """P_REG + RK2A on the smooth 64^2 problem: FP64 takes the oracle's Newton path (same Newton and
+    PCG counts, velocity to 1e-9); mixed reaches the stop rule within 1e-3 of the oracle's
+    velocity."""
+    n = 64
+    nt = cfl_nt(n, n, 0.5)
+    g = O.Grid(n, n)
+    mT = same_inputs(prec, synth.smooth_a_template(n, n))
+    vstar = synth.smooth_a_velocity(n, n)
+    mR = same_inputs(prec, O.rk2a_solve_state(g, vstar, mT, nt)[-1])
+    L = O.Level(g, mT, mR, O.Params(nt=nt, beta=1e-2, reg=1, transport="rk2a"))
+    v_ref, rep_ref = O.newton_solve(L, pc="reg", max_newton=10)
+    assert rep_ref["status"] == "ok"
+    ctx = _ctx(slnk, L, prec)
+    ctx.set_images(_t(mR, prec), _t(mT, prec))
+    v = torch.zeros((2, n, n), dtype=ctx.dtype, device="cuda")
+    rep = ctx.newton_solve(v, max_newton=10)
+    print(rep["grel"], rep["pcg"], rep_ref["grel"], flush=True)
+    assert rep["status"] == "SLNK_OK" and rep["grel"][-1] <= 1e-2
+    if prec == "fp64":
+        assert rep["newton_iters"] == rep_ref["newton_iters"] and rep["pcg_iters"] == rep_ref["pcg_iters"]
+    check_rel(f"RK2A Newton v smooth64 {prec}", _np(v), v_ref, 1e-9 if prec == "fp64" else 1e-3)
+    ctx.close()
+
+
+def test_rk2a_batch_items_equal_single_contexts(slnk):
+    n, prec = 64, "mixed"
+    nt = cfl_nt(n, n, 0.3)
+    probs = [_rk_level("gauss", n, n, nt, 1e-3, 2, prec, seed=90 + z, amp=0.2 + 0.1 * z) for z in range(2)]
+    cb = _ctx(slnk, probs[0][0], prec, batch=2)
+    cb.set_images(_t(np.stack([p[0].mR for p in probs]), prec), _t(np.stack([p[0].mT for p in probs]), prec))
+    vb = _t(np.stack([0.5 * p[1] for p in probs]), prec)
+    vtb = _t(np.stack([p[2] for p in probs]), prec)
+    gb = torch.empty_like(vb)
+    cb.gradient(vb, gb)
+    hb = torch.empty_like(vb)
+    cb.hessian_matvec(vtb, hb)
+    for z, (L, _, _) in enumerate(probs):
+        c1 = _ctx(slnk, L, prec)
+        c1.set_images(_t(L.mR, prec), _t(L.mT, prec))
+        g1 = torch.empty_like(vb[z])
+        c1.gradient(vb[z].contiguous(), g1)
+        h1 = torch.empty_like(g1)
+        c1.hessian_matvec(vtb[z].contiguous(), h1)
+        assert torch.equal(g1, gb[z]) and torch.equal(h1, hb[z]), z
+        c1.close()
+    cb.close()
+
+
+def test_rk2a_parameter_checks(slnk):
+    for kw in (dict(pc="2l"), dict(pc="reg", hessian="fn")):
+        with pytest.raises(slnk.SlnkError) as e:
+            slnk.Context(64, 64, 8, reg="h2", beta=1e-3, prec="fp64", transport="rk2a", **kw)
+        assert e.value.status == 1, kw
