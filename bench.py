@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--spectral", action="store_true",
                     help="spectral-pass probe: 20 two-field spectral scalings at 1024^2 x16, 256^2 x64 and 128^2 "
                          "x64 batches (for a kernel trace); no JSON line")
+    ap.add_argument("--probe-coarse", action="store_true",
+                    help="coarse-step probe: 200 incremental-adjoint SL steps of the 128^2 problem (the P_2L coarse "
+                         "grid of the 256^2 workload) for a kernel trace; no JSON line")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: 20 incremental-adjoint SL steps of the 256^2 problem, then a plain "
                          "64 MiB elementwise kernel (the reference of the traffic counters); no JSON line")
@@ -96,6 +99,27 @@ def probe():
     for _ in range(3):
         torch.mul(x, 2.0, out=y)  # reads and writes 64 MiB
     torch.cuda.synchronize()
+    ctx.close()
+
+
+def coarse_probe():
+    """Launch sequence of the coarse-step kernel trace: the gauss256 recipe on the 128^2 grid,
+    linearised at its generating velocity, 200 incremental-adjoint SL steps."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1604_02153_amd import Context
+    c = synth.config("gauss256", n=128)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=torch.float32)
+    ctx = Context(128, 128, 4, reg="h2", beta=1e-3, prec="mixed", pc="reg")
+    mT, vg = t(c["mT"]), t(c["v_gen"])
+    mR = torch.empty_like(mT)
+    ctx.transport_state(vg, mT, mR)
+    ctx.set_images(mR, mT)
+    g = torch.empty_like(vg)
+    ctx.gradient(vg, g)
+    print(f"128^2 incremental-adjoint step: {1e3 * ctx.time_kernel(3, 200):.2f} us per launch", flush=True)
     ctx.close()
 
 
@@ -688,6 +712,9 @@ def main():
         return
     if args.probe:
         probe()
+        return
+    if args.probe_coarse:
+        coarse_probe()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); runs on several GPUs are not "
