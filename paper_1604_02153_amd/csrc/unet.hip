@@ -37,6 +37,9 @@ __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >=
 // them; their partial sums meet in LDS and are added in a fixed order.  Small grids (the deep
 // levels: few pixels, many channels) take KS > 1 so that enough wavefronts run.  The K loop is
 // flat over (tap, chunk) and unrolled, so the loads of several steps are in flight together.
+// An output tile is a patch of 2 rows x 8 MW columns: row m of MFMA tile i is the pixel
+// (y0 + (m >> 1 & 1), x0 + 8 i + 2 (m >> 2) + (m & 1)), so the four results a lane receives
+// (rows 4g .. 4g + 3) form one 2 x 2 block, which the epilogue pools in registers.
 template <int MW, int KS>
 __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
   constexpr int PG = 4 / KS;  // output tiles per block
@@ -44,16 +47,19 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
   const int kpart = wave % KS, pg = wave / KS;
   const int r = lane & 15, g = lane >> 4;
   const int HW = a.H * a.W;
-  const int pbase = (blockIdx.x * PG + pg) * (16 * MW);
+  const int pw = a.W / (8 * MW);       // patches per row pair
+  const int npi = (a.H >> 1) * pw;     // patches per image
+  const int pt = blockIdx.x * PG + pg;
+  const int pb = pt / npi;
+  const int prem = pt - pb * npi;
+  const int prow = prem / pw;
+  const int y0 = 2 * prow, x0 = 8 * MW * (prem - prow * pw);
   const int cobase = blockIdx.y * 32;
-  int pb[MW], py[MW], px[MW];
+  int py[MW], px[MW];
 #pragma unroll
   for (int i = 0; i < MW; ++i) {
-    const int p = pbase + 16 * i + r;
-    pb[i] = p / HW;
-    const int rem = p - pb[i] * HW;
-    py[i] = rem / a.W;
-    px[i] = rem - py[i] * a.W;
+    py[i] = y0 + ((r >> 1) & 1);
+    px[i] = x0 + 8 * i + 2 * (r >> 2) + (r & 1);
   }
   v4f acc[MW][2];
 #pragma unroll
@@ -74,7 +80,7 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
 #pragma unroll
     for (int m = 0; m < MW; ++m) {
       const int yy = wrap(py[m] + dy, a.H), xx = wrap(px[m] + dx, a.W);
-      av[m] = load8(a.x + (size_t(pb[m]) * HW + size_t(yy) * a.W + xx) * a.xcs + a.xco + 8 * g + 32 * kc);
+      av[m] = load8(a.x + (size_t(pb) * HW + size_t(yy) * a.W + xx) * a.xcs + a.xco + 8 * g + 32 * kc);
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j)
@@ -119,16 +125,29 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
     for (int j = 0; j < 2; ++j) {
       const int co = cobase + 16 * j + r;
       const float bias = a.bias ? a.bias[co] : 0.f;
+      const int xb = x0 + 8 * i + 2 * g;  // this lane's 2 x 2 block: rows y0, y0 + 1, columns xb, xb + 1
+      float pooled = 0.f;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int p = pbase + 16 * i + 4 * g + q;
+        const int yq = y0 + (q >> 1), xq = xb + (q & 1);
+        const size_t p = size_t(pb) * HW + size_t(yq) * a.W + xq;
         float v = acc[i][j][q] + bias;
         if (a.relu) v = fmaxf(v, 0.f);
-        if (a.y) a.y[size_t(p) * a.ycs + a.yco + co] = f2bf(v);
-        if (a.v && co < a.nv) {
-          const int b = p / HW;
-          a.v[(size_t(b) * a.nv + co) * HW + (p - b * HW)] = v;
+        const bf16 h = f2bf(v);
+        pooled += bf2f(h);
+        if (a.y) a.y[p * a.ycs + a.yco + co] = h;
+        if (a.yu) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const size_t pu = (size_t(pb) * 2 * a.H + 2 * yq + (u >> 1)) * (2 * a.W) + 2 * xq + (u & 1);
+            a.yu[pu * a.yucs + a.yuco + co] = h;
+          }
         }
+        if (a.v && co < a.nv) a.v[(size_t(pb) * a.nv + co) * HW + size_t(yq) * a.W + xq] = v;
+      }
+      if (a.yp) {
+        const size_t po = (size_t(pb) * (a.H >> 1) + prow) * (a.W >> 1) + (xb >> 1);
+        a.yp[po * a.ypcs + a.ypco + co] = f2bf(0.25f * pooled);
       }
     }
 }
@@ -256,22 +275,6 @@ __global__ void k_relu_mask(bf16* dy, int dcs, int dco, const bf16* y, int ycs, 
   }
 }
 
-// 2x2 average pooling: out [B][H/2][W/2] from in [B][H][W] (H, W of the input)
-__global__ void k_pool(const bf16* x, int xcs, int xco, bf16* y, int ycs, int yco, int C, int B, int H, int W) {
-  const int Ho = H / 2, Wo = W / 2;
-  const size_t n = size_t(B) * Ho * Wo * C;
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
-    const int c = int(i % C);
-    const size_t po = i / C;
-    const int xo = int(po % Wo), yo = int((po / Wo) % Ho), b = int(po / (size_t(Wo) * Ho));
-    float s = 0.f;
-    for (int dy = 0; dy < 2; ++dy)
-      for (int dx = 0; dx < 2; ++dx)
-        s += bf2f(x[((size_t(b) * H + 2 * yo + dy) * W + 2 * xo + dx) * xcs + xco + c]);
-    y[po * ycs + yco + c] = f2bf(0.25f * s);
-  }
-}
-
 // gradient of the pooling, accumulated: dX[2y+i][2x+j] += dY[y][x] / 4
 __global__ void k_pool_bwd_add(const bf16* dy, int dcs, int dco, bf16* dx, int xcs, int xco, int C, int B, int H,
                                int W) {
@@ -283,17 +286,6 @@ __global__ void k_pool_bwd_add(const bf16* dy, int dcs, int dco, bf16* dx, int x
     const float gsrc = bf2f(dy[((size_t(b) * (H / 2) + y / 2) * (W / 2) + x / 2) * dcs + dco + c]);
     bf16* d = dx + p * xcs + xco + c;
     *d = f2bf(bf2f(*d) + 0.25f * gsrc);
-  }
-}
-
-// nearest-neighbour upsampling by 2: out [B][2H][2W] from in [B][H][W]
-__global__ void k_up(const bf16* x, int xcs, int xco, bf16* y, int ycs, int yco, int C, int B, int H, int W) {
-  const size_t n = size_t(B) * 4 * H * W * C;
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
-    const int c = int(i % C);
-    const size_t p = i / C;
-    const int xo = int(p % (2 * W)), yo = int((p / (2 * W)) % (2 * H)), b = int(p / (size_t(4) * H * W));
-    y[p * ycs + yco + c] = x[((size_t(b) * H + yo / 2) * W + xo / 2) * xcs + xco + c];
   }
 }
 
@@ -313,14 +305,13 @@ __global__ void k_up_bwd(const bf16* dy, int dcs, int dco, bf16* dx, int xcs, in
 }
 
 // network input: channels (m_R, m_T, m_R - m_T, 0, ...) of a C-channel tensor
+// (C a multiple of 8: each pixel is written as C / 8 16-byte stores)
 __global__ void k_prep(const float* mr, const float* mt, bf16* x, int C, size_t P) {
   for (size_t p = size_t(blockIdx.x) * blockDim.x + threadIdx.x; p < P; p += size_t(gridDim.x) * blockDim.x) {
     const float a = mr[p], b = mt[p];
-    bf16* o = x + p * C;
-    o[0] = f2bf(a);
-    o[1] = f2bf(b);
-    o[2] = f2bf(a - b);
-    for (int c = 3; c < C; ++c) o[c] = 0;
+    uint4* o = reinterpret_cast<uint4*>(x + p * C);
+    o[0] = make_uint4(unsigned(f2bf(a)) | (unsigned(f2bf(b)) << 16), unsigned(f2bf(a - b)), 0u, 0u);
+    for (int c = 1; c < C / 8; ++c) o[c] = make_uint4(0u, 0u, 0u, 0u);
   }
 }
 
@@ -474,10 +465,11 @@ void conv_variant_counts(long long out[6], bool reset) {
 
 hipError_t conv(hipStream_t s, const ConvArgs& a) {
   const int HW = a.H * a.W;
-  if (a.cin % 32 || a.cout % 32 || a.xcs % 8 || a.xco % 8 || HW % 64 || a.P % HW) return hipErrorInvalidValue;
-  // output tiles of 16 MW pixels x 32 channels; split K when they would not give about eight
+  if (a.cin % 32 || a.cout % 32 || a.xcs % 8 || a.xco % 8 || a.H % 2 || a.W % 8 || HW % 64 || a.P % HW)
+    return hipErrorInvalidValue;
+  // output tiles of 2 x 8 MW pixels x 32 channels; split K when they would not give about eight
   // wavefronts per compute unit
-  const int mw = HW % 128 == 0 ? 2 : 1;
+  const int mw = HW % 128 == 0 && a.W % 16 == 0 ? 2 : 1;
   const long tiles = long(a.P / (16 * mw)) * (a.cout / 32);
   const int ks = tiles >= 2048 ? 1 : tiles >= 1024 ? 2 : 4;
   const dim3 grid(a.P / (16 * mw * (4 / ks)), a.cout / 32);
@@ -531,23 +523,10 @@ hipError_t relu_mask(hipStream_t s, bf16* dy, int dcs, int dco, const bf16* y, i
   return hipGetLastError();
 }
 
-hipError_t pool(hipStream_t s, const bf16* x, int xcs, int xco, bf16* y, int ycs, int yco, int C, int B, int H,
-                int W) {
-  hipLaunchKernelGGL(k_pool, dim3(blocks_for(size_t(B) * H * W * C / 4)), dim3(256), 0, s, x, xcs, xco, y, ycs, yco,
-                     C, B, H, W);
-  return hipGetLastError();
-}
-
 hipError_t pool_bwd_add(hipStream_t s, const bf16* dy, int dcs, int dco, bf16* dx, int xcs, int xco, int C, int B,
                         int H, int W) {
   hipLaunchKernelGGL(k_pool_bwd_add, dim3(blocks_for(size_t(B) * H * W * C)), dim3(256), 0, s, dy, dcs, dco, dx, xcs,
                      xco, C, B, H, W);
-  return hipGetLastError();
-}
-
-hipError_t up(hipStream_t s, const bf16* x, int xcs, int xco, bf16* y, int ycs, int yco, int C, int B, int H, int W) {
-  hipLaunchKernelGGL(k_up, dim3(blocks_for(size_t(B) * 4 * H * W * C)), dim3(256), 0, s, x, xcs, xco, y, ycs, yco, C,
-                     B, H, W);
   return hipGetLastError();
 }
 
@@ -559,6 +538,7 @@ hipError_t up_bwd(hipStream_t s, const bf16* dy, int dcs, int dco, bf16* dx, int
 }
 
 hipError_t prep(hipStream_t s, const float* mr, const float* mt, bf16* x, int C, size_t P) {
+  if (C % 8 || C < 8) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_prep, dim3(blocks_for(P)), dim3(256), 0, s, mr, mt, x, C, P);
   return hipGetLastError();
 }

@@ -15,7 +15,10 @@ typedef unsigned short bf16;  // bfloat16 bit pattern
 // 3x3 periodic convolution as an implicit GEMM on BF16 MFMA.  Input view: x + pixel * xcs + xco,
 // cin channels; weights w[9][cout][cin] (tap t = 3 (dy + 1) + (dx + 1) reads pixel (y + dy,
 // x + dx)); output y + pixel * ycs + yco (BF16, optional) and/or v[b][c][pixel] (FP32, channels
-// c < nv, optional).  cin, cout multiples of 32; H W a multiple of 64; P = batch * H * W.
+// c < nv, optional).  Two optional outputs come from the same BF16 values: yp, their 2x2 average
+// pooling on the [H/2][W/2] grid (the same sums, in the same order, as pool()), and yu, their
+// nearest upsampling on the [2H][2W] grid (as up()).  cin, cout multiples of 32; H even, W a
+// multiple of 8, H W a multiple of 64; P = batch * H * W.
 struct ConvArgs {
   const bf16* x = nullptr;
   int xcs = 0, xco = 0, cin = 0;
@@ -24,6 +27,10 @@ struct ConvArgs {
   int cout = 0, relu = 0;
   bf16* y = nullptr;
   int ycs = 0, yco = 0;
+  bf16* yp = nullptr;
+  int ypcs = 0, ypco = 0;
+  bf16* yu = nullptr;
+  int yucs = 0, yuco = 0;
   float* v = nullptr;
   int nv = 0;
   int H = 0, W = 0, P = 0;
@@ -53,12 +60,10 @@ hipError_t sum_splits(hipStream_t s, const float* partial, int splits, size_t n,
 hipError_t wtrans(hipStream_t s, const bf16* w, int cout, int cin, bf16* wd);
 // dy *= (y > 0), C channels of P pixels
 hipError_t relu_mask(hipStream_t s, bf16* dy, int dcs, int dco, const bf16* y, int ycs, int yco, int C, int P);
-// 2x2 average pooling of a [B][H][W] view into [B][H/2][W/2], and its gradient added into dx
-hipError_t pool(hipStream_t s, const bf16* x, int xcs, int xco, bf16* y, int ycs, int yco, int C, int B, int H, int W);
+// gradient of the 2x2 average pooling (of a [B][H][W] view into [B][H/2][W/2]) added into dx
 hipError_t pool_bwd_add(hipStream_t s, const bf16* dy, int dcs, int dco, bf16* dx, int xcs, int xco, int C, int B,
                         int H, int W);
-// nearest upsampling of a [B][H][W] view into [B][2H][2W], and its gradient
-hipError_t up(hipStream_t s, const bf16* x, int xcs, int xco, bf16* y, int ycs, int yco, int C, int B, int H, int W);
+// gradient of the nearest upsampling of a [B][H][W] view into [B][2H][2W]
 hipError_t up_bwd(hipStream_t s, const bf16* dy, int dcs, int dco, bf16* dx, int xcs, int xco, int C, int B, int H,
                   int W);
 // input tensor (m_R, m_T, m_R - m_T, zeros) with C channels from FP32 images of P pixels

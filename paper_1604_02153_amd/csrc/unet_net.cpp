@@ -279,7 +279,10 @@ int level_of(const slnk_unet& u, int layer) {
   return 0;  // output layer
 }
 
-void run_conv(slnk_unet& u, hipStream_t s, int layer, int B, View in, View out, float* v, int nv) {
+// pooled / upsampled: further views that the convolution fills with the 2x2 average pooling or
+// the nearest upsampling of its output (the next level's input, the decoder's concatenation)
+void run_conv(slnk_unet& u, hipStream_t s, int layer, int B, View in, View out, float* v, int nv,
+              View pooled = View{}, View upsampled = View{}) {
   const auto& ly = u.layers[layer];
   const int l = level_of(u, layer);
   slnk::unet::ConvArgs a;
@@ -294,6 +297,12 @@ void run_conv(slnk_unet& u, hipStream_t s, int layer, int B, View in, View out, 
   a.y = out.p;
   a.ycs = out.cs;
   a.yco = out.co;
+  a.yp = pooled.p;
+  a.ypcs = pooled.cs;
+  a.ypco = pooled.co;
+  a.yu = upsampled.p;
+  a.yucs = upsampled.cs;
+  a.yuco = upsampled.co;
   a.v = v;
   a.nv = nv;
   a.H = u.Hs[l];
@@ -351,28 +360,27 @@ void back_conv(slnk_unet& u, hipStream_t s, int layer, int B, View in, View outv
 void forward(slnk_unet& u, hipStream_t s, int B, const float* mr, const float* mt, float* v, float* head_out) {
   const int L = u.L;
   UCHK(slnk::unet::prep(s, mr, mt, u.in0.p, kInC, size_t(B) * u.Hs[0] * u.Ws[0]));
+  // pooling and upsampling run in the epilogues of the convolutions that produce their inputs:
+  // enc_b[l] writes the skip and the pooled input of level l + 1; enc_b[L - 1] and dec_b[l]
+  // write their output and its upsampling into the first channels of the concatenation one
+  // level up
   for (int l = 0; l < L; ++l) {
     const View in = l == 0 ? u.in0.at() : u.pin[l].at();
     run_conv(u, s, u.enc_a[l], B, in, u.ea[l].at(), nullptr, 0);
-    if (l < L - 1) {
-      const View skip = u.cat[l].at(u.C[l + 1]);
-      run_conv(u, s, u.enc_b[l], B, u.ea[l].at(), skip, nullptr, 0);
-      UCHK(slnk::unet::pool(s, skip.p, skip.cs, skip.co, u.pin[l + 1].p, u.pin[l + 1].C, 0, u.C[l], B, u.Hs[l],
-                            u.Ws[l]));
-    } else {
-      run_conv(u, s, u.enc_b[l], B, u.ea[l].at(), u.eb.at(), nullptr, 0);
-    }
+    if (l < L - 1)
+      run_conv(u, s, u.enc_b[l], B, u.ea[l].at(), u.cat[l].at(u.C[l + 1]), nullptr, 0, u.pin[l + 1].at());
+    else
+      run_conv(u, s, u.enc_b[l], B, u.ea[l].at(), u.eb.at(), nullptr, 0, View{}, u.cat[L - 2].at());
   }
   for (int l = L - 2; l >= 0; --l) {
-    const Tensor& low = l == L - 2 ? u.eb : u.db[l + 1];
-    UCHK(slnk::unet::up(s, low.p, low.C, 0, u.cat[l].p, u.cat[l].C, 0, u.C[l + 1], B, u.Hs[l + 1], u.Ws[l + 1]));
     run_conv(u, s, u.dec_a[l], B, u.cat[l].at(), u.da[l].at(), nullptr, 0);
-    run_conv(u, s, u.dec_b[l], B, u.da[l].at(), u.db[l].at(), nullptr, 0);
+    run_conv(u, s, u.dec_b[l], B, u.da[l].at(), u.db[l].at(), nullptr, 0, View{},
+             l > 0 ? u.cat[l - 1].at() : View{});
   }
   run_conv(u, s, u.out_layer, B, u.db[0].at(), View{}, v, 2);
   const int lt = L - 1;
-  UCHK(slnk::unet::head(s, u.eb.p, u.C[lt], u.Hs[lt] * u.Ws[lt], B, u.w32 + u.hw_off, u.w32 + u.hb_off, u.hf, u.hs));
-  if (head_out) UCHK(hipMemcpyAsync(head_out, u.hs, B * sizeof(float), hipMemcpyDeviceToDevice, s));
+  UCHK(slnk::unet::head(s, u.eb.p, u.C[lt], u.Hs[lt] * u.Ws[lt], B, u.w32 + u.hw_off, u.w32 + u.hb_off, u.hf,
+                        head_out ? head_out : u.hs));
 }
 
 void backward(slnk_unet& u, hipStream_t s, int B) {

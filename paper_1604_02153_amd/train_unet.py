@@ -172,7 +172,9 @@ def evaluate(net, seeds, torch, dev):
                          plain_newton=plain["newton_iters"], learned_newton=learned["newton_iters"],
                          plain_pcg=plain["pcg_iters"], learned_pcg=learned["pcg_iters"],
                          plain_ok=plain["grel"][-1] <= 1e-2, learned_ok=learned["grel"][-1] <= 1e-2,
-                         fallback=learned["fallback"], emax_ratio=ratio))
+                         fallback=learned["fallback"], emax_ratio=ratio,
+                         plain_reest=plain["cheb_reestimates"] > 0,
+                         learned_reest=learned["cheb_reestimates"] > 0))
         if (i + 1) % 200 == 0:
             log(f"evaluated {i + 1}/{len(seeds)}")
     ctx.close()
@@ -191,6 +193,9 @@ def evaluate(net, seeds, torch, dev):
         "learned_pcg_mean": round(float(np.mean(col("learned_pcg"))), 2),
         "plain_reached": int(col("plain_ok").sum()), "learned_reached": int(col("learned_ok").sum()),
         "fallback_rate": round(float(np.mean(col("fallback"))), 4),
+        # solves in which PCG met r.z <= 0 and re-estimated e_max by Lanczos
+        "cheb_reestimate_rate_learned": round(float(np.mean(col("learned_reest"))), 4),
+        "cheb_reestimate_rate_plain": round(float(np.mean(col("plain_reest"))), 4),
         "learned_faster_fraction": round(float(np.mean(col("learned_ms") < col("plain_ms"))), 4),
         "emax_ratio_learned_over_lanczos": {q: round(float(np.percentile(col("emax_ratio"), p)), 4)
                                             for q, p in (("p5", 5), ("median", 50), ("p95", 95))},
