@@ -5,9 +5,11 @@ imports this module.
 
 Conventions (stated once, used everywhere below)
 ------------------------------------------------
-* Periodic grid on [0, 2*pi)^2 with n1 x n2 nodes, x_i = 2*pi*i/n (the paper's
-  (-pi, pi)^2 is the same torus, shifted).  Arrays are indexed [i1, i2] with
-  i2 the fastest axis; a velocity is an array of shape (2, n1, n2).
+* Periodic grid on [0, 2*pi)^d, d = 2 or 3, with n1 x n2 (x n3) nodes,
+  x_i = 2*pi*i/n (the paper's (-pi, pi)^2 is the same torus, shifted; the
+  method has nothing specific to d = 2, section 1 "Limitations and Unresolved
+  Issues").  Arrays are indexed [i1, i2(, i3)] with the last index the fastest
+  axis; a velocity is an array of shape (d, n1, n2(, n3)).
 * Pseudospectral calculus (section 3.2): unnormalised forward DFT, 1/N on the
   inverse; odd-order symbols (gradient, divergence) drop the Nyquist mode,
   even-order symbols (the regulariser) keep it.
@@ -23,6 +25,7 @@ Conventions (stated once, used everywhere below)
 
 from __future__ import annotations
 
+import itertools
 import math
 from dataclasses import dataclass, field, replace
 
@@ -49,29 +52,41 @@ __all__ = [
 # ---------------------------------------------------------------------------
 
 class Grid:
-    """Regular periodic grid, cell size h_i = 2*pi/n_i (section 3.2)."""
+    """Regular periodic grid in d = 2 or 3 dimensions, cell size h_i = 2*pi/n_i (section 3.2).
 
-    def __init__(self, n1: int, n2: int):
-        if n1 % 2 or n2 % 2:
+    K[i]: wave numbers along axis i (Nyquist -n_i/2); Ko[i]: the same with the
+    Nyquist mode zeroed (odd-order symbols); X: node coordinates, shape (d,) + shape.
+    """
+
+    def __init__(self, *n: int):
+        if len(n) not in (2, 3):
+            raise ValueError("a grid has 2 or 3 axes")
+        if any(int(ni) % 2 for ni in n):
             raise ValueError("grid sizes must be even")
-        self.n1, self.n2 = int(n1), int(n2)
-        self.shape = (self.n1, self.n2)
-        self.N = self.n1 * self.n2
-        self.h = (2.0 * math.pi / self.n1, 2.0 * math.pi / self.n2)
-        self.cell = self.h[0] * self.h[1]
-        k1 = np.fft.fftfreq(self.n1, 1.0 / self.n1)
-        k2 = np.fft.fftfreq(self.n2, 1.0 / self.n2)
-        self.K1, self.K2 = np.meshgrid(k1, k2, indexing="ij")
-        k1o = k1.copy(); k1o[self.n1 // 2] = 0.0
-        k2o = k2.copy(); k2o[self.n2 // 2] = 0.0
-        self.K1o, self.K2o = np.meshgrid(k1o, k2o, indexing="ij")
-        i1 = np.arange(self.n1, dtype=np.float64)
-        i2 = np.arange(self.n2, dtype=np.float64)
-        I1, I2 = np.meshgrid(i1, i2, indexing="ij")
-        self.X = np.stack([I1 * self.h[0], I2 * self.h[1]])
+        self.n = tuple(int(ni) for ni in n)
+        self.d = len(self.n)
+        self.n1, self.n2 = self.n[0], self.n[1]
+        if self.d == 3:
+            self.n3 = self.n[2]
+        self.shape = self.n
+        self.N = int(np.prod(self.n))
+        self.h = tuple(2.0 * math.pi / ni for ni in self.n)
+        self.cell = float(np.prod(self.h))
+        k = [np.fft.fftfreq(ni, 1.0 / ni) for ni in self.n]
+        ko = []
+        for ni, ki in zip(self.n, k):
+            ki = ki.copy()
+            ki[ni // 2] = 0.0
+            ko.append(ki)
+        self.K = np.meshgrid(*k, indexing="ij")
+        self.Ko = np.meshgrid(*ko, indexing="ij")
+        self.K1, self.K2 = self.K[0], self.K[1]
+        self.K1o, self.K2o = self.Ko[0], self.Ko[1]
+        idx = np.meshgrid(*[np.arange(ni, dtype=np.float64) for ni in self.n], indexing="ij")
+        self.X = np.stack([I * hi for I, hi in zip(idx, self.h)])
 
     def coarse(self) -> "Grid":
-        return Grid(self.n1 // 2, self.n2 // 2)
+        return Grid(*(ni // 2 for ni in self.n))
 
 
 @dataclass
@@ -101,22 +116,33 @@ class Params:
 # ---------------------------------------------------------------------------
 
 def _fft(u):
-    return np.fft.fft2(u)
+    return np.fft.fftn(u)
 
 
 def _ifft_real(U):
-    return np.fft.ifft2(U).real
+    return np.fft.ifftn(U).real
+
+
+def _dot(a, b):
+    """sum_i a[i] b[i] over the d components, in axis order."""
+    out = a[0] * b[0]
+    for i in range(1, len(a)):
+        out = out + a[i] * b[i]
+    return out
 
 
 def fft_grad(g: Grid, u):
-    """Spectral gradient of a scalar field: (d1 u, d2 u)."""
+    """Spectral gradient of a scalar field: (d1 u, ..., dd u)."""
     U = _fft(u)
-    return np.stack([_ifft_real(1j * g.K1o * U), _ifft_real(1j * g.K2o * U)])
+    return np.stack([_ifft_real(1j * Ki * U) for Ki in g.Ko])
 
 
 def fft_div(g: Grid, v):
     """Spectral divergence of a vector field."""
-    return _ifft_real(1j * g.K1o * _fft(v[0]) + 1j * g.K2o * _fft(v[1]))
+    S = 1j * g.Ko[0] * _fft(v[0])
+    for i in range(1, g.d):
+        S = S + 1j * g.Ko[i] * _fft(v[i])
+    return _ifft_real(S)
 
 
 def reg_symbol(g: Grid, reg: int):
@@ -126,22 +152,22 @@ def reg_symbol(g: Grid, reg: int):
     (the H3 sign is the one that makes A the positive semidefinite first
     variation of the seminorm).
     """
-    return (g.K1 ** 2 + g.K2 ** 2) ** reg
+    return _dot(g.K, g.K) ** reg
 
 
 def apply_reg(g: Grid, v, reg: int):
     a = reg_symbol(g, reg)
-    return np.stack([_ifft_real(a * _fft(v[c])) for c in range(2)])
+    return np.stack([_ifft_real(a * _fft(v[c])) for c in range(g.d)])
 
 
 def leray(g: Grid, b):
     """Leray projection K[b] = b - grad Laplacian^{-1} div b (section 3.1)."""
-    B1, B2 = _fft(b[0]), _fft(b[1])
-    k2 = g.K1o ** 2 + g.K2o ** 2
+    Bs = [_fft(b[c]) for c in range(g.d)]
+    k2 = _dot(g.Ko, g.Ko)
     safe = np.where(k2 > 0, k2, 1.0)
-    kb = (g.K1o * B1 + g.K2o * B2) / safe
+    kb = _dot(g.Ko, Bs) / safe
     kb = np.where(k2 > 0, kb, 0.0)
-    return np.stack([_ifft_real(B1 - g.K1o * kb), _ifft_real(B2 - g.K2o * kb)])
+    return np.stack([_ifft_real(Bs[c] - g.Ko[c] * kb) for c in range(g.d)])
 
 
 def apply_proj(g: Grid, b, proj: int):
@@ -164,9 +190,10 @@ def spline_coefficients(g: Grid, f):
     (c[i-1] + 4 c[i] + c[i+1]) / 6 = f[i]; a circulant system is diagonal in
     Fourier space, with eigenvalue (2 + cos(2 pi k / n)) / 3 per axis.
     """
-    b1 = (2.0 + np.cos(2.0 * np.pi * g.K1 / g.n1)) / 3.0
-    b2 = (2.0 + np.cos(2.0 * np.pi * g.K2 / g.n2)) / 3.0
-    return _ifft_real(_fft(f) / (b1 * b2))
+    b = (2.0 + np.cos(2.0 * np.pi * g.K[0] / g.n[0])) / 3.0
+    for i in range(1, g.d):
+        b = b * ((2.0 + np.cos(2.0 * np.pi * g.K[i] / g.n[i])) / 3.0)
+    return _ifft_real(_fft(f) / b)
 
 
 def bspline_weights(theta):
@@ -181,23 +208,24 @@ def bspline_weights(theta):
 
 
 def _eval_coefficients(g: Grid, c, X):
-    s1 = X[0] / g.h[0]
-    s2 = X[1] / g.h[1]
-    f1 = np.floor(s1); f2 = np.floor(s2)
-    w1 = bspline_weights(s1 - f1)
-    w2 = bspline_weights(s2 - f2)
-    i1 = f1.astype(np.int64); i2 = f2.astype(np.int64)
-    out = np.zeros(np.shape(s1))
-    for a in range(4):
-        r = np.mod(i1 + a - 1, g.n1)
-        for b in range(4):
-            q = np.mod(i2 + b - 1, g.n2)
-            out += w1[a] * w2[b] * c[r, q]
+    """Tensor-product cubic B-spline with coefficients c at the points X: the 4^d stencil
+    nodes floor(s_i) - 1 .. floor(s_i) + 2 (periodic) per axis, s_i = X_i / h_i."""
+    s = [X[i] / g.h[i] for i in range(g.d)]
+    f = [np.floor(si) for si in s]
+    w = [bspline_weights(si - fi) for si, fi in zip(s, f)]
+    base = [fi.astype(np.int64) for fi in f]
+    out = np.zeros(np.shape(s[0]))
+    for offs in itertools.product(range(4), repeat=g.d):
+        wt = w[0][offs[0]]
+        for i in range(1, g.d):
+            wt = wt * w[i][offs[i]]
+        idx = tuple(np.mod(base[i] + offs[i] - 1, g.n[i]) for i in range(g.d))
+        out += wt * c[idx]
     return out
 
 
 def interpolate(g: Grid, f, X):
-    """Value at the points X (shape (2, ...), radians) of the spline through f."""
+    """Value at the points X (shape (d, ...), radians) of the spline through f."""
     return _eval_coefficients(g, spline_coefficients(g, f), X)
 
 
@@ -216,7 +244,7 @@ def trace(g: Grid, v, ht: float, direction: int):
     """
     s = float(direction)
     Xs = g.X + s * ht * v
-    vs = np.stack([interpolate(g, v[0], Xs), interpolate(g, v[1], Xs)])
+    vs = np.stack([interpolate(g, v[c], Xs) for c in range(g.d)])
     return g.X + s * 0.5 * ht * (v + vs)
 
 
@@ -304,28 +332,28 @@ class Linearization:
 def rk2a_forward_op(g: Grid, v, divv, u):
     """L u = 1/2 (grad u . v + div(u v) - u div v)."""
     gu = fft_grad(g, u)
-    return 0.5 * (gu[0] * v[0] + gu[1] * v[1] + fft_div(g, u * v) - u * divv)
+    return 0.5 * (_dot(gu, v) + fft_div(g, u * v) - u * divv)
 
 
 def rk2a_adjoint_op(g: Grid, v, divv, lam):
     """A lam = 1/2 (div(lam v) + grad lam . v + lam div v); the adjoint equation is
     -d_t lam - A lam = 0 (A = -L^T for the discrete operators)."""
     gl = fft_grad(g, lam)
-    return 0.5 * (fft_div(g, lam * v) + gl[0] * v[0] + gl[1] * v[1] + lam * divv)
+    return 0.5 * (fft_div(g, lam * v) + _dot(gl, v) + lam * divv)
 
 
 def rk2a_state_source(g: Grid, m, vt):
     """S(m) vt = 1/2 (div(m vt) + grad m . vt - m div vt): the terms of the incremental state
     equation that carry vt (d_t m~ + L m~ + S(m) vt = 0)."""
     gm = fft_grad(g, m)
-    return 0.5 * (fft_div(g, m * vt) + gm[0] * vt[0] + gm[1] * vt[1] - m * fft_div(g, vt))
+    return 0.5 * (fft_div(g, m * vt) + _dot(gm, vt) - m * fft_div(g, vt))
 
 
 def rk2a_adjoint_source(g: Grid, lam, vt):
     """1/2 (div(lam vt) + grad lam . vt + lam div vt): the lambda terms of the full-Newton
     incremental adjoint equation (-d_t lam~ - A lam~ - this = 0)."""
     gl = fft_grad(g, lam)
-    return 0.5 * (fft_div(g, lam * vt) + gl[0] * vt[0] + gl[1] * vt[1] + lam * fft_div(g, vt))
+    return 0.5 * (fft_div(g, lam * vt) + _dot(gl, vt) + lam * fft_div(g, vt))
 
 
 def rk2a_integrand(g: Grid, lam, m):
@@ -431,7 +459,7 @@ def incremental_state(lin: Linearization, vt):
     L = lin.level
     g, p = L.grid, L.prm
     ht = 1.0 / p.nt
-    f = [-(vt[0] * gm[0] + vt[1] * gm[1]) for gm in lin.gradm]
+    f = [-_dot(vt, gm) for gm in lin.gradm]
     mt = [np.zeros(g.shape)]
     for j in range(1, p.nt + 1):
         mt.append(interpolate(g, mt[-1] + 0.5 * ht * f[j - 1], lin.Xf) + 0.5 * ht * f[j])
@@ -532,48 +560,56 @@ def _reg_symbol_nonzero(g: Grid, reg: int):
 def prec_reg(g: Grid, r, beta: float, reg: int):
     """P_REG^{-1} r: spectral inverse of beta A with the zero symbol replaced by 1 (eq. e:reg-precond)."""
     a = beta * _reg_symbol_nonzero(g, reg)
-    return np.stack([_ifft_real(_fft(r[c]) / a) for c in range(2)])
+    return np.stack([_ifft_real(_fft(r[c]) / a) for c in range(g.d)])
 
 
 def split_scale(g: Grid, r, beta: float, reg: int):
     """S r = (beta A')^{-1/2} r, the split spectral preconditioner's half step."""
     a = beta * _reg_symbol_nonzero(g, reg)
-    return np.stack([_ifft_real(_fft(r[c]) / np.sqrt(a)) for c in range(2)])
+    return np.stack([_ifft_real(_fft(r[c]) / np.sqrt(a)) for c in range(g.d)])
 
 
 def _low_mask(g: Grid):
     """Ideal low-pass: |k_i| < n_i/4, i.e. the modes a grid of half the size keeps (its Nyquist dropped)."""
-    return (np.abs(g.K1) < g.n1 / 4) & (np.abs(g.K2) < g.n2 / 4)
+    m = np.abs(g.K[0]) < g.n[0] / 4
+    for i in range(1, g.d):
+        m = m & (np.abs(g.K[i]) < g.n[i] / 4)
+    return m
 
 
 def lowpass(g: Grid, r):
     m = _low_mask(g)
-    return np.stack([_ifft_real(_fft(r[c]) * m) for c in range(2)])
+    return np.stack([_ifft_real(_fft(r[c]) * m) for c in range(g.d)])
 
 
 def _coarse_index(fine: Grid, coarse: Grid):
-    kc1 = np.fft.fftfreq(coarse.n1, 1.0 / coarse.n1).astype(np.int64)
-    kc2 = np.fft.fftfreq(coarse.n2, 1.0 / coarse.n2).astype(np.int64)
-    keep1 = np.abs(kc1) < coarse.n1 // 2
-    keep2 = np.abs(kc2) < coarse.n2 // 2
-    return kc1, kc2, keep1, keep2
+    """Fine-grid positions of the coarse modes (np.ix_ index) and the mask of the coarse modes
+    kept (|k_i| < n_i/2 of the coarse grid along every axis: its Nyquist dropped)."""
+    kc = [np.fft.fftfreq(nc, 1.0 / nc).astype(np.int64) for nc in coarse.n]
+    ix = np.ix_(*[np.mod(k, nf) for k, nf in zip(kc, fine.n)])
+    mask = np.ones(coarse.shape, dtype=bool)
+    for i, (k, nc) in enumerate(zip(kc, coarse.n)):
+        shape = [1] * coarse.d
+        shape[i] = nc
+        mask = mask & (np.abs(k) < nc // 2).reshape(shape)
+    return ix, mask
 
 
 def restrict(fine: Grid, coarse: Grid, u):
     """Spectral restriction: keep the modes |k_i| < n_i/4, rescale for the DFT size."""
-    kc1, kc2, keep1, keep2 = _coarse_index(fine, coarse)
+    ix, mask = _coarse_index(fine, coarse)
     U = _fft(u)
-    Uc = U[np.ix_(np.mod(kc1, fine.n1), np.mod(kc2, fine.n2))] * (coarse.N / fine.N)
-    Uc = Uc * np.outer(keep1, keep2)
+    Uc = U[ix] * (coarse.N / fine.N)
+    Uc = Uc * mask
     return _ifft_real(Uc)
 
 
 def prolong(fine: Grid, coarse: Grid, uc):
     """Spectral prolongation: zero padding of the coarse modes (coarse Nyquist dropped)."""
-    kc1, kc2, keep1, keep2 = _coarse_index(fine, coarse)
-    Uc = _fft(uc) * np.outer(keep1, keep2) * (fine.N / coarse.N)
+    ix, mask = _coarse_index(fine, coarse)
+    Uc = _fft(uc) * mask * (fine.N / coarse.N)
     U = np.zeros(fine.shape, dtype=np.complex128)
-    U[np.ix_(np.mod(kc1, fine.n1), np.mod(kc2, fine.n2))] = Uc
+    U[ix] = Uc
     return _ifft_real(U)
 
 
@@ -687,8 +723,8 @@ def setup_two_level(L: Level, cheb_iters=10, lanczos_steps=30, safety=1.05, seed
     fg = L.grid
     cg = fg.coarse()
     Lc = Level(cg, restrict(fg, cg, L.mT), restrict(fg, cg, L.mR), replace(L.prm, hessian="gn"))
-    lin0 = linearize(Lc, np.zeros((2,) + cg.shape))
-    q0 = splitmix64_uniform(seed, 2 * cg.N).reshape((2,) + cg.shape)
+    lin0 = linearize(Lc, np.zeros((cg.d,) + cg.shape))
+    q0 = splitmix64_uniform(seed, cg.d * cg.N).reshape((cg.d,) + cg.shape)
     emax = safety * lanczos_max(lambda s: split_matvec(lin0, s), q0, lanczos_steps)
     emin = float(np.min(1.0 + 1.0 / (L.prm.beta * _reg_symbol_nonzero(cg, L.prm.reg))))
     return TwoLevel(Lc, emin, emax, cheb_iters, solver=solver, eps=eps)
@@ -700,13 +736,13 @@ def apply_two_level(L: Level, tl: TwoLevel, r, outer_tol: float = 1.0):
     Returns z, or (z, inner iterations) for PCG(eps)."""
     fg, cg = L.grid, tl.coarse.grid
     high = r - lowpass(fg, r)
-    rc = np.stack([restrict(fg, cg, r[c]) for c in range(2)])
+    rc = np.stack([restrict(fg, cg, r[c]) for c in range(fg.d)])
     op = lambda s: split_matvec(tl.lin_c, s)
     if tl.solver == "pcg":
         zc, its, _ = pcg(op, rc, lambda x: x, tl.eps * outer_tol, tl.max_inner)
-        return high + np.stack([prolong(fg, cg, zc[c]) for c in range(2)]), its
+        return high + np.stack([prolong(fg, cg, zc[c]) for c in range(fg.d)]), its
     zc = chebyshev(op, rc, tl.emin, tl.emax, tl.cheb_iters)
-    return high + np.stack([prolong(fg, cg, zc[c]) for c in range(2)])
+    return high + np.stack([prolong(fg, cg, zc[c]) for c in range(fg.d)])
 
 
 # ---------------------------------------------------------------------------
@@ -769,7 +805,7 @@ def reestimate_emax(tl: TwoLevel, lanczos_steps=30, safety=1.05, seed=0x5EED) ->
     setup_two_level, now on the coarse split operator at the coarse problem's current
     linearisation point."""
     cg = tl.coarse.grid
-    q0 = splitmix64_uniform(seed, 2 * cg.N).reshape((2,) + cg.shape)
+    q0 = splitmix64_uniform(seed, cg.d * cg.N).reshape((cg.d,) + cg.shape)
     return safety * lanczos_max(lambda s: split_matvec(tl.lin_c, s), q0, lanczos_steps)
 
 
@@ -794,7 +830,7 @@ def newton_solve(L: Level, v0=None, pc: str = "reg", max_newton=10, gtol_rel=1e-
     the solve stops with status 'cheb_diverged'.
     """
     g, p = L.grid, L.prm
-    v = np.zeros((2,) + g.shape) if v0 is None else np.array(v0, dtype=np.float64)
+    v = np.zeros((g.d,) + g.shape) if v0 is None else np.array(v0, dtype=np.float64)
     rep = {"newton_iters": 0, "pcg_iters": 0, "matvecs": 0, "coarse_matvecs": 0,
            "grel": [], "J": [], "status": "ok", "alphas": []}
     tl = setup_two_level(L, cheb_iters, lanczos_steps, emax_safety, seed, coarse_solver, coarse_eps) \
@@ -834,7 +870,7 @@ def newton_solve(L: Level, v0=None, pc: str = "reg", max_newton=10, gtol_rel=1e-
             vt, its, st = pcg(op, -grad, lambda r: prec_reg(g, r, p.beta, p.reg), eta, max_pcg)
         else:
             fg, cg = g, tl.coarse.grid
-            vc = np.stack([restrict(fg, cg, v[c]) for c in range(2)])
+            vc = np.stack([restrict(fg, cg, v[c]) for c in range(fg.d)])
             tl.lin_c = linearize(tl.coarse, vc)
 
             def op(x):

@@ -21,7 +21,7 @@ import numpy as np
 
 __all__ = ["grid_coords", "smooth_a_template", "smooth_a_velocity", "gaussian_sum_isotropic",
            "gaussian_sum_anisotropic", "random_velocity", "config", "CONFIGS", "BATCH_SIZES", "batch_sizes",
-           "batch_pair"]
+           "batch_pair", "gaussian_sum_3d", "random_velocity_3d", "config_3d", "CONFIGS_3D"]
 
 
 def grid_coords(n1, n2):
@@ -194,3 +194,58 @@ def batch_pair(p, n):
     """Pair p of the batched workload on an n x n grid: the 'gauss256' recipe (32 isotropic
     Gaussians, 16-mode velocity |k| <= 4, amplitude 0.3) from the stream seeded 4000 + p."""
     return config("gauss256", n=n, seed=4000 + p)
+
+
+# ---------------------------------------------------------------------------
+# Three-dimensional recipes (the same families on [0, 2 pi)^3)
+# ---------------------------------------------------------------------------
+
+def gaussian_sum_3d(n1, n2, n3, rng, count=32, sigma=(0.2, 0.5), amplitude=(0.2, 1.0)):
+    """Sum of isotropic periodic 3-D Gaussians (widths in radians), min-max normalised to [0, 1]."""
+    xs = [2.0 * math.pi * np.arange(n) / n for n in (n1, n2, n3)]
+    centres = rng.uniform(0.0, 2.0 * math.pi, size=(count, 3))
+    sig = rng.uniform(sigma[0], sigma[1], size=count)
+    amp = rng.uniform(amplitude[0], amplitude[1], size=count)
+    inv = 1.0 / (2.0 * sig * sig)
+    u = np.zeros((n1, n2, n3))
+    for c in range(count):
+        f = [np.exp(-_wrap(x - centres[c, i]) ** 2 * inv[c]) for i, x in enumerate(xs)]
+        u += amp[c] * f[0][:, None, None] * f[1][None, :, None] * f[2][None, None, :]
+    return _normalise(u)
+
+
+def random_velocity_3d(n1, n2, n3, rng, modes=16, kmax=3, amplitude=0.3):
+    """Smooth periodic 3-D velocity from 'modes' random Fourier modes with 1 <= |k| <= kmax
+    (lattice points drawn without replacement, complex 3-vector coefficients with standard
+    normal parts), rescaled so that max_{x,i} |v_i(x)| equals 'amplitude'."""
+    cand = [(a, b, c) for a in range(-kmax, kmax + 1) for b in range(-kmax, kmax + 1)
+            for c in range(-kmax, kmax + 1) if 1 <= a * a + b * b + c * c <= kmax * kmax]
+    pick = rng.choice(len(cand), size=modes, replace=False)
+    xs = [2.0 * math.pi * np.arange(n) / n for n in (n1, n2, n3)]
+    v = np.zeros((3, n1, n2, n3))
+    for i in pick:
+        k = cand[i]
+        coef = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+        wave = (np.exp(1j * k[0] * xs[0])[:, None, None] * np.exp(1j * k[1] * xs[1])[None, :, None]
+                * np.exp(1j * k[2] * xs[2])[None, None, :])
+        for c in range(3):
+            v[c] += (coef[c] * wave).real
+    return v * (amplitude / float(np.max(np.abs(v))))
+
+
+# name -> (n, nt, beta, reg, template count, velocity amplitude, seed): volumes of the 2-D
+# recipes' kind (periodic Gaussian blobs moved by a smooth velocity)
+CONFIGS_3D = {
+    "gauss3d_small": (32, 4, 1e-3, 2, 12, 0.4, 21),
+    "gauss3d128": (128, 4, 1e-3, 2, 32, 0.4, 22),
+}
+
+
+def config_3d(name, n=None, seed=None):
+    """(mT, v_gen, nt, beta, reg) of a named 3-D recipe; m_R is mT transported by v_gen."""
+    n0, nt, beta, reg, count, amp, s0 = CONFIGS_3D[name]
+    n = n0 if n is None else n
+    rng = np.random.default_rng(s0 if seed is None else seed)
+    mT = gaussian_sum_3d(n, n, n, rng, count=count)
+    v = random_velocity_3d(n, n, n, rng, amplitude=amp)
+    return mT, v, nt, beta, reg
