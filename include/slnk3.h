@@ -1,0 +1,96 @@
+/* slnk3.h -- C ABI of the three-dimensional semi-Lagrangian Gauss--Newton--Krylov path on MI355X
+ * (gfx950).
+ *
+ * Nothing in the method of arXiv:1604.02153 is specific to two dimensions (section 1,
+ * "Limitations and Unresolved Issues"); this interface runs it on a periodic volume.  The
+ * operations are those of slnk.h for d = 3: the objective (eq. e:varopt:objective without the
+ * mass-source term), the reduced gradient g = beta A v + K int lambda grad m dt (eq. e:control-elim),
+ * the Gauss--Newton reduced Hessian matvec (eq. e:hessian-matvec with the lambda terms dropped,
+ * section 3.4.1), the spectral preconditioner P_REG (eq. e:reg-precond), and the globalised
+ * inexact Newton--PCG solve with P_REG (sections 3.4.1, 3.5).  Transport is the semi-Lagrangian
+ * scheme of section 3.3.2 (Heun trace of the characteristics, RK2 along them, periodic cubic
+ * spline interpolation -- here the tensor-product cubic B-spline in three dimensions, its
+ * coefficients from the exact spectral inverse of the (1, 4, 1)/6 system along each axis).
+ *
+ * Conventions
+ *   - Grid: periodic [0, 2 pi)^3 with n1 x n2 x n3 nodes, x_i = 2 pi i / n_i; every n_i a power of
+ *     two in [8, 512].  A scalar field is a row-major [n1][n2][n3] array (i3 fastest); a vector
+ *     field is three consecutive scalar fields ([3][n1][n2][n3]).
+ *   - Element type: double when params.prec == SLNK_PREC_FP64, float when SLNK_PREC_MIXED (fields
+ *     and Krylov vectors in FP32; every inner product, norm and the objective in FP64).  Scalar
+ *     outputs are double.
+ *   - Memory: every field pointer is a DEVICE pointer owned by the caller; the library owns its
+ *     workspace (allocated in slnk3_create, released in slnk3_destroy).
+ *   - Streams: all device work is enqueued on the stream given to slnk3_create; calls returning
+ *     host scalars synchronise it, and any call may synchronise to read a scalar it needs.
+ *   - Errors: every call returns an slnk_status (slnk.h); the message of the last failure is
+ *     available from slnk3_last_error.  A context is used by one host thread at a time.
+ */
+#ifndef SLNK3_H
+#define SLNK3_H
+
+#include "slnk.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct slnk3_ctx slnk3_ctx;
+
+/* nt: SL time steps on [0, 1] (>= 1); reg: SLNK_REG_H1/H2/H3 (A = -Lap, Lap^2, -Lap^3,
+ * eq. e:diffopregv); beta > 0; prec: SLNK_PREC_FP64 or SLNK_PREC_MIXED; proj: SLNK_PROJ_NONE
+ * (K = identity) or SLNK_PROJ_LERAY (K = the Leray projection, the incompressible case,
+ * section 3.1). */
+typedef struct {
+  int n1, n2, n3, nt;
+  int reg;
+  double beta;
+  int prec;
+  int proj;
+} slnk3_params;
+
+/* 64^3, nt = 4, H2, beta = 1e-3, mixed precision, K = identity. */
+void slnk3_default_params(slnk3_params* p);
+
+/* Create a context; *out is set on success.  SLNK_EINVAL for sizes outside the conventions,
+ * SLNK_ENOMEM when the workspace (about (4 nt + 60) fields of n1 n2 n3 elements) does not fit. */
+slnk_status slnk3_create(const slnk3_params* params, void* hip_stream, slnk3_ctx** out);
+void slnk3_destroy(slnk3_ctx* ctx);
+const char* slnk3_last_error(const slnk3_ctx* ctx);
+unsigned long long slnk3_workspace_bytes(const slnk3_ctx* ctx);
+
+/* Reference and template images (scalar fields); copied into the context. */
+slnk_status slnk3_set_images(slnk3_ctx* ctx, const void* m_R, const void* m_T);
+
+/* m1 = m0 transported by the stationary velocity v to t = 1 (the state equation, eq.
+ * e:state-slm).  Needs no images.  Changes the context's linearisation point. */
+slnk_status slnk3_transport_state(slnk3_ctx* ctx, const void* v, const void* m0, void* m1);
+
+/* J(v) (eq. e:varopt:objective: 1/2 ||m(1) - m_R||^2 + beta/2 <v, A v>, L2 products with the cell
+ * volume); linearises at v. */
+slnk_status slnk3_objective(slnk3_ctx* ctx, const void* v, double* J);
+
+/* g(v) (eq. e:control-elim) and, if J != NULL, J(v); linearises at v. */
+slnk_status slnk3_gradient(slnk3_ctx* ctx, const void* v, void* g, double* J);
+
+/* Hvt = beta A vt + K int lambda~ grad m dt, the Gauss--Newton matvec at the last linearisation
+ * point (eqs. e:hessian-matvec, e:inc-state-slm, e:inc-adj-slm).  SLNK_EINVAL before the first
+ * slnk3_gradient or slnk3_objective. */
+slnk_status slnk3_hessian_matvec(slnk3_ctx* ctx, const void* vt, void* Hvt);
+
+/* z = P_REG^{-1} r: the spectral inverse of beta A with its zero symbol replaced by 1 (eq.
+ * e:reg-precond). */
+slnk_status slnk3_precond_apply(slnk3_ctx* ctx, const void* r, void* z);
+
+/* Globalised inexact Gauss--Newton--Krylov solve with P_REG from v_inout (overwritten by the
+ * solution); options and report as in slnk.h (report->coarse_matvecs, emin, emax, fallback and
+ * cheb_reestimates are 0).  Returns SLNK_OK, or the status of a solve that ended early (also
+ * in report->status): SLNK_ELINESEARCH, SLNK_EMAXIT. */
+slnk_status slnk3_newton_solve(slnk3_ctx* ctx, void* v_inout, const slnk_solve_opts* opts,
+                               slnk_solve_report* report);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLNK3_H */

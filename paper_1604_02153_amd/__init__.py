@@ -11,7 +11,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["Context", "BatchContext", "UNet", "library_path", "load_library", "SolveOpts", "STATUS"]
+__all__ = ["Context", "Context3", "BatchContext", "UNet", "library_path", "load_library", "SolveOpts", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -55,6 +55,11 @@ class SolveReport(ctypes.Structure):
                 ("fallback", ctypes.c_int), ("cheb_reestimates", ctypes.c_int)]
 
 
+class Params3(ctypes.Structure):
+    _fields_ = [("n1", ctypes.c_int), ("n2", ctypes.c_int), ("n3", ctypes.c_int), ("nt", ctypes.c_int),
+                ("reg", ctypes.c_int), ("beta", ctypes.c_double), ("prec", ctypes.c_int), ("proj", ctypes.c_int)]
+
+
 class UNetParams(ctypes.Structure):
     _fields_ = [("height", ctypes.c_int), ("width", ctypes.c_int), ("levels", ctypes.c_int),
                 ("base_channels", ctypes.c_int), ("max_batch", ctypes.c_int), ("seed", ctypes.c_ulonglong),
@@ -70,6 +75,10 @@ EXPORTS = ["slnk_default_params", "slnk_default_opts", "slnk_create", "slnk_dest
            "slnk_unet_create", "slnk_unet_destroy", "slnk_unet_last_error", "slnk_unet_param_count",
            "slnk_unet_get_params", "slnk_unet_set_params", "slnk_unet_get_grads", "slnk_unet_forward",
            "slnk_unet_train_step", "slnk_unet_conv_variants", "slnk_set_images_learned", "slnk_newton_solve_learned"]
+# include/slnk3.h
+EXPORTS3 = ["slnk3_default_params", "slnk3_create", "slnk3_destroy", "slnk3_last_error", "slnk3_workspace_bytes",
+            "slnk3_set_images", "slnk3_transport_state", "slnk3_objective", "slnk3_gradient",
+            "slnk3_hessian_matvec", "slnk3_precond_apply", "slnk3_newton_solve"]
 
 
 def library_path() -> str:
@@ -129,6 +138,18 @@ def load_library():
         "slnk_unet_conv_variants": (None, [P(ctypes.c_longlong), ctypes.c_int]),
         "slnk_set_images_learned": (ctypes.c_int, [V, V, V, V]),
         "slnk_newton_solve_learned": (ctypes.c_int, [V, V, V, P(SolveOpts), P(SolveReport)]),
+        "slnk3_default_params": (None, [P(Params3)]),
+        "slnk3_create": (ctypes.c_int, [P(Params3), V, P(V)]),
+        "slnk3_destroy": (None, [V]),
+        "slnk3_last_error": (ctypes.c_char_p, [V]),
+        "slnk3_workspace_bytes": (ctypes.c_ulonglong, [V]),
+        "slnk3_set_images": (ctypes.c_int, [V, V, V]),
+        "slnk3_transport_state": (ctypes.c_int, [V, V, V, V]),
+        "slnk3_objective": (ctypes.c_int, [V, V, P(ctypes.c_double)]),
+        "slnk3_gradient": (ctypes.c_int, [V, V, V, P(ctypes.c_double)]),
+        "slnk3_hessian_matvec": (ctypes.c_int, [V, V, V]),
+        "slnk3_precond_apply": (ctypes.c_int, [V, V, V]),
+        "slnk3_newton_solve": (ctypes.c_int, [V, V, P(SolveOpts), P(SolveReport)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -315,6 +336,90 @@ class Context:
             "time_linesearch_ms": rep.time_linesearch_ms, "time_to_stop_ms": rep.time_to_stop_ms,
             "fallback": bool(rep.fallback), "cheb_reestimates": rep.cheb_reestimates,
         }
+
+
+class Context3:
+    """One registration problem on a periodic n1 x n2 x n3 volume (include/slnk3.h): scalar fields
+    [n1, n2, n3], velocities [3, n1, n2, n3] (float32 for prec="mixed", float64 for "fp64")."""
+
+    def __init__(self, n1, n2, n3, nt, reg="h2", beta=1e-3, prec="mixed", proj="none", stream=None):
+        import torch
+        lib = load_library()
+        p = Params3()
+        lib.slnk3_default_params(ctypes.byref(p))
+        p.n1, p.n2, p.n3, p.nt = int(n1), int(n2), int(n3), int(nt)
+        p.reg = REG[reg] if isinstance(reg, str) else int(reg)
+        p.beta = float(beta)
+        p.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+        p.proj = PROJ[proj] if isinstance(proj, str) else int(proj)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.dtype = torch.float64 if p.prec == 0 else torch.float32
+        self.shape = (p.n1, p.n2, p.n3)
+        self.params = p
+        self._lib = lib
+        self._ctx = ctypes.c_void_p()
+        self._check(lib.slnk3_create(ctypes.byref(p), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(self._ctx)))
+
+    def _check(self, st):
+        if st != 0:
+            msg = self._lib.slnk3_last_error(self._ctx).decode() if self._ctx else ""
+            raise SlnkError(st, msg)
+
+    def _ptr(self, t, ncomp):
+        shape = self.shape if ncomp == 1 else (ncomp,) + self.shape
+        if not t.is_cuda or t.dtype != self.dtype or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous {self.dtype} CUDA tensor of shape {shape}, got "
+                             f"{t.dtype} {tuple(t.shape)} on {t.device}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def close(self):
+        if self._ctx:
+            self._lib.slnk3_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self) -> int:
+        return int(self._lib.slnk3_workspace_bytes(self._ctx))
+
+    def set_images(self, m_R, m_T):
+        self._check(self._lib.slnk3_set_images(self._ctx, self._ptr(m_R, 1), self._ptr(m_T, 1)))
+
+    def transport_state(self, v, m0, m1):
+        self._check(self._lib.slnk3_transport_state(self._ctx, self._ptr(v, 3), self._ptr(m0, 1),
+                                                    self._ptr(m1, 1)))
+
+    def objective(self, v) -> float:
+        J = ctypes.c_double()
+        self._check(self._lib.slnk3_objective(self._ctx, self._ptr(v, 3), ctypes.byref(J)))
+        return J.value
+
+    def gradient(self, v, g) -> float:
+        J = ctypes.c_double()
+        self._check(self._lib.slnk3_gradient(self._ctx, self._ptr(v, 3), self._ptr(g, 3), ctypes.byref(J)))
+        return J.value
+
+    def hessian_matvec(self, vt, out):
+        self._check(self._lib.slnk3_hessian_matvec(self._ctx, self._ptr(vt, 3), self._ptr(out, 3)))
+
+    def precond_apply(self, r, z):
+        self._check(self._lib.slnk3_precond_apply(self._ctx, self._ptr(r, 3), self._ptr(z, 3)))
+
+    def newton_solve(self, v, opts: SolveOpts | None = None, **kw):
+        """Gauss--Newton--Krylov solve with P_REG in place; the report as a dict."""
+        if opts is None:
+            opts = default_opts(**kw)
+        rep = SolveReport()
+        st = self._lib.slnk3_newton_solve(self._ctx, self._ptr(v, 3), ctypes.byref(opts), ctypes.byref(rep))
+        if st not in (0, 5, 7):  # failed line search, Newton limit: reported
+            self._check(st)
+        return Context._report(rep)
 
 
 def transport_state_noalloc(v, m0, m1, nt, sl_path=0, stream=None):

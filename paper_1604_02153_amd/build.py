@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libslnk.so")
 SOURCES = ["spectral_f32.hip", "spectral_f64.hip", "transport.hip", "blas.hip", "unet.hip", "unet_net.cpp", "api.cpp",
-           "noalloc.hip", "rk2a.hip"]
+           "noalloc.hip", "rk2a.hip", "d3.hip", "d3_api.cpp"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

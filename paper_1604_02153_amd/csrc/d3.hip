@@ -1,0 +1,575 @@
+// Three-dimensional kernels on gfx950: FFT passes and spectral symbols (section 3.2), the
+// semi-Lagrangian step with the tricubic B-spline (section 3.3.2), the Heun trace, and the
+// elementwise and FP64 reduction kernels of the reduced gradient and Gauss--Newton matvec.
+//
+// FFT: every pass transforms lines of one axis in LDS.  The passes along x1 and x2 stage a tile of
+// CL neighbouring lines (consecutive in memory along x3) so that each global access moves CL
+// contiguous complex values; the pass along x3 (contiguous rows) stages RL whole rows.  Inside
+// LDS each line runs an iterative radix-2 Cooley--Tukey transform from bit-reversed order, with
+// twiddles from a table computed in FP64 on the host.
+#include <algorithm>
+
+#include "d3.hpp"
+
+namespace slnk {
+namespace d3 {
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename T>
+struct Tile;
+template <>
+struct Tile<float> {
+  static constexpr int CL = 16;  // lines per strided tile: 128 bytes of each row
+  static constexpr int RL = 8;   // rows per contiguous tile
+};
+template <>
+struct Tile<double> {
+  static constexpr int CL = 8;
+  static constexpr int RL = 4;
+};
+
+__device__ __forceinline__ int bitrev(int k, int logn) { return int(__brev(unsigned(k)) >> (32 - logn)); }
+
+inline int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+// In-place transforms of CL lines of length n held in LDS as s[k * CL + line], input in
+// bit-reversed order, output in natural order.  sign -1: exp(-2 pi i jk/n), +1: exp(+...).
+template <typename T, int CL>
+__device__ void lds_fft(cplx<T>* s, int n, int logn, int sign, const cplx<T>* __restrict__ tw) {
+  const int nb = (n / 2) * CL;
+  for (int st = 0; st < logn; ++st) {
+    const int half = 1 << st;
+    const int tshift = logn - 1 - st;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      const int c = b % CL, q = b / CL;
+      const int j = q & (half - 1);
+      const int i0 = ((q >> st) << (st + 1)) + j;
+      const int i1 = i0 + half;
+      cplx<T> w = tw[j << tshift];
+      if (sign > 0) w.y = -w.y;
+      const cplx<T> x0 = s[i0 * CL + c];
+      const cplx<T> x1 = cmul(w, s[i1 * CL + c]);
+      s[i0 * CL + c] = cadd(x0, x1);
+      s[i1 * CL + c] = csub(x0, x1);
+    }
+    __syncthreads();
+  }
+}
+
+// Transform along a strided axis: line (o, c) holds the elements base + k stride_k, base =
+// field z + o stride_o + c, k < n; c < inner runs over consecutive addresses.  Block: lines
+// c0 .. c0 + CL - 1 of one o (grid.y) and one field (grid.z).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_fft_strided(cplx<T>* data, size_t fstride, int n, int logn, int inner,
+                                                          long long stride_k, long long stride_o, int sign,
+                                                          const cplx<T>* __restrict__ tw) {
+  constexpr int CL = Tile<T>::CL;
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* s = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int c0 = blockIdx.x * CL;
+  cplx<T>* base = data + blockIdx.z * fstride + size_t(blockIdx.y) * stride_o + c0;
+  const int ncl = min(CL, inner - c0);
+  for (int e = threadIdx.x; e < n * CL; e += blockDim.x) {
+    const int c = e % CL, k = e / CL;
+    cplx<T> v = {T(0), T(0)};
+    if (c < ncl) v = base[k * stride_k + c];
+    s[bitrev(k, logn) * CL + c] = v;
+  }
+  __syncthreads();
+  lds_fft<T, CL>(s, n, logn, sign, tw);
+  for (int e = threadIdx.x; e < n * CL; e += blockDim.x) {
+    const int c = e % CL, k = e / CL;
+    if (c < ncl) base[k * stride_k + c] = s[k * CL + c];
+  }
+}
+
+// Real rows of length n (contiguous) -> their first n/2 + 1 Fourier coefficients.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_fft_r2c_rows(const T* __restrict__ in, size_t fin, cplx<T>* out,
+                                                           size_t fout, int rows, int n, int logn,
+                                                           const cplx<T>* __restrict__ tw) {
+  constexpr int RL = Tile<T>::RL;
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* s = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int r0 = blockIdx.x * RL;
+  const T* src = in + blockIdx.z * fin;
+  cplx<T>* dst = out + blockIdx.z * fout;
+  const int nh = n / 2 + 1;
+  for (int e = threadIdx.x; e < n * RL; e += blockDim.x) {
+    const int r = e / n, k = e - r * n;
+    const T v = r0 + r < rows ? src[size_t(r0 + r) * n + k] : T(0);
+    s[bitrev(k, logn) * RL + r] = cplx<T>{v, T(0)};
+  }
+  __syncthreads();
+  lds_fft<T, RL>(s, n, logn, -1, tw);
+  for (int e = threadIdx.x; e < nh * RL; e += blockDim.x) {
+    const int r = e / nh, k = e - r * nh;
+    if (r0 + r < rows) dst[size_t(r0 + r) * nh + k] = s[k * RL + r];
+  }
+}
+
+// Half spectra of rows -> real rows (the full row spectrum is the Hermitian extension), times scale.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_fft_c2r_rows(const cplx<T>* __restrict__ in, size_t fin, T* out,
+                                                           size_t fout, int rows, int n, int logn, T scale,
+                                                           const cplx<T>* __restrict__ tw) {
+  constexpr int RL = Tile<T>::RL;
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* s = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int r0 = blockIdx.x * RL;
+  const cplx<T>* src = in + blockIdx.z * fin;
+  T* dst = out + blockIdx.z * fout;
+  const int h = n / 2, nh = h + 1;
+  for (int e = threadIdx.x; e < n * RL; e += blockDim.x) {
+    const int r = e / n, k = e - r * n;
+    cplx<T> v = {T(0), T(0)};
+    if (r0 + r < rows) {
+      const size_t row = size_t(r0 + r) * nh;
+      v = k <= h ? src[row + k] : cconj(src[row + (n - k)]);
+    }
+    s[bitrev(k, logn) * RL + r] = v;
+  }
+  __syncthreads();
+  lds_fft<T, RL>(s, n, logn, +1, tw);
+  for (int e = threadIdx.x; e < n * RL; e += blockDim.x) {
+    const int r = e / n, k = e - r * n;
+    if (r0 + r < rows) dst[size_t(r0 + r) * n + k] = s[k * RL + r].x * scale;
+  }
+}
+
+template <typename T>
+hipError_t launch_strided(hipStream_t s, int nf, cplx<T>* S, size_t Fh, int n, int inner, int outer,
+                          long long stride_k, long long stride_o, int sign, const cplx<T>* tw) {
+  constexpr int CL = Tile<T>::CL;
+  const dim3 grid((inner + CL - 1) / CL, outer, nf);
+  const size_t lds = size_t(n) * CL * sizeof(cplx<T>);
+  hipLaunchKernelGGL(k_fft_strided<T>, grid, dim3(kThreads), lds, s, S, Fh, n, ilog2(n), inner, stride_k, stride_o,
+                     sign, tw);
+  return hipGetLastError();
+}
+
+// ---- spectral symbols ----------------------------------------------------------------------
+
+struct Wave {
+  int k1, k2, k3;      // signed wavenumbers (the x3 index of a half spectrum is k3 >= 0)
+  int o1, o2, o3;      // the same with the Nyquist components zeroed (odd-order symbols)
+};
+
+__device__ __forceinline__ Wave wave_of(size_t idx, const Dims& d) {
+  const int nh = d.nh();
+  const int i3 = int(idx % nh);
+  const size_t t = idx / nh;
+  const int i2 = int(t % d.n2), i1 = int(t / d.n2);
+  Wave w;
+  w.k1 = signed_wavenumber(i1, d.n1);
+  w.k2 = signed_wavenumber(i2, d.n2);
+  w.k3 = i3;
+  w.o1 = i1 == d.n1 / 2 ? 0 : w.k1;
+  w.o2 = i2 == d.n2 / 2 ? 0 : w.k2;
+  w.o3 = i3 == d.n3 / 2 ? 0 : w.k3;
+  return w;
+}
+
+__device__ __forceinline__ double symbol_value(const Wave& w, const Dims& d, const SymArgs& a) {
+  if (a.kind == Sym::One) return 1.0;
+  if (a.kind == Sym::Spline) {
+    const double b1 = (2.0 + cospi(2.0 * w.k1 / d.n1)) / 3.0;
+    const double b2 = (2.0 + cospi(2.0 * w.k2 / d.n2)) / 3.0;
+    const double b3 = (2.0 + cospi(2.0 * w.k3 / d.n3)) / 3.0;
+    return 1.0 / ((b1 * b2) * b3);
+  }
+  const double kk = double(w.k1) * w.k1 + double(w.k2) * w.k2 + double(w.k3) * w.k3;
+  double av = 1.0;
+  for (int r = 0; r < a.reg; ++r) av *= kk;
+  if (a.kind == Sym::Reg) return a.beta * av;
+  return 1.0 / (a.beta * (av == 0.0 ? 1.0 : av));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_symbol(Dims d, int nf, SymArgs a, cplx<T>* S) {
+  const size_t Fh = d.Fh();
+  const size_t idx = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= Fh) return;
+  const Wave w = wave_of(idx, d);
+  const T sv = T(symbol_value(w, d, a));
+  if (nf == 3 && a.proj) {
+    cplx<T> b[3] = {S[idx], S[Fh + idx], S[2 * Fh + idx]};
+    const T kk = T(double(w.o1) * w.o1 + double(w.o2) * w.o2 + double(w.o3) * w.o3);
+    if (kk > T(0)) {
+      const T o[3] = {T(w.o1), T(w.o2), T(w.o3)};
+      cplx<T> kb = cadd(cadd(cscale(b[0], o[0]), cscale(b[1], o[1])), cscale(b[2], o[2]));
+      kb = cscale(kb, T(1) / kk);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) b[c] = csub(b[c], cscale(kb, o[c]));
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) S[c * Fh + idx] = cscale(b[c], sv);
+    return;
+  }
+  for (int c = 0; c < nf; ++c) S[c * Fh + idx] = cscale(S[c * Fh + idx], sv);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_grad(Dims d, const cplx<T>* __restrict__ U, cplx<T>* out) {
+  const size_t Fh = d.Fh();
+  const size_t idx = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= Fh) return;
+  const Wave w = wave_of(idx, d);
+  const cplx<T> u = U[idx];
+  const cplx<T> iu = cmul_i(u);
+  out[idx] = cscale(iu, T(w.o1));
+  out[Fh + idx] = cscale(iu, T(w.o2));
+  out[2 * Fh + idx] = cscale(iu, T(w.o3));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_div(Dims d, cplx<T>* S) {
+  const size_t Fh = d.Fh();
+  const size_t idx = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= Fh) return;
+  const Wave w = wave_of(idx, d);
+  const cplx<T> s = cadd(cadd(cscale(S[idx], T(w.o1)), cscale(S[Fh + idx], T(w.o2))), cscale(S[2 * Fh + idx], T(w.o3)));
+  S[idx] = cmul_i(s);
+}
+
+// ---- semi-Lagrangian transport ---------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ void bspline_w(T t, T* w) {
+  const T t2 = t * t, t3 = t2 * t;
+  const T s = T(1) - t;
+  w[0] = s * s * s / T(6);
+  w[1] = (T(3) * t3 - T(6) * t2 + T(4)) / T(6);
+  w[2] = (T(-3) * t3 + T(3) * t2 + T(3) * t + T(1)) / T(6);
+  w[3] = t3 / T(6);
+}
+
+// Periodic tricubic spline with coefficients c at (s1, s2, s3) (cells): the 4 x 4 x 4 stencil
+// from floor(s_i) - 1.  Along x3 a stencil row is four consecutive values away from the end.
+template <typename T>
+__device__ T interp3(const T* __restrict__ c, const Dims& d, T s1, T s2, T s3) {
+  const T f1 = floor(s1), f2 = floor(s2), f3 = floor(s3);
+  T w1[4], w2[4], w3[4];
+  bspline_w(s1 - f1, w1);
+  bspline_w(s2 - f2, w2);
+  bspline_w(s3 - f3, w3);
+  const int b1 = wrap_index(int(f1) - 1, d.n1), b2 = wrap_index(int(f2) - 1, d.n2);
+  const int b3 = wrap_index(int(f3) - 1, d.n3);
+  int p[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) p[k] = b3 + k >= d.n3 ? b3 + k - d.n3 : b3 + k;
+  const bool straight = b3 + 3 < d.n3;
+  T acc = T(0);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int r = b1 + a >= d.n1 ? b1 + a - d.n1 : b1 + a;
+    T pa = T(0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int q = b2 + b >= d.n2 ? b2 + b - d.n2 : b2 + b;
+      const T* row = c + (size_t(r) * d.n2 + q) * d.n3;
+      T v[4];
+      if (straight) {
+        __builtin_memcpy(v, row + b3, sizeof(v));
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = row[p[k]];
+      }
+      pa += w2[b] * (w3[0] * v[0] + w3[1] * v[1] + w3[2] * v[2] + w3[3] * v[3]);
+    }
+    acc += w1[a] * pa;
+  }
+  return acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_sl_step(StepArgs<T> a) {
+  const Dims d = a.d;
+  const size_t F = d.F();
+  const size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= F) return;
+  const int i3 = int(i % d.n3);
+  const size_t t = i / d.n3;
+  const int i2 = int(t % d.n2), i1 = int(t / d.n2);
+  const T u = interp3(a.coef, d, T(i1) + a.disp[i], T(i2) + a.disp[F + i], T(i3) + a.disp[2 * F + i]);
+  switch (a.kind) {
+    case Kind::State:
+      a.dst[i] = u;
+      break;
+    case Kind::Adjoint:
+    case Kind::IncAdjoint: {
+      const T l = a.gamma[i] * u;
+      a.dst[i] = l;
+      const T wl = T(a.w) * l;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.acc[c * F + i] += wl * a.gm[c * F + i];
+      break;
+    }
+    case Kind::IncState: {
+      const T f = -(a.vt[i] * a.gm[i] + a.vt[F + i] * a.gm[F + i] + a.vt[2 * F + i] * a.gm[2 * F + i]);
+      if (!a.last) {
+        a.dst[i] = u + T(a.ht) * f;
+      } else {
+        const T lt = -(u + T(0.5 * a.ht) * f);
+        a.dst[i] = lt;
+        const T wl = T(a.w) * lt;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.acc[c * F + i] = wl * a.gm[c * F + i];
+      }
+      break;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_trace(Dims d, T ht, const T* __restrict__ v, const T* __restrict__ cv,
+                                                    const T* __restrict__ divv, const T* __restrict__ cdiv,
+                                                    T* __restrict__ df, T* __restrict__ da, T* __restrict__ gamma) {
+  const size_t F = d.F();
+  const size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= F) return;
+  const int i3 = int(i % d.n3);
+  const size_t t = i / d.n3;
+  const int i2 = int(t % d.n2), i1 = int(t / d.n2);
+  const T x[3] = {T(i1), T(i2), T(i3)};
+  const T cells[3] = {T(d.n1 / (2.0 * 3.14159265358979323846)), T(d.n2 / (2.0 * 3.14159265358979323846)),
+                      T(d.n3 / (2.0 * 3.14159265358979323846))};
+  T u[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u[c] = v[c * F + i] * cells[c];
+  // forward characteristic: X* = x - ht u; departure x - ht/2 (u + u(X*))
+  T w[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    w[c] = interp3(cv + c * F, d, x[0] - ht * u[0], x[1] - ht * u[1], x[2] - ht * u[2]) * cells[c];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) df[c * F + i] = -T(0.5) * ht * (u[c] + w[c]);
+  // adjoint characteristic: the same with +ht
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    w[c] = interp3(cv + c * F, d, x[0] + ht * u[0], x[1] + ht * u[1], x[2] + ht * u[2]) * cells[c];
+  T e[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    e[c] = T(0.5) * ht * (u[c] + w[c]);
+    da[c * F + i] = e[c];
+  }
+  const T dD = interp3(cdiv, d, x[0] + e[0], x[1] + e[1], x[2] + e[2]);
+  const T dx = divv[i];
+  gamma[i] = T(1) + T(0.5) * ht * (dD + dx) + T(0.5) * ht * ht * dD * dx;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_adjoint_start(size_t F, T w, const T* __restrict__ mR,
+                                                            const T* __restrict__ m1, const T* __restrict__ gm,
+                                                            T* __restrict__ lam, T* __restrict__ acc) {
+  const size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= F) return;
+  const T l = mR[i] - m1[i];
+  lam[i] = l;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) acc[c * F + i] = w * l * gm[c * F + i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_incstate_start(size_t F, T ht, const T* __restrict__ vt,
+                                                             const T* __restrict__ gm, T* __restrict__ q) {
+  const size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= F) return;
+  const T f = -(vt[i] * gm[i] + vt[F + i] * gm[F + i] + vt[2 * F + i] * gm[2 * F + i]);
+  q[i] = T(0.5) * ht * f;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_axpby(size_t n, T a, const T* __restrict__ x, T b,
+                                                    const T* __restrict__ y, T* __restrict__ out) {
+  for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
+    T r = T(0);
+    if (x) r = a * x[i];
+    if (y) r += b * y[i];
+    out[i] = r;
+  }
+}
+
+template <typename A, typename B>
+__global__ void __launch_bounds__(kThreads) k_convert(size_t n, const A* __restrict__ in, B* __restrict__ out) {
+  for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads)
+    out[i] = B(in[i]);
+}
+
+constexpr int kMaxReduceBlocks = 1024;
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_reduce(size_t n, int mode, const T* __restrict__ a,
+                                                     const T* __restrict__ b, double* __restrict__ partial) {
+  __shared__ double red[kThreads];
+  double s = 0.0;
+  for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
+    if (mode == 0) {
+      s += double(a[i]) * double(b[i]);
+    } else if (mode == 1) {
+      const double r = double(a[i]) - double(b[i]);
+      s += r * r;
+    } else {
+      s = fmax(s, fabs(double(a[i])));
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = mode == 2 ? fmax(red[threadIdx.x], red[threadIdx.x + w])
+                                                      : red[threadIdx.x] + red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kThreads) k_finish(int nb, int mode, const double* __restrict__ partial,
+                                                     double* __restrict__ out) {
+  __shared__ double red[kThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kThreads) s = mode == 2 ? fmax(s, partial[i]) : s + partial[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = mode == 2 ? fmax(red[threadIdx.x], red[threadIdx.x + w])
+                                                      : red[threadIdx.x] + red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+inline unsigned blocks_for(size_t n) { return unsigned((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+template <typename T>
+hipError_t fft_forward(hipStream_t s, const Dims& d, const Twiddles<T>& tw, int nf, const T* in, cplx<T>* S) {
+  constexpr int RL = Tile<T>::RL;
+  const int rows = d.n1 * d.n2, nh = d.nh();
+  const size_t F = d.F(), Fh = d.Fh();
+  hipLaunchKernelGGL(k_fft_r2c_rows<T>, dim3((rows + RL - 1) / RL, 1, nf), dim3(kThreads),
+                     size_t(d.n3) * RL * sizeof(cplx<T>), s, in, F, S, Fh, rows, d.n3, ilog2(d.n3), tw.t3);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // along x2: lines (i1, k3), element stride nh
+  e = launch_strided<T>(s, nf, S, Fh, d.n2, nh, d.n1, nh, (long long)d.n2 * nh, -1, tw.t2);
+  if (e != hipSuccess) return e;
+  // along x1: lines (i2, k3) = one contiguous run of n2 nh, element stride n2 nh
+  return launch_strided<T>(s, nf, S, Fh, d.n1, d.n2 * nh, 1, (long long)d.n2 * nh, 0, -1, tw.t1);
+}
+
+template <typename T>
+hipError_t fft_inverse(hipStream_t s, const Dims& d, const Twiddles<T>& tw, int nf, cplx<T>* S, T* out) {
+  constexpr int RL = Tile<T>::RL;
+  const int rows = d.n1 * d.n2, nh = d.nh();
+  const size_t F = d.F(), Fh = d.Fh();
+  hipError_t e = launch_strided<T>(s, nf, S, Fh, d.n1, d.n2 * nh, 1, (long long)d.n2 * nh, 0, +1, tw.t1);
+  if (e != hipSuccess) return e;
+  e = launch_strided<T>(s, nf, S, Fh, d.n2, nh, d.n1, nh, (long long)d.n2 * nh, +1, tw.t2);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fft_c2r_rows<T>, dim3((rows + RL - 1) / RL, 1, nf), dim3(kThreads),
+                     size_t(d.n3) * RL * sizeof(cplx<T>), s, S, Fh, out, F, rows, d.n3, ilog2(d.n3),
+                     T(1.0 / double(F)), tw.t3);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t spec_symbol(hipStream_t s, const Dims& d, int nf, SymArgs a, cplx<T>* S) {
+  hipLaunchKernelGGL(k_symbol<T>, dim3(blocks_for(d.Fh())), dim3(kThreads), 0, s, d, nf, a, S);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t spec_grad(hipStream_t s, const Dims& d, const cplx<T>* U, cplx<T>* out) {
+  hipLaunchKernelGGL(k_grad<T>, dim3(blocks_for(d.Fh())), dim3(kThreads), 0, s, d, U, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t spec_div(hipStream_t s, const Dims& d, cplx<T>* S) {
+  hipLaunchKernelGGL(k_div<T>, dim3(blocks_for(d.Fh())), dim3(kThreads), 0, s, d, S);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t sl_step(hipStream_t s, const StepArgs<T>& a) {
+  hipLaunchKernelGGL(k_sl_step<T>, dim3(blocks_for(a.d.F())), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t trace(hipStream_t s, const Dims& d, double ht, const T* v, const T* cv, const T* divv, const T* cdiv,
+                 T* df, T* da, T* gamma) {
+  hipLaunchKernelGGL(k_trace<T>, dim3(blocks_for(d.F())), dim3(kThreads), 0, s, d, T(ht), v, cv, divv, cdiv, df, da,
+                     gamma);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t adjoint_start(hipStream_t s, const Dims& d, double w, const T* mR, const T* m1, const T* gm, T* lam,
+                         T* acc) {
+  hipLaunchKernelGGL(k_adjoint_start<T>, dim3(blocks_for(d.F())), dim3(kThreads), 0, s, d.F(), T(w), mR, m1, gm, lam,
+                     acc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t incstate_start(hipStream_t s, const Dims& d, double ht, const T* vt, const T* gm, T* q) {
+  hipLaunchKernelGGL(k_incstate_start<T>, dim3(blocks_for(d.F())), dim3(kThreads), 0, s, d.F(), T(ht), vt, gm, q);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t axpby(hipStream_t s, size_t n, double a, const T* x, double b, const T* y, T* out) {
+  const unsigned nb = std::min<size_t>(blocks_for(n), 8192);
+  hipLaunchKernelGGL(k_axpby<T>, dim3(nb), dim3(kThreads), 0, s, n, T(a), x, T(b), y, out);
+  return hipGetLastError();
+}
+
+template <typename A, typename B>
+hipError_t convert(hipStream_t s, size_t n, const A* in, B* out) {
+  const unsigned nb = std::min<size_t>(blocks_for(n), 8192);
+  hipLaunchKernelGGL((k_convert<A, B>), dim3(nb), dim3(kThreads), 0, s, n, in, out);
+  return hipGetLastError();
+}
+template hipError_t convert<float, double>(hipStream_t, size_t, const float*, double*);
+template hipError_t convert<double, float>(hipStream_t, size_t, const double*, float*);
+
+int reduce_blocks(size_t n) { return int(std::min<size_t>(blocks_for(n), kMaxReduceBlocks)); }
+
+template <typename T>
+hipError_t reduce(hipStream_t s, size_t n, int mode, const T* a, const T* b, double* partial, double* out) {
+  const int nb = reduce_blocks(n);
+  hipLaunchKernelGGL(k_reduce<T>, dim3(nb), dim3(kThreads), 0, s, n, mode, a, b, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kThreads), 0, s, nb, mode, partial, out);
+  return hipGetLastError();
+}
+
+#define INST(T)                                                                                                   \
+  template hipError_t fft_forward<T>(hipStream_t, const Dims&, const Twiddles<T>&, int, const T*, cplx<T>*);      \
+  template hipError_t fft_inverse<T>(hipStream_t, const Dims&, const Twiddles<T>&, int, cplx<T>*, T*);            \
+  template hipError_t spec_symbol<T>(hipStream_t, const Dims&, int, SymArgs, cplx<T>*);                          \
+  template hipError_t spec_grad<T>(hipStream_t, const Dims&, const cplx<T>*, cplx<T>*);                          \
+  template hipError_t spec_div<T>(hipStream_t, const Dims&, cplx<T>*);                                           \
+  template hipError_t sl_step<T>(hipStream_t, const StepArgs<T>&);                                               \
+  template hipError_t trace<T>(hipStream_t, const Dims&, double, const T*, const T*, const T*, const T*, T*, T*,  \
+                               T*);                                                                               \
+  template hipError_t adjoint_start<T>(hipStream_t, const Dims&, double, const T*, const T*, const T*, T*, T*);  \
+  template hipError_t incstate_start<T>(hipStream_t, const Dims&, double, const T*, const T*, T*);               \
+  template hipError_t axpby<T>(hipStream_t, size_t, double, const T*, double, const T*, T*);                     \
+  template hipError_t reduce<T>(hipStream_t, size_t, int, const T*, const T*, double*, double*);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace d3
+}  // namespace slnk

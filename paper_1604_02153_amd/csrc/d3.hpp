@@ -1,0 +1,128 @@
+// Host-side launchers of the three-dimensional kernels (d3.hip).  The method carries over from
+// d = 2 unchanged (section 1, "Limitations and Unresolved Issues"): pseudospectral operators on a
+// periodic grid (section 3.2), the semi-Lagrangian transport of section 3.3.2 with the
+// tensor-product cubic B-spline in three dimensions, and the reduced gradient and Gauss--Newton
+// matvec built from them (eqs. e:control-elim, e:hessian-matvec).
+//
+// Layout: a scalar field is a row-major [n1][n2][n3] array (i3 fastest, F = n1 n2 n3 values); a
+// vector field is three consecutive scalar fields.  A half spectrum is [n1][n2][n3/2 + 1]
+// complex (Fh values): the real-to-complex transform runs along x3.  Every n_i is a power of two
+// in [8, 512].  Every launcher enqueues on the given stream, never synchronises or allocates,
+// and returns the launch status.
+#pragma once
+
+#include "common.hpp"
+
+namespace slnk {
+namespace d3 {
+
+struct Dims {
+  int n1 = 0, n2 = 0, n3 = 0;
+  __host__ __device__ size_t F() const { return size_t(n1) * n2 * n3; }
+  __host__ __device__ int nh() const { return n3 / 2 + 1; }
+  __host__ __device__ size_t Fh() const { return size_t(n1) * n2 * nh(); }
+};
+
+// Twiddle tables exp(-2 pi i j / n), j < n / 2, per axis (device memory, computed in FP64).
+template <typename T>
+struct Twiddles {
+  const cplx<T>* t1 = nullptr;
+  const cplx<T>* t2 = nullptr;
+  const cplx<T>* t3 = nullptr;
+};
+
+// Largest transform length supported (LDS tile of the strided passes).
+constexpr int kMaxN = 512;
+
+// Forward transform of nf real fields (consecutive, F apart) into nf half spectra (Fh apart):
+// unnormalised, exp(-i k x) (numpy's fftn convention).
+template <typename T>
+hipError_t fft_forward(hipStream_t s, const Dims& d, const Twiddles<T>& tw, int nf, const T* in, cplx<T>* S);
+// Inverse transform of nf half spectra into nf real fields, scaled by 1/F; the spectra are
+// overwritten.  Each half spectrum must be that of a real field (Hermitian along x3).
+template <typename T>
+hipError_t fft_inverse(hipStream_t s, const Dims& d, const Twiddles<T>& tw, int nf, cplx<T>* S, T* out);
+
+// Scalar symbols (all real and even in k).
+enum class Sym : int {
+  One = 0,      // 1
+  Reg = 1,      // beta a(k), a = |k|^(2 reg)
+  RegInv = 2,   // 1 / (beta a'(k)), a' = a with a(0) replaced by 1 (P_REG^{-1})
+  Spline = 3,   // 1 / (B(k1) B(k2) B(k3)), B(k) = (2 + cos(2 pi k / n)) / 3 (B-spline prefilter)
+};
+struct SymArgs {
+  Sym kind = Sym::One;
+  int reg = 2;
+  double beta = 1.0;
+  int proj = 0;  // nf = 3 only: apply the Leray projection b - k (k . b) / |k|^2 first (odd-order k)
+};
+// S[c] *= symbol for c < nf (nf = 1 or 3), in place.
+template <typename T>
+hipError_t spec_symbol(hipStream_t s, const Dims& d, int nf, SymArgs a, cplx<T>* S);
+// out[c] = i k_c U (c = 0, 1, 2; Nyquist components zero): the gradient's spectra.
+template <typename T>
+hipError_t spec_grad(hipStream_t s, const Dims& d, const cplx<T>* U, cplx<T>* out);
+// S[0] = sum_c i k_c S[c]: the divergence's spectrum (in place into the first spectrum).
+template <typename T>
+hipError_t spec_div(hipStream_t s, const Dims& d, cplx<T>* S);
+
+// One semi-Lagrangian time step (section 3.3.2) at every node x: u = I[coef](x + disp) (the
+// cubic spline with B-spline coefficients coef at the departure point, displacement in cells),
+// then, by kind:
+//   State       dst = u
+//   Adjoint     lam = gamma u; dst = lam; acc += w lam gm
+//   IncState    f = -(vt . gm); mt = u + ht/2 f; not last: dst = u + ht f (the next step's
+//               transported field m~ + ht/2 f); last: dst = -mt, acc = w (-mt) gm
+//   IncAdjoint  lt = gamma u; dst = lt; acc += w lt gm
+// (gm: gradient of the state at the output's time level; eqs. e:state-slm, e:adj-slm,
+// e:inc-state-slm, e:inc-adj-slm).
+enum class Kind : int { State = 0, Adjoint = 1, IncState = 2, IncAdjoint = 3 };
+template <typename T>
+struct StepArgs {
+  Dims d;
+  Kind kind = Kind::State;
+  const T* coef = nullptr;
+  const T* disp = nullptr;
+  const T* gamma = nullptr;
+  const T* gm = nullptr;
+  const T* vt = nullptr;
+  T* dst = nullptr;
+  T* acc = nullptr;
+  double w = 0.0, ht = 0.0;
+  int last = 0;
+};
+template <typename T>
+hipError_t sl_step(hipStream_t s, const StepArgs<T>& a);
+
+// Departure points of both characteristics by Heun's method and the adjoint factor:
+//   df = -ht/2 (u(x) + u(x - ht u(x))), da = +ht/2 (u(x) + u(x + ht u(x))) (cells; u the
+//   velocity in cells per unit time, its values off the grid from the coefficients cv),
+//   gamma = 1 + ht/2 (dD + dx) + ht^2/2 dD dx, dx = div v at x, dD = div v at x + da (from cdiv).
+template <typename T>
+hipError_t trace(hipStream_t s, const Dims& d, double ht, const T* v, const T* cv, const T* divv, const T* cdiv,
+                 T* df, T* da, T* gamma);
+
+// lam = mR - m1; acc = w lam gm (the adjoint's final value and its first b term)
+template <typename T>
+hipError_t adjoint_start(hipStream_t s, const Dims& d, double w, const T* mR, const T* m1, const T* gm, T* lam,
+                         T* acc);
+// q = -ht/2 (vt . gm): the incremental state's first transported field (m~(0) = 0)
+template <typename T>
+hipError_t incstate_start(hipStream_t s, const Dims& d, double ht, const T* vt, const T* gm, T* q);
+
+// out = in converted to the other precision, n values
+template <typename A, typename B>
+hipError_t convert(hipStream_t s, size_t n, const A* in, B* out);
+
+// out = a x + b y over n values (scalars cast to T; x or y may be null for a zero term)
+template <typename T>
+hipError_t axpby(hipStream_t s, size_t n, double a, const T* x, double b, const T* y, T* out);
+
+// FP64 reductions over n values into partial[blocks] (reduce_blocks(n) of them), then one
+// block sums them in a fixed order into *out: mode 0 sum a b, 1 sum (a - b)^2, 2 max |a|.
+int reduce_blocks(size_t n);
+template <typename T>
+hipError_t reduce(hipStream_t s, size_t n, int mode, const T* a, const T* b, double* partial, double* out);
+
+}  // namespace d3
+}  // namespace slnk

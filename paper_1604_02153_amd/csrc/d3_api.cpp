@@ -1,0 +1,653 @@
+// Host side of the three-dimensional path (include/slnk3.h): the context, the linearisation
+// (trace, state solve, gradients of the state), the reduced gradient, the Gauss--Newton matvec,
+// P_REG and the Newton--PCG solve with Armijo backtracking (sections 3.3.2, 3.4.1, 3.5), all on
+// the kernels of d3.hip.  Every inner product and norm is an FP64 reduction on the GPU, summed in
+// a fixed order (the same inputs give the same bits).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/slnk3.h"
+#include "d3.hpp"
+
+namespace slnk {
+namespace d3 {
+namespace {
+
+struct Err {
+  slnk_status st;
+  std::string msg;
+};
+
+#define D3CHK(expr)                                                                                           \
+  do {                                                                                                        \
+    hipError_t _e = (expr);                                                                                   \
+    if (_e != hipSuccess) throw Err{SLNK_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)};        \
+  } while (0)
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+bool size_ok(int n) { return n >= 8 && n <= kMaxN && (n & (n - 1)) == 0; }
+
+// weight of time level j in the composite trapezoid rule on t^0..t^nt (sums to 1)
+double trap_w(int j, int nt) { return (j == 0 || j == nt) ? 0.5 / nt : 1.0 / nt; }
+
+class Base {
+ public:
+  virtual ~Base() = default;
+  virtual void set_images(const void* mR, const void* mT) = 0;
+  virtual void transport_state(const void* v, const void* m0, void* m1) = 0;
+  virtual double objective(const void* v) = 0;
+  virtual double gradient(const void* v, void* g) = 0;
+  virtual void hessian(const void* vt, void* out) = 0;
+  virtual void precond(const void* r, void* z) = 0;
+  virtual slnk_status newton(void* v, const slnk_solve_opts& o, slnk_solve_report& rep) = 0;
+  size_t bytes = 0;
+};
+
+template <typename T>
+class Ctx final : public Base {
+ public:
+  Ctx(const slnk3_params& p, hipStream_t s) : p_(p), s_(s) {
+    d_.n1 = p.n1;
+    d_.n2 = p.n2;
+    d_.n3 = p.n3;
+    F_ = d_.F();
+    Fh_ = d_.Fh();
+    ht_ = 1.0 / p.nt;
+    cell_ = std::pow(2.0 * 3.14159265358979323846, 3) / double(F_);
+    try {
+      allocate();
+    } catch (...) {
+      release();
+      throw;
+    }
+  }
+  ~Ctx() override { release(); }
+
+  void set_images(const void* mR, const void* mT) override {
+    D3CHK(hipMemcpyAsync(mR_, mR, F_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+    D3CHK(hipMemcpyAsync(mT_, mT, F_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+    for (const T* img : {mR_, mT_})
+      if (!std::isfinite(reduce(0, F_, img, img))) throw Err{SLNK_ENAN, "non-finite image value"};
+    images_ = true;
+    lin_ = false;
+  }
+
+  void transport_state(const void* v, const void* m0, void* m1) override {
+    lin_ = false;
+    trace_at(static_cast<const T*>(v));
+    const T* cur = static_cast<const T*>(m0);
+    T* bufs[2] = {lam0_, lam1_};
+    for (int j = 1; j <= p_.nt; ++j) {
+      T* out = j == p_.nt ? static_cast<T*>(m1) : bufs[j & 1];
+      coefficients(cur, coef_, 1);
+      StepArgs<T> a;
+      a.d = d_;
+      a.kind = Kind::State;
+      a.coef = coef_;
+      a.disp = df_;
+      a.dst = out;
+      D3CHK(sl_step<T>(s_, a));
+      cur = out;
+    }
+    D3CHK(hipStreamSynchronize(s_));
+  }
+
+  double objective(const void* v) override {
+    need_images();
+    linearize(static_cast<const T*>(v));
+    return J_;
+  }
+
+  double gradient(const void* v, void* g) override {
+    need_images();
+    linearize(static_cast<const T*>(v));
+    gradient_at(static_cast<T*>(g));
+    D3CHK(hipStreamSynchronize(s_));
+    return J_;
+  }
+
+  void hessian(const void* vt, void* out) override {
+    if (!lin_) throw Err{SLNK_EINVAL, "the matvec needs a linearisation (slnk3_gradient or slnk3_objective)"};
+    matvec(static_cast<const T*>(vt), static_cast<T*>(out));
+  }
+
+  void precond(const void* r, void* z) override {
+    apply_symbol(static_cast<const T*>(r), static_cast<T*>(z), SymArgs{Sym::RegInv, p_.reg, p_.beta, 0});
+  }
+
+  slnk_status newton(void* vio, const slnk_solve_opts& o, slnk_solve_report& rep) override {
+    need_images();
+    std::memset(&rep, 0, sizeof(rep));
+    const double t0 = now_ms();
+    const size_t V = 3 * F_;
+    T* vin = static_cast<T*>(vio);
+    D3CHK(hipMemcpyAsync(vk_, vin, V * sizeof(T), hipMemcpyDeviceToDevice, s_));
+    double g0_inf, g0_two;
+    const bool cold = reduce(2, V, vk_, nullptr) == 0.0;
+    if (!cold) {  // norms of the gradient at v = 0 for the relative stopping test
+      D3CHK(hipMemsetAsync(trial_, 0, V * sizeof(T), s_));
+      linearize(trial_);
+      gradient_at(gk_);
+      g0_inf = reduce(2, V, gk_, nullptr);
+      g0_two = std::sqrt(reduce(0, V, gk_, gk_));
+    }
+    double tg = now_ms();
+    linearize(vk_);
+    gradient_at(gk_);
+    double Jk = J_;
+    rep.time_gradient_ms += now_ms() - tg;
+    if (cold) {
+      g0_inf = reduce(2, V, gk_, nullptr);
+      g0_two = std::sqrt(reduce(0, V, gk_, gk_));
+    }
+    rep.g0_inf = g0_inf;
+    rep.g0_two = g0_two;
+    if (!(g0_inf > 0.0) || !std::isfinite(g0_two)) throw Err{SLNK_ENAN, "gradient at v = 0 is zero or not finite"};
+    slnk_status status = SLNK_OK;
+    for (int k = 0; k <= o.max_newton; ++k) {
+      const double ginf = reduce(2, V, gk_, nullptr);
+      const double gtwo = std::sqrt(reduce(0, V, gk_, gk_));
+      if (!std::isfinite(gtwo)) throw Err{SLNK_ENAN, "non-finite gradient"};
+      if (k <= SLNK_REPORT_MAX_ITERS) {
+        rep.grel[k] = ginf / g0_inf;
+        rep.J[k] = Jk;
+      }
+      if (ginf / g0_inf <= o.gtol_rel || ginf <= o.gtol_abs) break;
+      if (k == o.max_newton) {
+        status = SLNK_EMAXIT;
+        break;
+      }
+      const double eta = std::min(0.5, gtwo / g0_two);
+      const double tp = now_ms();
+      const int its = pcg(eta, o.max_pcg, rep);
+      rep.time_pcg_ms += now_ms() - tp;
+      rep.pcg_iters += its;
+      if (k < SLNK_REPORT_MAX_ITERS) rep.pcg[k] = its;
+      const double slope = cell_ * reduce(0, V, gk_, x_);
+      const double tl = now_ms();
+      double alpha = 1.0;
+      bool accepted = false;
+      for (int h = 0; h <= o.max_halvings; ++h) {
+        D3CHK(axpby<T>(s_, V, 1.0, vk_, alpha, x_, trial_));
+        linearize(trial_);
+        ++rep.line_search_evals;
+        if (J_ <= Jk + o.armijo_c1 * alpha * slope) {
+          accepted = true;
+          break;
+        }
+        alpha *= 0.5;
+      }
+      rep.time_linesearch_ms += now_ms() - tl;
+      if (!accepted) {
+        status = SLNK_ELINESEARCH;
+        break;
+      }
+      std::swap(vk_, trial_);
+      Jk = J_;
+      tg = now_ms();
+      gradient_at(gk_);
+      rep.time_gradient_ms += now_ms() - tg;
+      rep.newton_iters = k + 1;
+    }
+    D3CHK(hipMemcpyAsync(vin, vk_, V * sizeof(T), hipMemcpyDeviceToDevice, s_));
+    D3CHK(hipStreamSynchronize(s_));
+    rep.status = status;
+    rep.time_total_ms = now_ms() - t0;
+    rep.time_to_stop_ms = rep.time_total_ms;
+    return status;
+  }
+
+ private:
+  void release() {
+    if (hres_) (void)hipHostFree(hres_);
+    if (base_) (void)hipFree(base_);
+    hres_ = nullptr;
+    base_ = nullptr;
+  }
+
+  void need_images() const {
+    if (!images_) throw Err{SLNK_EINVAL, "slnk3_set_images must come first"};
+  }
+
+  template <typename U>
+  U* take(size_t n) {
+    const size_t off = (used_ + 255) / 256 * 256;
+    used_ = off + n * sizeof(U);
+    return reinterpret_cast<U*>(base_ + off);
+  }
+
+  void carve() {
+    used_ = 0;
+    const size_t V = 3 * F_;
+    const int nt = p_.nt;
+    tw1_ = take<cplx<T>>(d_.n1 / 2);
+    tw2_ = take<cplx<T>>(d_.n2 / 2);
+    tw3_ = take<cplx<T>>(d_.n3 / 2);
+    mR_ = take<T>(F_);
+    mT_ = take<T>(F_);
+    v_ = take<T>(V);
+    cv_ = take<T>(V);
+    divv_ = take<T>(F_);
+    cdiv_ = take<T>(F_);
+    df_ = take<T>(V);
+    da_ = take<T>(V);
+    gamma_ = take<T>(F_);
+    Av_ = take<T>(V);
+    m_ = take<T>(size_t(nt + 1) * F_);
+    gm_ = take<T>(size_t(nt + 1) * V);
+    lam0_ = take<T>(F_);
+    lam1_ = take<T>(F_);
+    coef_ = take<T>(F_);
+    acc_ = take<T>(V);
+    t3a_ = take<T>(V);
+    t3b_ = take<T>(V);
+    vk_ = take<T>(V);
+    gk_ = take<T>(V);
+    trial_ = take<T>(V);
+    x_ = take<T>(V);
+    r_ = take<T>(V);
+    z_ = take<T>(V);
+    pp_ = take<T>(V);
+    q_ = take<T>(V);
+    S1_ = take<cplx<T>>(3 * Fh_);
+    S2_ = take<cplx<T>>(3 * Fh_);
+    if constexpr (std::is_same_v<T, float>) {  // FP64 beta A of the mixed context
+      twd1_ = take<cplx<double>>(d_.n1 / 2);
+      twd2_ = take<cplx<double>>(d_.n2 / 2);
+      twd3_ = take<cplx<double>>(d_.n3 / 2);
+      xd_ = take<double>(V);
+      Sd_ = take<cplx<double>>(3 * Fh_);
+    }
+    partial_ = take<double>(size_t(reduce_blocks(V)));
+    dres_ = take<double>(8);
+  }
+
+  void allocate() {
+    base_ = nullptr;
+    carve();  // sizes only (base_ null)
+    bytes = used_ + 256;
+    if (hipMalloc(reinterpret_cast<void**>(&base_), bytes) != hipSuccess) {
+      base_ = nullptr;
+      (void)hipGetLastError();
+      throw Err{SLNK_ENOMEM, "workspace allocation failed"};
+    }
+    carve();
+    D3CHK(hipHostMalloc(reinterpret_cast<void**>(&hres_), 8 * sizeof(double), hipHostMallocDefault));
+    D3CHK(hipMemsetAsync(base_, 0, bytes, s_));
+    upload_twiddles(tw1_, d_.n1);
+    upload_twiddles(tw2_, d_.n2);
+    upload_twiddles(tw3_, d_.n3);
+    tw_.t1 = tw1_;
+    tw_.t2 = tw2_;
+    tw_.t3 = tw3_;
+    if constexpr (std::is_same_v<T, float>) {
+      upload_twiddles(twd1_, d_.n1);
+      upload_twiddles(twd2_, d_.n2);
+      upload_twiddles(twd3_, d_.n3);
+      twd_.t1 = twd1_;
+      twd_.t2 = twd2_;
+      twd_.t3 = twd3_;
+    }
+  }
+
+  // twiddles exp(-2 pi i j / n), j < n/2, computed in FP64 and rounded to U
+  template <typename U>
+  void upload_twiddles(cplx<U>* dst, int n) {
+    std::vector<cplx<U>> h(n / 2);
+    for (int j = 0; j < n / 2; ++j) {
+      const double a = -2.0 * 3.14159265358979323846 * j / n;
+      h[j] = cplx<U>{U(std::cos(a)), U(std::sin(a))};
+    }
+    D3CHK(hipMemcpyAsync(dst, h.data(), h.size() * sizeof(cplx<U>), hipMemcpyHostToDevice, s_));
+    D3CHK(hipStreamSynchronize(s_));
+  }
+
+  // out = beta A x (a vector field).  The mixed context forms it in FP64 and rounds once: the
+  // symbol beta |k|^(2 reg) would otherwise multiply the FP32 rounding of the transform of x by up
+  // to beta max a(k).
+  void reg_apply(const T* x, T* out, double beta) {
+    const SymArgs a{Sym::Reg, p_.reg, beta, 0};
+    if constexpr (std::is_same_v<T, float>) {
+      const size_t V = 3 * F_;
+      D3CHK((convert<float, double>(s_, V, x, xd_)));
+      D3CHK(fft_forward<double>(s_, d_, twd_, 3, xd_, Sd_));
+      D3CHK(spec_symbol<double>(s_, d_, 3, a, Sd_));
+      D3CHK(fft_inverse<double>(s_, d_, twd_, 3, Sd_, xd_));
+      D3CHK((convert<double, float>(s_, V, xd_, out)));
+    } else {
+      apply_symbol(x, out, a);
+    }
+  }
+
+  // FP64 reduction of n values (mode 0: sum a b, 1: sum (a - b)^2, 2: max |a|), read on the host
+  double reduce(int mode, size_t n, const T* a, const T* b) {
+    D3CHK(d3::reduce<T>(s_, n, mode, a, b, partial_, dres_));
+    D3CHK(hipMemcpyAsync(hres_, dres_, sizeof(double), hipMemcpyDeviceToHost, s_));
+    D3CHK(hipStreamSynchronize(s_));
+    return hres_[0];
+  }
+
+  // B-spline coefficients of nf fields (nf = 1 or 3): the spectral inverse of the (1, 4, 1)/6
+  // system along each axis (section 3.3.2, "Interpolation")
+  void coefficients(const T* f, T* c, int nf) {
+    D3CHK(fft_forward<T>(s_, d_, tw_, nf, f, S1_));
+    D3CHK(spec_symbol<T>(s_, d_, nf, SymArgs{Sym::Spline, p_.reg, 1.0, 0}, S1_));
+    D3CHK(fft_inverse<T>(s_, d_, tw_, nf, S1_, c));
+  }
+
+  // out = symbol(in) for a vector field (with the Leray projection first when a.proj)
+  void apply_symbol(const T* in, T* out, SymArgs a) {
+    D3CHK(fft_forward<T>(s_, d_, tw_, 3, in, S1_));
+    D3CHK(spec_symbol<T>(s_, d_, 3, a, S1_));
+    D3CHK(fft_inverse<T>(s_, d_, tw_, 3, S1_, out));
+  }
+
+  void gradient_of(const T* f, T* g) {
+    D3CHK(fft_forward<T>(s_, d_, tw_, 1, f, S1_));
+    D3CHK(spec_grad<T>(s_, d_, S1_, S2_));
+    D3CHK(fft_inverse<T>(s_, d_, tw_, 3, S2_, g));
+  }
+
+  void divergence_of(const T* v, T* out) {
+    D3CHK(fft_forward<T>(s_, d_, tw_, 3, v, S1_));
+    D3CHK(spec_div<T>(s_, d_, S1_));
+    D3CHK(fft_inverse<T>(s_, d_, tw_, 1, S1_, out));
+  }
+
+  // characteristics and adjoint factor of v (copied into v_)
+  void trace_at(const T* v) {
+    if (v != v_) D3CHK(hipMemcpyAsync(v_, v, 3 * F_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+    if (!std::isfinite(reduce(0, 3 * F_, v_, v_))) throw Err{SLNK_ENAN, "non-finite velocity"};
+    coefficients(v_, cv_, 3);
+    divergence_of(v_, divv_);
+    coefficients(divv_, cdiv_, 1);
+    D3CHK(d3::trace<T>(s_, d_, ht_, v_, cv_, divv_, cdiv_, df_, da_, gamma_));
+  }
+
+  // trace, state m^0..m^nt (eq. e:state-slm), grad m^j, A v and J
+  void linearize(const T* v) {
+    trace_at(v);
+    const size_t V = 3 * F_;
+    D3CHK(hipMemcpyAsync(m_, mT_, F_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+    for (int j = 1; j <= p_.nt; ++j) {
+      coefficients(m_ + size_t(j - 1) * F_, coef_, 1);
+      StepArgs<T> a;
+      a.d = d_;
+      a.kind = Kind::State;
+      a.coef = coef_;
+      a.disp = df_;
+      a.dst = m_ + size_t(j) * F_;
+      D3CHK(sl_step<T>(s_, a));
+    }
+    for (int j = 0; j <= p_.nt; ++j) gradient_of(m_ + size_t(j) * F_, gm_ + size_t(j) * V);
+    reg_apply(v_, Av_, 1.0);
+    const double mis = reduce(1, F_, m_ + size_t(p_.nt) * F_, mR_);
+    const double reg = reduce(0, V, v_, Av_);
+    J_ = 0.5 * cell_ * mis + 0.5 * p_.beta * cell_ * reg;
+    if (!std::isfinite(J_)) throw Err{SLNK_ENAN, "non-finite objective"};
+    lin_ = true;
+  }
+
+  // g = beta A v + K b, b = int lambda grad m dt (adjoint eq. e:adj-slm backward from lambda(1) = m_R - m(1))
+  void gradient_at(T* g) {
+    const size_t V = 3 * F_;
+    const int nt = p_.nt;
+    D3CHK(adjoint_start<T>(s_, d_, trap_w(nt, nt), mR_, m_ + size_t(nt) * F_, gm_ + size_t(nt) * V, lam1_, acc_));
+    backward_sweep(lam1_, Kind::Adjoint);
+    project_and_add(p_.beta, Av_, g);
+  }
+
+  // adjoint-type sweep j = nt .. 1 from the field in 'start': lambda^{j-1} = gamma I[lambda^j](x + da),
+  // acc += w_{j-1} lambda^{j-1} grad m^{j-1}
+  void backward_sweep(T* start, Kind kind) {
+    const size_t V = 3 * F_;
+    T* cur = start;
+    T* nxt = start == lam0_ ? lam1_ : lam0_;
+    for (int j = p_.nt; j >= 1; --j) {
+      coefficients(cur, coef_, 1);
+      StepArgs<T> a;
+      a.d = d_;
+      a.kind = kind;
+      a.coef = coef_;
+      a.disp = da_;
+      a.gamma = gamma_;
+      a.gm = gm_ + size_t(j - 1) * V;
+      a.dst = nxt;
+      a.acc = acc_;
+      a.w = trap_w(j - 1, p_.nt);
+      D3CHK(sl_step<T>(s_, a));
+      std::swap(cur, nxt);
+    }
+  }
+
+  // out = c add + K acc (K the Leray projection or the identity)
+  void project_and_add(double c, const T* add, T* out) {
+    const T* kb = acc_;
+    if (p_.proj) {
+      apply_symbol(acc_, t3b_, SymArgs{Sym::One, p_.reg, 1.0, 1});
+      kb = t3b_;
+    }
+    D3CHK(axpby<T>(s_, 3 * F_, c, add, 1.0, kb, out));
+  }
+
+  // Gauss--Newton matvec: incremental state (eq. e:inc-state-slm) forward from m~(0) = 0, the
+  // incremental adjoint (eq. e:inc-adj-slm, lambda terms dropped) backward from -m~(1), then
+  // beta A vt + K int lambda~ grad m dt
+  void matvec(const T* vt, T* out) {
+    const size_t V = 3 * F_;
+    const int nt = p_.nt;
+    D3CHK(incstate_start<T>(s_, d_, ht_, vt, gm_, lam0_));
+    T* cur = lam0_;
+    T* nxt = lam1_;
+    for (int j = 1; j <= nt; ++j) {
+      coefficients(cur, coef_, 1);
+      StepArgs<T> a;
+      a.d = d_;
+      a.kind = Kind::IncState;
+      a.coef = coef_;
+      a.disp = df_;
+      a.gm = gm_ + size_t(j) * V;
+      a.vt = vt;
+      a.dst = nxt;
+      a.acc = acc_;
+      a.w = trap_w(nt, nt);
+      a.ht = ht_;
+      a.last = j == nt;
+      D3CHK(sl_step<T>(s_, a));
+      std::swap(cur, nxt);
+    }
+    backward_sweep(cur, Kind::IncAdjoint);
+    reg_apply(vt, t3a_, p_.beta);
+    project_and_add(1.0, t3a_, out);
+  }
+
+  // PCG on H x = -g_k with P_REG from x = 0 to ||r|| <= tol ||b|| (the oracle's pcg); returns
+  // the iterations; the step is left in x_
+  int pcg(double tol, int maxit, slnk_solve_report& rep) {
+    const size_t V = 3 * F_;
+    D3CHK(axpby<T>(s_, V, -1.0, gk_, 0.0, nullptr, r_));
+    D3CHK(hipMemsetAsync(x_, 0, V * sizeof(T), s_));
+    const double bnorm = std::sqrt(reduce(0, V, r_, r_));
+    if (bnorm == 0.0) return 0;
+    double tp = now_ms();
+    precond(r_, z_);
+    D3CHK(hipMemcpyAsync(pp_, z_, V * sizeof(T), hipMemcpyDeviceToDevice, s_));
+    double rz = reduce(0, V, r_, z_);
+    rep.time_precond_ms += now_ms() - tp;
+    for (int it = 1; it <= maxit; ++it) {
+      matvec(pp_, q_);
+      ++rep.matvecs;
+      const double pq = reduce(0, V, pp_, q_);
+      if (!(pq > 0.0)) {
+        if (it == 1) D3CHK(hipMemcpyAsync(x_, z_, V * sizeof(T), hipMemcpyDeviceToDevice, s_));
+        return it;
+      }
+      const double alpha = rz / pq;
+      D3CHK(axpby<T>(s_, V, 1.0, x_, alpha, pp_, x_));
+      D3CHK(axpby<T>(s_, V, 1.0, r_, -alpha, q_, r_));
+      if (std::sqrt(reduce(0, V, r_, r_)) <= tol * bnorm) return it;
+      if (!(rz > 0.0)) return it;
+      tp = now_ms();
+      precond(r_, z_);
+      const double rz_next = reduce(0, V, r_, z_);
+      rep.time_precond_ms += now_ms() - tp;
+      D3CHK(axpby<T>(s_, V, 1.0, z_, rz_next / rz, pp_, pp_));
+      rz = rz_next;
+    }
+    return maxit;
+  }
+
+  slnk3_params p_;
+  hipStream_t s_;
+  Dims d_;
+  size_t F_ = 0, Fh_ = 0;
+  double ht_ = 0.0, cell_ = 0.0, J_ = 0.0;
+  bool images_ = false, lin_ = false;
+  char* base_ = nullptr;
+  size_t used_ = 0;
+  double* hres_ = nullptr;
+  Twiddles<T> tw_;
+  cplx<T>*tw1_ = nullptr, *tw2_ = nullptr, *tw3_ = nullptr;
+  T *mR_ = nullptr, *mT_ = nullptr, *v_ = nullptr, *cv_ = nullptr, *divv_ = nullptr, *cdiv_ = nullptr;
+  T *df_ = nullptr, *da_ = nullptr, *gamma_ = nullptr, *Av_ = nullptr, *m_ = nullptr, *gm_ = nullptr;
+  T *lam0_ = nullptr, *lam1_ = nullptr, *coef_ = nullptr, *acc_ = nullptr, *t3a_ = nullptr, *t3b_ = nullptr;
+  T *vk_ = nullptr, *gk_ = nullptr, *trial_ = nullptr, *x_ = nullptr, *r_ = nullptr, *z_ = nullptr, *pp_ = nullptr,
+    *q_ = nullptr;
+  cplx<T>*S1_ = nullptr, *S2_ = nullptr;
+  Twiddles<double> twd_;
+  cplx<double>*twd1_ = nullptr, *twd2_ = nullptr, *twd3_ = nullptr, *Sd_ = nullptr;
+  double* xd_ = nullptr;
+  double *partial_ = nullptr, *dres_ = nullptr;
+};
+
+}  // namespace
+}  // namespace d3
+}  // namespace slnk
+
+struct slnk3_ctx {
+  std::unique_ptr<slnk::d3::Base> impl;
+  std::string err;
+};
+
+namespace {
+
+template <class Fn>
+slnk_status guard3(slnk3_ctx* ctx, Fn&& fn) {
+  if (!ctx || !ctx->impl) return SLNK_EINVAL;
+  try {
+    fn(*ctx->impl);
+    return SLNK_OK;
+  } catch (const slnk::d3::Err& e) {
+    ctx->err = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return SLNK_ENOMEM;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void slnk3_default_params(slnk3_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->n1 = p->n2 = p->n3 = 64;
+  p->nt = 4;
+  p->reg = SLNK_REG_H2;
+  p->beta = 1e-3;
+  p->prec = SLNK_PREC_MIXED;
+  p->proj = SLNK_PROJ_NONE;
+}
+
+slnk_status slnk3_create(const slnk3_params* p, void* hip_stream, slnk3_ctx** out) {
+  if (!p || !out) return SLNK_EINVAL;
+  *out = nullptr;
+  using slnk::d3::size_ok;
+  if (!size_ok(p->n1) || !size_ok(p->n2) || !size_ok(p->n3) || p->nt < 1 || p->nt > 1000 || p->reg < 1 ||
+      p->reg > 3 || !(p->beta > 0.0) || !std::isfinite(p->beta) ||
+      (p->prec != SLNK_PREC_FP64 && p->prec != SLNK_PREC_MIXED) || (p->proj != 0 && p->proj != 1))
+    return SLNK_EINVAL;
+  auto ctx = std::make_unique<slnk3_ctx>();
+  try {
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (p->prec == SLNK_PREC_FP64)
+      ctx->impl = std::make_unique<slnk::d3::Ctx<double>>(*p, s);
+    else
+      ctx->impl = std::make_unique<slnk::d3::Ctx<float>>(*p, s);
+  } catch (const slnk::d3::Err& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    return SLNK_ENOMEM;
+  }
+  *out = ctx.release();
+  return SLNK_OK;
+}
+
+void slnk3_destroy(slnk3_ctx* ctx) { delete ctx; }
+
+const char* slnk3_last_error(const slnk3_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+unsigned long long slnk3_workspace_bytes(const slnk3_ctx* ctx) {
+  return ctx && ctx->impl ? (unsigned long long)ctx->impl->bytes : 0ull;
+}
+
+slnk_status slnk3_set_images(slnk3_ctx* ctx, const void* m_R, const void* m_T) {
+  if (!m_R || !m_T) return SLNK_EINVAL;
+  return guard3(ctx, [&](slnk::d3::Base& c) { c.set_images(m_R, m_T); });
+}
+
+slnk_status slnk3_transport_state(slnk3_ctx* ctx, const void* v, const void* m0, void* m1) {
+  if (!v || !m0 || !m1) return SLNK_EINVAL;
+  return guard3(ctx, [&](slnk::d3::Base& c) { c.transport_state(v, m0, m1); });
+}
+
+slnk_status slnk3_objective(slnk3_ctx* ctx, const void* v, double* J) {
+  if (!v || !J) return SLNK_EINVAL;
+  return guard3(ctx, [&](slnk::d3::Base& c) { *J = c.objective(v); });
+}
+
+slnk_status slnk3_gradient(slnk3_ctx* ctx, const void* v, void* g, double* J) {
+  if (!v || !g) return SLNK_EINVAL;
+  return guard3(ctx, [&](slnk::d3::Base& c) {
+    const double j = c.gradient(v, g);
+    if (J) *J = j;
+  });
+}
+
+slnk_status slnk3_hessian_matvec(slnk3_ctx* ctx, const void* vt, void* Hvt) {
+  if (!vt || !Hvt) return SLNK_EINVAL;
+  return guard3(ctx, [&](slnk::d3::Base& c) { c.hessian(vt, Hvt); });
+}
+
+slnk_status slnk3_precond_apply(slnk3_ctx* ctx, const void* r, void* z) {
+  if (!r || !z) return SLNK_EINVAL;
+  return guard3(ctx, [&](slnk::d3::Base& c) { c.precond(r, z); });
+}
+
+slnk_status slnk3_newton_solve(slnk3_ctx* ctx, void* v_inout, const slnk_solve_opts* opts,
+                               slnk_solve_report* report) {
+  if (!v_inout) return SLNK_EINVAL;
+  slnk_solve_opts o;
+  slnk_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.max_newton < 0 || o.max_pcg < 1 || o.max_halvings < 0) return SLNK_EINVAL;
+  slnk_solve_report rep;
+  slnk_status result = SLNK_OK;
+  const slnk_status st = guard3(ctx, [&](slnk::d3::Base& c) { result = c.newton(v_inout, o, rep); });
+  if (st != SLNK_OK) return st;
+  if (report) *report = rep;
+  return result;
+}
+
+}  // extern "C"

@@ -11,6 +11,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "slnk.h")
+HEADER3 = os.path.join(ROOT, "include", "slnk3.h")
 
 
 @pytest.fixture(scope="module")
@@ -23,10 +24,10 @@ def pkg():
     return p
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER, prefix="slnk_"):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(slnk_\w+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(" + prefix + r"\w+)\s*\(", text, flags=re.M)))
 
 
 def test_header_declares_the_entry_points():
@@ -42,12 +43,16 @@ def test_library_exports_every_declared_symbol(pkg):
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing
     assert sorted(pkg.EXPORTS) == names  # the binding covers exactly the header
+    names3 = declared_functions(HEADER3, "slnk3_")
+    assert "slnk3_newton_solve" in names3 and "slnk3_hessian_matvec" in names3
+    assert not [n for n in names3 if not hasattr(lib, n)]
+    assert sorted(pkg.EXPORTS3) == names3
 
 
 LAYOUT_PROGRAM = r"""
 #include <stddef.h>
 #include <stdio.h>
-#include "slnk.h"
+#include "slnk3.h"
 #define F(T, m) printf(#T " " #m " %zu %zu\n", offsetof(T, m), sizeof(((T*)0)->m))
 int main(void) {
   printf("slnk_params size %zu 0\n", sizeof(slnk_params));
@@ -71,6 +76,9 @@ int main(void) {
   F(slnk_unet_params, height); F(slnk_unet_params, width); F(slnk_unet_params, levels);
   F(slnk_unet_params, base_channels); F(slnk_unet_params, max_batch); F(slnk_unet_params, seed);
   F(slnk_unet_params, start_kmax);
+  printf("slnk3_params size %zu 0\n", sizeof(slnk3_params));
+  F(slnk3_params, n1); F(slnk3_params, n2); F(slnk3_params, n3); F(slnk3_params, nt); F(slnk3_params, reg);
+  F(slnk3_params, beta); F(slnk3_params, prec); F(slnk3_params, proj);
   return 0;
 }
 """
@@ -83,7 +91,7 @@ def test_ctypes_structs_match_the_header(pkg, tmp_path):
     subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
     structs = {"slnk_params": pkg.Params, "slnk_solve_opts": pkg.SolveOpts, "slnk_solve_report": pkg.SolveReport,
-               "slnk_unet_params": pkg.UNetParams}
+               "slnk_unet_params": pkg.UNetParams, "slnk3_params": pkg.Params3}
     seen = {k: [] for k in structs}
     for line in filter(None, out):
         name, field, off, size = line.split()
@@ -143,3 +151,20 @@ def test_unet_create_rejects_bad_shapes(pkg, change):
     u = ctypes.c_void_p()
     assert lib.slnk_unet_create(ctypes.byref(p), None, ctypes.byref(u)) == 1
     assert not u.value
+
+
+@pytest.mark.parametrize("change", [dict(n1=24), dict(n3=1024), dict(n2=4), dict(nt=0), dict(reg=0), dict(beta=-1.0),
+                                    dict(prec=2), dict(proj=2)])
+def test_create3_rejects_bad_parameters_before_device_work(pkg, change):
+    lib = pkg.load_library()
+    p = pkg.Params3()
+    lib.slnk3_default_params(ctypes.byref(p))
+    assert (p.n1, p.n2, p.n3, p.nt, p.reg) == (64, 64, 64, 4, 2)
+    for k, v in change.items():
+        setattr(p, k, v)
+    ctx = ctypes.c_void_p()
+    assert lib.slnk3_create(ctypes.byref(p), None, ctypes.byref(ctx)) == 1  # SLNK_EINVAL
+    assert not ctx.value
+    assert lib.slnk3_gradient(None, None, None, None) == 1
+    assert lib.slnk3_workspace_bytes(None) == 0
+    assert lib.slnk3_last_error(None) == b"null context"

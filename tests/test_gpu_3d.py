@@ -1,0 +1,192 @@
+"""GPU parity of the three-dimensional path (include/slnk3.h; the method for d = 3, section 1
+"Limitations and Unresolved Issues"), through the C ABI, against the FP64 oracle on the same
+inputs: state transport, objective, reduced gradient (K = I and Leray), Gauss--Newton matvec,
+P_REG and the Newton--Krylov solve, on cubes and on grids with a different size per axis, in FP64
+and mixed precision; at the benchmark size, the properties that hold at any size (exact
+integer-cell shifts, the closed forms at v = 0, which the oracle evaluates spectrally)."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+import synth
+from gpu_common import EPS, check_rel, record, same_inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL3 = {"fp64": {"transport": 1e-11, "objective": 1e-12, "gradient": 1e-10, "matvec": 1e-10, "prec": 1e-12},
+        "mixed": {"transport": 2e-5, "objective": 1e-5, "gradient": 2e-4, "matvec": 2e-4, "prec": 1e-6}}
+
+
+@pytest.fixture(scope="module")
+def slnk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1604_02153_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def _t(a, prec):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dt)
+
+
+def _np(t):
+    return t.double().cpu().numpy()
+
+
+def _level(shape, prec, nt=4, beta=1e-3, reg=2, proj=0, seed=3, amp=0.4):
+    """Oracle level of the 3-D Gaussian recipe (inputs rounded as the GPU receives them)."""
+    g = O.Grid(*shape)
+    rng = np.random.default_rng(seed)
+    mT = synth.gaussian_sum_3d(*shape, rng, count=8, sigma=(0.4, 0.8))
+    vgen = synth.random_velocity_3d(*shape, rng, modes=8, kmax=2, amplitude=amp)
+    vt = synth.random_velocity_3d(*shape, np.random.default_rng(seed + 1000), modes=8, kmax=3, amplitude=0.1)
+    mT, vgen, vt = same_inputs(prec, mT, vgen, vt)
+    mR = same_inputs(prec, O.transport_state(g, vgen, mT, nt))
+    return O.Level(g, mT, mR, O.Params(nt=nt, beta=beta, reg=reg, proj=proj)), vgen, vt
+
+
+def _ctx(slnk, L, prec):
+    p = L.prm
+    return slnk.Context3(*L.grid.shape, p.nt, reg=p.reg, beta=p.beta, prec=prec, proj="leray" if p.proj else "none")
+
+
+def _amax(L):
+    return float(sum((n / 2) ** 2 for n in L.grid.shape) ** L.prm.reg)
+
+
+def _matvec_tol(L, prec, vt, ref):
+    """Relative L2 bound of the matvec: the precision's tolerance plus the rounding floor of
+    beta A vt (the symbol beta |k|^(2 reg) multiplies the transform's rounding, about eps log2 N
+    of ||vt|| on every mode, by up to beta max a(k))."""
+    floor = 64.0 * EPS[prec] * L.prm.beta * _amax(L) * float(np.linalg.norm(vt)) / float(np.linalg.norm(ref))
+    return TOL3[prec]["matvec"] + floor
+
+
+CASES = [((16, 16, 16), 2, 0), ((8, 16, 32), 2, 0), ((16, 8, 16), 3, 1), ((16, 16, 8), 1, 0)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape,reg,proj", CASES)
+def test_gradient_and_matvec_match_oracle(slnk, prec, shape, reg, proj):
+    L, vgen, vt = _level(shape, prec, reg=reg, proj=proj)
+    g = L.grid
+    print(f"case {shape} reg{reg} proj{proj} {prec}", flush=True)
+    v = same_inputs(prec, 0.6 * vgen)
+    ctx = _ctx(slnk, L, prec)
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    # state transport
+    m1 = torch.empty(g.shape, dtype=ctx.dtype, device="cuda")
+    ctx.transport_state(_t(v, prec), _t(L.mT, prec), m1)
+    check_rel(f"3d transport {shape} {prec}", _np(m1), O.transport_state(g, v, L.mT, L.prm.nt),
+              TOL3[prec]["transport"])
+    # objective and gradient
+    lin = O.linearize(L, v)
+    gref = O.gradient(lin)
+    gt = torch.empty((3,) + g.shape, dtype=ctx.dtype, device="cuda")
+    J = ctx.gradient(_t(v, prec), gt)
+    record(f"3d objective {shape} {prec}", abs(J - lin.J) / abs(lin.J), TOL3[prec]["objective"])
+    assert abs(J - lin.J) <= TOL3[prec]["objective"] * abs(lin.J)
+    check_rel(f"3d gradient {shape} reg{reg} proj{proj} {prec}", _np(gt), gref, TOL3[prec]["gradient"])
+    # Gauss--Newton matvec at the same linearisation
+    href = O.hessian_matvec(lin, vt)
+    ht = torch.empty_like(gt)
+    ctx.hessian_matvec(_t(vt, prec), ht)
+    check_rel(f"3d matvec {shape} reg{reg} proj{proj} {prec}", _np(ht), href, _matvec_tol(L, prec, vt, href))
+    # P_REG
+    z = torch.empty_like(gt)
+    ctx.precond_apply(_t(gref, prec), z)
+    check_rel(f"3d P_REG {shape} reg{reg} {prec}", _np(z),
+              O.prec_reg(g, same_inputs(prec, gref), L.prm.beta, reg), TOL3[prec]["prec"])
+    if proj:  # the projected part of the gradient, g - beta A v, is divergence free
+        kb = _np(gt) - L.prm.beta * O.apply_reg(g, v, reg)
+        assert np.abs(O.fft_div(g, kb)).max() < TOL3[prec]["gradient"] * np.abs(kb).max() * max(g.shape)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_newton_solve_matches_oracle(slnk, prec):
+    shape = (16, 16, 16)
+    L, vgen, _ = _level(shape, prec, beta=1e-3)
+    vs, rep = O.newton_solve(L, pc="reg", max_newton=6)
+    ctx = _ctx(slnk, L, prec)
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    v = torch.zeros((3,) + shape, dtype=ctx.dtype, device="cuda")
+    r = ctx.newton_solve(v, max_newton=6)
+    print("oracle", rep["newton_iters"], rep["pcg_iters"], rep["grel"][-1], "gpu", r["newton_iters"],
+          r["pcg_iters"], r["grel"][-1], flush=True)
+    assert r["status"] == "SLNK_OK" and rep["status"] == "ok"
+    assert r["grel"][-1] <= 1e-2
+    if prec == "fp64":
+        assert (r["newton_iters"], r["pcg_iters"]) == (rep["newton_iters"], rep["pcg_iters"])
+        check_rel("3d newton v fp64", _np(v), vs, 1e-9)
+    else:
+        assert abs(r["newton_iters"] - rep["newton_iters"]) <= 1
+        check_rel("3d newton v mixed", _np(v), vs, 1e-3)
+    # the oracle's gradient at the GPU's solution meets the stopping test
+    gi = O.gradient(O.linearize(L, _np(v)))
+    assert np.abs(gi).max() <= 1.02e-2 * rep["g0_inf"]
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_integer_shift_is_exact_at_benchmark_size(slnk, prec):
+    """Constant velocity moving every node by whole cells per step: the spline reproduces the
+    nodal values, so the state at t = 1 is m0 rolled by nt steps (any size; here 128^3)."""
+    n, nt = 128, 4
+    c = (1, -2, 3)
+    h = 2 * np.pi / n
+    v = np.stack([np.full((n, n, n), ci * nt * h) for ci in c])
+    rng = np.random.default_rng(11)
+    m0 = same_inputs(prec, synth.gaussian_sum_3d(n, n, n, rng, count=16))
+    ctx = slnk.Context3(n, n, n, nt, prec=prec)
+    m1 = torch.empty((n, n, n), dtype=ctx.dtype, device="cuda")
+    ctx.transport_state(_t(v, prec), _t(m0, prec), m1)
+    ref = np.roll(m0, shift=tuple(nt * ci for ci in c), axis=(0, 1, 2))
+    check_rel(f"3d integer shift 128^3 {prec}", _np(m1), ref, 1e-12 if prec == "fp64" else 2e-6)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_closed_forms_at_zero_velocity_at_benchmark_size(slnk, prec):
+    """v = 0 at 128^3: g = (m_R - m_T) grad m_T and H vt = beta A vt + (vt . grad m_T) grad m_T,
+    the oracle's spectral gradient and regulariser (no transport) giving the expected values."""
+    n = 128
+    g = O.Grid(n, n, n)
+    rng = np.random.default_rng(12)
+    mT = same_inputs(prec, synth.gaussian_sum_3d(n, n, n, rng, count=32))
+    mR = same_inputs(prec, synth.gaussian_sum_3d(n, n, n, rng, count=32))
+    vt = same_inputs(prec, synth.random_velocity_3d(n, n, n, rng, amplitude=0.1))
+    ctx = slnk.Context3(n, n, n, 4, prec=prec)
+    ctx.set_images(_t(mR, prec), _t(mT, prec))
+    zero = torch.zeros((3, n, n, n), dtype=ctx.dtype, device="cuda")
+    gt = torch.empty_like(zero)
+    ctx.gradient(zero, gt)
+    gm = O.fft_grad(g, mT)
+    check_rel(f"3d gradient v=0 128^3 {prec}", _np(gt), (mR - mT) * gm, TOL3[prec]["gradient"])
+    del gt
+    ht = torch.empty_like(zero)
+    ctx.hessian_matvec(_t(vt, prec), ht)
+    ref = 1e-3 * O.apply_reg(g, vt, 2) + (vt[0] * gm[0] + vt[1] * gm[1] + vt[2] * gm[2]) * gm
+    L = O.Level(g, mT, mR, O.Params(nt=4, beta=1e-3, reg=2))
+    check_rel(f"3d matvec v=0 128^3 {prec}", _np(ht), ref, _matvec_tol(L, prec, vt, ref))
+    ctx.close()
+
+
+def test_bad_calls_are_rejected(slnk):
+    ctx = slnk.Context3(16, 16, 16, 2, prec="fp64")
+    x = torch.zeros((3, 16, 16, 16), dtype=torch.float64, device="cuda")
+    with pytest.raises(slnk.SlnkError):
+        ctx.hessian_matvec(x, torch.empty_like(x))  # no linearisation yet
+    with pytest.raises(slnk.SlnkError):
+        ctx.gradient(x, torch.empty_like(x))  # no images yet
+    nan = torch.full((16, 16, 16), float("nan"), dtype=torch.float64, device="cuda")
+    with pytest.raises(slnk.SlnkError):
+        ctx.set_images(nan, nan)
+    with pytest.raises(ValueError):
+        ctx.precond_apply(x[:2], x[:2])
+    ctx.close()
