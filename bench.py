@@ -71,6 +71,11 @@ def parse():
     ap.add_argument("--probe-coarse", action="store_true",
                     help="coarse-step probe: 200 incremental-adjoint SL steps of the 128^2 problem (the P_2L coarse "
                          "grid of the 256^2 workload) for a kernel trace; no JSON line")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 three-dimensional workload")
+    ap.add_argument("--d3-matvecs", type=int, default=20, help="timed matvecs of the 128^3 workload")
+    ap.add_argument("--probe-3d", action="store_true",
+                    help="3-D probe: gradient and 20 Gauss-Newton matvecs of the 128^3 problem (mixed), for "
+                         "rocprofv3")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: 20 incremental-adjoint SL steps of the 256^2 problem, then a plain "
                          "64 MiB elementwise kernel (the reference of the traffic counters); no JSON line")
@@ -439,6 +444,103 @@ def brain512(args, dev):
     return out
 
 
+def d3_matvec_bytes(n, nt, elem=4):
+    """Algorithmic HBM bytes of one 3-D Gauss-Newton matvec (each field read or written once per
+    use): the incremental state's start (vt, grad m^0 in, q out: 7 fields), per incremental state
+    step the B-spline coefficients (2) and the step (displacement 3, coefficients 1, grad m^j 3,
+    vt 3, out 1), the last step's b~ start (3), per incremental adjoint step coefficients (2) and
+    the step (displacement 3, coefficients 1, gamma 1, grad m 3, b~ 3 in and 3 out, out 1), beta A
+    vt (6) and the final K b~ + beta A vt (9): 25 + 30 nt fields of n^3 values."""
+    return (25 + 30 * nt) * n ** 3 * elem
+
+
+def d3_setup(dev, prec, n=128, sl_path=0):
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1604_02153_amd import Context3
+    mT, vgen, nt, beta, reg = synth.config_3d("gauss3d128", n=n)
+    dt = torch.float32 if prec == "mixed" else torch.float64
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)
+    vt = synth.random_velocity_3d(n, n, n, np.random.default_rng(1234), amplitude=0.1)
+    ctx = Context3(n, n, n, nt, reg=reg, beta=beta, prec=prec, sl_path=sl_path)
+    mT_t, vgen_t = t(mT), t(vgen)
+    mR_t = torch.empty_like(mT_t)
+    ctx.transport_state(vgen_t, mT_t, mR_t)
+    ctx.set_images(mR_t, mT_t)
+    return ctx, mR_t, mT_t, vgen_t, t(vt), nt, beta
+
+
+def d3_probe():
+    import torch
+    dev = torch.device("cuda:0")
+    for sl_path in (0, 1):
+        ctx, mR, mT, vgen, vt, nt, beta = d3_setup(dev, "mixed", sl_path=sl_path)
+        g = torch.empty_like(vgen)
+        ctx.gradient(vgen, g)
+        out = torch.empty_like(vgen)
+        for _ in range(20):
+            ctx.hessian_matvec(vt, out)
+        torch.cuda.synchronize()
+        log(f"3-D probe done: sl_path {sl_path}, 1 gradient, 20 matvecs at 128^3")
+        ctx.close()
+
+
+def d3_workload(args, dev):
+    """The method in three dimensions: the Gaussian-blob recipe on a 128^3 volume (nt = 4, H2,
+    beta = 1e-3), mixed precision and FP64: isolated GN matvecs and a Newton-PCG solve with P_REG."""
+    import torch
+    out = {"workload": "gauss3d128: 128^3, nt=4, H2 beta=1e-3, P_REG, K = I; m_R = m_T transported by v_gen"}
+    for prec in ("mixed", "fp64"):
+        ctx, mR, mT, vgen, vt, nt, beta = d3_setup(dev, prec)
+        g = torch.empty_like(vgen)
+        ctx.gradient(vgen, g)
+        hv = torch.empty_like(vgen)
+        ctx.hessian_matvec(vt, hv)
+        torch.cuda.synchronize()
+        reps = args.d3_matvecs if prec == "mixed" else max(5, args.d3_matvecs // 2)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.hessian_matvec(vt, hv)
+        torch.cuda.synchronize()
+        mv_ms = 1e3 * (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        ctx.gradient(vgen, g)
+        torch.cuda.synchronize()
+        grad_ms = 1e3 * (time.perf_counter() - t0)
+        v = torch.zeros_like(vgen)
+        t0 = time.perf_counter()
+        rep = ctx.newton_solve(v)
+        solve_ms = 1e3 * (time.perf_counter() - t0)
+        elem = 4 if prec == "mixed" else 8
+        gbs = d3_matvec_bytes(128, nt, elem) / (mv_ms * 1e-3) / 1e9
+        if prec == "mixed":  # the other SL path (stencils read from the global coefficients)
+            ctx1, _, _, vgen1, vt1, _, _ = d3_setup(dev, prec, sl_path=1)
+            g1 = torch.empty_like(vgen1)
+            ctx1.gradient(vgen1, g1)
+            ctx1.hessian_matvec(vt1, g1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx1.hessian_matvec(vt1, g1)
+            torch.cuda.synchronize()
+            out["mixed_global_gather_matvec_ms"] = round(1e3 * (time.perf_counter() - t0) / reps, 3)
+            ctx1.close()
+            del g1, vgen1, vt1
+        out[prec] = {"matvec_ms": round(mv_ms, 3), "matvecs_per_s": round(1e3 / mv_ms, 2),
+                     "matvec_GBps_algorithmic": round(gbs, 1), "matvec_frac_of_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                     "gradient_ms": round(grad_ms, 3), "solve_ms": round(solve_ms, 2),
+                     "newton_iters": rep["newton_iters"], "pcg_iters": rep["pcg_iters"],
+                     "grel_final": rep["grel"][-1], "status": rep["status"],
+                     "workspace_GB": round(ctx.workspace_bytes() / 1e9, 3)}
+        ctx.close()
+        del g, hv, v, mR, mT, vgen, vt
+        torch.cuda.empty_cache()
+        log(f"3-D {prec}: matvec {mv_ms:.2f} ms, solve {solve_ms:.1f} ms")
+    return out
+
+
 def unet_flops(h, w, levels=4, base=32):
     """Multiply-add flops (2 per MAC) of one forward pass of the U-Net on an h x w pair."""
     C = [base << l for l in range(levels)]
@@ -716,6 +818,9 @@ def main():
     if args.probe_coarse:
         coarse_probe()
         return
+    if args.probe_3d:
+        d3_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); runs on several GPUs are not "
               "part of this benchmark.", file=sys.stderr)
@@ -830,6 +935,9 @@ def main():
     if not args.no_batched:
         line["batched"] = batched(args, dev)
         log("batched workload done")
+    if not args.no_3d:
+        line["d3"] = d3_workload(args, dev)
+        log("3-D workload done")
     if oracle_timing is not None:
         line["cpu_baseline"] = oracle_timing
     print(json.dumps(line), flush=True)

@@ -10,7 +10,9 @@
  * inexact Newton--PCG solve with P_REG (sections 3.4.1, 3.5).  Transport is the semi-Lagrangian
  * scheme of section 3.3.2 (Heun trace of the characteristics, RK2 along them, periodic cubic
  * spline interpolation -- here the tensor-product cubic B-spline in three dimensions, its
- * coefficients from the exact spectral inverse of the (1, 4, 1)/6 system along each axis).
+ * coefficients from the periodic inverse of the (1, 4, 1)/6 system along each axis, applied as the
+ * exponential filter sqrt(3) sum z^|t| f_{i+t}, z = sqrt(3) - 2, truncated below the working
+ * precision).
  *
  * Conventions
  *   - Grid: periodic [0, 2 pi)^3 with n1 x n2 x n3 nodes, x_i = 2 pi i / n_i; every n_i a power of
@@ -40,13 +42,16 @@ typedef struct slnk3_ctx slnk3_ctx;
 /* nt: SL time steps on [0, 1] (>= 1); reg: SLNK_REG_H1/H2/H3 (A = -Lap, Lap^2, -Lap^3,
  * eq. e:diffopregv); beta > 0; prec: SLNK_PREC_FP64 or SLNK_PREC_MIXED; proj: SLNK_PROJ_NONE
  * (K = identity) or SLNK_PROJ_LERAY (K = the Leray projection, the incompressible case,
- * section 3.1). */
+ * section 3.1); sl_path: 0 = each SL step stages its tiles' stencil footprint in LDS whenever the
+ * displacement bound lets it fit, else reads the stencils from the global coefficient field;
+ * 1 = always the global reads (a tuning choice: both give the same interpolant up to rounding). */
 typedef struct {
   int n1, n2, n3, nt;
   int reg;
   double beta;
   int prec;
   int proj;
+  int sl_path;
 } slnk3_params;
 
 /* 64^3, nt = 4, H2, beta = 1e-3, mixed precision, K = identity. */

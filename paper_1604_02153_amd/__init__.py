@@ -57,7 +57,8 @@ class SolveReport(ctypes.Structure):
 
 class Params3(ctypes.Structure):
     _fields_ = [("n1", ctypes.c_int), ("n2", ctypes.c_int), ("n3", ctypes.c_int), ("nt", ctypes.c_int),
-                ("reg", ctypes.c_int), ("beta", ctypes.c_double), ("prec", ctypes.c_int), ("proj", ctypes.c_int)]
+                ("reg", ctypes.c_int), ("beta", ctypes.c_double), ("prec", ctypes.c_int), ("proj", ctypes.c_int),
+                ("sl_path", ctypes.c_int)]
 
 
 class UNetParams(ctypes.Structure):
@@ -342,7 +343,7 @@ class Context3:
     """One registration problem on a periodic n1 x n2 x n3 volume (include/slnk3.h): scalar fields
     [n1, n2, n3], velocities [3, n1, n2, n3] (float32 for prec="mixed", float64 for "fp64")."""
 
-    def __init__(self, n1, n2, n3, nt, reg="h2", beta=1e-3, prec="mixed", proj="none", stream=None):
+    def __init__(self, n1, n2, n3, nt, reg="h2", beta=1e-3, prec="mixed", proj="none", sl_path=0, stream=None):
         import torch
         lib = load_library()
         p = Params3()
@@ -352,6 +353,7 @@ class Context3:
         p.beta = float(beta)
         p.prec = PREC[prec] if isinstance(prec, str) else int(prec)
         p.proj = PROJ[proj] if isinstance(proj, str) else int(proj)
+        p.sl_path = int(sl_path)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

@@ -8,6 +8,9 @@
 // LDS each line runs an iterative radix-2 Cooley--Tukey transform from bit-reversed order, with
 // twiddles from a table computed in FP64 on the host.
 #include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <mutex>
 
 #include "d3.hpp"
 
@@ -36,6 +39,20 @@ inline int ilog2(int n) {
   int l = 0;
   while ((1 << l) < n) ++l;
   return l;
+}
+
+// Raise a kernel's dynamic LDS limit (once per kernel and size) for launches above the default.
+std::mutex g_lds_mutex;
+template <typename K>
+hipError_t ensure_lds(K kernel, size_t bytes) {
+  static std::atomic<size_t> allowed{64 * 1024};
+  if (bytes <= allowed.load(std::memory_order_acquire)) return hipSuccess;
+  std::lock_guard<std::mutex> lock(g_lds_mutex);
+  if (bytes <= allowed.load(std::memory_order_relaxed)) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  if (e == hipSuccess) allowed.store(bytes, std::memory_order_release);
+  return e;
 }
 
 // In-place transforms of CL lines of length n held in LDS as s[k * CL + line], input in
@@ -154,6 +171,120 @@ hipError_t launch_strided(hipStream_t s, int nf, cplx<T>* S, size_t Fh, int n, i
   return hipGetLastError();
 }
 
+// ---- B-spline prefilter -------------------------------------------------------------------
+// Truncation error of the filter relative to max |f|: 2 sqrt(3) |z|^(K+1) / (1 - |z|), 4.7e-8 for
+// K = 13 (below FP32 rounding) and 1.2e-16 for K = 28 (FP64).
+template <typename T>
+struct Fir;
+template <>
+struct Fir<float> {
+  static constexpr int K = 13;
+  static constexpr int CL = 16;  // lines per strided tile
+  static constexpr int RL = 8;   // rows per contiguous tile
+};
+template <>
+struct Fir<double> {
+  static constexpr int K = 28;
+  static constexpr int CL = 8;
+  static constexpr int RL = 4;
+};
+
+// periodic index of k - K for 0 <= k < n + 2K: one addition or subtraction unless n < K
+template <int K>
+__device__ __forceinline__ int fir_src(int k, int n) {
+  int x = k - K;
+  x = x < 0 ? x + n : (x >= n ? x - n : x);
+  return (x < 0 || x >= n) ? wrap_index(x, n) : x;
+}
+template <typename T>
+struct Taps {
+  T t[Fir<T>::K + 1];  // sqrt(3) z^t, t = 0..K
+};
+
+// Lines are staged with K wrapped values on each side: s[(k + K) * L + line] holds element
+// (k mod n) for -K <= k < n + K, so the filter needs no index arithmetic.  A thread produces R
+// consecutive outputs of one line from a register window of R + 2K staged values.
+template <typename T, int L, int R>
+__device__ __forceinline__ void fir_window(const T* s, int k0, int line, const Taps<T>& tp, T* o) {
+  constexpr int K = Fir<T>::K;
+  T x[R + 2 * K];
+#pragma unroll
+  for (int i = 0; i < R + 2 * K; ++i) x[i] = s[(k0 + i) * L + line];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    T acc = tp.t[0] * x[r + K];
+#pragma unroll
+    for (int t = 1; t <= K; ++t) acc += tp.t[t] * (x[r + K - t] + x[r + K + t]);
+    o[r] = acc;
+  }
+}
+
+constexpr int kFirR = 4;  // outputs per thread (every n here is a multiple of 8)
+
+// filter along a strided axis (lines as in k_fft_strided, real values)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_fir_strided(const T* in, T* out, size_t fstride, int n, int inner,
+                                                          long long stride_k, long long stride_o, Taps<T> tp) {
+  constexpr int CL = Fir<T>::CL, K = Fir<T>::K;
+  extern __shared__ unsigned char smem_raw[];
+  T* s = reinterpret_cast<T*>(smem_raw);
+  const int c0 = blockIdx.x * CL;
+  const size_t off = blockIdx.z * fstride + size_t(blockIdx.y) * stride_o + c0;
+  const int ncl = min(CL, inner - c0);
+  const int P = n + 2 * K;
+  for (int e = threadIdx.x; e < P * CL; e += blockDim.x) {
+    const int c = e % CL, k = e / CL;
+    const int src = fir_src<K>(k, n);
+    s[k * CL + c] = c < ncl ? in[off + src * stride_k + c] : T(0);
+  }
+  __syncthreads();
+  const int segs = n / kFirR;
+  for (int e = threadIdx.x; e < segs * CL; e += blockDim.x) {
+    const int c = e % CL, q = e / CL;
+    T o[kFirR];
+    fir_window<T, CL, kFirR>(s, q * kFirR, c, tp, o);
+    if (c < ncl) {
+#pragma unroll
+      for (int r = 0; r < kFirR; ++r) out[off + (q * kFirR + r) * stride_k + c] = o[r];
+    }
+  }
+}
+
+// filter along the contiguous axis: RL whole rows per block, staged transposed (s[(k + K) * RL + r])
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_fir_rows(const T* in, T* out, size_t fstride, int rows, int n,
+                                                       Taps<T> tp) {
+  constexpr int RL = Fir<T>::RL, K = Fir<T>::K;
+  extern __shared__ unsigned char smem_raw[];
+  T* s = reinterpret_cast<T*>(smem_raw);
+  const int r0 = blockIdx.x * RL;
+  const size_t off = blockIdx.z * fstride;
+  const int P = n + 2 * K;
+  for (int e = threadIdx.x; e < P * RL; e += blockDim.x) {
+    const int r = e / P, k = e - r * P;
+    s[k * RL + r] = r0 + r < rows ? in[off + size_t(r0 + r) * n + fir_src<K>(k, n)] : T(0);
+  }
+  __syncthreads();
+  const int segs = n / kFirR;
+  for (int e = threadIdx.x; e < segs * RL; e += blockDim.x) {
+    const int r = e % RL, q = e / RL;
+    T o[kFirR];
+    fir_window<T, RL, kFirR>(s, q * kFirR, r, tp, o);
+    if (r0 + r < rows) {
+#pragma unroll
+      for (int j = 0; j < kFirR; ++j) out[off + size_t(r0 + r) * n + q * kFirR + j] = o[j];
+    }
+  }
+}
+
+template <typename T>
+Taps<T> make_taps() {
+  Taps<T> tp;
+  const double z = std::sqrt(3.0) - 2.0;
+  for (int t = 0; t <= Fir<T>::K; ++t) tp.t[t] = T(std::sqrt(3.0) * std::pow(z, t));
+  return tp;
+}
+
 // ---- spectral symbols ----------------------------------------------------------------------
 
 struct Wave {
@@ -176,14 +307,8 @@ __device__ __forceinline__ Wave wave_of(size_t idx, const Dims& d) {
   return w;
 }
 
-__device__ __forceinline__ double symbol_value(const Wave& w, const Dims& d, const SymArgs& a) {
+__device__ __forceinline__ double symbol_value(const Wave& w, const SymArgs& a) {
   if (a.kind == Sym::One) return 1.0;
-  if (a.kind == Sym::Spline) {
-    const double b1 = (2.0 + cospi(2.0 * w.k1 / d.n1)) / 3.0;
-    const double b2 = (2.0 + cospi(2.0 * w.k2 / d.n2)) / 3.0;
-    const double b3 = (2.0 + cospi(2.0 * w.k3 / d.n3)) / 3.0;
-    return 1.0 / ((b1 * b2) * b3);
-  }
   const double kk = double(w.k1) * w.k1 + double(w.k2) * w.k2 + double(w.k3) * w.k3;
   double av = 1.0;
   for (int r = 0; r < a.reg; ++r) av *= kk;
@@ -197,7 +322,7 @@ __global__ void __launch_bounds__(kThreads) k_symbol(Dims d, int nf, SymArgs a, 
   const size_t idx = size_t(blockIdx.x) * kThreads + threadIdx.x;
   if (idx >= Fh) return;
   const Wave w = wave_of(idx, d);
-  const T sv = T(symbol_value(w, d, a));
+  const T sv = T(symbol_value(w, a));
   if (nf == 3 && a.proj) {
     cplx<T> b[3] = {S[idx], S[Fh + idx], S[2 * Fh + idx]};
     const T kk = T(double(w.o1) * w.o1 + double(w.o2) * w.o2 + double(w.o3) * w.o3);
@@ -244,10 +369,11 @@ template <typename T>
 __device__ __forceinline__ void bspline_w(T t, T* w) {
   const T t2 = t * t, t3 = t2 * t;
   const T s = T(1) - t;
-  w[0] = s * s * s / T(6);
-  w[1] = (T(3) * t3 - T(6) * t2 + T(4)) / T(6);
-  w[2] = (T(-3) * t3 + T(3) * t2 + T(3) * t + T(1)) / T(6);
-  w[3] = t3 / T(6);
+  const T sixth = T(1.0 / 6.0);
+  w[0] = s * s * s * sixth;
+  w[1] = (T(3) * t3 - T(6) * t2 + T(4)) * sixth;
+  w[2] = (T(-3) * t3 + T(3) * t2 + T(3) * t + T(1)) * sixth;
+  w[3] = t3 * sixth;
 }
 
 // Periodic tricubic spline with coefficients c at (s1, s2, s3) (cells): the 4 x 4 x 4 stencil
@@ -275,8 +401,13 @@ __device__ T interp3(const T* __restrict__ c, const Dims& d, T s1, T s2, T s3) {
       const int q = b2 + b >= d.n2 ? b2 + b - d.n2 : b2 + b;
       const T* row = c + (size_t(r) * d.n2 + q) * d.n3;
       T v[4];
-      if (straight) {
-        __builtin_memcpy(v, row + b3, sizeof(v));
+      if (straight) {  // one 4-wide load (unaligned addresses are legal for global loads on gfx950)
+        typedef T V4 __attribute__((ext_vector_type(4), aligned(sizeof(T))));
+        const V4 q4 = *reinterpret_cast<const V4*>(row + b3);
+        v[0] = q4.x;
+        v[1] = q4.y;
+        v[2] = q4.z;
+        v[3] = q4.w;
       } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k) v[k] = row[p[k]];
@@ -288,16 +419,9 @@ __device__ T interp3(const T* __restrict__ c, const Dims& d, T s1, T s2, T s3) {
   return acc;
 }
 
+// the update of a step at node i from the interpolated value u
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_sl_step(StepArgs<T> a) {
-  const Dims d = a.d;
-  const size_t F = d.F();
-  const size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x;
-  if (i >= F) return;
-  const int i3 = int(i % d.n3);
-  const size_t t = i / d.n3;
-  const int i2 = int(t % d.n2), i1 = int(t / d.n2);
-  const T u = interp3(a.coef, d, T(i1) + a.disp[i], T(i2) + a.disp[F + i], T(i3) + a.disp[2 * F + i]);
+__device__ __forceinline__ void step_update(const StepArgs<T>& a, size_t i, size_t F, T u) {
   switch (a.kind) {
     case Kind::State:
       a.dst[i] = u;
@@ -324,6 +448,119 @@ __global__ void __launch_bounds__(kThreads) k_sl_step(StepArgs<T> a) {
       }
       break;
     }
+  }
+}
+
+// step with the stencil read from the global coefficient field (any displacement)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_sl_step(StepArgs<T> a) {
+  const Dims d = a.d;
+  const size_t F = d.F();
+  const size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= F) return;
+  const int i3 = int(i % d.n3);
+  const size_t t = i / d.n3;
+  const int i2 = int(t % d.n2), i1 = int(t / d.n2);
+  const T u = interp3(a.coef, d, T(i1) + a.disp[i], T(i2) + a.disp[F + i], T(i3) + a.disp[2 * F + i]);
+  step_update(a, i, F, u);
+}
+
+// step with the stencil footprint of an 8 x 8 x 16 tile staged in LDS (four nodes per thread:
+// x1 = o1 + j1 + 4 h1, x2 = o2 + j2 + 4 h2): every departure point lies within D cells of its
+// node, so its 4 x 4 x 4 stencil lies in [origin - D - 1, origin + tile + D + 1] per axis
+// (G_i = tile_i + 2D + 3 values), which the block loads once, row by row along x3, instead of 64
+// scattered loads per node.  D is a template parameter: every footprint size and LDS offset is a
+// compile-time constant.  Indices are 32-bit (every grid here has fewer than 2^31 nodes).
+constexpr int kT1 = 8, kT2 = 8, kT3 = 16;
+constexpr int kRowLanes = 32;    // threads per staged row (G3 <= 32: D <= 6)
+constexpr int kStageBatch = 16;  // rows per thread whose loads are in flight together
+constexpr int kMaxStagedHalo = 6;
+// periodic index for -n <= x < 2n
+__device__ __forceinline__ int wrap1(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kThreads) k_sl_step_lds(StepArgs<T> a) {
+  constexpr int G1 = kT1 + 2 * D + 3, G2 = kT2 + 2 * D + 3, G3 = kT3 + 2 * D + 3;
+  constexpr int NR = G1 * G2;
+  constexpr int kRowsPerPass = kThreads / kRowLanes;
+  constexpr int kPasses = (NR + kRowsPerPass - 1) / kRowsPerPass;
+  static_assert(G3 <= kRowLanes, "one staged row per lane group");
+  static_assert(kT3 * 4 * 4 == kThreads && kT1 == 8 && kT2 == 8, "four nodes per thread");
+  __shared__ T C[G1 * G2 * G3];
+  const Dims d = a.d;
+  const unsigned F = unsigned(d.F());
+  const int o1 = blockIdx.z * kT1, o2 = blockIdx.y * kT2, o3 = blockIdx.x * kT3;
+  const int tid = threadIdx.x;
+  const int j1 = tid / (4 * kT3), j2 = (tid / kT3) % 4, j3 = tid % kT3;
+  unsigned node[4];
+  T dsp[4][3];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {  // per-node displacements first: their latency overlaps the staging
+    node[h] = (unsigned(o1 + j1 + 4 * (h >> 1)) * d.n2 + (o2 + j2 + 4 * (h & 1))) * d.n3 + (o3 + j3);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dsp[h][c] = a.disp[c * F + node[h]];
+  }
+  const int b1 = o1 - D - 1, b2 = o2 - D - 1, b3 = o3 - D - 1;
+  const int lane = tid % kRowLanes;
+  const int col = wrap1(b3 + min(lane, G3 - 1), d.n3);
+  // staging: rows r = tid / 32 + 8 k walked incrementally; each batch of loads is issued before
+  // any of its stores
+  int r = tid / kRowLanes;
+  int l1 = r / G2, l2 = r - l1 * G2;
+#pragma unroll
+  for (int k0 = 0; k0 < kPasses; k0 += kStageBatch) {
+    T v[kStageBatch];
+    int rr = r, q1 = l1, q2 = l2;
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k) {
+      if (k0 + k < kPasses) {
+        const int c1 = min(q1, G1 - 1);  // rows past the footprint load a valid row, stored nowhere
+        v[k] = a.coef[(unsigned(wrap1(b1 + c1, d.n1)) * d.n2 + wrap1(b2 + q2, d.n2)) * d.n3 + col];
+        q2 += kRowsPerPass;
+        while (q2 >= G2) {
+          q2 -= G2;
+          ++q1;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k) {
+      if (k0 + k < kPasses) {
+        if (rr < NR && lane < G3) C[rr * G3 + lane] = v[k];
+        rr += kRowsPerPass;
+      }
+    }
+    r = rr;
+    l1 = q1;
+    l2 = q2;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const T s1 = T(o1 + j1 + 4 * (h >> 1)) + dsp[h][0], s2 = T(o2 + j2 + 4 * (h & 1)) + dsp[h][1];
+    const T s3 = T(o3 + j3) + dsp[h][2];
+    const T f1 = floor(s1), f2 = floor(s2), f3 = floor(s3);
+    T w1[4], w2[4], w3[4];
+    bspline_w(s1 - f1, w1);
+    bspline_w(s2 - f2, w2);
+    bspline_w(s3 - f3, w3);
+    // LDS coordinates of the stencil's first node; the clamp is inactive when |d| <= D
+    const int m1 = min(max(int(f1) - 1 - b1, 0), G1 - 4);
+    const int m2 = min(max(int(f2) - 1 - b2, 0), G2 - 4);
+    const int m3 = min(max(int(f3) - 1 - b3, 0), G3 - 4);
+    const T* base = C + (m1 * G2 + m2) * G3 + m3;
+    T u = T(0);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      T pa = T(0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const T* row = base + (p * G2 + q) * G3;
+        pa += w2[q] * (w3[0] * row[0] + w3[1] * row[1] + w3[2] * row[2] + w3[3] * row[3]);
+      }
+      u += w1[p] * pa;
+    }
+    step_update(a, node[h], F, u);
   }
 }
 
@@ -481,6 +718,32 @@ hipError_t fft_inverse(hipStream_t s, const Dims& d, const Twiddles<T>& tw, int 
 }
 
 template <typename T>
+hipError_t spline_coefficients(hipStream_t s, const Dims& d, int nf, const T* in, T* out) {
+  const Taps<T> tp = make_taps<T>();
+  const size_t F = d.F();
+  constexpr int RL = Fir<T>::RL, CL = Fir<T>::CL;
+  const int rows = d.n1 * d.n2;
+  // along x3 (rows), then x2 (lines (i1, i3), element stride n3), then x1 (stride n2 n3); the
+  // last two in place
+  constexpr int K = Fir<T>::K;
+  hipLaunchKernelGGL(k_fir_rows<T>, dim3((rows + RL - 1) / RL, 1, nf), dim3(kThreads),
+                     size_t(d.n3 + 2 * K) * RL * sizeof(T), s, in, out, F, rows, d.n3, tp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = ensure_lds(k_fir_strided<T>, size_t(std::max(d.n1, d.n2) + 2 * K) * CL * sizeof(T));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fir_strided<T>, dim3((d.n3 + CL - 1) / CL, d.n1, nf), dim3(kThreads),
+                     size_t(d.n2 + 2 * K) * CL * sizeof(T), s, out, out, F, d.n2, d.n3, (long long)d.n3,
+                     (long long)d.n2 * d.n3, tp);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fir_strided<T>, dim3((d.n2 * d.n3 + CL - 1) / CL, 1, nf), dim3(kThreads),
+                     size_t(d.n1 + 2 * K) * CL * sizeof(T), s, out, out, F, d.n1, d.n2 * d.n3, (long long)d.n2 * d.n3, 0LL,
+                     tp);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t spec_symbol(hipStream_t s, const Dims& d, int nf, SymArgs a, cplx<T>* S) {
   hipLaunchKernelGGL(k_symbol<T>, dim3(blocks_for(d.Fh())), dim3(kThreads), 0, s, d, nf, a, S);
   return hipGetLastError();
@@ -498,8 +761,38 @@ hipError_t spec_div(hipStream_t s, const Dims& d, cplx<T>* S) {
   return hipGetLastError();
 }
 
+// the staged kernel for halo D when its footprint fits the default 64 KiB of static LDS, else the
+// global-gather kernel
+template <typename T, int D>
+hipError_t launch_staged(hipStream_t s, const StepArgs<T>& a) {
+  constexpr size_t bytes = size_t(kT1 + 2 * D + 3) * (kT2 + 2 * D + 3) * (kT3 + 2 * D + 3) * sizeof(T);
+  if constexpr (bytes <= 64 * 1024) {
+    hipLaunchKernelGGL((k_sl_step_lds<T, D>), dim3(a.d.n3 / kT3, a.d.n2 / kT2, a.d.n1 / kT1), dim3(kThreads), 0, s,
+                       a);
+  } else {
+    hipLaunchKernelGGL(k_sl_step<T>, dim3(blocks_for(a.d.F())), dim3(kThreads), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t sl_step(hipStream_t s, const StepArgs<T>& a) {
+  // the staged kernel: halo known and small, the grid divisible into tiles, the staged region
+  // within one period on each side (halo + 2 <= n, for wrap1)
+  const int nmin = std::min(a.d.n1, std::min(a.d.n2, a.d.n3));
+  const bool staged = a.halo >= 0 && a.halo <= kMaxStagedHalo && a.halo + 2 <= nmin && a.d.n1 % kT1 == 0 &&
+                      a.d.n2 % kT2 == 0 && a.d.n3 % kT3 == 0;
+  if (staged) {
+    switch (a.halo) {
+      case 0: return launch_staged<T, 0>(s, a);
+      case 1: return launch_staged<T, 1>(s, a);
+      case 2: return launch_staged<T, 2>(s, a);
+      case 3: return launch_staged<T, 3>(s, a);
+      case 4: return launch_staged<T, 4>(s, a);
+      case 5: return launch_staged<T, 5>(s, a);
+      default: return launch_staged<T, 6>(s, a);
+    }
+  }
   hipLaunchKernelGGL(k_sl_step<T>, dim3(blocks_for(a.d.F())), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
@@ -558,6 +851,7 @@ hipError_t reduce(hipStream_t s, size_t n, int mode, const T* a, const T* b, dou
   template hipError_t fft_forward<T>(hipStream_t, const Dims&, const Twiddles<T>&, int, const T*, cplx<T>*);      \
   template hipError_t fft_inverse<T>(hipStream_t, const Dims&, const Twiddles<T>&, int, cplx<T>*, T*);            \
   template hipError_t spec_symbol<T>(hipStream_t, const Dims&, int, SymArgs, cplx<T>*);                          \
+  template hipError_t spline_coefficients<T>(hipStream_t, const Dims&, int, const T*, T*);                       \
   template hipError_t spec_grad<T>(hipStream_t, const Dims&, const cplx<T>*, cplx<T>*);                          \
   template hipError_t spec_div<T>(hipStream_t, const Dims&, cplx<T>*);                                           \
   template hipError_t sl_step<T>(hipStream_t, const StepArgs<T>&);                                               \

@@ -48,7 +48,6 @@ enum class Sym : int {
   One = 0,      // 1
   Reg = 1,      // beta a(k), a = |k|^(2 reg)
   RegInv = 2,   // 1 / (beta a'(k)), a' = a with a(0) replaced by 1 (P_REG^{-1})
-  Spline = 3,   // 1 / (B(k1) B(k2) B(k3)), B(k) = (2 + cos(2 pi k / n)) / 3 (B-spline prefilter)
 };
 struct SymArgs {
   Sym kind = Sym::One;
@@ -65,6 +64,13 @@ hipError_t spec_grad(hipStream_t s, const Dims& d, const cplx<T>* U, cplx<T>* ou
 // S[0] = sum_c i k_c S[c]: the divergence's spectrum (in place into the first spectrum).
 template <typename T>
 hipError_t spec_div(hipStream_t s, const Dims& d, cplx<T>* S);
+
+// B-spline coefficients of nf scalar fields (consecutive, F apart), in place allowed: along
+// each axis the periodic inverse of the (1, 4, 1)/6 system as the filter
+// c_i = sqrt(3) sum_{|t| <= K} z^|t| f_{i+t} (z = sqrt(3) - 2, indices periodic), truncated where
+// |z|^K falls below the working precision (K = 13 in FP32, 28 in FP64): three passes, one per axis.
+template <typename T>
+hipError_t spline_coefficients(hipStream_t s, const Dims& d, int nf, const T* in, T* out);
 
 // One semi-Lagrangian time step (section 3.3.2) at every node x: u = I[coef](x + disp) (the
 // cubic spline with B-spline coefficients coef at the departure point, displacement in cells),
@@ -90,6 +96,7 @@ struct StepArgs {
   T* acc = nullptr;
   double w = 0.0, ht = 0.0;
   int last = 0;
+  int halo = -1;  // whole cells bounding |disp| (the LDS-staged kernel when its footprint fits), or -1
 };
 template <typename T>
 hipError_t sl_step(hipStream_t s, const StepArgs<T>& a);

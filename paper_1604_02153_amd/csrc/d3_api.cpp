@@ -91,6 +91,7 @@ class Ctx final : public Base {
       coefficients(cur, coef_, 1);
       StepArgs<T> a;
       a.d = d_;
+      a.halo = halo_;
       a.kind = Kind::State;
       a.coef = coef_;
       a.disp = df_;
@@ -336,13 +337,9 @@ class Ctx final : public Base {
     return hres_[0];
   }
 
-  // B-spline coefficients of nf fields (nf = 1 or 3): the spectral inverse of the (1, 4, 1)/6
-  // system along each axis (section 3.3.2, "Interpolation")
-  void coefficients(const T* f, T* c, int nf) {
-    D3CHK(fft_forward<T>(s_, d_, tw_, nf, f, S1_));
-    D3CHK(spec_symbol<T>(s_, d_, nf, SymArgs{Sym::Spline, p_.reg, 1.0, 0}, S1_));
-    D3CHK(fft_inverse<T>(s_, d_, tw_, nf, S1_, c));
-  }
+  // B-spline coefficients of nf fields (nf = 1 or 3): the periodic inverse of the (1, 4, 1)/6
+  // system along each axis (section 3.3.2, "Interpolation") by the truncated exponential filter
+  void coefficients(const T* f, T* c, int nf) { D3CHK(spline_coefficients<T>(s_, d_, nf, f, c)); }
 
   // out = symbol(in) for a vector field (with the Leray projection first when a.proj)
   void apply_symbol(const T* in, T* out, SymArgs a) {
@@ -371,6 +368,9 @@ class Ctx final : public Base {
     divergence_of(v_, divv_);
     coefficients(divv_, cdiv_, 1);
     D3CHK(d3::trace<T>(s_, d_, ht_, v_, cv_, divv_, cdiv_, df_, da_, gamma_));
+    // whole cells bounding every departure displacement (selects the LDS-staged step kernel)
+    const double dmax = std::max(reduce(2, 3 * F_, df_, nullptr), reduce(2, 3 * F_, da_, nullptr));
+    halo_ = p_.sl_path == 0 && dmax < 1e6 ? int(std::ceil(dmax)) : -1;
   }
 
   // trace, state m^0..m^nt (eq. e:state-slm), grad m^j, A v and J
@@ -382,6 +382,7 @@ class Ctx final : public Base {
       coefficients(m_ + size_t(j - 1) * F_, coef_, 1);
       StepArgs<T> a;
       a.d = d_;
+      a.halo = halo_;
       a.kind = Kind::State;
       a.coef = coef_;
       a.disp = df_;
@@ -416,6 +417,7 @@ class Ctx final : public Base {
       coefficients(cur, coef_, 1);
       StepArgs<T> a;
       a.d = d_;
+      a.halo = halo_;
       a.kind = kind;
       a.coef = coef_;
       a.disp = da_;
@@ -452,6 +454,7 @@ class Ctx final : public Base {
       coefficients(cur, coef_, 1);
       StepArgs<T> a;
       a.d = d_;
+      a.halo = halo_;
       a.kind = Kind::IncState;
       a.coef = coef_;
       a.disp = df_;
@@ -511,6 +514,7 @@ class Ctx final : public Base {
   Dims d_;
   size_t F_ = 0, Fh_ = 0;
   double ht_ = 0.0, cell_ = 0.0, J_ = 0.0;
+  int halo_ = -1;
   bool images_ = false, lin_ = false;
   char* base_ = nullptr;
   size_t used_ = 0;
@@ -576,7 +580,8 @@ slnk_status slnk3_create(const slnk3_params* p, void* hip_stream, slnk3_ctx** ou
   using slnk::d3::size_ok;
   if (!size_ok(p->n1) || !size_ok(p->n2) || !size_ok(p->n3) || p->nt < 1 || p->nt > 1000 || p->reg < 1 ||
       p->reg > 3 || !(p->beta > 0.0) || !std::isfinite(p->beta) ||
-      (p->prec != SLNK_PREC_FP64 && p->prec != SLNK_PREC_MIXED) || (p->proj != 0 && p->proj != 1))
+      (p->prec != SLNK_PREC_FP64 && p->prec != SLNK_PREC_MIXED) || (p->proj != 0 && p->proj != 1) ||
+      (p->sl_path != 0 && p->sl_path != 1))
     return SLNK_EINVAL;
   auto ctx = std::make_unique<slnk3_ctx>();
   try {

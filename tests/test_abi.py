@@ -78,7 +78,7 @@ int main(void) {
   F(slnk_unet_params, start_kmax);
   printf("slnk3_params size %zu 0\n", sizeof(slnk3_params));
   F(slnk3_params, n1); F(slnk3_params, n2); F(slnk3_params, n3); F(slnk3_params, nt); F(slnk3_params, reg);
-  F(slnk3_params, beta); F(slnk3_params, prec); F(slnk3_params, proj);
+  F(slnk3_params, beta); F(slnk3_params, prec); F(slnk3_params, proj); F(slnk3_params, sl_path);
   return 0;
 }
 """
@@ -154,7 +154,7 @@ def test_unet_create_rejects_bad_shapes(pkg, change):
 
 
 @pytest.mark.parametrize("change", [dict(n1=24), dict(n3=1024), dict(n2=4), dict(nt=0), dict(reg=0), dict(beta=-1.0),
-                                    dict(prec=2), dict(proj=2)])
+                                    dict(prec=2), dict(proj=2), dict(sl_path=2)])
 def test_create3_rejects_bad_parameters_before_device_work(pkg, change):
     lib = pkg.load_library()
     p = pkg.Params3()

@@ -50,9 +50,10 @@ def _level(shape, prec, nt=4, beta=1e-3, reg=2, proj=0, seed=3, amp=0.4):
     return O.Level(g, mT, mR, O.Params(nt=nt, beta=beta, reg=reg, proj=proj)), vgen, vt
 
 
-def _ctx(slnk, L, prec):
+def _ctx(slnk, L, prec, sl_path=0):
     p = L.prm
-    return slnk.Context3(*L.grid.shape, p.nt, reg=p.reg, beta=p.beta, prec=prec, proj="leray" if p.proj else "none")
+    return slnk.Context3(*L.grid.shape, p.nt, reg=p.reg, beta=p.beta, prec=prec, proj="leray" if p.proj else "none",
+                         sl_path=sl_path)
 
 
 def _amax(L):
@@ -67,17 +68,19 @@ def _matvec_tol(L, prec, vt, ref):
     return TOL3[prec]["matvec"] + floor
 
 
-CASES = [((16, 16, 16), 2, 0), ((8, 16, 32), 2, 0), ((16, 8, 16), 3, 1), ((16, 16, 8), 1, 0)]
+# (shape, reg, proj, sl_path): sl_path 0 stages the stencil footprint in LDS, 1 reads it globally
+CASES = [((16, 16, 16), 2, 0, 0), ((16, 16, 16), 2, 0, 1), ((8, 16, 32), 2, 0, 0), ((16, 8, 16), 3, 1, 0),
+         ((16, 16, 8), 1, 0, 1), ((32, 16, 16), 2, 0, 0)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("shape,reg,proj", CASES)
-def test_gradient_and_matvec_match_oracle(slnk, prec, shape, reg, proj):
+@pytest.mark.parametrize("shape,reg,proj,sl_path", CASES)
+def test_gradient_and_matvec_match_oracle(slnk, prec, shape, reg, proj, sl_path):
     L, vgen, vt = _level(shape, prec, reg=reg, proj=proj)
     g = L.grid
-    print(f"case {shape} reg{reg} proj{proj} {prec}", flush=True)
+    print(f"case {shape} reg{reg} proj{proj} sl_path{sl_path} {prec}", flush=True)
     v = same_inputs(prec, 0.6 * vgen)
-    ctx = _ctx(slnk, L, prec)
+    ctx = _ctx(slnk, L, prec, sl_path)
     ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
     # state transport
     m1 = torch.empty(g.shape, dtype=ctx.dtype, device="cuda")
