@@ -454,7 +454,7 @@ def d3_matvec_bytes(n, nt, elem=4):
     return (25 + 30 * nt) * n ** 3 * elem
 
 
-def d3_setup(dev, prec, n=128, sl_path=0):
+def d3_setup(dev, prec, n=128, sl_path=0, pc="reg"):
     import numpy as np
     import torch
 
@@ -464,11 +464,12 @@ def d3_setup(dev, prec, n=128, sl_path=0):
     dt = torch.float32 if prec == "mixed" else torch.float64
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)
     vt = synth.random_velocity_3d(n, n, n, np.random.default_rng(1234), amplitude=0.1)
-    ctx = Context3(n, n, n, nt, reg=reg, beta=beta, prec=prec, sl_path=sl_path)
+    ctx = Context3(n, n, n, nt, reg=reg, beta=beta, prec=prec, sl_path=sl_path, pc=pc)
     mT_t, vgen_t = t(mT), t(vgen)
     mR_t = torch.empty_like(mT_t)
     ctx.transport_state(vgen_t, mT_t, mR_t)
-    ctx.set_images(mR_t, mT_t)
+    if pc == "reg":
+        ctx.set_images(mR_t, mT_t)
     return ctx, mR_t, mT_t, vgen_t, t(vt), nt, beta
 
 
@@ -491,7 +492,8 @@ def d3_workload(args, dev):
     """The method in three dimensions: the Gaussian-blob recipe on a 128^3 volume (nt = 4, H2,
     beta = 1e-3), mixed precision and FP64: isolated GN matvecs and a Newton-PCG solve with P_REG."""
     import torch
-    out = {"workload": "gauss3d128: 128^3, nt=4, H2 beta=1e-3, P_REG, K = I; m_R = m_T transported by v_gen"}
+    out = {"workload": "gauss3d128: 128^3, nt=4, H2 beta=1e-3, K = I; P_REG and P_2L (64^3, CHEB(10)); "
+                       "m_R = m_T transported by v_gen"}
     for prec in ("mixed", "fp64"):
         ctx, mR, mT, vgen, vt, nt, beta = d3_setup(dev, prec)
         g = torch.empty_like(vgen)
@@ -528,12 +530,27 @@ def d3_workload(args, dev):
             out["mixed_global_gather_matvec_ms"] = round(1e3 * (time.perf_counter() - t0) / reps, 3)
             ctx1.close()
             del g1, vgen1, vt1
+        # the same problem with P_2L (coarse grid 64^3, CHEB(10), 30 Lanczos steps at set-up)
+        ctx2, mR2, mT2, vgen2, _, _, _ = d3_setup(dev, prec, pc="2l")
+        v2 = torch.zeros_like(vgen2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx2.set_images(mR2, mT2)
+        rep2 = ctx2.newton_solve(v2)
+        setup_solve2 = 1e3 * (time.perf_counter() - t0)
+        two_level = {"setup_plus_solve_ms": round(setup_solve2, 2), "solve_ms": round(rep2["time_total_ms"], 2),
+                     "newton_iters": rep2["newton_iters"], "pcg_iters": rep2["pcg_iters"],
+                     "coarse_matvecs": rep2["coarse_matvecs"], "grel_final": rep2["grel"][-1],
+                     "status": rep2["status"], "emax": round(rep2["emax"], 3),
+                     "time_precond_ms": round(rep2["time_precond_ms"], 2)}
+        ctx2.close()
+        del mR2, mT2, vgen2, v2
         out[prec] = {"matvec_ms": round(mv_ms, 3), "matvecs_per_s": round(1e3 / mv_ms, 2),
                      "matvec_GBps_algorithmic": round(gbs, 1), "matvec_frac_of_hbm": round(gbs / HBM_PEAK_GBS, 4),
                      "gradient_ms": round(grad_ms, 3), "solve_ms": round(solve_ms, 2),
                      "newton_iters": rep["newton_iters"], "pcg_iters": rep["pcg_iters"],
                      "grel_final": rep["grel"][-1], "status": rep["status"],
-                     "workspace_GB": round(ctx.workspace_bytes() / 1e9, 3)}
+                     "workspace_GB": round(ctx.workspace_bytes() / 1e9, 3), "two_level": two_level}
         ctx.close()
         del g, hv, v, mR, mT, vgen, vt
         torch.cuda.empty_cache()

@@ -44,7 +44,11 @@ typedef struct slnk3_ctx slnk3_ctx;
  * (K = identity) or SLNK_PROJ_LERAY (K = the Leray projection, the incompressible case,
  * section 3.1); sl_path: 0 = each SL step stages its tiles' stencil footprint in LDS whenever the
  * displacement bound lets it fit, else reads the stencils from the global coefficient field;
- * 1 = always the global reads (a tuning choice: both give the same interpolant up to rounding). */
+ * 1 = always the global reads (a tuning choice: both give the same interpolant up to rounding);
+ * pc: SLNK_PC_REG (PCG on H with P_REG) or SLNK_PC_2L (PCG on the split system
+ * (I + S Q S) s = -S g, S = (beta A')^{-1/2}, with the nested two-level preconditioner of section
+ * 3.4.2 on a coarse grid of n_i / 2 points per axis, every n_i / 2 >= 8); cheb_iters, lanczos_steps,
+ * emax_safety, lanczos_seed: CHEB(k) and the Lanczos estimate of e_max at v = 0 as in slnk.h. */
 typedef struct {
   int n1, n2, n3, nt;
   int reg;
@@ -52,9 +56,15 @@ typedef struct {
   int prec;
   int proj;
   int sl_path;
+  int pc;
+  int cheb_iters;
+  int lanczos_steps;
+  double emax_safety;
+  unsigned long long lanczos_seed;
 } slnk3_params;
 
-/* 64^3, nt = 4, H2, beta = 1e-3, mixed precision, K = identity. */
+/* 64^3, nt = 4, H2, beta = 1e-3, mixed precision, K = identity, P_REG (CHEB(10), 30 Lanczos
+ * steps, safety 1.05 for P_2L). */
 void slnk3_default_params(slnk3_params* p);
 
 /* Create a context; *out is set on success.  SLNK_EINVAL for sizes outside the conventions,
@@ -64,7 +74,11 @@ void slnk3_destroy(slnk3_ctx* ctx);
 const char* slnk3_last_error(const slnk3_ctx* ctx);
 unsigned long long slnk3_workspace_bytes(const slnk3_ctx* ctx);
 
-/* Reference and template images (scalar fields); copied into the context. */
+/* Reference and template images (scalar fields); copied into the context.  With P_2L also the
+ * set-up of section 3.4.2: the spectrally restricted images of the coarse problem and e_max, the
+ * largest Ritz value of lanczos_steps Lanczos steps on the coarse split operator at v = 0 from a
+ * SplitMix64 start vector, times emax_safety; e_min = min_k 1 + 1 / (beta a'(k)) over the coarse
+ * modes. */
 slnk_status slnk3_set_images(slnk3_ctx* ctx, const void* m_R, const void* m_T);
 
 /* m1 = m0 transported by the stationary velocity v to t = 1 (the state equation, eq.
@@ -84,13 +98,25 @@ slnk_status slnk3_gradient(slnk3_ctx* ctx, const void* v, void* g, double* J);
 slnk_status slnk3_hessian_matvec(slnk3_ctx* ctx, const void* vt, void* Hvt);
 
 /* z = P_REG^{-1} r: the spectral inverse of beta A with its zero symbol replaced by 1 (eq.
- * e:reg-precond). */
+ * e:reg-precond); with P_2L, z = P_2L^{-1} r = (I - L) r + Pro CHEB(M_c) Res r (section 3.4.2: L
+ * the ideal low-pass onto the coarse modes, Res / Pro spectral restriction and prolongation, M_c
+ * the coarse split operator linearised at the restricted current point), SLNK_EINVAL before the
+ * first slnk3_gradient or slnk3_objective. */
 slnk_status slnk3_precond_apply(slnk3_ctx* ctx, const void* r, void* z);
 
-/* Globalised inexact Gauss--Newton--Krylov solve with P_REG from v_inout (overwritten by the
- * solution); options and report as in slnk.h (report->coarse_matvecs, emin, emax, fallback and
- * cheb_reestimates are 0).  Returns SLNK_OK, or the status of a solve that ended early (also
- * in report->status): SLNK_ELINESEARCH, SLNK_EMAXIT. */
+/* out = (I + S Q S) s, S = (beta A')^{-1/2}, Q the transport part of the GN matvec at the last
+ * linearisation point: the split spectrally preconditioned Hessian of section 3.4.2. */
+slnk_status slnk3_split_matvec(slnk3_ctx* ctx, const void* s, void* out);
+
+/* The Chebyshev bounds of P_2L (the set-up values, or those of the last solve); 0 with P_REG. */
+slnk_status slnk3_get_cheb_bounds(const slnk3_ctx* ctx, double* emin, double* emax);
+
+/* Globalised inexact Gauss--Newton--Krylov solve with P_REG or P_2L (params.pc) from v_inout
+ * (overwritten by the solution); options and report as in slnk.h (fallback is 0).  Each solve
+ * starts from the set-up e_max; a PCG step with r.z <= 0 (CHEB(k) indefinite) re-estimates e_max
+ * by Lanczos at the current coarse linearisation and runs PCG again (section 4.2.1).  Returns
+ * SLNK_OK, or the status of a solve that ended early (also in report->status):
+ * SLNK_ELINESEARCH, SLNK_EMAXIT, SLNK_ECHEB_DIVERGED. */
 slnk_status slnk3_newton_solve(slnk3_ctx* ctx, void* v_inout, const slnk_solve_opts* opts,
                                slnk_solve_report* report);
 

@@ -58,7 +58,8 @@ class SolveReport(ctypes.Structure):
 class Params3(ctypes.Structure):
     _fields_ = [("n1", ctypes.c_int), ("n2", ctypes.c_int), ("n3", ctypes.c_int), ("nt", ctypes.c_int),
                 ("reg", ctypes.c_int), ("beta", ctypes.c_double), ("prec", ctypes.c_int), ("proj", ctypes.c_int),
-                ("sl_path", ctypes.c_int)]
+                ("sl_path", ctypes.c_int), ("pc", ctypes.c_int), ("cheb_iters", ctypes.c_int),
+                ("lanczos_steps", ctypes.c_int), ("emax_safety", ctypes.c_double), ("lanczos_seed", ctypes.c_ulonglong)]
 
 
 class UNetParams(ctypes.Structure):
@@ -79,7 +80,8 @@ EXPORTS = ["slnk_default_params", "slnk_default_opts", "slnk_create", "slnk_dest
 # include/slnk3.h
 EXPORTS3 = ["slnk3_default_params", "slnk3_create", "slnk3_destroy", "slnk3_last_error", "slnk3_workspace_bytes",
             "slnk3_set_images", "slnk3_transport_state", "slnk3_objective", "slnk3_gradient",
-            "slnk3_hessian_matvec", "slnk3_precond_apply", "slnk3_newton_solve"]
+            "slnk3_hessian_matvec", "slnk3_precond_apply", "slnk3_split_matvec", "slnk3_get_cheb_bounds",
+            "slnk3_newton_solve"]
 
 
 def library_path() -> str:
@@ -150,6 +152,8 @@ def load_library():
         "slnk3_gradient": (ctypes.c_int, [V, V, V, P(ctypes.c_double)]),
         "slnk3_hessian_matvec": (ctypes.c_int, [V, V, V]),
         "slnk3_precond_apply": (ctypes.c_int, [V, V, V]),
+        "slnk3_split_matvec": (ctypes.c_int, [V, V, V]),
+        "slnk3_get_cheb_bounds": (ctypes.c_int, [V, P(ctypes.c_double), P(ctypes.c_double)]),
         "slnk3_newton_solve": (ctypes.c_int, [V, V, P(SolveOpts), P(SolveReport)]),
     }
     for name, (res, args) in sig.items():
@@ -343,7 +347,8 @@ class Context3:
     """One registration problem on a periodic n1 x n2 x n3 volume (include/slnk3.h): scalar fields
     [n1, n2, n3], velocities [3, n1, n2, n3] (float32 for prec="mixed", float64 for "fp64")."""
 
-    def __init__(self, n1, n2, n3, nt, reg="h2", beta=1e-3, prec="mixed", proj="none", sl_path=0, stream=None):
+    def __init__(self, n1, n2, n3, nt, reg="h2", beta=1e-3, prec="mixed", proj="none", sl_path=0, pc="reg",
+                 cheb_iters=10, lanczos_steps=30, emax_safety=1.05, lanczos_seed=0x5EED, stream=None):
         import torch
         lib = load_library()
         p = Params3()
@@ -354,6 +359,9 @@ class Context3:
         p.prec = PREC[prec] if isinstance(prec, str) else int(prec)
         p.proj = PROJ[proj] if isinstance(proj, str) else int(proj)
         p.sl_path = int(sl_path)
+        p.pc = PC[pc] if isinstance(pc, str) else int(pc)
+        p.cheb_iters, p.lanczos_steps = int(cheb_iters), int(lanczos_steps)
+        p.emax_safety, p.lanczos_seed = float(emax_safety), int(lanczos_seed)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -413,13 +421,21 @@ class Context3:
     def precond_apply(self, r, z):
         self._check(self._lib.slnk3_precond_apply(self._ctx, self._ptr(r, 3), self._ptr(z, 3)))
 
+    def split_matvec(self, s, out):
+        self._check(self._lib.slnk3_split_matvec(self._ctx, self._ptr(s, 3), self._ptr(out, 3)))
+
+    def cheb_bounds(self):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.slnk3_get_cheb_bounds(self._ctx, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def newton_solve(self, v, opts: SolveOpts | None = None, **kw):
-        """Gauss--Newton--Krylov solve with P_REG in place; the report as a dict."""
+        """Gauss--Newton--Krylov solve (P_REG or P_2L) in place; the report as a dict."""
         if opts is None:
             opts = default_opts(**kw)
         rep = SolveReport()
         st = self._lib.slnk3_newton_solve(self._ctx, self._ptr(v, 3), ctypes.byref(opts), ctypes.byref(rep))
-        if st not in (0, 5, 7):  # failed line search, Newton limit: reported
+        if st not in (0, 5, 7, 8):  # failed line search, Newton limit, indefinite P_2L: reported
             self._check(st)
         return Context._report(rep)
 

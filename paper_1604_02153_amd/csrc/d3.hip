@@ -313,7 +313,8 @@ __device__ __forceinline__ double symbol_value(const Wave& w, const SymArgs& a) 
   double av = 1.0;
   for (int r = 0; r < a.reg; ++r) av *= kk;
   if (a.kind == Sym::Reg) return a.beta * av;
-  return 1.0 / (a.beta * (av == 0.0 ? 1.0 : av));
+  const double ap = a.beta * (av == 0.0 ? 1.0 : av);
+  return a.kind == Sym::RegInv ? 1.0 / ap : 1.0 / sqrt(ap);
 }
 
 template <typename T>
@@ -338,6 +339,45 @@ __global__ void __launch_bounds__(kThreads) k_symbol(Dims d, int nf, SymArgs a, 
     return;
   }
   for (int c = 0; c < nf; ++c) S[c * Fh + idx] = cscale(S[c * Fh + idx], sv);
+}
+
+// coarse half-spectrum index -> fine one; keep: the mode is one the coarse grid keeps
+__device__ __forceinline__ size_t coarse_to_fine(size_t idx, const Dims& f, const Dims& c, bool& keep) {
+  const int nhc = c.nh(), nhf = f.nh();
+  const int i3 = int(idx % nhc);
+  const size_t t = idx / nhc;
+  const int i2 = int(t % c.n2), i1 = int(t / c.n2);
+  const int k1 = signed_wavenumber(i1, c.n1), k2 = signed_wavenumber(i2, c.n2);
+  keep = i1 != c.n1 / 2 && i2 != c.n2 / 2 && i3 < c.n3 / 2;
+  const int f1 = k1 < 0 ? k1 + f.n1 : k1, f2 = k2 < 0 ? k2 + f.n2 : k2;
+  return (size_t(f1) * f.n2 + f2) * nhf + i3;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_restrict(Dims f, Dims c, int nf, const cplx<T>* __restrict__ Sf,
+                                                       cplx<T>* __restrict__ Sc) {
+  const size_t Fhc = c.Fh(), Fhf = f.Fh();
+  const size_t idx = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= Fhc) return;
+  bool keep;
+  const size_t fi = coarse_to_fine(idx, f, c, keep);
+  const T scale = T(double(c.F()) / double(f.F()));
+  for (int k = 0; k < nf; ++k) Sc[k * Fhc + idx] = keep ? cscale(Sf[k * Fhf + fi], scale) : cplx<T>{T(0), T(0)};
+}
+
+// over the coarse half spectrum: every fine mode of the coarse set is written from its coarse
+// mode (the others keep the fine values)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_prolong_combine(Dims f, Dims c, int nf, cplx<T>* __restrict__ Sf,
+                                                              const cplx<T>* __restrict__ Sc) {
+  const size_t Fhc = c.Fh(), Fhf = f.Fh();
+  const size_t idx = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (idx >= Fhc) return;
+  bool keep;
+  const size_t fi = coarse_to_fine(idx, f, c, keep);
+  if (!keep) return;
+  const T scale = T(double(f.F()) / double(c.F()));
+  for (int k = 0; k < nf; ++k) Sf[k * Fhf + fi] = cscale(Sc[k * Fhc + idx], scale);
 }
 
 template <typename T>
@@ -750,6 +790,20 @@ hipError_t spec_symbol(hipStream_t s, const Dims& d, int nf, SymArgs a, cplx<T>*
 }
 
 template <typename T>
+hipError_t spec_restrict(hipStream_t s, const Dims& fine, const Dims& coarse, int nf, const cplx<T>* Sf, cplx<T>* Sc) {
+  hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for(coarse.Fh())), dim3(kThreads), 0, s, fine, coarse, nf, Sf, Sc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t spec_prolong_combine(hipStream_t s, const Dims& fine, const Dims& coarse, int nf, cplx<T>* Sf,
+                                const cplx<T>* Sc) {
+  hipLaunchKernelGGL(k_prolong_combine<T>, dim3(blocks_for(coarse.Fh())), dim3(kThreads), 0, s, fine, coarse, nf, Sf,
+                     Sc);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t spec_grad(hipStream_t s, const Dims& d, const cplx<T>* U, cplx<T>* out) {
   hipLaunchKernelGGL(k_grad<T>, dim3(blocks_for(d.Fh())), dim3(kThreads), 0, s, d, U, out);
   return hipGetLastError();
@@ -853,6 +907,9 @@ hipError_t reduce(hipStream_t s, size_t n, int mode, const T* a, const T* b, dou
   template hipError_t spec_symbol<T>(hipStream_t, const Dims&, int, SymArgs, cplx<T>*);                          \
   template hipError_t spline_coefficients<T>(hipStream_t, const Dims&, int, const T*, T*);                       \
   template hipError_t spec_grad<T>(hipStream_t, const Dims&, const cplx<T>*, cplx<T>*);                          \
+  template hipError_t spec_restrict<T>(hipStream_t, const Dims&, const Dims&, int, const cplx<T>*, cplx<T>*);    \
+  template hipError_t spec_prolong_combine<T>(hipStream_t, const Dims&, const Dims&, int, cplx<T>*,             \
+                                              const cplx<T>*);                                                   \
   template hipError_t spec_div<T>(hipStream_t, const Dims&, cplx<T>*);                                           \
   template hipError_t sl_step<T>(hipStream_t, const StepArgs<T>&);                                               \
   template hipError_t trace<T>(hipStream_t, const Dims&, double, const T*, const T*, const T*, const T*, T*, T*,  \

@@ -48,6 +48,7 @@ enum class Sym : int {
   One = 0,      // 1
   Reg = 1,      // beta a(k), a = |k|^(2 reg)
   RegInv = 2,   // 1 / (beta a'(k)), a' = a with a(0) replaced by 1 (P_REG^{-1})
+  RegInvSqrt = 3,  // (beta a'(k))^{-1/2} (the split preconditioner's half step S)
 };
 struct SymArgs {
   Sym kind = Sym::One;
@@ -71,6 +72,17 @@ hipError_t spec_div(hipStream_t s, const Dims& d, cplx<T>* S);
 // |z|^K falls below the working precision (K = 13 in FP32, 28 in FP64): three passes, one per axis.
 template <typename T>
 hipError_t spline_coefficients(hipStream_t s, const Dims& d, int nf, const T* in, T* out);
+
+// Two-grid transfer on half spectra (section 3.4.2, spectral restriction and prolongation): the
+// coarse grid has half the points per axis and keeps the fine modes |k_i| < n_i / 4 (its own
+// Nyquist modes dropped).  restrict: Sc = those modes of Sf times Fc / F (zero elsewhere);
+// prolong_combine: Sf keeps its modes outside that set (the high-pass part of the fine field) and
+// takes Sc times F / Fc on it.  nf spectra each.
+template <typename T>
+hipError_t spec_restrict(hipStream_t s, const Dims& fine, const Dims& coarse, int nf, const cplx<T>* Sf, cplx<T>* Sc);
+template <typename T>
+hipError_t spec_prolong_combine(hipStream_t s, const Dims& fine, const Dims& coarse, int nf, cplx<T>* Sf,
+                                const cplx<T>* Sc);
 
 // One semi-Lagrangian time step (section 3.3.2) at every node x: u = I[coef](x + disp) (the
 // cubic spline with B-spline coefficients coef at the departure point, displacement in cells),

@@ -39,6 +39,50 @@ bool size_ok(int n) { return n >= 8 && n <= kMaxN && (n & (n - 1)) == 0; }
 // weight of time level j in the composite trapezoid rule on t^0..t^nt (sums to 1)
 double trap_w(int j, int nt) { return (j == 0 || j == nt) ? 0.5 / nt : 1.0 / nt; }
 
+// Largest eigenvalue of the symmetric tridiagonal matrix (diagonal a, off-diagonal b): bisection
+// on the Sturm count of eigenvalues below x.
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  const int n = int(a.size());
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < n; ++i) {  // Gershgorin bounds
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto below = [&](double x) {
+    int c = 0;
+    double q = 1.0;
+    for (int i = 0; i < n; ++i) {
+      q = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / q : 0.0);
+      if (q == 0.0) q = -1e-300;
+      if (q < 0.0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    (below(mid) == n ? hi : lo) = mid;
+  }
+  return hi;
+}
+
+// Uniform values in [-1/2, 1/2) from SplitMix64 (Steele, Lea, Flood 2014): the state advances by
+// 0x9E3779B97F4A7C15; the output is the state after two xor-shift-multiply rounds and a final
+// xor-shift; its top 53 bits are the fraction.
+std::vector<double> splitmix_uniform(unsigned long long seed, size_t count) {
+  std::vector<double> out(count);
+  unsigned long long x = seed;
+  for (size_t i = 0; i < count; ++i) {
+    x += 0x9E3779B97F4A7C15ULL;
+    unsigned long long z = x;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    out[i] = double(z >> 11) / 9007199254740992.0 - 0.5;
+  }
+  return out;
+}
+
 class Base {
  public:
   virtual ~Base() = default;
@@ -48,6 +92,8 @@ class Base {
   virtual double gradient(const void* v, void* g) = 0;
   virtual void hessian(const void* vt, void* out) = 0;
   virtual void precond(const void* r, void* z) = 0;
+  virtual void split_matvec_api(const void* s, void* out) = 0;
+  virtual void cheb_bounds(double* emin, double* emax) const = 0;
   virtual slnk_status newton(void* v, const slnk_solve_opts& o, slnk_solve_report& rep) = 0;
   size_t bytes = 0;
 };
@@ -65,10 +111,19 @@ class Ctx final : public Base {
     cell_ = std::pow(2.0 * 3.14159265358979323846, 3) / double(F_);
     try {
       allocate();
+      if (p.pc == SLNK_PC_2L) {  // the coarse level: half the points per axis, GN, its own workspace
+        slnk3_params pc = p;
+        pc.n1 /= 2;
+        pc.n2 /= 2;
+        pc.n3 /= 2;
+        pc.pc = SLNK_PC_REG;
+        coarse_ = std::make_unique<Ctx<T>>(pc, s);
+      }
     } catch (...) {
       release();
       throw;
     }
+    if (coarse_) bytes += coarse_->bytes;
   }
   ~Ctx() override { release(); }
 
@@ -79,6 +134,7 @@ class Ctx final : public Base {
       if (!std::isfinite(reduce(0, F_, img, img))) throw Err{SLNK_ENAN, "non-finite image value"};
     images_ = true;
     lin_ = false;
+    if (coarse_) setup_two_level();
   }
 
   void transport_state(const void* v, const void* m0, void* m1) override {
@@ -121,8 +177,25 @@ class Ctx final : public Base {
     matvec(static_cast<const T*>(vt), static_cast<T*>(out));
   }
 
+  // P_REG^{-1} r, or P_2L^{-1} r at the coarse linearisation of the current point
   void precond(const void* r, void* z) override {
-    apply_symbol(static_cast<const T*>(r), static_cast<T*>(z), SymArgs{Sym::RegInv, p_.reg, p_.beta, 0});
+    if (!coarse_) {
+      prec_reg(static_cast<const T*>(r), static_cast<T*>(z));
+      return;
+    }
+    if (!lin_) throw Err{SLNK_EINVAL, "P_2L needs a linearisation (slnk3_gradient or slnk3_objective)"};
+    coarse_linearize();
+    apply_two_level(static_cast<const T*>(r), static_cast<T*>(z));
+  }
+
+  void split_matvec_api(const void* sv, void* out) override {
+    if (!lin_) throw Err{SLNK_EINVAL, "the matvec needs a linearisation (slnk3_gradient or slnk3_objective)"};
+    split_matvec(static_cast<const T*>(sv), static_cast<T*>(out));
+  }
+
+  void cheb_bounds(double* emin, double* emax) const override {
+    *emin = emin_;
+    *emax = emax_;
   }
 
   slnk_status newton(void* vio, const slnk_solve_opts& o, slnk_solve_report& rep) override {
@@ -132,6 +205,11 @@ class Ctx final : public Base {
     const size_t V = 3 * F_;
     T* vin = static_cast<T*>(vio);
     D3CHK(hipMemcpyAsync(vk_, vin, V * sizeof(T), hipMemcpyDeviceToDevice, s_));
+    if (coarse_) {  // every solve starts from the set-up bound
+      emax_ = emax_setup_;
+      rep.emin = emin_;
+      rep.emax = emax_;
+    }
     double g0_inf, g0_two;
     const bool cold = reduce(2, V, vk_, nullptr) == 0.0;
     if (!cold) {  // norms of the gradient at v = 0 for the relative stopping test
@@ -169,7 +247,41 @@ class Ctx final : public Base {
       }
       const double eta = std::min(0.5, gtwo / g0_two);
       const double tp = now_ms();
-      const int its = pcg(eta, o.max_pcg, rep);
+      int its = 0;
+      if (!coarse_) {
+        D3CHK(axpby<T>(s_, V, -1.0, gk_, 0.0, nullptr, b_));
+        int st = 0;
+        its = pcg(
+            b_, eta, o.max_pcg, [&](const T* x, T* y) { matvec(x, y); },
+            [&](const T* r, T* z) { prec_reg(r, z); }, rep, st);
+      } else {
+        // the split system (I + S Q S) s = -S g with P_2L, vt = S s; the coarse problem is
+        // linearised at the restricted iterate once per Newton step
+        coarse_linearize();
+        apply_symbol(gk_, b_, SymArgs{Sym::RegInvSqrt, p_.reg, p_.beta, 0});
+        D3CHK(axpby<T>(s_, V, -1.0, b_, 0.0, nullptr, b_));
+        auto op = [&](const T* x, T* y) { split_matvec(x, y); };
+        auto pr = [&](const T* r, T* z) {
+          const double t = now_ms();
+          apply_two_level(r, z);
+          rep.coarse_matvecs += std::max(p_.cheb_iters - 1, 0);
+          rep.time_precond_ms += now_ms() - t;
+        };
+        int st = 0;
+        its = pcg(b_, eta, o.max_pcg, op, pr, rep, st);
+        if (st == kIndefinite) {  // section 4.2.1: re-estimate the eigenvalues and run again
+          reestimate_emax();
+          ++rep.cheb_reestimates;
+          int its2 = pcg(b_, eta, o.max_pcg, op, pr, rep, st);
+          its += its2;
+        }
+        if (st == kIndefinite) {
+          rep.pcg_iters += its;
+          status = SLNK_ECHEB_DIVERGED;
+          break;
+        }
+        apply_symbol(x_, x_, SymArgs{Sym::RegInvSqrt, p_.reg, p_.beta, 0});
+      }
       rep.time_pcg_ms += now_ms() - tp;
       rep.pcg_iters += its;
       if (k < SLNK_REPORT_MAX_ITERS) rep.pcg[k] = its;
@@ -202,6 +314,7 @@ class Ctx final : public Base {
     D3CHK(hipMemcpyAsync(vin, vk_, V * sizeof(T), hipMemcpyDeviceToDevice, s_));
     D3CHK(hipStreamSynchronize(s_));
     rep.status = status;
+    if (coarse_) rep.emax = emax_;
     rep.time_total_ms = now_ms() - t0;
     rep.time_to_stop_ms = rep.time_total_ms;
     return status;
@@ -259,6 +372,9 @@ class Ctx final : public Base {
     z_ = take<T>(V);
     pp_ = take<T>(V);
     q_ = take<T>(V);
+    b_ = take<T>(V);
+    st_ = take<T>(V);
+    Sr_ = take<cplx<T>>(3 * Fh_);
     S1_ = take<cplx<T>>(3 * Fh_);
     S2_ = take<cplx<T>>(3 * Fh_);
     if constexpr (std::is_same_v<T, float>) {  // FP64 beta A of the mixed context
@@ -396,6 +512,7 @@ class Ctx final : public Base {
     J_ = 0.5 * cell_ * mis + 0.5 * p_.beta * cell_ * reg;
     if (!std::isfinite(J_)) throw Err{SLNK_ENAN, "non-finite objective"};
     lin_ = true;
+    coarse_lin_ = false;
   }
 
   // g = beta A v + K b, b = int lambda grad m dt (adjoint eq. e:adj-slm backward from lambda(1) = m_R - m(1))
@@ -438,13 +555,13 @@ class Ctx final : public Base {
       apply_symbol(acc_, t3b_, SymArgs{Sym::One, p_.reg, 1.0, 1});
       kb = t3b_;
     }
-    D3CHK(axpby<T>(s_, 3 * F_, c, add, 1.0, kb, out));
+    D3CHK(axpby<T>(s_, 3 * F_, c, add, 1.0, kb, out));  // add may be null (c = 0)
   }
 
   // Gauss--Newton matvec: incremental state (eq. e:inc-state-slm) forward from m~(0) = 0, the
   // incremental adjoint (eq. e:inc-adj-slm, lambda terms dropped) backward from -m~(1), then
-  // beta A vt + K int lambda~ grad m dt
-  void matvec(const T* vt, T* out) {
+  // beta A vt + K int lambda~ grad m dt (with_reg false: the transport part Q alone)
+  void matvec(const T* vt, T* out, bool with_reg = true) {
     const size_t V = 3 * F_;
     const int nt = p_.nt;
     D3CHK(incstate_start<T>(s_, d_, ht_, vt, gm_, lam0_));
@@ -469,25 +586,143 @@ class Ctx final : public Base {
       std::swap(cur, nxt);
     }
     backward_sweep(cur, Kind::IncAdjoint);
-    reg_apply(vt, t3a_, p_.beta);
-    project_and_add(1.0, t3a_, out);
+    if (with_reg) {
+      reg_apply(vt, t3a_, p_.beta);
+      project_and_add(1.0, t3a_, out);
+    } else {
+      project_and_add(0.0, nullptr, out);
+    }
   }
 
-  // PCG on H x = -g_k with P_REG from x = 0 to ||r|| <= tol ||b|| (the oracle's pcg); returns
-  // the iterations; the step is left in x_
-  int pcg(double tol, int maxit, slnk_solve_report& rep) {
+  void prec_reg(const T* r, T* z) { apply_symbol(r, z, SymArgs{Sym::RegInv, p_.reg, p_.beta, 0}); }
+
+  // M s = s + S Q S s, S = (beta A')^{-1/2}: the split spectrally preconditioned Hessian
+  // (section 3.4.2) at this level's linearisation
+  void split_matvec(const T* sv, T* out) {
+    const SymArgs S{Sym::RegInvSqrt, p_.reg, p_.beta, 0};
+    apply_symbol(sv, st_, S);
+    matvec(st_, out, false);
+    apply_symbol(out, out, S);
+    D3CHK(axpby<T>(s_, 3 * F_, 1.0, out, 1.0, sv, out));
+  }
+
+  // ---- two-level preconditioner (section 3.4.2, "Nested Preconditioner") ---------------------
+  // spectral restriction of nf fine fields into the coarse level's fields
+  void restrict_to_coarse(const T* f, T* c, int nf) {
+    D3CHK(fft_forward<T>(s_, d_, tw_, nf, f, S1_));
+    D3CHK(spec_restrict<T>(s_, d_, coarse_->d_, nf, S1_, coarse_->S1_));
+    D3CHK(fft_inverse<T>(s_, coarse_->d_, coarse_->tw_, nf, coarse_->S1_, c));
+  }
+
+  // the coarse problem linearised at the restricted current point (once per point)
+  void coarse_linearize() {
+    if (coarse_lin_) return;
+    restrict_to_coarse(v_, coarse_->trial_, 3);
+    coarse_->linearize(coarse_->trial_);
+    coarse_lin_ = true;
+  }
+
+  // coarse images, Lanczos e_max at v = 0, analytic e_min
+  void setup_two_level() {
+    restrict_to_coarse(mR_, coarse_->mR_, 1);
+    restrict_to_coarse(mT_, coarse_->mT_, 1);
+    coarse_->images_ = true;
+    D3CHK(hipMemsetAsync(coarse_->trial_, 0, 3 * coarse_->F_ * sizeof(T), s_));
+    coarse_->linearize(coarse_->trial_);
+    emax_setup_ = p_.emax_safety * coarse_->lanczos_max(p_.lanczos_steps, p_.lanczos_seed);
+    emax_ = emax_setup_;
+    // e_min = min_k 1 + 1 / (beta a'(k)) over the coarse modes: the largest |k|^2 is at the corner
+    const Dims& c = coarse_->d_;
+    const double kk = 0.25 * (double(c.n1) * c.n1 + double(c.n2) * c.n2 + double(c.n3) * c.n3);
+    emin_ = 1.0 + 1.0 / (p_.beta * std::pow(kk, p_.reg));
+    coarse_lin_ = false;
+  }
+
+  // a new e_max when CHEB(k) turned out indefinite: Lanczos at the current coarse linearisation
+  void reestimate_emax() { emax_ = p_.emax_safety * coarse_->lanczos_max(p_.lanczos_steps, p_.lanczos_seed); }
+
+  // largest Ritz value of 'steps' Lanczos steps on this level's split operator from the
+  // SplitMix64 start vector (no re-orthogonalisation; stops at breakdown)
+  double lanczos_max(int steps, unsigned long long seed) {
     const size_t V = 3 * F_;
-    D3CHK(axpby<T>(s_, V, -1.0, gk_, 0.0, nullptr, r_));
+    const std::vector<double> h = splitmix_uniform(seed, V);
+    std::vector<T> ht(h.begin(), h.end());
+    T* q = x_;
+    T* qp = r_;
+    T* w = q_;
+    D3CHK(hipMemcpyAsync(q, ht.data(), V * sizeof(T), hipMemcpyHostToDevice, s_));
+    const double nq = std::sqrt(reduce(0, V, q, q));  // synchronises before ht is released
+    D3CHK(axpby<T>(s_, V, 1.0 / nq, q, 0.0, nullptr, q));
+    D3CHK(hipMemsetAsync(qp, 0, V * sizeof(T), s_));
+    std::vector<double> al, be;
+    double beta = 0.0;
+    for (int j = 0; j < steps; ++j) {
+      split_matvec(q, w);
+      D3CHK(axpby<T>(s_, V, 1.0, w, -beta, qp, w));
+      const double alpha = reduce(0, V, q, w);
+      D3CHK(axpby<T>(s_, V, 1.0, w, -alpha, q, w));
+      al.push_back(alpha);
+      beta = std::sqrt(reduce(0, V, w, w));
+      if (j == steps - 1 || beta <= 1e-14 * std::fabs(alpha)) break;
+      be.push_back(beta);
+      std::swap(qp, q);
+      D3CHK(axpby<T>(s_, V, 1.0 / beta, w, 0.0, nullptr, q));
+    }
+    return tridiag_max_eig(al, be);
+  }
+
+  // k steps of the Chebyshev iteration for M x = b from x = 0 on this level (bounds [emin, emax]);
+  // the k-th update needs no new residual (k - 1 operator applications); result in x_
+  void chebyshev(const T* b, double emin, double emax, int k) {
+    const size_t V = 3 * F_;
+    const double theta = 0.5 * (emax + emin), delta = 0.5 * (emax - emin);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    D3CHK(hipMemsetAsync(x_, 0, V * sizeof(T), s_));
+    D3CHK(hipMemcpyAsync(r_, b, V * sizeof(T), hipMemcpyDeviceToDevice, s_));
+    D3CHK(axpby<T>(s_, V, 1.0 / theta, r_, 0.0, nullptr, pp_));
+    for (int i = 0; i < k; ++i) {
+      D3CHK(axpby<T>(s_, V, 1.0, x_, 1.0, pp_, x_));
+      if (i == k - 1) break;
+      split_matvec(pp_, q_);
+      D3CHK(axpby<T>(s_, V, 1.0, r_, -1.0, q_, r_));
+      const double rho_next = 1.0 / (2.0 * sigma - rho);
+      D3CHK(axpby<T>(s_, V, rho_next * rho, pp_, 2.0 * rho_next / delta, r_, pp_));
+      rho = rho_next;
+    }
+  }
+
+  // P_2L^{-1} r = (I - L) r + Pro CHEB(M_c) Res r, the low/high split and both transfers spectral
+  void apply_two_level(const T* r, T* z) {
+    Ctx<T>& c = *coarse_;
+    D3CHK(fft_forward<T>(s_, d_, tw_, 3, r, Sr_));
+    D3CHK(spec_restrict<T>(s_, d_, c.d_, 3, Sr_, c.S1_));
+    D3CHK(fft_inverse<T>(s_, c.d_, c.tw_, 3, c.S1_, c.b_));
+    c.chebyshev(c.b_, emin_, emax_, p_.cheb_iters);
+    D3CHK(fft_forward<T>(s_, c.d_, c.tw_, 3, c.x_, c.S1_));
+    D3CHK(spec_prolong_combine<T>(s_, d_, c.d_, 3, Sr_, c.S1_));
+    D3CHK(fft_inverse<T>(s_, d_, tw_, 3, Sr_, z));
+  }
+
+  static constexpr int kIndefinite = 1;
+
+  // PCG from x = 0 to ||r|| <= tol ||b|| (Euclidean products, the oracle's pcg): stops on
+  // non-positive curvature (x = the preconditioned residual at the first step), or with status
+  // kIndefinite when the r.z that gave a step was not positive.  Returns the iterations; the
+  // step is left in x_.
+  template <class Op, class Prec>
+  int pcg(const T* b, double tol, int maxit, Op&& op, Prec&& prec, slnk_solve_report& rep, int& status) {
+    const size_t V = 3 * F_;
+    status = 0;
+    D3CHK(hipMemcpyAsync(r_, b, V * sizeof(T), hipMemcpyDeviceToDevice, s_));
     D3CHK(hipMemsetAsync(x_, 0, V * sizeof(T), s_));
     const double bnorm = std::sqrt(reduce(0, V, r_, r_));
     if (bnorm == 0.0) return 0;
-    double tp = now_ms();
-    precond(r_, z_);
+    prec(r_, z_);
     D3CHK(hipMemcpyAsync(pp_, z_, V * sizeof(T), hipMemcpyDeviceToDevice, s_));
     double rz = reduce(0, V, r_, z_);
-    rep.time_precond_ms += now_ms() - tp;
     for (int it = 1; it <= maxit; ++it) {
-      matvec(pp_, q_);
+      op(pp_, q_);
       ++rep.matvecs;
       const double pq = reduce(0, V, pp_, q_);
       if (!(pq > 0.0)) {
@@ -498,11 +733,12 @@ class Ctx final : public Base {
       D3CHK(axpby<T>(s_, V, 1.0, x_, alpha, pp_, x_));
       D3CHK(axpby<T>(s_, V, 1.0, r_, -alpha, q_, r_));
       if (std::sqrt(reduce(0, V, r_, r_)) <= tol * bnorm) return it;
-      if (!(rz > 0.0)) return it;
-      tp = now_ms();
-      precond(r_, z_);
+      if (!(rz > 0.0)) {
+        status = kIndefinite;
+        return it;
+      }
+      prec(r_, z_);
       const double rz_next = reduce(0, V, r_, z_);
-      rep.time_precond_ms += now_ms() - tp;
       D3CHK(axpby<T>(s_, V, 1.0, z_, rz_next / rz, pp_, pp_));
       rz = rz_next;
     }
@@ -515,6 +751,9 @@ class Ctx final : public Base {
   size_t F_ = 0, Fh_ = 0;
   double ht_ = 0.0, cell_ = 0.0, J_ = 0.0;
   int halo_ = -1;
+  std::unique_ptr<Ctx<T>> coarse_;  // P_2L's coarse level (pc = SLNK_PC_2L)
+  bool coarse_lin_ = false;          // the coarse level is linearised at the restricted current point
+  double emin_ = 0.0, emax_ = 0.0, emax_setup_ = 0.0;
   bool images_ = false, lin_ = false;
   char* base_ = nullptr;
   size_t used_ = 0;
@@ -525,7 +764,8 @@ class Ctx final : public Base {
   T *df_ = nullptr, *da_ = nullptr, *gamma_ = nullptr, *Av_ = nullptr, *m_ = nullptr, *gm_ = nullptr;
   T *lam0_ = nullptr, *lam1_ = nullptr, *coef_ = nullptr, *acc_ = nullptr, *t3a_ = nullptr, *t3b_ = nullptr;
   T *vk_ = nullptr, *gk_ = nullptr, *trial_ = nullptr, *x_ = nullptr, *r_ = nullptr, *z_ = nullptr, *pp_ = nullptr,
-    *q_ = nullptr;
+    *q_ = nullptr, *b_ = nullptr, *st_ = nullptr;
+  cplx<T>* Sr_ = nullptr;
   cplx<T>*S1_ = nullptr, *S2_ = nullptr;
   Twiddles<double> twd_;
   cplx<double>*twd1_ = nullptr, *twd2_ = nullptr, *twd3_ = nullptr, *Sd_ = nullptr;
@@ -572,6 +812,12 @@ void slnk3_default_params(slnk3_params* p) {
   p->beta = 1e-3;
   p->prec = SLNK_PREC_MIXED;
   p->proj = SLNK_PROJ_NONE;
+  p->sl_path = 0;
+  p->pc = SLNK_PC_REG;
+  p->cheb_iters = 10;
+  p->lanczos_steps = 30;
+  p->emax_safety = 1.05;
+  p->lanczos_seed = 0x5EED;
 }
 
 slnk_status slnk3_create(const slnk3_params* p, void* hip_stream, slnk3_ctx** out) {
@@ -581,7 +827,10 @@ slnk_status slnk3_create(const slnk3_params* p, void* hip_stream, slnk3_ctx** ou
   if (!size_ok(p->n1) || !size_ok(p->n2) || !size_ok(p->n3) || p->nt < 1 || p->nt > 1000 || p->reg < 1 ||
       p->reg > 3 || !(p->beta > 0.0) || !std::isfinite(p->beta) ||
       (p->prec != SLNK_PREC_FP64 && p->prec != SLNK_PREC_MIXED) || (p->proj != 0 && p->proj != 1) ||
-      (p->sl_path != 0 && p->sl_path != 1))
+      (p->sl_path != 0 && p->sl_path != 1) || (p->pc != SLNK_PC_REG && p->pc != SLNK_PC_2L))
+    return SLNK_EINVAL;
+  if (p->pc == SLNK_PC_2L && (!size_ok(p->n1 / 2) || !size_ok(p->n2 / 2) || !size_ok(p->n3 / 2) ||
+                              p->cheb_iters < 1 || p->lanczos_steps < 1 || !(p->emax_safety >= 1.0)))
     return SLNK_EINVAL;
   auto ctx = std::make_unique<slnk3_ctx>();
   try {
@@ -633,6 +882,17 @@ slnk_status slnk3_gradient(slnk3_ctx* ctx, const void* v, void* g, double* J) {
 slnk_status slnk3_hessian_matvec(slnk3_ctx* ctx, const void* vt, void* Hvt) {
   if (!vt || !Hvt) return SLNK_EINVAL;
   return guard3(ctx, [&](slnk::d3::Base& c) { c.hessian(vt, Hvt); });
+}
+
+slnk_status slnk3_split_matvec(slnk3_ctx* ctx, const void* s, void* out) {
+  if (!s || !out) return SLNK_EINVAL;
+  return guard3(ctx, [&](slnk::d3::Base& c) { c.split_matvec_api(s, out); });
+}
+
+slnk_status slnk3_get_cheb_bounds(const slnk3_ctx* ctx, double* emin, double* emax) {
+  if (!ctx || !ctx->impl || !emin || !emax) return SLNK_EINVAL;
+  ctx->impl->cheb_bounds(emin, emax);
+  return SLNK_OK;
 }
 
 slnk_status slnk3_precond_apply(slnk3_ctx* ctx, const void* r, void* z) {

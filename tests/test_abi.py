@@ -79,6 +79,8 @@ int main(void) {
   printf("slnk3_params size %zu 0\n", sizeof(slnk3_params));
   F(slnk3_params, n1); F(slnk3_params, n2); F(slnk3_params, n3); F(slnk3_params, nt); F(slnk3_params, reg);
   F(slnk3_params, beta); F(slnk3_params, prec); F(slnk3_params, proj); F(slnk3_params, sl_path);
+  F(slnk3_params, pc); F(slnk3_params, cheb_iters); F(slnk3_params, lanczos_steps); F(slnk3_params, emax_safety);
+  F(slnk3_params, lanczos_seed);
   return 0;
 }
 """
@@ -154,7 +156,8 @@ def test_unet_create_rejects_bad_shapes(pkg, change):
 
 
 @pytest.mark.parametrize("change", [dict(n1=24), dict(n3=1024), dict(n2=4), dict(nt=0), dict(reg=0), dict(beta=-1.0),
-                                    dict(prec=2), dict(proj=2), dict(sl_path=2)])
+                                    dict(prec=2), dict(proj=2), dict(sl_path=2), dict(pc=3),
+                                    dict(pc=2, n1=8), dict(pc=2, cheb_iters=0), dict(pc=2, emax_safety=0.5)])
 def test_create3_rejects_bad_parameters_before_device_work(pkg, change):
     lib = pkg.load_library()
     p = pkg.Params3()

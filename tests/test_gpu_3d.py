@@ -61,10 +61,10 @@ def _amax(L):
 
 
 def _matvec_tol(L, prec, vt, ref):
-    """Relative L2 bound of the matvec: the precision's tolerance plus the rounding floor of
-    beta A vt (the symbol beta |k|^(2 reg) multiplies the transform's rounding, about eps log2 N
-    of ||vt|| on every mode, by up to beta max a(k))."""
-    floor = 64.0 * EPS[prec] * L.prm.beta * _amax(L) * float(np.linalg.norm(vt)) / float(np.linalg.norm(ref))
+    """Relative L2 bound of the matvec: the precision's tolerance plus the FP64 rounding floor of
+    beta A vt (both contexts form it in FP64; the symbol beta |k|^(2 reg) multiplies the
+    transform's rounding, about eps log2 N of ||vt|| on every mode, by up to beta max a(k))."""
+    floor = 64.0 * EPS["fp64"] * L.prm.beta * _amax(L) * float(np.linalg.norm(vt)) / float(np.linalg.norm(ref))
     return TOL3[prec]["matvec"] + floor
 
 
@@ -192,4 +192,66 @@ def test_bad_calls_are_rejected(slnk):
         ctx.set_images(nan, nan)
     with pytest.raises(ValueError):
         ctx.precond_apply(x[:2], x[:2])
+    ctx.close()
+
+
+def _restrict_vec(L, v):
+    cg = L.grid.coarse()
+    return np.stack([O.restrict(L.grid, cg, v[c]) for c in range(3)])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape,reg,proj", [((16, 16, 16), 2, 0), ((16, 32, 16), 3, 1)])
+def test_two_level_operators_match_oracle(slnk, prec, shape, reg, proj):
+    """P_2L in 3-D (section 3.4.2): the Chebyshev bounds of the set-up, the split operator
+    I + S Q S and the preconditioner at the restricted current point, against the oracle."""
+    L, vgen, vt = _level(shape, prec, reg=reg, proj=proj)
+    g = L.grid
+    print(f"2l case {shape} reg{reg} proj{proj} {prec}", flush=True)
+    v = same_inputs(prec, 0.6 * vgen)
+    tl = O.setup_two_level(L)
+    ctx = slnk.Context3(*shape, L.prm.nt, reg=reg, beta=L.prm.beta, prec=prec, proj="leray" if proj else "none",
+                        pc="2l")
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    emin, emax = ctx.cheb_bounds()
+    record(f"3d emax {shape} {prec}", abs(emax - tl.emax) / tl.emax, 1e-9 if prec == "fp64" else 1e-4)
+    assert abs(emin - tl.emin) <= 1e-12 * tl.emin
+    assert abs(emax - tl.emax) <= (1e-9 if prec == "fp64" else 1e-4) * tl.emax
+    gt = torch.empty((3,) + shape, dtype=ctx.dtype, device="cuda")
+    ctx.gradient(_t(v, prec), gt)
+    lin = O.linearize(L, v)
+    out = torch.empty_like(gt)
+    ctx.split_matvec(_t(vt, prec), out)
+    tol = 1e-10 if prec == "fp64" else 2e-4
+    check_rel(f"3d split matvec {shape} {prec}", _np(out), O.split_matvec(lin, vt), tol)
+    tl.lin_c = O.linearize(tl.coarse, _restrict_vec(L, v))
+    r = same_inputs(prec, O.gradient(lin))
+    z = torch.empty_like(gt)
+    ctx.precond_apply(_t(r, prec), z)
+    check_rel(f"3d P_2L {shape} {prec}", _np(z), O.apply_two_level(L, tl, r), tol)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_two_level_newton_solve_matches_oracle(slnk, prec):
+    shape = (16, 16, 16)
+    L, vgen, _ = _level(shape, prec, beta=1e-3)
+    vs, rep = O.newton_solve(L, pc="2l", max_newton=6)
+    ctx = slnk.Context3(*shape, L.prm.nt, beta=1e-3, prec=prec, pc="2l")
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    v = torch.zeros((3,) + shape, dtype=ctx.dtype, device="cuda")
+    r = ctx.newton_solve(v, max_newton=6)
+    print("oracle 2l", rep["newton_iters"], rep["pcg_iters"], rep["grel"][-1], "gpu", r["newton_iters"],
+          r["pcg_iters"], r["grel"][-1], r["coarse_matvecs"], flush=True)
+    assert r["status"] == "SLNK_OK" and rep["status"] == "ok"
+    assert r["grel"][-1] <= 1e-2
+    if prec == "fp64":
+        assert (r["newton_iters"], r["pcg_iters"], r["coarse_matvecs"]) == \
+            (rep["newton_iters"], rep["pcg_iters"], rep["coarse_matvecs"])
+        check_rel("3d newton 2l v fp64", _np(v), vs, 1e-9)
+    else:
+        assert abs(r["newton_iters"] - rep["newton_iters"]) <= 1
+        check_rel("3d newton 2l v mixed", _np(v), vs, 1e-3)
+    gi = O.gradient(O.linearize(L, _np(v)))
+    assert np.abs(gi).max() <= 1.02e-2 * rep["g0_inf"]
     ctx.close()
