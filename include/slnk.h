@@ -80,9 +80,11 @@ typedef enum { SLNK_TRANSPORT_SL = 0, SLNK_TRANSPORT_RK2A = 1 } slnk_transport;
  *                 (recorded once per context and buffer pair); 0: launch every kernel
  *   batch         number of same-size problems B held by the context, 1 <= B <= 4096
  *   sl_path       SL step kernels: 0 = fused (LDS prefilter + gather in one kernel) whenever the
- *                 displacement halo fits in LDS, else coefficient pass + global gather;
- *                 1 = always the coefficient pass + global gather (a tuning choice: both give the
- *                 same interpolant up to rounding)
+ *                 displacement halo fits in LDS, else coefficient pass + global gather; the fused
+ *                 tile of 16 x 16 nodes runs 16 x 32 threads on launches of at most 512 tiles and
+ *                 16 x 16 above; 1 = always the coefficient pass + global gather; 2, 3 = as 0 with
+ *                 16 x 16 or 16 x 32 threads per fused tile whatever the launch size (tuning
+ *                 choices: all give the same interpolant up to rounding)
  *   hessian       SLNK_HESS_GN (default): the Gauss--Newton matvec, which drops every lambda term of
  *                 eq. e:hessian-matvec; SLNK_HESS_FN: the full-Newton matvec, whose incremental
  *                 adjoint carries the source div(lambda vt) (eq. e:inc-adj-slm) and whose b~ adds
@@ -368,7 +370,8 @@ slnk_status slnk_batch_newton_solve(slnk_batch* b, void* const* v_inout, const s
                                     slnk_solve_report* reports);
 /* Autotuner: for every bucket (one at a time), time 'reps' applications of the Krylov operator
  * at the current linearisation (set by slnk_batch_gradient) on the direction vt under each of
- * sl_path in {0, 1} x use_graphs in {0, 1}, and keep the fastest.  best_ms (array of buckets,
+ * sl_path in {1, 2, 3} (two-kernel step; fused step with 16 x 16 or 16 x 32 threads per tile) x
+ * use_graphs in {0, 1}, and keep the fastest.  best_ms (array of buckets,
  * may be NULL) receives the winning time per bucket. */
 slnk_status slnk_batch_autotune(slnk_batch* b, const void* const* vt, int reps, double* best_ms);
 

@@ -340,7 +340,7 @@ struct Context {
     if (p.reg < 1 || p.reg > 3) throw Fail{SLNK_EINVAL, "reg must be 1, 2 or 3"};
     if (!(p.beta > 0)) throw Fail{SLNK_EINVAL, "beta must be positive"};
     if (p.pc != SLNK_PC_REG && p.pc != SLNK_PC_2L) throw Fail{SLNK_EINVAL, "pc must be SLNK_PC_REG or SLNK_PC_2L"};
-    if (p.sl_path != 0 && p.sl_path != 1) throw Fail{SLNK_EINVAL, "sl_path must be 0 or 1"};
+    if (p.sl_path < 0 || p.sl_path > 3) throw Fail{SLNK_EINVAL, "sl_path must be 0, 1, 2 or 3"};
     if (p.hessian != SLNK_HESS_GN && p.hessian != SLNK_HESS_FN)
       throw Fail{SLNK_EINVAL, "hessian must be SLNK_HESS_GN or SLNK_HESS_FN"};
     full_newton = p.hessian == SLNK_HESS_FN;
@@ -543,6 +543,7 @@ struct Context {
     a.st_coef2 = (long long)lv.F;
     a.ht = 1.0 / lv.nt;
     a.force_global = prm.sl_path == 1;
+    a.fused_rows = prm.sl_path == 2 ? 16 : prm.sl_path == 3 ? 32 : 0;
     return a;
   }
 
@@ -2316,7 +2317,8 @@ slnk_status slnk_batch_autotune(slnk_batch* b, const void* const* vt, int reps, 
         if (!C.has_grad) throw slnk::Fail{SLNK_EINVAL, "no linearisation point: call slnk_batch_gradient first"};
         double best = 1e300;
         int bp = 0, bg = 1;
-        for (int path = 0; path < 2; ++path)
+        // the two-kernel step, and the fused step with 16 x 16 or 16 x 32 threads per tile
+        for (int path = 1; path < 4; ++path)
           for (int gr = 0; gr < 2; ++gr) {
             C.retune(path, gr);
             const double ms = C.time_operator(reinterpret_cast<const T*>(k.vin), reinterpret_cast<T*>(k.vout), reps);

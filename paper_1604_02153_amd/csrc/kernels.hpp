@@ -183,6 +183,7 @@ struct StepArgs {
   double w_old = 0;          // trapezoid weight of the src level (first step only)
   int first = 0, last = 0;
   int force_global = 0;      // 1: coefficient pass + global gather even when the halo fits LDS
+  int fused_rows = 0;        // threads per tile column of the fused step: 16 or 32 (0: by launch size)
   double* partial = nullptr; // FP64 per-block partial sums, item z at partial + z * 2 * tiles
                              // (state last step: misfit; adjoint last step: sum g^2, max |g|)
 };

@@ -194,6 +194,7 @@ Err run(const slnk_params& p, hipStream_t s, const T* v, const T* m0, T* m1, uns
     a.st_coef2 = (long long)F;
     a.ht = ht;
     a.force_global = p.sl_path == 1;
+    a.fused_rows = p.sl_path == 2 ? 16 : p.sl_path == 3 ? 32 : 0;
     a.src = cur;
     a.dst = j == nt ? m1 : nxt;
     a.st_src = a.st_dst = (long long)F;
@@ -223,7 +224,7 @@ extern "C" slnk_status slnk_transport_state_noalloc(const slnk_params* params, v
   if (!fft_size_ok(p.n1) || !fft_size_ok(p.n2)) return fail(SLNK_EINVAL, "grid sizes must be even products of 2, 3, 5 in [8, 2048]");
   if (p.nt < 1 || p.nt > 512) return fail(SLNK_EINVAL, "nt must be in [1, 512]");
   if (p.batch < 1) return fail(SLNK_EINVAL, "batch must be at least 1");
-  if (p.sl_path != 0 && p.sl_path != 1) return fail(SLNK_EINVAL, "sl_path must be 0 or 1");
+  if (p.sl_path < 0 || p.sl_path > 3) return fail(SLNK_EINVAL, "sl_path must be 0, 1, 2 or 3");
   if (p.prec != SLNK_PREC_FP64 && p.prec != SLNK_PREC_MIXED) return fail(SLNK_EINVAL, "prec must be FP64 or MIXED");
   const bool f64 = p.prec == SLNK_PREC_FP64;
   const size_t need = f64 ? scratch_need<double>(p.n1, p.n2, p.batch) : scratch_need<float>(p.n1, p.n2, p.batch);

@@ -811,7 +811,9 @@ hipError_t launch_fused(hipStream_t s, const StepArgs<T>& a, dim3 grid) {
 template <typename T, int KIND, bool FIRST>
 hipError_t launch_step(hipStream_t s, const StepArgs<T>& a, dim3 grid, dim3 block, bool fused) {
   if (fused) {
-    if ((long long)grid.x * grid.y * grid.z <= kWideBlocks) return launch_fused<T, KIND, FIRST, kFusedRows>(s, a, grid);
+    const bool wide = a.fused_rows == kFusedRows ||
+                      (a.fused_rows == 0 && (long long)grid.x * grid.y * grid.z <= kWideBlocks);
+    if (wide) return launch_fused<T, KIND, FIRST, kFusedRows>(s, a, grid);
     return launch_fused<T, KIND, FIRST, kTile>(s, a, grid);
   } else if (!a.two_pass_coef && a.n1 >= Prefilter2D<T>::PS && a.n2 >= Prefilter2D<T>::PS) {
     using P2 = Prefilter2D<T>;

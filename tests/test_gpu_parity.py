@@ -444,11 +444,14 @@ def test_batch_newton_items_stop_on_their_own(slnk, prec, pc):
     cb.close()
 
 
-def test_forced_global_path_matches_oracle(slnk):
-    """sl_path = 1 (coefficient pass + global gather for every step) gives the oracle's results."""
+@pytest.mark.parametrize("path", [1, 2, 3])
+def test_forced_sl_paths_match_oracle(slnk, path):
+    """sl_path = 1 (coefficient pass + global gather for every step), 2 and 3 (the fused step with
+    16 x 16 or 16 x 32 threads per tile whatever the launch size) give the oracle's results."""
     n, nt = 64, 4
+    print(f"sl_path {path}", flush=True)
     L, vgen, vt = problem("smooth", n, n, nt=nt, beta=1e-2, reg=1)
-    ctx = _ctx(slnk, L, "fp64", sl_path=1)
+    ctx = _ctx(slnk, L, "fp64", sl_path=path)
     ctx.set_images(_t(L.mR, "fp64"), _t(L.mT, "fp64"))
     v = 0.6 * vgen
     lin = O.linearize(L, v)
