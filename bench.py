@@ -359,7 +359,7 @@ def batched(args, dev):
     }
 
 
-def brain512(args, dev):
+def brain512(args, dev, oracle_ref=None):
     """Single 512^2 pair, nt = 8, H1 beta 1e-3, P_2L (the 'brain512' recipe): Newton solve time and
     isolated GN matvec rate under both SL kernel paths, with the fraction of the HBM roofline.  (H1
     without divergence control: on this pair the Gauss-Newton steps blow up at 256^2 and 512^2 and
@@ -441,7 +441,38 @@ def brain512(args, dev):
         "pcg_iters": rep["pcg_iters"], "grel": [float(f"{x:.3g}") for x in rep["grel"]],
         "matvecs_per_s": round(rate, 1)}
     ctx.close()
+    if oracle_ref is not None:
+        out["errors_vs_oracle"] = {
+            "inputs": "each recipe rounded to FP32, m_R by the oracle's transport, gradient and matvec at v_gen",
+            "brain512": brain_errors(oracle_ref["brain512"], dev, proj="none"),
+            "brain512ic": brain_errors(oracle_ref["brain512ic"], dev, proj="leray")}
     return out
+
+
+def brain_errors(ref, dev, proj):
+    """Mixed context against the FP64 oracle's results of the cpu_baseline leg on the 512^2 recipe's
+    own inputs (rounded to FP32; m_R by the oracle's transport): relative L2 errors of the state
+    transport, the gradient and the GN matvec at v_gen (nt = 8, H1, beta = 1e-3; K = Leray for the
+    incompressible recipe)."""
+    import numpy as np
+    import torch
+
+    from paper_1604_02153_amd import Context
+    n1, n2 = ref["mT"].shape
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=torch.float32)
+    host = lambda x: x.double().cpu().numpy()
+    ctx = Context(n1, n2, ref["nt"], reg="h1", beta=ref["beta"], prec="mixed", pc="2l", proj=proj)
+    m1g = torch.empty((n1, n2), dtype=torch.float32, device=dev)
+    ctx.transport_state(t(ref["v_gen"]), t(ref["mT"]), m1g)
+    ctx.set_images(t(ref["mR"]), t(ref["mT"]))
+    gg = torch.empty((2, n1, n2), dtype=torch.float32, device=dev)
+    ctx.gradient(t(ref["v_gen"]), gg)
+    hg = torch.empty_like(gg)
+    ctx.hessian_matvec(t(ref["vt"]), hg)
+    ctx.close()
+    return {"transport_state": float(f"{rel_l2(host(m1g), ref['m1']):.3g}"),
+            "gradient": float(f"{rel_l2(host(gg), ref['grad']):.3g}"),
+            "gn_matvec": float(f"{rel_l2(host(hg), ref['hvt']):.3g}")}
 
 
 def d3_matvec_bytes(n, nt, elem=4):
@@ -728,6 +759,19 @@ def cpu_baseline(cfg, min_seconds):
                         "grel_final": float(f"{rep['grel'][-1]:.4g}"), "status": rep["status"]}}
     ref = {"mT": mT, "mR": mR, "v_gen": vgen, "vt": vt, "J": lin.J, "m1": lin.m[-1], "grad": grad, "hvt": h,
            "p2l_vt": z, "v_sol": v_sol, "g0_inf": rep["g0_inf"], "emax": tl.emax, "emin": tl.emin}
+    # the 512^2 recipes (nt = 8, H1; K = I and K = Leray): the oracle's transport, gradient and GN
+    # matvec at v_gen on the inputs rounded to FP32
+    import synth
+    for name, proj in (("brain512", 0), ("brain512ic", 1)):
+        bc = synth.config(name)
+        with threadpool_limits(limits=1):
+            gb = O.Grid(bc["n1"], bc["n2"])
+            bT, bv, bvt = r32(bc["mT"]), r32(bc["v_gen"]), r32(bc["vt"])
+            b1 = O.transport_state(gb, bv, bT, bc["nt"])
+            Lb = O.Level(gb, bT, r32(b1), O.Params(nt=bc["nt"], beta=bc["beta"], reg=bc["reg"], proj=proj))
+            linb = O.linearize(Lb, bv)
+            ref[name] = {"mT": bT, "mR": Lb.mR, "v_gen": bv, "vt": bvt, "m1": b1, "grad": O.gradient(linb),
+                         "hvt": O.hessian_matvec(linb, bvt), "nt": bc["nt"], "beta": bc["beta"]}
     return timing, ref
 
 
@@ -942,7 +986,7 @@ def main():
         line["learned_vs_plain"] = learned(args, dev)
         log("learned vs plain done")
     if not args.no_brain:
-        line["brain512"] = brain512(args, dev)
+        line["brain512"] = brain512(args, dev, oracle_ref)
         log("512^2 workload done")
     if not args.no_full_newton:
         line["full_newton"] = full_newton(args, dev)
