@@ -313,8 +313,10 @@ slnk_status slnk_unet_get_grads(slnk_unet* u, float* host);
  * (reset != 0 clears them after reading).  counts[3 (mw - 1) + j]: mw = 1 for output tiles of 16
  * pixels (H W an odd multiple of 64), 2 for 32 pixels; j = 0, 1, 2 for the reduction over input
  * channels split 1, 2 or 4 ways across the block's wavefronts (chosen from the number of output
- * tiles, so that a launch keeps about eight wavefronts per compute unit). */
-void slnk_unet_conv_variants(long long counts[6], int reset);
+ * tiles, so that a launch keeps about eight wavefronts per compute unit); counts[6], counts[7]:
+ * the LDS-tiled kernel (input halo patch and weights of each 32-channel chunk staged once per
+ * block) with 32 or 64 output channels per block, taken by launches of at least 512 blocks. */
+void slnk_unet_conv_variants(long long counts[8], int reset);
 /* v [batch][2][H][W] = network(m_R, m_T), images [batch][H][W]; head [batch] (may be NULL)
  * receives the scalar head's output */
 slnk_status slnk_unet_forward(slnk_unet* u, int batch, const float* m_R, const float* m_T, float* v,

@@ -642,10 +642,13 @@ class UNet:
     @staticmethod
     def conv_variant_counts(reset=True) -> dict:
         """Launches of each convolution kernel variant in this process since the last reset, keyed
-        by (pixels per output tile, ways the channel reduction is split)."""
-        c = (ctypes.c_longlong * 6)()
+        by (pixels per output tile, ways the channel reduction is split) for the direct kernel and
+        ("lds", output channels per block) for the LDS-tiled one."""
+        c = (ctypes.c_longlong * 8)()
         load_library().slnk_unet_conv_variants(c, 1 if reset else 0)
-        return {(16 * mw, ks): int(c[3 * (mw - 1) + j]) for mw in (1, 2) for j, ks in enumerate((1, 2, 4))}
+        out = {(16 * mw, ks): int(c[3 * (mw - 1) + j]) for mw in (1, 2) for j, ks in enumerate((1, 2, 4))}
+        out[("lds", 32)], out[("lds", 64)] = int(c[6]), int(c[7])
+        return out
 
     def forward(self, m_R, m_T, v, head=None):
         b, h, w = m_R.shape

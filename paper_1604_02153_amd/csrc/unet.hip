@@ -32,6 +32,38 @@ __device__ __forceinline__ v8bf load8(const bf16* p) { return *reinterpret_cast<
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // ---- convolution (forward, and input gradient with transformed weights) ----------------------
+// Epilogue of one lane's share of a 16 x 16 MFMA result: the four values of the 2 x 2 pixel block
+// at rows y0, y0 + 1 and columns xb, xb + 1 of image pb, output channel co.  Adds the bias, applies
+// the ReLU, stores the BF16 output, its 2 x 2 average (the same BF16 values summed in the order of
+// the pooling) and its four upsampled copies, and the FP32 values of the first nv channels.
+__device__ __forceinline__ void conv_store(const ConvArgs& a, int pb, int y0, int xb, int co, v4f acc) {
+  const int HW = a.H * a.W;
+  const float bias = a.bias ? a.bias[co] : 0.f;
+  float pooled = 0.f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int yq = y0 + (q >> 1), xq = xb + (q & 1);
+    const size_t p = size_t(pb) * HW + size_t(yq) * a.W + xq;
+    float v = acc[q] + bias;
+    if (a.relu) v = fmaxf(v, 0.f);
+    const bf16 h = f2bf(v);
+    pooled += bf2f(h);
+    if (a.y) a.y[p * a.ycs + a.yco + co] = h;
+    if (a.yu) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const size_t pu = (size_t(pb) * 2 * a.H + 2 * yq + (u >> 1)) * (2 * a.W) + 2 * xq + (u & 1);
+        a.yu[pu * a.yucs + a.yuco + co] = h;
+      }
+    }
+    if (a.v && co < a.nv) a.v[(size_t(pb) * a.nv + co) * HW + size_t(yq) * a.W + xq] = v;
+  }
+  if (a.yp) {
+    const size_t po = (size_t(pb) * (a.H >> 1) + (y0 >> 1)) * (a.W >> 1) + (xb >> 1);
+    a.yp[po * a.ypcs + a.ypco + co] = f2bf(0.25f * pooled);
+  }
+}
+
 // Block: four wavefronts.  KS of them (1, 2 or 4) share one output tile of 16 MW pixels x 32
 // output channels (MW x 2 MFMA tiles) and split its K = 9 taps x cin/32 channel chunks between
 // them; their partial sums meet in LDS and are added in a fixed order.  Small grids (the deep
@@ -122,34 +154,89 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
 #pragma unroll
   for (int i = 0; i < MW; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int co = cobase + 16 * j + r;
-      const float bias = a.bias ? a.bias[co] : 0.f;
-      const int xb = x0 + 8 * i + 2 * g;  // this lane's 2 x 2 block: rows y0, y0 + 1, columns xb, xb + 1
-      float pooled = 0.f;
+    for (int j = 0; j < 2; ++j) conv_store(a, pb, y0, x0 + 8 * i + 2 * g, cobase + 16 * j + r, acc[i][j]);
+}
+
+// LDS-tiled variant for large launches.  A block computes 2 rows x TW columns of pixels x NC output
+// channels (NC = 64: 2 x 2 wavefronts over pixels x channels, TW = 32; NC = 32: 4 x 1, TW = 64);
+// each wavefront holds 2 x 2 MFMA tiles (two 2 x 8 pixel patches x 32 channels).  For each chunk of
+// 32 input channels the block stages the input's 4 x (TW + 2) halo patch (periodic) and the nine
+// taps' weights for its NC channels in LDS once, and every tap then reads its operands there: each
+// input value serves nine taps and NC channels, each weight 2 TW pixels.  Operands are 16-byte LDS
+// reads at the same lane layout as k_conv (so the same epilogue applies).
+template <int NC>
+__global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a) {
+  constexpr int WM = NC == 64 ? 2 : 4;  // wavefronts along the pixels
+  constexpr int TW = 16 * WM;           // tile width in pixels
+  constexpr int IW = TW + 2;            // staged halo width
+  __shared__ __attribute__((aligned(16))) bf16 sIn[4 * IW * 32];
+  __shared__ __attribute__((aligned(16))) bf16 sW[9 * NC * 32];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int wm = wave % WM, wn = wave / WM;
+  const int HW = a.H * a.W;
+  const int tpr = a.W / TW;                 // tiles per row pair
+  const int tpi = (a.H >> 1) * tpr;         // tiles per image
+  const int tile = blockIdx.x;
+  const int pb = tile / tpi;
+  const int trem = tile - pb * tpi;
+  const int prow = trem / tpr;
+  const int y0 = 2 * prow, x0 = TW * (trem - prow * tpr);
+  const int cobase = blockIdx.y * NC;
+  const size_t img = size_t(pb) * HW;
+  // this lane's pixel of M-tile i (tile coordinates): row (r >> 1) & 1, column 16 wm + 8 i + 2 (r >> 2) + (r & 1)
+  int aoff[2];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int yq = y0 + (q >> 1), xq = xb + (q & 1);
-        const size_t p = size_t(pb) * HW + size_t(yq) * a.W + xq;
-        float v = acc[i][j][q] + bias;
-        if (a.relu) v = fmaxf(v, 0.f);
-        const bf16 h = f2bf(v);
-        pooled += bf2f(h);
-        if (a.y) a.y[p * a.ycs + a.yco + co] = h;
-        if (a.yu) {
+  for (int i = 0; i < 2; ++i) {
+    const int ly = (r >> 1) & 1, lx = 16 * wm + 8 * i + 2 * (r >> 2) + (r & 1);
+    aoff[i] = ((ly + 1) * IW + (lx + 1)) * 32 + 8 * g;  // centre tap; tap (dy, dx) adds (dy IW + dx) 32
+  }
+  int boff[2];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const size_t pu = (size_t(pb) * 2 * a.H + 2 * yq + (u >> 1)) * (2 * a.W) + 2 * xq + (u & 1);
-            a.yu[pu * a.yucs + a.yuco + co] = h;
-          }
-        }
-        if (a.v && co < a.nv) a.v[(size_t(pb) * a.nv + co) * HW + size_t(yq) * a.W + xq] = v;
-      }
-      if (a.yp) {
-        const size_t po = (size_t(pb) * (a.H >> 1) + prow) * (a.W >> 1) + (xb >> 1);
-        a.yp[po * a.ypcs + a.ypco + co] = f2bf(0.25f * pooled);
-      }
+  for (int j = 0; j < 2; ++j) boff[j] = (32 * (WM == 2 ? wn : 0) + 16 * j + r) * 32 + 8 * g;
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int nk = a.cin >> 5;
+  for (int kc = 0; kc < nk; ++kc) {
+    __syncthreads();  // the previous chunk's operands are no longer read
+    // input halo: 4 rows x IW columns x 4 vectors of 8 channels
+    for (int e = tid; e < 4 * IW * 4; e += 256) {
+      const int part = e & 3, pix = e >> 2;
+      const int row = pix / IW, col = pix - row * IW;
+      const int yy = wrap(y0 - 1 + row, a.H), xx = wrap(x0 - 1 + col, a.W);
+      *reinterpret_cast<uint4*>(sIn + pix * 32 + 8 * part) = *reinterpret_cast<const uint4*>(
+          a.x + (img + size_t(yy) * a.W + xx) * a.xcs + a.xco + 32 * kc + 8 * part);
     }
+    // weights: 9 taps x NC channels x 4 vectors of 8 input channels
+    for (int e = tid; e < 9 * NC * 4; e += 256) {
+      const int part = e & 3, tc = e >> 2;
+      const int t = tc / NC, co = tc - t * NC;
+      *reinterpret_cast<uint4*>(sW + tc * 32 + 8 * part) = *reinterpret_cast<const uint4*>(
+          a.w + (size_t(t) * a.cout + cobase + co) * a.cin + 32 * kc + 8 * part);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int shift = ((t / 3 - 1) * IW + (t % 3 - 1)) * 32;
+      v8bf av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = load8(sIn + aoff[i] + shift);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = load8(sW + t * NC * 32 + boff[j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      conv_store(a, pb, y0, x0 + 16 * wm + 8 * i + 2 * g, cobase + 32 * (WM == 2 ? wn : 0) + 16 * j + r, acc[i][j]);
 }
 
 // ---- weight gradient ----------------------------------------------------------------------------
@@ -456,17 +543,32 @@ inline unsigned blocks_for(size_t n) {
 }  // namespace
 
 namespace {
-std::atomic<long long> g_conv_launches[6];
+std::atomic<long long> g_conv_launches[kConvVariants];
 }
 
-void conv_variant_counts(long long out[6], bool reset) {
-  for (int i = 0; i < 6; ++i) out[i] = reset ? g_conv_launches[i].exchange(0) : g_conv_launches[i].load();
+void conv_variant_counts(long long out[kConvVariants], bool reset) {
+  for (int i = 0; i < kConvVariants; ++i)
+    out[i] = reset ? g_conv_launches[i].exchange(0) : g_conv_launches[i].load();
 }
 
 hipError_t conv(hipStream_t s, const ConvArgs& a) {
   const int HW = a.H * a.W;
   if (a.cin % 32 || a.cout % 32 || a.xcs % 8 || a.xco % 8 || a.H % 2 || a.W % 8 || HW % 64 || a.P % HW)
     return hipErrorInvalidValue;
+  // large launches: the LDS-tiled kernel (at least two blocks per compute unit)
+  const int nc = a.cout % 64 == 0 && a.W % 32 == 0 ? 64 : (a.W % 64 == 0 ? 32 : 0);
+  if (nc) {
+    const long blocks = long(a.P / (2 * (nc == 64 ? 32 : 64))) * (a.cout / nc);
+    if (blocks >= kLdsConvMinBlocks) {
+      const dim3 grid(unsigned(a.P / (2 * (nc == 64 ? 32 : 64))), a.cout / nc);
+      g_conv_launches[nc == 64 ? 7 : 6].fetch_add(1);
+      if (nc == 64)
+        hipLaunchKernelGGL((k_conv_lds<64>), grid, dim3(256), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_conv_lds<32>), grid, dim3(256), 0, s, a);
+      return hipGetLastError();
+    }
+  }
   // output tiles of 2 x 8 MW pixels x 32 channels; split K when they would not give about eight
   // wavefronts per compute unit
   const int mw = HW % 128 == 0 && a.W % 16 == 0 ? 2 : 1;

@@ -36,9 +36,13 @@ struct ConvArgs {
   int H = 0, W = 0, P = 0;
 };
 hipError_t conv(hipStream_t s, const ConvArgs& a);
+// Launches of at least this many blocks take the LDS-tiled kernel (when the shape allows it).
+constexpr long kLdsConvMinBlocks = 512;
 // Process-wide counts of the convolution launches per kernel variant since the last reset:
-// out[3 (mw - 1) + j], mw = pixel tiles of 16 or 32 (1, 2), j = 0, 1, 2 for K split 1, 2, 4 ways.
-void conv_variant_counts(long long out[6], bool reset);
+// out[3 (mw - 1) + j], mw = pixel tiles of 16 or 32 (1, 2), j = 0, 1, 2 for K split 1, 2, 4 ways;
+// out[6], out[7]: the LDS-tiled kernel with 32 or 64 output channels per block.
+constexpr int kConvVariants = 8;
+void conv_variant_counts(long long out[kConvVariants], bool reset);
 
 // Weight-gradient partials: partial[z][t][co][ci] = sum over pixel chunk z of
 // dy[p][co] * x[p + d_t][ci]; wgrad_splits(P, chunk) chunks (chunk a multiple of 128).

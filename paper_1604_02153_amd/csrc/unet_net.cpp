@@ -525,7 +525,7 @@ slnk_status slnk_unet_get_grads(slnk_unet* u, float* host) {
   });
 }
 
-void slnk_unet_conv_variants(long long counts[6], int reset) {
+void slnk_unet_conv_variants(long long counts[8], int reset) {
   if (counts) slnk::unet::conv_variant_counts(counts, reset != 0);
 }
 

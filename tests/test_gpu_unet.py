@@ -113,9 +113,9 @@ def _shipped(slnk, max_batch):
 
 def test_shipped_network_forward_matches_reference(slnk):
     """The shipped 256^2, 4-level, 32-channel network at batch 1 (the learned solve's forward):
-    output velocity and head against the reference.  Its launches take the kernel variants with
-    32-pixel output tiles and the channel reduction split 1 (65536-pixel level), 2 (128^2 level)
-    and 4 ways (the two coarsest levels)."""
+    output velocity and head against the reference.  Its launches take the LDS-tiled kernel
+    (65536-pixel level, 32 channels per block) and the direct kernel with 32-pixel output tiles and
+    the channel reduction split 2 (128^2 level) and 4 ways (the two coarsest levels)."""
     from paper_1604_02153_amd.train_unet import make_pair
     net, arch, params = _shipped(slnk, 1)
     assert arch.n == net.n_params
@@ -129,7 +129,7 @@ def test_shipped_network_forward_matches_reference(slnk):
     net.forward(_t(mR), _t(mT), v, head)
     counts = slnk.UNet.conv_variant_counts()
     print("variants", counts, flush=True)
-    assert counts[(32, 1)] > 0 and counts[(32, 2)] > 0 and counts[(32, 4)] > 0, counts
+    assert counts[("lds", 32)] > 0 and counts[(32, 2)] > 0 and counts[(32, 4)] > 0, counts
     v_ref, cache = U.forward(arch, params, mR, mT, bf16=True)
     err = rel(v.cpu().numpy(), v_ref)
     record("U-Net 256^2 forward (shipped weights)", err, 1e-2)
@@ -143,8 +143,8 @@ def test_shipped_network_forward_matches_reference(slnk):
 def test_shipped_network_gradients_match_reference(slnk):
     """A training step of the shipped 256^2 network at batch 2 (lr 0): the loss and every layer's
     weight and bias gradients against the reference.  The weight gradients of the 256^2 level sum
-    64 pixel chunks; the forward and input-gradient launches take the unsplit reduction on the two
-    finest levels."""
+    64 pixel chunks; the forward and input-gradient launches take the LDS-tiled kernel on the two
+    finest levels (32 and 64 channels per block) and the direct kernel below."""
     from paper_1604_02153_amd.train_unet import make_pair
     import oracle as O
     net, arch, params = _shipped(slnk, 2)
@@ -159,7 +159,7 @@ def test_shipped_network_gradients_match_reference(slnk):
     loss = net.train_step(_t(mR), _t(mT), _t(tgt), 0.0)
     counts = slnk.UNet.conv_variant_counts()
     print("variants", counts, flush=True)
-    assert counts[(32, 1)] > 0 and counts[(32, 2)] > 0, counts
+    assert counts[("lds", 32)] > 0 and counts[("lds", 64)] > 0 and counts[(32, 2)] > 0, counts
     g = net.get_grads().astype(np.float64)[: arch.trunk_n]
     v_ref, cache = U.forward(arch, params, mR, mT, bf16=True)
     l_ref, dv = U.mse(v_ref, tgt)
