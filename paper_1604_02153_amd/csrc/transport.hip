@@ -569,6 +569,11 @@ __global__ void __launch_bounds__(Prefilter2D<T>::NT) k_prefilter_2d(StepArgs<T>
 // instead of two, with two waves per SIMD to cover each other's LDS latency -- and the gather and
 // update take the first 16 rows; larger launches keep 16 x 16 blocks, which fill the CUs better.
 constexpr int kFusedRows = 2 * kTile;
+// Largest halo the fused step takes: a tile of 16 x 16 nodes filters a (16 + 2 halo + 3 + 2K)^2
+// footprint, which past about 8 cells costs more than the two-kernel step's extra coefficient
+// pass (measured single-pair matvecs: 512^2 at halo 5, fused 0.19 vs 0.22 ms; 1024^2 at halo 13,
+// fused 0.42 vs 0.22 ms).
+constexpr int kFusedMaxHalo = 8;
 constexpr long long kWideBlocks = 512;
 
 template <typename T, int KIND, bool FIRST, bool GLOBAL, int TY = kTile>
@@ -858,7 +863,7 @@ template <typename T>
 hipError_t sl_step(hipStream_t s, StepKind kind, const StepArgs<T>& a, int* nblocks_out) {
   hipError_t e = upload_taps();
   if (e != hipSuccess) return e;
-  const int maxh = sl_step_max_halo<T>();
+  const int maxh = std::min(sl_step_max_halo<T>(), kFusedMaxHalo);
   if (a.halo < 0) return hipErrorInvalidValue;
   const bool fused = a.halo <= maxh && !a.force_global;
   if (!fused && (a.coef == nullptr || a.coef2 == nullptr)) return hipErrorInvalidValue;
