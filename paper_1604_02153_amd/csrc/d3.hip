@@ -35,6 +35,8 @@ struct Tile<double> {
 
 __device__ __forceinline__ int bitrev(int k, int logn) { return int(__brev(unsigned(k)) >> (32 - logn)); }
 
+__device__ __forceinline__ int ilog2_dev(int n) { return 31 - __clz(n); }
+
 inline int ilog2(int n) {
   int l = 0;
   while ((1 << l) < n) ++l;
@@ -55,16 +57,18 @@ hipError_t ensure_lds(K kernel, size_t bytes) {
   return e;
 }
 
-// In-place transforms of CL lines of length n held in LDS as s[k * CL + line], input in
-// bit-reversed order, output in natural order.  sign -1: exp(-2 pi i jk/n), +1: exp(+...).
-template <typename T, int CL>
-__device__ void lds_fft(cplx<T>* s, int n, int logn, int sign, const cplx<T>* __restrict__ tw) {
-  const int nb = (n / 2) * CL;
+// In-place transforms of lines line0 .. line0 + NL - 1 of length n held in LDS as
+// s[k * STRIDE + line], input in bit-reversed order, output in natural order.
+// sign -1: exp(-2 pi i jk/n), +1: exp(+...).
+template <typename T, int STRIDE, int NL = STRIDE>
+__device__ void lds_fft(cplx<T>* s, int n, int logn, int sign, const cplx<T>* __restrict__ tw, int line0 = 0) {
+  constexpr int CL = STRIDE;
+  const int nb = (n / 2) * NL;
   for (int st = 0; st < logn; ++st) {
     const int half = 1 << st;
     const int tshift = logn - 1 - st;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-      const int c = b % CL, q = b / CL;
+      const int c = line0 + b % NL, q = b / NL;
       const int j = q & (half - 1);
       const int i0 = ((q >> st) << (st + 1)) + j;
       const int i1 = i0 + half;
@@ -106,21 +110,21 @@ __global__ void __launch_bounds__(kThreads) k_fft_strided(cplx<T>* data, size_t 
   }
 }
 
-// Real rows of length n (contiguous) -> their first n/2 + 1 Fourier coefficients.
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_fft_r2c_rows(const T* __restrict__ in, size_t fin, cplx<T>* out,
+// Real rows of length n (contiguous, element type TF) -> their first n/2 + 1 Fourier coefficients.
+template <typename T, typename TF = T>
+__global__ void __launch_bounds__(kThreads) k_fft_r2c_rows(const TF* __restrict__ in, size_t fin, cplx<T>* out,
                                                            size_t fout, int rows, int n, int logn,
                                                            const cplx<T>* __restrict__ tw) {
   constexpr int RL = Tile<T>::RL;
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* s = reinterpret_cast<cplx<T>*>(smem_raw);
   const int r0 = blockIdx.x * RL;
-  const T* src = in + blockIdx.z * fin;
+  const TF* src = in + blockIdx.z * fin;
   cplx<T>* dst = out + blockIdx.z * fout;
   const int nh = n / 2 + 1;
   for (int e = threadIdx.x; e < n * RL; e += blockDim.x) {
     const int r = e / n, k = e - r * n;
-    const T v = r0 + r < rows ? src[size_t(r0 + r) * n + k] : T(0);
+    const T v = r0 + r < rows ? T(src[size_t(r0 + r) * n + k]) : T(0);
     s[bitrev(k, logn) * RL + r] = cplx<T>{v, T(0)};
   }
   __syncthreads();
@@ -131,9 +135,10 @@ __global__ void __launch_bounds__(kThreads) k_fft_r2c_rows(const T* __restrict__
   }
 }
 
-// Half spectra of rows -> real rows (the full row spectrum is the Hermitian extension), times scale.
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_fft_c2r_rows(const cplx<T>* __restrict__ in, size_t fin, T* out,
+// Half spectra of rows -> real rows (the full row spectrum is the Hermitian extension), times scale,
+// stored as TF.
+template <typename T, typename TF = T>
+__global__ void __launch_bounds__(kThreads) k_fft_c2r_rows(const cplx<T>* __restrict__ in, size_t fin, TF* out,
                                                            size_t fout, int rows, int n, int logn, T scale,
                                                            const cplx<T>* __restrict__ tw) {
   constexpr int RL = Tile<T>::RL;
@@ -141,7 +146,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_c2r_rows(const cplx<T>* __rest
   cplx<T>* s = reinterpret_cast<cplx<T>*>(smem_raw);
   const int r0 = blockIdx.x * RL;
   const cplx<T>* src = in + blockIdx.z * fin;
-  T* dst = out + blockIdx.z * fout;
+  TF* dst = out + blockIdx.z * fout;
   const int h = n / 2, nh = h + 1;
   for (int e = threadIdx.x; e < n * RL; e += blockDim.x) {
     const int r = e / n, k = e - r * n;
@@ -156,7 +161,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_c2r_rows(const cplx<T>* __rest
   lds_fft<T, RL>(s, n, logn, +1, tw);
   for (int e = threadIdx.x; e < n * RL; e += blockDim.x) {
     const int r = e / n, k = e - r * n;
-    if (r0 + r < rows) dst[size_t(r0 + r) * n + k] = s[k * RL + r].x * scale;
+    if (r0 + r < rows) dst[size_t(r0 + r) * n + k] = TF(s[k * RL + r].x * scale);
   }
 }
 
@@ -401,6 +406,104 @@ __global__ void __launch_bounds__(kThreads) k_div(Dims d, cplx<T>* S) {
   const Wave w = wave_of(idx, d);
   const cplx<T> s = cadd(cadd(cscale(S[idx], T(w.o1)), cscale(S[Fh + idx], T(w.o2))), cscale(S[2 * Fh + idx], T(w.o3)));
   S[idx] = cmul_i(s);
+}
+
+// ---- transform along x1 fused with the spectral operator ---------------------------------------
+// Every line along x1 of a half spectrum holds all k1 of one (k2, k3): the last forward pass, the
+// operator (pointwise in k) and the first inverse pass run on it in LDS.  NB buffers of n x CL
+// lines: the NI input fields' lines are transformed, the operator leaves its NO output fields in
+// bit-reversed order (each thread handles the pair k, bitrev(k), so the reordering is in place),
+// and the outputs are transformed back.  OP 0: symbol (with the Leray projection for three fields);
+// 1: gradient (one field in, three out, in buffers 1..3); 2: divergence (three in, one out).
+template <typename T, int OP, int NI>
+struct X1Op {
+  static constexpr int NO = OP == 1 ? 3 : (OP == 2 ? 1 : NI);
+  static constexpr int NB = OP == 1 ? 4 : NI;
+  static constexpr int OUT0 = OP == 1 ? 1 : 0;  // first output buffer
+};
+
+template <typename T, int OP, int NI>
+__global__ void __launch_bounds__(kThreads) k_x1_op(Dims d, const cplx<T>* Sin, cplx<T>* Sout, SymArgs a,
+                                                    const cplx<T>* __restrict__ tw) {
+  constexpr int CL = Tile<T>::CL;
+  using X = X1Op<T, OP, NI>;
+  constexpr int L = X::NB * CL;  // lines in LDS: buffer b, line c at column b CL + c
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* s = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int n = d.n1, logn = ilog2_dev(n);
+  const int nh = d.nh();
+  const int inner = d.n2 * nh;
+  const long long stride_k = inner;
+  const size_t Fh = d.Fh();
+  const int c0 = blockIdx.x * CL;
+  const int ncl = min(CL, inner - c0);
+  for (int e = threadIdx.x; e < n * NI * CL; e += blockDim.x) {
+    const int c = e % CL, b = (e / CL) % NI, k = e / (CL * NI);
+    cplx<T> v = {T(0), T(0)};
+    if (c < ncl) v = Sin[b * Fh + size_t(k) * stride_k + c0 + c];
+    s[bitrev(k, logn) * L + b * CL + c] = v;
+  }
+  __syncthreads();
+  lds_fft<T, L, NI * CL>(s, n, logn, -1, tw);  // the input buffers
+  // operator at natural k, stored at bitrev(k): pairs (k, kb) with k <= kb
+  for (int e = threadIdx.x; e < n * CL; e += blockDim.x) {
+    const int c = e % CL, k = e / CL;
+    const int kb = bitrev(k, logn);
+    if (k > kb) continue;
+    const int idx2 = min(c0 + c, inner - 1);
+    const int i2 = idx2 / nh, i3 = idx2 - i2 * nh;
+    cplx<T> res[2][3];
+    const int ks[2] = {k, kb};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i1 = ks[h];
+      Wave w;
+      w.k1 = signed_wavenumber(i1, d.n1);
+      w.k2 = signed_wavenumber(i2, d.n2);
+      w.k3 = i3;
+      w.o1 = i1 == d.n1 / 2 ? 0 : w.k1;
+      w.o2 = i2 == d.n2 / 2 ? 0 : w.k2;
+      w.o3 = i3 == d.n3 / 2 ? 0 : w.k3;
+      cplx<T> x[3];
+#pragma unroll
+      for (int b = 0; b < NI; ++b) x[b] = s[i1 * L + b * CL + c];
+      if constexpr (OP == 0) {
+        const T sv = T(symbol_value(w, a));
+        if constexpr (NI == 3) {
+          if (a.proj) {
+            const T kk = T(double(w.o1) * w.o1 + double(w.o2) * w.o2 + double(w.o3) * w.o3);
+            if (kk > T(0)) {
+              const T o[3] = {T(w.o1), T(w.o2), T(w.o3)};
+              cplx<T> kb3 = cadd(cadd(cscale(x[0], o[0]), cscale(x[1], o[1])), cscale(x[2], o[2]));
+              kb3 = cscale(kb3, T(1) / kk);
+#pragma unroll
+              for (int q = 0; q < 3; ++q) x[q] = csub(x[q], cscale(kb3, o[q]));
+            }
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < NI; ++b) res[h][b] = cscale(x[b], sv);
+      } else if constexpr (OP == 1) {
+        const cplx<T> iu = cmul_i(x[0]);
+        res[h][0] = cscale(iu, T(w.o1));
+        res[h][1] = cscale(iu, T(w.o2));
+        res[h][2] = cscale(iu, T(w.o3));
+      } else {
+        res[h][0] = cmul_i(cadd(cadd(cscale(x[0], T(w.o1)), cscale(x[1], T(w.o2))), cscale(x[2], T(w.o3))));
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < X::NO; ++b) {
+      s[kb * L + (X::OUT0 + b) * CL + c] = res[0][b];
+      s[k * L + (X::OUT0 + b) * CL + c] = res[1][b];
+    }
+  }
+  __syncthreads();
+  lds_fft<T, L, X::NO * CL>(s, n, logn, +1, tw, X::OUT0 * CL);  // the output buffers
+  for (int e = threadIdx.x; e < n * X::NO * CL; e += blockDim.x) {
+    const int c = e % CL, b = (e / CL) % X::NO, k = e / (CL * X::NO);
+    if (c < ncl) Sout[b * Fh + size_t(k) * stride_k + c0 + c] = s[k * L + (X::OUT0 + b) * CL + c];
+  }
 }
 
 // ---- semi-Lagrangian transport ---------------------------------------------------------------
@@ -783,6 +886,82 @@ hipError_t spline_coefficients(hipStream_t s, const Dims& d, int nf, const T* in
   return hipGetLastError();
 }
 
+size_t device_lds_limit() {
+  static std::atomic<size_t> lim{0};
+  size_t v = lim.load(std::memory_order_acquire);
+  if (v == 0) {
+    int dev = 0, b = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                                                hipSuccess)
+      return 64 * 1024;
+    v = size_t(b);
+    lim.store(v, std::memory_order_release);
+  }
+  return v;
+}
+
+template <typename T, int OP, int NI>
+hipError_t launch_x1_op(hipStream_t s, const Dims& d, const cplx<T>* Sin, cplx<T>* Sout, SymArgs a,
+                        const cplx<T>* tw, bool& done) {
+  constexpr int CL = Tile<T>::CL;
+  const size_t lds = size_t(X1Op<T, OP, NI>::NB) * CL * d.n1 * sizeof(cplx<T>);
+  done = false;
+  if (lds > device_lds_limit()) return hipSuccess;
+  const hipError_t e = ensure_lds(k_x1_op<T, OP, NI>, lds);
+  if (e != hipSuccess) return e;
+  const int inner = d.n2 * d.nh();
+  hipLaunchKernelGGL((k_x1_op<T, OP, NI>), dim3((inner + CL - 1) / CL), dim3(kThreads), lds, s, d, Sin, Sout, a, tw);
+  done = true;
+  return hipGetLastError();
+}
+
+template <typename T, typename TF>
+hipError_t spec_apply(hipStream_t s, const Dims& d, const Twiddles<T>& tw, SpecOp op, int nf, SymArgs a, const TF* in,
+                      TF* out, cplx<T>* S1, cplx<T>* S2) {
+  constexpr int RL = Tile<T>::RL;
+  const int nin = op == SpecOp::Grad ? 1 : nf;
+  const int nout = op == SpecOp::Grad ? 3 : (op == SpecOp::Div ? 1 : nf);
+  if ((op == SpecOp::Scale && nf != 1 && nf != 3) || (op != SpecOp::Scale && nf != (op == SpecOp::Grad ? 1 : 3)))
+    return hipErrorInvalidValue;
+  const int rows = d.n1 * d.n2, nh = d.nh();
+  const size_t F = d.F(), Fh = d.Fh();
+  const long long sx1 = (long long)d.n2 * nh;
+  hipLaunchKernelGGL((k_fft_r2c_rows<T, TF>), dim3((rows + RL - 1) / RL, 1, nin), dim3(kThreads),
+                     size_t(d.n3) * RL * sizeof(cplx<T>), s, in, F, S1, Fh, rows, d.n3, ilog2(d.n3), tw.t3);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_strided<T>(s, nin, S1, Fh, d.n2, nh, d.n1, nh, sx1, -1, tw.t2);
+  if (e != hipSuccess) return e;
+  cplx<T>* So = op == SpecOp::Grad ? S2 : S1;
+  bool done = false;
+  if (op == SpecOp::Scale)
+    e = nf == 1 ? launch_x1_op<T, 0, 1>(s, d, S1, So, a, tw.t1, done) : launch_x1_op<T, 0, 3>(s, d, S1, So, a, tw.t1, done);
+  else if (op == SpecOp::Grad)
+    e = launch_x1_op<T, 1, 1>(s, d, S1, So, a, tw.t1, done);
+  else
+    e = launch_x1_op<T, 2, 3>(s, d, S1, So, a, tw.t1, done);
+  if (e != hipSuccess) return e;
+  if (!done) {  // the lines do not fit the LDS: transform, operator and inverse as three passes
+    e = launch_strided<T>(s, nin, S1, Fh, d.n1, d.n2 * nh, 1, sx1, 0, -1, tw.t1);
+    if (e != hipSuccess) return e;
+    if (op == SpecOp::Scale)
+      e = spec_symbol<T>(s, d, nf, a, S1);
+    else if (op == SpecOp::Grad)
+      e = spec_grad<T>(s, d, S1, S2);
+    else
+      e = spec_div<T>(s, d, S1);
+    if (e != hipSuccess) return e;
+    e = launch_strided<T>(s, nout, So, Fh, d.n1, d.n2 * nh, 1, sx1, 0, +1, tw.t1);
+    if (e != hipSuccess) return e;
+  }
+  e = launch_strided<T>(s, nout, So, Fh, d.n2, nh, d.n1, nh, sx1, +1, tw.t2);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fft_c2r_rows<T, TF>), dim3((rows + RL - 1) / RL, 1, nout), dim3(kThreads),
+                     size_t(d.n3) * RL * sizeof(cplx<T>), s, So, Fh, out, F, rows, d.n3, ilog2(d.n3),
+                     T(1.0 / double(F)), tw.t3);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t spec_symbol(hipStream_t s, const Dims& d, int nf, SymArgs a, cplx<T>* S) {
   hipLaunchKernelGGL(k_symbol<T>, dim3(blocks_for(d.Fh())), dim3(kThreads), 0, s, d, nf, a, S);
@@ -888,6 +1067,8 @@ hipError_t convert(hipStream_t s, size_t n, const A* in, B* out) {
 }
 template hipError_t convert<float, double>(hipStream_t, size_t, const float*, double*);
 template hipError_t convert<double, float>(hipStream_t, size_t, const double*, float*);
+template hipError_t spec_apply<double, float>(hipStream_t, const Dims&, const Twiddles<double>&, SpecOp, int, SymArgs,
+                                              const float*, float*, cplx<double>*, cplx<double>*);
 
 int reduce_blocks(size_t n) { return int(std::min<size_t>(blocks_for(n), kMaxReduceBlocks)); }
 
@@ -905,6 +1086,8 @@ hipError_t reduce(hipStream_t s, size_t n, int mode, const T* a, const T* b, dou
   template hipError_t fft_forward<T>(hipStream_t, const Dims&, const Twiddles<T>&, int, const T*, cplx<T>*);      \
   template hipError_t fft_inverse<T>(hipStream_t, const Dims&, const Twiddles<T>&, int, cplx<T>*, T*);            \
   template hipError_t spec_symbol<T>(hipStream_t, const Dims&, int, SymArgs, cplx<T>*);                          \
+  template hipError_t spec_apply<T, T>(hipStream_t, const Dims&, const Twiddles<T>&, SpecOp, int, SymArgs, const T*, \
+                                       T*, cplx<T>*, cplx<T>*);                                                  \
   template hipError_t spline_coefficients<T>(hipStream_t, const Dims&, int, const T*, T*);                       \
   template hipError_t spec_grad<T>(hipStream_t, const Dims&, const cplx<T>*, cplx<T>*);                          \
   template hipError_t spec_restrict<T>(hipStream_t, const Dims&, const Dims&, int, const cplx<T>*, cplx<T>*);    \

@@ -56,6 +56,16 @@ struct SymArgs {
   double beta = 1.0;
   int proj = 0;  // nf = 3 only: apply the Leray projection b - k (k . b) / |k|^2 first (odd-order k)
 };
+// out = op(in) through the transform: Scale (nf = 1 or 3 fields: the symbol, with the Leray
+// projection first when a.proj and nf = 3), Grad (one field in, its three derivatives out), Div
+// (three fields in, one out).  The forward pass along x1, the operator and the inverse pass along
+// x1 run in one LDS kernel where the lines fit.  TF: the fields' element type (float fields
+// through an FP64 transform for the mixed context's beta A).  S1, S2: 3 Fh spectra each.
+enum class SpecOp : int { Scale = 0, Grad = 1, Div = 2 };
+template <typename T, typename TF>
+hipError_t spec_apply(hipStream_t s, const Dims& d, const Twiddles<T>& tw, SpecOp op, int nf, SymArgs a, const TF* in,
+                      TF* out, cplx<T>* S1, cplx<T>* S2);
+
 // S[c] *= symbol for c < nf (nf = 1 or 3), in place.
 template <typename T>
 hipError_t spec_symbol(hipStream_t s, const Dims& d, int nf, SymArgs a, cplx<T>* S);

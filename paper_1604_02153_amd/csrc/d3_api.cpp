@@ -381,7 +381,6 @@ class Ctx final : public Base {
       twd1_ = take<cplx<double>>(d_.n1 / 2);
       twd2_ = take<cplx<double>>(d_.n2 / 2);
       twd3_ = take<cplx<double>>(d_.n3 / 2);
-      xd_ = take<double>(V);
       Sd_ = take<cplx<double>>(3 * Fh_);
     }
     partial_ = take<double>(size_t(reduce_blocks(V)));
@@ -434,12 +433,7 @@ class Ctx final : public Base {
   void reg_apply(const T* x, T* out, double beta) {
     const SymArgs a{Sym::Reg, p_.reg, beta, 0};
     if constexpr (std::is_same_v<T, float>) {
-      const size_t V = 3 * F_;
-      D3CHK((convert<float, double>(s_, V, x, xd_)));
-      D3CHK(fft_forward<double>(s_, d_, twd_, 3, xd_, Sd_));
-      D3CHK(spec_symbol<double>(s_, d_, 3, a, Sd_));
-      D3CHK(fft_inverse<double>(s_, d_, twd_, 3, Sd_, xd_));
-      D3CHK((convert<double, float>(s_, V, xd_, out)));
+      D3CHK((spec_apply<double, float>(s_, d_, twd_, SpecOp::Scale, 3, a, x, out, Sd_, Sd_)));
     } else {
       apply_symbol(x, out, a);
     }
@@ -459,21 +453,15 @@ class Ctx final : public Base {
 
   // out = symbol(in) for a vector field (with the Leray projection first when a.proj)
   void apply_symbol(const T* in, T* out, SymArgs a) {
-    D3CHK(fft_forward<T>(s_, d_, tw_, 3, in, S1_));
-    D3CHK(spec_symbol<T>(s_, d_, 3, a, S1_));
-    D3CHK(fft_inverse<T>(s_, d_, tw_, 3, S1_, out));
+    D3CHK((spec_apply<T, T>(s_, d_, tw_, SpecOp::Scale, 3, a, in, out, S1_, S2_)));
   }
 
   void gradient_of(const T* f, T* g) {
-    D3CHK(fft_forward<T>(s_, d_, tw_, 1, f, S1_));
-    D3CHK(spec_grad<T>(s_, d_, S1_, S2_));
-    D3CHK(fft_inverse<T>(s_, d_, tw_, 3, S2_, g));
+    D3CHK((spec_apply<T, T>(s_, d_, tw_, SpecOp::Grad, 1, SymArgs{}, f, g, S1_, S2_)));
   }
 
   void divergence_of(const T* v, T* out) {
-    D3CHK(fft_forward<T>(s_, d_, tw_, 3, v, S1_));
-    D3CHK(spec_div<T>(s_, d_, S1_));
-    D3CHK(fft_inverse<T>(s_, d_, tw_, 1, S1_, out));
+    D3CHK((spec_apply<T, T>(s_, d_, tw_, SpecOp::Div, 3, SymArgs{}, v, out, S1_, S2_)));
   }
 
   // characteristics and adjoint factor of v (copied into v_)
@@ -769,7 +757,7 @@ class Ctx final : public Base {
   cplx<T>*S1_ = nullptr, *S2_ = nullptr;
   Twiddles<double> twd_;
   cplx<double>*twd1_ = nullptr, *twd2_ = nullptr, *twd3_ = nullptr, *Sd_ = nullptr;
-  double* xd_ = nullptr;
+
   double *partial_ = nullptr, *dres_ = nullptr;
 };
 
