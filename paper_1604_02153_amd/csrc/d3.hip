@@ -777,12 +777,6 @@ __global__ void __launch_bounds__(kThreads) k_axpby(size_t n, T a, const T* __re
   }
 }
 
-template <typename A, typename B>
-__global__ void __launch_bounds__(kThreads) k_convert(size_t n, const A* __restrict__ in, B* __restrict__ out) {
-  for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads)
-    out[i] = B(in[i]);
-}
-
 constexpr int kMaxReduceBlocks = 1024;
 
 template <typename T>
@@ -1059,14 +1053,6 @@ hipError_t axpby(hipStream_t s, size_t n, double a, const T* x, double b, const 
   return hipGetLastError();
 }
 
-template <typename A, typename B>
-hipError_t convert(hipStream_t s, size_t n, const A* in, B* out) {
-  const unsigned nb = std::min<size_t>(blocks_for(n), 8192);
-  hipLaunchKernelGGL((k_convert<A, B>), dim3(nb), dim3(kThreads), 0, s, n, in, out);
-  return hipGetLastError();
-}
-template hipError_t convert<float, double>(hipStream_t, size_t, const float*, double*);
-template hipError_t convert<double, float>(hipStream_t, size_t, const double*, float*);
 template hipError_t spec_apply<double, float>(hipStream_t, const Dims&, const Twiddles<double>&, SpecOp, int, SymArgs,
                                               const float*, float*, cplx<double>*, cplx<double>*);
 

@@ -139,10 +139,6 @@ hipError_t adjoint_start(hipStream_t s, const Dims& d, double w, const T* mR, co
 template <typename T>
 hipError_t incstate_start(hipStream_t s, const Dims& d, double ht, const T* vt, const T* gm, T* q);
 
-// out = in converted to the other precision, n values
-template <typename A, typename B>
-hipError_t convert(hipStream_t s, size_t n, const A* in, B* out);
-
 // out = a x + b y over n values (scalars cast to T; x or y may be null for a zero term)
 template <typename T>
 hipError_t axpby(hipStream_t s, size_t n, double a, const T* x, double b, const T* y, T* out);
