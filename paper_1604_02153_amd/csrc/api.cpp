@@ -230,7 +230,6 @@ struct Context {
   void* tw64_col = nullptr;
   double* v64[2] = {};
   double* bAv64[2] = {};
-  double* vt64 = nullptr;  // mixed context: FP64 copy of a matvec's input, then beta A of it
   cplx<double>* S64a = nullptr;
   cplx<double>* S64b = nullptr;
   // captured HIP graphs of the matvec and of the preconditioner, keyed by (operation, input,
@@ -376,7 +375,7 @@ struct Context {
     partial_half = size_t(B) * (std::max(reduce_blocks(2 * F), tiles) * 4 + 64);
     size_t bytes = level_bytes(p.n1, p.n2, p.nt, B) + (two_level ? level_bytes(p.n1 / 2, p.n2 / 2, p.nt, B) : 0);
     bytes += (2 * partial_half + 8 * B + 16 * B + 2 * 64 * B + B) * sizeof(double) + 5 * B * sizeof(int) + 8192;
-    bytes += B * (5 * 2 * F * sizeof(double) + 2 * 2 * size_t(p.n1) * spec_stride(p.n2) * sizeof(cplx<double>)) +
+    bytes += B * (4 * 2 * F * sizeof(double) + 2 * 2 * size_t(p.n1) * spec_stride(p.n2) * sizeof(cplx<double>)) +
              2 * (p.n1 + p.n2) * sizeof(cplx<double>) + 16 * 256;
     bytes += B * (2 * F * sizeof(T) + sizeof(float)) + 2 * 256;
     if (full_newton) bytes += B * size_t(6 * p.nt + 5) * F * sizeof(T) + 6 * 256;
@@ -426,7 +425,6 @@ struct Context {
       v64[sl] = arena.take<double>(B * 2 * F);
       bAv64[sl] = arena.take<double>(B * 2 * F);
     }
-    if (std::is_same_v<T, float>) vt64 = arena.take<double>(B * 2 * F);
     S64a = arena.take<cplx<double>>(B * 2 * sg64.spec());
     S64b = arena.take<cplx<double>>(B * 2 * sg64.spec());
     learned_v = arena.take<T>(B * 2 * F);
@@ -958,10 +956,8 @@ struct Context {
   void hessian(Level<T>& lv, const T* vt, T* out, const int* mk) {
     transport(lv, vt, mk);
     if (leray) HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, symK(Symbol::One), 2, lv.bt, lv.bt, nullptr, lv.S1, lv.S2));
-    if (std::is_same_v<T, float> && &lv == &fine) {  // sg64 and vt64 belong to the fine grid
-      HIPCHK(cast_back<T>(stream, B * 2 * lv.F, vt, vt64));
-      HIPCHK(spec_scale<double>(stream, sg64, B, mk, sym(Symbol::Reg), 2, vt64, vt64, nullptr, S64a, S64b));
-      HIPCHK(add_mixed<T>(stream, B, 2 * lv.F, vt64, lv.bt, out, mk));
+    if (std::is_same_v<T, float> && &lv == &fine) {  // sg64 belongs to the fine grid
+      HIPCHK((spec_scale<double, T>(stream, sg64, B, mk, sym(Symbol::Reg), 2, vt, out, lv.bt, S64a, S64b)));
     } else {
       HIPCHK(spec_scale<T>(stream, lv.sg, B, mk, sym(Symbol::Reg), 2, vt, out, lv.bt, lv.S1, lv.S2));
     }

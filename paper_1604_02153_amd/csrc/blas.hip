@@ -161,16 +161,6 @@ __global__ void k_xpay_mixed(size_t n, const double* __restrict__ xb, double a, 
 }
 
 template <typename T>
-__global__ void k_add_mixed(size_t n, const double* __restrict__ xb, const T* __restrict__ yb, T* __restrict__ ob,
-                            const int* mask) {
-  const int z = blockIdx.y;
-  if (mask && !mask[z]) return;
-  const size_t off = size_t(z) * n;
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
-    ob[off + i] = T(xb[off + i] + double(yb[off + i]));
-}
-
-template <typename T>
 __global__ void k_masked_copy(size_t n, const T* __restrict__ src, long long ss, T* __restrict__ dst, long long ds,
                               const int* mask) {
   const int z = blockIdx.y;
@@ -405,12 +395,6 @@ hipError_t xpay_mixed(hipStream_t s, int batch, size_t n, const double* x, doubl
 }
 
 template <typename T>
-hipError_t add_mixed(hipStream_t s, int batch, size_t n, const double* x, const T* y, T* out, const int* mask) {
-  hipLaunchKernelGGL(k_add_mixed<T>, dim3(grid_for(n), batch), dim3(kThreads), 0, s, n, x, y, out, mask);
-  return hipGetLastError();
-}
-
-template <typename T>
 hipError_t masked_copy(hipStream_t s, int batch, size_t n, const T* src, long long src_stride, T* dst,
                        long long dst_stride, const int* mask) {
   hipLaunchKernelGGL(k_masked_copy<T>, dim3(grid_for(n), batch), dim3(kThreads), 0, s, n, src, src_stride, dst,
@@ -464,7 +448,6 @@ hipError_t sub_strided(hipStream_t s, int batch, size_t n, const T* x, long long
   template hipError_t xpay_mixed<T>(hipStream_t, int, size_t, const double*, double, const double*,       \
                                     const T*, double*, const int*);                                       \
   template hipError_t masked_copy<T>(hipStream_t, int, size_t, const T*, long long, T*, long long, const int*); \
-  template hipError_t add_mixed<T>(hipStream_t, int, size_t, const double*, const T*, T*, const int*);      \
   template hipError_t fn_products<T>(hipStream_t, int, size_t, int, const T*, const T*, T*);               \
   template hipError_t fn_source<T>(hipStream_t, int, size_t, int, double, const T*, const T*, T*);         \
   template hipError_t fn_accumulate<T>(hipStream_t, int, size_t, int, double, const T*, const T*, T*,      \

@@ -67,10 +67,17 @@ size_t spec_lds_bytes(int n1, int n2);
 // field() elements) and items follow each other.  'active' (optional, [batch]) skips items.
 // Scratch spectra: S1, S2 hold batch * (fields per item) * spec() complex.
 //
-// out = symbol(in) + (add ? add : 0), nf = 1 or 2 fields per item.
-template <typename T>
+// out = symbol(in) + (add ? add : 0), nf = 1 or 2 fields per item.  TF is the fields' element
+// type: float fields through the FP64 transform (T = double) read FP32 input, form the symbol and
+// the sum in FP64 and round once on the store (the mixed context's beta A); otherwise TF = T.
+// (the addend takes no part in deducing TF, so that it may be passed as nullptr)
+template <typename U>
+struct NoDeduce {
+  using type = U;
+};
+template <typename T, typename TF = T>
 hipError_t spec_scale(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, SymbolParams sym, int nf,
-                      const T* in, T* out, const T* add, cplx<T>* S1, cplx<T>* S2);
+                      const TF* in, TF* out, const typename NoDeduce<TF>::type* add, cplx<T>* S1, cplx<T>* S2);
 
 // out1 = sym1(in), out2 = sym2(in) for vector fields (two fields per item): one forward transform.
 // S1 >= 2 batch spec(), S2 >= 4 batch spec().
@@ -257,9 +264,6 @@ hipError_t cast_back(hipStream_t s, size_t n, const T* x, double* y);
 template <typename T>
 hipError_t xpay_mixed(hipStream_t s, int batch, size_t n, const double* x, double a, const double* ad, const T* y,
                       double* z, const int* mask);
-// per item z with mask[z] != 0 (mask optional): out = T(x + y) over n elements, the sum in FP64
-template <typename T>
-hipError_t add_mixed(hipStream_t s, int batch, size_t n, const double* x, const T* y, T* out, const int* mask);
 // per item z with mask[z] != 0 (mask optional): n elements from src + z src_stride to
 // dst + z dst_stride
 template <typename T>

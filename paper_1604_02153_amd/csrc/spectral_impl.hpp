@@ -251,8 +251,8 @@ struct OutFields {
 
 // Forward row pass: fields (2q, 2q+1) of 'in' (batch item z) packed as one complex row, FFT along
 // x2, unpacked into half spectra S[z][f][x1][k2] (f = 2q, 2q+1; k2 in [0, n2/2]).
-template <typename T>
-__global__ void __launch_bounds__(256) k_row_fwd(RealFields<T> in, cplx<T>* __restrict__ S, int n1, int n2,
+template <typename T, typename TF>
+__global__ void __launch_bounds__(256) k_row_fwd(RealFields<TF> in, cplx<T>* __restrict__ S, int n1, int n2,
                                                  int rpb, FFTPlanDev pl) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -266,13 +266,13 @@ __global__ void __launch_bounds__(256) k_row_fwd(RealFields<T> in, cplx<T>* __re
   const int fa = 2 * q, fb = 2 * q + 1;
   if (in.active && !in.active[z / in.item_div]) return;
   load_twiddles<T>(tw, pl, threadIdx.x, blockDim.x);
-  const T* A = in.p[fa] + z * in.bstride[fa];
-  const T* B = fb < in.count ? in.p[fb] + z * in.bstride[fb] : nullptr;
+  const TF* A = in.p[fa] + z * in.bstride[fa];
+  const TF* B = fb < in.count ? in.p[fb] + z * in.bstride[fb] : nullptr;
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int idx = tid; idx < rows * n2; idx += nthr) {
     const int r = idx / n2, c = idx - r * n2;
     const size_t gi = size_t(r0 + r) * n2 + c;
-    buf[r * bs + swz(c)] = {A[gi], B ? B[gi] : T(0)};
+    buf[r * bs + swz(c)] = {T(A[gi]), B ? T(B[gi]) : T(0)};
   }
   __syncthreads();
   fft_lds<T>(buf, tw, pl, rows, bs, -1, tid, nthr);
@@ -291,8 +291,8 @@ __global__ void __launch_bounds__(256) k_row_fwd(RealFields<T> in, cplx<T>* __re
 }
 
 // Inverse row pass: half spectra (2q, 2q+1) of S[z] -> real fields out (plus optional addend).
-template <typename T>
-__global__ void __launch_bounds__(256) k_row_inv(const cplx<T>* __restrict__ S, int nspec, OutFields<T> out,
+template <typename T, typename TF>
+__global__ void __launch_bounds__(256) k_row_inv(const cplx<T>* __restrict__ S, int nspec, OutFields<TF> out,
                                                  int n1, int n2, int rpb, FFTPlanDev pl) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -331,16 +331,16 @@ __global__ void __launch_bounds__(256) k_row_inv(const cplx<T>* __restrict__ S, 
   }
   __syncthreads();
   fft_lds<T>(buf, tw, pl, rows, bs, +1, tid, nthr);
-  T* OA = out.p[fa] + z * out.bstride[fa];
-  T* OB = hasb ? out.p[fb] + z * out.bstride[fb] : nullptr;
-  const T* AA = out.add[fa] ? out.add[fa] + z * out.bstride[fa] : nullptr;
-  const T* AB = hasb && out.add[fb] ? out.add[fb] + z * out.bstride[fb] : nullptr;
+  TF* OA = out.p[fa] + z * out.bstride[fa];
+  TF* OB = hasb ? out.p[fb] + z * out.bstride[fb] : nullptr;
+  const TF* AA = out.add[fa] ? out.add[fa] + z * out.bstride[fa] : nullptr;
+  const TF* AB = hasb && out.add[fb] ? out.add[fb] + z * out.bstride[fb] : nullptr;
   for (int idx = tid; idx < rows * n2; idx += nthr) {
     const int r = idx / n2, c = idx - r * n2;
     const size_t gi = size_t(r0 + r) * n2 + c;
     const cplx<T> val = buf[r * bs + swz(c)];
-    OA[gi] = AA ? val.x + AA[gi] : val.x;
-    if (OB) OB[gi] = AB ? val.y + AB[gi] : val.y;
+    OA[gi] = TF(AA ? val.x + T(AA[gi]) : val.x);
+    if (OB) OB[gi] = TF(AB ? val.y + T(AB[gi]) : val.y);
   }
 }
 
@@ -566,8 +566,8 @@ struct FRow {
 
 // Forward row pass: fields (2q, 2q+1) of item z packed as one complex row, transformed along x2,
 // unpacked into the transposed half spectra of fields 2q and 2q+1.
-template <typename T, int N>
-__global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_fwd(RealFields<T> in, cplx<T>* __restrict__ S, int n1,
+template <typename T, int N, typename TF>
+__global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_fwd(RealFields<TF> in, cplx<T>* __restrict__ S, int n1,
                                                                    const cplx<T>* __restrict__ roots) {
   using PL = WPlan<N>;
   using RW = FRow<T, N>;
@@ -580,8 +580,8 @@ __global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_fwd(RealFields<
   if (in.active && !in.active[z / in.item_div]) return;
   const int fa = 2 * blockIdx.y, fb = fa + 1;
   const int r0 = blockIdx.x * R;
-  const T* A = in.p[fa] + z * in.bstride[fa];
-  const T* B = fb < in.count ? in.p[fb] + z * in.bstride[fb] : nullptr;
+  const TF* A = in.p[fa] + z * in.bstride[fa];
+  const TF* B = fb < in.count ? in.p[fb] + z * in.bstride[fb] : nullptr;
   const int tid = threadIdx.x, lane = tid & 63;
   const int lp = lane % PL::LPT;
   const int row = (tid >> 6) * PL::T + lane / PL::LPT;
@@ -590,7 +590,7 @@ __global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_fwd(RealFields<
 #pragma unroll
   for (int m = 0; m < PL::E; ++m) {
     const int e = wmap<N, r1>(lp, m);
-    x[m] = {A[gb + e], B ? B[gb + e] : T(0)};
+    x[m] = {T(A[gb + e]), B ? T(B[gb + e]) : T(0)};
   }
   fill_twiddles<T, N, false>(rt, roots, tid, RW::kThreads);
   __syncthreads();
@@ -616,9 +616,9 @@ __global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_fwd(RealFields<
 // Inverse row pass: transposed half spectra (2q, 2q+1) of item z -> real fields (plus addend).
 // With CHEB the four fields (S Q y, S^2 Q y) are not stored: they complete the Chebyshev step in
 // place (pair 0 updates r, d, x; pair 1 updates u, y; the arithmetic of cheb_step).
-template <typename T, int N, bool CHEB>
+template <typename T, int N, bool CHEB, typename TF>
 __global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_inv(const cplx<T>* __restrict__ S, int nspec,
-                                                                   OutFields<T> out, int n1,
+                                                                   OutFields<TF> out, int n1,
                                                                    const cplx<T>* __restrict__ roots,
                                                                    ChebTail<T> ct) {
   using PL = WPlan<N>;
@@ -707,25 +707,25 @@ __global__ void __launch_bounds__((FRow<T, N>::kThreads)) k_frow_inv(const cplx<
     }
     return;
   }
-  T* OA = out.p[fa] + z * out.bstride[fa] + gb;
-  T* OB = hasb ? out.p[fb] + z * out.bstride[fb] + gb : nullptr;
-  const T* AA = out.add[fa] ? out.add[fa] + z * out.bstride[fa] + gb : nullptr;
-  const T* AB = hasb && out.add[fb] ? out.add[fb] + z * out.bstride[fb] + gb : nullptr;
+  TF* OA = out.p[fa] + z * out.bstride[fa] + gb;
+  TF* OB = hasb ? out.p[fb] + z * out.bstride[fb] + gb : nullptr;
+  const TF* AA = out.add[fa] ? out.add[fa] + z * out.bstride[fa] + gb : nullptr;
+  const TF* AB = hasb && out.add[fb] ? out.add[fb] + z * out.bstride[fb] + gb : nullptr;
   // addends loaded in full before the first store (the outputs may alias nothing, but the
   // compiler cannot know that, and would otherwise wait for each load in turn)
   if (AA) {
 #pragma unroll
-    for (int m = 0; m < PL::E; ++m) x[m].x += AA[wmap<N, rL>(lp, m)];
+    for (int m = 0; m < PL::E; ++m) x[m].x += T(AA[wmap<N, rL>(lp, m)]);
   }
   if (AB) {
 #pragma unroll
-    for (int m = 0; m < PL::E; ++m) x[m].y += AB[wmap<N, rL>(lp, m)];
+    for (int m = 0; m < PL::E; ++m) x[m].y += T(AB[wmap<N, rL>(lp, m)]);
   }
 #pragma unroll
   for (int m = 0; m < PL::E; ++m) {
     const int e = wmap<N, rL>(lp, m);
-    OA[e] = x[m].x;
-    if (OB) OB[e] = x[m].y;
+    OA[e] = TF(x[m].x);
+    if (OB) OB[e] = TF(x[m].y);
   }
 }
 
@@ -1159,28 +1159,28 @@ void row_config(int n2, int& nthr, int& rpb) {
   while (rpb * n2 > nthr * kMaxE) --rpb;
 }
 
-template <typename T>
-hipError_t launch_row_fwd(hipStream_t s, const SpecGrid<T>& g, RealFields<T> in, int batch, cplx<T>* S) {
+template <typename T, typename TF>
+hipError_t launch_row_fwd(hipStream_t s, const SpecGrid<T>& g, RealFields<TF> in, int batch, cplx<T>* S) {
   int nthr, rpb;
   row_config<T>(g.n2, nthr, rpb);
   dim3 grid((g.n1 + rpb - 1) / rpb, (in.count + 1) / 2, batch);
   size_t lds = (size_t(rpb) * lds_stride(g.n2) + g.n2) * sizeof(cplx<T>);
   static std::atomic<size_t> allowed{0};
-  RET_IF(allow_lds(k_row_fwd<T>, lds, allowed));
-  hipLaunchKernelGGL(k_row_fwd<T>, grid, dim3(nthr), lds, s, in, S, g.n1, g.n2, rpb, g.row);
+  RET_IF(allow_lds(k_row_fwd<T, TF>, lds, allowed));
+  hipLaunchKernelGGL((k_row_fwd<T, TF>), grid, dim3(nthr), lds, s, in, S, g.n1, g.n2, rpb, g.row);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_row_inv(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* S, int nspec, OutFields<T> out,
+template <typename T, typename TF>
+hipError_t launch_row_inv(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* S, int nspec, OutFields<TF> out,
                           int batch) {
   int nthr, rpb;
   row_config<T>(g.n2, nthr, rpb);
   dim3 grid((g.n1 + rpb - 1) / rpb, (out.count + 1) / 2, batch);
   size_t lds = (size_t(rpb) * lds_stride(g.n2) + g.n2) * sizeof(cplx<T>);
   static std::atomic<size_t> allowed{0};
-  RET_IF(allow_lds(k_row_inv<T>, lds, allowed));
-  hipLaunchKernelGGL(k_row_inv<T>, grid, dim3(nthr), lds, s, S, nspec, out, g.n1, g.n2, rpb, g.row);
+  RET_IF(allow_lds(k_row_inv<T, TF>, lds, allowed));
+  hipLaunchKernelGGL((k_row_inv<T, TF>), grid, dim3(nthr), lds, s, S, nspec, out, g.n1, g.n2, rpb, g.row);
   return hipGetLastError();
 }
 
@@ -1237,25 +1237,25 @@ bool fast_grid(const SpecGrid<T>& g) {
 
 #define SLNK_FAST_CASES(X) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
 
-template <typename T, int N>
-hipError_t launch_frow_fwd_n(hipStream_t s, const SpecGrid<T>& g, RealFields<T> in, int batch, cplx<T>* S) {
+template <typename T, int N, typename TF>
+hipError_t launch_frow_fwd_n(hipStream_t s, const SpecGrid<T>& g, RealFields<TF> in, int batch, cplx<T>* S) {
   using RW = FRow<T, N>;
   static std::atomic<size_t> allowed{0};
-  RET_IF(allow_lds(k_frow_fwd<T, N>, RW::kLds, allowed));
+  RET_IF(allow_lds(k_frow_fwd<T, N, TF>, RW::kLds, allowed));
   dim3 grid(g.n1 / RW::R, (in.count + 1) / 2, batch);
-  hipLaunchKernelGGL((k_frow_fwd<T, N>), grid, dim3(RW::kThreads), RW::kLds, s, in, S, g.n1,
+  hipLaunchKernelGGL((k_frow_fwd<T, N, TF>), grid, dim3(RW::kThreads), RW::kLds, s, in, S, g.n1,
                      static_cast<const cplx<T>*>(g.row.roots));
   return hipGetLastError();
 }
 
-template <typename T, int N, bool CHEB = false>
-hipError_t launch_frow_inv_n(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* S, int nspec, OutFields<T> out,
+template <typename T, int N, bool CHEB = false, typename TF = T>
+hipError_t launch_frow_inv_n(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* S, int nspec, OutFields<TF> out,
                              int batch, ChebTail<T> ct = {}) {
   using RW = FRow<T, N>;
   static std::atomic<size_t> allowed{0};
-  RET_IF(allow_lds(k_frow_inv<T, N, CHEB>, RW::kLds, allowed));
+  RET_IF(allow_lds(k_frow_inv<T, N, CHEB, TF>, RW::kLds, allowed));
   dim3 grid(g.n1 / RW::R, (out.count + 1) / 2, batch);
-  hipLaunchKernelGGL((k_frow_inv<T, N, CHEB>), grid, dim3(RW::kThreads), RW::kLds, s, S, nspec, out, g.n1,
+  hipLaunchKernelGGL((k_frow_inv<T, N, CHEB, TF>), grid, dim3(RW::kThreads), RW::kLds, s, S, nspec, out, g.n1,
                      static_cast<const cplx<T>*>(g.row.roots), ct);
   return hipGetLastError();
 }
@@ -1277,27 +1277,27 @@ hipError_t launch_fcol_n(hipStream_t s, const SpecGrid<T>& g, const cplx<T>* Sin
 }
 
 // Pass dispatch: wave-level passes (transposed spectra) when 'fast', else the generic ones.
-template <typename T>
-hipError_t row_fwd(bool fast, hipStream_t s, const SpecGrid<T>& g, RealFields<T> in, int batch, cplx<T>* S) {
-  if (!fast) return launch_row_fwd<T>(s, g, in, batch, S);
+template <typename T, typename TF>
+hipError_t row_fwd(bool fast, hipStream_t s, const SpecGrid<T>& g, RealFields<TF> in, int batch, cplx<T>* S) {
+  if (!fast) return launch_row_fwd<T, TF>(s, g, in, batch, S);
   switch (g.n2) {
 #define X(N) \
   case N:    \
-    return launch_frow_fwd_n<T, N>(s, g, in, batch, S);
+    return launch_frow_fwd_n<T, N, TF>(s, g, in, batch, S);
     SLNK_FAST_CASES(X)
 #undef X
   }
   return hipErrorInvalidValue;
 }
 
-template <typename T>
-hipError_t row_inv(bool fast, hipStream_t s, const SpecGrid<T>& g, const cplx<T>* S, int nspec, OutFields<T> out,
+template <typename T, typename TF>
+hipError_t row_inv(bool fast, hipStream_t s, const SpecGrid<T>& g, const cplx<T>* S, int nspec, OutFields<TF> out,
                    int batch) {
-  if (!fast) return launch_row_inv<T>(s, g, S, nspec, out, batch);
+  if (!fast) return launch_row_inv<T, TF>(s, g, S, nspec, out, batch);
   switch (g.n2) {
 #define X(N) \
   case N:    \
-    return launch_frow_inv_n<T, N>(s, g, S, nspec, out, batch);
+    return launch_frow_inv_n<T, N, false, TF>(s, g, S, nspec, out, batch);
     SLNK_FAST_CASES(X)
 #undef X
   }
@@ -1342,17 +1342,17 @@ size_t spec_lds_bytes(int n1, int n2) {
   return std::max(row, col);
 }
 
-template <typename T>
+template <typename T, typename TF>
 hipError_t spec_scale(hipStream_t s, const SpecGrid<T>& g, int batch, const int* active, SymbolParams sym, int nf,
-                      const T* in, T* out, const T* add, cplx<T>* S1, cplx<T>* S2) {
+                      const TF* in, TF* out, const typename NoDeduce<TF>::type* add, cplx<T>* S1, cplx<T>* S2) {
   const size_t F = g.field();
   const bool fast = fast_grid(g);
-  RealFields<T> rin{};
-  set_fields(rin, nf, const_cast<T*>(in), F, active);
-  OutFields<T> rout{};
+  RealFields<TF> rin{};
+  set_fields(rin, nf, const_cast<TF*>(in), F, active);
+  OutFields<TF> rout{};
   set_fields(rout, nf, out, F, active);
   for (int f = 0; f < nf; ++f) rout.add[f] = add ? add + f * F : nullptr;
-  RET_IF(row_fwd<T>(fast, s, g, rin, batch, S1));
+  RET_IF((row_fwd<T, TF>(fast, s, g, rin, batch, S1)));
   const double inv_n = 1.0 / double(F);
   if (nf == 1) {
     OpScale<T, 1> op{sym, g.n1, g.n2, inv_n};
@@ -1361,7 +1361,7 @@ hipError_t spec_scale(hipStream_t s, const SpecGrid<T>& g, int batch, const int*
     OpScale<T, 2> op{sym, g.n1, g.n2, inv_n};
     RET_IF(col<0>(fast, s, g, S1, S2, op, batch, active));
   }
-  return row_inv<T>(fast, s, g, S2, nf, rout, batch);
+  return row_inv<T, TF>(fast, s, g, S2, nf, rout, batch);
 }
 
 template <typename T>
@@ -1498,7 +1498,7 @@ hipError_t spec_restrict(hipStream_t s, const SpecGrid<T>& g, const SpecGrid<T>&
   const bool fast = fast_grid(g) && fast_grid(gc);
   RealFields<T> rin{};
   set_fields(rin, nf, const_cast<T*>(in), F, active);
-  RET_IF(row_fwd<T>(fast, s, g, rin, batch, S1));
+  RET_IF((row_fwd<T>(fast, s, g, rin, batch, S1)));
   const double inv_n = 1.0 / double(F);
   // the fine column pass only writes the coarse k-space (and keeps the fine spectrum if asked)
   if (nf == 1) {
@@ -1540,8 +1540,8 @@ hipError_t spec_prolong_combine(hipStream_t s, const SpecGrid<T>& g, const SpecG
 
 #define INST(T)                                                                                                 \
   template size_t spec_lds_bytes<T>(int, int);                                                                  \
-  template hipError_t spec_scale<T>(hipStream_t, const SpecGrid<T>&, int, const int*, SymbolParams, int, const T*, \
-                                    T*, const T*, cplx<T>*, cplx<T>*);                                          \
+  template hipError_t spec_scale<T, T>(hipStream_t, const SpecGrid<T>&, int, const int*, SymbolParams, int,      \
+                                       const T*, T*, const T*, cplx<T>*, cplx<T>*);                             \
   template hipError_t spec_grad<T>(hipStream_t, const SpecGrid<T>&, int, const T*, T*, cplx<T>*, cplx<T>*);     \
   template hipError_t spec_scale2<T>(hipStream_t, const SpecGrid<T>&, int, const int*, SymbolParams, SymbolParams, \
                                      const T*, T*, T*, cplx<T>*, cplx<T>*);                                     \
