@@ -40,6 +40,15 @@ __host__ __device__ __forceinline__ int wrap_index(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// The same with one add or subtract for -n <= i < 2n (stencil footprints on grids wider than
+// them), the division only otherwise: an integer division costs a few dozen instructions.
+__host__ __device__ __forceinline__ int wrap_near(int i, int n) {
+  i += i < 0 ? n : 0;
+  i -= i >= n ? n : 0;
+  if (unsigned(i) >= unsigned(n)) i = wrap_index(i, n);
+  return i;
+}
+
 // row stride (complex elements) of a half spectrum [n1][n2/2 + 1]: padded to a multiple of 16 so
 // that every row starts on a 128-byte boundary (FP32) and the strided column passes move whole
 // aligned segments

@@ -528,8 +528,8 @@ __device__ T interp3(const T* __restrict__ c, const Dims& d, T s1, T s2, T s3) {
   bspline_w(s1 - f1, w1);
   bspline_w(s2 - f2, w2);
   bspline_w(s3 - f3, w3);
-  const int b1 = wrap_index(int(f1) - 1, d.n1), b2 = wrap_index(int(f2) - 1, d.n2);
-  const int b3 = wrap_index(int(f3) - 1, d.n3);
+  const int b1 = wrap_near(int(f1) - 1, d.n1), b2 = wrap_near(int(f2) - 1, d.n2);
+  const int b3 = wrap_near(int(f3) - 1, d.n3);
   int p[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) p[k] = b3 + k >= d.n3 ? b3 + k - d.n3 : b3 + k;

@@ -85,15 +85,20 @@ __device__ __forceinline__ void xcd_tile(int& ty, int& tx) {
   tx = t - ty * gridDim.x;
 }
 
+// cubic B-spline weights of the four stencil nodes at fractional offset t in [0, 1)
+// (products with 1/6 rather than divisions: a correctly rounded division costs about ten
+// instructions, and the weights of every departure point are formed in the step's critical path)
 template <typename T>
 __device__ __forceinline__ void bspline_w(T t, T* w) {
+  const T c6 = T(1.0 / 6.0);
   const T t2 = t * t, t3 = t2 * t;
   const T s = T(1) - t;
-  w[0] = s * s * s / T(6);
-  w[1] = (T(3) * t3 - T(6) * t2 + T(4)) / T(6);
-  w[2] = (T(-3) * t3 + T(3) * t2 + T(3) * t + T(1)) / T(6);
-  w[3] = t3 / T(6);
+  w[0] = s * s * s * c6;
+  w[1] = (T(3) * t3 - T(6) * t2 + T(4)) * c6;
+  w[2] = (T(-3) * t3 + T(3) * t2 + T(3) * t + T(1)) * c6;
+  w[3] = t3 * c6;
 }
+
 
 // Spline value at (s1, s2) (in cells) from a global coefficient field, periodic.  The stencil's
 // first row and column are wrapped once (a division only for departure points outside the
@@ -244,7 +249,7 @@ __device__ __forceinline__ void stage_batched(const StepArgs<T>& a, T* A, int P,
 #pragma unroll
   for (int i = 0; i < CHR; ++i) {
     const int r = min(ty + TY * i, P - 1);
-    const size_t rowoff = size_t(wrap_index(ry + r, a.n1)) * a.n2;
+    const size_t rowoff = size_t(wrap_near(ry + r, a.n1)) * a.n2;
 #pragma unroll
     for (int k = 0; k < CHC; ++k) v[i][k] = load_src<T, KIND, FIRST>(a, rowoff + colw[k]);
   }
@@ -259,60 +264,37 @@ __device__ __forceinline__ void stage_batched(const StepArgs<T>& a, T* A, int P,
   }
 }
 
-// Stage the transported field over the rows [y0 - lo - K, y0 - lo + G + K) (and likewise the
-// columns) and filter it into the B-spline coefficients of the inner G x G region, which starts
-// at global node (y0 - lo, x0 - lo) and is left at LDS offset 0 of 'A'.  The step kernel uses
-// lo = D + 1, G = 16 + 2D + 3 (the stencil footprint of displacements |d| <= D); the
-// coefficient-only kernel uses lo = 0, G = 16.
+// Prefilter of a P x P block of staged values A (row stride P, P = G + 2K) into the B-spline
+// coefficients of its inner G x G region, left at offset 0 of A (row stride G).
 // LDS layout: A = P x P staged values (later the G x G coefficients), R words of slack (zero), then
-// B1 = (P + R) x G row-filtered values (the last R rows zero).  Each filter pass gives a thread R consecutive outputs
-// from a register window of R + 2K inputs; consecutive threads take consecutive rows (row pass)
-// or columns (column pass), so the window loads do not conflict across LDS banks.
-template <typename T, int KIND, bool FIRST, int TY>
-__device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, int y0, int x0, int lo, int G) {
+// B1 = (P + R) x G row-filtered values (the last R rows zero).  Each filter pass gives a thread R
+// consecutive outputs from a register window of R + 2K inputs; consecutive threads take
+// consecutive rows (row pass) or columns (column pass), so the window loads do not conflict
+// across LDS banks.  The last window of a row (column) reaches up to R - 1 values past the
+// footprint: into the next staged row, or into the slack words after A and the extra rows of B1,
+// which zero_filter_slack clears (before the barrier that ends the staging).  The recursive
+// filter carries those values into the valid outputs (multiplied by taps that cancel exactly), so
+// they must be finite.
+template <typename T>
+__device__ __forceinline__ void zero_filter_slack(T* A, int P, int G, int tid, int nth) {
+  constexpr int R = FilterTaps<T>::R;
+  T* B1 = A + P * P + R;
+  for (int i = tid; i < R; i += nth) A[P * P + i] = T(0);
+  for (int i = tid; i < R * G; i += nth) B1[P * G + i] = T(0);
+}
+
+template <typename T, int NTH>
+__device__ __forceinline__ void filter_coefficients(T* A, int P, int G, int tid) {
   constexpr int K = FilterTaps<T>::K;
   constexpr int R = FilterTaps<T>::R;
-  const int P = G + 2 * K;
   T* B1 = A + P * P + R;
   T* C = A;
-  const int n1 = a.n1, n2 = a.n2;
-  const int ry = y0 - lo - K, rx = x0 - lo - K;
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  const int tid = ty * kTile + tx;
-  constexpr int NTH = kTile * TY;
-  // The last window of a row (column) reaches up to R - 1 values past the footprint: into the next
-  // staged row, or into the R slack words after A and the R extra rows of B1, which are zeroed
-  // here.  The recursive filter carries those values into the valid outputs (multiplied by taps
-  // that cancel exactly), so they must be finite.
-  for (int i = tid; i < R; i += NTH) A[P * P + i] = T(0);
-  for (int i = tid; i < R * G; i += NTH) B1[P * G + i] = T(0);
-  // 1. stage (periodic wrap), rows ty + TY i, columns tx + 16 k
-  int colw[kMaxChunks];
-#pragma unroll
-  for (int k = 0; k < kMaxChunks; ++k) {
-    const int c = tx + kTile * k;
-    colw[k] = c < P ? wrap_index(rx + c, n2) : 0;
-  }
-  if (P <= 4 * kTile) {
-    stage_batched<T, KIND, FIRST, (4 * kTile + TY - 1) / TY, 4, TY>(a, A, P, ry, colw);
-  } else if (P <= 6 * kTile) {
-    stage_batched<T, KIND, FIRST, (6 * kTile + TY - 1) / TY, 6, TY>(a, A, P, ry, colw);
-  } else {
-    for (int r = ty; r < P; r += TY) {
-      const size_t rowoff = size_t(wrap_index(ry + r, n1)) * n2;
-      T* dst = A + r * P;
-#pragma unroll
-      for (int k = 0; k < kMaxChunks; ++k) {
-        const int c = tx + kTile * k;
-        if (c < P) dst[c] = load_src<T, KIND, FIRST>(a, rowoff + colw[k]);
-      }
-    }
-  }
-  __syncthreads();
   const int segs = (G + R - 1) / R;
-  // 2. prefilter along x2: thread -> (row r, segment q), outputs at columns q R .. q R + R - 1
+  // prefilter along x2: thread -> (row r, segment q), outputs at columns q R .. q R + R - 1; task
+  // sidx = q P + r, stepped by NTH without a division per task
+  const int dq1 = NTH / P, dr1 = NTH - dq1 * P;
+  int q = tid / P, r = tid - q * P;
   for (int sidx = tid; sidx < P * segs; sidx += NTH) {
-    const int q = sidx / P, r = sidx - q * P;
     const T* src = A + r * P + q * R;
     T x[R + 2 * K], o[R];
 #pragma unroll
@@ -323,11 +305,16 @@ __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, i
       const int c = q * R + j;
       if (c < G) B1[r * G + c] = o[j];
     }
+    q += dq1;
+    r += dr1;
+    if (r >= P) r -= P, ++q;
   }
   __syncthreads();
-  // 3. prefilter along x1: thread -> (column c, segment q), outputs at rows q R .. q R + R - 1
+  // prefilter along x1: thread -> (column c, segment q), outputs at rows q R .. q R + R - 1
+  const int dq2 = NTH / G, dc2 = NTH - dq2 * G;
+  q = tid / G;
+  int c = tid - q * G;
   for (int sidx = tid; sidx < G * segs; sidx += NTH) {
-    const int q = sidx / G, c = sidx - q * G;
     const T* src = B1 + (q * R) * G + c;
     T x[R + 2 * K], o[R];
 #pragma unroll
@@ -335,11 +322,55 @@ __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, i
     filter_window<T, R, K>(x, o);
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-      const int r = q * R + j;
-      if (r < G) C[r * G + c] = o[j];
+      const int rr = q * R + j;
+      if (rr < G) C[rr * G + c] = o[j];
+    }
+    q += dq2;
+    c += dc2;
+    if (c >= G) c -= G, ++q;
+  }
+  __syncthreads();
+}
+
+// Stage the transported field over the rows [y0 - lo - K, y0 - lo + G + K) (and likewise the
+// columns) and filter it into the B-spline coefficients of the inner G x G region, which starts
+// at global node (y0 - lo, x0 - lo) and is left at LDS offset 0 of 'A' (layout of
+// filter_coefficients).  The step kernel uses lo = D + 1, G = 16 + 2D + 3 (the stencil footprint
+// of displacements |d| <= D).
+template <typename T, int KIND, bool FIRST, int TY>
+__device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, int y0, int x0, int lo, int G) {
+  constexpr int K = FilterTaps<T>::K;
+  const int P = G + 2 * K;
+  const int n1 = a.n1, n2 = a.n2;
+  const int ry = y0 - lo - K, rx = x0 - lo - K;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tid = ty * kTile + tx;
+  constexpr int NTH = kTile * TY;
+  zero_filter_slack(A, P, G, tid, NTH);
+  // stage (periodic wrap), rows ty + TY i, columns tx + 16 k
+  int colw[kMaxChunks];
+#pragma unroll
+  for (int k = 0; k < kMaxChunks; ++k) {
+    const int c = tx + kTile * k;
+    colw[k] = c < P ? wrap_near(rx + c, n2) : 0;
+  }
+  if (P <= 4 * kTile) {
+    stage_batched<T, KIND, FIRST, (4 * kTile + TY - 1) / TY, 4, TY>(a, A, P, ry, colw);
+  } else if (P <= 6 * kTile) {
+    stage_batched<T, KIND, FIRST, (6 * kTile + TY - 1) / TY, 6, TY>(a, A, P, ry, colw);
+  } else {
+    for (int r = ty; r < P; r += TY) {
+      const size_t rowoff = size_t(wrap_near(ry + r, n1)) * n2;
+      T* dst = A + r * P;
+#pragma unroll
+      for (int k = 0; k < kMaxChunks; ++k) {
+        const int c = tx + kTile * k;
+        if (c < P) dst[c] = load_src<T, KIND, FIRST>(a, rowoff + colw[k]);
+      }
     }
   }
   __syncthreads();
+  filter_coefficients<T, NTH>(A, P, G, tid);
 }
 
 // Coefficient pass of the two-kernel step (whole-field B-spline coefficients into a.coef, read
@@ -435,7 +466,7 @@ __global__ void __launch_bounds__(256) k_prefilter_cols(StepArgs<T> args) {
   for (int idx = threadIdx.x; idx < (kColH + 2 * K) * kColW; idx += 256) {  // 256 threads per block
     const int r = idx / kColW, c = idx - r * kColW;
     const int col = min(x0 + c, n2 - 1);
-    const T val = a.coef2[size_t(wrap_index(y0 - K + r, n1)) * n2 + col];
+    const T val = a.coef2[size_t(wrap_near(y0 - K + r, n1)) * n2 + col];
     L[idx] = x0 + c < n2 ? val : T(0);
   }
   __syncthreads();
