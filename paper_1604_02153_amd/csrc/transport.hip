@@ -422,13 +422,7 @@ __global__ void __launch_bounds__(256) k_prefilter_rows(StepArgs<T> args, int rp
     for (int i = 0; i < kRowSeg + 2 * K; ++i) x[i] = xw[i + i / kRowSeg];
     T* out = a.coef2 + size_t(r0 + r) * n2 + q * kRowSeg;
     T y[kRowSeg];
-#pragma unroll
-    for (int j = 0; j < kRowSeg; ++j) {
-      T acc = tap<T>(0) * x[j + K];
-#pragma unroll
-      for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[j + K - t] + x[j + K + t]);
-      y[j] = acc;
-    }
+    filter_window<T, kRowSeg, K>(x, y);
     // a lane's outputs are contiguous: 16-byte stores where the row length keeps them aligned
     if (n2 % kRowSeg == 0) {
       using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
@@ -472,16 +466,14 @@ __global__ void __launch_bounds__(256) k_prefilter_cols(StepArgs<T> args) {
   __syncthreads();
   const int c = threadIdx.x % kColW, q = threadIdx.x / kColW;
   const int col = x0 + c;
-  T x[R + 2 * K];
+  T x[R + 2 * K], o[R];
 #pragma unroll
   for (int i = 0; i < R + 2 * K; ++i) x[i] = L[(q * R + i) * kColW + c];
+  filter_window<T, R, K>(x, o);
 #pragma unroll
   for (int j = 0; j < R; ++j) {
-    T acc = tap<T>(0) * x[j + K];
-#pragma unroll
-    for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[j + K - t] + x[j + K + t]);
     const int row = y0 + q * R + j;
-    if (row < n1 && col < n2) a.coef[size_t(row) * n2 + col] = acc;
+    if (row < n1 && col < n2) a.coef[size_t(row) * n2 + col] = o[j];
   }
 }
 
@@ -555,13 +547,7 @@ __global__ void __launch_bounds__(Prefilter2D<T>::NT) k_prefilter_2d(StepArgs<T>
       T x[R + 2 * K];
 #pragma unroll
       for (int i = 0; i < R + 2 * K; ++i) x[i] = src[i];
-#pragma unroll
-      for (int j = 0; j < R; ++j) {
-        T acc = tap<T>(0) * x[j + K];
-#pragma unroll
-        for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[j + K - t] + x[j + K + t]);
-        y[k][j] = acc;
-      }
+      filter_window<T, R, K>(x, y[k]);
     }
   }
   __syncthreads();
@@ -579,17 +565,15 @@ __global__ void __launch_bounds__(Prefilter2D<T>::NT) k_prefilter_2d(StepArgs<T>
   for (int task = tid; task < TS * (TS / R); task += NT) {
     const int q = task / TS, c = task - q * TS;
     const T* src = B + (q * R) * SB + c;
-    T x[R + 2 * K];
+    T x[R + 2 * K], o[R];
 #pragma unroll
     for (int i = 0; i < R + 2 * K; ++i) x[i] = src[i * SB];
+    filter_window<T, R, K>(x, o);
     const int col = x0 + c;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-      T acc = tap<T>(0) * x[j + K];
-#pragma unroll
-      for (int t = 1; t <= K; ++t) acc += tap<T>(t) * (x[j + K - t] + x[j + K + t]);
       const int row = y0 + q * R + j;
-      if (row < n1 && col < n2) a.coef[size_t(row) * n2 + col] = acc;
+      if (row < n1 && col < n2) a.coef[size_t(row) * n2 + col] = o[j];
     }
   }
 }
