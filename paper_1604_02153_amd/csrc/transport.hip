@@ -275,18 +275,16 @@ __device__ __forceinline__ void stage_batched(const StepArgs<T>& a, T* A, int P,
 // which zero_filter_slack clears (before the barrier that ends the staging).  The recursive
 // filter carries those values into the valid outputs (multiplied by taps that cancel exactly), so
 // they must be finite.
-template <typename T>
+template <typename T, int R>
 __device__ __forceinline__ void zero_filter_slack(T* A, int P, int G, int tid, int nth) {
-  constexpr int R = FilterTaps<T>::R;
   T* B1 = A + P * P + R;
   for (int i = tid; i < R; i += nth) A[P * P + i] = T(0);
   for (int i = tid; i < R * G; i += nth) B1[P * G + i] = T(0);
 }
 
-template <typename T, int NTH>
+template <typename T, int NTH, int R>
 __device__ __forceinline__ void filter_coefficients(T* A, int P, int G, int tid) {
   constexpr int K = FilterTaps<T>::K;
-  constexpr int R = FilterTaps<T>::R;
   T* B1 = A + P * P + R;
   T* C = A;
   const int segs = (G + R - 1) / R;
@@ -336,17 +334,20 @@ __device__ __forceinline__ void filter_coefficients(T* A, int P, int G, int tid)
 // columns) and filter it into the B-spline coefficients of the inner G x G region, which starts
 // at global node (y0 - lo, x0 - lo) and is left at LDS offset 0 of 'A' (layout of
 // filter_coefficients).  The step kernel uses lo = D + 1, G = 16 + 2D + 3 (the stencil footprint
-// of displacements |d| <= D).
+// of displacements |d| <= D).  The 16 x 32-thread blocks of small (latency-bound) launches give
+// each FP32 filter task 4 outputs rather than 8: twice the tasks for their threads, each with a
+// shorter dependence chain.
 template <typename T, int KIND, bool FIRST, int TY>
 __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, int y0, int x0, int lo, int G) {
   constexpr int K = FilterTaps<T>::K;
+  constexpr int R = (sizeof(T) == 4 && TY > kTile) ? 4 : FilterTaps<T>::R;
   const int P = G + 2 * K;
   const int n1 = a.n1, n2 = a.n2;
   const int ry = y0 - lo - K, rx = x0 - lo - K;
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * kTile + tx;
   constexpr int NTH = kTile * TY;
-  zero_filter_slack(A, P, G, tid, NTH);
+  zero_filter_slack<T, R>(A, P, G, tid, NTH);
   // stage (periodic wrap), rows ty + TY i, columns tx + 16 k
   int colw[kMaxChunks];
 #pragma unroll
@@ -370,7 +371,7 @@ __device__ __forceinline__ void stage_coefficients(const StepArgs<T>& a, T* A, i
     }
   }
   __syncthreads();
-  filter_coefficients<T, NTH>(A, P, G, tid);
+  filter_coefficients<T, NTH, R>(A, P, G, tid);
 }
 
 // Coefficient pass of the two-kernel step (whole-field B-spline coefficients into a.coef, read

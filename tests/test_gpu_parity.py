@@ -543,7 +543,10 @@ def test_large_grids_match_oracle(slnk, shape):
 
 def test_wide_batch_matches_single_contexts(slnk):
     """A 16-item batch at 128^2 gives its column FFT passes wide panels (several adjacent columns
-    per workgroup); every item still equals its own batch-1 context bit for bit, and the oracle."""
+    per workgroup); every item still equals its own batch-1 context bit for bit, and the oracle.
+    Both contexts run the fused SL step with 16 x 32 threads per tile (sl_path 3): by launch size
+    the 1024-tile batch would take 16 x 16-thread blocks, whose filter tasks group their outputs
+    differently (the same values up to rounding)."""
     n, B, prec = 128, 16, "mixed"
     probs = _batch_problems(n, n, seeds=tuple(range(50, 50 + B)), amps=[0.1 + 0.02 * i for i in range(B)])
     for L, _, _ in probs:
@@ -551,7 +554,7 @@ def test_wide_batch_matches_single_contexts(slnk):
     vs = [same_inputs(prec, 0.5 * p[1]) for p in probs]
     vts = [same_inputs(prec, p[2]) for p in probs]
     stack = lambda arrs: _t(np.stack(arrs), prec)
-    cb = _ctx(slnk, probs[0][0], prec, pc="reg", batch=B)
+    cb = _ctx(slnk, probs[0][0], prec, pc="reg", batch=B, sl_path=3)
     cb.set_images(stack([p[0].mR for p in probs]), stack([p[0].mT for p in probs]))
     gb = torch.empty((B, 2, n, n), dtype=torch.float32, device="cuda")
     cb.gradient(stack(vs), gb)
@@ -559,7 +562,7 @@ def test_wide_batch_matches_single_contexts(slnk):
     cb.hessian_matvec(stack(vts), hb)
     for z in (0, 7, 15):
         L = probs[z][0]
-        c1 = _ctx(slnk, L, prec, pc="reg")
+        c1 = _ctx(slnk, L, prec, pc="reg", sl_path=3)
         c1.set_images(_t(L.mR, prec), _t(L.mT, prec))
         g1, h1 = torch.empty_like(gb[0]), torch.empty_like(gb[0])
         c1.gradient(_t(vs[z], prec), g1)
