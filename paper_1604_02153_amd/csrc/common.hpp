@@ -40,6 +40,37 @@ __host__ __device__ __forceinline__ int wrap_index(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// R consecutive outputs o[j] = sum_{|t| <= K} tap(t) x[K + j + t] of the truncated exponential
+// filter of the periodic cubic B-spline prefilter (tap(t) = tap(0) z^t, z = sqrt(3) - 2) from a
+// window x of R + 2K values.  The causal half P_j = sum_{t=0..K} tap(t) x[K + j - t] of the first
+// output and the anticausal half Q_j = sum_{t=1..K} tap(t) x[K + j + t] of the last are summed
+// directly; the others follow from the first-order recursions of the exponential taps, which keep
+// the truncation exactly:
+//   P_{j+1} = tap(0) x[K+j+1] + z P_j - z tap(K) x[j],  Q_j = z (tap(0) x[K+j+1] + Q_{j+1}) - z tap(K) x[2K+j+1]
+// (|z| < 0.27, so rounding errors decay along the recursion).  About (2K + 3R) / R operations per
+// output instead of 2K + 1.
+template <typename T, int R, int K, class Tap>
+__device__ __forceinline__ void filter_window_rec(const T* x, T* o, Tap tap) {
+  const T z = T(-0.26794919243112270647);
+  const T t0 = tap(0), zK = z * tap(K);
+  T q[R];
+  T acc = T(0);
+#pragma unroll
+  for (int t = 1; t <= K; ++t) acc += tap(t) * x[K + R - 1 + t];
+  q[R - 1] = acc;
+#pragma unroll
+  for (int j = R - 2; j >= 0; --j) q[j] = z * (t0 * x[K + j + 1] + q[j + 1]) - zK * x[2 * K + j + 1];
+  T pc = T(0);
+#pragma unroll
+  for (int t = 0; t <= K; ++t) pc += tap(t) * x[K - t];
+  o[0] = pc + q[0];
+#pragma unroll
+  for (int j = 0; j < R - 1; ++j) {
+    pc = t0 * x[K + j + 1] + z * pc - zK * x[j];
+    o[j + 1] = pc + q[j + 1];
+  }
+}
+
 // The same with one add or subtract for -n <= i < 2n (stencil footprints on grids wider than
 // them), the division only otherwise: an integer division costs a few dozen instructions.
 __host__ __device__ __forceinline__ int wrap_near(int i, int n) {

@@ -215,13 +215,7 @@ __device__ __forceinline__ void fir_window(const T* s, int k0, int line, const T
   T x[R + 2 * K];
 #pragma unroll
   for (int i = 0; i < R + 2 * K; ++i) x[i] = s[(k0 + i) * L + line];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    T acc = tp.t[0] * x[r + K];
-#pragma unroll
-    for (int t = 1; t <= K; ++t) acc += tp.t[t] * (x[r + K - t] + x[r + K + t]);
-    o[r] = acc;
-  }
+  filter_window_rec<T, R, K>(x, o, [&](int t) { return tp.t[t]; });
 }
 
 constexpr int kFirR = 4;  // outputs per thread (every n here is a multiple of 8)

@@ -209,33 +209,11 @@ __device__ __forceinline__ T load_src(const StepArgs<T>& a, size_t gi) {
   }
 }
 
-// R consecutive outputs o[j] = sum_{|t| <= K} tap_t x[K + j + t] of the truncated exponential filter
-// (tap_t = tap_0 z^t, z = sqrt(3) - 2) from a window x of R + 2K values.  The causal half
-// P_j = sum_{t=0..K} tap_t x[K + j - t] of the first output and the anticausal half
-// Q_j = sum_{t=1..K} tap_t x[K + j + t] of the last are summed directly; the others follow from the
-// first-order recursions of the exponential taps, which keep the truncation exactly:
-//   P_{j+1} = tap_0 x[K+j+1] + z P_j - z tap_K x[j],  Q_j = z (tap_0 x[K+j+1] + Q_{j+1}) - z tap_K x[2K+j+1]
-// (|z| < 0.27, so rounding errors decay along the recursion).
+// R consecutive outputs of the truncated exponential filter from a window of R + 2K values (the
+// recursive form shared with the three-dimensional passes), taps from constant memory
 template <typename T, int R, int K>
 __device__ __forceinline__ void filter_window(const T* x, T* o) {
-  const T z = T(-0.26794919243112270647);
-  const T t0 = tap<T>(0), zK = z * tap<T>(K);
-  T q[R];
-  T acc = T(0);
-#pragma unroll
-  for (int t = 1; t <= K; ++t) acc += tap<T>(t) * x[K + R - 1 + t];
-  q[R - 1] = acc;
-#pragma unroll
-  for (int j = R - 2; j >= 0; --j) q[j] = z * (t0 * x[K + j + 1] + q[j + 1]) - zK * x[2 * K + j + 1];
-  T pc = T(0);
-#pragma unroll
-  for (int t = 0; t <= K; ++t) pc += tap<T>(t) * x[K - t];
-  o[0] = pc + q[0];
-#pragma unroll
-  for (int j = 0; j < R - 1; ++j) {
-    pc = t0 * x[K + j + 1] + z * pc - zK * x[j];
-    o[j + 1] = pc + q[j + 1];
-  }
+  filter_window_rec<T, R, K>(x, o, [](int t) { return tap<T>(t); });
 }
 
 // Staging of a P x P footprint by a 16 x TY block (P <= TY CHR rows, P <= 16 CHC columns): every
