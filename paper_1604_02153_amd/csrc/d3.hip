@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <map>
 #include <mutex>
 
 #include "d3.hpp"
@@ -44,16 +45,19 @@ inline int ilog2(int n) {
 }
 
 // Raise a kernel's dynamic LDS limit (once per kernel and size) for launches above the default.
+// The sizes already allowed are kept per kernel (kernels of one signature share a function type,
+// so a static per type would not tell them apart).
 std::mutex g_lds_mutex;
+std::map<const void*, size_t> g_lds_allowed;
 template <typename K>
 hipError_t ensure_lds(K kernel, size_t bytes) {
-  static std::atomic<size_t> allowed{64 * 1024};
-  if (bytes <= allowed.load(std::memory_order_acquire)) return hipSuccess;
+  if (bytes <= 64 * 1024) return hipSuccess;
+  const void* key = reinterpret_cast<const void*>(kernel);
   std::lock_guard<std::mutex> lock(g_lds_mutex);
-  if (bytes <= allowed.load(std::memory_order_relaxed)) return hipSuccess;
-  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
-  if (e == hipSuccess) allowed.store(bytes, std::memory_order_release);
+  size_t& allowed = g_lds_allowed[key];
+  if (bytes <= allowed) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  if (e == hipSuccess) allowed = bytes;
   return e;
 }
 
@@ -273,6 +277,65 @@ __global__ void __launch_bounds__(kThreads) k_fir_rows(const T* in, T* out, size
 #pragma unroll
       for (int j = 0; j < kFirR; ++j) out[off + size_t(r0 + r) * n + q * kFirR + j] = o[j];
     }
+  }
+}
+
+// Filter along x3 and then x2 in one pass.  A block takes a band of BR rows (x2) of one x1 plane:
+// it stages rows r0 - K .. r0 + BR + K - 1 (periodic in x2), each with K wrapped values on either
+// side (periodic in x3), filters every staged row along x3 into a second buffer, then every
+// column of the band along x2.  One read and one write of the field instead of two of each; the
+// 2K halo rows are read twice (from L2).  blockDim = (64, 8).
+template <typename T>
+struct FirPlane {
+  static constexpr int kThreadsX = 64, kThreadsY = 8;
+  static int band(int n2) { return std::min(n2, 32); }
+  static size_t lds_bytes(int n2, int n3) {
+    constexpr int K = Fir<T>::K;
+    const int NR = band(n2) + 2 * K, W = n3 + 2 * K;
+    return size_t(NR) * ((W | 1) + (n3 | 1)) * sizeof(T);
+  }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_fir_plane(const T* in, T* out, size_t fstride, int n2, int n3, int BR,
+                                                   Taps<T> tp) {
+  constexpr int K = Fir<T>::K, R = kFirR;
+  constexpr int NT = FirPlane<T>::kThreadsX * FirPlane<T>::kThreadsY;
+  extern __shared__ unsigned char smem_raw[];
+  // odd row strides: the rows of consecutive threads fall on different banks
+  const int NR = BR + 2 * K, W = n3 + 2 * K, SA = W | 1, SB = n3 | 1;
+  T* A = reinterpret_cast<T*>(smem_raw);  // [NR][SA] staged
+  T* Bf = A + size_t(NR) * SA;            // [NR][SB] filtered along x3
+  const int r0 = blockIdx.x * BR;
+  const size_t plane = blockIdx.z * fstride + size_t(blockIdx.y) * n2 * n3;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * FirPlane<T>::kThreadsX + tx;
+  for (int r = ty; r < NR; r += FirPlane<T>::kThreadsY) {
+    const T* row = in + plane + size_t(wrap_near(r0 - K + r, n2)) * n3;
+    for (int k = tx; k < W; k += FirPlane<T>::kThreadsX) A[r * SA + k] = row[fir_src<K>(k, n3)];
+  }
+  __syncthreads();
+  // along x3: task (staged row r, segment q), consecutive threads on consecutive rows
+  const int segs3 = n3 / R;
+  for (int t = tid; t < NR * segs3; t += NT) {
+    const int q = t / NR, r = t - q * NR;
+    T x[R + 2 * K], o[R];
+#pragma unroll
+    for (int i = 0; i < R + 2 * K; ++i) x[i] = A[r * SA + q * R + i];
+    filter_window_rec<T, R, K>(x, o, [&](int j) { return tp.t[j]; });
+#pragma unroll
+    for (int j = 0; j < R; ++j) Bf[r * SB + q * R + j] = o[j];
+  }
+  __syncthreads();
+  // along x2: task (column c, segment q), consecutive threads on consecutive columns
+  const int segs2 = BR / R;
+  for (int t = tid; t < n3 * segs2; t += NT) {
+    const int q = t / n3, c = t - q * n3;
+    T x[R + 2 * K], o[R];
+#pragma unroll
+    for (int i = 0; i < R + 2 * K; ++i) x[i] = Bf[(q * R + i) * SB + c];
+    filter_window_rec<T, R, K>(x, o, [&](int j) { return tp.t[j]; });
+#pragma unroll
+    for (int j = 0; j < R; ++j) out[plane + size_t(r0 + q * R + j) * n3 + c] = o[j];
   }
 }
 
@@ -848,25 +911,43 @@ hipError_t fft_inverse(hipStream_t s, const Dims& d, const Twiddles<T>& tw, int 
   return hipGetLastError();
 }
 
+size_t device_lds_limit();
+
 template <typename T>
 hipError_t spline_coefficients(hipStream_t s, const Dims& d, int nf, const T* in, T* out) {
   const Taps<T> tp = make_taps<T>();
   const size_t F = d.F();
   constexpr int RL = Fir<T>::RL, CL = Fir<T>::CL;
   const int rows = d.n1 * d.n2;
-  // along x3 (rows), then x2 (lines (i1, i3), element stride n3), then x1 (stride n2 n3); the
-  // last two in place
+  // along x3 and x2 in one pass where a band of rows fits in LDS (else along x3 (rows), then x2
+  // (lines (i1, i3), element stride n3)), then x1 (stride n2 n3); the passes after the first in
+  // place
   constexpr int K = Fir<T>::K;
-  hipLaunchKernelGGL(k_fir_rows<T>, dim3((rows + RL - 1) / RL, 1, nf), dim3(kThreads),
-                     size_t(d.n3 + 2 * K) * RL * sizeof(T), s, in, out, F, rows, d.n3, tp);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  const size_t plane_lds = FirPlane<T>::lds_bytes(d.n2, d.n3);
+  if (plane_lds <= device_lds_limit()) {
+    e = ensure_lds(k_fir_plane<T>, plane_lds);
+    if (e != hipSuccess) return e;
+    const int BR = FirPlane<T>::band(d.n2);
+    hipLaunchKernelGGL(k_fir_plane<T>, dim3(d.n2 / BR, d.n1, nf),
+                       dim3(FirPlane<T>::kThreadsX, FirPlane<T>::kThreadsY), plane_lds, s, in, out, F, d.n2, d.n3,
+                       BR, tp);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(k_fir_rows<T>, dim3((rows + RL - 1) / RL, 1, nf), dim3(kThreads),
+                       size_t(d.n3 + 2 * K) * RL * sizeof(T), s, in, out, F, rows, d.n3, tp);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = ensure_lds(k_fir_strided<T>, size_t(std::max(d.n1, d.n2) + 2 * K) * CL * sizeof(T));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fir_strided<T>, dim3((d.n3 + CL - 1) / CL, d.n1, nf), dim3(kThreads),
+                       size_t(d.n2 + 2 * K) * CL * sizeof(T), s, out, out, F, d.n2, d.n3, (long long)d.n3,
+                       (long long)d.n2 * d.n3, tp);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   e = ensure_lds(k_fir_strided<T>, size_t(std::max(d.n1, d.n2) + 2 * K) * CL * sizeof(T));
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fir_strided<T>, dim3((d.n3 + CL - 1) / CL, d.n1, nf), dim3(kThreads),
-                     size_t(d.n2 + 2 * K) * CL * sizeof(T), s, out, out, F, d.n2, d.n3, (long long)d.n3,
-                     (long long)d.n2 * d.n3, tp);
-  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fir_strided<T>, dim3((d.n2 * d.n3 + CL - 1) / CL, 1, nf), dim3(kThreads),
                      size_t(d.n1 + 2 * K) * CL * sizeof(T), s, out, out, F, d.n1, d.n2 * d.n3, (long long)d.n2 * d.n3, 0LL,
