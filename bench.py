@@ -43,7 +43,8 @@ INC_ADJ_FIELDS_PER_POINT = 13
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "sl_step_incadj_gauss256_counters.txt")
 WEIGHTS = os.path.join(ROOT, "paper_1604_02153_amd", "weights", "unet_gauss256.bin")
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1604_02153_amd", "csrc", "transport.hip")
+# the step kernel's sources (the counters go stale when either changes)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1604_02153_amd", "csrc", f) for f in ("transport.hip", "common.hpp")]
 
 
 def log(msg):
@@ -156,8 +157,11 @@ def measured_traffic():
     try:
         with open(COUNTERS_FILE) as f:
             kv = dict(line.split("=", 1) for line in f.read().splitlines() if "=" in line and not line.startswith("#"))
-        with open(KERNEL_SOURCE, "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()[:16]
+        sha = hashlib.sha256()
+        for src in KERNEL_SOURCES:
+            with open(src, "rb") as f:
+                sha.update(f.read())
+        h = sha.hexdigest()[:16]
         if kv.get("source_sha256_16", "").strip() != h:
             return None
         return float(kv["traffic_bytes_per_launch"])
