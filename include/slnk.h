@@ -73,7 +73,7 @@ typedef enum { SLNK_TRANSPORT_SL = 0, SLNK_TRANSPORT_RK2A = 1 } slnk_transport;
  *   pc            SLNK_PC_REG: PCG on H with P_REG; SLNK_PC_2L: PCG on the split system
  *                 (I + S Q S) s = -S g, S = (beta A')^{-1/2}, with P_2L; coarse grid n/2
  *   cheb_iters    k of CHEB(k) (k steps, k - 1 coarse operator applications); paper: 10
- *   lanczos_steps Lanczos steps for e_max at v = 0 (paper: about 30)
+ *   lanczos_steps Lanczos steps for e_max at v = 0 (paper: about 30; 2 to 1000 with P_2L)
  *   emax_safety   e_max = emax_safety * largest Ritz value (>= 1)
  *   lanczos_seed  seed of the SplitMix64 start vector of the Lanczos iteration
  *   use_graphs    1: replay the Hessian matvec and the preconditioner from captured HIP graphs

@@ -218,6 +218,8 @@ struct Context {
   double* dres = nullptr;     // device results [2][4B]
   double* hres = nullptr;     // pinned host copy of dres
   double* dsc = nullptr;      // device per-item scalars [16][B]
+  double* lz_log = nullptr;   // Lanczos (alpha, beta) per item and step [B][steps][2] (P_2L)
+  int* lz_live = nullptr;     // Lanczos: items whose tridiagonal matrix is still growing [B]
   double* hsc = nullptr;      // pinned staging of dsc
   double* cheb_tab = nullptr; // device [2][cheb_iters][B]: Chebyshev d-update coefficients
   double* inv_theta = nullptr;  // device [B]: 1 / theta of each item's Chebyshev interval
@@ -360,7 +362,8 @@ struct Context {
     two_level = p.pc == SLNK_PC_2L;
     if (two_level) {
       if (!fft_size_ok(p.n1 / 2) || !fft_size_ok(p.n2 / 2)) throw Fail{SLNK_EINVAL, "coarse grid n/2 not supported"};
-      if (p.cheb_iters < 1 || p.cheb_iters > 64 || p.lanczos_steps < 2 || !(p.emax_safety >= 1.0))
+      if (p.cheb_iters < 1 || p.cheb_iters > 64 || p.lanczos_steps < 2 || p.lanczos_steps > 1000 ||
+          !(p.emax_safety >= 1.0))
         throw Fail{SLNK_EINVAL, "bad P_2L parameters"};
     }
     {
@@ -380,6 +383,7 @@ struct Context {
     bytes += B * (2 * F * sizeof(T) + sizeof(float)) + 2 * 256;
     if (full_newton) bytes += B * size_t(6 * p.nt + 5) * F * sizeof(T) + 6 * 256;
     if (rk2a) bytes += B * size_t(24) * F * sizeof(T) + 14 * 256;  // w3, d3, w3s, d3s 12; k, y, src 5; pair 2; g4 4; divt 1
+    if (two_level) bytes += B * (2 * size_t(p.lanczos_steps) * sizeof(double) + sizeof(int)) + 2 * 256;  // Lanczos log
     void* base = nullptr;
     if (hipMalloc(&base, bytes) != hipSuccess) throw Fail{SLNK_ENOMEM, "hipMalloc of the workspace failed"};
     arena.base = static_cast<char*>(base);
@@ -393,6 +397,10 @@ struct Context {
     cheb_tab = arena.take<double>(2 * 64 * B);
     inv_theta = arena.take<double>(B);
     masks = arena.take<int>(5 * B);
+    if (two_level) {
+      lz_log = arena.take<double>(B * 2 * size_t(p.lanczos_steps));
+      lz_live = arena.take<int>(B);
+    }
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hres), 8 * B * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hsc), 16 * B * sizeof(double), hipHostMallocDefault));
     alloc_level(fine, p.n1, p.n2, p.nt);
@@ -1006,38 +1014,37 @@ struct Context {
     put_scalars(0, nq);
     HIPCHK(axpby<T>(stream, B, n, 1.0, sc(0), q, 0.0, nullptr, q));
     HIPCHK(fill<T>(stream, B * n, 0.0, qp));
-    std::vector<double> beta(B, 0.0);
-    std::vector<int> live = current ? hmask : std::vector<int>(B, 1);
-    for (int j = 0; j < prm.lanczos_steps; ++j) {
+    // the step scalars stay on the device (k_lanczos_coef); the (alpha, beta) log is read once
+    const std::vector<int> live0 = current ? hmask : std::vector<int>(B, 1);
+    const int steps = prm.lanczos_steps;
+    HIPCHK(set_ints(stream, lz_live, live0.data(), B));
+    HIPCHK(fill<double>(stream, B, 0.0, sc(1)));  // beta of the step before the first
+    for (int j = 0; j < steps; ++j) {
       if (current)
         split_matvec(coarse, q, w, mk);
       else
         split_matvec_zero(coarse, q, w);
-      put_scalars(1, beta);
       HIPCHK(axpby<T>(stream, B, n, -1.0, sc(1), qp, 1.0, nullptr, w));
-      std::vector<double> alpha = dots(coarse, q, w);
-      put_scalars(2, alpha);
+      HIPCHK(dot<T>(stream, B, n, q, w, partial, dres));
+      HIPCHK(lanczos_coef(stream, LANCZOS_ALPHA, B, j, steps, dres, lz_live, sc(2), sc(1), sc(3), lz_log));
       HIPCHK(axpby<T>(stream, B, n, -1.0, sc(2), q, 1.0, nullptr, w));
-      std::vector<double> ww = dots(coarse, w, w);
-      bool more = false;
-      std::vector<double> inv(B, 0.0);
-      for (int z = 0; z < B; ++z) {
-        if (!live[z]) continue;
-        al[z].push_back(alpha[z]);
-        beta[z] = std::sqrt(ww[z]);
-        if (j == prm.lanczos_steps - 1 || beta[z] <= 1e-14 * std::fabs(alpha[z])) {
-          live[z] = 0;  // last step or breakdown: this item's tridiagonal matrix is complete
-          beta[z] = 0.0;
-        } else {
-          be[z].push_back(beta[z]);
-          inv[z] = 1.0 / beta[z];
-          more = true;
-        }
-      }
-      if (!more) break;
+      HIPCHK(dot<T>(stream, B, n, w, w, partial, dres));
+      HIPCHK(lanczos_coef(stream, LANCZOS_BETA, B, j, steps, dres, lz_live, sc(2), sc(1), sc(3), lz_log));
+      if (j == steps - 1) break;
       std::swap(qp, q);  // qp <- q
-      put_scalars(3, inv);
       HIPCHK(axpby<T>(stream, B, n, 1.0, sc(3), w, 0.0, nullptr, q));  // q <- w / beta
+    }
+    std::vector<double> log(size_t(B) * steps * 2);
+    HIPCHK(hipMemcpyAsync(log.data(), lz_log, log.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    for (int z = 0; z < B; ++z) {
+      if (!live0[z]) continue;
+      for (int j = 0; j < steps; ++j) {
+        const double* e = log.data() + (size_t(z) * steps + j) * 2;
+        al[z].push_back(e[0]);
+        if (e[1] < 0.0) break;  // last step or breakdown
+        be[z].push_back(e[1]);
+      }
     }
   }
 

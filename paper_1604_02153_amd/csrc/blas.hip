@@ -263,6 +263,41 @@ __global__ void k_pcg_coef(int mode, int batch, const int* mask, const double* r
   }
 }
 
+// Device-side scalars of one Lanczos step (item z's reduction at red[4 z], z < batch).
+// LANCZOS_ALPHA: alpha[z] = q.w (the coefficient of w <- w - alpha q), logged at
+// log[(z * steps + j) * 2] for live items.  LANCZOS_BETA: red = w.w; for a live item beta = sqrt(w.w)
+// ends its tridiagonal matrix at the last step or at breakdown (beta <= 1e-14 |alpha|): then the
+// item is marked dead, its log entry is -1 and beta[z] = inv[z] = 0; otherwise the log holds beta,
+// beta[z] = beta (the next step's coefficient of w <- w - beta q_prev) and inv[z] = 1 / beta.
+// Dead items keep beta[z] = 0 and get inv[z] = 0.
+__global__ void k_lanczos_coef(int mode, int batch, int j, int steps, const double* red, int* live, double* alpha,
+                               double* beta, double* inv, double* log) {
+  const int z = threadIdx.x + blockIdx.x * blockDim.x;
+  if (z >= batch) return;
+  const double v = red[4 * z];
+  double* lz = log + (size_t(z) * steps + j) * 2;
+  if (mode == LANCZOS_ALPHA) {
+    alpha[z] = v;
+    if (live[z]) lz[0] = v;
+    return;
+  }
+  if (!live[z]) {
+    inv[z] = 0.0;
+    return;
+  }
+  const double b = sqrt(v);
+  if (j == steps - 1 || b <= 1e-14 * fabs(alpha[z])) {
+    live[z] = 0;
+    lz[1] = -1.0;
+    beta[z] = 0.0;
+    inv[z] = 0.0;
+  } else {
+    lz[1] = b;
+    beta[z] = b;
+    inv[z] = 1.0 / b;
+  }
+}
+
 struct IntPack {
   int v[64];
 };
@@ -287,6 +322,14 @@ hipError_t pcg_coef(hipStream_t s, int mode, int batch, const int* mask, const d
                     double* c1) {
   if (batch <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_pcg_coef, dim3((batch + 63) / 64), dim3(64), 0, s, mode, batch, mask, red, rz, c0, c1);
+  return hipGetLastError();
+}
+
+hipError_t lanczos_coef(hipStream_t s, int mode, int batch, int j, int steps, const double* red, int* live,
+                        double* alpha, double* beta, double* inv, double* log) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lanczos_coef, dim3((batch + 63) / 64), dim3(64), 0, s, mode, batch, j, steps, red, live, alpha,
+                     beta, inv, log);
   return hipGetLastError();
 }
 

@@ -278,6 +278,16 @@ enum { PCG_RZ = 0, PCG_ALPHA = 1, PCG_BETA = 2 };
 hipError_t pcg_coef(hipStream_t s, int mode, int batch, const int* mask, const double* red, double* rz, double* c0,
                     double* c1);
 
+// Device-side scalars of Lanczos step j of 'steps' (item z's reduction at red[4 z]), so that the
+// iteration needs no host round trip: LANCZOS_ALPHA stores alpha = q.w in alpha[z] (and, for live
+// items, in log[(z steps + j) 2]); LANCZOS_BETA takes w.w and, for live items, logs beta =
+// sqrt(w.w) at log[(z steps + j) 2 + 1] and sets beta[z] = beta, inv[z] = 1 / beta -- or, at the
+// last step or a breakdown (beta <= 1e-14 |alpha|), logs -1, sets both to 0 and clears live[z];
+// dead items get inv[z] = 0.
+enum { LANCZOS_ALPHA = 0, LANCZOS_BETA = 1 };
+hipError_t lanczos_coef(hipStream_t s, int mode, int batch, int j, int steps, const double* red, int* live,
+                        double* alpha, double* beta, double* inv, double* log);
+
 // ---- full-Newton matvec (eqs. e:hessian-matvec, e:inc-adj-slm with the lambda terms kept).
 // Per item z: lam [nt+1] fields (adjoint lambda^0..lambda^nt), vt 2 fields.
 // prod[z][j] = lam[z][j] vt[z] (2 fields per level j = 0..nt)

@@ -120,7 +120,7 @@ def test_defaults_are_the_paper_settings(pkg):
 
 @pytest.mark.parametrize("change", [dict(n1=30, n2=34), dict(nt=0), dict(batch=0), dict(reg=4), dict(beta=0.0),
                                     dict(prec=7), dict(pc=3), dict(n1=2048 * 2), dict(n1=2048), dict(cheb_iters=0),
-                                    dict(sl_path=4)])
+                                    dict(sl_path=4), dict(lanczos_steps=1001)])
 def test_create_rejects_bad_parameters_before_device_work(pkg, change):
     lib = pkg.load_library()
     p = pkg.Params()
