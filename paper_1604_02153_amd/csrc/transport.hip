@@ -490,28 +490,39 @@ __global__ void __launch_bounds__(Prefilter2D<T>::NT) k_prefilter_2d(StepArgs<T>
   xcd_tile(by, bx);
   const int y0 = by * TS, x0 = bx * TS;
   const int tid = threadIdx.x;
-  // 1. stage: every load of the thread is issued before any store (no per-load wait); the grid
-  // is at least PS in both directions (caller), so one add or subtract wraps an index
-  constexpr int NL = (PS * PS + NT - 1) / NT;
-  T v[NL];
+  // 1. stage: wavefront ty takes rows ty + SR i, its lane tx columns tx and tx + 64, so that the
+  // wrapped row offsets and column indices are formed once per thread (the kernel is bound by its
+  // instruction count, and a per-element division and wrap had been most of it); every load of
+  // the thread is issued before any store (no per-load wait).  The grid is at least PS in both
+  // directions (caller), so one add or subtract wraps an index.
+  constexpr int SR = NT / 64, NRI = (PS + SR - 1) / SR, NCI = (PS + 63) / 64;
+  const int tx = tid & 63, ty = tid >> 6;
+  int gcol[NCI];
 #pragma unroll
-  for (int k = 0; k < NL; ++k) {
-    const int idx = min(tid + NT * k, PS * PS - 1);  // past the end: repeat a valid load
-    const int r = idx / PS, c = idx - r * PS;
-    int gr = y0 - K + r, gc = x0 - K + c;
-    gr += gr < 0 ? n1 : 0;
-    gr -= gr >= n1 ? n1 : 0;
+  for (int j = 0; j < NCI; ++j) {
+    int gc = x0 - K + tx + 64 * j;
     gc += gc < 0 ? n2 : 0;
     gc -= gc >= n2 ? n2 : 0;
-    v[k] = load_src<T, KIND, FIRST>(a, size_t(gr) * n2 + gc);
+    gcol[j] = gc;
+  }
+  T v[NRI][NCI];
+#pragma unroll
+  for (int i = 0; i < NRI; ++i) {
+    const int r = ty + SR * i;
+    int gr = y0 - K + r;
+    gr += gr < 0 ? n1 : 0;
+    gr -= gr >= n1 ? n1 : 0;
+    const size_t rowoff = size_t(gr) * n2;
+#pragma unroll
+    for (int j = 0; j < NCI; ++j)
+      if (r < PS && tx + 64 * j < PS) v[i][j] = load_src<T, KIND, FIRST>(a, rowoff + gcol[j]);
   }
 #pragma unroll
-  for (int k = 0; k < NL; ++k) {
-    const int idx = tid + NT * k;
-    if (idx < PS * PS) {
-      const int r = idx / PS, c = idx - r * PS;
-      A[r * SA + c] = v[k];
-    }
+  for (int i = 0; i < NRI; ++i) {
+    const int r = ty + SR * i;
+#pragma unroll
+    for (int j = 0; j < NCI; ++j)
+      if (r < PS && tx + 64 * j < PS) A[r * SA + tx + 64 * j] = v[i][j];
   }
   __syncthreads();
   // 2. rows: task (row r, segment q), consecutive threads on consecutive rows; every task's
