@@ -314,28 +314,38 @@ __global__ void __launch_bounds__(512) k_fir_plane(const T* in, T* out, size_t f
     for (int k = tx; k < W; k += FirPlane<T>::kThreadsX) A[r * SA + k] = row[fir_src<K>(k, n3)];
   }
   __syncthreads();
-  // along x3: task (staged row r, segment q), consecutive threads on consecutive rows
+  // along x3: task t = q NR + r (staged row r, segment q), consecutive threads on consecutive
+  // rows; (q, r) stepped by NT without a division per task
   const int segs3 = n3 / R;
+  const int dq3 = NT / NR, dr3 = NT - dq3 * NR;
+  int q = tid / NR, r = tid - q * NR;
   for (int t = tid; t < NR * segs3; t += NT) {
-    const int q = t / NR, r = t - q * NR;
     T x[R + 2 * K], o[R];
 #pragma unroll
     for (int i = 0; i < R + 2 * K; ++i) x[i] = A[r * SA + q * R + i];
     filter_window_rec<T, R, K>(x, o, [&](int j) { return tp.t[j]; });
 #pragma unroll
     for (int j = 0; j < R; ++j) Bf[r * SB + q * R + j] = o[j];
+    q += dq3;
+    r += dr3;
+    if (r >= NR) r -= NR, ++q;
   }
   __syncthreads();
-  // along x2: task (column c, segment q), consecutive threads on consecutive columns
+  // along x2: task t = q n3 + c (column c, segment q), consecutive threads on consecutive columns
   const int segs2 = BR / R;
+  const int dq2 = NT / n3, dc2 = NT - dq2 * n3;
+  q = tid / n3;
+  int c = tid - q * n3;
   for (int t = tid; t < n3 * segs2; t += NT) {
-    const int q = t / n3, c = t - q * n3;
     T x[R + 2 * K], o[R];
 #pragma unroll
     for (int i = 0; i < R + 2 * K; ++i) x[i] = Bf[(q * R + i) * SB + c];
     filter_window_rec<T, R, K>(x, o, [&](int j) { return tp.t[j]; });
 #pragma unroll
     for (int j = 0; j < R; ++j) out[plane + size_t(r0 + q * R + j) * n3 + c] = o[j];
+    q += dq2;
+    c += dc2;
+    if (c >= n3) c -= n3, ++q;
   }
 }
 
