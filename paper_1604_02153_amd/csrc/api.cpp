@@ -1320,6 +1320,7 @@ struct Context {
     HIPCHK(axpby<T>(stream, B, n, 1.0, nullptr, z, 0.0, nullptr, p));
     HIPCHK(dot<T>(stream, B, n, r, z, partial, rz_dev));
     HIPCHK(pcg_coef(stream, PCG_RZ, B, mk, rz_dev, rz, nullptr, nullptr));
+    std::vector<int> mask_set = active;  // the contents of kMaskPcg (rewritten only on a change)
     for (int it = 1; it <= maxit; ++it) {
       op(p, q, mk, active);
       HIPCHK(dot<T>(stream, B, n, p, q, partial, pq_dev));
@@ -1356,7 +1357,10 @@ struct Context {
       }
       if (!more) return;
       if (it == maxit) break;
-      put_mask(kMaskPcg, active);
+      if (active != mask_set) {
+        put_mask(kMaskPcg, active);
+        mask_set = active;
+      }
       precond(r, z, mk, active);
       HIPCHK(dot<T>(stream, B, n, r, z, partial, rz_dev));
       // p <- z + beta p for the running items; stopped items keep p (coefficients 0, 1)
