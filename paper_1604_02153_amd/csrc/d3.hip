@@ -833,6 +833,19 @@ __global__ void __launch_bounds__(kThreads) k_incstate_start(size_t F, T ht, con
   q[i] = T(0.5) * ht * f;
 }
 
+// out_c = (w . g) g_c: the transport part of the GN matvec at v = 0
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_q_at_zero(size_t F, const T* __restrict__ w, const T* __restrict__ g,
+                                                        T* __restrict__ out) {
+  const size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= F) return;
+  const T g0 = g[i], g1 = g[F + i], g2 = g[2 * F + i];
+  const T wg = w[i] * g0 + w[F + i] * g1 + w[2 * F + i] * g2;
+  out[i] = wg * g0;
+  out[F + i] = wg * g1;
+  out[2 * F + i] = wg * g2;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_axpby(size_t n, T a, const T* __restrict__ x, T b,
                                                     const T* __restrict__ y, T* __restrict__ out) {
@@ -1132,6 +1145,12 @@ hipError_t incstate_start(hipStream_t s, const Dims& d, double ht, const T* vt, 
 }
 
 template <typename T>
+hipError_t q_at_zero(hipStream_t s, const Dims& d, const T* w, const T* g, T* out) {
+  hipLaunchKernelGGL(k_q_at_zero<T>, dim3(blocks_for(d.F())), dim3(kThreads), 0, s, d.F(), w, g, out);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t axpby(hipStream_t s, size_t n, double a, const T* x, double b, const T* y, T* out) {
   const unsigned nb = std::min<size_t>(blocks_for(n), 8192);
   hipLaunchKernelGGL(k_axpby<T>, dim3(nb), dim3(kThreads), 0, s, n, T(a), x, T(b), y, out);
@@ -1170,6 +1189,7 @@ hipError_t reduce(hipStream_t s, size_t n, int mode, const T* a, const T* b, dou
                                T*);                                                                               \
   template hipError_t adjoint_start<T>(hipStream_t, const Dims&, double, const T*, const T*, const T*, T*, T*);  \
   template hipError_t incstate_start<T>(hipStream_t, const Dims&, double, const T*, const T*, T*);               \
+  template hipError_t q_at_zero<T>(hipStream_t, const Dims&, const T*, const T*, T*);                           \
   template hipError_t axpby<T>(hipStream_t, size_t, double, const T*, double, const T*, T*);                     \
   template hipError_t reduce<T>(hipStream_t, size_t, int, const T*, const T*, double*, double*);
 INST(float)

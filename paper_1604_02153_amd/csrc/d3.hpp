@@ -139,6 +139,11 @@ hipError_t adjoint_start(hipStream_t s, const Dims& d, double w, const T* mR, co
 template <typename T>
 hipError_t incstate_start(hipStream_t s, const Dims& d, double ht, const T* vt, const T* gm, T* q);
 
+// out_c = (w . g) g_c (c = 0, 1, 2): the transport part Q w of the GN matvec at v = 0, where m is
+// m_T at every time, m~(1) = -(w . grad m_T) and lambda~ = w . grad m_T throughout (g = grad m_T)
+template <typename T>
+hipError_t q_at_zero(hipStream_t s, const Dims& d, const T* w, const T* g, T* out);
+
 // out = a x + b y over n values (scalars cast to T; x or y may be null for a zero term)
 template <typename T>
 hipError_t axpby(hipStream_t s, size_t n, double a, const T* x, double b, const T* y, T* out);

@@ -594,6 +594,17 @@ class Ctx final : public Base {
     D3CHK(axpby<T>(s_, 3 * F_, 1.0, out, 1.0, sv, out));
   }
 
+  // M s at v = 0 in closed form (the set-up's Lanczos operator): Q S s = K (S s . grad m_T) grad m_T,
+  // grad m_T in gm_ (level 0)
+  void split_matvec_zero(const T* sv, T* out) {
+    const SymArgs S{Sym::RegInvSqrt, p_.reg, p_.beta, 0};
+    apply_symbol(sv, st_, S);
+    D3CHK(q_at_zero<T>(s_, d_, st_, gm_, acc_));
+    project_and_add(0.0, nullptr, out);
+    apply_symbol(out, out, S);
+    D3CHK(axpby<T>(s_, 3 * F_, 1.0, out, 1.0, sv, out));
+  }
+
   // ---- two-level preconditioner (section 3.4.2, "Nested Preconditioner") ---------------------
   // spectral restriction of nf fine fields into the coarse level's fields
   void restrict_to_coarse(const T* f, T* c, int nf) {
@@ -615,9 +626,9 @@ class Ctx final : public Base {
     restrict_to_coarse(mR_, coarse_->mR_, 1);
     restrict_to_coarse(mT_, coarse_->mT_, 1);
     coarse_->images_ = true;
-    D3CHK(hipMemsetAsync(coarse_->trial_, 0, 3 * coarse_->F_ * sizeof(T), s_));
-    coarse_->linearize(coarse_->trial_);
-    emax_setup_ = p_.emax_safety * coarse_->lanczos_max(p_.lanczos_steps, p_.lanczos_seed);
+    // the split operator at v = 0 needs grad m_T alone (m is m_T at every time)
+    coarse_->gradient_of(coarse_->mT_, coarse_->gm_);
+    emax_setup_ = p_.emax_safety * coarse_->lanczos_max(p_.lanczos_steps, p_.lanczos_seed, true);
     emax_ = emax_setup_;
     // e_min = min_k 1 + 1 / (beta a'(k)) over the coarse modes: the largest |k|^2 is at the corner
     const Dims& c = coarse_->d_;
@@ -630,8 +641,9 @@ class Ctx final : public Base {
   void reestimate_emax() { emax_ = p_.emax_safety * coarse_->lanczos_max(p_.lanczos_steps, p_.lanczos_seed); }
 
   // largest Ritz value of 'steps' Lanczos steps on this level's split operator from the
-  // SplitMix64 start vector (no re-orthogonalisation; stops at breakdown)
-  double lanczos_max(int steps, unsigned long long seed) {
+  // SplitMix64 start vector (no re-orthogonalisation; stops at breakdown): at this level's
+  // linearisation, or at v = 0 in closed form (at_zero)
+  double lanczos_max(int steps, unsigned long long seed, bool at_zero = false) {
     const size_t V = 3 * F_;
     const std::vector<double> h = splitmix_uniform(seed, V);
     std::vector<T> ht(h.begin(), h.end());
@@ -645,7 +657,10 @@ class Ctx final : public Base {
     std::vector<double> al, be;
     double beta = 0.0;
     for (int j = 0; j < steps; ++j) {
-      split_matvec(q, w);
+      if (at_zero)
+        split_matvec_zero(q, w);
+      else
+        split_matvec(q, w);
       D3CHK(axpby<T>(s_, V, 1.0, w, -beta, qp, w));
       const double alpha = reduce(0, V, q, w);
       D3CHK(axpby<T>(s_, V, 1.0, w, -alpha, q, w));
