@@ -48,7 +48,8 @@ typedef struct slnk3_ctx slnk3_ctx;
  * pc: SLNK_PC_REG (PCG on H with P_REG) or SLNK_PC_2L (PCG on the split system
  * (I + S Q S) s = -S g, S = (beta A')^{-1/2}, with the nested two-level preconditioner of section
  * 3.4.2 on a coarse grid of n_i / 2 points per axis, every n_i / 2 >= 8); cheb_iters, lanczos_steps,
- * emax_safety, lanczos_seed: CHEB(k) and the Lanczos estimate of e_max at v = 0 as in slnk.h. */
+ * emax_safety, lanczos_seed: CHEB(k) and the Lanczos estimate of e_max at v = 0 as in slnk.h
+ * (lanczos_steps 1 to 1000 with P_2L). */
 typedef struct {
   int n1, n2, n3, nt;
   int reg;

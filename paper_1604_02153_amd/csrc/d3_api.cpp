@@ -14,6 +14,7 @@
 
 #include "../../include/slnk3.h"
 #include "d3.hpp"
+#include "kernels.hpp"
 
 namespace slnk {
 namespace d3 {
@@ -385,6 +386,9 @@ class Ctx final : public Base {
     }
     partial_ = take<double>(size_t(reduce_blocks(V)));
     dres_ = take<double>(8);
+    lz_cap_ = std::min(std::max(p_.lanczos_steps, 1), kMaxLanczos);
+    lz_ = take<double>(4 + 2 * size_t(lz_cap_));
+    lz_live_ = take<int>(1);
   }
 
   void allocate() {
@@ -644,6 +648,7 @@ class Ctx final : public Base {
   // SplitMix64 start vector (no re-orthogonalisation; stops at breakdown): at this level's
   // linearisation, or at v = 0 in closed form (at_zero)
   double lanczos_max(int steps, unsigned long long seed, bool at_zero = false) {
+    if (steps < 1 || steps > lz_cap_) throw Err{SLNK_EINVAL, "lanczos_steps out of range"};
     const size_t V = 3 * F_;
     const std::vector<double> h = splitmix_uniform(seed, V);
     std::vector<T> ht(h.begin(), h.end());
@@ -654,22 +659,38 @@ class Ctx final : public Base {
     const double nq = std::sqrt(reduce(0, V, q, q));  // synchronises before ht is released
     D3CHK(axpby<T>(s_, V, 1.0 / nq, q, 0.0, nullptr, q));
     D3CHK(hipMemsetAsync(qp, 0, V * sizeof(T), s_));
-    std::vector<double> al, be;
-    double beta = 0.0;
+    // the step scalars stay on the device (the 2-D library's k_lanczos_coef, one item); the
+    // (alpha, beta) log is read once
+    double* alpha = lz_;
+    double* beta = lz_ + 1;
+    double* inv = lz_ + 2;
+    double* log = lz_ + 4;
+    const int live = 1;
+    D3CHK(set_ints(s_, lz_live_, &live, 1));
+    D3CHK(fill<double>(s_, 1, 0.0, beta));
     for (int j = 0; j < steps; ++j) {
       if (at_zero)
         split_matvec_zero(q, w);
       else
         split_matvec(q, w);
-      D3CHK(axpby<T>(s_, V, 1.0, w, -beta, qp, w));
-      const double alpha = reduce(0, V, q, w);
-      D3CHK(axpby<T>(s_, V, 1.0, w, -alpha, q, w));
-      al.push_back(alpha);
-      beta = std::sqrt(reduce(0, V, w, w));
-      if (j == steps - 1 || beta <= 1e-14 * std::fabs(alpha)) break;
-      be.push_back(beta);
+      D3CHK((slnk::axpby<T>(s_, 1, V, -1.0, beta, qp, 1.0, nullptr, w)));
+      D3CHK(d3::reduce<T>(s_, V, 0, q, w, partial_, dres_));
+      D3CHK(lanczos_coef(s_, LANCZOS_ALPHA, 1, j, steps, dres_, lz_live_, alpha, beta, inv, log));
+      D3CHK((slnk::axpby<T>(s_, 1, V, -1.0, alpha, q, 1.0, nullptr, w)));
+      D3CHK(d3::reduce<T>(s_, V, 0, w, w, partial_, dres_));
+      D3CHK(lanczos_coef(s_, LANCZOS_BETA, 1, j, steps, dres_, lz_live_, alpha, beta, inv, log));
+      if (j == steps - 1) break;
       std::swap(qp, q);
-      D3CHK(axpby<T>(s_, V, 1.0 / beta, w, 0.0, nullptr, q));
+      D3CHK((slnk::axpby<T>(s_, 1, V, 1.0, inv, w, 0.0, nullptr, q)));  // q <- w / beta
+    }
+    std::vector<double> lg(2 * size_t(steps));
+    D3CHK(hipMemcpyAsync(lg.data(), log, lg.size() * sizeof(double), hipMemcpyDeviceToHost, s_));
+    D3CHK(hipStreamSynchronize(s_));
+    std::vector<double> al, be;
+    for (int j = 0; j < steps; ++j) {
+      al.push_back(lg[2 * j]);
+      if (lg[2 * j + 1] < 0.0) break;  // last step or breakdown
+      be.push_back(lg[2 * j + 1]);
     }
     return tridiag_max_eig(al, be);
   }
@@ -761,6 +782,11 @@ class Ctx final : public Base {
   char* base_ = nullptr;
   size_t used_ = 0;
   double* hres_ = nullptr;
+  // Lanczos: device scalars alpha, beta, 1 / beta, then the (alpha, beta) log of up to lz_cap_ steps
+  static constexpr int kMaxLanczos = 1000;
+  int lz_cap_ = 0;
+  double* lz_ = nullptr;
+  int* lz_live_ = nullptr;
   Twiddles<T> tw_;
   cplx<T>*tw1_ = nullptr, *tw2_ = nullptr, *tw3_ = nullptr;
   T *mR_ = nullptr, *mT_ = nullptr, *v_ = nullptr, *cv_ = nullptr, *divv_ = nullptr, *cdiv_ = nullptr;
@@ -833,7 +859,8 @@ slnk_status slnk3_create(const slnk3_params* p, void* hip_stream, slnk3_ctx** ou
       (p->sl_path != 0 && p->sl_path != 1) || (p->pc != SLNK_PC_REG && p->pc != SLNK_PC_2L))
     return SLNK_EINVAL;
   if (p->pc == SLNK_PC_2L && (!size_ok(p->n1 / 2) || !size_ok(p->n2 / 2) || !size_ok(p->n3 / 2) ||
-                              p->cheb_iters < 1 || p->lanczos_steps < 1 || !(p->emax_safety >= 1.0)))
+                              p->cheb_iters < 1 || p->lanczos_steps < 1 || p->lanczos_steps > 1000 ||
+                              !(p->emax_safety >= 1.0)))
     return SLNK_EINVAL;
   auto ctx = std::make_unique<slnk3_ctx>();
   try {
