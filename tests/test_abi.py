@@ -157,7 +157,8 @@ def test_unet_create_rejects_bad_shapes(pkg, change):
 
 @pytest.mark.parametrize("change", [dict(n1=24), dict(n3=1024), dict(n2=4), dict(nt=0), dict(reg=0), dict(beta=-1.0),
                                     dict(prec=2), dict(proj=2), dict(sl_path=2), dict(pc=3),
-                                    dict(pc=2, n1=8), dict(pc=2, cheb_iters=0), dict(pc=2, emax_safety=0.5)])
+                                    dict(pc=2, n1=8), dict(pc=2, cheb_iters=0), dict(pc=2, emax_safety=0.5),
+                                    dict(pc=2, lanczos_steps=1001)])
 def test_create3_rejects_bad_parameters_before_device_work(pkg, change):
     lib = pkg.load_library()
     p = pkg.Params3()
