@@ -465,6 +465,33 @@ def test_forced_sl_paths_match_oracle(slnk, path):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_tiled_coefficient_pass_on_ragged_grid(slnk, prec):
+    """sl_path = 1 on 96 x 160: the two-kernel step's 2-D coefficient pass (64 x 64 output tiles
+    with their 90-point filter halo staged in LDS) on a grid that leaves partial tiles in both
+    directions and is barely wider than the staged side, so the periodic wraps of the halo are
+    exercised; transport, gradient and matvec against the oracle."""
+    n1, n2 = 96, 160
+    print(f"tiled coefficient pass {n1}x{n2} {prec}", flush=True)
+    L, vgen, vt = problem("gauss", n1, n2, nt=4, beta=1e-3, reg=2, seed=71, amp=0.3)
+    L.mT, L.mR, vgen, vt = same_inputs(prec, L.mT, L.mR, vgen, vt)
+    ctx = _ctx(slnk, L, prec, pc="reg", sl_path=1)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    m1 = torch.empty((n1, n2), dtype=dt, device="cuda")
+    ctx.transport_state(_t(vgen, prec), _t(L.mT, prec), m1)
+    check_rel(f"transport {n1}x{n2} {prec}", _np(m1), O.transport_state(L.grid, vgen, L.mT, 4), TOL[prec]["transport"])
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    v = same_inputs(prec, 0.7 * vgen)
+    lin = O.linearize(L, v)
+    g = torch.empty((2, n1, n2), dtype=dt, device="cuda")
+    ctx.gradient(_t(v, prec), g)
+    _check_reg_op(L, prec, _np(g), O.gradient(lin), v, TOL[prec]["gradient"], "gradient")
+    h = torch.empty_like(g)
+    ctx.hessian_matvec(_t(vt, prec), h)
+    _check_reg_op(L, prec, _np(h), O.hessian_matvec(lin, vt), vt, TOL[prec]["matvec"], "matvec")
+    ctx.close()
+
+
 def test_ragged_batch_matches_single_contexts(slnk):
     """Pairs of three different grid sizes in one ragged batch: every pair's gradient, matvec and
     Newton solve equal those of its own batch-1 context; after autotuning, results still match the
