@@ -64,20 +64,54 @@ hipError_t ensure_lds(K kernel, size_t bytes) {
 // In-place transforms of lines line0 .. line0 + NL - 1 of length n held in LDS as
 // s[k * STRIDE + line], input in bit-reversed order, output in natural order.
 // sign -1: exp(-2 pi i jk/n), +1: exp(+...).
+// Radix-2 stages st (blocks of 2h, h = 2^st) are taken two at a time: a thread owns the four
+// elements a, a + h, a + 2h, a + 3h of a block of 4h and applies both stages' butterflies to them
+// in registers (the same operations in the same order as two separate radix-2 stages, so the
+// results are identical), which halves the barriers and the LDS traffic; an odd last stage runs
+// alone.
 template <typename T, int STRIDE, int NL = STRIDE>
 __device__ void lds_fft(cplx<T>* s, int n, int logn, int sign, const cplx<T>* __restrict__ tw, int line0 = 0) {
   constexpr int CL = STRIDE;
-  const int nb = (n / 2) * NL;
-  for (int st = 0; st < logn; ++st) {
+  auto twiddle = [&](int m) {
+    cplx<T> w = tw[m];
+    if (sign > 0) w.y = -w.y;
+    return w;
+  };
+  int st = 0;
+  for (; st + 1 < logn; st += 2) {
+    const int half = 1 << st;
+    const int ng = (n / 4) * NL;
+    for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+      const int c = line0 + g % NL, q = g / NL;
+      const int j = q & (half - 1);
+      const int ia = ((q >> st) << (st + 2)) + j;
+      const cplx<T> w1 = twiddle(j << (logn - 1 - st));
+      const cplx<T> w2a = twiddle(j << (logn - 2 - st));
+      const cplx<T> w2b = twiddle((j + half) << (logn - 2 - st));
+      const cplx<T> xa = s[ia * CL + c], xb = s[(ia + half) * CL + c];
+      const cplx<T> xc = s[(ia + 2 * half) * CL + c], xd = s[(ia + 3 * half) * CL + c];
+      // stage st: (a, b) and (c, d), twiddle of offset j
+      const cplx<T> tb = cmul(w1, xb), td = cmul(w1, xd);
+      const cplx<T> a1 = cadd(xa, tb), b1 = csub(xa, tb), c1 = cadd(xc, td), d1 = csub(xc, td);
+      // stage st + 1: (a, c) at offset j, (b, d) at offset j + h
+      const cplx<T> tc = cmul(w2a, c1), tdd = cmul(w2b, d1);
+      s[ia * CL + c] = cadd(a1, tc);
+      s[(ia + 2 * half) * CL + c] = csub(a1, tc);
+      s[(ia + half) * CL + c] = cadd(b1, tdd);
+      s[(ia + 3 * half) * CL + c] = csub(b1, tdd);
+    }
+    __syncthreads();
+  }
+  if (st < logn) {  // the last stage alone
     const int half = 1 << st;
     const int tshift = logn - 1 - st;
+    const int nb = (n / 2) * NL;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
       const int c = line0 + b % NL, q = b / NL;
       const int j = q & (half - 1);
       const int i0 = ((q >> st) << (st + 1)) + j;
       const int i1 = i0 + half;
-      cplx<T> w = tw[j << tshift];
-      if (sign > 0) w.y = -w.y;
+      const cplx<T> w = twiddle(j << tshift);
       const cplx<T> x0 = s[i0 * CL + c];
       const cplx<T> x1 = cmul(w, s[i1 * CL + c]);
       s[i0 * CL + c] = cadd(x0, x1);
