@@ -386,6 +386,7 @@ class Ctx final : public Base {
     }
     partial_ = take<double>(size_t(reduce_blocks(V)));
     dres_ = take<double>(8);
+    pcg_sc_ = take<double>(8);
     lz_cap_ = std::min(std::max(p_.lanczos_steps, 1), kMaxLanczos);
     lz_ = take<double>(4 + 2 * size_t(lz_cap_));
     lz_live_ = take<int>(1);
@@ -744,27 +745,43 @@ class Ctx final : public Base {
     if (bnorm == 0.0) return 0;
     prec(r_, z_);
     D3CHK(hipMemcpyAsync(pp_, z_, V * sizeof(T), hipMemcpyDeviceToDevice, s_));
-    double rz = reduce(0, V, r_, z_);
+    // the step coefficients stay on the device (the 2-D library's k_pcg_coef, one item): p.q,
+    // r.r and r.z land in dres_[0..2], and one read per iteration returns p.q, r.r and the r.z
+    // that made the step
+    double* rz = pcg_sc_;
+    double* alpha = pcg_sc_ + 1;
+    double* c0 = pcg_sc_ + 2;
+    double* c1 = pcg_sc_ + 3;
+    D3CHK(d3::reduce<T>(s_, V, 0, r_, z_, partial_, dres_ + 2));
+    D3CHK(pcg_coef(s_, PCG_RZ, 1, nullptr, dres_ + 2, rz, nullptr, nullptr));
     for (int it = 1; it <= maxit; ++it) {
       op(pp_, q_);
       ++rep.matvecs;
-      const double pq = reduce(0, V, pp_, q_);
+      D3CHK(d3::reduce<T>(s_, V, 0, pp_, q_, partial_, dres_));
+      // alpha = rz / pq, 0 where pq is not positive and finite (the updates then leave x, r as
+      // they are)
+      D3CHK(pcg_coef(s_, PCG_ALPHA, 1, nullptr, dres_, rz, alpha, nullptr));
+      D3CHK((slnk::axpby<T>(s_, 1, V, 1.0, alpha, pp_, 1.0, nullptr, x_)));
+      D3CHK((slnk::axpby<T>(s_, 1, V, -1.0, alpha, q_, 1.0, nullptr, r_)));
+      D3CHK(d3::reduce<T>(s_, V, 0, r_, r_, partial_, dres_ + 1));
+      D3CHK(hipMemcpyAsync(hres_, dres_, 2 * sizeof(double), hipMemcpyDeviceToHost, s_));
+      D3CHK(hipMemcpyAsync(hres_ + 2, rz, sizeof(double), hipMemcpyDeviceToHost, s_));
+      D3CHK(hipStreamSynchronize(s_));
+      const double pq = hres_[0], rr = hres_[1], rzh = hres_[2];
       if (!(pq > 0.0)) {
         if (it == 1) D3CHK(hipMemcpyAsync(x_, z_, V * sizeof(T), hipMemcpyDeviceToDevice, s_));
         return it;
       }
-      const double alpha = rz / pq;
-      D3CHK(axpby<T>(s_, V, 1.0, x_, alpha, pp_, x_));
-      D3CHK(axpby<T>(s_, V, 1.0, r_, -alpha, q_, r_));
-      if (std::sqrt(reduce(0, V, r_, r_)) <= tol * bnorm) return it;
-      if (!(rz > 0.0)) {
+      if (std::sqrt(rr) <= tol * bnorm) return it;
+      if (!(rzh > 0.0)) {
         status = kIndefinite;
         return it;
       }
       prec(r_, z_);
-      const double rz_next = reduce(0, V, r_, z_);
-      D3CHK(axpby<T>(s_, V, 1.0, z_, rz_next / rz, pp_, pp_));
-      rz = rz_next;
+      D3CHK(d3::reduce<T>(s_, V, 0, r_, z_, partial_, dres_ + 2));
+      // p <- z + (rz_new / rz) p, rz <- rz_new
+      D3CHK(pcg_coef(s_, PCG_BETA, 1, nullptr, dres_ + 2, rz, c0, c1));
+      D3CHK((slnk::axpby<T>(s_, 1, V, 1.0, c0, z_, 1.0, c1, pp_)));
     }
     return maxit;
   }
@@ -782,6 +799,8 @@ class Ctx final : public Base {
   char* base_ = nullptr;
   size_t used_ = 0;
   double* hres_ = nullptr;
+  // PCG: device scalars rz, alpha, (1, beta) of the step updates
+  double* pcg_sc_ = nullptr;
   // Lanczos: device scalars alpha, beta, 1 / beta, then the (alpha, beta) log of up to lz_cap_ steps
   static constexpr int kMaxLanczos = 1000;
   int lz_cap_ = 0;
