@@ -89,8 +89,9 @@ typedef enum { SLNK_TRANSPORT_SL = 0, SLNK_TRANSPORT_RK2A = 1 } slnk_transport;
  *                 eq. e:hessian-matvec; SLNK_HESS_FN: the full-Newton matvec, whose incremental
  *                 adjoint carries the source div(lambda vt) (eq. e:inc-adj-slm) and whose b~ adds
  *                 lambda grad m~ (table t:computational-complexity-theoretical, FN rows).  FN keeps
- *                 lambda^0..lambda^nt of the last gradient, (6 nt + 5) more fields per item; the
- *                 coarse operator of P_2L stays Gauss--Newton (Chebyshev needs it positive definite)
+ *                 lambda^0..lambda^nt of the last gradient, (6 nt + 5) more fields per item with the
+ *                 SL scheme, (nt + 3) with RK2A; the coarse operator of P_2L stays Gauss--Newton
+ *                 (Chebyshev needs it positive definite)
  *   proj          SLNK_PROJ_NONE (default): the compressible case, K = identity; SLNK_PROJ_LERAY:
  *                 the incompressible case (w = 0), K = the Leray projection b - grad Lap^{-1} div b
  *                 applied to b in the gradient and to b~ in every matvec (section 3.1), on both
@@ -105,8 +106,10 @@ typedef enum { SLNK_TRANSPORT_SL = 0, SLNK_TRANSPORT_RK2A = 1 } slnk_transport;
  *                 "Stabilized RK2 Scheme" -- the state, adjoint, incremental state and incremental
  *                 adjoint equations in antisymmetric form with pseudospectral derivatives, Heun's
  *                 method on the nt steps, and b, b~ in their antisymmetric forms.  Conditionally
- *                 stable: nt must follow the CFL condition (the paper uses CFL 0.2).  With P_REG and
- *                 the Gauss--Newton matvec (the paper's earlier solver); sl_path is ignored */
+ *                 stable: nt must follow the CFL condition (the paper uses CFL 0.2).  With P_REG
+ *                 (the paper's earlier solver) and either matvec: full Newton adds the incremental
+ *                 adjoint's source 1/2 (div(lambda vt) + vt . grad lambda + lambda div vt) and the
+ *                 antisymmetric form of lambda grad m~ to b~; sl_path is ignored */
 typedef struct {
   int n1, n2, nt;
   int reg;

@@ -185,7 +185,7 @@ struct Context {
   bool leray = false;
   // P_2L coarse solver: CHEB(k), or PCG(eps) to eps times the outer tolerance of each item
   bool coarse_pcg = false;
-  // stabilised RK2 transport instead of the SL scheme (fine level; P_REG, Gauss--Newton)
+  // stabilised RK2 transport instead of the SL scheme (fine level; P_REG)
   bool rk2a = false;
   struct {
     T* w3 = nullptr;      // 3F: (y, y v1, y v2) of the Heun stage's input
@@ -198,6 +198,8 @@ struct Context {
     T* pair = nullptr;    // 2F: (lam, lam m)
     T* g4 = nullptr;      // 4F: (grad lam, grad(lam m))
     T* divt = nullptr;    // F: div of the matvec direction
+    T* lam = nullptr;     // (nt+1) F, full Newton: lambda^0..lambda^nt of the last gradient
+    T* gmt = nullptr;     // 2F, full Newton: grad m~^j
   } rk;
   std::vector<double> outer_tol;
   static constexpr int kMaxInner = 200;
@@ -357,8 +359,7 @@ struct Context {
     if (p.transport != SLNK_TRANSPORT_SL && p.transport != SLNK_TRANSPORT_RK2A)
       throw Fail{SLNK_EINVAL, "transport must be SLNK_TRANSPORT_SL or SLNK_TRANSPORT_RK2A"};
     rk2a = p.transport == SLNK_TRANSPORT_RK2A;
-    if (rk2a && (p.pc != SLNK_PC_REG || full_newton))
-      throw Fail{SLNK_EINVAL, "RK2A transport runs with P_REG and the Gauss--Newton matvec"};
+    if (rk2a && p.pc != SLNK_PC_REG) throw Fail{SLNK_EINVAL, "RK2A transport runs with P_REG"};
     two_level = p.pc == SLNK_PC_2L;
     if (two_level) {
       if (!fft_size_ok(p.n1 / 2) || !fft_size_ok(p.n2 / 2)) throw Fail{SLNK_EINVAL, "coarse grid n/2 not supported"};
@@ -381,8 +382,9 @@ struct Context {
     bytes += B * (4 * 2 * F * sizeof(double) + 2 * 2 * size_t(p.n1) * spec_stride(p.n2) * sizeof(cplx<double>)) +
              2 * (p.n1 + p.n2) * sizeof(cplx<double>) + 16 * 256;
     bytes += B * (2 * F * sizeof(T) + sizeof(float)) + 2 * 256;
-    if (full_newton) bytes += B * size_t(6 * p.nt + 5) * F * sizeof(T) + 6 * 256;
+    if (full_newton && !rk2a) bytes += B * size_t(6 * p.nt + 5) * F * sizeof(T) + 6 * 256;
     if (rk2a) bytes += B * size_t(24) * F * sizeof(T) + 14 * 256;  // w3, d3, w3s, d3s 12; k, y, src 5; pair 2; g4 4; divt 1
+    if (rk2a && full_newton) bytes += B * size_t(p.nt + 3) * F * sizeof(T) + 2 * 256;  // lam nt+1; gmt 2
     if (two_level) bytes += B * (2 * size_t(p.lanczos_steps) * sizeof(double) + sizeof(int)) + 2 * 256;  // Lanczos log
     void* base = nullptr;
     if (hipMalloc(&base, bytes) != hipSuccess) throw Fail{SLNK_ENOMEM, "hipMalloc of the workspace failed"};
@@ -405,7 +407,7 @@ struct Context {
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hsc), 16 * B * sizeof(double), hipHostMallocDefault));
     alloc_level(fine, p.n1, p.n2, p.nt);
     if (two_level) alloc_level(coarse, p.n1 / 2, p.n2 / 2, p.nt);
-    if (full_newton) {
+    if (full_newton && !rk2a) {
       fn.lam = arena.take<T>(B * (p.nt + 1) * F);
       fn.mt = arena.take<T>(B * p.nt * F);
       fn.x2 = arena.take<T>(B * 2 * (p.nt + 1) * F);
@@ -424,6 +426,10 @@ struct Context {
       rk.pair = arena.take<T>(B * 2 * F);
       rk.g4 = arena.take<T>(B * 4 * F);
       rk.divt = arena.take<T>(B * F);
+      if (full_newton) {
+        rk.lam = arena.take<T>(B * (p.nt + 1) * F);
+        rk.gmt = arena.take<T>(B * 2 * F);
+      }
     }
     sg64.n1 = p.n1;
     sg64.n2 = p.n2;
@@ -674,45 +680,69 @@ struct Context {
     HIPCHK(rk2a_stage<T>(stream, B, a));
   }
 
-  // acc (init: =, else +=) ht w_j 1/2 (lam grad m^j - m^j grad lam + grad(lam m^j)) at time level j
-  void rk2a_accumulate(Level<T>& lv, int j, const T* lam, T* acc, bool init) {
+  // acc (init: =, else +=) ht w_j 1/2 (lam grad m - m grad lam + grad(lam m)) at time level j for
+  // fields lam, m and the gradient gm of m (item strides sl, sm, sgm)
+  void rk2a_accumulate(Level<T>& lv, int j, const T* lam, long long sl, const T* m, long long sm, const T* gm,
+                       long long sgm, T* acc, bool init) {
     const size_t F = lv.F;
-    const int nt = lv.nt;
-    auto& L = lv.lin[0];
-    const long long sm = (long long)((nt + 1) * F);
-    HIPCHK(rk2a_pair<T>(stream, B, F, lam, (long long)F, L.m + j * F, sm, rk.pair));
+    HIPCHK(rk2a_pair<T>(stream, B, F, lam, sl, m, sm, rk.pair));
     HIPCHK(spec_grad<T>(stream, lv.sg, 2 * B, rk.pair, rk.g4, lv.S1, lv.S2));
-    HIPCHK(rk2a_accum<T>(stream, B, F, trapezoid_weight(j, nt), init ? 1 : 0, lam, (long long)F, L.m + j * F, sm,
-                         L.gm + 2 * j * F, (long long)(2 * (nt + 1) * F), rk.g4, acc, (long long)(2 * F)));
+    HIPCHK(rk2a_accum<T>(stream, B, F, trapezoid_weight(j, lv.nt), init ? 1 : 0, lam, sl, m, sm, gm, sgm, rk.g4, acc,
+                         (long long)(2 * F)));
   }
 
-  // adjoint equation from lam^nt (in rk.y[cur]) backward to t = 0, accumulating b (or b~) into acc;
-  // lam stays in rk.y
-  void rk2a_adjoint_sweep(Level<T>& lv, int cur, T* acc) {
+  // the same with m = m^j, the state of the slot-0 linearisation
+  void rk2a_accumulate_state(Level<T>& lv, int j, const T* lam, long long sl, T* acc, bool init) {
     const size_t F = lv.F;
-    rk2a_accumulate(lv, lv.nt, rk.y[cur], acc, true);
-    HIPCHK(rk2a_prod<T>(stream, B, F, rk.y[cur], (long long)F, lv.lin[0].v, (long long)(2 * F), rk.w3));
-    for (int j = lv.nt; j >= 1; --j) {
-      rk2a_step(lv, 0, +1, +1, rk.y[cur], (long long)F, rk.y[1 - cur], (long long)F, nullptr, nullptr);
-      cur = 1 - cur;
-      rk2a_accumulate(lv, j - 1, rk.y[cur], acc, false);
+    const long long sm = (long long)((lv.nt + 1) * F);
+    auto& L = lv.lin[0];
+    rk2a_accumulate(lv, j, lam, sl, L.m + j * F, sm, L.gm + 2 * j * F, 2 * sm, acc, init);
+  }
+
+  // time level j of an adjoint sweep: every level in rk.lam (keep: the full-Newton gradient), else
+  // two rotating fields
+  T* adj_level(const Level<T>& lv, int j, bool keep) const { return keep ? rk.lam + j * lv.F : rk.y[j % 2]; }
+  long long adj_stride(const Level<T>& lv, bool keep) const {
+    return (long long)(keep ? (lv.nt + 1) * lv.F : lv.F);
+  }
+
+  // adjoint equation d_s y = A y + src from y^nt (at adj_level(nt, keep)) backward to t = 0,
+  // accumulating b (or b~) into acc (init: its first term sets acc).  source(j, out) writes the
+  // equation's source at level j into out and returns out, or returns nullptr (no source).
+  template <class Source>
+  void rk2a_adjoint_sweep(Level<T>& lv, bool keep, T* acc, bool init, Source source) {
+    const size_t F = lv.F;
+    const int nt = lv.nt;
+    const long long sy = adj_stride(lv, keep);
+    rk2a_accumulate_state(lv, nt, adj_level(lv, nt, keep), sy, acc, init);
+    HIPCHK(rk2a_prod<T>(stream, B, F, adj_level(lv, nt, keep), sy, lv.lin[0].v, (long long)(2 * F), rk.w3));
+    const T* s_hi = source(nt, rk.src[nt % 2]);
+    for (int j = nt; j >= 1; --j) {
+      const T* s_lo = source(j - 1, rk.src[(j - 1) % 2]);
+      rk2a_step(lv, 0, +1, +1, adj_level(lv, j, keep), sy, adj_level(lv, j - 1, keep), sy, s_hi, s_lo);
+      rk2a_accumulate_state(lv, j - 1, adj_level(lv, j - 1, keep), sy, acc, false);
+      s_hi = s_lo;
     }
   }
 
-  // b = int 1/2 (lam grad m - m grad lam + grad(lam m)) dt at slot 0 into lv.acc
+  // b = int 1/2 (lam grad m - m grad lam + grad(lam m)) dt at slot 0 into lv.acc; with the
+  // full-Newton matvec every lambda^j stays in rk.lam
   void rk2a_gradient(Level<T>& lv) {
     const size_t F = lv.F;
     const int nt = lv.nt;
     auto& L = lv.lin[0];
+    const bool keep = full_newton;
     HIPCHK(spec_div<T>(stream, lv.sg, B, L.v, lv.divv, lv.S1, lv.S2));
-    HIPCHK(sub_strided<T>(stream, B, F, lv.mR, (long long)F, L.m + nt * F, (long long)((nt + 1) * F), rk.y[0],
-                          (long long)F));
-    rk2a_adjoint_sweep(lv, 0, lv.acc);
+    HIPCHK(sub_strided<T>(stream, B, F, lv.mR, (long long)F, L.m + nt * F, (long long)((nt + 1) * F),
+                          adj_level(lv, nt, keep), adj_stride(lv, keep)));
+    rk2a_adjoint_sweep(lv, keep, lv.acc, true, [](int, T*) -> const T* { return nullptr; });
   }
 
-  // b~ of the Gauss--Newton matvec with RK2A transport at slot 0 into lv.bt: the incremental state
+  // b~ of the matvec with RK2A transport at slot 0 into lv.bt: the incremental state
   // d_t m~ = -L m~ - S(m) vt, S(m) vt = 1/2 (div(m vt) + vt . grad m - m div vt), from m~ = 0; then the
-  // adjoint equation from -m~(1) with b~ in its antisymmetric form
+  // adjoint equation from -m~(1) with b~ in its antisymmetric form.  Full Newton: the incremental
+  // adjoint carries the source 1/2 (div(lam vt) + vt . grad lam + lam div vt) and b~ adds
+  // int 1/2 (lam grad m~ - m~ grad lam + grad(lam m~)) dt, lam from the last gradient.
   void rk2a_transport(Level<T>& lv, const T* vt) {
     const size_t F = lv.F;
     const int nt = lv.nt;
@@ -720,24 +750,32 @@ struct Context {
     const long long sm = (long long)((nt + 1) * F);
     HIPCHK(spec_div<T>(stream, lv.sg, B, L.v, lv.divv, lv.S1, lv.S2));
     HIPCHK(spec_div<T>(stream, lv.sg, B, vt, rk.divt, lv.S1, lv.S2));
-    auto source = [&](int j, T* out) {
-      HIPCHK(rk2a_prod<T>(stream, B, F, L.m + j * F, sm, vt, (long long)(2 * F), rk.w3s));
+    // sgn 1/2 (div(y vt) + vt . grad y + sgn y div vt) into out
+    auto source = [&](const T* y, long long sy, int sgn, T* out) -> const T* {
+      HIPCHK(rk2a_prod<T>(stream, B, F, y, sy, vt, (long long)(2 * F), rk.w3s));
       HIPCHK(spec_rk2a<T>(stream, lv.sg, B, rk.w3s, rk.d3s, lv.S1, lv.S2));
-      HIPCHK(rk2a_eval<T>(stream, B, F, -1, -1, rk.d3s, L.m + j * F, sm, vt, (long long)(2 * F), rk.divt,
-                          (long long)F, out, (long long)F));
+      HIPCHK(rk2a_eval<T>(stream, B, F, sgn, sgn, rk.d3s, y, sy, vt, (long long)(2 * F), rk.divt, (long long)F, out,
+                          (long long)F));
+      return out;
     };
-    source(0, rk.src[0]);
+    source(L.m, sm, -1, rk.src[0]);
     HIPCHK(fill<T>(stream, B * F, 0.0, rk.y[0]));
     HIPCHK(fill<T>(stream, B * 3 * F, 0.0, rk.w3));
     int cur = 0;
     for (int j = 1; j <= nt; ++j) {
-      source(j, rk.src[j % 2]);
+      source(L.m + j * F, sm, -1, rk.src[j % 2]);
       rk2a_step(lv, 0, -1, -1, rk.y[cur], (long long)F, rk.y[1 - cur], (long long)F, rk.src[(j - 1) % 2],
                 rk.src[j % 2]);
       cur = 1 - cur;
+      if (full_newton) {  // the lam grad m~ term at level j (m~^0 = 0 adds nothing)
+        HIPCHK(spec_grad<T>(stream, lv.sg, B, rk.y[cur], rk.gmt, lv.S1, lv.S2));
+        rk2a_accumulate(lv, j, rk.lam + j * F, sm, rk.y[cur], (long long)F, rk.gmt, (long long)(2 * F), lv.bt, j == 1);
+      }
     }
     HIPCHK(axpby<T>(stream, B, F, -1.0, nullptr, rk.y[cur], 0.0, nullptr, rk.y[cur]));  // lam~(1) = -m~(1)
-    rk2a_adjoint_sweep(lv, cur, lv.bt);
+    rk2a_adjoint_sweep(lv, false, lv.bt, !full_newton, [&](int j, T* out) -> const T* {
+      return full_newton ? source(rk.lam + j * F, sm, +1, out) : nullptr;
+    });
   }
 
   void ensure_gm(Level<T>& lv) {

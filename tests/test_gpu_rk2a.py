@@ -1,8 +1,8 @@
 """GPU parity of the stabilised RK2 transport (transport = SLNK_TRANSPORT_RK2A; section 3.3.1 and
 the appendix "Stabilized RK2 Scheme"), through the C ABI, against the FP64 oracle: state solve,
-objective, gradient and Gauss--Newton matvec (FP64 1e-11 plus the FP64 rounding floor of beta A,
-mixed 1e-5 / 1e-4), the Newton--Krylov path with P_REG, batched items against single contexts,
-and the parameter checks."""
+objective, gradient, Gauss--Newton and full-Newton matvecs (FP64 1e-11 plus the FP64 rounding
+floor of beta A, mixed 1e-5 / 1e-4), the Newton--Krylov path with P_REG (both matvecs), batched
+items against single contexts, and the parameter checks."""
 
 import numpy as np
 import pytest
@@ -34,12 +34,12 @@ def _np(t):
     return t.double().cpu().numpy()
 
 
-def _rk_level(kind, n1, n2, nt, beta, reg, prec, seed=2, amp=0.3, proj=0):
+def _rk_level(kind, n1, n2, nt, beta, reg, prec, seed=2, amp=0.3, proj=0, hessian="gn"):
     L, vgen, vt = problem(kind, n1, n2, nt=nt, beta=beta, reg=reg, seed=seed, amp=amp)
     mT, vgen, vt = same_inputs(prec, L.mT, vgen, vt)
     g = L.grid
     mR = same_inputs(prec, O.rk2a_solve_state(g, vgen, mT, nt)[-1])
-    L = O.Level(g, mT, mR, O.Params(nt=nt, beta=beta, reg=reg, transport="rk2a", proj=proj))
+    L = O.Level(g, mT, mR, O.Params(nt=nt, beta=beta, reg=reg, transport="rk2a", proj=proj, hessian=hessian))
     return L, vgen, vt
 
 
@@ -47,7 +47,7 @@ def _ctx(slnk, L, prec, **kw):
     p = L.prm
     reg = {1: "h1", 2: "h2", 3: "h3"}[p.reg]
     return slnk.Context(L.grid.n1, L.grid.n2, p.nt, reg=reg, beta=p.beta, prec=prec, pc="reg", transport="rk2a",
-                        proj="leray" if p.proj else "none", **kw)
+                        proj="leray" if p.proj else "none", hessian=p.hessian, **kw)
 
 
 def cfl_nt(n1, n2, vmax, c=0.2):
@@ -91,6 +91,42 @@ def test_rk2a_transport_gradient_matvec(slnk, case):
     ctx.close()
 
 
+FN_CASES = [
+    ("smooth", 64, 64, cfl_nt(64, 64, 0.5), 1e-2, 1, "fp64"),
+    ("gauss", 96, 80, cfl_nt(96, 80, 0.3), 1e-3, 2, "fp64"),
+    ("gauss", 96, 80, cfl_nt(96, 80, 0.3), 1e-3, 2, "mixed"),
+    ("smooth", 60, 120, cfl_nt(60, 120, 0.5), 1e-2, 1, "mixed"),
+]
+
+
+@pytest.mark.parametrize("case", FN_CASES, ids=lambda c: f"{c[0]}{c[1]}x{c[2]}_nt{c[3]}_{c[6]}")
+def test_rk2a_full_newton_matvec(slnk, case):
+    """The full-Newton matvec with RK2A transport: lambda of the last gradient drives the incremental
+    adjoint's source and the lambda grad m~ term of b~.  Checked at two linearisation points in a row
+    (the second gradient must replace the kept lambda), and the lambda terms must be large against
+    the tolerance, so that a matvec without them fails."""
+    kind, n1, n2, nt, beta, reg, prec = case
+    print(f"rk2a fn case {case}", flush=True)
+    L, vgen, vt = _rk_level(kind, n1, n2, nt, beta, reg, prec, hessian="fn")
+    Lgn = O.Level(L.grid, L.mT, L.mR, O.Params(nt=nt, beta=beta, reg=reg, transport="rk2a"))
+    tol = TOL[prec]
+    ctx = _ctx(slnk, L, prec)
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    g = torch.empty((2, n1, n2), dtype=ctx.dtype, device="cuda")
+    h = torch.empty_like(g)
+    for scale in (0.6, 0.3):
+        v = same_inputs(prec, scale * vgen)
+        lin = O.linearize(L, v)
+        ctx.gradient(_t(v, prec), g)
+        check_reg_op(L, _np(g), O.gradient(lin), v, tol["gradient"], f"RK2A FN gradient {prec}")
+        ref = O.hessian_matvec(lin, vt)
+        ref_gn = O.hessian_matvec(O.linearize(Lgn, v), vt)
+        assert np.linalg.norm(ref - ref_gn) > 100 * tol["matvec"] * np.linalg.norm(ref)
+        ctx.hessian_matvec(_t(vt, prec), h)
+        check_reg_op(L, _np(h), ref, vt, tol["matvec"], f"RK2A FN matvec v={scale} vgen {prec}")
+    ctx.close()
+
+
 def test_rk2a_incompressible_matvec(slnk):
     """K = Leray with RK2A transport (the paper's incompressible runs pair RK2A with P_REG)."""
     prec = "fp64"
@@ -108,18 +144,18 @@ def test_rk2a_incompressible_matvec(slnk):
     ctx.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_rk2a_newton_solve_matches_oracle(slnk, prec):
+@pytest.mark.parametrize("prec,hessian", [("fp64", "gn"), ("mixed", "gn"), ("fp64", "fn")])
+def test_rk2a_newton_solve_matches_oracle(slnk, prec, hessian):
     """P_REG + RK2A on the smooth 64^2 problem: FP64 takes the oracle's Newton path (same Newton and
-    PCG counts, velocity to 1e-9); mixed reaches the stop rule within 1e-3 of the oracle's
-    velocity."""
+    PCG counts, velocity to 1e-9), with the Gauss--Newton and with the full-Newton matvec; mixed
+    reaches the stop rule within 1e-3 of the oracle's velocity."""
     n = 64
     nt = cfl_nt(n, n, 0.5)
     g = O.Grid(n, n)
     mT = same_inputs(prec, synth.smooth_a_template(n, n))
     vstar = synth.smooth_a_velocity(n, n)
     mR = same_inputs(prec, O.rk2a_solve_state(g, vstar, mT, nt)[-1])
-    L = O.Level(g, mT, mR, O.Params(nt=nt, beta=1e-2, reg=1, transport="rk2a"))
+    L = O.Level(g, mT, mR, O.Params(nt=nt, beta=1e-2, reg=1, transport="rk2a", hessian=hessian))
     v_ref, rep_ref = O.newton_solve(L, pc="reg", max_newton=10)
     assert rep_ref["status"] == "ok"
     ctx = _ctx(slnk, L, prec)
@@ -130,14 +166,16 @@ def test_rk2a_newton_solve_matches_oracle(slnk, prec):
     assert rep["status"] == "SLNK_OK" and rep["grel"][-1] <= 1e-2
     if prec == "fp64":
         assert rep["newton_iters"] == rep_ref["newton_iters"] and rep["pcg_iters"] == rep_ref["pcg_iters"]
-    check_rel(f"RK2A Newton v smooth64 {prec}", _np(v), v_ref, 1e-9 if prec == "fp64" else 1e-3)
+    check_rel(f"RK2A Newton ({hessian}) v smooth64 {prec}", _np(v), v_ref, 1e-9 if prec == "fp64" else 1e-3)
     ctx.close()
 
 
-def test_rk2a_batch_items_equal_single_contexts(slnk):
+@pytest.mark.parametrize("hessian", ["gn", "fn"])
+def test_rk2a_batch_items_equal_single_contexts(slnk, hessian):
     n, prec = 64, "mixed"
     nt = cfl_nt(n, n, 0.3)
-    probs = [_rk_level("gauss", n, n, nt, 1e-3, 2, prec, seed=90 + z, amp=0.2 + 0.1 * z) for z in range(2)]
+    probs = [_rk_level("gauss", n, n, nt, 1e-3, 2, prec, seed=90 + z, amp=0.2 + 0.1 * z, hessian=hessian)
+             for z in range(2)]
     cb = _ctx(slnk, probs[0][0], prec, batch=2)
     cb.set_images(_t(np.stack([p[0].mR for p in probs]), prec), _t(np.stack([p[0].mT for p in probs]), prec))
     vb = _t(np.stack([0.5 * p[1] for p in probs]), prec)
@@ -159,7 +197,7 @@ def test_rk2a_batch_items_equal_single_contexts(slnk):
 
 
 def test_rk2a_parameter_checks(slnk):
-    for kw in (dict(pc="2l"), dict(pc="reg", hessian="fn")):
+    for kw in (dict(pc="2l"), dict(pc="2l", hessian="fn")):
         with pytest.raises(slnk.SlnkError) as e:
             slnk.Context(64, 64, 8, reg="h2", beta=1e-3, prec="fp64", transport="rk2a", **kw)
         assert e.value.status == 1, kw
