@@ -240,3 +240,69 @@ def test_newton_solve_in_three_dimensions(pc):
     vs, rep = O.newton_solve(L, pc=pc, max_newton=6)
     assert rep["status"] == "ok" and rep["grel"][-1] <= 1e-2, rep
     assert rep["J"][-1] < 0.2 * rep["J"][0]
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_full_newton_reduces_to_the_two_dimensional_oracle(axis):
+    """The full-Newton matvec of a problem constant along 'axis' with no velocity along it equals
+    the (pinned) 2-D full-Newton matvec on the other two axes, with lambda != 0 and div v != 0."""
+    g3 = _grid()
+    keep = [i for i in range(3) if i != axis]
+    g2 = O.Grid(*(g3.n[i] for i in keep))
+    rng = np.random.default_rng(14 + axis)
+    mT2 = synth.gaussian_sum_isotropic(*g2.n, rng, count=5, sigma=(0.5, 0.9))
+    v2 = synth.random_velocity(*g2.n, rng, modes=6, kmax=2, amplitude=0.5)
+    vt2 = synth.random_velocity(*g2.n, rng, modes=6, kmax=3, amplitude=0.2)
+    prm = O.Params(nt=4, beta=1e-2, reg=2, hessian="fn")
+    mR2 = 0.8 * O.transport_state(g2, v2, mT2, 4) + 0.1
+    L2 = O.Level(g2, mT2, mR2, prm)
+
+    def lift_scalar(u):
+        return np.repeat(np.expand_dims(u, axis), g3.n[axis], axis=axis)
+
+    def lift_vector(w):
+        out = np.zeros((3,) + g3.shape)
+        for j, i in enumerate(keep):
+            out[i] = lift_scalar(w[j])
+        return out
+
+    L3 = O.Level(g3, lift_scalar(mT2), lift_scalar(mR2), prm)
+    a2 = O.hessian_matvec(O.linearize(L2, 0.7 * v2), vt2)
+    a3 = O.hessian_matvec(O.linearize(L3, lift_vector(0.7 * v2)), lift_vector(vt2))
+    sl = [slice(None)] * 3
+    sl[axis] = 0
+    red = np.stack([a3[i][tuple(sl)] for i in keep])
+    scale = np.abs(a2).max()
+    assert np.abs(red - a2).max() < 1e-11 * scale
+    assert np.abs(a3[axis]).max() < 1e-11 * scale
+    L2gn = O.Level(g2, mT2, mR2, O.Params(nt=4, beta=1e-2, reg=2))
+    assert np.abs(O.hessian_matvec(O.linearize(L2gn, 0.7 * v2), vt2) - a2).max() > 1e-3 * scale
+
+
+def test_full_newton_matvec_is_derivative_of_gradient_in_three_dimensions():
+    """SL in 3-D, away from the minimiser and with div v != 0: the full-Newton matvec matches the
+    central difference of the gradient up to the scheme's time error, which falls at about second
+    order in ht (band-limited images, so that the spatial error stays below it); Gauss--Newton stays
+    O(1e-1) away.  A dropped or first-order source term in the incremental adjoint would stall the
+    convergence."""
+    n = 24
+    g = O.Grid(n, n, n)
+    X1, X2, X3 = g.X
+    mT = 0.5 + 0.2 * np.sin(X1) * np.cos(X2) * np.sin(X3) + 0.1 * np.cos(X2 + X3)
+    mR = 0.5 + 0.2 * np.sin(X1 + 0.3) * np.cos(X2) * np.sin(X3 - 0.2) + 0.1 * np.cos(X2 + X3 - 0.1)
+    rng = np.random.default_rng(11)
+    v = synth.random_velocity_3d(n, n, n, rng, modes=5, kmax=1, amplitude=0.3)
+    w = synth.random_velocity_3d(n, n, n, rng, modes=5, kmax=1, amplitude=0.2)
+    assert np.abs(O.fft_div(g, v)).max() > 0.1
+
+    def fd_error(nt, hess):
+        L = O.Level(g, mT, mR, O.Params(nt=nt, beta=1e-3, reg=2, hessian=hess))
+        Hw = O.hessian_matvec(O.linearize(L, v), w)
+        eps = 1e-4
+        fd = (O.gradient(O.linearize(L, v + eps * w)) - O.gradient(O.linearize(L, v - eps * w))) / (2 * eps)
+        return np.linalg.norm(Hw - fd) / np.linalg.norm(fd)
+
+    fn = [fd_error(nt, "fn") for nt in (2, 4, 8)]
+    gn = fd_error(8, "gn")
+    assert fn[0] / fn[1] > 3.0 and fn[1] / fn[2] > 2.5 and fn[2] < 5e-4, fn
+    assert gn > 100 * fn[2], (fn, gn)
