@@ -49,7 +49,10 @@ typedef struct slnk3_ctx slnk3_ctx;
  * (I + S Q S) s = -S g, S = (beta A')^{-1/2}, with the nested two-level preconditioner of section
  * 3.4.2 on a coarse grid of n_i / 2 points per axis, every n_i / 2 >= 8); cheb_iters, lanczos_steps,
  * emax_safety, lanczos_seed: CHEB(k) and the Lanczos estimate of e_max at v = 0 as in slnk.h
- * (lanczos_steps 1 to 1000 with P_2L). */
+ * (lanczos_steps 1 to 1000 with P_2L); hessian: SLNK_HESS_GN (default) or SLNK_HESS_FN, the
+ * full-Newton matvec as in slnk.h (the incremental adjoint with its source div(lambda vt), b~ with
+ * lambda grad m~; lambda^0..lambda^nt of the last gradient kept, nt + 8 more fields; the coarse
+ * operator of P_2L stays Gauss--Newton). */
 typedef struct {
   int n1, n2, n3, nt;
   int reg;
@@ -62,6 +65,7 @@ typedef struct {
   int lanczos_steps;
   double emax_safety;
   unsigned long long lanczos_seed;
+  int hessian;
 } slnk3_params;
 
 /* 64^3, nt = 4, H2, beta = 1e-3, mixed precision, K = identity, P_REG (CHEB(10), 30 Lanczos
@@ -94,8 +98,10 @@ slnk_status slnk3_objective(slnk3_ctx* ctx, const void* v, double* J);
 slnk_status slnk3_gradient(slnk3_ctx* ctx, const void* v, void* g, double* J);
 
 /* Hvt = beta A vt + K int lambda~ grad m dt, the Gauss--Newton matvec at the last linearisation
- * point (eqs. e:hessian-matvec, e:inc-state-slm, e:inc-adj-slm).  SLNK_EINVAL before the first
- * slnk3_gradient or slnk3_objective. */
+ * point (eqs. e:hessian-matvec, e:inc-state-slm, e:inc-adj-slm); with hessian = SLNK_HESS_FN the
+ * full-Newton matvec beta A vt + K int (lambda~ grad m + lambda grad m~) dt.  SLNK_EINVAL before the
+ * first slnk3_gradient or slnk3_objective, and for SLNK_HESS_FN unless the last of them at this
+ * point was slnk3_gradient (the matvec needs its lambda). */
 slnk_status slnk3_hessian_matvec(slnk3_ctx* ctx, const void* vt, void* Hvt);
 
 /* z = P_REG^{-1} r: the spectral inverse of beta A with its zero symbol replaced by 1 (eq.

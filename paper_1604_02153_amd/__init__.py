@@ -59,7 +59,8 @@ class Params3(ctypes.Structure):
     _fields_ = [("n1", ctypes.c_int), ("n2", ctypes.c_int), ("n3", ctypes.c_int), ("nt", ctypes.c_int),
                 ("reg", ctypes.c_int), ("beta", ctypes.c_double), ("prec", ctypes.c_int), ("proj", ctypes.c_int),
                 ("sl_path", ctypes.c_int), ("pc", ctypes.c_int), ("cheb_iters", ctypes.c_int),
-                ("lanczos_steps", ctypes.c_int), ("emax_safety", ctypes.c_double), ("lanczos_seed", ctypes.c_ulonglong)]
+                ("lanczos_steps", ctypes.c_int), ("emax_safety", ctypes.c_double), ("lanczos_seed", ctypes.c_ulonglong),
+                ("hessian", ctypes.c_int)]
 
 
 class UNetParams(ctypes.Structure):
@@ -348,7 +349,7 @@ class Context3:
     [n1, n2, n3], velocities [3, n1, n2, n3] (float32 for prec="mixed", float64 for "fp64")."""
 
     def __init__(self, n1, n2, n3, nt, reg="h2", beta=1e-3, prec="mixed", proj="none", sl_path=0, pc="reg",
-                 cheb_iters=10, lanczos_steps=30, emax_safety=1.05, lanczos_seed=0x5EED, stream=None):
+                 cheb_iters=10, lanczos_steps=30, emax_safety=1.05, lanczos_seed=0x5EED, hessian="gn", stream=None):
         import torch
         lib = load_library()
         p = Params3()
@@ -362,6 +363,7 @@ class Context3:
         p.pc = PC[pc] if isinstance(pc, str) else int(pc)
         p.cheb_iters, p.lanczos_steps = int(cheb_iters), int(lanczos_steps)
         p.emax_safety, p.lanczos_seed = float(emax_safety), int(lanczos_seed)
+        p.hessian = HESSIAN[hessian] if isinstance(hessian, str) else int(hessian)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -430,7 +432,7 @@ class Context3:
         return a.value, b.value
 
     def newton_solve(self, v, opts: SolveOpts | None = None, **kw):
-        """Gauss--Newton--Krylov solve (P_REG or P_2L) in place; the report as a dict."""
+        """Newton--Krylov solve (the GN or FN matvec; P_REG or P_2L) in place; the report as a dict."""
         if opts is None:
             opts = default_opts(**kw)
         rep = SolveReport()

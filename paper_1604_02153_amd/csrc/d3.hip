@@ -672,7 +672,8 @@ __device__ __forceinline__ void step_update(const StepArgs<T>& a, size_t i, size
       break;
     case Kind::Adjoint:
     case Kind::IncAdjoint: {
-      const T l = a.gamma[i] * u;
+      T l = a.gamma[i] * u;
+      if (a.add) l += a.add[i];
       a.dst[i] = l;
       const T wl = T(a.w) * l;
 #pragma unroll
@@ -681,10 +682,12 @@ __device__ __forceinline__ void step_update(const StepArgs<T>& a, size_t i, size
     }
     case Kind::IncState: {
       const T f = -(a.vt[i] * a.gm[i] + a.vt[F + i] * a.gm[F + i] + a.vt[2 * F + i] * a.gm[2 * F + i]);
+      const T mt = u + T(0.5 * a.ht) * f;
+      if (a.mt) a.mt[i] = mt;
       if (!a.last) {
         a.dst[i] = u + T(a.ht) * f;
       } else {
-        const T lt = -(u + T(0.5 * a.ht) * f);
+        const T lt = -mt;
         a.dst[i] = lt;
         const T wl = T(a.w) * lt;
 #pragma unroll
@@ -878,6 +881,37 @@ __global__ void __launch_bounds__(kThreads) k_q_at_zero(size_t F, const T* __res
   out[i] = wg * g0;
   out[F + i] = wg * g1;
   out[2 * F + i] = wg * g2;
+}
+
+// out_c = a v_c (c = 0, 1, 2)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_scale_vec(size_t F, const T* __restrict__ a, const T* __restrict__ v,
+                                                        T* __restrict__ out) {
+  const size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= F) return;
+  const T s = a[i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) out[c * F + i] = s * v[c * F + i];
+}
+
+// out = ht/2 (1 + ht divv) e + ht/2 sig
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_fn_source(size_t F, T ht, const T* __restrict__ divv, const T* e,
+                                                        const T* __restrict__ sig, T* out) {  // out may be e
+  const size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= F) return;
+  out[i] = T(0.5) * ht * (T(1) + ht * divv[i]) * e[i] + T(0.5) * ht * sig[i];
+}
+
+// acc_c (init: =, else +=) w lam g_c (c = 0, 1, 2)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_acc_scalar_grad(size_t F, T w, int init, const T* __restrict__ lam,
+                                                              const T* __restrict__ g, T* __restrict__ acc) {
+  const size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= F) return;
+  const T wl = w * lam[i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) acc[c * F + i] = init ? wl * g[c * F + i] : acc[c * F + i] + wl * g[c * F + i];
 }
 
 template <typename T>
@@ -1185,6 +1219,25 @@ hipError_t q_at_zero(hipStream_t s, const Dims& d, const T* w, const T* g, T* ou
 }
 
 template <typename T>
+hipError_t scale_vec(hipStream_t s, const Dims& d, const T* a, const T* v, T* out) {
+  hipLaunchKernelGGL(k_scale_vec<T>, dim3(blocks_for(d.F())), dim3(kThreads), 0, s, d.F(), a, v, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fn_source(hipStream_t s, const Dims& d, double ht, const T* divv, const T* e, const T* sig, T* out) {
+  hipLaunchKernelGGL(k_fn_source<T>, dim3(blocks_for(d.F())), dim3(kThreads), 0, s, d.F(), T(ht), divv, e, sig, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t acc_scalar_grad(hipStream_t s, const Dims& d, double w, int init, const T* lam, const T* g, T* acc) {
+  hipLaunchKernelGGL(k_acc_scalar_grad<T>, dim3(blocks_for(d.F())), dim3(kThreads), 0, s, d.F(), T(w), init, lam, g,
+                     acc);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t axpby(hipStream_t s, size_t n, double a, const T* x, double b, const T* y, T* out) {
   const unsigned nb = std::min<size_t>(blocks_for(n), 8192);
   hipLaunchKernelGGL(k_axpby<T>, dim3(nb), dim3(kThreads), 0, s, n, T(a), x, T(b), y, out);
@@ -1224,6 +1277,9 @@ hipError_t reduce(hipStream_t s, size_t n, int mode, const T* a, const T* b, dou
   template hipError_t adjoint_start<T>(hipStream_t, const Dims&, double, const T*, const T*, const T*, T*, T*);  \
   template hipError_t incstate_start<T>(hipStream_t, const Dims&, double, const T*, const T*, T*);               \
   template hipError_t q_at_zero<T>(hipStream_t, const Dims&, const T*, const T*, T*);                           \
+  template hipError_t scale_vec<T>(hipStream_t, const Dims&, const T*, const T*, T*);                           \
+  template hipError_t fn_source<T>(hipStream_t, const Dims&, double, const T*, const T*, const T*, T*);         \
+  template hipError_t acc_scalar_grad<T>(hipStream_t, const Dims&, double, int, const T*, const T*, T*);        \
   template hipError_t axpby<T>(hipStream_t, size_t, double, const T*, double, const T*, T*);                     \
   template hipError_t reduce<T>(hipStream_t, size_t, int, const T*, const T*, double*, double*);
 INST(float)

@@ -98,10 +98,10 @@ hipError_t spec_prolong_combine(hipStream_t s, const Dims& fine, const Dims& coa
 // cubic spline with B-spline coefficients coef at the departure point, displacement in cells),
 // then, by kind:
 //   State       dst = u
-//   Adjoint     lam = gamma u; dst = lam; acc += w lam gm
-//   IncState    f = -(vt . gm); mt = u + ht/2 f; not last: dst = u + ht f (the next step's
-//               transported field m~ + ht/2 f); last: dst = -mt, acc = w (-mt) gm
-//   IncAdjoint  lt = gamma u; dst = lt; acc += w lt gm
+//   Adjoint     lam = gamma u (+ add); dst = lam; acc += w lam gm
+//   IncState    f = -(vt . gm); mt = u + ht/2 f (into 'mt' when given); not last: dst = u + ht f
+//               (the next step's transported field m~ + ht/2 f); last: dst = -mt, acc = w (-mt) gm
+//   IncAdjoint  lt = gamma u (+ add: the full-Newton source); dst = lt; acc += w lt gm
 // (gm: gradient of the state at the output's time level; eqs. e:state-slm, e:adj-slm,
 // e:inc-state-slm, e:inc-adj-slm).
 enum class Kind : int { State = 0, Adjoint = 1, IncState = 2, IncAdjoint = 3 };
@@ -116,6 +116,8 @@ struct StepArgs {
   const T* vt = nullptr;
   T* dst = nullptr;
   T* acc = nullptr;
+  const T* add = nullptr;  // Adjoint / IncAdjoint: a field added to gamma u (optional)
+  T* mt = nullptr;         // IncState: m~ at the output's time level (optional)
   double w = 0.0, ht = 0.0;
   int last = 0;
   int halo = -1;  // whole cells bounding |disp| (the LDS-staged kernel when its footprint fits), or -1
@@ -143,6 +145,18 @@ hipError_t incstate_start(hipStream_t s, const Dims& d, double ht, const T* vt, 
 // m_T at every time, m~(1) = -(w . grad m_T) and lambda~ = w . grad m_T throughout (g = grad m_T)
 template <typename T>
 hipError_t q_at_zero(hipStream_t s, const Dims& d, const T* w, const T* g, T* out);
+
+// Full-Newton matvec terms (eq. e:inc-adj-slm with its lambda source; b~ with lambda grad m~):
+// out_c = a v_c (c = 0, 1, 2), the product lambda vt whose divergence is the source sigma
+template <typename T>
+hipError_t scale_vec(hipStream_t s, const Dims& d, const T* a, const T* v, T* out);
+// out = ht/2 (1 + ht divv) e + ht/2 sig: Heun's source terms of one incremental adjoint step along the
+// adjoint characteristic, e = sigma^j at the departure point, sig = sigma^{j-1} at the node (out may be e)
+template <typename T>
+hipError_t fn_source(hipStream_t s, const Dims& d, double ht, const T* divv, const T* e, const T* sig, T* out);
+// acc_c (init: =, else +=) w lam g_c (c = 0, 1, 2)
+template <typename T>
+hipError_t acc_scalar_grad(hipStream_t s, const Dims& d, double w, int init, const T* lam, const T* g, T* acc);
 
 // out = a x + b y over n values (scalars cast to T; x or y may be null for a zero term)
 template <typename T>

@@ -110,6 +110,7 @@ class Ctx final : public Base {
     Fh_ = d_.Fh();
     ht_ = 1.0 / p.nt;
     cell_ = std::pow(2.0 * 3.14159265358979323846, 3) / double(F_);
+    fn_ = p.hessian == SLNK_HESS_FN;
     try {
       allocate();
       if (p.pc == SLNK_PC_2L) {  // the coarse level: half the points per axis, GN, its own workspace
@@ -118,6 +119,7 @@ class Ctx final : public Base {
         pc.n2 /= 2;
         pc.n3 /= 2;
         pc.pc = SLNK_PC_REG;
+        pc.hessian = SLNK_HESS_GN;
         coarse_ = std::make_unique<Ctx<T>>(pc, s);
       }
     } catch (...) {
@@ -140,6 +142,7 @@ class Ctx final : public Base {
 
   void transport_state(const void* v, const void* m0, void* m1) override {
     lin_ = false;
+    lam_ok_ = false;
     trace_at(static_cast<const T*>(v));
     const T* cur = static_cast<const T*>(m0);
     T* bufs[2] = {lam0_, lam1_};
@@ -390,6 +393,14 @@ class Ctx final : public Base {
     lz_cap_ = std::min(std::max(p_.lanczos_steps, 1), kMaxLanczos);
     lz_ = take<double>(4 + 2 * size_t(lz_cap_));
     lz_live_ = take<int>(1);
+    if (fn_) {
+      lamk_ = take<T>(size_t(nt + 1) * F_);
+      sig_[0] = take<T>(F_);
+      sig_[1] = take<T>(F_);
+      e_ = take<T>(F_);
+      mtj_ = take<T>(F_);
+      accfn_ = take<T>(V);
+    }
   }
 
   void allocate() {
@@ -505,25 +516,56 @@ class Ctx final : public Base {
     J_ = 0.5 * cell_ * mis + 0.5 * p_.beta * cell_ * reg;
     if (!std::isfinite(J_)) throw Err{SLNK_ENAN, "non-finite objective"};
     lin_ = true;
+    lam_ok_ = false;
     coarse_lin_ = false;
   }
 
-  // g = beta A v + K b, b = int lambda grad m dt (adjoint eq. e:adj-slm backward from lambda(1) = m_R - m(1))
+  // g = beta A v + K b, b = int lambda grad m dt (adjoint eq. e:adj-slm backward from lambda(1) = m_R - m(1));
+  // the full-Newton context keeps lambda^0..lambda^nt in lamk_
   void gradient_at(T* g) {
     const size_t V = 3 * F_;
     const int nt = p_.nt;
-    D3CHK(adjoint_start<T>(s_, d_, trap_w(nt, nt), mR_, m_ + size_t(nt) * F_, gm_ + size_t(nt) * V, lam1_, acc_));
-    backward_sweep(lam1_, Kind::Adjoint);
+    T* lam1 = fn_ ? lamk_ + size_t(nt) * F_ : lam1_;
+    D3CHK(adjoint_start<T>(s_, d_, trap_w(nt, nt), mR_, m_ + size_t(nt) * F_, gm_ + size_t(nt) * V, lam1, acc_));
+    backward_sweep(lam1, Kind::Adjoint);
     project_and_add(p_.beta, Av_, g);
+    lam_ok_ = true;
+  }
+
+  // sigma^j = div(lambda^j vt), the source of the full-Newton incremental adjoint at time level j
+  void sigma_at(int j, const T* vt, T* out) {
+    D3CHK(scale_vec<T>(s_, d_, lamk_ + size_t(j) * F_, vt, t3b_));
+    divergence_of(t3b_, out);
   }
 
   // adjoint-type sweep j = nt .. 1 from the field in 'start': lambda^{j-1} = gamma I[lambda^j](x + da),
-  // acc += w_{j-1} lambda^{j-1} grad m^{j-1}
-  void backward_sweep(T* start, Kind kind) {
+  // acc += w_{j-1} lambda^{j-1} grad m^{j-1}.  The full-Newton context keeps every adjoint level in
+  // lamk_; with vt given (full-Newton incremental adjoint), Heun's step along the adjoint
+  // characteristic adds the source sigma = div(lambda vt): ht/2 (1 + ht div v) sigma^j at the
+  // departure point and ht/2 sigma^{j-1} at the node.
+  void backward_sweep(T* start, Kind kind, const T* vt = nullptr) {
     const size_t V = 3 * F_;
+    const bool keep = fn_ && kind == Kind::Adjoint;
     T* cur = start;
     T* nxt = start == lam0_ ? lam1_ : lam0_;
+    if (vt) sigma_at(p_.nt, vt, sig_[p_.nt % 2]);
     for (int j = p_.nt; j >= 1; --j) {
+      if (keep) nxt = lamk_ + size_t(j - 1) * F_;
+      const T* add = nullptr;
+      if (vt) {
+        sigma_at(j - 1, vt, sig_[(j - 1) % 2]);
+        coefficients(sig_[j % 2], coef_, 1);
+        StepArgs<T> b;
+        b.d = d_;
+        b.halo = halo_;
+        b.kind = Kind::State;
+        b.coef = coef_;
+        b.disp = da_;
+        b.dst = e_;
+        D3CHK(sl_step<T>(s_, b));
+        D3CHK(fn_source<T>(s_, d_, ht_, divv_, e_, sig_[(j - 1) % 2], e_));
+        add = e_;
+      }
       coefficients(cur, coef_, 1);
       StepArgs<T> a;
       a.d = d_;
@@ -535,9 +577,13 @@ class Ctx final : public Base {
       a.gm = gm_ + size_t(j - 1) * V;
       a.dst = nxt;
       a.acc = acc_;
+      a.add = add;
       a.w = trap_w(j - 1, p_.nt);
       D3CHK(sl_step<T>(s_, a));
-      std::swap(cur, nxt);
+      if (keep)
+        cur = nxt;
+      else
+        std::swap(cur, nxt);
     }
   }
 
@@ -553,10 +599,14 @@ class Ctx final : public Base {
 
   // Gauss--Newton matvec: incremental state (eq. e:inc-state-slm) forward from m~(0) = 0, the
   // incremental adjoint (eq. e:inc-adj-slm, lambda terms dropped) backward from -m~(1), then
-  // beta A vt + K int lambda~ grad m dt (with_reg false: the transport part Q alone)
+  // beta A vt + K int lambda~ grad m dt (with_reg false: the transport part Q alone).  Full Newton:
+  // the incremental adjoint keeps its source div(lambda vt) and b~ adds int lambda grad m~ dt,
+  // lambda from the gradient at this linearisation.
   void matvec(const T* vt, T* out, bool with_reg = true) {
     const size_t V = 3 * F_;
     const int nt = p_.nt;
+    if (fn_ && !lam_ok_)
+      throw Err{SLNK_EINVAL, "the full-Newton matvec needs the gradient at this point (slnk3_gradient)"};
     D3CHK(incstate_start<T>(s_, d_, ht_, vt, gm_, lam0_));
     T* cur = lam0_;
     T* nxt = lam1_;
@@ -575,10 +625,16 @@ class Ctx final : public Base {
       a.w = trap_w(nt, nt);
       a.ht = ht_;
       a.last = j == nt;
+      a.mt = fn_ ? mtj_ : nullptr;
       D3CHK(sl_step<T>(s_, a));
+      if (fn_) {  // lambda^j grad m~^j (m~^0 = 0 adds nothing)
+        gradient_of(mtj_, t3a_);
+        D3CHK(acc_scalar_grad<T>(s_, d_, trap_w(j, nt), j == 1, lamk_ + size_t(j) * F_, t3a_, accfn_));
+      }
       std::swap(cur, nxt);
     }
-    backward_sweep(cur, Kind::IncAdjoint);
+    backward_sweep(cur, Kind::IncAdjoint, fn_ ? vt : nullptr);
+    if (fn_) D3CHK(axpby<T>(s_, V, 1.0, acc_, 1.0, accfn_, acc_));
     if (with_reg) {
       reg_apply(vt, t3a_, p_.beta);
       project_and_add(1.0, t3a_, out);
@@ -796,6 +852,15 @@ class Ctx final : public Base {
   bool coarse_lin_ = false;          // the coarse level is linearised at the restricted current point
   double emin_ = 0.0, emax_ = 0.0, emax_setup_ = 0.0;
   bool images_ = false, lin_ = false;
+  // full-Newton matvec (this level; the coarse level of P_2L stays Gauss--Newton): lambda^0..nt of
+  // the last gradient (lam_ok_: taken at the current linearisation), sigma at two levels, the
+  // interpolated source, m~^j, and the lambda grad m~ part of b~
+  bool fn_ = false, lam_ok_ = false;
+  T* lamk_ = nullptr;
+  T* sig_[2] = {};
+  T* e_ = nullptr;
+  T* mtj_ = nullptr;
+  T* accfn_ = nullptr;
   char* base_ = nullptr;
   size_t used_ = 0;
   double* hres_ = nullptr;
@@ -866,6 +931,7 @@ void slnk3_default_params(slnk3_params* p) {
   p->lanczos_steps = 30;
   p->emax_safety = 1.05;
   p->lanczos_seed = 0x5EED;
+  p->hessian = SLNK_HESS_GN;
 }
 
 slnk_status slnk3_create(const slnk3_params* p, void* hip_stream, slnk3_ctx** out) {
@@ -875,7 +941,8 @@ slnk_status slnk3_create(const slnk3_params* p, void* hip_stream, slnk3_ctx** ou
   if (!size_ok(p->n1) || !size_ok(p->n2) || !size_ok(p->n3) || p->nt < 1 || p->nt > 1000 || p->reg < 1 ||
       p->reg > 3 || !(p->beta > 0.0) || !std::isfinite(p->beta) ||
       (p->prec != SLNK_PREC_FP64 && p->prec != SLNK_PREC_MIXED) || (p->proj != 0 && p->proj != 1) ||
-      (p->sl_path != 0 && p->sl_path != 1) || (p->pc != SLNK_PC_REG && p->pc != SLNK_PC_2L))
+      (p->sl_path != 0 && p->sl_path != 1) || (p->pc != SLNK_PC_REG && p->pc != SLNK_PC_2L) ||
+      (p->hessian != SLNK_HESS_GN && p->hessian != SLNK_HESS_FN))
     return SLNK_EINVAL;
   if (p->pc == SLNK_PC_2L && (!size_ok(p->n1 / 2) || !size_ok(p->n2 / 2) || !size_ok(p->n3 / 2) ||
                               p->cheb_iters < 1 || p->lanczos_steps < 1 || p->lanczos_steps > 1000 ||

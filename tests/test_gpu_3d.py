@@ -1,9 +1,11 @@
 """GPU parity of the three-dimensional path (include/slnk3.h; the method for d = 3, section 1
 "Limitations and Unresolved Issues"), through the C ABI, against the FP64 oracle on the same
-inputs: state transport, objective, reduced gradient (K = I and Leray), Gauss--Newton matvec,
-P_REG and the Newton--Krylov solve, on cubes and on grids with a different size per axis, in FP64
+inputs: state transport, objective, reduced gradient (K = I and Leray), Gauss--Newton and
+full-Newton matvecs, P_REG and the Newton--Krylov solve, on cubes and on grids with a different size per axis, in FP64
 and mixed precision; at the benchmark size, the properties that hold at any size (exact
 integer-cell shifts, the closed forms at v = 0, which the oracle evaluates spectrally)."""
+
+from dataclasses import replace
 
 import numpy as np
 import pytest
@@ -50,10 +52,10 @@ def _level(shape, prec, nt=4, beta=1e-3, reg=2, proj=0, seed=3, amp=0.4):
     return O.Level(g, mT, mR, O.Params(nt=nt, beta=beta, reg=reg, proj=proj)), vgen, vt
 
 
-def _ctx(slnk, L, prec, sl_path=0):
+def _ctx(slnk, L, prec, sl_path=0, **kw):
     p = L.prm
     return slnk.Context3(*L.grid.shape, p.nt, reg=p.reg, beta=p.beta, prec=prec, proj="leray" if p.proj else "none",
-                         sl_path=sl_path)
+                         sl_path=sl_path, hessian=p.hessian, **kw)
 
 
 def _amax(L):
@@ -113,6 +115,62 @@ def test_gradient_and_matvec_match_oracle(slnk, prec, shape, reg, proj, sl_path)
     if proj:  # the projected part of the gradient, g - beta A v, is divergence free
         kb = _np(gt) - L.prm.beta * O.apply_reg(g, v, reg)
         assert np.abs(O.fft_div(g, kb)).max() < TOL3[prec]["gradient"] * np.abs(kb).max() * max(g.shape)
+    ctx.close()
+
+
+FN_CASES = [((16, 16, 16), 2, 0, 0), ((16, 16, 16), 2, 0, 1), ((8, 16, 32), 2, 0, 0), ((16, 8, 16), 3, 1, 0)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape,reg,proj,sl_path", FN_CASES)
+def test_full_newton_matvec_matches_oracle(slnk, prec, shape, reg, proj, sl_path):
+    """The 3-D full-Newton matvec (incremental adjoint with its source div(lambda vt), b~ with
+    lambda grad m~) at two linearisation points in a row, each after its gradient; the lambda terms
+    are large against the tolerance.  After slnk3_objective alone the matvec is refused (its lambda
+    would belong to another point)."""
+    L, vgen, vt = _level(shape, prec, reg=reg, proj=proj)
+    L = O.Level(L.grid, L.mT, L.mR, replace(L.prm, hessian="fn"))
+    Lgn = O.Level(L.grid, L.mT, L.mR, replace(L.prm, hessian="gn"))
+    g = L.grid
+    print(f"fn case {shape} reg{reg} proj{proj} sl_path{sl_path} {prec}", flush=True)
+    ctx = _ctx(slnk, L, prec, sl_path)
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    gt = torch.empty((3,) + g.shape, dtype=ctx.dtype, device="cuda")
+    ht = torch.empty_like(gt)
+    for scale in (0.6, 0.3):
+        v = same_inputs(prec, scale * vgen)
+        lin = O.linearize(L, v)
+        ctx.gradient(_t(v, prec), gt)
+        href = O.hessian_matvec(lin, vt)
+        hgn = O.hessian_matvec(O.linearize(Lgn, v), vt)
+        tol = _matvec_tol(L, prec, vt, href)
+        assert np.linalg.norm(href - hgn) > 50 * tol * np.linalg.norm(href)
+        ctx.hessian_matvec(_t(vt, prec), ht)
+        check_rel(f"3d FN matvec v={scale} vgen {shape} reg{reg} proj{proj} {prec}", _np(ht), href, tol)
+    ctx.objective(_t(same_inputs(prec, 0.5 * vgen), prec))
+    with pytest.raises(slnk.SlnkError) as e:
+        ctx.hessian_matvec(_t(vt, prec), ht)
+    assert e.value.status == 1
+    ctx.close()
+
+
+@pytest.mark.parametrize("pc", ["reg", "2l"])
+def test_full_newton_solve_fp64_matches_oracle(slnk, pc):
+    """Newton--Krylov with the full-Newton matvec in 3-D (P_REG, and P_2L whose coarse operator
+    stays Gauss--Newton): the oracle's Newton and PCG counts and its velocity to 1e-9."""
+    shape, prec = (16, 16, 16), "fp64"
+    L, _, _ = _level(shape, prec, beta=1e-3)
+    L = O.Level(L.grid, L.mT, L.mR, replace(L.prm, hessian="fn"))
+    vs, rep = O.newton_solve(L, pc=pc, max_newton=6)
+    ctx = _ctx(slnk, L, prec, pc=pc)
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    v = torch.zeros((3,) + shape, dtype=ctx.dtype, device="cuda")
+    r = ctx.newton_solve(v, max_newton=6)
+    print("oracle", rep["newton_iters"], rep["pcg_iters"], rep["grel"], "gpu", r["newton_iters"], r["pcg_iters"],
+          r["grel"], flush=True)
+    assert r["status"] == "SLNK_OK" and rep["status"] == "ok" and r["grel"][-1] <= 1e-2
+    assert (r["newton_iters"], r["pcg_iters"]) == (rep["newton_iters"], rep["pcg_iters"])
+    check_rel(f"3d FN newton v fp64 {pc}", _np(v), vs, 1e-9)
     ctx.close()
 
 
