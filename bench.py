@@ -489,7 +489,7 @@ def d3_matvec_bytes(n, nt, elem=4):
     return (25 + 30 * nt) * n ** 3 * elem
 
 
-def d3_setup(dev, prec, n=128, sl_path=0, pc="reg"):
+def d3_setup(dev, prec, n=128, sl_path=0, pc="reg", hessian="gn"):
     import numpy as np
     import torch
 
@@ -499,7 +499,7 @@ def d3_setup(dev, prec, n=128, sl_path=0, pc="reg"):
     dt = torch.float32 if prec == "mixed" else torch.float64
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)
     vt = synth.random_velocity_3d(n, n, n, np.random.default_rng(1234), amplitude=0.1)
-    ctx = Context3(n, n, n, nt, reg=reg, beta=beta, prec=prec, sl_path=sl_path, pc=pc)
+    ctx = Context3(n, n, n, nt, reg=reg, beta=beta, prec=prec, sl_path=sl_path, pc=pc, hessian=hessian)
     mT_t, vgen_t = t(mT), t(vgen)
     mR_t = torch.empty_like(mT_t)
     ctx.transport_state(vgen_t, mT_t, mR_t)
@@ -565,6 +565,29 @@ def d3_workload(args, dev):
             out["mixed_global_gather_matvec_ms"] = round(1e3 * (time.perf_counter() - t0) / reps, 3)
             ctx1.close()
             del g1, vgen1, vt1
+            # the full-Newton matvec (incremental adjoint with its div(lambda vt) source, b~ with
+            # lambda grad m~) at v_gen / 2, where lambda != 0, and a full-Newton P_2L solve from v = 0
+            ctxf, mRf, mTf, vgenf, vtf, _, _ = d3_setup(dev, prec, pc="2l", hessian="fn")
+            ctxf.set_images(mRf, mTf)
+            gf = torch.empty_like(vgenf)
+            ctxf.gradient(0.5 * vgenf, gf)
+            ctxf.hessian_matvec(vtf, gf)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctxf.hessian_matvec(vtf, gf)
+            torch.cuda.synchronize()
+            fn_mv_ms = 1e3 * (time.perf_counter() - t0) / reps
+            vf = torch.zeros_like(vgenf)
+            repf = ctxf.newton_solve(vf)
+            out["mixed_full_newton"] = {
+                "matvec_ms": round(fn_mv_ms, 3), "matvec_at": "v_gen / 2",
+                "two_level_solve": {"solve_ms": round(repf["time_total_ms"], 2), "newton_iters": repf["newton_iters"],
+                                    "pcg_iters": repf["pcg_iters"], "coarse_matvecs": repf["coarse_matvecs"],
+                                    "grel_final": repf["grel"][-1], "status": repf["status"]},
+                "workspace_GB": round(ctxf.workspace_bytes() / 1e9, 3)}
+            ctxf.close()
+            del gf, vf, mRf, mTf, vgenf, vtf
         # the same problem with P_2L (coarse grid 64^3, CHEB(10), 30 Lanczos steps at set-up)
         ctx2, mR2, mT2, vgen2, _, _, _ = d3_setup(dev, prec, pc="2l")
         v2 = torch.zeros_like(vgen2)
