@@ -52,7 +52,10 @@ typedef struct slnk3_ctx slnk3_ctx;
  * (lanczos_steps 1 to 1000 with P_2L); hessian: SLNK_HESS_GN (default) or SLNK_HESS_FN, the
  * full-Newton matvec as in slnk.h (the incremental adjoint with its source div(lambda vt), b~ with
  * lambda grad m~; lambda^0..lambda^nt of the last gradient kept, nt + 8 more fields; the coarse
- * operator of P_2L stays Gauss--Newton). */
+ * operator of P_2L stays Gauss--Newton); coarse_solver, coarse_eps: P_2L's coarse solver as in
+ * slnk.h, SLNK_COARSE_CHEB (default, CHEB(cheb_iters)) or SLNK_COARSE_PCG (the nested PCG(eps) solve:
+ * CG on the coarse split operator from zero to coarse_eps times the outer PCG tolerance, 1 in
+ * slnk3_precond_apply, at most 200 steps; coarse_eps in (0, 1), default 0.1). */
 typedef struct {
   int n1, n2, n3, nt;
   int reg;
@@ -66,6 +69,8 @@ typedef struct {
   double emax_safety;
   unsigned long long lanczos_seed;
   int hessian;
+  int coarse_solver;
+  double coarse_eps;
 } slnk3_params;
 
 /* 64^3, nt = 4, H2, beta = 1e-3, mixed precision, K = identity, P_REG (CHEB(10), 30 Lanczos

@@ -60,7 +60,7 @@ class Params3(ctypes.Structure):
                 ("reg", ctypes.c_int), ("beta", ctypes.c_double), ("prec", ctypes.c_int), ("proj", ctypes.c_int),
                 ("sl_path", ctypes.c_int), ("pc", ctypes.c_int), ("cheb_iters", ctypes.c_int),
                 ("lanczos_steps", ctypes.c_int), ("emax_safety", ctypes.c_double), ("lanczos_seed", ctypes.c_ulonglong),
-                ("hessian", ctypes.c_int)]
+                ("hessian", ctypes.c_int), ("coarse_solver", ctypes.c_int), ("coarse_eps", ctypes.c_double)]
 
 
 class UNetParams(ctypes.Structure):
@@ -349,7 +349,8 @@ class Context3:
     [n1, n2, n3], velocities [3, n1, n2, n3] (float32 for prec="mixed", float64 for "fp64")."""
 
     def __init__(self, n1, n2, n3, nt, reg="h2", beta=1e-3, prec="mixed", proj="none", sl_path=0, pc="reg",
-                 cheb_iters=10, lanczos_steps=30, emax_safety=1.05, lanczos_seed=0x5EED, hessian="gn", stream=None):
+                 cheb_iters=10, lanczos_steps=30, emax_safety=1.05, lanczos_seed=0x5EED, hessian="gn",
+                 coarse_solver="cheb", coarse_eps=0.1, stream=None):
         import torch
         lib = load_library()
         p = Params3()
@@ -364,6 +365,8 @@ class Context3:
         p.cheb_iters, p.lanczos_steps = int(cheb_iters), int(lanczos_steps)
         p.emax_safety, p.lanczos_seed = float(emax_safety), int(lanczos_seed)
         p.hessian = HESSIAN[hessian] if isinstance(hessian, str) else int(hessian)
+        p.coarse_solver = COARSE[coarse_solver] if isinstance(coarse_solver, str) else int(coarse_solver)
+        p.coarse_eps = float(coarse_eps)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

@@ -111,6 +111,7 @@ class Ctx final : public Base {
     ht_ = 1.0 / p.nt;
     cell_ = std::pow(2.0 * 3.14159265358979323846, 3) / double(F_);
     fn_ = p.hessian == SLNK_HESS_FN;
+    coarse_pcg_ = p.pc == SLNK_PC_2L && p.coarse_solver == SLNK_COARSE_PCG;
     try {
       allocate();
       if (p.pc == SLNK_PC_2L) {  // the coarse level: half the points per axis, GN, its own workspace
@@ -189,6 +190,7 @@ class Ctx final : public Base {
     }
     if (!lin_) throw Err{SLNK_EINVAL, "P_2L needs a linearisation (slnk3_gradient or slnk3_objective)"};
     coarse_linearize();
+    outer_tol_ = 1.0;
     apply_two_level(static_cast<const T*>(r), static_cast<T*>(z));
   }
 
@@ -268,12 +270,13 @@ class Ctx final : public Base {
         auto pr = [&](const T* r, T* z) {
           const double t = now_ms();
           apply_two_level(r, z);
-          rep.coarse_matvecs += std::max(p_.cheb_iters - 1, 0);
+          rep.coarse_matvecs += coarse_pcg_ ? last_inner_ : std::max(p_.cheb_iters - 1, 0);
           rep.time_precond_ms += now_ms() - t;
         };
         int st = 0;
+        outer_tol_ = eta;  // PCG(eps) solves the coarse system to eps times the forcing term
         its = pcg(b_, eta, o.max_pcg, op, pr, rep, st);
-        if (st == kIndefinite) {  // section 4.2.1: re-estimate the eigenvalues and run again
+        if (st == kIndefinite && !coarse_pcg_) {  // section 4.2.1: re-estimate the eigenvalues and run again
           reestimate_emax();
           ++rep.cheb_reestimates;
           int its2 = pcg(b_, eta, o.max_pcg, op, pr, rep, st);
@@ -773,13 +776,54 @@ class Ctx final : public Base {
     }
   }
 
-  // P_2L^{-1} r = (I - L) r + Pro CHEB(M_c) Res r, the low/high split and both transfers spectral
+  // CG on this level's split operator M x = b from x = 0, the nested PCG(eps) coarse solve of
+  // section 3.4.2 (M is spectrally preconditioned already: no inner preconditioner), to
+  // ||b - M x|| <= tol ||b||, non-positive curvature (rounding only: M is positive definite; the
+  // iterate is kept) or maxit steps.  x in x_; uses this level's r_, pp_, q_ and step scalars (the
+  // fine level's PCG keeps its own across the call).  Returns the steps.
+  int cg(const T* b, double tol, int maxit) {
+    const size_t V = 3 * F_;
+    D3CHK(hipMemsetAsync(x_, 0, V * sizeof(T), s_));
+    D3CHK(hipMemcpyAsync(r_, b, V * sizeof(T), hipMemcpyDeviceToDevice, s_));
+    D3CHK(hipMemcpyAsync(pp_, b, V * sizeof(T), hipMemcpyDeviceToDevice, s_));
+    const double bnorm = std::sqrt(reduce(0, V, r_, r_));
+    if (bnorm == 0.0) return 0;
+    double* rr = pcg_sc_;
+    double* alpha = pcg_sc_ + 1;
+    double* c0 = pcg_sc_ + 2;
+    double* c1 = pcg_sc_ + 3;
+    D3CHK(d3::reduce<T>(s_, V, 0, r_, r_, partial_, dres_ + 1));
+    D3CHK(pcg_coef(s_, PCG_RZ, 1, nullptr, dres_ + 1, rr, nullptr, nullptr));
+    for (int it = 1; it <= maxit; ++it) {
+      split_matvec(pp_, q_);
+      D3CHK(d3::reduce<T>(s_, V, 0, pp_, q_, partial_, dres_));
+      D3CHK(pcg_coef(s_, PCG_ALPHA, 1, nullptr, dres_, rr, alpha, nullptr));
+      D3CHK((slnk::axpby<T>(s_, 1, V, 1.0, alpha, pp_, 1.0, nullptr, x_)));
+      D3CHK((slnk::axpby<T>(s_, 1, V, -1.0, alpha, q_, 1.0, nullptr, r_)));
+      D3CHK(d3::reduce<T>(s_, V, 0, r_, r_, partial_, dres_ + 1));
+      D3CHK(hipMemcpyAsync(hres_, dres_, 2 * sizeof(double), hipMemcpyDeviceToHost, s_));
+      D3CHK(hipStreamSynchronize(s_));
+      const double pq = hres_[0], rrh = hres_[1];
+      if (!std::isfinite(pq) || !std::isfinite(rrh)) throw Err{SLNK_ENAN, "non-finite coarse CG"};
+      if (!(pq > 0.0) || std::sqrt(rrh) <= tol * bnorm) return it;
+      // p <- r + (r.r new / r.r) p
+      D3CHK(pcg_coef(s_, PCG_BETA, 1, nullptr, dres_ + 1, rr, c0, c1));
+      D3CHK((slnk::axpby<T>(s_, 1, V, 1.0, c0, r_, 1.0, c1, pp_)));
+    }
+    return maxit;
+  }
+
+  // P_2L^{-1} r = (I - L) r + Pro C(M_c) Res r, the low/high split and both transfers spectral; C =
+  // CHEB(k), or PCG(eps) to eps times outer_tol_ (the forcing term of the outer solve, 1 outside it)
   void apply_two_level(const T* r, T* z) {
     Ctx<T>& c = *coarse_;
     D3CHK(fft_forward<T>(s_, d_, tw_, 3, r, Sr_));
     D3CHK(spec_restrict<T>(s_, d_, c.d_, 3, Sr_, c.S1_));
     D3CHK(fft_inverse<T>(s_, c.d_, c.tw_, 3, c.S1_, c.b_));
-    c.chebyshev(c.b_, emin_, emax_, p_.cheb_iters);
+    if (coarse_pcg_)
+      last_inner_ = c.cg(c.b_, p_.coarse_eps * outer_tol_, kMaxInner);
+    else
+      c.chebyshev(c.b_, emin_, emax_, p_.cheb_iters);
     D3CHK(fft_forward<T>(s_, c.d_, c.tw_, 3, c.x_, c.S1_));
     D3CHK(spec_prolong_combine<T>(s_, d_, c.d_, 3, Sr_, c.S1_));
     D3CHK(fft_inverse<T>(s_, d_, tw_, 3, Sr_, z));
@@ -856,6 +900,12 @@ class Ctx final : public Base {
   // the last gradient (lam_ok_: taken at the current linearisation), sigma at two levels, the
   // interpolated source, m~^j, and the lambda grad m~ part of b~
   bool fn_ = false, lam_ok_ = false;
+  // P_2L's coarse solver: CHEB(k), or PCG(eps) (at most kMaxInner steps; last_inner_: the steps
+  // of the last application) to eps times outer_tol_
+  bool coarse_pcg_ = false;
+  double outer_tol_ = 1.0;
+  int last_inner_ = 0;
+  static constexpr int kMaxInner = 200;
   T* lamk_ = nullptr;
   T* sig_[2] = {};
   T* e_ = nullptr;
@@ -932,6 +982,8 @@ void slnk3_default_params(slnk3_params* p) {
   p->emax_safety = 1.05;
   p->lanczos_seed = 0x5EED;
   p->hessian = SLNK_HESS_GN;
+  p->coarse_solver = SLNK_COARSE_CHEB;
+  p->coarse_eps = 0.1;
 }
 
 slnk_status slnk3_create(const slnk3_params* p, void* hip_stream, slnk3_ctx** out) {
@@ -942,7 +994,9 @@ slnk_status slnk3_create(const slnk3_params* p, void* hip_stream, slnk3_ctx** ou
       p->reg > 3 || !(p->beta > 0.0) || !std::isfinite(p->beta) ||
       (p->prec != SLNK_PREC_FP64 && p->prec != SLNK_PREC_MIXED) || (p->proj != 0 && p->proj != 1) ||
       (p->sl_path != 0 && p->sl_path != 1) || (p->pc != SLNK_PC_REG && p->pc != SLNK_PC_2L) ||
-      (p->hessian != SLNK_HESS_GN && p->hessian != SLNK_HESS_FN))
+      (p->hessian != SLNK_HESS_GN && p->hessian != SLNK_HESS_FN) ||
+      (p->coarse_solver != SLNK_COARSE_CHEB && p->coarse_solver != SLNK_COARSE_PCG) ||
+      (p->coarse_solver == SLNK_COARSE_PCG && !(p->coarse_eps > 0.0 && p->coarse_eps < 1.0)))
     return SLNK_EINVAL;
   if (p->pc == SLNK_PC_2L && (!size_ok(p->n1 / 2) || !size_ok(p->n2 / 2) || !size_ok(p->n3 / 2) ||
                               p->cheb_iters < 1 || p->lanczos_steps < 1 || p->lanczos_steps > 1000 ||

@@ -318,3 +318,41 @@ def test_two_level_newton_solve_matches_oracle(slnk, prec):
     gi = O.gradient(O.linearize(L, _np(v)))
     assert np.abs(gi).max() <= 1.02e-2 * rep["g0_inf"]
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_nested_pcg_coarse_solve_matches_oracle(slnk, prec):
+    """P_2L with the nested PCG(eps) coarse solve in 3-D (section 3.4.2): the preconditioner (CG on
+    the coarse split operator to eps = 0.1 of the residual, outer tolerance 1) against the oracle's,
+    then Newton--PCG with PCG(0.1): FP64 on the oracle's Newton, outer PCG and coarse CG counts with
+    its velocity to 1e-9; mixed reaches the stop rule within 1e-3 of the oracle's velocity."""
+    shape = (16, 16, 16)
+    L, vgen, _ = _level(shape, prec, beta=1e-3)
+    print(f"nested pcg {shape} {prec}", flush=True)
+    tl = O.setup_two_level(L, solver="pcg", eps=0.1)
+    ctx = slnk.Context3(*shape, L.prm.nt, beta=1e-3, prec=prec, pc="2l", coarse_solver="pcg", coarse_eps=0.1)
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    v = same_inputs(prec, 0.6 * vgen)
+    gt = torch.empty((3,) + shape, dtype=ctx.dtype, device="cuda")
+    ctx.gradient(_t(v, prec), gt)
+    lin = O.linearize(L, v)
+    tl.lin_c = O.linearize(tl.coarse, _restrict_vec(L, v))
+    r = same_inputs(prec, O.gradient(lin))
+    zref, its = O.apply_two_level(L, tl, r)
+    assert its > 1
+    z = torch.empty_like(gt)
+    ctx.precond_apply(_t(r, prec), z)
+    check_rel(f"3d P_2L PCG(0.1) {shape} {prec}", _np(z), zref, 1e-10 if prec == "fp64" else 2e-4)
+    vs, rep = O.newton_solve(L, pc="2l", max_newton=6, coarse_solver="pcg", coarse_eps=0.1)
+    v0 = torch.zeros((3,) + shape, dtype=ctx.dtype, device="cuda")
+    rg = ctx.newton_solve(v0, max_newton=6)
+    print("oracle", rep["newton_iters"], rep["pcg_iters"], rep["coarse_matvecs"], rep["grel"], "gpu",
+          rg["newton_iters"], rg["pcg_iters"], rg["coarse_matvecs"], rg["grel"], flush=True)
+    assert rg["status"] == "SLNK_OK" and rep["status"] == "ok" and rg["grel"][-1] <= 1e-2
+    if prec == "fp64":
+        assert (rg["newton_iters"], rg["pcg_iters"], rg["coarse_matvecs"]) == \
+            (rep["newton_iters"], rep["pcg_iters"], rep["coarse_matvecs"])
+        check_rel("3d newton PCG(0.1) v fp64", _np(v0), vs, 1e-9)
+    else:
+        check_rel("3d newton PCG(0.1) v mixed", _np(v0), vs, 1e-3)
+    ctx.close()
