@@ -489,7 +489,7 @@ def d3_matvec_bytes(n, nt, elem=4):
     return (25 + 30 * nt) * n ** 3 * elem
 
 
-def d3_setup(dev, prec, n=128, sl_path=0, pc="reg", hessian="gn"):
+def d3_setup(dev, prec, n=128, sl_path=0, pc="reg", hessian="gn", coarse_solver="cheb"):
     import numpy as np
     import torch
 
@@ -499,7 +499,8 @@ def d3_setup(dev, prec, n=128, sl_path=0, pc="reg", hessian="gn"):
     dt = torch.float32 if prec == "mixed" else torch.float64
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)
     vt = synth.random_velocity_3d(n, n, n, np.random.default_rng(1234), amplitude=0.1)
-    ctx = Context3(n, n, n, nt, reg=reg, beta=beta, prec=prec, sl_path=sl_path, pc=pc, hessian=hessian)
+    ctx = Context3(n, n, n, nt, reg=reg, beta=beta, prec=prec, sl_path=sl_path, pc=pc, hessian=hessian,
+                   coarse_solver=coarse_solver, coarse_eps=0.1)
     mT_t, vgen_t = t(mT), t(vgen)
     mR_t = torch.empty_like(mT_t)
     ctx.transport_state(vgen_t, mT_t, mR_t)
@@ -588,6 +589,21 @@ def d3_workload(args, dev):
                 "workspace_GB": round(ctxf.workspace_bytes() / 1e9, 3)}
             ctxf.close()
             del gf, vf, mRf, mTf, vgenf, vtf
+            # P_2L with the nested PCG(0.1) coarse solve instead of CHEB(10)
+            ctxp, mRp, mTp, vgenp, _, _, _ = d3_setup(dev, prec, pc="2l", coarse_solver="pcg")
+            vp = torch.zeros_like(vgenp)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctxp.set_images(mRp, mTp)
+            repp = ctxp.newton_solve(vp)
+            out["mixed_two_level_pcg0.1"] = {
+                "setup_plus_solve_ms": round(1e3 * (time.perf_counter() - t0), 2),
+                "solve_ms": round(repp["time_total_ms"], 2), "newton_iters": repp["newton_iters"],
+                "pcg_iters": repp["pcg_iters"], "coarse_matvecs": repp["coarse_matvecs"],
+                "grel_final": repp["grel"][-1], "status": repp["status"],
+                "time_precond_ms": round(repp["time_precond_ms"], 2)}
+            ctxp.close()
+            del vp, mRp, mTp, vgenp
         # the same problem with P_2L (coarse grid 64^3, CHEB(10), 30 Lanczos steps at set-up)
         ctx2, mR2, mT2, vgen2, _, _, _ = d3_setup(dev, prec, pc="2l")
         v2 = torch.zeros_like(vgen2)
