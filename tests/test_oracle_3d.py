@@ -306,3 +306,41 @@ def test_full_newton_matvec_is_derivative_of_gradient_in_three_dimensions():
     gn = fd_error(8, "gn")
     assert fn[0] / fn[1] > 3.0 and fn[1] / fn[2] > 2.5 and fn[2] < 5e-4, fn
     assert gn > 100 * fn[2], (fn, gn)
+
+
+def test_rk2a_adjoint_error_at_machine_precision_in_three_dimensions():
+    """RK2A in 3-D: the discrete adjoint solve is the transpose of the state solve (the adjoint
+    error of the paper's section 4.1 at rounding), A = -L^T on a dense operator of a small grid,
+    and the b-form integrand is the transpose of the state source; the SL scheme's adjoint error
+    is not at rounding."""
+    g = O.Grid(4, 6, 8)
+    X1, X2, X3 = g.X
+    v = np.stack([0.4 * np.sin(X2) + 0.1 * np.cos(2 * X3), 0.3 * np.cos(X1 + X3), 0.2 * np.sin(X1 - X2)])
+    divv = O.fft_div(g, v)
+    n = g.N
+    L = np.empty((n, n))
+    A = np.empty((n, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        L[:, k] = O.rk2a_forward_op(g, v, divv, e.reshape(g.shape)).ravel()
+        A[:, k] = O.rk2a_adjoint_op(g, v, divv, e.reshape(g.shape)).ravel()
+    assert np.abs(A + L.T).max() < 1e-13 * np.abs(L).max()
+    rng = np.random.default_rng(0)
+    m, lam, vt = rng.standard_normal(g.shape), rng.standard_normal(g.shape), rng.standard_normal((3,) + g.shape)
+    lhs = np.sum(O.rk2a_state_source(g, m, vt) * lam)
+    assert abs(lhs - np.sum(vt * O.rk2a_integrand(g, lam, m))) < 1e-12 * abs(lhs)
+    g = O.Grid(16, 16, 16)
+    X1, X2, X3 = g.X
+    m0 = 0.5 + 0.2 * np.sin(X1) * np.cos(X2) * np.sin(X3)
+    v = np.stack([0.5 * np.sin(X2), 0.4 * np.cos(X3), 0.3 * np.sin(X1 + X2)])
+    for nt in (4, 8):
+        m1 = O.rk2a_solve_state(g, v, m0, nt)[-1]
+        lam0 = O.rk2a_solve_adjoint(g, v, m1, nt)[0]
+        a = np.sum(m1 * m1)
+        assert abs(a - np.sum(lam0 * m0)) / a < 1e-14
+    ht = 1.0 / 4
+    Xf, Xa = O.trace(g, v, ht, -1), O.trace(g, v, ht, +1)
+    m1 = O.solve_state(g, Xf, m0, 4)[-1]
+    lam0 = O.solve_adjoint(g, Xa, O.adjoint_factor(g, v, Xa, ht), m1, 4)[0]
+    assert abs(np.sum(m1 * m1) - np.sum(lam0 * m0)) / np.sum(m1 * m1) > 1e-9
