@@ -55,7 +55,11 @@ typedef struct slnk3_ctx slnk3_ctx;
  * operator of P_2L stays Gauss--Newton); coarse_solver, coarse_eps: P_2L's coarse solver as in
  * slnk.h, SLNK_COARSE_CHEB (default, CHEB(cheb_iters)) or SLNK_COARSE_PCG (the nested PCG(eps) solve:
  * CG on the coarse split operator from zero to coarse_eps times the outer PCG tolerance, 1 in
- * slnk3_precond_apply, at most 200 steps; coarse_eps in (0, 1), default 0.1). */
+ * slnk3_precond_apply, at most 200 steps; coarse_eps in (0, 1), default 0.1); transport:
+ * SLNK_TRANSPORT_SL (default) or SLNK_TRANSPORT_RK2A, the stabilised RK2 scheme of section 3.3.1
+ * and the appendix "Stabilized RK2 Scheme" as in slnk.h (antisymmetric-form state, adjoint and
+ * incremental equations with pseudospectral derivatives, Heun's method; conditionally stable, nt by
+ * the CFL condition; with P_REG; GN or full Newton; sl_path ignored). */
 typedef struct {
   int n1, n2, n3, nt;
   int reg;
@@ -71,6 +75,7 @@ typedef struct {
   int hessian;
   int coarse_solver;
   double coarse_eps;
+  int transport;
 } slnk3_params;
 
 /* 64^3, nt = 4, H2, beta = 1e-3, mixed precision, K = identity, P_REG (CHEB(10), 30 Lanczos

@@ -60,7 +60,8 @@ class Params3(ctypes.Structure):
                 ("reg", ctypes.c_int), ("beta", ctypes.c_double), ("prec", ctypes.c_int), ("proj", ctypes.c_int),
                 ("sl_path", ctypes.c_int), ("pc", ctypes.c_int), ("cheb_iters", ctypes.c_int),
                 ("lanczos_steps", ctypes.c_int), ("emax_safety", ctypes.c_double), ("lanczos_seed", ctypes.c_ulonglong),
-                ("hessian", ctypes.c_int), ("coarse_solver", ctypes.c_int), ("coarse_eps", ctypes.c_double)]
+                ("hessian", ctypes.c_int), ("coarse_solver", ctypes.c_int), ("coarse_eps", ctypes.c_double),
+                ("transport", ctypes.c_int)]
 
 
 class UNetParams(ctypes.Structure):
@@ -350,7 +351,7 @@ class Context3:
 
     def __init__(self, n1, n2, n3, nt, reg="h2", beta=1e-3, prec="mixed", proj="none", sl_path=0, pc="reg",
                  cheb_iters=10, lanczos_steps=30, emax_safety=1.05, lanczos_seed=0x5EED, hessian="gn",
-                 coarse_solver="cheb", coarse_eps=0.1, stream=None):
+                 coarse_solver="cheb", coarse_eps=0.1, transport="sl", stream=None):
         import torch
         lib = load_library()
         p = Params3()
@@ -367,6 +368,7 @@ class Context3:
         p.hessian = HESSIAN[hessian] if isinstance(hessian, str) else int(hessian)
         p.coarse_solver = COARSE[coarse_solver] if isinstance(coarse_solver, str) else int(coarse_solver)
         p.coarse_eps = float(coarse_eps)
+        p.transport = TRANSPORT[transport] if isinstance(transport, str) else int(transport)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

@@ -915,6 +915,61 @@ __global__ void __launch_bounds__(kThreads) k_acc_scalar_grad(size_t F, T w, int
 }
 
 template <typename T>
+__global__ void __launch_bounds__(kThreads) k_rk_stage(size_t F, RkStage<T> a) {
+  const size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= F) return;
+  const T v0 = a.v[i], v1 = a.v[F + i], v2 = a.v[2 * F + i];
+  const T y = a.y[i];
+  T k = T(0.5 * a.sgn) * (v0 * a.g[i] + v1 * a.g[F + i] + v2 * a.g[2 * F + i] + a.dv[i] + T(a.dsgn) * y * a.divv[i]);
+  if (a.src) k += a.src[i];
+  T out;
+  if (a.stage == 1) {
+    a.kbuf[i] = k;
+    out = y + T(a.ht) * k;
+  } else {
+    out = a.y0[i] + T(0.5 * a.ht) * (a.kbuf[i] + k);
+  }
+  a.dst[i] = out;
+  a.yv[i] = out * v0;
+  a.yv[F + i] = out * v1;
+  a.yv[2 * F + i] = out * v2;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_rk_eval(size_t F, int sgn, int dsgn, const T* __restrict__ g,
+                                                      const T* __restrict__ dv, const T* __restrict__ a,
+                                                      const T* __restrict__ w, const T* __restrict__ divw,
+                                                      T* __restrict__ out) {
+  const size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= F) return;
+  out[i] = T(0.5 * sgn) *
+           (w[i] * g[i] + w[F + i] * g[F + i] + w[2 * F + i] * g[2 * F + i] + dv[i] + T(dsgn) * a[i] * divw[i]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_mul(size_t F, const T* __restrict__ a, const T* __restrict__ b,
+                                                  T* __restrict__ out) {
+  const size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= F) return;
+  out[i] = a[i] * b[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_rk_accum(size_t F, T w, int init, const T* __restrict__ lam,
+                                                       const T* __restrict__ m, const T* __restrict__ gm,
+                                                       const T* __restrict__ gl, const T* __restrict__ glm,
+                                                       T* __restrict__ acc) {
+  const size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= F) return;
+  const T l = lam[i], mm = m[i];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T t = T(0.5) * w * (l * gm[c * F + i] - mm * gl[c * F + i] + glm[c * F + i]);
+    acc[c * F + i] = init ? t : acc[c * F + i] + t;
+  }
+}
+
+template <typename T>
 __global__ void __launch_bounds__(kThreads) k_axpby(size_t n, T a, const T* __restrict__ x, T b,
                                                     const T* __restrict__ y, T* __restrict__ out) {
   for (size_t i = size_t(blockIdx.x) * kThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
@@ -1238,6 +1293,34 @@ hipError_t acc_scalar_grad(hipStream_t s, const Dims& d, double w, int init, con
 }
 
 template <typename T>
+hipError_t rk_stage(hipStream_t s, const Dims& d, const RkStage<T>& a) {
+  hipLaunchKernelGGL(k_rk_stage<T>, dim3(blocks_for(d.F())), dim3(kThreads), 0, s, d.F(), a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t rk_eval(hipStream_t s, const Dims& d, int sgn, int dsgn, const T* g, const T* dv, const T* a, const T* w,
+                   const T* divw, T* out) {
+  hipLaunchKernelGGL(k_rk_eval<T>, dim3(blocks_for(d.F())), dim3(kThreads), 0, s, d.F(), sgn, dsgn, g, dv, a, w, divw,
+                     out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mul(hipStream_t s, const Dims& d, const T* a, const T* b, T* out) {
+  hipLaunchKernelGGL(k_mul<T>, dim3(blocks_for(d.F())), dim3(kThreads), 0, s, d.F(), a, b, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t rk_accum(hipStream_t s, const Dims& d, double w, int init, const T* lam, const T* m, const T* gm,
+                    const T* gl, const T* glm, T* acc) {
+  hipLaunchKernelGGL(k_rk_accum<T>, dim3(blocks_for(d.F())), dim3(kThreads), 0, s, d.F(), T(w), init, lam, m, gm, gl,
+                     glm, acc);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t axpby(hipStream_t s, size_t n, double a, const T* x, double b, const T* y, T* out) {
   const unsigned nb = std::min<size_t>(blocks_for(n), 8192);
   hipLaunchKernelGGL(k_axpby<T>, dim3(nb), dim3(kThreads), 0, s, n, T(a), x, T(b), y, out);
@@ -1278,6 +1361,12 @@ hipError_t reduce(hipStream_t s, size_t n, int mode, const T* a, const T* b, dou
   template hipError_t incstate_start<T>(hipStream_t, const Dims&, double, const T*, const T*, T*);               \
   template hipError_t q_at_zero<T>(hipStream_t, const Dims&, const T*, const T*, T*);                           \
   template hipError_t scale_vec<T>(hipStream_t, const Dims&, const T*, const T*, T*);                           \
+  template hipError_t rk_stage<T>(hipStream_t, const Dims&, const RkStage<T>&);                                 \
+  template hipError_t rk_eval<T>(hipStream_t, const Dims&, int, int, const T*, const T*, const T*, const T*,    \
+                                 const T*, T*);                                                                 \
+  template hipError_t mul<T>(hipStream_t, const Dims&, const T*, const T*, T*);                                 \
+  template hipError_t rk_accum<T>(hipStream_t, const Dims&, double, int, const T*, const T*, const T*,          \
+                                  const T*, const T*, T*);                                                      \
   template hipError_t fn_source<T>(hipStream_t, const Dims&, double, const T*, const T*, const T*, T*);         \
   template hipError_t acc_scalar_grad<T>(hipStream_t, const Dims&, double, int, const T*, const T*, T*);        \
   template hipError_t axpby<T>(hipStream_t, size_t, double, const T*, double, const T*, T*);                     \

@@ -158,6 +158,46 @@ hipError_t fn_source(hipStream_t s, const Dims& d, double ht, const T* divv, con
 template <typename T>
 hipError_t acc_scalar_grad(hipStream_t s, const Dims& d, double w, int init, const T* lam, const T* g, T* acc);
 
+// ---- stabilised RK2 transport (section 3.3.1; appendix "Stabilized RK2 Scheme") ----------------
+// Antisymmetric-form operators L_s y = 1/2 (v . grad y + div(y v) + s y div v): s = -1 the state
+// operator L (d_t m = -L m), s = +1 the adjoint operator A (d_s lam = A lam backward in time); grad y
+// and div(y v) come from the spectral Grad and Div passes.  One Heun stage of
+// dy/ds = sgn L_dsgn y + src (src optional) at every node: k = sgn L_dsgn y + src from g = grad y,
+// dv = div(y v) and y; stage 1: kbuf = k, dst = y + ht k; stage 2: dst = y0 + ht/2 (kbuf + k);
+// both: yv = dst v (the product the next evaluation differentiates).
+template <typename T>
+struct RkStage {
+  int stage = 1;
+  int sgn = -1, dsgn = -1;
+  double ht = 0.0;
+  const T* g = nullptr;
+  const T* dv = nullptr;
+  const T* y = nullptr;
+  const T* v = nullptr;
+  const T* divv = nullptr;
+  const T* src = nullptr;
+  const T* y0 = nullptr;
+  T* kbuf = nullptr;
+  T* dst = nullptr;
+  T* yv = nullptr;
+};
+template <typename T>
+hipError_t rk_stage(hipStream_t s, const Dims& d, const RkStage<T>& a);
+// out = sgn 1/2 (w . g + dv + dsgn a divw), g = grad a, dv = div(a w): a source of the incremental
+// equations (sgn = dsgn = -1: -S(m) vt of the incremental state; +1: the full-Newton incremental
+// adjoint's lambda terms)
+template <typename T>
+hipError_t rk_eval(hipStream_t s, const Dims& d, int sgn, int dsgn, const T* g, const T* dv, const T* a, const T* w,
+                   const T* divw, T* out);
+// out = a b
+template <typename T>
+hipError_t mul(hipStream_t s, const Dims& d, const T* a, const T* b, T* out);
+// acc_c (init: =, else +=) w/2 (lam gm_c - m gl_c + glm_c), gm = grad m, gl = grad lam,
+// glm = grad(lam m): the antisymmetric form of lam grad m in b and b~
+template <typename T>
+hipError_t rk_accum(hipStream_t s, const Dims& d, double w, int init, const T* lam, const T* m, const T* gm,
+                    const T* gl, const T* glm, T* acc);
+
 // out = a x + b y over n values (scalars cast to T; x or y may be null for a zero term)
 template <typename T>
 hipError_t axpby(hipStream_t s, size_t n, double a, const T* x, double b, const T* y, T* out);

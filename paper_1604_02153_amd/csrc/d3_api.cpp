@@ -112,6 +112,7 @@ class Ctx final : public Base {
     cell_ = std::pow(2.0 * 3.14159265358979323846, 3) / double(F_);
     fn_ = p.hessian == SLNK_HESS_FN;
     coarse_pcg_ = p.pc == SLNK_PC_2L && p.coarse_solver == SLNK_COARSE_PCG;
+    rk_ = p.transport == SLNK_TRANSPORT_RK2A;
     try {
       allocate();
       if (p.pc == SLNK_PC_2L) {  // the coarse level: half the points per axis, GN, its own workspace
@@ -144,6 +145,18 @@ class Ctx final : public Base {
   void transport_state(const void* v, const void* m0, void* m1) override {
     lin_ = false;
     lam_ok_ = false;
+    if (rk_) {  // Heun on d_t m = -L m
+      rk_prepare(static_cast<const T*>(v));
+      const T* cur = static_cast<const T*>(m0);
+      D3CHK(scale_vec<T>(s_, d_, cur, v_, rk_yv_));
+      for (int j = 1; j <= p_.nt; ++j) {
+        T* out = j == p_.nt ? static_cast<T*>(m1) : rk_y_[j & 1];
+        rk_step(-1, -1, cur, out, nullptr, nullptr);
+        cur = out;
+      }
+      D3CHK(hipStreamSynchronize(s_));
+      return;
+    }
     trace_at(static_cast<const T*>(v));
     const T* cur = static_cast<const T*>(m0);
     T* bufs[2] = {lam0_, lam1_};
@@ -396,6 +409,20 @@ class Ctx final : public Base {
     lz_cap_ = std::min(std::max(p_.lanczos_steps, 1), kMaxLanczos);
     lz_ = take<double>(4 + 2 * size_t(lz_cap_));
     lz_live_ = take<int>(1);
+    if (rk_) {
+      rk_g_ = take<T>(V);
+      rk_yv_ = take<T>(V);
+      rk_gl_ = take<T>(V);
+      rk_glm_ = take<T>(V);
+      rk_dv_ = take<T>(F_);
+      rk_dvs_ = take<T>(F_);
+      rk_tmp_ = take<T>(F_);
+      rk_k_ = take<T>(F_);
+      rk_p_ = take<T>(F_);
+      rk_divt_ = take<T>(F_);
+      for (auto& y : rk_y_) y = take<T>(F_);
+      for (auto& y : rk_src_) y = take<T>(F_);
+    }
     if (fn_) {
       lamk_ = take<T>(size_t(nt + 1) * F_);
       sig_[0] = take<T>(F_);
@@ -498,10 +525,17 @@ class Ctx final : public Base {
 
   // trace, state m^0..m^nt (eq. e:state-slm), grad m^j, A v and J
   void linearize(const T* v) {
-    trace_at(v);
     const size_t V = 3 * F_;
-    D3CHK(hipMemcpyAsync(m_, mT_, F_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
-    for (int j = 1; j <= p_.nt; ++j) {
+    if (rk_) {
+      rk_prepare(v);
+      D3CHK(hipMemcpyAsync(m_, mT_, F_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+      D3CHK(scale_vec<T>(s_, d_, m_, v_, rk_yv_));
+      for (int j = 1; j <= p_.nt; ++j) rk_step(-1, -1, m_ + size_t(j - 1) * F_, m_ + size_t(j) * F_, nullptr, nullptr);
+    } else {
+      trace_at(v);
+      D3CHK(hipMemcpyAsync(m_, mT_, F_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+    }
+    for (int j = 1; j <= p_.nt && !rk_; ++j) {
       coefficients(m_ + size_t(j - 1) * F_, coef_, 1);
       StepArgs<T> a;
       a.d = d_;
@@ -528,11 +562,123 @@ class Ctx final : public Base {
   void gradient_at(T* g) {
     const size_t V = 3 * F_;
     const int nt = p_.nt;
+    if (rk_) {  // RK2A: lambda^nt = m_R - m^nt, Heun on d_s lam = A lam, b in its antisymmetric form
+      D3CHK(axpby<T>(s_, F_, 1.0, mR_, -1.0, m_ + size_t(nt) * F_, rk_level(nt, fn_)));
+      rk_adjoint_sweep(fn_, true, nullptr);
+      project_and_add(p_.beta, Av_, g);
+      lam_ok_ = true;
+      return;
+    }
     T* lam1 = fn_ ? lamk_ + size_t(nt) * F_ : lam1_;
     D3CHK(adjoint_start<T>(s_, d_, trap_w(nt, nt), mR_, m_ + size_t(nt) * F_, gm_ + size_t(nt) * V, lam1, acc_));
     backward_sweep(lam1, Kind::Adjoint);
     project_and_add(p_.beta, Av_, g);
     lam_ok_ = true;
+  }
+
+  // ---- stabilised RK2 (RK2A) transport ---------------------------------------------------------
+  // v into v_ and div v (no characteristics)
+  void rk_prepare(const T* v) {
+    if (v != v_) D3CHK(hipMemcpyAsync(v_, v, 3 * F_ * sizeof(T), hipMemcpyDeviceToDevice, s_));
+    if (!std::isfinite(reduce(0, 3 * F_, v_, v_))) throw Err{SLNK_ENAN, "non-finite velocity"};
+    divergence_of(v_, divv_);
+  }
+
+  // one Heun step of dy/ds = sgn L_dsgn y + src from y0 into dst (src0, src1: the sources at the
+  // step's two ends, or null); rk_yv_ holds y0 v on entry and dst v on exit
+  void rk_step(int sgn, int dsgn, const T* y0, T* dst, const T* src0, const T* src1) {
+    RkStage<T> a;
+    a.sgn = sgn;
+    a.dsgn = dsgn;
+    a.ht = ht_;
+    a.g = rk_g_;
+    a.dv = rk_dv_;
+    a.v = v_;
+    a.divv = divv_;
+    a.kbuf = rk_k_;
+    a.yv = rk_yv_;
+    gradient_of(y0, rk_g_);
+    divergence_of(rk_yv_, rk_dv_);
+    a.stage = 1;
+    a.y = y0;
+    a.src = src0;
+    a.dst = rk_tmp_;
+    D3CHK(rk_stage<T>(s_, d_, a));
+    gradient_of(rk_tmp_, rk_g_);
+    divergence_of(rk_yv_, rk_dv_);
+    a.stage = 2;
+    a.y = rk_tmp_;
+    a.src = src1;
+    a.y0 = y0;
+    a.dst = dst;
+    D3CHK(rk_stage<T>(s_, d_, a));
+  }
+
+  // acc (init: =, else +=) w_j 1/2 (lam grad m - m grad lam + grad(lam m)) for m = m~ (its gradient in
+  // gm) or the state m^j
+  void rk_accumulate(int j, const T* lam, const T* m, const T* gm, bool init) {
+    gradient_of(lam, rk_gl_);
+    D3CHK(mul<T>(s_, d_, lam, m, rk_p_));
+    gradient_of(rk_p_, rk_glm_);
+    D3CHK(rk_accum<T>(s_, d_, trap_w(j, p_.nt), init, lam, m, gm, rk_gl_, rk_glm_, acc_));
+  }
+
+  // time level j of an RK2A adjoint sweep: every level in lamk_ (keep: the full-Newton gradient),
+  // else two rotating fields
+  T* rk_level(int j, bool keep) { return keep ? lamk_ + size_t(j) * F_ : rk_y_[j & 1]; }
+
+  // d_s y = A y (+ the full-Newton source when vt is given) from y^nt at rk_level(nt, keep) back to
+  // t = 0, acc (init: set by the first term) += w_j 1/2 (y grad m - m grad y + grad(y m)) at every level
+  void rk_adjoint_sweep(bool keep, bool init, const T* vt) {
+    const size_t V = 3 * F_;
+    const int nt = p_.nt;
+    // 1/2 (div(lam^j vt) + vt . grad lam^j + lam^j div vt): the full-Newton incremental adjoint's source
+    auto source = [&](int j, T* out) -> const T* {
+      if (!vt) return nullptr;
+      const T* lj = lamk_ + size_t(j) * F_;
+      gradient_of(lj, t3b_);
+      D3CHK(scale_vec<T>(s_, d_, lj, vt, t3a_));
+      divergence_of(t3a_, rk_dvs_);
+      D3CHK(rk_eval<T>(s_, d_, +1, +1, t3b_, rk_dvs_, lj, vt, rk_divt_, out));
+      return out;
+    };
+    rk_accumulate(nt, rk_level(nt, keep), m_ + size_t(nt) * F_, gm_ + size_t(nt) * V, init);
+    D3CHK(scale_vec<T>(s_, d_, rk_level(nt, keep), v_, rk_yv_));
+    const T* s_hi = source(nt, rk_src_[nt & 1]);
+    for (int j = nt; j >= 1; --j) {
+      const T* s_lo = source(j - 1, rk_src_[(j - 1) & 1]);
+      rk_step(+1, +1, rk_level(j, keep), rk_level(j - 1, keep), s_hi, s_lo);
+      rk_accumulate(j - 1, rk_level(j - 1, keep), m_ + size_t(j - 1) * F_, gm_ + size_t(j - 1) * V, false);
+      s_hi = s_lo;
+    }
+  }
+
+  // b~ of the RK2A matvec into acc_: the incremental state d_t m~ = -L m~ - S(m) vt from m~ = 0
+  // (S(m) vt = 1/2 (div(m vt) + vt . grad m - m div vt)), then the adjoint equation from -m~(1) with b~
+  // in its antisymmetric form; full Newton adds the lambda terms (the incremental adjoint's source,
+  // and 1/2 (lam grad m~ - m~ grad lam + grad(lam m~)) in b~, added as each m~^j is formed)
+  void rk_transport(const T* vt) {
+    const size_t V = 3 * F_;
+    const int nt = p_.nt;
+    divergence_of(vt, rk_divt_);
+    auto source = [&](int j, T* out) {
+      D3CHK(scale_vec<T>(s_, d_, m_ + size_t(j) * F_, vt, t3a_));
+      divergence_of(t3a_, rk_dvs_);
+      D3CHK(rk_eval<T>(s_, d_, -1, -1, gm_ + size_t(j) * V, rk_dvs_, m_ + size_t(j) * F_, vt, rk_divt_, out));
+    };
+    source(0, rk_src_[0]);
+    D3CHK(axpby<T>(s_, F_, 0.0, nullptr, 0.0, nullptr, rk_y_[0]));
+    D3CHK(axpby<T>(s_, V, 0.0, nullptr, 0.0, nullptr, rk_yv_));
+    for (int j = 1; j <= nt; ++j) {
+      source(j, rk_src_[j & 1]);
+      rk_step(-1, -1, rk_y_[(j - 1) & 1], rk_y_[j & 1], rk_src_[(j - 1) & 1], rk_src_[j & 1]);
+      if (fn_) {
+        gradient_of(rk_y_[j & 1], t3b_);
+        rk_accumulate(j, lamk_ + size_t(j) * F_, rk_y_[j & 1], t3b_, j == 1);
+      }
+    }
+    D3CHK(axpby<T>(s_, F_, -1.0, rk_y_[nt & 1], 0.0, nullptr, rk_y_[nt & 1]));  // lam~(1) = -m~(1)
+    rk_adjoint_sweep(false, !fn_, fn_ ? vt : nullptr);
   }
 
   // sigma^j = div(lambda^j vt), the source of the full-Newton incremental adjoint at time level j
@@ -610,6 +756,16 @@ class Ctx final : public Base {
     const int nt = p_.nt;
     if (fn_ && !lam_ok_)
       throw Err{SLNK_EINVAL, "the full-Newton matvec needs the gradient at this point (slnk3_gradient)"};
+    if (rk_) {
+      rk_transport(vt);
+      if (with_reg) {
+        reg_apply(vt, t3a_, p_.beta);
+        project_and_add(1.0, t3a_, out);
+      } else {
+        project_and_add(0.0, nullptr, out);
+      }
+      return;
+    }
     D3CHK(incstate_start<T>(s_, d_, ht_, vt, gm_, lam0_));
     T* cur = lam0_;
     T* nxt = lam1_;
@@ -903,6 +1059,22 @@ class Ctx final : public Base {
   // P_2L's coarse solver: CHEB(k), or PCG(eps) (at most kMaxInner steps; last_inner_: the steps
   // of the last application) to eps times outer_tol_
   bool coarse_pcg_ = false;
+  // RK2A transport (P_REG): derivatives of the Heun stage's input, its products with v, grad lambda and
+  // grad(lambda m) of the b-form, div(y v) of the step and of a source, the stage value and slope,
+  // lambda m, div vt, two rotating levels and two source levels
+  bool rk_ = false;
+  T* rk_g_ = nullptr;
+  T* rk_yv_ = nullptr;
+  T* rk_gl_ = nullptr;
+  T* rk_glm_ = nullptr;
+  T* rk_dv_ = nullptr;
+  T* rk_dvs_ = nullptr;
+  T* rk_tmp_ = nullptr;
+  T* rk_k_ = nullptr;
+  T* rk_p_ = nullptr;
+  T* rk_divt_ = nullptr;
+  T* rk_y_[2] = {};
+  T* rk_src_[2] = {};
   double outer_tol_ = 1.0;
   int last_inner_ = 0;
   static constexpr int kMaxInner = 200;
@@ -984,6 +1156,7 @@ void slnk3_default_params(slnk3_params* p) {
   p->hessian = SLNK_HESS_GN;
   p->coarse_solver = SLNK_COARSE_CHEB;
   p->coarse_eps = 0.1;
+  p->transport = SLNK_TRANSPORT_SL;
 }
 
 slnk_status slnk3_create(const slnk3_params* p, void* hip_stream, slnk3_ctx** out) {
@@ -996,7 +1169,9 @@ slnk_status slnk3_create(const slnk3_params* p, void* hip_stream, slnk3_ctx** ou
       (p->sl_path != 0 && p->sl_path != 1) || (p->pc != SLNK_PC_REG && p->pc != SLNK_PC_2L) ||
       (p->hessian != SLNK_HESS_GN && p->hessian != SLNK_HESS_FN) ||
       (p->coarse_solver != SLNK_COARSE_CHEB && p->coarse_solver != SLNK_COARSE_PCG) ||
-      (p->coarse_solver == SLNK_COARSE_PCG && !(p->coarse_eps > 0.0 && p->coarse_eps < 1.0)))
+      (p->coarse_solver == SLNK_COARSE_PCG && !(p->coarse_eps > 0.0 && p->coarse_eps < 1.0)) ||
+      (p->transport != SLNK_TRANSPORT_SL && p->transport != SLNK_TRANSPORT_RK2A) ||
+      (p->transport == SLNK_TRANSPORT_RK2A && p->pc != SLNK_PC_REG))
     return SLNK_EINVAL;
   if (p->pc == SLNK_PC_2L && (!size_ok(p->n1 / 2) || !size_ok(p->n2 / 2) || !size_ok(p->n3 / 2) ||
                               p->cheb_iters < 1 || p->lanczos_steps < 1 || p->lanczos_steps > 1000 ||

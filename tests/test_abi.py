@@ -81,7 +81,7 @@ int main(void) {
   F(slnk3_params, beta); F(slnk3_params, prec); F(slnk3_params, proj); F(slnk3_params, sl_path);
   F(slnk3_params, pc); F(slnk3_params, cheb_iters); F(slnk3_params, lanczos_steps); F(slnk3_params, emax_safety);
   F(slnk3_params, lanczos_seed); F(slnk3_params, hessian); F(slnk3_params, coarse_solver);
-  F(slnk3_params, coarse_eps);
+  F(slnk3_params, coarse_eps); F(slnk3_params, transport);
   return 0;
 }
 """
@@ -161,12 +161,14 @@ def test_unet_create_rejects_bad_shapes(pkg, change):
                                     dict(pc=2, n1=8), dict(pc=2, cheb_iters=0), dict(pc=2, emax_safety=0.5),
                                     dict(pc=2, lanczos_steps=1001), dict(hessian=2),
                                     dict(coarse_solver=2), dict(pc=2, coarse_solver=1, coarse_eps=0.0),
-                                    dict(pc=2, coarse_solver=1, coarse_eps=1.0)])
+                                    dict(pc=2, coarse_solver=1, coarse_eps=1.0), dict(transport=2),
+                                    dict(pc=2, transport=1)])
 def test_create3_rejects_bad_parameters_before_device_work(pkg, change):
     lib = pkg.load_library()
     p = pkg.Params3()
     lib.slnk3_default_params(ctypes.byref(p))
-    assert (p.n1, p.n2, p.n3, p.nt, p.reg, p.hessian, p.coarse_solver, p.coarse_eps) == (64, 64, 64, 4, 2, 0, 0, 0.1)
+    assert (p.n1, p.n2, p.n3, p.nt, p.reg, p.hessian, p.coarse_solver, p.coarse_eps, p.transport) == \
+        (64, 64, 64, 4, 2, 0, 0, 0.1, 0)
     for k, v in change.items():
         setattr(p, k, v)
     ctx = ctypes.c_void_p()

@@ -356,3 +356,75 @@ def test_nested_pcg_coarse_solve_matches_oracle(slnk, prec):
     else:
         check_rel("3d newton PCG(0.1) v mixed", _np(v0), vs, 1e-3)
     ctx.close()
+
+
+def _rk_level(shape, prec, beta=1e-3, reg=2, seed=3, amp=0.3, hessian="gn"):
+    """Oracle level of the 3-D Gaussian recipe with RK2A transport, nt from the CFL number 0.2 of
+    the generating velocity (the paper's RK2A setting)."""
+    g = O.Grid(*shape)
+    rng = np.random.default_rng(seed)
+    mT = synth.gaussian_sum_3d(*shape, rng, count=8, sigma=(0.4, 0.8))
+    vgen = synth.random_velocity_3d(*shape, rng, modes=8, kmax=2, amplitude=amp)
+    vt = synth.random_velocity_3d(*shape, np.random.default_rng(seed + 1000), modes=8, kmax=3, amplitude=0.1)
+    mT, vgen, vt = same_inputs(prec, mT, vgen, vt)
+    vmax = float(np.sqrt((vgen ** 2).sum(axis=0)).max())
+    nt = max(2, int(np.ceil(vmax * max(shape) / (2 * np.pi * 0.2))))
+    mR = same_inputs(prec, O.rk2a_solve_state(g, vgen, mT, nt)[-1])
+    prm = O.Params(nt=nt, beta=beta, reg=reg, transport="rk2a", hessian=hessian)
+    return O.Level(g, mT, mR, prm), vgen, vt
+
+
+RK_CASES = [((16, 16, 16), "gn"), ((8, 16, 32), "gn"), ((16, 16, 16), "fn"), ((16, 8, 16), "fn")]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape,hessian", RK_CASES)
+def test_rk2a_matches_oracle(slnk, prec, shape, hessian):
+    """RK2A transport in 3-D (section 3.3.1; appendix "Stabilized RK2 Scheme"): state transport,
+    objective, gradient and the GN or full-Newton matvec against the oracle (the full-Newton lambda
+    terms large against the tolerance)."""
+    L, vgen, vt = _rk_level(shape, prec, hessian=hessian)
+    g, nt = L.grid, L.prm.nt
+    print(f"rk2a case {shape} nt{nt} {hessian} {prec}", flush=True)
+    ctx = _ctx(slnk, L, prec, transport="rk2a")
+    m1 = torch.empty(g.shape, dtype=ctx.dtype, device="cuda")
+    ctx.transport_state(_t(vgen, prec), _t(L.mT, prec), m1)
+    check_rel(f"3d RK2A transport {shape} {prec}", _np(m1), O.rk2a_solve_state(g, vgen, L.mT, nt)[-1],
+              TOL3[prec]["transport"])
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    v = same_inputs(prec, 0.6 * vgen)
+    lin = O.linearize(L, v)
+    gref = O.gradient(lin)
+    gt = torch.empty((3,) + g.shape, dtype=ctx.dtype, device="cuda")
+    J = ctx.gradient(_t(v, prec), gt)
+    assert abs(J - lin.J) <= TOL3[prec]["objective"] * abs(lin.J)
+    check_rel(f"3d RK2A gradient {shape} {prec}", _np(gt), gref,
+              TOL3[prec]["gradient"] + _matvec_tol(L, prec, v, gref) - TOL3[prec]["matvec"])
+    href = O.hessian_matvec(lin, vt)
+    tol = _matvec_tol(L, prec, vt, href)
+    if hessian == "fn":
+        Lgn = O.Level(g, L.mT, L.mR, replace(L.prm, hessian="gn"))
+        hgn = O.hessian_matvec(O.linearize(Lgn, v), vt)
+        assert np.linalg.norm(href - hgn) > 50 * tol * np.linalg.norm(href)
+    ht = torch.empty_like(gt)
+    ctx.hessian_matvec(_t(vt, prec), ht)
+    check_rel(f"3d RK2A {hessian} matvec {shape} {prec}", _np(ht), href, tol)
+    ctx.close()
+
+
+@pytest.mark.parametrize("hessian", ["gn", "fn"])
+def test_rk2a_newton_solve_fp64_matches_oracle(slnk, hessian):
+    """P_REG + RK2A in 3-D, FP64: the oracle's Newton and PCG counts and its velocity to 1e-9."""
+    shape, prec = (16, 16, 16), "fp64"
+    L, _, _ = _rk_level(shape, prec, hessian=hessian)
+    vs, rep = O.newton_solve(L, pc="reg", max_newton=6)
+    ctx = _ctx(slnk, L, prec, transport="rk2a")
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    v = torch.zeros((3,) + shape, dtype=ctx.dtype, device="cuda")
+    r = ctx.newton_solve(v, max_newton=6)
+    print("oracle", rep["newton_iters"], rep["pcg_iters"], rep["grel"], "gpu", r["newton_iters"], r["pcg_iters"],
+          r["grel"], flush=True)
+    assert r["status"] == "SLNK_OK" and rep["status"] == "ok" and r["grel"][-1] <= 1e-2
+    assert (r["newton_iters"], r["pcg_iters"]) == (rep["newton_iters"], rep["pcg_iters"])
+    check_rel(f"3d RK2A newton ({hessian}) v fp64", _np(v), vs, 1e-9)
+    ctx.close()
