@@ -524,6 +524,49 @@ def d3_probe():
         ctx.close()
 
 
+def d3_rk2a(dev, reps=3):
+    """The 128^3 problem with RK2A transport at CFL 0.2 (nt from the generating velocity) and P_REG,
+    the paper's earlier solver, mixed precision: m_R = m_T transported by RK2A, isolated GN matvecs
+    at v_gen, and the Newton-PCG solve from v = 0."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1604_02153_amd import Context3
+    n = 128
+    mT, vgen, _, beta, reg = synth.config_3d("gauss3d128", n=n)
+    nt = max(2, int(np.ceil(float(np.sqrt((vgen ** 2).sum(axis=0)).max()) * n / (2 * np.pi * 0.2))))
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=torch.float32)
+    vt = t(synth.random_velocity_3d(n, n, n, np.random.default_rng(1234), amplitude=0.1))
+    ctx = Context3(n, n, n, nt, reg=reg, beta=beta, prec="mixed", pc="reg", transport="rk2a")
+    mT_t, vgen_t = t(mT), t(vgen)
+    mR_t = torch.empty_like(mT_t)
+    ctx.transport_state(vgen_t, mT_t, mR_t)
+    ctx.set_images(mR_t, mT_t)
+    g = torch.empty_like(vgen_t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.gradient(vgen_t, g)
+    torch.cuda.synchronize()
+    grad_ms = 1e3 * (time.perf_counter() - t0)
+    hv = torch.empty_like(vgen_t)
+    ctx.hessian_matvec(vt, hv)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.hessian_matvec(vt, hv)
+    torch.cuda.synchronize()
+    mv_ms = 1e3 * (time.perf_counter() - t0) / reps
+    v = torch.zeros_like(vgen_t)
+    rep = ctx.newton_solve(v)
+    ctx.close()
+    log(f"3-D RK2A: nt {nt}, matvec {mv_ms:.1f} ms, solve {rep['time_total_ms']:.0f} ms")
+    return {"workload": f"gauss3d128 with RK2A transport, CFL 0.2 (nt={nt}), P_REG; m_R = m_T transported by RK2A",
+            "nt": nt, "matvec_ms": round(mv_ms, 2), "gradient_ms": round(grad_ms, 2),
+            "solve_ms": round(rep["time_total_ms"], 1), "newton_iters": rep["newton_iters"],
+            "pcg_iters": rep["pcg_iters"], "grel_final": rep["grel"][-1], "status": rep["status"]}
+
+
 def d3_workload(args, dev):
     """The method in three dimensions: the Gaussian-blob recipe on a 128^3 volume (nt = 4, H2,
     beta = 1e-3), mixed precision and FP64: isolated GN matvecs and a Newton-PCG solve with P_REG."""
@@ -604,6 +647,7 @@ def d3_workload(args, dev):
                 "time_precond_ms": round(repp["time_precond_ms"], 2)}
             ctxp.close()
             del vp, mRp, mTp, vgenp
+            out["mixed_rk2a"] = d3_rk2a(dev, reps=3)
         # the same problem with P_2L (coarse grid 64^3, CHEB(10), 30 Lanczos steps at set-up)
         ctx2, mR2, mT2, vgen2, _, _, _ = d3_setup(dev, prec, pc="2l")
         v2 = torch.zeros_like(vgen2)
