@@ -11,7 +11,7 @@ torch = pytest.importorskip("torch")
 
 import oracle as O
 import synth
-from gpu_common import TOL, check_reg_op, check_rel, problem, same_inputs
+from gpu_common import TOL, check_reg_op, check_rel, problem, record, same_inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -201,3 +201,43 @@ def test_rk2a_parameter_checks(slnk):
         with pytest.raises(slnk.SlnkError) as e:
             slnk.Context(64, 64, 8, reg="h2", beta=1e-3, prec="fp64", transport="rk2a", **kw)
         assert e.value.status == 1, kw
+
+
+@pytest.mark.parametrize("n", [256, 512])
+def test_sl_converges_to_the_rk2a_reference(slnk, n):
+    """On the smooth problem at the paper's grid sizes, the SL state m(1) and the transport part of
+    the SL gradient approach those of RK2A at CFL 0.2 as nt grows (the comparisons of tables
+    t:convergence-SL-to-RK2A-transporteqs and t:convergence-SL-to-RK2A-gradient): a property that
+    holds at any size, checked where the oracle is too slow.  FP64 on both sides."""
+    prec = "fp64"
+    g = O.Grid(n, n)
+    mT = synth.smooth_a_template(n, n)
+    v = synth.smooth_a_velocity(n, n)
+    mR = np.roll(mT, n // 16, axis=0)
+    vmax = float(np.sqrt((v ** 2).sum(axis=0)).max())
+    nt_ref = cfl_nt(n, n, vmax)
+    bAv = 1e-2 * O.apply_reg(g, v, 1)
+
+    def run(transport, nt):
+        ctx = slnk.Context(n, n, nt, reg="h1", beta=1e-2, prec=prec, pc="reg", transport=transport)
+        m1 = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        ctx.transport_state(_t(v, prec), _t(mT, prec), m1)
+        ctx.set_images(_t(mR, prec), _t(mT, prec))
+        gr = torch.empty((2, n, n), dtype=torch.float64, device="cuda")
+        ctx.gradient(_t(v, prec), gr)
+        ctx.close()
+        return _np(m1), _np(gr) - bAv
+
+    m_ref, b_ref = run("rk2a", nt_ref)
+    em, eb = [], []
+    for nt in (2, 4, 8, 16, 32):
+        m1, b = run("sl", nt)
+        em.append(np.linalg.norm(m1 - m_ref) / np.linalg.norm(m_ref))
+        eb.append(np.linalg.norm(b - b_ref) / np.linalg.norm(b_ref))
+    print(f"n {n} nt_ref {nt_ref} state {['%.2e' % e for e in em]} gradient {['%.2e' % e for e in eb]}", flush=True)
+    for k, e in enumerate(em):
+        record(f"SL state vs RK2A(0.2) {n}^2 nt={2 << k}", e, 1.0)
+    for k, e in enumerate(eb):
+        record(f"SL gradient vs RK2A(0.2) {n}^2 nt={2 << k}", e, 1.0)
+    assert all(a > b for a, b in zip(em, em[1:])) and em[1] / em[2] > 3.0, em
+    assert all(a > b for a, b in zip(eb, eb[1:])) and eb[1] / eb[2] > 3.0, eb
