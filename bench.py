@@ -857,8 +857,24 @@ def cpu_baseline(cfg, min_seconds):
             b1 = O.transport_state(gb, bv, bT, bc["nt"])
             Lb = O.Level(gb, bT, r32(b1), O.Params(nt=bc["nt"], beta=bc["beta"], reg=bc["reg"], proj=proj))
             linb = O.linearize(Lb, bv)
-            ref[name] = {"mT": bT, "mR": Lb.mR, "v_gen": bv, "vt": bvt, "m1": b1, "grad": O.gradient(linb),
-                         "hvt": O.hessian_matvec(linb, bvt), "nt": bc["nt"], "beta": bc["beta"]}
+            gradb = O.gradient(linb)
+            t0 = time.perf_counter()
+            hvtb = O.hessian_matvec(linb, bvt)
+            if proj == 0:  # one matvec of the 512^2 nt = 8 problem
+                timing["matvec_512_single_thread_s"] = round(time.perf_counter() - t0, 2)
+            ref[name] = {"mT": bT, "mR": Lb.mR, "v_gen": bv, "vt": bvt, "m1": b1, "grad": gradb,
+                         "hvt": hvtb, "nt": bc["nt"], "beta": bc["beta"]}
+    # the smooth 64^2 problem (FP64, H1, beta = 1e-2, P_REG): the oracle's solve on one thread
+    sc = synth.config("smooth64")
+    with threadpool_limits(limits=1):
+        gs = O.Grid(sc["n1"], sc["n2"])
+        Ls = O.Level(gs, sc["mT"], O.transport_state(gs, sc["v_gen"], sc["mT"], sc["nt"]),
+                     O.Params(nt=sc["nt"], beta=sc["beta"], reg=sc["reg"]))
+        t0 = time.perf_counter()
+        _, reps = O.newton_solve(Ls, pc="reg", max_newton=20)
+        timing["solve_smooth64_single_thread_s"] = round(time.perf_counter() - t0, 2)
+        timing["solve_smooth64"] = {"newton_iters": reps["newton_iters"], "pcg_iters": reps["pcg_iters"],
+                                    "status": reps["status"]}
     return timing, ref
 
 
