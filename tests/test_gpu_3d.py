@@ -358,7 +358,7 @@ def test_nested_pcg_coarse_solve_matches_oracle(slnk, prec):
     ctx.close()
 
 
-def _rk_level(shape, prec, beta=1e-3, reg=2, seed=3, amp=0.3, hessian="gn"):
+def _rk_level(shape, prec, beta=1e-3, reg=2, seed=3, amp=0.3, hessian="gn", proj=0):
     """Oracle level of the 3-D Gaussian recipe with RK2A transport, nt from the CFL number 0.2 of
     the generating velocity (the paper's RK2A setting)."""
     g = O.Grid(*shape)
@@ -370,22 +370,24 @@ def _rk_level(shape, prec, beta=1e-3, reg=2, seed=3, amp=0.3, hessian="gn"):
     vmax = float(np.sqrt((vgen ** 2).sum(axis=0)).max())
     nt = max(2, int(np.ceil(vmax * max(shape) / (2 * np.pi * 0.2))))
     mR = same_inputs(prec, O.rk2a_solve_state(g, vgen, mT, nt)[-1])
-    prm = O.Params(nt=nt, beta=beta, reg=reg, transport="rk2a", hessian=hessian)
+    prm = O.Params(nt=nt, beta=beta, reg=reg, transport="rk2a", hessian=hessian, proj=proj)
     return O.Level(g, mT, mR, prm), vgen, vt
 
 
-RK_CASES = [((16, 16, 16), "gn"), ((8, 16, 32), "gn"), ((16, 16, 16), "fn"), ((16, 8, 16), "fn")]
+# (shape, hessian, reg, proj)
+RK_CASES = [((16, 16, 16), "gn", 2, 0), ((8, 16, 32), "gn", 2, 0), ((16, 16, 16), "fn", 2, 0), ((16, 8, 16), "fn", 2, 0),
+            ((16, 8, 16), "gn", 3, 1)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("shape,hessian", RK_CASES)
-def test_rk2a_matches_oracle(slnk, prec, shape, hessian):
+@pytest.mark.parametrize("shape,hessian,reg,proj", RK_CASES)
+def test_rk2a_matches_oracle(slnk, prec, shape, hessian, reg, proj):
     """RK2A transport in 3-D (section 3.3.1; appendix "Stabilized RK2 Scheme"): state transport,
     objective, gradient and the GN or full-Newton matvec against the oracle (the full-Newton lambda
-    terms large against the tolerance)."""
-    L, vgen, vt = _rk_level(shape, prec, hessian=hessian)
+    terms large against the tolerance), K = I or Leray."""
+    L, vgen, vt = _rk_level(shape, prec, hessian=hessian, reg=reg, proj=proj)
     g, nt = L.grid, L.prm.nt
-    print(f"rk2a case {shape} nt{nt} {hessian} {prec}", flush=True)
+    print(f"rk2a case {shape} nt{nt} {hessian} reg{reg} proj{proj} {prec}", flush=True)
     ctx = _ctx(slnk, L, prec, transport="rk2a")
     m1 = torch.empty(g.shape, dtype=ctx.dtype, device="cuda")
     ctx.transport_state(_t(vgen, prec), _t(L.mT, prec), m1)
@@ -408,7 +410,7 @@ def test_rk2a_matches_oracle(slnk, prec, shape, hessian):
         assert np.linalg.norm(href - hgn) > 50 * tol * np.linalg.norm(href)
     ht = torch.empty_like(gt)
     ctx.hessian_matvec(_t(vt, prec), ht)
-    check_rel(f"3d RK2A {hessian} matvec {shape} {prec}", _np(ht), href, tol)
+    check_rel(f"3d RK2A {hessian} matvec {shape} reg{reg} proj{proj} {prec}", _np(ht), href, tol)
     ctx.close()
 
 
