@@ -1,18 +1,18 @@
-/* slnk3.h -- C ABI of the three-dimensional semi-Lagrangian Gauss--Newton--Krylov path on MI355X
- * (gfx950).
+/* slnk3.h -- C ABI of the three-dimensional semi-Lagrangian Newton--Krylov path on MI355X (gfx950).
  *
  * Nothing in the method of arXiv:1604.02153 is specific to two dimensions (section 1,
  * "Limitations and Unresolved Issues"); this interface runs it on a periodic volume.  The
  * operations are those of slnk.h for d = 3: the objective (eq. e:varopt:objective without the
  * mass-source term), the reduced gradient g = beta A v + K int lambda grad m dt (eq. e:control-elim),
  * the Gauss--Newton reduced Hessian matvec (eq. e:hessian-matvec with the lambda terms dropped,
- * section 3.4.1), the spectral preconditioner P_REG (eq. e:reg-precond), and the globalised
- * inexact Newton--PCG solve with P_REG (sections 3.4.1, 3.5).  Transport is the semi-Lagrangian
- * scheme of section 3.3.2 (Heun trace of the characteristics, RK2 along them, periodic cubic
- * spline interpolation -- here the tensor-product cubic B-spline in three dimensions, its
- * coefficients from the periodic inverse of the (1, 4, 1)/6 system along each axis, applied as the
- * exponential filter sqrt(3) sum z^|t| f_{i+t}, z = sqrt(3) - 2, truncated below the working
- * precision).
+ * section 3.4.1) or the full-Newton one, the preconditioners P_REG (eq. e:reg-precond) and P_2L
+ * (section 3.4.2, CHEB(k) or the nested PCG(eps) coarse solve), and the globalised inexact
+ * Newton--PCG solve (sections 3.4.1, 3.5).  Transport is the semi-Lagrangian scheme of section 3.3.2
+ * (Heun trace of the characteristics, RK2 along them, periodic cubic spline interpolation -- here
+ * the tensor-product cubic B-spline in three dimensions, its coefficients from the periodic inverse
+ * of the (1, 4, 1)/6 system along each axis, applied as the exponential filter
+ * sqrt(3) sum z^|t| f_{i+t}, z = sqrt(3) - 2, truncated below the working precision), or on request
+ * the stabilised RK2 scheme of section 3.3.1.
  *
  * Conventions
  *   - Grid: periodic [0, 2 pi)^3 with n1 x n2 x n3 nodes, x_i = 2 pi i / n_i; every n_i a power of
