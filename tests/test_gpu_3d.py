@@ -430,3 +430,23 @@ def test_rk2a_newton_solve_fp64_matches_oracle(slnk, hessian):
     assert (r["newton_iters"], r["pcg_iters"]) == (rep["newton_iters"], rep["pcg_iters"])
     check_rel(f"3d RK2A newton ({hessian}) v fp64", _np(v), vs, 1e-9)
     ctx.close()
+
+
+def test_full_newton_with_nested_pcg_fp64_matches_oracle(slnk):
+    """The full-Newton matvec with P_2L's nested PCG(0.1) coarse solve (Gauss--Newton coarse
+    operator) in 3-D, FP64: the oracle's Newton, outer PCG and coarse CG counts, velocity to 1e-9."""
+    shape, prec = (16, 16, 16), "fp64"
+    L, _, _ = _level(shape, prec, beta=1e-3)
+    L = O.Level(L.grid, L.mT, L.mR, replace(L.prm, hessian="fn"))
+    vs, rep = O.newton_solve(L, pc="2l", max_newton=6, coarse_solver="pcg", coarse_eps=0.1)
+    ctx = _ctx(slnk, L, prec, pc="2l", coarse_solver="pcg", coarse_eps=0.1)
+    ctx.set_images(_t(L.mR, prec), _t(L.mT, prec))
+    v = torch.zeros((3,) + shape, dtype=ctx.dtype, device="cuda")
+    r = ctx.newton_solve(v, max_newton=6)
+    print("oracle", rep["newton_iters"], rep["pcg_iters"], rep["coarse_matvecs"], "gpu", r["newton_iters"],
+          r["pcg_iters"], r["coarse_matvecs"], flush=True)
+    assert r["status"] == "SLNK_OK" and rep["status"] == "ok" and r["grel"][-1] <= 1e-2
+    assert (r["newton_iters"], r["pcg_iters"], r["coarse_matvecs"]) == \
+        (rep["newton_iters"], rep["pcg_iters"], rep["coarse_matvecs"])
+    check_rel("3d FN + PCG(0.1) newton v fp64", _np(v), vs, 1e-9)
+    ctx.close()
